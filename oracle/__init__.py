@@ -1,0 +1,127 @@
+"""FP64 CPU oracle for plane-evaluation Gaussian beamlet decomposition.
+
+TEST INFRASTRUCTURE: only ``tests/``, ``__graft_entry__.smoke()`` and the
+benchmark's ``cpu_baseline`` leg may import this package.  The product path
+(``paper_2404_12454_amd``) never imports it, and the two share no code; the
+only common module is the seeded input generator, which holds no propagation
+arithmetic.
+
+``gbd_oracle.c`` is a plain, slow, direct FP64 implementation (libm exp/sin/
+cos, no fast-math, OpenMP over pixels).  ``metrics`` and ``mlp`` hold the FP64
+figures of merit and the surrogate's reference network in numpy.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "gbd_oracle.c")
+_LIB = os.path.join(_HERE, "libgbd_oracle.so")
+_lib = None
+
+ERRORS = {0: "ok", -1: "EINVAL", -2: "ENOTSYMPLECTIC", -3: "EBRANCH", -4: "EPARALLEL"}
+
+
+class OracleError(RuntimeError):
+    def __init__(self, code: int):
+        super().__init__(f"oracle error {code} ({ERRORS.get(code, '?')})")
+        self.code = code
+
+
+def build(force: bool = False) -> str:
+    """Compile the C oracle with gcc -O2 -fopenmp (no fast-math)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + f".tmp{os.getpid()}"
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-D_GNU_SOURCE", "-fopenmp", "-fPIC", "-shared",
+                               "-Wall", "-Wno-unknown-pragmas", _SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        build()
+        lib = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        lib.oracle_eval.restype = ctypes.c_int
+        lib.oracle_eval.argtypes = [ctypes.c_int64, ctypes.c_double, ctypes.c_double, P, P, P, ctypes.c_int64,
+                                    P, P, P, ctypes.c_int, P, P, P, ctypes.c_int32, ctypes.c_int32,
+                                    ctypes.c_double, ctypes.c_double, ctypes.c_int64, P, P, ctypes.c_int, P, P, P]
+        lib.oracle_beamlet.restype = ctypes.c_int
+        lib.oracle_beamlet.argtypes = [ctypes.c_double, P, P, ctypes.c_double, ctypes.c_double, P,
+                                       ctypes.c_double, P]
+        lib.oracle_symplectic_ok.restype = ctypes.c_int
+        lib.oracle_symplectic_ok.argtypes = [P]
+        _lib = lib
+    return _lib
+
+
+def _ptr(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _f64(a):
+    return None if a is None else np.ascontiguousarray(a, dtype=np.float64)
+
+
+def eval_field(scene, model: int = 0, pixels: Optional[tuple] = None, extra_point=None,
+               threads: Optional[int] = None):
+    """Coherent field of ``scene`` on its detector plane, complex128.
+
+    model 0 = plane-evaluation, model 1 = exact paraxial point evaluation.
+    pixels = (ix, iy) int arrays for a sample of pixels, else the full
+    [ny][nx] grid.  extra_point = (a, b) plane coordinates also evaluated
+    (returned second)."""
+    lib = _load()
+    pl = scene.plane
+    r1, th1, w0, amp, path, abcd = (_f64(scene.r1), _f64(scene.th1), _f64(scene.w0), _f64(scene.amp),
+                                    _f64(scene.path), _f64(scene.abcd))
+    shared = 1 if abcd.shape[0] == 1 else 0
+    if pixels is not None:
+        ix = np.ascontiguousarray(pixels[0], dtype=np.int32).ravel()
+        iy = np.ascontiguousarray(pixels[1], dtype=np.int32).ravel()
+        m = ix.size
+        out = np.empty(2 * m)
+    else:
+        ix = iy = None
+        m = pl.nx * pl.ny
+        out = np.empty(2 * m)
+    ep = _f64(extra_point)
+    oe = np.zeros(2) if ep is not None else None
+    if threads is not None:
+        os.environ["OMP_NUM_THREADS"] = str(threads)
+    rc = lib.oracle_eval(scene.n, scene.lam, scene.l0, _ptr(r1), _ptr(th1), _ptr(w0), w0.size, _ptr(amp),
+                         _ptr(path), _ptr(abcd), shared, _ptr(_f64(pl.origin)), _ptr(_f64(pl.normal)),
+                         _ptr(_f64(pl.xhint)), pl.nx, pl.ny, pl.dx, pl.dy, m, _ptr(ix), _ptr(iy), model,
+                         _ptr(out), _ptr(ep), _ptr(oe))
+    if rc != 0:
+        raise OracleError(rc)
+    E = out.view(np.complex128)
+    if pixels is None:
+        E = E.reshape(pl.ny, pl.nx)
+    if ep is not None:
+        return E, complex(oe[0], oe[1])
+    return E
+
+
+def beamlet(lam, r1, th1, w0, W, abcd, z=0.0):
+    """One beamlet propagated by abcd extended with free space z.
+    Returns dict(Qinv [2,2] complex, gamma, r2 [2], th2 [2], tau)."""
+    lib = _load()
+    out = np.empty(15)
+    rc = lib.oracle_beamlet(float(lam), _ptr(_f64(r1)), _ptr(_f64(th1)), float(w0), float(W),
+                            _ptr(_f64(np.asarray(abcd).reshape(16))), float(z), _ptr(out))
+    if rc != 0:
+        raise OracleError(rc)
+    Q = (out[0:8:2] + 1j * out[1:8:2]).reshape(2, 2)
+    return dict(Qinv=Q, gamma=complex(out[8], out[9]), r2=out[10:12].copy(), th2=out[12:14].copy(), tau=out[14])
+
+
+def symplectic_ok(abcd) -> bool:
+    return bool(_load().oracle_symplectic_ok(_ptr(_f64(np.asarray(abcd).reshape(16)))))
