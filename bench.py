@@ -1,0 +1,171 @@
+#!/usr/bin/env python3
+"""Benchmark of the plane-evaluation GBD hot path on one MI355X.
+
+One step = the per-beamlet FP64 setup (complex-curvature law, eigenvalue-branch
+amplitude, base ray, hit point, phasor coefficients; with its status check)
+followed by the N x M mixed-precision evaluation of the coherent field, on
+inputs already resident in HBM.  Workload: 51,468 beamlets (256 across a
+10 mm f/10 pupil, OF 1.7) onto a 512 x 512 focal-plane detector spanning
++-20 lambda F.  value = N * M / (time per step), beamlet-pixel evaluations/s.
+
+Also reported: the FP64 form on the same workload (and the mixed/FP64
+speed-up), the instruction-mix roofline of the dominant kernel with its live
+HIP-event duration, and the FP64 CPU oracle timed on a bounded pixel sample
+(which also gives the mixed form's error against the oracle on that sample).
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+METRIC = "beamlet·pixel evals/s (FP32+FP64-phase vs FP64) at ≤1e-5 rel field err"
+
+# Instruction-mix roofline of the mixed evaluation kernel (per beamlet-pixel
+# pair, per-lane-beamlet terms amortised over the rows a lane owns):
+#   FP64: 2 FMA (phase quadratic in the row step) + fract + cvt to f32 = 4
+#   FP32: 2 FMA (log2-amplitude) + 2 FMA (complex accumulate)          = 4
+#   transcendental: exp2, sin, cos                                     = 3
+# issue rates in lanes/CU/clock on gfx950: FP64 64 (78.6 TFLOP/s FP64 FMA),
+# FP32 128 (157.3 TFLOP/s FP32), transcendental 32 (measured).
+CUS, CLOCK_HZ = 256, 2.4e9
+MIX = {"fp64": (4, 64), "fp32": (4, 128), "trans": (3, 32)}
+CYCLES_PER_PAIR = sum(n / r for n, r in MIX.values())
+PEAK_EVALS = CUS * CLOCK_HZ / CYCLES_PER_PAIR
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="airy256_512")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--fp64-steps", type=int, default=5)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build measures one GPU; multi-GPU runs are not part of it "
+              "(the path would shard by pixel rows, see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_2404_12454_amd as gbd
+    from paper_2404_12454_amd import scenes
+
+    if not os.path.exists(gbd.library_path()):
+        from paper_2404_12454_amd import build
+        build.build()
+
+    sc = scenes.config(args.workload)
+    N, M = sc.n, sc.plane.npix
+    ctx = gbd.Context(0)
+    stream = torch.cuda.current_stream()
+    b = gbd.beamlets_from_scene(ctx, sc)
+    p = gbd.plane_from_scene(ctx, sc)
+    plan = gbd.Plan(ctx, N)
+    out = torch.empty((sc.plane.ny, sc.plane.nx), dtype=torch.complex64, device="cuda")
+    out64 = torch.empty((sc.plane.ny, sc.plane.nx), dtype=torch.complex128, device="cuda")
+
+    def step(precision, o, ev=None):
+        plan.setup(b, p)                      # setup kernel + status sync
+        if ev is not None:
+            ev[0].record(stream)
+        plan.eval(precision, o)
+        if ev is not None:
+            ev[1].record(stream)
+
+    for _ in range(args.warmup):
+        step(gbd.GBD_MIXED, out)
+    torch.cuda.synchronize()
+
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    t_start = torch.cuda.Event(enable_timing=True)
+    t_end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    t_start.record(stream)
+    for i in range(args.steps):
+        step(gbd.GBD_MIXED, out, evs[i])
+    t_end.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    ms_total = t_start.elapsed_time(t_end)
+    ms_step = ms_total / args.steps
+    eval_ms = [a.elapsed_time(z) for a, z in evs]
+    eval_ms_mean = float(np.mean(eval_ms))
+    value = N * M / (ms_step * 1e-3)
+
+    # FP64 form on the same workload
+    step(gbd.GBD_FP64, out64)
+    torch.cuda.synchronize()
+    ev64 = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.fp64_steps)]
+    for i in range(args.fp64_steps):
+        step(gbd.GBD_FP64, out64, ev64[i])
+    torch.cuda.synchronize()
+    eval64_ms = float(np.mean([a.elapsed_time(z) for a, z in ev64]))
+    E32 = out.cpu().numpy().astype(np.complex128)
+    E64 = out64.cpu().numpy()
+    mixed_vs_fp64 = float(np.linalg.norm(E32 - E64) / np.linalg.norm(E64))
+
+    shape = plan.shape(gbd.GBD_MIXED)
+    achieved = N * M / (eval_ms_mean * 1e-3)
+    rec = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64+f32",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {N} beamlets x {sc.plane.nx}x{sc.plane.ny} px, f/10, "
+                               f"+-{sc.meta.get('half_span_lamF', 0):g} lamF, mixed precision",
+                   "n_beamlets": N, "n_pixels": M, "launch": shape},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_EVALS, "unit": "evals/s",
+                     "frac": achieved / PEAK_EVALS, "traffic": None, "kernel": "eval_mixed_kernel",
+                     "kernel_ms": eval_ms_mean, "cycles_per_pair": CYCLES_PER_PAIR},
+        "setup_ms": ms_step - eval_ms_mean,
+        "fp64": {"value": N * M / (eval64_ms * 1e-3), "eval_ms": eval64_ms,
+                 "speedup_mixed_over_fp64": eval64_ms / eval_ms_mean},
+        "err_mixed_vs_fp64_full_grid": mixed_vs_fp64,
+        "wall_s_timed": wall,
+    }
+
+    if not args.no_cpu_baseline:
+        rec["cpu_baseline"] = cpu_baseline(sc, E32, E64)
+    print(json.dumps(rec), flush=True)
+
+
+def cpu_baseline(sc, E32, E64):
+    """The FP64 oracle on every 4th pixel row (a bounded sample of the same
+    workload), all host threads; also the GPU fields' error on that sample."""
+    import numpy as np
+    import oracle
+    ny, nx = sc.plane.ny, sc.plane.nx
+    rows = np.arange(0, ny, 4)
+    iy, ix = np.meshgrid(rows, np.arange(nx), indexing="ij")
+    ix, iy = ix.ravel().astype(np.int32), iy.ravel().astype(np.int32)
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    t0 = time.perf_counter()
+    ref = oracle.eval_field(sc, pixels=(ix, iy), threads=threads)
+    dt = time.perf_counter() - t0
+    pairs = sc.n * ix.size
+    e32 = E32[iy, ix]
+    e64 = E64[iy, ix]
+    return {"value": pairs / dt, "unit": "evals/s", "cores": threads, "kind": "oracle",
+            "sample": f"every 4th pixel row ({rows.size} of {ny} rows, {ix.size} px x {sc.n} beamlets), "
+                      f"{dt:.1f} s",
+            "err_mixed_vs_oracle": float(np.linalg.norm(e32 - ref) / np.linalg.norm(ref)),
+            "err_fp64_vs_oracle": float(np.linalg.norm(e64 - ref) / np.linalg.norm(ref))}
+
+
+if __name__ == "__main__":
+    main()

@@ -56,6 +56,8 @@ def _load():
         lib.oracle_beamlet.restype = ctypes.c_int
         lib.oracle_beamlet.argtypes = [ctypes.c_double, P, P, ctypes.c_double, ctypes.c_double, P,
                                        ctypes.c_double, P]
+        lib.oracle_set_threads.restype = ctypes.c_int
+        lib.oracle_set_threads.argtypes = [ctypes.c_int]
         lib.oracle_symplectic_ok.restype = ctypes.c_int
         lib.oracle_symplectic_ok.argtypes = [P]
         _lib = lib
@@ -95,7 +97,7 @@ def eval_field(scene, model: int = 0, pixels: Optional[tuple] = None, extra_poin
     ep = _f64(extra_point)
     oe = np.zeros(2) if ep is not None else None
     if threads is not None:
-        os.environ["OMP_NUM_THREADS"] = str(threads)
+        lib.oracle_set_threads(int(threads))
     rc = lib.oracle_eval(scene.n, scene.lam, scene.l0, _ptr(r1), _ptr(th1), _ptr(w0), w0.size, _ptr(amp),
                          _ptr(path), _ptr(abcd), shared, _ptr(_f64(pl.origin)), _ptr(_f64(pl.normal)),
                          _ptr(_f64(pl.xhint)), pl.nx, pl.ny, pl.dx, pl.dy, m, _ptr(ix), _ptr(iy), model,
@@ -121,6 +123,11 @@ def beamlet(lam, r1, th1, w0, W, abcd, z=0.0):
         raise OracleError(rc)
     Q = (out[0:8:2] + 1j * out[1:8:2]).reshape(2, 2)
     return dict(Qinv=Q, gamma=complex(out[8], out[9]), r2=out[10:12].copy(), th2=out[12:14].copy(), tau=out[14])
+
+
+def set_threads(n: int = 0) -> int:
+    """Set the oracle's OpenMP thread count (0 keeps it); returns the count in use."""
+    return int(_load().oracle_set_threads(int(n)))
 
 
 def symplectic_ok(abcd) -> bool:

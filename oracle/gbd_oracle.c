@@ -456,5 +456,19 @@ int oracle_beamlet(double lam, const double *r1, const double *th1, double w0, d
     return OR_OK;
 }
 
+/* thread count of the OpenMP pixel loop (0 = leave the runtime default) */
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+int oracle_set_threads(int n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
+}
+
 /* symplectic check exposed for the input-validation tests */
 int oracle_symplectic_ok(const double *abcd) { return symplectic_ok(abcd); }

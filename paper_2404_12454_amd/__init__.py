@@ -1,0 +1,271 @@
+"""MI355X plane-evaluation Gaussian beamlet decomposition (arXiv:2404.12454).
+
+Thin ctypes binding of the C ABI in ``include/gbd.h``: argument marshalling
+only.  Every step of the computation runs in the HIP library ``libgbd.so``
+built in-tree for gfx950 (``python -m paper_2404_12454_amd.build``); there is
+no CPU fallback, and calls fail loudly when the library is missing.  PyTorch
+supplies device memory (output tensors) and the HIP stream.
+
+Names follow the C ABI: ``gbd_ctx_create``, ``gbd_beamlets``, ``gbd_plane``,
+``gbd_eval``, ``gbd_plan_create``, ``gbd_plan_setup``, ``gbd_plan_eval``,
+``gbd_plan_shape``.  Handles are small Python objects that free their C
+handle when collected.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+__all__ = [
+    "GBD_FP64", "GBD_MIXED", "GbdError", "gbd_eval_opts", "library_path", "load_library",
+    "gbd_ctx_create", "gbd_beamlets", "gbd_plane", "gbd_eval", "gbd_plan_create", "gbd_plan_setup",
+    "gbd_plan_eval", "gbd_plan_shape", "beamlets_from_scene", "plane_from_scene", "Context", "Beamlets",
+    "Plane", "Plan",
+]
+
+GBD_FP64 = 0
+GBD_MIXED = 1
+ERRORS = {0: "GBD_OK", -1: "GBD_EINVAL", -2: "GBD_ENOTSYMPLECTIC", -3: "GBD_EBRANCH", -4: "GBD_EPARALLEL",
+          -5: "GBD_ENOMEM", -6: "GBD_EHIP", -7: "GBD_ERANGE"}
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libgbd.so")
+_lib = None
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+class GbdError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class gbd_eval_opts(ctypes.Structure):
+    _fields_ = [("rows_per_lane", ctypes.c_int32), ("waves", ctypes.c_int32), ("segments", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+def load_library():
+    """Load the in-tree HIP library; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise RuntimeError(f"{_LIB_PATH} is missing: build it with `python -m paper_2404_12454_amd.build`")
+    lib = ctypes.CDLL(_LIB_PATH)
+    P, I32, I64, D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    PP = ctypes.POINTER(ctypes.c_void_p)
+    sig = {
+        "gbd_ctx_create": (ctypes.c_int, [PP, ctypes.c_int, P]),
+        "gbd_ctx_set_stream": (ctypes.c_int, [P, P]),
+        "gbd_ctx_destroy": (None, [P]),
+        "gbd_last_error": (ctypes.c_char_p, []),
+        "gbd_beamlets": (ctypes.c_int, [P, PP, I64, D, D, P, P, P, I64, P, P, P, I64]),
+        "gbd_beamlets_free": (None, [P]),
+        "gbd_plane": (ctypes.c_int, [P, PP, P, P, P, I32, I32, D, D]),
+        "gbd_plane_free": (None, [P]),
+        "gbd_eval": (ctypes.c_int, [P, P, P, ctypes.c_int, P, I64, P]),
+        "gbd_plan_create": (ctypes.c_int, [P, PP, I64]),
+        "gbd_plan_setup": (ctypes.c_int, [P, P, P, P]),
+        "gbd_plan_eval": (ctypes.c_int, [P, P, ctypes.c_int, P, I64, P]),
+        "gbd_plan_free": (None, [P]),
+        "gbd_plan_shape": (ctypes.c_int, [P, P, ctypes.c_int, P, P]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(rc: int):
+    if rc != 0:
+        raise GbdError(rc, load_library().gbd_last_error().decode(errors="replace"))
+
+
+def _f64(a) -> Optional[np.ndarray]:
+    return None if a is None else np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _p(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+class Context:
+    """A library context bound to one device and one HIP stream (default:
+    torch's current stream on that device)."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+        lib = load_library()
+        self.device = int(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = ctypes.c_void_p()
+        _check(lib.gbd_ctx_create(ctypes.byref(h), self.device, ctypes.c_void_p(self.stream.cuda_stream)))
+        self.handle = h
+
+    def set_stream(self, stream):
+        self.stream = stream
+        _check(load_library().gbd_ctx_set_stream(self.handle, ctypes.c_void_p(stream.cuda_stream)))
+
+    def close(self):
+        if getattr(self, "handle", None) and self.handle.value:
+            load_library().gbd_ctx_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def gbd_ctx_create(device: int = 0, stream=None) -> Context:
+    return Context(device, stream)
+
+
+class Beamlets:
+    def __init__(self, handle, n):
+        self.handle, self.n = handle, n
+
+    def __del__(self):
+        try:
+            if self.handle.value:
+                load_library().gbd_beamlets_free(self.handle)
+        except Exception:
+            pass
+
+
+class Plane:
+    def __init__(self, handle, nx, ny):
+        self.handle, self.nx, self.ny = handle, nx, ny
+
+    def __del__(self):
+        try:
+            if self.handle.value:
+                load_library().gbd_plane_free(self.handle)
+        except Exception:
+            pass
+
+
+def gbd_beamlets(ctx: Context, n: int, lam: float, l0: float, r1, th1=None, w0=None, amp=None, path=None,
+                 abcd=None) -> Beamlets:
+    """Validate, copy and upload a beamlet decomposition (see gbd.h)."""
+    r1, th1, w0, amp, path, abcd = map(_f64, (r1, th1, w0, amp, path, abcd))
+    w0 = np.atleast_1d(w0) if w0 is not None else None
+    abcd = None if abcd is None else abcd.reshape(-1, 16)
+    h = ctypes.c_void_p()
+    _check(load_library().gbd_beamlets(ctx.handle, ctypes.byref(h), int(n), float(lam), float(l0), _p(r1), _p(th1),
+                                       _p(w0), 0 if w0 is None else w0.size, _p(amp), _p(path), _p(abcd),
+                                       0 if abcd is None else abcd.shape[0]))
+    return Beamlets(h, int(n))
+
+
+def gbd_plane(ctx: Context, origin, normal, xhint, nx: int, ny: int, dx: float, dy: float) -> Plane:
+    o, n, x = _f64(origin), _f64(normal), _f64(xhint)
+    h = ctypes.c_void_p()
+    _check(load_library().gbd_plane(ctx.handle, ctypes.byref(h), _p(o), _p(n), _p(x), int(nx), int(ny),
+                                    float(dx), float(dy)))
+    return Plane(h, int(nx), int(ny))
+
+
+def beamlets_from_scene(ctx: Context, s) -> Beamlets:
+    return gbd_beamlets(ctx, s.n, s.lam, s.l0, s.r1, s.th1, s.w0, s.amp, s.path, s.abcd)
+
+
+def plane_from_scene(ctx: Context, s) -> Plane:
+    pl = s.plane
+    return gbd_plane(ctx, pl.origin, pl.normal, pl.xhint, pl.nx, pl.ny, pl.dx, pl.dy)
+
+
+def _opts(opts) -> Optional[gbd_eval_opts]:
+    if opts is None:
+        return None
+    if isinstance(opts, gbd_eval_opts):
+        return opts
+    return gbd_eval_opts(int(opts.get("rows_per_lane", 0)), int(opts.get("waves", 0)),
+                         int(opts.get("segments", 0)), 0)
+
+
+def _out_tensor(ctx: Context, plane_nx: int, plane_ny: int, precision: int, out):
+    import torch
+    dt = torch.complex128 if precision == GBD_FP64 else torch.complex64
+    if out is None:
+        out = torch.empty((plane_ny, plane_nx), dtype=dt, device=f"cuda:{ctx.device}")
+    if out.dtype != dt or not out.is_contiguous() or out.device.type != "cuda":
+        raise ValueError(f"out must be a contiguous {dt} CUDA tensor")
+    return out
+
+
+def gbd_eval(ctx: Context, beamlets: Beamlets, plane: Plane, precision: int = GBD_MIXED, out=None, opts=None):
+    """Field [ny, nx] on the plane (complex128 for GBD_FP64, complex64 for
+    GBD_MIXED), written asynchronously on the context stream."""
+    out = _out_tensor(ctx, plane.nx, plane.ny, precision, out)
+    o = _opts(opts)
+    _check(load_library().gbd_eval(ctx.handle, beamlets.handle, plane.handle, int(precision),
+                                   ctypes.c_void_p(out.data_ptr()), out.numel() * out.element_size(),
+                                   None if o is None else ctypes.byref(o)))
+    return out
+
+
+class Plan:
+    """Per-beamlet records for one (beamlets, plane) pair, re-usable across
+    evaluations (gbd_plan_* of the C ABI)."""
+
+    def __init__(self, ctx: Context, capacity: int):
+        self.ctx = ctx
+        self.capacity = int(capacity)
+        h = ctypes.c_void_p()
+        _check(load_library().gbd_plan_create(ctx.handle, ctypes.byref(h), self.capacity))
+        self.handle = h
+        self.nx = self.ny = 0
+
+    def setup(self, beamlets: Beamlets, plane: Plane):
+        _check(load_library().gbd_plan_setup(self.ctx.handle, self.handle, beamlets.handle, plane.handle))
+        self.nx, self.ny = plane.nx, plane.ny
+        return self
+
+    def eval(self, precision: int = GBD_MIXED, out=None, opts=None):
+        out = _out_tensor(self.ctx, self.nx, self.ny, precision, out)
+        o = _opts(opts)
+        _check(load_library().gbd_plan_eval(self.ctx.handle, self.handle, int(precision),
+                                            ctypes.c_void_p(out.data_ptr()), out.numel() * out.element_size(),
+                                            None if o is None else ctypes.byref(o)))
+        return out
+
+    def shape(self, precision: int = GBD_MIXED, opts=None) -> dict:
+        o = _opts(opts)
+        r = gbd_eval_opts()
+        _check(load_library().gbd_plan_shape(self.ctx.handle, self.handle, int(precision),
+                                             None if o is None else ctypes.byref(o), ctypes.byref(r)))
+        return dict(rows_per_lane=r.rows_per_lane, waves=r.waves, segments=r.segments)
+
+    def __del__(self):
+        try:
+            if self.handle.value:
+                load_library().gbd_plan_free(self.handle)
+        except Exception:
+            pass
+
+
+def gbd_plan_create(ctx: Context, capacity: int) -> Plan:
+    return Plan(ctx, capacity)
+
+
+def gbd_plan_setup(plan: Plan, beamlets: Beamlets, plane: Plane) -> Plan:
+    return plan.setup(beamlets, plane)
+
+
+def gbd_plan_eval(plan: Plan, precision: int = GBD_MIXED, out=None, opts=None):
+    return plan.eval(precision, out, opts)
+
+
+def gbd_plan_shape(plan: Plan, precision: int = GBD_MIXED, opts=None) -> dict:
+    return plan.shape(precision, opts)

@@ -1,0 +1,214 @@
+"""GPU parity of the HIP path (called through the C ABI) against the FP64
+oracle on the same seeded inputs.
+
+Tolerances (relative L2 field error, raw and global-phase aligned):
+  FP64 form  <= 1e-12
+  mixed form <= 1e-5   (FP64 phase, FP32 exp2/sin/cos, FP32 compensated sums)
+Full-size workloads are checked on pixel samples the oracle computes one by
+one, in the launch configuration the benchmark uses, and through symmetry
+properties that hold on the whole grid.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2404_12454_amd as gbd
+from paper_2404_12454_amd import scenes
+from gbd_testutil import ensure_library, rel_l2, rel_l2_phase_aligned
+
+pytestmark = pytest.mark.gpu
+
+TOL = {gbd.GBD_FP64: 1e-12, gbd.GBD_MIXED: 1e-5}
+BOTH = [gbd.GBD_FP64, gbd.GBD_MIXED]
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    ensure_library()
+    return gbd.Context(0)
+
+
+def run(ctx, sc, precision, opts=None):
+    import torch
+    b = gbd.beamlets_from_scene(ctx, sc)
+    p = gbd.plane_from_scene(ctx, sc)
+    E = gbd.gbd_eval(ctx, b, p, precision, opts=opts)
+    torch.cuda.synchronize()
+    return E.cpu().numpy()
+
+
+def check(E, ref, precision, what=""):
+    e1, e2 = rel_l2(E, ref), rel_l2_phase_aligned(E, ref)
+    print(f"{what} precision={precision} rel_l2={e1:.3e} aligned={e2:.3e}", flush=True)
+    assert e1 <= TOL[precision] and e2 <= TOL[precision], (what, e1, e2)
+
+
+@pytest.mark.parametrize("precision", BOTH)
+def test_airy32_64_full_grid(ctx, precision):
+    sc = scenes.config("airy32_64")
+    check(run(ctx, sc, precision), oracle.eval_field(sc), precision, "airy32_64")
+
+
+@pytest.mark.parametrize("precision", BOTH)
+def test_tilted_aberrated_ragged_grid(ctx, precision):
+    """f/4, 1 deg field, Zernike seed 2404, plane tilted 10 deg at +50 um;
+    200 x 137 pixels (ragged in both tile directions), 32 across."""
+    sc = scenes.zernike_scene(2404, n_across=32, npix=200, half_span=60e-6)
+    sc.plane.ny = 137
+    check(run(ctx, sc, precision), oracle.eval_field(sc), precision, "zern32_200x137")
+
+
+SHAPES = [dict(rows_per_lane=r, waves=w, segments=s) for r in (1, 2, 4, 8) for w in (1, 2, 4) for s in (1, 3)]
+
+
+@pytest.mark.parametrize("precision", BOTH)
+def test_every_launch_shape_matches_oracle(ctx, precision):
+    sc = scenes.zernike_scene(99, n_across=20, npix=70, half_span=40e-6)
+    sc.plane.ny = 45
+    ref = oracle.eval_field(sc)
+    for o in SHAPES:
+        check(run(ctx, sc, precision, opts=o), ref, precision, f"shape {o}")
+
+
+@pytest.mark.parametrize("precision", BOTH)
+def test_bitwise_run_to_run(ctx, precision):
+    sc = scenes.zernike_scene(5, n_across=24, npix=96)
+    a = run(ctx, sc, precision)
+    b = run(ctx, sc, precision)
+    assert np.array_equal(a.view(np.uint8), b.view(np.uint8))
+
+
+def sample_pixels(nx, ny, count, seed):
+    rng = np.random.default_rng(seed)
+    ix = np.concatenate([rng.integers(0, nx, count), [0, nx - 1, nx // 2, 0, nx - 1]])
+    iy = np.concatenate([rng.integers(0, ny, count), [0, ny - 1, ny // 2, ny - 1, 0]])
+    return ix.astype(np.int32), iy.astype(np.int32)
+
+
+@pytest.mark.parametrize("precision", BOTH)
+def test_airy256_512_full_size_sampled(ctx, precision):
+    """51,468 beamlets on 512 x 512 pixels, default (benchmark) launch shape."""
+    sc = scenes.config("airy256_512")
+    E = run(ctx, sc, precision)
+    ix, iy = sample_pixels(512, 512, 200, 1)
+    ref = oracle.eval_field(sc, pixels=(ix, iy))
+    check(E[iy, ix], ref, precision, "airy256_512 sampled")
+    # whole-grid property: the on-axis pattern is symmetric under x -> -x and y -> -y
+    scale = np.abs(E).max()
+    assert np.abs(E - E[:, ::-1]).max() <= 4 * TOL[precision] * scale
+    assert np.abs(E - E[::-1, :]).max() <= 4 * TOL[precision] * scale
+
+
+@pytest.mark.parametrize("precision", BOTH)
+def test_zern128_1024_full_size_sampled(ctx, precision):
+    """12,892 aberrated beamlets on a 1024 x 1024 tilted plane."""
+    sc = scenes.config("zern128_1024")
+    E = run(ctx, sc, precision)
+    ix, iy = sample_pixels(1024, 1024, 200, 2)
+    ref = oracle.eval_field(sc, pixels=(ix, iy))
+    check(E[iy, ix], ref, precision, "zern128_1024 sampled")
+    assert np.isfinite(E).all()
+
+
+def test_plan_reuse_and_shape(ctx):
+    import torch
+    sc = scenes.config("airy32_64")
+    b = gbd.beamlets_from_scene(ctx, sc)
+    p = gbd.plane_from_scene(ctx, sc)
+    plan = gbd.gbd_plan_create(ctx, sc.n)
+    plan.setup(b, p)
+    shp = plan.shape(gbd.GBD_MIXED)
+    assert shp["rows_per_lane"] in (1, 2, 4, 8) and shp["segments"] >= 1
+    E1 = plan.eval(gbd.GBD_FP64)
+    E2 = plan.eval(gbd.GBD_FP64, opts=dict(rows_per_lane=2, waves=1, segments=5))
+    torch.cuda.synchronize()
+    ref = oracle.eval_field(sc)
+    check(E1.cpu().numpy(), ref, gbd.GBD_FP64, "plan default")
+    check(E2.cpu().numpy(), ref, gbd.GBD_FP64, "plan 2x1x5")
+
+
+def test_edge_cases(ctx):
+    import torch
+    # empty decomposition: zero field
+    sc = scenes.airy_scene(8, npix=5)
+    empty = scenes.Scene(sc.lam, sc.l0, np.zeros((0, 2)), np.zeros((0, 2)), np.zeros(0) + 1e-3,
+                         np.zeros((0, 2)), np.zeros(0), sc.abcd, sc.plane)
+    for prec in BOTH:
+        E = run(ctx, empty, prec)
+        assert E.shape == (5, 5) and not np.any(E)
+    # one pixel, one beamlet; 65 x 1 strip; 1 x 70 column
+    for nx, ny in ((1, 1), (65, 1), (1, 70)):
+        s = scenes.zernike_scene(8, n_across=6, npix=8, half_span=20e-6)
+        s.plane.nx, s.plane.ny = nx, ny
+        ref = oracle.eval_field(s)
+        for prec in BOTH:
+            check(run(ctx, s, prec), ref, prec, f"{nx}x{ny}")
+    one = scenes.airy_scene(1, npix=16, half_span_lamF=1.0)
+    assert one.n == 1
+    for prec in BOTH:
+        check(run(ctx, one, prec), oracle.eval_field(one), prec, "single beamlet")
+    # every pixel of this grid lies 50 or more e-folds below the spot's peak:
+    # FP64 keeps its bar; the mixed form's FP32 log2-amplitude carries an
+    # absolute error ~ eps * |log2 amplitude|, so its bound there is 1e-3
+    tail = scenes.airy_scene(1, npix=16, half_span_lamF=30.0)
+    ref = oracle.eval_field(tail)
+    check(run(ctx, tail, gbd.GBD_FP64), ref, gbd.GBD_FP64, "far tail")
+    E = run(ctx, tail, gbd.GBD_MIXED)
+    assert np.isfinite(E).all() and rel_l2(E, ref) < 1e-3
+    # zero-size plane writes nothing and succeeds
+    z = scenes.airy_scene(8, npix=4)
+    b = gbd.beamlets_from_scene(ctx, z)
+    p = gbd.gbd_plane(ctx, z.plane.origin, z.plane.normal, z.plane.xhint, 0, 7, 1e-6, 1e-6)
+    out = torch.empty((7, 0), dtype=torch.complex64, device="cuda")
+    gbd.gbd_eval(ctx, b, p, gbd.GBD_MIXED, out=out)
+
+
+def test_errors_are_reported_before_any_write(ctx):
+    import torch
+    sc = scenes.airy_scene(8, npix=4)
+    bad = sc.abcd.copy()
+    bad[0, 1] = 0.3
+    with pytest.raises(gbd.GbdError) as e:
+        gbd.gbd_beamlets(ctx, sc.n, sc.lam, sc.l0, sc.r1, sc.th1, sc.w0, sc.amp, sc.path, bad)
+    assert e.value.code == -2
+    w0 = sc.w0.copy()
+    w0[2] = -1.0
+    with pytest.raises(gbd.GbdError) as e:
+        gbd.gbd_beamlets(ctx, sc.n, sc.lam, sc.l0, sc.r1, sc.th1, w0, sc.amp, sc.path, sc.abcd)
+    assert e.value.code == -1
+    r1 = sc.r1.copy()
+    r1[1, 1] = np.inf
+    with pytest.raises(gbd.GbdError) as e:
+        gbd.gbd_beamlets(ctx, sc.n, sc.lam, sc.l0, r1, sc.th1, sc.w0, sc.amp, sc.path, sc.abcd)
+    assert e.value.code == -1
+    with pytest.raises(gbd.GbdError) as e:
+        gbd.gbd_plane(ctx, [0, 0, 0], [0, 0, 1], [0, 0, 2], 4, 4, 1e-6, 1e-6)
+    assert e.value.code == -1
+    # plane containing an on-axis base ray
+    b1 = gbd.gbd_beamlets(ctx, 1, 1e-6, 0.1, [[0.0, 0.0]], None, [1e-3], None, None,
+                          scenes.lens_then_distance(0.1, 0.1))
+    side = gbd.gbd_plane(ctx, [0, 0, 0], [1, 0, 0], [0, 1, 0], 4, 4, 1e-6, 1e-6)
+    sentinel = torch.full((4, 4), 7.0 + 7.0j, dtype=torch.complex64, device="cuda")
+    with pytest.raises(gbd.GbdError) as e:
+        gbd.gbd_eval(ctx, b1, side, gbd.GBD_MIXED, out=sentinel)
+    assert e.value.code == -4
+    # inverting relay: eigenvalue on the branch cut
+    binv = gbd.gbd_beamlets(ctx, sc.n, sc.lam, sc.l0, sc.r1, sc.th1, sc.w0, sc.amp, sc.path, -np.eye(4))
+    p = gbd.plane_from_scene(ctx, sc)
+    with pytest.raises(gbd.GbdError) as e:
+        gbd.gbd_eval(ctx, binv, p, gbd.GBD_MIXED, out=sentinel)
+    assert e.value.code == -3
+    torch.cuda.synchronize()
+    assert bool((sentinel == (7.0 + 7.0j)).all())
+    # output buffer too small
+    good = gbd.beamlets_from_scene(ctx, sc)
+    small = torch.empty((3, 4), dtype=torch.complex128, device="cuda")
+    with pytest.raises(gbd.GbdError) as e:
+        load = gbd.load_library()
+        import ctypes
+        rc = load.gbd_eval(ctx.handle, good.handle, p.handle, gbd.GBD_FP64, ctypes.c_void_p(small.data_ptr()),
+                           small.numel() * 16, None)
+        gbd._check(rc)
+    assert e.value.code == -7
