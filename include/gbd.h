@@ -130,6 +130,84 @@ void gbd_plan_free(gbd_plan_t plan);
 int gbd_plan_shape(gbd_ctx_t ctx, gbd_plan_t plan, int precision, const gbd_eval_opts *opts,
                    gbd_eval_opts *resolved);
 
+/* --- autotuner ---------------------------------------------------------------
+ * gbd_autotune: times every launch shape of gbd_plan_eval for this plan and
+ * precision (rows_per_lane in {2,4,8} x waves in {1,2,4} x segment counts of
+ * 1/2, 1 and 2 times the automatic choice; `reps` timed launches each, HIP
+ * events on the context stream), stores the fastest in the context's cache
+ * keyed by (precision, log2 N, log2 M) and returns it in *best (resolved
+ * segment count) and its time in *best_ms.  Later calls with all-zero opts
+ * on the same bucket use it.  Synchronises; overwrites no caller buffer.
+ * gbd_autotune_batch: the same over rows_per_lane x waves for gbd_eval_batch
+ * on these instances (host wall time per call), cached by (log2 pairs,
+ * log2 instances).
+ * gbd_autotune_save / _load: the cache as a text file (load returns the
+ * number of entries read, or a negative code). */
+int gbd_autotune(gbd_ctx_t ctx, gbd_plan_t plan, int precision, int32_t reps, gbd_eval_opts *best, double *best_ms);
+int gbd_autotune_batch(gbd_ctx_t ctx, int32_t n_inst, const gbd_beamlets_t *beamlets, const gbd_plane_t *planes,
+                       const float *airy, int64_t airy_bytes, int32_t reps, gbd_eval_opts *best, double *best_ms);
+int gbd_autotune_save(gbd_ctx_t ctx, const char *path);
+int gbd_autotune_load(gbd_ctx_t ctx, const char *path);
+
+/* --- a6: analytic reference irradiance ------------------------------------
+ * out[iy][ix] = (2 J1(v)/v)^2 with v = pi D r / (lambda f), r the distance of
+ * the pixel from the plane origin: the Airy pattern of an unobscured circular
+ * pupil of diameter D focused at focal length f, normalised to 1 on axis (the
+ * analytic reference of Sec. 4.2 and of the search in Sec. 6).  FP64
+ * evaluation, FP32 device output; out_bytes >= 4 nx ny. */
+int gbd_airy(gbd_ctx_t ctx, gbd_plane_t p, double D, double f, double lambda, float *out, int64_t out_bytes);
+
+/* --- a7: batched parameter sweep (Sec. 6) ----------------------------------
+ * Evaluates n_inst independent instances (beamlets[i] on planes[i], mixed
+ * precision) in one persistent launch whose workgroups pull (instance, pixel
+ * tile) items, largest instances first, from an atomic queue.
+ *   airy        device float [ny][nx] reference irradiance shared by all
+ *               instances (all planes then need the same nx, ny), or NULL
+ *   zone_edges  n_zones + 1 non-decreasing radii (m, in plane coordinates)
+ *               bounding annular zones, n_zones in [0, 4] (Sec. 6's zone
+ *               study); NULL when n_zones == 0
+ *   metrics_out host double [n_inst][2 + n_zones]: RMS and peak over all
+ *               pixels of |E/E(0)|^2 - airy, E(0) the field at the plane
+ *               origin, then the RMS of each zone; required iff airy != NULL
+ *   fields_out  optional device complex64 fields, instance after instance
+ *               ([n_inst][ny_i][nx_i]); fields_bytes its size
+ * opts: rows_per_lane and waves as for gbd_eval (segments is ignored).
+ * Synchronises the context stream (setup status, then metrics). */
+int gbd_eval_batch(gbd_ctx_t ctx, int32_t n_inst, const gbd_beamlets_t *beamlets, const gbd_plane_t *planes,
+                   const float *airy, int64_t airy_bytes, const double *zone_edges, int32_t n_zones,
+                   double *metrics_out, void *fields_out, int64_t fields_bytes, const gbd_eval_opts *opts);
+
+/* --- a8: surrogate network --------------------------------------------------
+ * A multilayer perceptron n_in -> width (SiLU) x depth -> 1 trained with AdamW
+ * on the mean squared error (the figure of merit of Sec. 6 as a function of
+ * the decomposition's free parameters).  Parameters are one flat FP32 vector:
+ * for each layer W [out][in] row-major then b [out]; the handle owns the
+ * parameters, gradients and AdamW moments on the device.
+ * mode GBD_MLP_BF16: hidden-layer products on BF16 MFMA (operands rounded to
+ * BF16, FP32 accumulate); GBD_MLP_FP32: the same products in FP32.  The head,
+ * loss, bias gradients and optimiser are FP32 in both modes.
+ *   x      device float [*][n_in] inputs; rows: optional device int32 [batch]
+ *          row indices into x (NULL = rows 0..batch-1); target likewise [*]
+ *   y      device float [batch] predictions
+ *   backward runs the forward pass, then leaves the gradients of
+ *          mean((y - target)^2) in the handle; loss_dev (optional, device) gets
+ *          the loss
+ *   adamw  one decoupled-weight-decay Adam step with bias correction
+ *   set_params uploads parameters and zeroes the optimiser state. */
+enum { GBD_MLP_FP32 = 0, GBD_MLP_BF16 = 1 };
+typedef struct gbd_mlp_s *gbd_mlp_t;
+int gbd_mlp_create(gbd_ctx_t ctx, gbd_mlp_t *out, int32_t n_in, int32_t width, int32_t depth, int32_t max_batch,
+                   int mode);
+void gbd_mlp_free(gbd_mlp_t m);
+int64_t gbd_mlp_num_params(gbd_mlp_t m);
+int gbd_mlp_set_params(gbd_mlp_t m, const float *params_host, int64_t n);
+int gbd_mlp_get_params(gbd_mlp_t m, float *params_host, int64_t n);
+int gbd_mlp_get_grads(gbd_mlp_t m, float *grads_host, int64_t n);
+int gbd_mlp_forward(gbd_mlp_t m, const float *x, const int32_t *rows, int32_t batch, float *y);
+int gbd_mlp_backward(gbd_mlp_t m, const float *x, const float *target, const int32_t *rows, int32_t batch,
+                     float *loss_dev);
+int gbd_mlp_adamw(gbd_mlp_t m, float lr, float beta1, float beta2, float eps, float weight_decay);
+
 #ifdef __cplusplus
 }
 #endif

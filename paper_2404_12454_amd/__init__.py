@@ -22,12 +22,15 @@ import numpy as np
 __all__ = [
     "GBD_FP64", "GBD_MIXED", "GbdError", "gbd_eval_opts", "library_path", "load_library",
     "gbd_ctx_create", "gbd_beamlets", "gbd_plane", "gbd_eval", "gbd_plan_create", "gbd_plan_setup",
-    "gbd_plan_eval", "gbd_plan_shape", "beamlets_from_scene", "plane_from_scene", "Context", "Beamlets",
-    "Plane", "Plan",
+    "gbd_plan_eval", "gbd_plan_shape", "gbd_airy", "gbd_eval_batch", "gbd_autotune", "gbd_autotune_batch",
+    "gbd_autotune_save", "gbd_autotune_load", "GBD_MLP_FP32", "GBD_MLP_BF16", "Mlp", "gbd_mlp_create", "beamlets_from_scene", "plane_from_scene",
+    "Context", "Beamlets", "Plane", "Plan",
 ]
 
 GBD_FP64 = 0
 GBD_MIXED = 1
+GBD_MLP_FP32 = 0
+GBD_MLP_BF16 = 1
 ERRORS = {0: "GBD_OK", -1: "GBD_EINVAL", -2: "GBD_ENOTSYMPLECTIC", -3: "GBD_EBRANCH", -4: "GBD_EPARALLEL",
           -5: "GBD_ENOMEM", -6: "GBD_EHIP", -7: "GBD_ERANGE"}
 
@@ -76,6 +79,22 @@ def load_library():
         "gbd_plan_eval": (ctypes.c_int, [P, P, ctypes.c_int, P, I64, P]),
         "gbd_plan_free": (None, [P]),
         "gbd_plan_shape": (ctypes.c_int, [P, P, ctypes.c_int, P, P]),
+        "gbd_airy": (ctypes.c_int, [P, P, D, D, D, P, I64]),
+        "gbd_autotune": (ctypes.c_int, [P, P, ctypes.c_int, I32, P, P]),
+        "gbd_mlp_create": (ctypes.c_int, [P, PP, I32, I32, I32, I32, ctypes.c_int]),
+        "gbd_mlp_free": (None, [P]),
+        "gbd_mlp_num_params": (I64, [P]),
+        "gbd_mlp_set_params": (ctypes.c_int, [P, P, I64]),
+        "gbd_mlp_get_params": (ctypes.c_int, [P, P, I64]),
+        "gbd_mlp_get_grads": (ctypes.c_int, [P, P, I64]),
+        "gbd_mlp_forward": (ctypes.c_int, [P, P, P, I32, P]),
+        "gbd_mlp_backward": (ctypes.c_int, [P, P, P, P, I32, P]),
+        "gbd_mlp_adamw": (ctypes.c_int, [P, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                         ctypes.c_float]),
+        "gbd_autotune_batch": (ctypes.c_int, [P, I32, P, P, P, I64, I32, P, P]),
+        "gbd_autotune_save": (ctypes.c_int, [P, ctypes.c_char_p]),
+        "gbd_autotune_load": (ctypes.c_int, [P, ctypes.c_char_p]),
+        "gbd_eval_batch": (ctypes.c_int, [P, I32, P, P, P, I64, P, I32, P, P, I64, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -269,3 +288,144 @@ def gbd_plan_eval(plan: Plan, precision: int = GBD_MIXED, out=None, opts=None):
 
 def gbd_plan_shape(plan: Plan, precision: int = GBD_MIXED, opts=None) -> dict:
     return plan.shape(precision, opts)
+
+
+def gbd_airy(ctx: Context, plane: Plane, D: float, f: float, lam: float, out=None):
+    """Reference irradiance (2 J1(v)/v)^2 on the plane grid, float32 [ny, nx] on the device."""
+    import torch
+    if out is None:
+        out = torch.empty((plane.ny, plane.nx), dtype=torch.float32, device=f"cuda:{ctx.device}")
+    if out.dtype != torch.float32 or not out.is_contiguous():
+        raise ValueError("out must be a contiguous float32 CUDA tensor")
+    _check(load_library().gbd_airy(ctx.handle, plane.handle, float(D), float(f), float(lam),
+                                   ctypes.c_void_p(out.data_ptr()), out.numel() * 4))
+    return out
+
+
+def gbd_eval_batch(ctx: Context, beamlets, planes, airy=None, zone_edges=None, fields: bool = False, opts=None):
+    """Evaluate many instances in one persistent launch (mixed precision).
+
+    Returns (metrics, fields): metrics is a float64 array [n_inst, 2 + n_zones]
+    (RMS, peak, zone RMS...) when ``airy`` (a float32 [ny, nx] device tensor)
+    is given, else None; fields is a list of complex64 [ny_i, nx_i] device
+    tensors (views of one allocation) when ``fields`` is true, else None."""
+    import torch
+    n = len(beamlets)
+    if len(planes) != n:
+        raise ValueError("beamlets and planes differ in length")
+    hb = (ctypes.c_void_p * max(n, 1))(*[b.handle.value for b in beamlets])
+    hp = (ctypes.c_void_p * max(n, 1))(*[p.handle.value for p in planes])
+    ze = None if zone_edges is None else _f64(zone_edges)
+    nz = 0 if ze is None else ze.size - 1
+    metrics = np.zeros((n, 2 + nz)) if airy is not None else None
+    fbuf = None
+    if fields:
+        total = sum(p.nx * p.ny for p in planes)
+        fbuf = torch.empty(max(total, 1), dtype=torch.complex64, device=f"cuda:{ctx.device}")
+    o = _opts(opts)
+    _check(load_library().gbd_eval_batch(
+        ctx.handle, n, hb, hp, None if airy is None else ctypes.c_void_p(airy.data_ptr()),
+        0 if airy is None else airy.numel() * 4, _p(ze), nz, _p(metrics),
+        None if fbuf is None else ctypes.c_void_p(fbuf.data_ptr()), 0 if fbuf is None else fbuf.numel() * 8,
+        None if o is None else ctypes.byref(o)))
+    out_fields = None
+    if fbuf is not None:
+        out_fields, off = [], 0
+        for p in planes:
+            m = p.nx * p.ny
+            out_fields.append(fbuf[off:off + m].view(p.ny, p.nx))
+            off += m
+    return metrics, out_fields
+
+
+def gbd_autotune(plan: Plan, precision: int = GBD_MIXED, reps: int = 3):
+    """Time every launch shape for this plan; the fastest is cached in the
+    context and returned as (opts dict, ms per evaluation)."""
+    best = gbd_eval_opts()
+    ms = ctypes.c_double()
+    _check(load_library().gbd_autotune(plan.ctx.handle, plan.handle, int(precision), int(reps), ctypes.byref(best),
+                                       ctypes.byref(ms)))
+    return dict(rows_per_lane=best.rows_per_lane, waves=best.waves, segments=best.segments), ms.value
+
+
+def gbd_autotune_batch(ctx: Context, beamlets, planes, airy, reps: int = 2):
+    n = len(beamlets)
+    hb = (ctypes.c_void_p * n)(*[b.handle.value for b in beamlets])
+    hp = (ctypes.c_void_p * n)(*[p.handle.value for p in planes])
+    best = gbd_eval_opts()
+    ms = ctypes.c_double()
+    _check(load_library().gbd_autotune_batch(ctx.handle, n, hb, hp, ctypes.c_void_p(airy.data_ptr()), airy.numel() * 4,
+                                             int(reps), ctypes.byref(best), ctypes.byref(ms)))
+    return dict(rows_per_lane=best.rows_per_lane, waves=best.waves), ms.value
+
+
+def gbd_autotune_save(ctx: Context, path: str):
+    _check(load_library().gbd_autotune_save(ctx.handle, os.fsencode(path)))
+
+
+def gbd_autotune_load(ctx: Context, path: str) -> int:
+    rc = load_library().gbd_autotune_load(ctx.handle, os.fsencode(path))
+    if rc < 0:
+        _check(rc)
+    return rc
+
+
+class Mlp:
+    """Surrogate network handle (gbd_mlp_* of the C ABI): n_in -> width (SiLU)
+    x depth -> 1, parameters/gradients/AdamW state on the device."""
+
+    def __init__(self, ctx: Context, n_in: int = 5, width: int = 128, depth: int = 3, max_batch: int = 256,
+                 mode: int = GBD_MLP_BF16):
+        self.ctx = ctx
+        self.n_in, self.width, self.depth, self.max_batch, self.mode = n_in, width, depth, max_batch, mode
+        h = ctypes.c_void_p()
+        _check(load_library().gbd_mlp_create(ctx.handle, ctypes.byref(h), n_in, width, depth, max_batch, mode))
+        self.handle = h
+        self.num_params = int(load_library().gbd_mlp_num_params(h))
+
+    def set_params(self, params):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        _check(load_library().gbd_mlp_set_params(self.handle, _p(p), p.size))
+
+    def get_params(self) -> np.ndarray:
+        p = np.empty(self.num_params, np.float32)
+        _check(load_library().gbd_mlp_get_params(self.handle, _p(p), p.size))
+        return p
+
+    def get_grads(self) -> np.ndarray:
+        g = np.empty(self.num_params, np.float32)
+        _check(load_library().gbd_mlp_get_grads(self.handle, _p(g), g.size))
+        return g
+
+    def forward(self, x, rows=None, batch=None, out=None):
+        """x: device float32 [*, n_in]; rows: optional device int32 indices."""
+        import torch
+        batch = int(rows.numel() if rows is not None else (x.shape[0] if batch is None else batch))
+        if out is None:
+            out = torch.empty(batch, dtype=torch.float32, device=x.device)
+        _check(load_library().gbd_mlp_forward(self.handle, ctypes.c_void_p(x.data_ptr()),
+                                              None if rows is None else ctypes.c_void_p(rows.data_ptr()), batch,
+                                              ctypes.c_void_p(out.data_ptr())))
+        return out
+
+    def backward(self, x, target, rows=None, loss_out=None):
+        batch = int(rows.numel() if rows is not None else x.shape[0])
+        _check(load_library().gbd_mlp_backward(self.handle, ctypes.c_void_p(x.data_ptr()),
+                                               ctypes.c_void_p(target.data_ptr()),
+                                               None if rows is None else ctypes.c_void_p(rows.data_ptr()), batch,
+                                               None if loss_out is None else ctypes.c_void_p(loss_out.data_ptr())))
+
+    def adamw(self, lr, beta1=0.9, beta2=0.999, eps=1e-8, weight_decay=0.0):
+        _check(load_library().gbd_mlp_adamw(self.handle, float(lr), float(beta1), float(beta2), float(eps),
+                                            float(weight_decay)))
+
+    def __del__(self):
+        try:
+            if self.handle.value:
+                load_library().gbd_mlp_free(self.handle)
+        except Exception:
+            pass
+
+
+def gbd_mlp_create(ctx: Context, n_in=5, width=128, depth=3, max_batch=256, mode=GBD_MLP_BF16) -> Mlp:
+    return Mlp(ctx, n_in, width, depth, max_batch, mode)

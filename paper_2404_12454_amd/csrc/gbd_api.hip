@@ -8,17 +8,47 @@
 #include <string.h>
 
 #include <algorithm>
+#include <chrono>
+#include <map>
 #include <new>
 #include <string>
 #include <vector>
 
 using namespace gbd;
 
+// grow-only device buffer
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+
+struct BatchWork {
+    DevBuf rec, inst, offs, eval, items, e0, part, metrics, flags;
+    uint32_t *host_flags = nullptr;  // pinned: status, bad instance
+};
+
+// autotuner cache key: (kind, precision, log2 N bucket, log2 M bucket)
+struct TuneKey {
+    int kind, precision, ln, lm;
+    bool operator<(const TuneKey &o) const {
+        if (kind != o.kind) return kind < o.kind;
+        if (precision != o.precision) return precision < o.precision;
+        if (ln != o.ln) return ln < o.ln;
+        return lm < o.lm;
+    }
+};
+struct TuneVal {
+    int rows, waves, seg_scale_pct;  // segments = auto count * pct / 100
+    double ms;
+};
+
 struct gbd_ctx_s {
     int device;
     hipStream_t stream;
     int cus;
     gbd_plan_s *own_plan;  // plan used by gbd_eval
+    BatchWork batch;
+    std::map<TuneKey, TuneVal> tuned;
 };
 
 struct gbd_beamlets_s {
@@ -43,6 +73,19 @@ struct gbd_plan_s {
     uint32_t *status_host;  // pinned
     void *scratch;
     size_t scratch_bytes;
+};
+
+struct gbd_mlp_s {
+    gbd_ctx_s *ctx;
+    int n_in, width, depth, max_batch, mode;
+    int64_t P;
+    std::vector<int64_t> woff, boff;  // per layer (depth hidden + head): W and b offsets in the flat vector
+    float *mem;                       // one allocation holding everything below
+    float *params, *grads, *m, *v;
+    float *Z, *H;                     // [depth][max_batch][width]
+    float *dz0, *dz1;                 // [max_batch][width]
+    float *xb, *yb, *yhat, *g, *loss;
+    int64_t step;
 };
 
 namespace {
@@ -102,11 +145,32 @@ struct Shape {
     int rows, waves, nseg;
 };
 
+int ilog2(int64_t v) {
+    int r = 0;
+    while (v > 1) {
+        v >>= 1;
+        r++;
+    }
+    return r;
+}
+
+TuneKey tune_key(int kind, int precision, int64_t n, int64_t m) { return TuneKey{kind, precision, ilog2(n), ilog2(m)}; }
+
 Shape choose_shape(const gbd_ctx_s *ctx, int precision, int64_t n, const PlaneGeom &pl, const gbd_eval_opts *o) {
     Shape s;
     s.rows = (precision == GBD_MIXED) ? 8 : 4;
     s.waves = 4;
     s.nseg = 0;
+    int seg_pct = 100;
+    const bool user = o && (o->rows_per_lane || o->waves || o->segments);
+    if (!user) {
+        auto it = ctx->tuned.find(tune_key(0, precision, n, (int64_t)pl.nx * pl.ny));
+        if (it != ctx->tuned.end()) {
+            s.rows = it->second.rows;
+            s.waves = it->second.waves;
+            seg_pct = it->second.seg_scale_pct;
+        }
+    }
     if (o) {
         if (o->rows_per_lane) s.rows = o->rows_per_lane;
         if (o->waves) s.waves = o->waves;
@@ -120,6 +184,7 @@ Shape choose_shape(const gbd_ctx_s *ctx, int precision, int64_t n, const PlaneGe
         const int64_t tiles = std::max<int64_t>(1, tx * ty);
         const int64_t target_blocks = (int64_t)ctx->cus * 4 * 6 / s.waves;
         int64_t seg = (target_blocks + tiles - 1) / tiles;
+        seg = std::max<int64_t>(1, seg * seg_pct / 100);
         seg = std::min<int64_t>(seg, std::max<int64_t>(1, n / 256));
         s.nseg = (int)std::max<int64_t>(1, std::min<int64_t>(seg, 1024));
     }
@@ -244,6 +309,26 @@ int plan_new(gbd_ctx_s *ctx, int64_t capacity, gbd_plan_s **out) {
     return GBD_OK;
 }
 
+int grow(DevBuf &b, size_t bytes, const char *what) {
+    if (bytes <= b.bytes) return GBD_OK;
+    if (b.p) (void)hipFree(b.p);
+    b.p = nullptr;
+    b.bytes = 0;
+    bytes = std::max<size_t>(bytes, 256);
+    hipError_t e = hipMalloc(&b.p, bytes);
+    if (e != hipSuccess) return hip_fail(e, what);
+    b.bytes = bytes;
+    return GBD_OK;
+}
+
+void batch_free(BatchWork &w) {
+    DevBuf *all[] = {&w.rec, &w.inst, &w.offs, &w.eval, &w.items, &w.e0, &w.part, &w.metrics, &w.flags};
+    for (DevBuf *b : all)
+        if (b->p) (void)hipFree(b->p);
+    if (w.host_flags) (void)hipHostFree(w.host_flags);
+    w = BatchWork();
+}
+
 }  // namespace
 
 extern "C" {
@@ -276,7 +361,9 @@ int gbd_ctx_set_stream(gbd_ctx_t ctx, void *hip_stream) {
 
 void gbd_ctx_destroy(gbd_ctx_t ctx) {
     if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
     plan_destroy(ctx->own_plan);
+    batch_free(ctx->batch);
     delete ctx;
 }
 
@@ -450,6 +537,523 @@ int gbd_eval(gbd_ctx_t ctx, gbd_beamlets_t b, gbd_plane_t p, int precision, void
     int rc = plan_setup_impl(ctx, ctx->own_plan, b, p);
     if (rc) return rc;
     return plan_eval_impl(ctx, ctx->own_plan, precision, field_out, out_bytes, opts);
+}
+
+int gbd_autotune(gbd_ctx_t ctx, gbd_plan_t plan, int precision, int32_t reps, gbd_eval_opts *best, double *best_ms) {
+    if (!ctx || !plan) return fail(GBD_EINVAL, "NULL argument");
+    if (!plan->ready) return fail(GBD_EINVAL, "gbd_autotune: plan has no valid setup");
+    if (precision != GBD_FP64 && precision != GBD_MIXED) return fail(GBD_EINVAL, "precision must be GBD_FP64 or GBD_MIXED");
+    if (reps < 1) reps = 1;
+    const int64_t M = (int64_t)plan->pl.nx * plan->pl.ny;
+    if (M == 0 || plan->n == 0) return fail(GBD_EINVAL, "nothing to tune (empty plan)");
+    int rc = ensure_device(ctx);
+    if (rc) return rc;
+    void *out = nullptr;
+    const int64_t out_bytes = M * (precision == GBD_FP64 ? 16 : 8);
+    HIP_TRY(hipMalloc(&out, (size_t)out_bytes), "hipMalloc(autotune output)");
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t he = hipEventCreate(&e0);
+    if (he == hipSuccess) he = hipEventCreate(&e1);
+    TuneVal bestv{0, 0, 100, 1e300};
+    static const int rows_c[] = {2, 4, 8}, waves_c[] = {1, 2, 4}, pct_c[] = {50, 100, 200};
+    for (int ri = 0; ri < 3 && he == hipSuccess && rc == GBD_OK; ri++)
+        for (int wi = 0; wi < 3 && he == hipSuccess && rc == GBD_OK; wi++)
+            for (int pi = 0; pi < 3 && he == hipSuccess && rc == GBD_OK; pi++) {
+                // a candidate is addressed through the cache so that choose_shape
+                // resolves its segment count exactly as a tuned call would
+                const TuneKey key = tune_key(0, precision, plan->n, M);
+                const auto saved = ctx->tuned.find(key) != ctx->tuned.end() ? ctx->tuned[key] : TuneVal{0, 0, 0, -1};
+                ctx->tuned[key] = TuneVal{rows_c[ri], waves_c[wi], pct_c[pi], 0.0};
+                rc = plan_eval_impl(ctx, plan, precision, out, out_bytes, nullptr);  // warm-up / scratch growth
+                double ms = 0.0;
+                if (rc == GBD_OK) {
+                    he = hipEventRecord(e0, ctx->stream);
+                    for (int r = 0; r < reps && rc == GBD_OK && he == hipSuccess; r++)
+                        rc = plan_eval_impl(ctx, plan, precision, out, out_bytes, nullptr);
+                    if (he == hipSuccess) he = hipEventRecord(e1, ctx->stream);
+                    if (he == hipSuccess) he = hipEventSynchronize(e1);
+                    float f = 0.f;
+                    if (he == hipSuccess) he = hipEventElapsedTime(&f, e0, e1);
+                    ms = f / reps;
+                }
+                if (saved.ms < 0)
+                    ctx->tuned.erase(key);
+                else
+                    ctx->tuned[key] = saved;
+                if (rc == GBD_OK && he == hipSuccess && ms < bestv.ms)
+                    bestv = TuneVal{rows_c[ri], waves_c[wi], pct_c[pi], ms};
+            }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(out);
+    if (rc) return rc;
+    if (he != hipSuccess) return hip_fail(he, "autotune timing");
+    ctx->tuned[tune_key(0, precision, plan->n, M)] = bestv;
+    if (best) {
+        const Shape s = choose_shape(ctx, precision, plan->n, plan->pl, nullptr);
+        const EvalGeom g = make_geom(plan->pl, plan->n, s);
+        *best = gbd_eval_opts{s.rows, s.waves, g.nseg, 0};
+    }
+    if (best_ms) *best_ms = bestv.ms;
+    return GBD_OK;
+}
+
+int gbd_autotune_save(gbd_ctx_t ctx, const char *path) {
+    if (!ctx || !path) return fail(GBD_EINVAL, "NULL argument");
+    FILE *f = fopen(path, "w");
+    if (!f) return fail(GBD_EINVAL, "cannot write %s", path);
+    fprintf(f, "# kind precision log2N log2M rows waves seg_pct ms\n");
+    for (const auto &kv : ctx->tuned)
+        fprintf(f, "%d %d %d %d %d %d %d %.6f\n", kv.first.kind, kv.first.precision, kv.first.ln, kv.first.lm,
+                kv.second.rows, kv.second.waves, kv.second.seg_scale_pct, kv.second.ms);
+    fclose(f);
+    return GBD_OK;
+}
+
+int gbd_autotune_load(gbd_ctx_t ctx, const char *path) {
+    if (!ctx || !path) return fail(GBD_EINVAL, "NULL argument");
+    FILE *f = fopen(path, "r");
+    if (!f) return fail(GBD_EINVAL, "cannot read %s", path);
+    char line[256];
+    int loaded = 0;
+    while (fgets(line, sizeof line, f)) {
+        if (line[0] == '#') continue;
+        TuneKey k;
+        TuneVal v;
+        if (sscanf(line, "%d %d %d %d %d %d %d %lf", &k.kind, &k.precision, &k.ln, &k.lm, &v.rows, &v.waves,
+                   &v.seg_scale_pct, &v.ms) == 8 &&
+            valid_shape(v.rows, v.waves) && v.seg_scale_pct > 0 && v.seg_scale_pct <= 10000) {
+            ctx->tuned[k] = v;
+            loaded++;
+        }
+    }
+    fclose(f);
+    return loaded;
+}
+
+int gbd_airy(gbd_ctx_t ctx, gbd_plane_t p, double D, double f, double lambda, float *out, int64_t out_bytes) {
+    if (!ctx || !p) return fail(GBD_EINVAL, "NULL argument");
+    if (!(D > 0.0) || !(f > 0.0) || !(lambda > 0.0) || !std::isfinite(D) || !std::isfinite(f) || !std::isfinite(lambda))
+        return fail(GBD_EINVAL, "D, f and lambda must be finite and > 0");
+    const int64_t M = (int64_t)p->g.nx * p->g.ny;
+    if (M == 0) return GBD_OK;
+    if (!out) return fail(GBD_EINVAL, "out is NULL");
+    if (out_bytes < M * 4) return fail(GBD_ERANGE, "out holds %lld bytes, %lld needed", (long long)out_bytes, (long long)(M * 4));
+    int rc = ensure_device(ctx);
+    if (rc) return rc;
+    const double vscale = M_PI * D / (lambda * f);
+    HIP_TRY(launch_airy(p->g.nx, p->g.ny, p->g.dx, p->g.dy, vscale, out, ctx->stream), "airy kernel launch");
+    return GBD_OK;
+}
+
+int gbd_eval_batch(gbd_ctx_t ctx, int32_t n_inst, const gbd_beamlets_t *bs, const gbd_plane_t *ps, const float *airy,
+                   int64_t airy_bytes, const double *zone_edges, int32_t n_zones, double *metrics_out,
+                   void *fields_out, int64_t fields_bytes, const gbd_eval_opts *opts) {
+    if (!ctx) return fail(GBD_EINVAL, "ctx is NULL");
+    if (n_inst < 0) return fail(GBD_EINVAL, "n_inst < 0");
+    if (n_inst == 0) return GBD_OK;
+    if (!bs || !ps) return fail(GBD_EINVAL, "beamlets/planes arrays are NULL");
+    if (n_zones < 0 || n_zones > kMaxZones) return fail(GBD_EINVAL, "n_zones must be in [0, %d]", kMaxZones);
+    if (n_zones > 0) {
+        if (!zone_edges) return fail(GBD_EINVAL, "zone_edges is NULL");
+        for (int z = 0; z <= n_zones; z++)
+            if (!(zone_edges[z] >= 0.0) || !std::isfinite(zone_edges[z]) || (z > 0 && zone_edges[z] < zone_edges[z - 1]))
+                return fail(GBD_EINVAL, "zone_edges must be finite, >= 0 and non-decreasing");
+    }
+    if (metrics_out && !airy) return fail(GBD_EINVAL, "metrics need the reference irradiance");
+    if (airy && !metrics_out) return fail(GBD_EINVAL, "metrics_out is NULL");
+    int rows = 8, waves = 4;
+    int64_t pairs = 0;
+    for (int32_t i = 0; i < n_inst; i++) {
+        if (!bs[i] || !ps[i]) return fail(GBD_EINVAL, "instance %d has a NULL handle", i);
+        pairs += bs[i]->dev.n * ((int64_t)ps[i]->g.nx * ps[i]->g.ny);
+    }
+    if (!(opts && (opts->rows_per_lane || opts->waves))) {
+        auto it = ctx->tuned.find(tune_key(1, GBD_MIXED, pairs, n_inst));
+        if (it != ctx->tuned.end()) {
+            rows = it->second.rows;
+            waves = it->second.waves;
+        }
+    }
+    if (opts) {
+        if (opts->rows_per_lane) rows = opts->rows_per_lane;
+        if (opts->waves) waves = opts->waves;
+    }
+    if (!valid_shape(rows, waves)) return fail(GBD_EINVAL, "unsupported rows_per_lane %d / waves %d", rows, waves);
+    int64_t total = 0, field_elems = 0, n_items = 0;
+    for (int32_t i = 0; i < n_inst; i++) {
+        const PlaneGeom &g = ps[i]->g;
+        if (airy) {
+            if (g.nx != ps[0]->g.nx || g.ny != ps[0]->g.ny)
+                return fail(GBD_EINVAL, "instances sharing a reference irradiance need equal grids (instance %d)", i);
+            if (airy_bytes < (int64_t)g.nx * g.ny * 4) return fail(GBD_ERANGE, "reference irradiance too small");
+        }
+        total += bs[i]->dev.n;
+        field_elems += (int64_t)g.nx * g.ny;
+        n_items += (int64_t)((g.nx + 63) / 64) * ((g.ny + waves * rows - 1) / (waves * rows));
+    }
+    if (fields_out && fields_bytes < field_elems * 8)
+        return fail(GBD_ERANGE, "fields_out holds %lld bytes, %lld needed", (long long)fields_bytes,
+                    (long long)(field_elems * 8));
+    if (n_items > 0x3fffffff) return fail(GBD_ERANGE, "too many work items");
+    int rc = ensure_device(ctx);
+    if (rc) return rc;
+
+    // host tables; the work list takes instances largest first (LPT), each
+    // instance's tiles contiguous and in order
+    std::vector<BatchInst> inst(n_inst);
+    std::vector<int64_t> offs(n_inst + 1, 0);
+    std::vector<BatchEval> ev(n_inst);
+    for (int32_t i = 0; i < n_inst; i++) {
+        const BeamletsDev &b = bs[i]->dev;
+        const PlaneGeom &g = ps[i]->g;
+        offs[i + 1] = offs[i] + b.n;
+        const double g0 = b.l0 / b.lam;
+        inst[i].b = b;
+        inst[i].pl = g;
+        inst[i].rec_off = offs[i];
+        inst[i].gturns = g0 - nearbyint(g0);
+        BatchEval &e = ev[i];
+        e.rec_off = offs[i];
+        e.n = b.n;
+        e.nx = g.nx;
+        e.ny = g.ny;
+        e.tiles_x = (g.nx + 63) / 64;
+        e.tiles_y = (g.ny + waves * rows - 1) / (waves * rows);
+        e.dx = g.dx;
+        e.dy = g.dy;
+        e.a0 = -0.5 * (g.nx - 1) * g.dx;
+        e.b0 = -0.5 * (g.ny - 1) * g.dy;
+    }
+    std::vector<int32_t> order(n_inst);
+    for (int32_t i = 0; i < n_inst; i++) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
+        return ev[x].n * ((int64_t)ev[x].nx * ev[x].ny) > ev[y].n * ((int64_t)ev[y].nx * ev[y].ny);
+    });
+    std::vector<int32_t> items;
+    items.reserve(2 * n_items);
+    int64_t foff = 0;
+    for (int32_t i = 0; i < n_inst; i++) {
+        ev[i].field_off = foff;
+        foff += (int64_t)ev[i].nx * ev[i].ny;
+    }
+    for (int32_t k = 0; k < n_inst; k++) {
+        const int32_t i = order[k];
+        ev[i].item_off = (int64_t)items.size() / 2;
+        const int32_t tiles = ev[i].tiles_x * ev[i].tiles_y;
+        for (int32_t t = 0; t < tiles; t++) {
+            items.push_back(i);
+            items.push_back(t);
+        }
+    }
+    const int PS = 2 + 2 * n_zones;
+    BatchWork &w = ctx->batch;
+    if ((rc = grow(w.rec, (size_t)std::max<int64_t>(total, 1) * sizeof(Rec32), "batch records")) ||
+        (rc = grow(w.inst, n_inst * sizeof(BatchInst), "batch table")) ||
+        (rc = grow(w.offs, (n_inst + 1) * sizeof(int64_t), "batch offsets")) ||
+        (rc = grow(w.eval, n_inst * sizeof(BatchEval), "batch table")) ||
+        (rc = grow(w.items, std::max<size_t>(items.size(), 2) * sizeof(int32_t), "batch work list")) ||
+        (rc = grow(w.e0, n_inst * sizeof(double2), "batch normalisation")) ||
+        (rc = grow(w.part, (size_t)std::max<int64_t>(n_items, 1) * PS * sizeof(double), "batch partials")) ||
+        (rc = grow(w.metrics, (size_t)n_inst * (2 + n_zones) * sizeof(double), "batch metrics")) ||
+        (rc = grow(w.flags, 4 * sizeof(uint32_t), "batch flags")))
+        return rc;
+    if (!w.host_flags) HIP_TRY(hipHostMalloc(&w.host_flags, 4 * sizeof(uint32_t), hipHostMallocDefault), "hipHostMalloc");
+    hipStream_t st = ctx->stream;
+    HIP_TRY(hipMemcpyAsync(w.inst.p, inst.data(), n_inst * sizeof(BatchInst), hipMemcpyHostToDevice, st), "table upload");
+    HIP_TRY(hipMemcpyAsync(w.offs.p, offs.data(), (n_inst + 1) * sizeof(int64_t), hipMemcpyHostToDevice, st), "table upload");
+    HIP_TRY(hipMemcpyAsync(w.eval.p, ev.data(), n_inst * sizeof(BatchEval), hipMemcpyHostToDevice, st), "table upload");
+    if (!items.empty())
+        HIP_TRY(hipMemcpyAsync(w.items.p, items.data(), items.size() * sizeof(int32_t), hipMemcpyHostToDevice, st),
+                "work list upload");
+    uint32_t *flags = static_cast<uint32_t *>(w.flags.p);  // [0] status, [1] first bad instance, [2] queue head
+    HIP_TRY(hipMemsetAsync(flags, 0, sizeof(uint32_t), st), "hipMemsetAsync");
+    HIP_TRY(hipMemsetAsync(flags + 1, 0x7f, sizeof(uint32_t), st), "hipMemsetAsync");
+    HIP_TRY(launch_batch_setup(static_cast<BatchInst *>(w.inst.p), static_cast<int64_t *>(w.offs.p), n_inst, total,
+                               static_cast<Rec32 *>(w.rec.p), flags, reinterpret_cast<int32_t *>(flags + 1), st),
+            "batch setup launch");
+    HIP_TRY(hipMemcpyAsync(w.host_flags, flags, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, st), "status copy");
+    HIP_TRY(hipStreamSynchronize(st), "hipStreamSynchronize");
+    const uint32_t stat = w.host_flags[0];
+    const int32_t bad = (int32_t)w.host_flags[1];
+    if (stat & FLAG_PARALLEL) return fail(GBD_EPARALLEL, "instance %d: a base ray is parallel to the plane", bad);
+    if (stat & FLAG_BRANCH) return fail(GBD_EBRANCH, "instance %d: an eigenvalue left the principal branch", bad);
+    if (stat & FLAG_NONFINITE) return fail(GBD_EINVAL, "instance %d: non-finite beamlet parameters", bad);
+
+    BatchArgs a;
+    a.inst = static_cast<const BatchEval *>(w.eval.p);
+    a.n_inst = n_inst;
+    a.items = static_cast<const int32_t *>(w.items.p);
+    a.n_items = (int32_t)n_items;
+    a.rec = static_cast<const Rec32 *>(w.rec.p);
+    a.e0 = static_cast<const double2 *>(w.e0.p);
+    a.airy = airy;
+    a.fields = static_cast<float2 *>(fields_out);
+    a.part = static_cast<double *>(w.part.p);
+    a.counter = flags + 2;
+    a.n_zones = n_zones;
+    for (int z = 0; z <= kMaxZones; z++)
+        a.zone_r2[z] = (z <= n_zones && n_zones > 0) ? zone_edges[z] * zone_edges[z] : 0.0;
+    if (airy)
+        HIP_TRY(launch_batch_e0(a.inst, n_inst, a.rec, static_cast<double2 *>(w.e0.p), st), "normalisation launch");
+    HIP_TRY(hipMemsetAsync(flags + 2, 0, sizeof(uint32_t), st), "hipMemsetAsync");
+    HIP_TRY(launch_batch_eval(rows, waves, ctx->cus, a, st), "batch eval launch");
+    if (airy) {
+        HIP_TRY(launch_batch_finalize(a.inst, n_inst, a.part, n_zones, static_cast<double *>(w.metrics.p), st),
+                "finalize launch");
+        HIP_TRY(hipMemcpyAsync(metrics_out, w.metrics.p, (size_t)n_inst * (2 + n_zones) * sizeof(double),
+                               hipMemcpyDeviceToHost, st),
+                "metrics copy");
+        HIP_TRY(hipStreamSynchronize(st), "hipStreamSynchronize");
+    }
+    return GBD_OK;
+}
+
+int gbd_autotune_batch(gbd_ctx_t ctx, int32_t n_inst, const gbd_beamlets_t *bs, const gbd_plane_t *ps,
+                       const float *airy, int64_t airy_bytes, int32_t reps, gbd_eval_opts *best, double *best_ms) {
+    if (!ctx || n_inst <= 0 || !bs || !ps || !airy) return fail(GBD_EINVAL, "bad argument");
+    if (reps < 1) reps = 1;
+    int64_t pairs = 0;
+    for (int32_t i = 0; i < n_inst; i++) {
+        if (!bs[i] || !ps[i]) return fail(GBD_EINVAL, "instance %d has a NULL handle", i);
+        pairs += bs[i]->dev.n * ((int64_t)ps[i]->g.nx * ps[i]->g.ny);
+    }
+    std::vector<double> metrics((size_t)n_inst * 2);
+    static const int rows_c[] = {2, 4, 8}, waves_c[] = {1, 2, 4};
+    TuneVal bestv{0, 0, 100, 1e300};
+    for (int ri = 0; ri < 3; ri++)
+        for (int wi = 0; wi < 3; wi++) {
+            gbd_eval_opts o{rows_c[ri], waves_c[wi], 0, 0};
+            int rc = gbd_eval_batch(ctx, n_inst, bs, ps, airy, airy_bytes, nullptr, 0, metrics.data(), nullptr, 0, &o);
+            if (rc) return rc;
+            const auto t0 = std::chrono::steady_clock::now();
+            for (int r = 0; r < reps; r++) {
+                rc = gbd_eval_batch(ctx, n_inst, bs, ps, airy, airy_bytes, nullptr, 0, metrics.data(), nullptr, 0, &o);
+                if (rc) return rc;
+            }
+            const double ms =
+                std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count() / reps;
+            if (ms < bestv.ms) bestv = TuneVal{rows_c[ri], waves_c[wi], 100, ms};
+        }
+    ctx->tuned[tune_key(1, GBD_MIXED, pairs, n_inst)] = bestv;
+    if (best) *best = gbd_eval_opts{bestv.rows, bestv.waves, 0, 0};
+    if (best_ms) *best_ms = bestv.ms;
+    return GBD_OK;
+}
+
+int gbd_mlp_create(gbd_ctx_t ctx, gbd_mlp_t *out, int32_t n_in, int32_t width, int32_t depth, int32_t max_batch,
+                   int mode) {
+    if (!ctx || !out) return fail(GBD_EINVAL, "NULL argument");
+    if (n_in < 1 || n_in > 64 || width < 1 || width > 1024 || depth < 1 || depth > 8 || max_batch < 1 ||
+        max_batch > 65536)
+        return fail(GBD_EINVAL, "unsupported network shape (n_in %d, width %d, depth %d, max_batch %d)", n_in, width,
+                    depth, max_batch);
+    if (mode != GBD_MLP_FP32 && mode != GBD_MLP_BF16) return fail(GBD_EINVAL, "mode must be GBD_MLP_FP32 or GBD_MLP_BF16");
+    int rc = ensure_device(ctx);
+    if (rc) return rc;
+    gbd_mlp_s *m = new (std::nothrow) gbd_mlp_s();
+    if (!m) return fail(GBD_ENOMEM, "host allocation failed");
+    m->ctx = ctx;
+    m->n_in = n_in;
+    m->width = width;
+    m->depth = depth;
+    m->max_batch = max_batch;
+    m->mode = mode;
+    int64_t k = 0, prev = n_in;
+    for (int l = 0; l <= depth; l++) {
+        const int64_t o = (l < depth) ? width : 1;
+        m->woff.push_back(k);
+        k += o * prev;
+        m->boff.push_back(k);
+        k += o;
+        prev = width;
+    }
+    m->P = k;
+    const int64_t act = (int64_t)depth * max_batch * width, bw = (int64_t)max_batch * width;
+    const int64_t total = 4 * m->P + 2 * act + 2 * bw + (int64_t)max_batch * (n_in + 3) + 1;
+    hipError_t e = hipMalloc(&m->mem, (size_t)total * sizeof(float));
+    if (e != hipSuccess) {
+        delete m;
+        return hip_fail(e, "hipMalloc(mlp)");
+    }
+    float *q = m->mem;
+    m->params = q; q += m->P;
+    m->grads = q; q += m->P;
+    m->m = q; q += m->P;
+    m->v = q; q += m->P;
+    m->Z = q; q += act;
+    m->H = q; q += act;
+    m->dz0 = q; q += bw;
+    m->dz1 = q; q += bw;
+    m->xb = q; q += (int64_t)max_batch * n_in;
+    m->yb = q; q += max_batch;
+    m->yhat = q; q += max_batch;
+    m->g = q; q += max_batch;
+    m->loss = q;
+    e = hipMemsetAsync(m->mem, 0, (size_t)total * sizeof(float), ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) {
+        (void)hipFree(m->mem);
+        delete m;
+        return hip_fail(e, "mlp init");
+    }
+    *out = m;
+    return GBD_OK;
+}
+
+void gbd_mlp_free(gbd_mlp_t m) {
+    if (!m) return;
+    if (m->mem) (void)hipFree(m->mem);
+    delete m;
+}
+
+int64_t gbd_mlp_num_params(gbd_mlp_t m) { return m ? m->P : (int64_t)fail(GBD_EINVAL, "NULL argument"); }
+
+int gbd_mlp_set_params(gbd_mlp_t m, const float *params, int64_t n) {
+    if (!m || !params) return fail(GBD_EINVAL, "NULL argument");
+    if (n != m->P) return fail(GBD_EINVAL, "expected %lld parameters, got %lld", (long long)m->P, (long long)n);
+    for (int64_t i = 0; i < n; i++)
+        if (!std::isfinite(params[i])) return fail(GBD_EINVAL, "non-finite parameter %lld", (long long)i);
+    int rc = ensure_device(m->ctx);
+    if (rc) return rc;
+    hipStream_t st = m->ctx->stream;
+    HIP_TRY(hipMemcpyAsync(m->params, params, n * sizeof(float), hipMemcpyHostToDevice, st), "parameter upload");
+    HIP_TRY(hipMemsetAsync(m->m, 0, 2 * n * sizeof(float), st), "optimiser reset");  // m and v are adjacent
+    HIP_TRY(hipStreamSynchronize(st), "hipStreamSynchronize");
+    m->step = 0;
+    return GBD_OK;
+}
+
+static int mlp_copy_out(gbd_mlp_t m, const float *src, float *dst, int64_t n) {
+    if (!m || !dst) return fail(GBD_EINVAL, "NULL argument");
+    if (n != m->P) return fail(GBD_EINVAL, "expected %lld values, got %lld", (long long)m->P, (long long)n);
+    int rc = ensure_device(m->ctx);
+    if (rc) return rc;
+    HIP_TRY(hipMemcpyAsync(dst, src, n * sizeof(float), hipMemcpyDeviceToHost, m->ctx->stream), "download");
+    HIP_TRY(hipStreamSynchronize(m->ctx->stream), "hipStreamSynchronize");
+    return GBD_OK;
+}
+
+int gbd_mlp_get_params(gbd_mlp_t m, float *params, int64_t n) { return mlp_copy_out(m, m ? m->params : nullptr, params, n); }
+int gbd_mlp_get_grads(gbd_mlp_t m, float *grads, int64_t n) { return mlp_copy_out(m, m ? m->grads : nullptr, grads, n); }
+
+// forward over the batch already gathered into m->xb; leaves Z, H, yhat
+static int mlp_forward_impl(gbd_mlp_t m, int B) {
+    hipStream_t st = m->ctx->stream;
+    const int W = m->width;
+    const float *in = m->xb;
+    int fan = m->n_in;
+    for (int l = 0; l < m->depth; l++) {
+        MlpGemm g{};
+        g.M = B;
+        g.N = W;
+        g.K = fan;
+        g.A = in;
+        g.sam = fan;
+        g.sak = 1;
+        g.B = m->params + m->woff[l];
+        g.sbk = 1;
+        g.sbn = fan;
+        g.bias = m->params + m->boff[l];
+        g.C = m->Z + (int64_t)l * m->max_batch * W;
+        g.H = m->H + (int64_t)l * m->max_batch * W;
+        g.epi = 0;
+        HIP_TRY(launch_mlp_gemm(m->mode == GBD_MLP_BF16, g, st), "mlp forward launch");
+        in = g.H;
+        fan = W;
+    }
+    HIP_TRY(launch_mlp_head_forward(in, m->params + m->woff[m->depth], m->params + m->boff[m->depth], B, W, m->yhat, st),
+            "mlp head launch");
+    return GBD_OK;
+}
+
+int gbd_mlp_forward(gbd_mlp_t m, const float *x, const int32_t *rows, int32_t batch, float *y) {
+    if (!m || !x || !y) return fail(GBD_EINVAL, "NULL argument");
+    if (batch < 0 || batch > m->max_batch) return fail(GBD_ERANGE, "batch %d outside [0, %d]", batch, m->max_batch);
+    if (batch == 0) return GBD_OK;
+    int rc = ensure_device(m->ctx);
+    if (rc) return rc;
+    hipStream_t st = m->ctx->stream;
+    HIP_TRY(launch_mlp_gather(x, nullptr, rows, batch, m->n_in, m->xb, nullptr, st), "mlp gather launch");
+    rc = mlp_forward_impl(m, batch);
+    if (rc) return rc;
+    HIP_TRY(hipMemcpyAsync(y, m->yhat, batch * sizeof(float), hipMemcpyDeviceToDevice, st), "mlp output copy");
+    return GBD_OK;
+}
+
+int gbd_mlp_backward(gbd_mlp_t m, const float *x, const float *target, const int32_t *rows, int32_t batch,
+                     float *loss_dev) {
+    if (!m || !x || !target) return fail(GBD_EINVAL, "NULL argument");
+    if (batch < 1 || batch > m->max_batch) return fail(GBD_ERANGE, "batch %d outside [1, %d]", batch, m->max_batch);
+    int rc = ensure_device(m->ctx);
+    if (rc) return rc;
+    hipStream_t st = m->ctx->stream;
+    const int W = m->width, B = batch, D = m->depth;
+    HIP_TRY(launch_mlp_gather(x, target, rows, B, m->n_in, m->xb, m->yb, st), "mlp gather launch");
+    rc = mlp_forward_impl(m, B);
+    if (rc) return rc;
+    const int64_t stride = (int64_t)m->max_batch * W;
+    const float *Hlast = m->H + (int64_t)(D - 1) * stride;
+    const float *Zlast = m->Z + (int64_t)(D - 1) * stride;
+    // head: loss, its gradient, head weights' gradient, dZ of the last hidden layer
+    HIP_TRY(launch_mlp_head_backward(m->yhat, m->yb, Hlast, m->params + m->woff[D], Zlast, B, W, m->g, m->loss,
+                                     m->grads + m->woff[D], m->dz0, st),
+            "mlp head backward launch");
+    float *dz = m->dz0, *dz_next = m->dz1;
+    for (int l = D - 1; l >= 0; l--) {
+        const int fan = (l == 0) ? m->n_in : W;
+        const float *Hprev = (l == 0) ? m->xb : m->H + (int64_t)(l - 1) * stride;
+        // dW_l[o][i] = sum_b dZ[b][o] Hprev[b][i]
+        MlpGemm gw{};
+        gw.M = W;
+        gw.N = fan;
+        gw.K = B;
+        gw.A = dz;
+        gw.sam = 1;
+        gw.sak = W;
+        gw.B = Hprev;
+        gw.sbk = fan;
+        gw.sbn = 1;
+        gw.C = m->grads + m->woff[l];
+        gw.epi = 2;
+        HIP_TRY(launch_mlp_gemm(m->mode == GBD_MLP_BF16, gw, st), "mlp weight-gradient launch");
+        HIP_TRY(launch_mlp_colsum(dz, B, W, m->grads + m->boff[l], st), "mlp bias-gradient launch");
+        if (l > 0) {
+            // dZ_{l-1}[b][i] = (sum_o dZ[b][o] W_l[o][i]) SiLU'(Z_{l-1}[b][i])
+            MlpGemm gh{};
+            gh.M = B;
+            gh.N = W;
+            gh.K = W;
+            gh.A = dz;
+            gh.sam = W;
+            gh.sak = 1;
+            gh.B = m->params + m->woff[l];
+            gh.sbk = W;
+            gh.sbn = 1;
+            gh.zmul = m->Z + (int64_t)(l - 1) * stride;
+            gh.C = dz_next;
+            gh.epi = 1;
+            HIP_TRY(launch_mlp_gemm(m->mode == GBD_MLP_BF16, gh, st), "mlp backward launch");
+            std::swap(dz, dz_next);
+        }
+    }
+    if (loss_dev) HIP_TRY(hipMemcpyAsync(loss_dev, m->loss, sizeof(float), hipMemcpyDeviceToDevice, st), "loss copy");
+    return GBD_OK;
+}
+
+int gbd_mlp_adamw(gbd_mlp_t m, float lr, float beta1, float beta2, float eps, float weight_decay) {
+    if (!m) return fail(GBD_EINVAL, "NULL argument");
+    if (!(lr >= 0.0f) || !(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) || !(eps >= 0.0f) ||
+        !(weight_decay >= 0.0f))
+        return fail(GBD_EINVAL, "invalid AdamW hyper-parameters");
+    int rc = ensure_device(m->ctx);
+    if (rc) return rc;
+    m->step++;
+    const float c1 = 1.0f - powf(beta1, (float)m->step), c2 = 1.0f - powf(beta2, (float)m->step);
+    HIP_TRY(launch_mlp_adamw(m->params, m->grads, m->m, m->v, m->P, lr, beta1, beta2, eps, weight_decay, c1, c2,
+                             m->ctx->stream),
+            "adamw launch");
+    return GBD_OK;
 }
 
 }  // extern "C"

@@ -1,0 +1,257 @@
+// Batched parameter sweep (Sec. 6): many independent GBD instances of uneven
+// size in one persistent launch, with the Airy figure of merit (Sec. 4.2 and
+// Sec. 6: RMS difference of the peak-normalised irradiance to the analytic
+// Airy pattern, plus annular zones) reduced in the same kernel.
+//
+//  batch_setup_kernel  per-beamlet FP64 setup over the concatenated beamlets
+//  batch_e0_kernel     field at each plane's origin (the normalisation point)
+//  batch_eval_kernel   persistent workgroups pull (instance, pixel tile) items,
+//                      largest instances first, from an atomic queue head;
+//                      each item sums all of its instance's beamlets (mixed
+//                      precision) and reduces its metric contribution with
+//                      wavefront shuffles
+//  batch_finalize      per instance, fixed-order sum of its items' partials
+//  airy_kernel         reference irradiance (2 J1(v)/v)^2 in FP64
+#include "gbd_device.h"
+
+namespace gbd {
+
+namespace {
+
+using namespace dev;
+
+__global__ void __launch_bounds__(256) batch_setup_kernel(const BatchInst *__restrict__ inst,
+                                                          const int64_t *__restrict__ offs, int32_t n_inst,
+                                                          int64_t total, Rec32 *__restrict__ rec,
+                                                          uint32_t *__restrict__ status, int32_t *__restrict__ bad) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= total) return;
+    // instance holding beamlet j: the last i with offs[i] <= j (empty instances skipped)
+    int lo = 0, hi = n_inst - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (offs[mid] <= j)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    const BatchInst &I = inst[lo];
+    const uint32_t flag = setup_one(I.b, I.pl, I.gturns, j - offs[lo], nullptr, rec + I.rec_off);
+    if (flag) {
+        atomicOr(status, flag);
+        atomicMin(bad, lo);
+    }
+}
+
+// E(0): the same mixed-precision phasor at plane coordinates (0, 0), summed
+// in FP64 with a fixed-order tree in LDS.
+__global__ void __launch_bounds__(256) batch_e0_kernel(const BatchEval *__restrict__ inst,
+                                                       const Rec32 *__restrict__ rec, double2 *__restrict__ e0) {
+    __shared__ double sre[256], sim[256];
+    const BatchEval I = inst[blockIdx.x];
+    double re = 0.0, im = 0.0;
+    for (int64_t j = threadIdx.x; j < I.n; j += 256) {
+        const Rec32 r = rec[I.rec_off + j];
+        const double da = -r.arho, db = -r.brho;
+        const double th = r.p[0] + da * (r.p[1] + r.p[3] * da) + db * (r.p[2] + r.p[4] * da + r.p[5] * db);
+        const float ph = (float)__builtin_amdgcn_fract(th);
+        const float daf = -r.arho_f, dbf = -r.brho_f;
+        const float L = r.m[0] + daf * (r.m[1] + r.m[3] * daf) + dbf * (r.m[2] + r.m[4] * daf + r.m[5] * dbf);
+        const float m = __builtin_amdgcn_exp2f(L);
+        re += (double)(m * __builtin_amdgcn_cosf(ph));
+        im += (double)(m * __builtin_amdgcn_sinf(ph));
+    }
+    sre[threadIdx.x] = re;
+    sim[threadIdx.x] = im;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) {
+            sre[threadIdx.x] += sre[threadIdx.x + h];
+            sim[threadIdx.x] += sim[threadIdx.x + h];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) e0[blockIdx.x] = make_double2(sre[0], sim[0]);
+}
+
+template <int WIDTH>
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+    for (int o = WIDTH / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, WIDTH);
+    return v;
+}
+template <int WIDTH>
+__device__ inline double wave_max(double v) {
+#pragma unroll
+    for (int o = WIDTH / 2; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, WIDTH));
+    return v;
+}
+
+template <int ROWS, int WAVES>
+__global__ void __launch_bounds__(64 * WAVES) batch_eval_kernel(BatchArgs A) {
+    constexpr int NQ = 2 + 2 * kMaxZones;
+    __shared__ Rec32 tile[kMixedTile];
+    __shared__ int s_item;
+    __shared__ double red[WAVES][NQ];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int PS = 2 + 2 * A.n_zones;
+    for (;;) {
+        if (threadIdx.x == 0) s_item = (int)atomicAdd(A.counter, 1u);
+        __syncthreads();
+        const int item = s_item;
+        __syncthreads();
+        if (item >= A.n_items) break;  // uniform across the workgroup
+        const int i = A.items[2 * item], t = A.items[2 * item + 1];
+        const BatchEval I = A.inst[i];
+        const int ty = t / I.tiles_x, tx = t - ty * I.tiles_x;
+        const int ix = tx * 64 + lane;
+        const int iy0 = (ty * WAVES + wv) * ROWS;
+        const double a = I.a0 + ix * I.dx;
+        const double b0 = I.b0 + iy0 * I.dy;
+        float s_re[ROWS], s_im[ROWS], c_re[ROWS], c_im[ROWS];
+#pragma unroll
+        for (int k = 0; k < ROWS; k++) s_re[k] = s_im[k] = c_re[k] = c_im[k] = 0.0f;
+        mixed_accumulate<ROWS, 64 * WAVES>(tile, A.rec + I.rec_off, 0, I.n, a, b0, I.dy, s_re, s_im, c_re, c_im);
+
+        // epilogue: optional field store, irradiance error against the reference
+        double q[NQ];
+#pragma unroll
+        for (int z = 0; z < NQ; z++) q[z] = 0.0;
+        const double2 e0 = A.e0[i];
+        const double n0 = e0.x * e0.x + e0.y * e0.y;
+        const double inv0 = n0 > 0.0 ? 1.0 / n0 : 0.0;  // an empty instance compares a zero field
+#pragma unroll
+        for (int k = 0; k < ROWS; k++) {
+            const int iy = iy0 + k;
+            if (ix < I.nx && iy < I.ny) {
+                const int64_t p = (int64_t)iy * I.nx + ix;
+                const float er = s_re[k] - c_re[k], ei = s_im[k] - c_im[k];
+                if (A.fields) A.fields[I.field_off + p] = make_float2(er, ei);
+                if (A.airy) {
+                    const double d = ((double)er * er + (double)ei * ei) * inv0 - (double)A.airy[p];
+                    q[0] += d * d;
+                    q[1] = fmax(q[1], fabs(d));
+                    const double bk = b0 + k * I.dy;
+                    const double r2 = a * a + bk * bk;
+#pragma unroll
+                    for (int z = 0; z < kMaxZones; z++)
+                        if (z < A.n_zones && r2 >= A.zone_r2[z] && r2 < A.zone_r2[z + 1]) {
+                            q[2 + 2 * z] += d * d;
+                            q[3 + 2 * z] += 1.0;
+                        }
+                }
+            }
+        }
+        if (A.airy) {
+#pragma unroll
+            for (int z = 0; z < NQ; z++) q[z] = (z == 1) ? wave_max<64>(q[z]) : wave_sum<64>(q[z]);
+            if (lane == 0)
+#pragma unroll
+                for (int z = 0; z < NQ; z++) red[wv][z] = q[z];
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                double *dst = A.part + (int64_t)item * PS;
+                for (int z = 0; z < PS; z++) {
+                    double v = red[0][z];
+                    for (int w = 1; w < WAVES; w++) v = (z == 1) ? fmax(v, red[w][z]) : v + red[w][z];
+                    dst[z] = v;
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void __launch_bounds__(64) batch_finalize_kernel(const BatchEval *__restrict__ inst, int32_t n_inst,
+                                                            const double *__restrict__ part, int32_t n_zones,
+                                                            double *__restrict__ metrics) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_inst) return;
+    const BatchEval I = inst[i];
+    const int PS = 2 + 2 * n_zones;
+    const int tiles = I.tiles_x * I.tiles_y;
+    double s = 0.0, mx = 0.0, zs[kMaxZones], zc[kMaxZones];
+    for (int z = 0; z < kMaxZones; z++) zs[z] = zc[z] = 0.0;
+    for (int t = 0; t < tiles; t++) {
+        const double *q = part + (I.item_off + t) * PS;
+        s += q[0];
+        mx = fmax(mx, q[1]);
+        for (int z = 0; z < n_zones; z++) {
+            zs[z] += q[2 + 2 * z];
+            zc[z] += q[3 + 2 * z];
+        }
+    }
+    double *o = metrics + (int64_t)i * (2 + n_zones);
+    const double M = (double)I.nx * I.ny;
+    o[0] = M > 0 ? sqrt(s / M) : 0.0;
+    o[1] = mx;
+    for (int z = 0; z < n_zones; z++) o[2 + z] = zc[z] > 0 ? sqrt(zs[z] / zc[z]) : 0.0;
+}
+
+// (2 J1(v)/v)^2 with v = vscale * r, r the distance from the plane origin.
+__global__ void __launch_bounds__(256) airy_kernel(int32_t nx, int32_t ny, double dx, double dy, double vscale,
+                                                   float *__restrict__ out) {
+    const int64_t M = (int64_t)nx * ny;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < M; p += (int64_t)gridDim.x * blockDim.x) {
+        const int iy = (int)(p / nx), ix = (int)(p - (int64_t)iy * nx);
+        const double a = (ix - 0.5 * (nx - 1)) * dx, b = (iy - 0.5 * (ny - 1)) * dy;
+        const double v = vscale * hypot(a, b);
+        const double f = v > 0.0 ? 2.0 * j1(v) / v : 1.0;
+        out[p] = (float)(f * f);
+    }
+}
+
+template <int ROWS, int WAVES>
+hipError_t launch_batch_eval_t(int cus, const BatchArgs &a, hipStream_t s) {
+    int per_cu = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_eval_kernel<ROWS, WAVES>, 64 * WAVES, 0);
+    if (e != hipSuccess) return e;
+    if (per_cu < 1) per_cu = 1;
+    const int grid = (int)min((int64_t)a.n_items, (int64_t)cus * per_cu);
+    if (grid <= 0) return hipSuccess;
+    batch_eval_kernel<ROWS, WAVES><<<grid, 64 * WAVES, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_batch_setup(const BatchInst *inst, const int64_t *offs, int32_t n_inst, int64_t total, Rec32 *rec,
+                              uint32_t *status, int32_t *bad, hipStream_t s) {
+    if (total == 0) return hipSuccess;
+    batch_setup_kernel<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(inst, offs, n_inst, total, rec, status, bad);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_e0(const BatchEval *inst, int32_t n_inst, const Rec32 *rec, double2 *e0, hipStream_t s) {
+    if (n_inst == 0) return hipSuccess;
+    batch_e0_kernel<<<n_inst, 256, 0, s>>>(inst, rec, e0);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_eval(int rows, int waves, int cus, const BatchArgs &a, hipStream_t s) {
+#define GBD_CASE(R, W) \
+    if (rows == R && waves == W) return launch_batch_eval_t<R, W>(cus, a, s);
+    GBD_CASE(1, 1) GBD_CASE(1, 2) GBD_CASE(1, 4)
+    GBD_CASE(2, 1) GBD_CASE(2, 2) GBD_CASE(2, 4)
+    GBD_CASE(4, 1) GBD_CASE(4, 2) GBD_CASE(4, 4)
+    GBD_CASE(8, 1) GBD_CASE(8, 2) GBD_CASE(8, 4)
+#undef GBD_CASE
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_batch_finalize(const BatchEval *inst, int32_t n_inst, const double *part, int32_t n_zones,
+                                 double *metrics, hipStream_t s) {
+    if (n_inst == 0) return hipSuccess;
+    batch_finalize_kernel<<<(n_inst + 63) / 64, 64, 0, s>>>(inst, n_inst, part, n_zones, metrics);
+    return hipGetLastError();
+}
+
+hipError_t launch_airy(int32_t nx, int32_t ny, double dx, double dy, double vscale, float *out, hipStream_t s) {
+    const int64_t M = (int64_t)nx * ny;
+    if (M == 0) return hipSuccess;
+    const int64_t blocks = min((M + 255) / 256, (int64_t)4096);
+    airy_kernel<<<(unsigned)blocks, 256, 0, s>>>(nx, ny, dx, dy, vscale, out);
+    return hipGetLastError();
+}
+
+}  // namespace gbd

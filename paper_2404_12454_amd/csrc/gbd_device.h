@@ -1,0 +1,281 @@
+// Device-side building blocks shared by the single-instance and batched
+// kernels: complex FP64 helpers, the per-beamlet FP64 setup, and the mixed
+// precision tile accumulation of the N x M evaluation.
+#pragma once
+
+#include "gbd_internal.h"
+
+#include <math.h>
+
+namespace gbd {
+namespace dev {
+
+constexpr double kPi = 3.14159265358979323846;
+
+struct cd {
+    double re, im;
+};
+__device__ inline cd mk(double r, double i) { return cd{r, i}; }
+__device__ inline cd add(cd a, cd b) { return cd{a.re + b.re, a.im + b.im}; }
+__device__ inline cd sub(cd a, cd b) { return cd{a.re - b.re, a.im - b.im}; }
+__device__ inline cd mul(cd a, cd b) { return cd{a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
+__device__ inline cd scl(cd a, double s) { return cd{a.re * s, a.im * s}; }
+__device__ inline cd cdiv(cd a, cd b) {
+    // Smith's algorithm: no overflow for widely scaled operands.
+    if (fabs(b.re) >= fabs(b.im)) {
+        const double r = b.im / b.re, d = b.re + b.im * r;
+        return cd{(a.re + a.im * r) / d, (a.im - a.re * r) / d};
+    }
+    const double r = b.re / b.im, d = b.re * r + b.im;
+    return cd{(a.re * r + a.im) / d, (a.im * r - a.re) / d};
+}
+// principal square root (cut on the negative real axis; the sign of a zero
+// imaginary part picks the side)
+__device__ inline cd csqrt_p(cd z) {
+    const double m = hypot(z.re, z.im);
+    if (m == 0.0) return cd{0.0, z.im};
+    if (z.re >= 0.0) {
+        const double t = sqrt(0.5 * (m + z.re));
+        return cd{t, z.im / (2.0 * t)};
+    }
+    const double t = sqrt(0.5 * (m - z.re));
+    return cd{fabs(z.im) / (2.0 * t), copysign(t, z.im)};
+}
+
+// Eigenvalues admitted on the principal-root branch: the open lower half
+// plane and the positive real axis (reached from 1 without crossing the cut).
+__device__ inline bool on_branch(cd mu) {
+    const double m = hypot(mu.re, mu.im);
+    const double tol = 1e-12 * m;
+    if (!(m > 0.0)) return false;
+    if (mu.im > tol) return false;
+    if (mu.im >= -tol && mu.re <= 0.0) return false;
+    return true;
+}
+
+// One beamlet propagated onto the plane; writes its phasor records (either
+// pointer may be null) and returns FLAG_* bits (0 = fine).
+__device__ inline uint32_t setup_one(const BeamletsDev &b, const PlaneGeom &pl, double gturns, int64_t j,
+                                     Rec64 *r64, Rec32 *r32) {
+    const double *M = b.abcd + (b.n_abcd == 1 ? 0 : 16 * j);
+    double A[2][2], B[2][2], C[2][2], D[2][2];
+#pragma unroll
+    for (int r = 0; r < 2; r++)
+#pragma unroll
+        for (int c = 0; c < 2; c++) {
+            A[r][c] = M[4 * r + c];
+            B[r][c] = M[4 * r + c + 2];
+            C[r][c] = M[4 * (r + 2) + c];
+            D[r][c] = M[4 * (r + 2) + c + 2];
+        }
+    const double r1[2] = {b.r1[2 * j], b.r1[2 * j + 1]};
+    const double t1[2] = {b.th1[2 * j], b.th1[2 * j + 1]};
+    const double w0 = b.w0[b.n_w0 == 1 ? 0 : j];
+    const cd amp = mk(b.amp[2 * j], b.amp[2 * j + 1]);
+    const double W = b.path[j];
+    const double lam = b.lam;
+
+    // base ray at the ABCD output plane (Appendix A, ab/cd laws)
+    double r2M[2], th[2];
+#pragma unroll
+    for (int r = 0; r < 2; r++) {
+        r2M[r] = A[r][0] * r1[0] + A[r][1] * r1[1] + B[r][0] * t1[0] + B[r][1] * t1[1];
+        th[r] = C[r][0] * r1[0] + C[r][1] * r1[1] + D[r][0] * t1[0] + D[r][1] * t1[1];
+    }
+    // where the base ray (r2M + z th, z) meets the plane
+    const double nd = pl.n[0] * th[0] + pl.n[1] * th[1] + pl.n[2];
+    const double dl = sqrt(th[0] * th[0] + th[1] * th[1] + 1.0);
+    Rec64 o64 = {};
+    Rec32 o32 = {};
+    uint32_t flag = 0;
+    if (!(fabs(nd) > 1e-6 * dl)) {
+        flag |= FLAG_PARALLEL;
+    } else {
+        const double z = (pl.n[0] * (pl.O[0] - r2M[0]) + pl.n[1] * (pl.O[1] - r2M[1]) + pl.n[2] * pl.O[2]) / nd;
+        const double X[3] = {r2M[0] + z * th[0] - pl.O[0], r2M[1] + z * th[1] - pl.O[1], z - pl.O[2]};
+        const double arho = pl.e1[0] * X[0] + pl.e1[1] * X[1] + pl.e1[2] * X[2];
+        const double brho = pl.e2[0] * X[0] + pl.e2[1] * X[1] + pl.e2[2] * X[2];
+
+        // system extended by free space z; Q1^-1 = -i kappa I
+        const double kappa = lam / (kPi * w0 * w0);
+        cd Mm[2][2], Nm[2][2];
+#pragma unroll
+        for (int r = 0; r < 2; r++)
+#pragma unroll
+            for (int c = 0; c < 2; c++) {
+                Mm[r][c] = mk(A[r][c] + z * C[r][c], -kappa * (B[r][c] + z * D[r][c]));
+                Nm[r][c] = mk(C[r][c], -kappa * D[r][c]);
+            }
+        // complex-curvature law Q^-1 = Nm Mm^-1 (closed-form 2x2 inverse), symmetrised
+        const cd det = sub(mul(Mm[0][0], Mm[1][1]), mul(Mm[0][1], Mm[1][0]));
+        cd Mi[2][2];
+        Mi[0][0] = cdiv(Mm[1][1], det);
+        Mi[1][1] = cdiv(Mm[0][0], det);
+        Mi[0][1] = cdiv(scl(Mm[0][1], -1.0), det);
+        Mi[1][0] = cdiv(scl(Mm[1][0], -1.0), det);
+        cd Q[2][2];
+#pragma unroll
+        for (int r = 0; r < 2; r++)
+#pragma unroll
+            for (int c = 0; c < 2; c++) Q[r][c] = add(mul(Nm[r][0], Mi[0][c]), mul(Nm[r][1], Mi[1][c]));
+        const cd qo = scl(add(Q[0][1], Q[1][0]), 0.5);
+        Q[0][1] = qo;
+        Q[1][0] = qo;
+        // amplitude det(Mm)^(-1/2) from the eigenvalues' principal roots
+        const cd tr = add(Mm[0][0], Mm[1][1]);
+        const cd disc = csqrt_p(sub(mul(tr, tr), scl(det, 4.0)));
+        const cd mu1 = scl(add(tr, disc), 0.5), mu2 = scl(sub(tr, disc), 0.5);
+        if (!on_branch(mu1) || !on_branch(mu2)) flag |= FLAG_BRANCH;
+        const cd gamma = cdiv(mk(1.0, 0.0), mul(csqrt_p(mu1), csqrt_p(mu2)));
+
+        // misalignment phase at the hit point, in turns (l0 handled by the host)
+        const double r2[2] = {r2M[0] + z * th[0], r2M[1] + z * th[1]};
+        const double S = 0.5 * (th[0] * r2[0] + th[1] * r2[1] - t1[0] * r1[0] - t1[1] * r1[1]);
+        const double tau = (z + W + S) / lam;
+
+        // plane basis seen from the beamlet: w = Pm d, zeta = ez . d
+        const double *e[2] = {pl.e1, pl.e2};
+        double Pm[2][2], ez[2];
+#pragma unroll
+        for (int c = 0; c < 2; c++) {
+            ez[c] = e[c][2];
+#pragma unroll
+            for (int r = 0; r < 2; r++) Pm[r][c] = e[c][r] - e[c][2] * th[r];
+        }
+        const cd trQ = add(Q[0][0], Q[1][1]);
+        const cd trQ2 = add(add(mul(Q[0][0], Q[0][0]), mul(Q[1][1], Q[1][1])), scl(mul(Q[0][1], Q[1][0]), 2.0));
+        // G = Pm^T Q Pm
+        cd QP[2][2], G[2][2];
+#pragma unroll
+        for (int r = 0; r < 2; r++)
+#pragma unroll
+            for (int c = 0; c < 2; c++) QP[r][c] = add(scl(Q[r][0], Pm[0][c]), scl(Q[r][1], Pm[1][c]));
+#pragma unroll
+        for (int r = 0; r < 2; r++)
+#pragma unroll
+            for (int c = 0; c < 2; c++) G[r][c] = add(scl(QP[0][c], Pm[0][r]), scl(QP[1][c], Pm[1][r]));
+        const double h = 1.0 + 0.5 * (th[0] * th[0] + th[1] * th[1]);
+        // (1 + |th|^2/2) ez + Pm^T th
+        const double lin[2] = {h * ez[0] + Pm[0][0] * th[0] + Pm[1][0] * th[1],
+                               h * ez[1] + Pm[0][1] * th[0] + Pm[1][1] * th[1]};
+        const double i4pi = 1.0 / (4.0 * kPi), i8pi = 1.0 / (8.0 * kPi), kh = kPi / lam;
+        double p[6], l[6];
+        const cd ag = mul(amp, gamma);
+        const double tred = tau - rint(tau);
+        const double p0 = atan2(ag.im, ag.re) / (2.0 * kPi) - tred - gturns;
+        // phase polynomial (turns)
+        p[0] = p0 - rint(p0);
+        p[1] = -lin[0] / lam - trQ.im * ez[0] * i4pi;
+        p[2] = -lin[1] / lam - trQ.im * ez[1] * i4pi;
+        p[3] = -G[0][0].re / (2.0 * lam) + trQ2.im * ez[0] * ez[0] * i8pi;
+        p[4] = 2.0 * (-G[0][1].re / (2.0 * lam) + trQ2.im * ez[0] * ez[1] * i8pi);
+        p[5] = -G[1][1].re / (2.0 * lam) + trQ2.im * ez[1] * ez[1] * i8pi;
+        // log-amplitude polynomial (natural log)
+        l[0] = log(hypot(ag.re, ag.im));
+        l[1] = -0.5 * trQ.re * ez[0];
+        l[2] = -0.5 * trQ.re * ez[1];
+        l[3] = kh * G[0][0].im + 0.25 * trQ2.re * ez[0] * ez[0];
+        l[4] = 2.0 * (kh * G[0][1].im + 0.25 * trQ2.re * ez[0] * ez[1]);
+        l[5] = kh * G[1][1].im + 0.25 * trQ2.re * ez[1] * ez[1];
+        bool fin = isfinite(arho) && isfinite(brho) && isfinite(ag.re) && isfinite(ag.im);
+#pragma unroll
+        for (int i = 0; i < 6; i++) fin = fin && isfinite(p[i]) && (i == 0 || isfinite(l[i]));
+        if (!fin) flag |= FLAG_NONFINITE;
+        o64.arho = arho;
+        o64.brho = brho;
+        o32.arho = arho;
+        o32.brho = brho;
+        o32.arho_f = (float)arho;
+        o32.brho_f = (float)brho;
+        const double il2 = 1.4426950408889634074;  // 1 / ln 2
+#pragma unroll
+        for (int i = 0; i < 6; i++) {
+            o64.p[i] = p[i];
+            o64.l[i] = l[i];
+            o32.p[i] = p[i];
+            o32.m[i] = (float)(l[i] * il2);
+        }
+    }
+    if (flag) {
+        // a refused beamlet contributes nothing (the host refuses the call anyway)
+        o64.l[0] = -INFINITY;
+        o32.m[0] = -INFINITY;
+    }
+    if (r64) r64[j] = o64;
+    if (r32) r32[j] = o32;
+    return flag;
+}
+
+__device__ inline void kahan(float &s, float &c, float x) {
+    const float y = x - c;
+    const float t = s + y;
+    c = (t - s) - y;
+    s = t;
+}
+
+constexpr int kMixedTile = 128;  // Rec32 records staged per LDS tile (12 KiB)
+
+// Mixed-precision sum over beamlets [jb, je) of the ROWS pixels a lane owns:
+// pixel k of the lane sits at plane coordinates (a, b0 + k dy).  The FP64
+// phase along the lane's column is a quadratic in k, reduced to turns with
+// fract and converted to FP32; the log2-amplitude is an FP32 quadratic in the
+// pixel's own row offset; v_exp_f32 computes 2^x and v_sin_f32 / v_cos_f32
+// take revolutions.  Per-tile FP32 sums are folded into Kahan-compensated
+// (s, c) accumulators, value = s - c.  All threads of the workgroup must call
+// this together (it synchronises on the LDS tile).
+template <int ROWS, int NT>
+__device__ inline void mixed_accumulate(Rec32 *tile, const Rec32 *__restrict__ rec, int64_t jb, int64_t je,
+                                        double a, double b0, double dy, float (&s_re)[ROWS], float (&s_im)[ROWS],
+                                        float (&c_re)[ROWS], float (&c_im)[ROWS]) {
+    const double dy2 = dy * dy;
+    const float af = (float)a, b0f = (float)b0, dyf = (float)dy;
+    float acc_re[ROWS], acc_im[ROWS];
+#pragma unroll
+    for (int k = 0; k < ROWS; k++) acc_re[k] = acc_im[k] = 0.0f;
+    for (int64_t j0 = jb; j0 < je; j0 += kMixedTile) {
+        const int cnt = (int)min((int64_t)kMixedTile, je - j0);
+        __syncthreads();
+        {
+            const float4 *src = reinterpret_cast<const float4 *>(rec + j0);
+            float4 *dst = reinterpret_cast<float4 *>(tile);
+            for (int i = threadIdx.x; i < cnt * 6; i += NT) dst[i] = src[i];
+        }
+        __syncthreads();
+        for (int jj = 0; jj < cnt; jj++) {
+            const Rec32 &r = tile[jj];
+            const double da = a - r.arho, db = b0 - r.brho;
+            const double q = r.p[2] + r.p[4] * da;
+            const double T0 = r.p[0] + da * (r.p[1] + r.p[3] * da) + db * (q + r.p[5] * db);
+            const double T1 = dy * (q + 2.0 * r.p[5] * db);
+            const double T2 = r.p[5] * dy2;
+            // log2-amplitude from each pixel's own row offset (an expansion
+            // in k would cancel catastrophically far from the spot)
+            const float daf = af - r.arho_f, dbf0 = b0f - r.brho_f;
+            const float qf = r.m[2] + r.m[4] * daf;
+            const float Uc = r.m[0] + daf * (r.m[1] + r.m[3] * daf);
+#pragma unroll
+            for (int k = 0; k < ROWS; k++) {
+                const double th = T0 + (double)k * (T1 + (double)k * T2);
+                const float ph = (float)__builtin_amdgcn_fract(th);
+                const float dbf = fmaf((float)k, dyf, dbf0);
+                const float L = Uc + dbf * (qf + r.m[5] * dbf);
+                const float m = __builtin_amdgcn_exp2f(L);
+                acc_re[k] = fmaf(m, __builtin_amdgcn_cosf(ph), acc_re[k]);
+                acc_im[k] = fmaf(m, __builtin_amdgcn_sinf(ph), acc_im[k]);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < ROWS; k++) {
+            kahan(s_re[k], c_re[k], acc_re[k]);
+            kahan(s_im[k], c_im[k], acc_im[k]);
+            acc_re[k] = acc_im[k] = 0.0f;
+        }
+    }
+}
+
+// XCD-aware work mapping: workgroup b runs on XCD (b mod 8); give each XCD a
+// contiguous range of work items.  The grid is padded to a multiple of 8.
+__device__ inline int work_item(int b, int G) { return (b & 7) * (G >> 3) + (b >> 3); }
+
+}  // namespace dev
+}  // namespace gbd

@@ -67,6 +67,77 @@ struct EvalGeom {
     int32_t work;        // tiles_x * tiles_y * nseg work items
 };
 
+// --- batched sweep ------------------------------------------------------
+constexpr int kMaxZones = 4;
+
+// per instance, for the batched setup kernel
+struct BatchInst {
+    BeamletsDev b;
+    PlaneGeom pl;
+    int64_t rec_off;
+    double gturns;
+};
+
+// per instance, for the batched evaluation
+struct BatchEval {
+    int64_t rec_off, n;
+    int32_t nx, ny, tiles_x, tiles_y;
+    double dx, dy, a0, b0;
+    int64_t item_off;   // first work item; an instance's items are contiguous, in tile order
+    int64_t field_off;  // element offset of this instance in the optional field output
+};
+
+struct BatchArgs {
+    const BatchEval *inst;
+    int32_t n_inst;
+    const int32_t *items;  // [n_items][2] = (instance, tile), largest instances first
+    int32_t n_items;
+    const Rec32 *rec;
+    const double2 *e0;     // field at the plane origin, per instance
+    const float *airy;     // reference irradiance [ny][nx] shared by all instances, or null
+    float2 *fields;        // optional complex64 fields
+    double *part;          // [n_items][2 + 2 n_zones] partial metrics
+    uint32_t *counter;     // work-queue head, zeroed before the launch
+    int32_t n_zones;
+    double zone_r2[kMaxZones + 1];  // squared radii bounding the annular zones
+};
+
+hipError_t launch_batch_setup(const BatchInst *inst, const int64_t *offs, int32_t n_inst, int64_t total,
+                              Rec32 *rec, uint32_t *status, int32_t *bad, hipStream_t s);
+hipError_t launch_batch_e0(const BatchEval *inst, int32_t n_inst, const Rec32 *rec, double2 *e0, hipStream_t s);
+hipError_t launch_batch_eval(int rows, int waves, int cus, const BatchArgs &a, hipStream_t s);
+hipError_t launch_batch_finalize(const BatchEval *inst, int32_t n_inst, const double *part, int32_t n_zones,
+                                 double *metrics, hipStream_t s);
+hipError_t launch_airy(int32_t nx, int32_t ny, double dx, double dy, double vscale, float *out, hipStream_t s);
+
+// --- surrogate network ----------------------------------------------------
+// C[m][n] = sum_k A(m, k) B(k, n) with A(m, k) = A[m sam + k sak] and
+// B(k, n) = B[k sbk + n sbn]; epilogue 0: C = acc + bias, H = SiLU(C);
+// 1: C = acc * SiLU'(zmul[m][n]); 2: C = acc.
+struct MlpGemm {
+    int M, N, K;
+    const float *A;
+    int64_t sam, sak;
+    const float *B;
+    int64_t sbk, sbn;
+    const float *bias;
+    const float *zmul;
+    float *C;
+    float *H;
+    int epi;
+};
+
+hipError_t launch_mlp_gemm(int bf16, const MlpGemm &g, hipStream_t s);
+hipError_t launch_mlp_gather(const float *X, const float *y, const int32_t *idx, int B, int n_in, float *Xb, float *yb,
+                             hipStream_t s);
+hipError_t launch_mlp_head_forward(const float *H, const float *w, const float *w0, int B, int W, float *yhat,
+                                   hipStream_t s);
+hipError_t launch_mlp_head_backward(const float *yhat, const float *y, const float *H, const float *w, const float *Z,
+                                    int B, int W, float *g, float *loss, float *dw, float *dZ, hipStream_t s);
+hipError_t launch_mlp_colsum(const float *dZ, int B, int W, float *db, hipStream_t s);
+hipError_t launch_mlp_adamw(float *p, const float *g, float *m, float *v, int64_t n, float lr, float b1, float b2,
+                            float eps, float wd, float c1, float c2, hipStream_t s);
+
 hipError_t launch_setup(const BeamletsDev &b, const PlaneGeom &pl, double global_turns, Rec64 *r64,
                         Rec32 *r32, uint32_t *status, hipStream_t s);
 
