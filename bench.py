@@ -24,17 +24,40 @@ import time
 
 METRIC = "beamlet·pixel evals/s (FP32+FP64-phase vs FP64) at ≤1e-5 rel field err"
 
-# Instruction-mix roofline of the mixed evaluation kernel (per beamlet-pixel
-# pair, per-lane-beamlet terms amortised over the rows a lane owns):
-#   FP64: 2 FMA (phase quadratic in the row step) + fract + cvt to f32 = 4
-#   FP32: 2 FMA (log2-amplitude) + 2 FMA (complex accumulate)          = 4
-#   transcendental: exp2, sin, cos                                     = 3
-# issue rates in lanes/CU/clock on gfx950: FP64 64 (78.6 TFLOP/s FP64 FMA),
-# FP32 128 (157.3 TFLOP/s FP32), transcendental 32 (measured).
+# Instruction-mix roofline of the mixed evaluation kernel.  Issue rates in
+# lanes per CU per clock from the chip's unit counts: FP64 64 (78.6 TFLOP/s
+# FP64 FMA), FP32 128 (157.3 TFLOP/s FP32), transcendental 32 (half the FP64
+# rate, measured on gfx950).  Instructions per beamlet-pixel pair for R rows
+# per lane (per-lane-beamlet work amortised over the R pixels it serves):
+#   stepped form: per pixel 2 transcendental (sin, cos in revolutions) and
+#     6 FP32 (2 phase-step FMA, 2 amplitude-step multiply, 2 accumulate FMA);
+#     per lane-beamlet 15 FP64 (offsets, phase quadratic, row slope,
+#     reductions, conversions), 7 further FP32 (log2-amplitude anchor and
+#     ratio; 4 of the per-pixel steps are not needed at the column's ends)
+#     and 2 exp2
+#   direct form: per pixel 4 FP64 (2 FMA, fract, cvt), 5 FP32 (3 amplitude,
+#     2 accumulate), 3 transcendental; per lane-beamlet 10 FP64 and 5 FP32
 CUS, CLOCK_HZ = 256, 2.4e9
-MIX = {"fp64": (4, 64), "fp32": (4, 128), "trans": (3, 32)}
-CYCLES_PER_PAIR = sum(n / r for n, r in MIX.values())
-PEAK_EVALS = CUS * CLOCK_HZ / CYCLES_PER_PAIR
+RATE = {"fp64": 64, "fp32": 128, "trans": 32}
+
+
+# HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE (x2.0)
+# and WRITE_SIZE (x1.0) runs, scale factors from a plain 256 MiB copy; valid
+# only for the kernel and launch they were taken on (else traffic is null).
+TRAFFIC = {("airy256_512", 16, 4, 24, 2): (2859.25 * 2.0 + 98304.0 * 1.0) * 1024}
+
+
+def instruction_mix(rows, variant):
+    R = float(rows)
+    if variant == 2:
+        return {"fp64": 15 / R, "fp32": (6 * R + 7) / R, "trans": (2 * R + 2) / R}
+    return {"fp64": (4 * R + 10) / R, "fp32": (5 * R + 5) / R, "trans": 3.0}
+
+
+def roofline_peak(rows, variant):
+    mix = instruction_mix(rows, variant)
+    cycles = sum(n / RATE[k] for k, n in mix.items())
+    return CUS * CLOCK_HZ / cycles, cycles, mix
 
 
 def main():
@@ -45,6 +68,8 @@ def main():
     ap.add_argument("--workload", default="airy256_512")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--fp64-steps", type=int, default=5)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one plain 256 MiB device copy (a known-size kernel for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build measures one GPU; multi-GPU runs are not part of it "
@@ -78,6 +103,13 @@ def main():
         if ev is not None:
             ev[1].record(stream)
 
+    if args.copy_calibration:
+        src = torch.empty(64 << 20, dtype=torch.float32, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     for _ in range(args.warmup):
         step(gbd.GBD_MIXED, out)
     torch.cuda.synchronize()
@@ -113,6 +145,7 @@ def main():
 
     shape = plan.shape(gbd.GBD_MIXED)
     achieved = N * M / (eval_ms_mean * 1e-3)
+    peak, cycles, mix = roofline_peak(shape["rows_per_lane"], shape["variant"])
     rec = {
         "metric": METRIC,
         "value": value,
@@ -129,9 +162,12 @@ def main():
         "config": {"workload": f"{args.workload}: {N} beamlets x {sc.plane.nx}x{sc.plane.ny} px, f/10, "
                                f"+-{sc.meta.get('half_span_lamF', 0):g} lamF, mixed precision",
                    "n_beamlets": N, "n_pixels": M, "launch": shape},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_EVALS, "unit": "evals/s",
-                     "frac": achieved / PEAK_EVALS, "traffic": None, "kernel": "eval_mixed_kernel",
-                     "kernel_ms": eval_ms_mean, "cycles_per_pair": CYCLES_PER_PAIR},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "evals/s",
+                     "frac": achieved / peak,
+                     "traffic": TRAFFIC.get((args.workload, shape["rows_per_lane"], shape["waves"],
+                                             shape["segments"], shape["variant"])),
+                     "kernel": "eval_mixed_kernel",
+                     "kernel_ms": eval_ms_mean, "cu_cycles_per_pair": cycles, "instructions_per_pair": mix},
         "setup_ms": ms_step - eval_ms_mean,
         "fp64": {"value": N * M / (eval64_ms * 1e-3), "eval_ms": eval64_ms,
                  "speedup_mixed_over_fp64": eval64_ms / eval_ms_mean},

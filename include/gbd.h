@@ -59,10 +59,15 @@ typedef struct gbd_plan_s *gbd_plan_t;
 /* Launch shape of the N x M evaluation kernels.  All-zero = library choice
  * (autotuner cache if filled, else built-in defaults). */
 typedef struct {
-    int32_t rows_per_lane;  /* pixels per lane along a detector column: 1, 2, 4 or 8 */
+    int32_t rows_per_lane;  /* pixels per lane along a detector column: 1, 2, 4, 8 (16: mixed only) */
     int32_t waves;          /* wavefronts per workgroup: 1, 2 or 4 */
     int32_t segments;       /* beamlet segments evaluated by separate workgroups, 0 = auto */
-    int32_t reserved;
+    int32_t variant;        /* mixed form only.  0 = auto; 1 = direct: FP64 phase and
+                               exp2 per pixel; 2 = stepped: FP64 phase per lane and beamlet
+                               with FP32 row steps, amplitude stepped by multiplication.
+                               Stepped is used (auto) or honoured (2) only when the setup
+                               finds every beamlet's log2-amplitude curvature below 0.1
+                               per row^2 (well-sampled spots); otherwise direct. */
 } gbd_eval_opts;
 
 /* --- context ------------------------------------------------------------ */
@@ -132,8 +137,9 @@ int gbd_plan_shape(gbd_ctx_t ctx, gbd_plan_t plan, int precision, const gbd_eval
 
 /* --- autotuner ---------------------------------------------------------------
  * gbd_autotune: times every launch shape of gbd_plan_eval for this plan and
- * precision (rows_per_lane in {2,4,8} x waves in {1,2,4} x segment counts of
- * 1/2, 1 and 2 times the automatic choice; `reps` timed launches each, HIP
+ * precision (rows_per_lane in {2,4,8} (and 16 for the mixed form) x waves in
+ * {1,2,4} x segment counts of
+ * 1/2, 1, 2 and 4 times the automatic choice; `reps` timed launches each, HIP
  * events on the context stream), stores the fastest in the context's cache
  * keyed by (precision, log2 N, log2 M) and returns it in *best (resolved
  * segment count) and its time in *best_ms.  Later calls with all-zero opts

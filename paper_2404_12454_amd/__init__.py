@@ -51,7 +51,7 @@ class GbdError(RuntimeError):
 
 class gbd_eval_opts(ctypes.Structure):
     _fields_ = [("rows_per_lane", ctypes.c_int32), ("waves", ctypes.c_int32), ("segments", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("variant", ctypes.c_int32)]
 
 
 def load_library():
@@ -210,7 +210,7 @@ def _opts(opts) -> Optional[gbd_eval_opts]:
     if isinstance(opts, gbd_eval_opts):
         return opts
     return gbd_eval_opts(int(opts.get("rows_per_lane", 0)), int(opts.get("waves", 0)),
-                         int(opts.get("segments", 0)), 0)
+                         int(opts.get("segments", 0)), int(opts.get("variant", 0)))
 
 
 def _out_tensor(ctx: Context, plane_nx: int, plane_ny: int, precision: int, out):
@@ -264,7 +264,7 @@ class Plan:
         r = gbd_eval_opts()
         _check(load_library().gbd_plan_shape(self.ctx.handle, self.handle, int(precision),
                                              None if o is None else ctypes.byref(o), ctypes.byref(r)))
-        return dict(rows_per_lane=r.rows_per_lane, waves=r.waves, segments=r.segments)
+        return dict(rows_per_lane=r.rows_per_lane, waves=r.waves, segments=r.segments, variant=r.variant)
 
     def __del__(self):
         try:
@@ -345,7 +345,8 @@ def gbd_autotune(plan: Plan, precision: int = GBD_MIXED, reps: int = 3):
     ms = ctypes.c_double()
     _check(load_library().gbd_autotune(plan.ctx.handle, plan.handle, int(precision), int(reps), ctypes.byref(best),
                                        ctypes.byref(ms)))
-    return dict(rows_per_lane=best.rows_per_lane, waves=best.waves, segments=best.segments), ms.value
+    return dict(rows_per_lane=best.rows_per_lane, waves=best.waves, segments=best.segments,
+                variant=best.variant), ms.value
 
 
 def gbd_autotune_batch(ctx: Context, beamlets, planes, airy, reps: int = 2):

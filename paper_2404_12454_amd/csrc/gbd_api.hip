@@ -67,6 +67,7 @@ struct gbd_plan_s {
     int64_t n;
     PlaneGeom pl;
     bool ready;
+    bool steep;  // some beamlet's amplitude is too steep for the stepped mixed kernel
     Rec64 *r64;
     Rec32 *r32;
     uint32_t *status_dev;
@@ -142,8 +143,15 @@ int ensure_device(gbd_ctx_s *ctx) {
 }
 
 struct Shape {
-    int rows, waves, nseg;
+    int rows, waves, nseg, step;
 };
+
+// stepped mixed kernel: requested or automatic, and safe for this setup
+int pick_step(int precision, bool steep, const gbd_eval_opts *o) {
+    if (precision != GBD_MIXED || steep) return 0;
+    const int v = o ? o->variant : 0;
+    return v == 1 ? 0 : 1;
+}
 
 int ilog2(int64_t v) {
     int r = 0;
@@ -158,9 +166,10 @@ TuneKey tune_key(int kind, int precision, int64_t n, int64_t m) { return TuneKey
 
 Shape choose_shape(const gbd_ctx_s *ctx, int precision, int64_t n, const PlaneGeom &pl, const gbd_eval_opts *o) {
     Shape s;
-    s.rows = (precision == GBD_MIXED) ? 8 : 4;
+    s.rows = (precision == GBD_MIXED) ? 16 : 4;
     s.waves = 4;
     s.nseg = 0;
+    s.step = 0;
     int seg_pct = 100;
     const bool user = o && (o->rows_per_lane || o->waves || o->segments);
     if (!user) {
@@ -191,8 +200,9 @@ Shape choose_shape(const gbd_ctx_s *ctx, int precision, int64_t n, const PlaneGe
     return s;
 }
 
-bool valid_shape(int rows, int waves) {
-    return (rows == 1 || rows == 2 || rows == 4 || rows == 8) && (waves == 1 || waves == 2 || waves == 4);
+bool valid_shape(int rows, int waves, int precision = GBD_MIXED) {
+    const bool r = rows == 1 || rows == 2 || rows == 4 || rows == 8 || (rows == 16 && precision == GBD_MIXED);
+    return r && (waves == 1 || waves == 2 || waves == 4);
 }
 
 EvalGeom make_geom(const PlaneGeom &pl, int64_t n, const Shape &s) {
@@ -226,7 +236,10 @@ int plan_eval_impl(gbd_ctx_s *ctx, gbd_plan_s *plan, int precision, void *out, i
     if (out_bytes < M * elem)
         return fail(GBD_ERANGE, "field_out holds %lld bytes, %lld needed", (long long)out_bytes, (long long)(M * elem));
     Shape s = choose_shape(ctx, precision, plan->n, plan->pl, opts);
-    if (!valid_shape(s.rows, s.waves)) return fail(GBD_EINVAL, "unsupported rows_per_lane %d / waves %d", s.rows, s.waves);
+    if (!valid_shape(s.rows, s.waves, precision))
+        return fail(GBD_EINVAL, "unsupported rows_per_lane %d / waves %d", s.rows, s.waves);
+    if (opts && (opts->variant < 0 || opts->variant > 2)) return fail(GBD_EINVAL, "variant must be 0, 1 or 2");
+    s.step = pick_step(precision, plan->steep, opts);
     int rc = ensure_device(ctx);
     if (rc) return rc;
     if (plan->n == 0) {
@@ -247,7 +260,7 @@ int plan_eval_impl(gbd_ctx_s *ctx, gbd_plan_s *plan, int precision, void *out, i
         }
     }
     const void *rec = precision == GBD_FP64 ? (const void *)plan->r64 : (const void *)plan->r32;
-    HIP_TRY(launch_eval(precision, s.rows, s.waves, g, rec, plan->scratch, out, ctx->stream), "eval kernel launch");
+    HIP_TRY(launch_eval(precision, s.rows, s.waves, s.step, g, rec, plan->scratch, out, ctx->stream), "eval kernel launch");
     if (g.nseg > 1) HIP_TRY(launch_reduce(precision, g, plan->scratch, out, ctx->stream), "reduce kernel launch");
     return GBD_OK;
 }
@@ -258,6 +271,7 @@ int plan_setup_impl(gbd_ctx_s *ctx, gbd_plan_s *plan, gbd_beamlets_s *b, gbd_pla
     int rc = ensure_device(ctx);
     if (rc) return rc;
     plan->ready = false;
+    plan->steep = false;
     plan->n = b->dev.n;
     plan->pl = p->g;
     if (b->dev.n > 0) {
@@ -276,6 +290,7 @@ int plan_setup_impl(gbd_ctx_s *ctx, gbd_plan_s *plan, gbd_beamlets_s *b, gbd_pla
         if (st & FLAG_BRANCH)
             return fail(GBD_EBRANCH, "an eigenvalue of A + B Q1^-1 lies off the principal branch (inverting system)");
         if (st & FLAG_NONFINITE) return fail(GBD_EINVAL, "non-finite beamlet parameters after propagation");
+        plan->steep = (st & FLAG_STEEP) != 0;
     }
     plan->ready = true;
     return GBD_OK;
@@ -513,7 +528,7 @@ int gbd_plan_shape(gbd_ctx_t ctx, gbd_plan_t plan, int precision, const gbd_eval
     resolved->rows_per_lane = s.rows;
     resolved->waves = s.waves;
     resolved->segments = g.nseg;
-    resolved->reserved = 0;
+    resolved->variant = precision == GBD_MIXED ? (pick_step(precision, plan->steep, opts) ? 2 : 1) : 0;
     return GBD_OK;
 }
 
@@ -555,10 +570,11 @@ int gbd_autotune(gbd_ctx_t ctx, gbd_plan_t plan, int precision, int32_t reps, gb
     hipError_t he = hipEventCreate(&e0);
     if (he == hipSuccess) he = hipEventCreate(&e1);
     TuneVal bestv{0, 0, 100, 1e300};
-    static const int rows_c[] = {2, 4, 8}, waves_c[] = {1, 2, 4}, pct_c[] = {50, 100, 200};
-    for (int ri = 0; ri < 3 && he == hipSuccess && rc == GBD_OK; ri++)
+    static const int rows_c[] = {2, 4, 8, 16}, waves_c[] = {1, 2, 4}, pct_c[] = {50, 100, 200, 400};
+    const int n_rows = precision == GBD_MIXED ? 4 : 3;
+    for (int ri = 0; ri < n_rows && he == hipSuccess && rc == GBD_OK; ri++)
         for (int wi = 0; wi < 3 && he == hipSuccess && rc == GBD_OK; wi++)
-            for (int pi = 0; pi < 3 && he == hipSuccess && rc == GBD_OK; pi++) {
+            for (int pi = 0; pi < 4 && he == hipSuccess && rc == GBD_OK; pi++) {
                 // a candidate is addressed through the cache so that choose_shape
                 // resolves its segment count exactly as a tuned call would
                 const TuneKey key = tune_key(0, precision, plan->n, M);
@@ -592,7 +608,7 @@ int gbd_autotune(gbd_ctx_t ctx, gbd_plan_t plan, int precision, int32_t reps, gb
     if (best) {
         const Shape s = choose_shape(ctx, precision, plan->n, plan->pl, nullptr);
         const EvalGeom g = make_geom(plan->pl, plan->n, s);
-        *best = gbd_eval_opts{s.rows, s.waves, g.nseg, 0};
+        *best = gbd_eval_opts{s.rows, s.waves, g.nseg, pick_step(precision, plan->steep, nullptr) ? 2 : (precision == GBD_MIXED ? 1 : 0)};
     }
     if (best_ms) *best_ms = bestv.ms;
     return GBD_OK;
@@ -622,7 +638,7 @@ int gbd_autotune_load(gbd_ctx_t ctx, const char *path) {
         TuneVal v;
         if (sscanf(line, "%d %d %d %d %d %d %d %lf", &k.kind, &k.precision, &k.ln, &k.lm, &v.rows, &v.waves,
                    &v.seg_scale_pct, &v.ms) == 8 &&
-            valid_shape(v.rows, v.waves) && v.seg_scale_pct > 0 && v.seg_scale_pct <= 10000) {
+            valid_shape(v.rows, v.waves, k.precision) && v.seg_scale_pct > 0 && v.seg_scale_pct <= 10000) {
             ctx->tuned[k] = v;
             loaded++;
         }
@@ -662,7 +678,7 @@ int gbd_eval_batch(gbd_ctx_t ctx, int32_t n_inst, const gbd_beamlets_t *bs, cons
     }
     if (metrics_out && !airy) return fail(GBD_EINVAL, "metrics need the reference irradiance");
     if (airy && !metrics_out) return fail(GBD_EINVAL, "metrics_out is NULL");
-    int rows = 8, waves = 4;
+    int rows = 16, waves = 4;
     int64_t pairs = 0;
     for (int32_t i = 0; i < n_inst; i++) {
         if (!bs[i] || !ps[i]) return fail(GBD_EINVAL, "instance %d has a NULL handle", i);
@@ -779,6 +795,8 @@ int gbd_eval_batch(gbd_ctx_t ctx, int32_t n_inst, const gbd_beamlets_t *bs, cons
     if (stat & FLAG_PARALLEL) return fail(GBD_EPARALLEL, "instance %d: a base ray is parallel to the plane", bad);
     if (stat & FLAG_BRANCH) return fail(GBD_EBRANCH, "instance %d: an eigenvalue left the principal branch", bad);
     if (stat & FLAG_NONFINITE) return fail(GBD_EINVAL, "instance %d: non-finite beamlet parameters", bad);
+    if (opts && (opts->variant < 0 || opts->variant > 2)) return fail(GBD_EINVAL, "variant must be 0, 1 or 2");
+    const int step = pick_step(GBD_MIXED, (stat & FLAG_STEEP) != 0, opts);
 
     BatchArgs a;
     a.inst = static_cast<const BatchEval *>(w.eval.p);
@@ -797,7 +815,7 @@ int gbd_eval_batch(gbd_ctx_t ctx, int32_t n_inst, const gbd_beamlets_t *bs, cons
     if (airy)
         HIP_TRY(launch_batch_e0(a.inst, n_inst, a.rec, static_cast<double2 *>(w.e0.p), st), "normalisation launch");
     HIP_TRY(hipMemsetAsync(flags + 2, 0, sizeof(uint32_t), st), "hipMemsetAsync");
-    HIP_TRY(launch_batch_eval(rows, waves, ctx->cus, a, st), "batch eval launch");
+    HIP_TRY(launch_batch_eval(rows, waves, step, ctx->cus, a, st), "batch eval launch");
     if (airy) {
         HIP_TRY(launch_batch_finalize(a.inst, n_inst, a.part, n_zones, static_cast<double *>(w.metrics.p), st),
                 "finalize launch");
@@ -819,9 +837,9 @@ int gbd_autotune_batch(gbd_ctx_t ctx, int32_t n_inst, const gbd_beamlets_t *bs, 
         pairs += bs[i]->dev.n * ((int64_t)ps[i]->g.nx * ps[i]->g.ny);
     }
     std::vector<double> metrics((size_t)n_inst * 2);
-    static const int rows_c[] = {2, 4, 8}, waves_c[] = {1, 2, 4};
+    static const int rows_c[] = {2, 4, 8, 16}, waves_c[] = {1, 2, 4};
     TuneVal bestv{0, 0, 100, 1e300};
-    for (int ri = 0; ri < 3; ri++)
+    for (int ri = 0; ri < 4; ri++)
         for (int wi = 0; wi < 3; wi++) {
             gbd_eval_opts o{rows_c[ri], waves_c[wi], 0, 0};
             int rc = gbd_eval_batch(ctx, n_inst, bs, ps, airy, airy_bytes, nullptr, 0, metrics.data(), nullptr, 0, &o);

@@ -37,10 +37,8 @@ __global__ void __launch_bounds__(256) batch_setup_kernel(const BatchInst *__res
     }
     const BatchInst &I = inst[lo];
     const uint32_t flag = setup_one(I.b, I.pl, I.gturns, j - offs[lo], nullptr, rec + I.rec_off);
-    if (flag) {
-        atomicOr(status, flag);
-        atomicMin(bad, lo);
-    }
+    if (flag) atomicOr(status, flag);
+    if (flag & FLAG_ERRORS) atomicMin(bad, lo);
 }
 
 // E(0): the same mixed-precision phasor at plane coordinates (0, 0), summed
@@ -87,7 +85,7 @@ __device__ inline double wave_max(double v) {
     return v;
 }
 
-template <int ROWS, int WAVES>
+template <int ROWS, int WAVES, int STEP>
 __global__ void __launch_bounds__(64 * WAVES) batch_eval_kernel(BatchArgs A) {
     constexpr int NQ = 2 + 2 * kMaxZones;
     __shared__ Rec32 tile[kMixedTile];
@@ -111,7 +109,11 @@ __global__ void __launch_bounds__(64 * WAVES) batch_eval_kernel(BatchArgs A) {
         float s_re[ROWS], s_im[ROWS], c_re[ROWS], c_im[ROWS];
 #pragma unroll
         for (int k = 0; k < ROWS; k++) s_re[k] = s_im[k] = c_re[k] = c_im[k] = 0.0f;
-        mixed_accumulate<ROWS, 64 * WAVES>(tile, A.rec + I.rec_off, 0, I.n, a, b0, I.dy, s_re, s_im, c_re, c_im);
+        if (STEP)
+            mixed_accumulate_step<ROWS, 64 * WAVES>(tile, A.rec + I.rec_off, 0, I.n, a, b0, I.dy, s_re, s_im, c_re,
+                                                    c_im);
+        else
+            mixed_accumulate<ROWS, 64 * WAVES>(tile, A.rec + I.rec_off, 0, I.n, a, b0, I.dy, s_re, s_im, c_re, c_im);
 
         // epilogue: optional field store, irradiance error against the reference
         double q[NQ];
@@ -201,15 +203,16 @@ __global__ void __launch_bounds__(256) airy_kernel(int32_t nx, int32_t ny, doubl
     }
 }
 
-template <int ROWS, int WAVES>
+template <int ROWS, int WAVES, int STEP>
 hipError_t launch_batch_eval_t(int cus, const BatchArgs &a, hipStream_t s) {
     int per_cu = 0;
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_eval_kernel<ROWS, WAVES>, 64 * WAVES, 0);
+    hipError_t e =
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_eval_kernel<ROWS, WAVES, STEP>, 64 * WAVES, 0);
     if (e != hipSuccess) return e;
     if (per_cu < 1) per_cu = 1;
     const int grid = (int)min((int64_t)a.n_items, (int64_t)cus * per_cu);
     if (grid <= 0) return hipSuccess;
-    batch_eval_kernel<ROWS, WAVES><<<grid, 64 * WAVES, 0, s>>>(a);
+    batch_eval_kernel<ROWS, WAVES, STEP><<<grid, 64 * WAVES, 0, s>>>(a);
     return hipGetLastError();
 }
 
@@ -228,13 +231,15 @@ hipError_t launch_batch_e0(const BatchEval *inst, int32_t n_inst, const Rec32 *r
     return hipGetLastError();
 }
 
-hipError_t launch_batch_eval(int rows, int waves, int cus, const BatchArgs &a, hipStream_t s) {
-#define GBD_CASE(R, W) \
-    if (rows == R && waves == W) return launch_batch_eval_t<R, W>(cus, a, s);
+hipError_t launch_batch_eval(int rows, int waves, int step, int cus, const BatchArgs &a, hipStream_t s) {
+#define GBD_CASE(R, W)                                                              \
+    if (rows == R && waves == W)                                                    \
+        return step ? launch_batch_eval_t<R, W, 1>(cus, a, s) : launch_batch_eval_t<R, W, 0>(cus, a, s);
     GBD_CASE(1, 1) GBD_CASE(1, 2) GBD_CASE(1, 4)
     GBD_CASE(2, 1) GBD_CASE(2, 2) GBD_CASE(2, 4)
     GBD_CASE(4, 1) GBD_CASE(4, 2) GBD_CASE(4, 4)
     GBD_CASE(8, 1) GBD_CASE(8, 2) GBD_CASE(8, 4)
+    GBD_CASE(16, 1) GBD_CASE(16, 2) GBD_CASE(16, 4)
 #undef GBD_CASE
     return hipErrorInvalidValue;
 }

@@ -53,6 +53,8 @@ __device__ inline bool on_branch(cd mu) {
     return true;
 }
 
+__device__ inline double il2_dev() { return 1.4426950408889634074; }  // 1 / ln 2
+
 // One beamlet propagated onto the plane; writes its phasor records (either
 // pointer may be null) and returns FLAG_* bits (0 = fine).
 __device__ inline uint32_t setup_one(const BeamletsDev &b, const PlaneGeom &pl, double gturns, int64_t j,
@@ -181,6 +183,7 @@ __device__ inline uint32_t setup_one(const BeamletsDev &b, const PlaneGeom &pl, 
 #pragma unroll
         for (int i = 0; i < 6; i++) fin = fin && isfinite(p[i]) && (i == 0 || isfinite(l[i]));
         if (!fin) flag |= FLAG_NONFINITE;
+        if (fabs(l[5]) * il2_dev() * pl.dy * pl.dy > kStepCurvature) flag |= FLAG_STEEP;
         o64.arho = arho;
         o64.brho = brho;
         o32.arho = arho;
@@ -195,8 +198,14 @@ __device__ inline uint32_t setup_one(const BeamletsDev &b, const PlaneGeom &pl, 
             o32.p[i] = p[i];
             o32.m[i] = (float)(l[i] * il2);
         }
+        // row-step terms of the stepped kernel (k^2 t2 with k integer: reduce mod 1)
+        const double t2 = p[5] * pl.dy * pl.dy;
+        o32.t2 = (float)(t2 - rint(t2));
+        const float dyf = (float)pl.dy;
+        o32.u2 = o32.m[5] * (dyf * dyf);
+        o32.s2 = exp2f(fminf(2.0f * o32.u2, 1.0f));
     }
-    if (flag) {
+    if (flag & FLAG_ERRORS) {
         // a refused beamlet contributes nothing (the host refuses the call anyway)
         o64.l[0] = -INFINITY;
         o32.m[0] = -INFINITY;
@@ -213,7 +222,7 @@ __device__ inline void kahan(float &s, float &c, float x) {
     s = t;
 }
 
-constexpr int kMixedTile = 128;  // Rec32 records staged per LDS tile (12 KiB)
+constexpr int kMixedTile = 128;  // Rec32 records staged per LDS tile (14 KiB)
 
 // Mixed-precision sum over beamlets [jb, je) of the ROWS pixels a lane owns:
 // pixel k of the lane sits at plane coordinates (a, b0 + k dy).  The FP64
@@ -238,7 +247,7 @@ __device__ inline void mixed_accumulate(Rec32 *tile, const Rec32 *__restrict__ r
         {
             const float4 *src = reinterpret_cast<const float4 *>(rec + j0);
             float4 *dst = reinterpret_cast<float4 *>(tile);
-            for (int i = threadIdx.x; i < cnt * 6; i += NT) dst[i] = src[i];
+            for (int i = threadIdx.x; i < cnt * kRec32Vec4; i += NT) dst[i] = src[i];
         }
         __syncthreads();
         for (int jj = 0; jj < cnt; jj++) {
@@ -262,6 +271,68 @@ __device__ inline void mixed_accumulate(Rec32 *tile, const Rec32 *__restrict__ r
                 const float m = __builtin_amdgcn_exp2f(L);
                 acc_re[k] = fmaf(m, __builtin_amdgcn_cosf(ph), acc_re[k]);
                 acc_im[k] = fmaf(m, __builtin_amdgcn_sinf(ph), acc_im[k]);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < ROWS; k++) {
+            kahan(s_re[k], c_re[k], acc_re[k]);
+            kahan(s_im[k], c_im[k], acc_im[k]);
+            acc_re[k] = acc_im[k] = 0.0f;
+        }
+    }
+}
+
+// Faster mixed form for well-sampled grids.  Per (lane, beamlet) the FP64
+// phase at the lane's first row is reduced to turns; the row-step terms T1,
+// T2 enter as k T1 + k^2 T2 with k integer, so they are reduced modulo 1 in
+// FP64 without changing the phase mod 1, and the in-column phase is formed
+// in FP32 (v_sin / v_cos take revolutions, no further reduction needed).  The
+// amplitude 2^(L0 + k U1 + k^2 U2) is stepped by two multiplications per row;
+// the setup kernel flags (FLAG_STEEP) grids where |U2| > kStepCurvature and
+// the host then uses mixed_accumulate instead.
+template <int ROWS, int NT>
+__device__ inline void mixed_accumulate_step(Rec32 *tile, const Rec32 *__restrict__ rec, int64_t jb, int64_t je,
+                                             double a, double b0, double dy, float (&s_re)[ROWS],
+                                             float (&s_im)[ROWS], float (&c_re)[ROWS], float (&c_im)[ROWS]) {
+    const float af = (float)a, b0f = (float)b0, dyf = (float)dy;
+    float acc_re[ROWS], acc_im[ROWS];
+#pragma unroll
+    for (int k = 0; k < ROWS; k++) acc_re[k] = acc_im[k] = 0.0f;
+    for (int64_t j0 = jb; j0 < je; j0 += kMixedTile) {
+        const int cnt = (int)min((int64_t)kMixedTile, je - j0);
+        __syncthreads();
+        {
+            const float4 *src = reinterpret_cast<const float4 *>(rec + j0);
+            float4 *dst = reinterpret_cast<float4 *>(tile);
+            for (int i = threadIdx.x; i < cnt * kRec32Vec4; i += NT) dst[i] = src[i];
+        }
+        __syncthreads();
+        for (int jj = 0; jj < cnt; jj++) {
+            const Rec32 &r = tile[jj];
+            const double da = a - r.arho, db = b0 - r.brho;
+            const double q = r.p[2] + r.p[4] * da;
+            const double T0 = r.p[0] + da * (r.p[1] + r.p[3] * da) + db * (q + r.p[5] * db);
+            const double T1 = dy * (q + 2.0 * r.p[5] * db);
+            const float base = (float)__builtin_amdgcn_fract(T0);
+            const float t1 = (float)(T1 - rint(T1));
+            const float t2 = r.t2;
+            const float daf = af - r.arho_f, dbf = b0f - r.brho_f;
+            const float qf = r.m[2] + r.m[4] * daf;
+            const float L0 = r.m[0] + daf * (r.m[1] + r.m[3] * daf) + dbf * (qf + r.m[5] * dbf);
+            const float U1 = dyf * (qf + 2.0f * r.m[5] * dbf);
+            // clamps only act where the amplitude is already below 2^-126
+            float m = __builtin_amdgcn_exp2f(L0);
+            float rat = __builtin_amdgcn_exp2f(fminf(U1 + r.u2, 64.0f));
+            const float s2 = r.s2;
+#pragma unroll
+            for (int k = 0; k < ROWS; k++) {
+                const float ph = (k == 0) ? base : fmaf((float)k, fmaf((float)k, t2, t1), base);
+                acc_re[k] = fmaf(m, __builtin_amdgcn_cosf(ph), acc_re[k]);
+                acc_im[k] = fmaf(m, __builtin_amdgcn_sinf(ph), acc_im[k]);
+                if (k + 1 < ROWS) {
+                    m *= rat;
+                    rat *= s2;
+                }
             }
         }
 #pragma unroll

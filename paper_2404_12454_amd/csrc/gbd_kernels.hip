@@ -32,7 +32,7 @@ __global__ void __launch_bounds__(256) setup_kernel(BeamletsDev b, PlaneGeom pl,
 // Mixed form.  Each lane owns ROWS pixels of one detector column; a
 // wavefront spans 64 consecutive columns (coalesced stores); WAVES
 // wavefronts stack in y; the workgroup sums one segment of beamlets.
-template <int ROWS, int WAVES>
+template <int ROWS, int WAVES, int STEP>
 __global__ void __launch_bounds__(64 * WAVES) eval_mixed_kernel(EvalGeom g, const Rec32 *__restrict__ rec,
                                                                 float4 *__restrict__ partial,
                                                                 float2 *__restrict__ out) {
@@ -54,7 +54,10 @@ __global__ void __launch_bounds__(64 * WAVES) eval_mixed_kernel(EvalGeom g, cons
     for (int k = 0; k < ROWS; k++) s_re[k] = s_im[k] = c_re[k] = c_im[k] = 0.0f;
     const int64_t jb = (int64_t)seg * g.seg_len;
     const int64_t je = min(g.n, jb + g.seg_len);
-    mixed_accumulate<ROWS, 64 * WAVES>(tile, rec, jb, je, a, b0, g.dy, s_re, s_im, c_re, c_im);
+    if (STEP)
+        mixed_accumulate_step<ROWS, 64 * WAVES>(tile, rec, jb, je, a, b0, g.dy, s_re, s_im, c_re, c_im);
+    else
+        mixed_accumulate<ROWS, 64 * WAVES>(tile, rec, jb, je, a, b0, g.dy, s_re, s_im, c_re, c_im);
 
     if (ix >= g.nx) return;
     const int64_t M = (int64_t)g.nx * g.ny;
@@ -172,16 +175,23 @@ __global__ void __launch_bounds__(256) reduce_fp64_kernel(int64_t M, int32_t nse
 }
 
 template <int ROWS, int WAVES>
-hipError_t launch_eval_t(int precision, const EvalGeom &g, const void *rec, void *partial, void *out, hipStream_t s) {
+hipError_t launch_eval_t(int precision, int step, const EvalGeom &g, const void *rec, void *partial, void *out,
+                         hipStream_t s) {
     const int grid = (g.work + 7) / 8 * 8;
-    if (precision == 1)
-        eval_mixed_kernel<ROWS, WAVES><<<grid, 64 * WAVES, 0, s>>>(g, static_cast<const Rec32 *>(rec),
-                                                                   static_cast<float4 *>(partial),
-                                                                   static_cast<float2 *>(out));
-    else
+    if (precision == 1 && step)
+        eval_mixed_kernel<ROWS, WAVES, 1><<<grid, 64 * WAVES, 0, s>>>(g, static_cast<const Rec32 *>(rec),
+                                                                      static_cast<float4 *>(partial),
+                                                                      static_cast<float2 *>(out));
+    else if (precision == 1)
+        eval_mixed_kernel<ROWS, WAVES, 0><<<grid, 64 * WAVES, 0, s>>>(g, static_cast<const Rec32 *>(rec),
+                                                                      static_cast<float4 *>(partial),
+                                                                      static_cast<float2 *>(out));
+    else if constexpr (ROWS <= 8)
         eval_fp64_kernel<ROWS, WAVES><<<grid, 64 * WAVES, 0, s>>>(g, static_cast<const Rec64 *>(rec),
                                                                   static_cast<double2 *>(partial),
                                                                   static_cast<double2 *>(out));
+    else
+        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 
@@ -195,15 +205,20 @@ hipError_t launch_setup(const BeamletsDev &b, const PlaneGeom &pl, double global
     return hipGetLastError();
 }
 
-hipError_t launch_eval(int precision, int rows, int waves, const EvalGeom &g, const void *rec, void *partial,
+hipError_t launch_eval(int precision, int rows, int waves, int step, const EvalGeom &g, const void *rec, void *partial,
                        void *out, hipStream_t s) {
 #define GBD_CASE(R, W) \
-    if (rows == R && waves == W) return launch_eval_t<R, W>(precision, g, rec, partial, out, s);
+    if (rows == R && waves == W) return launch_eval_t<R, W>(precision, step, g, rec, partial, out, s);
     GBD_CASE(1, 1) GBD_CASE(1, 2) GBD_CASE(1, 4)
     GBD_CASE(2, 1) GBD_CASE(2, 2) GBD_CASE(2, 4)
     GBD_CASE(4, 1) GBD_CASE(4, 2) GBD_CASE(4, 4)
     GBD_CASE(8, 1) GBD_CASE(8, 2) GBD_CASE(8, 4)
 #undef GBD_CASE
+    if (precision == 1 && rows == 16) {
+        if (waves == 1) return launch_eval_t<16, 1>(precision, step, g, rec, partial, out, s);
+        if (waves == 2) return launch_eval_t<16, 2>(precision, step, g, rec, partial, out, s);
+        if (waves == 4) return launch_eval_t<16, 4>(precision, step, g, rec, partial, out, s);
+    }
     return hipErrorInvalidValue;
 }
 

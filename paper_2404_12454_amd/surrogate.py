@@ -1,0 +1,207 @@
+"""Learned surrogate of the beamlet-parameter search (Sec. 6).
+
+The figure of merit of the search is the RMS difference between the GBD
+irradiance (peak-normalised at the plane origin) and the analytic Airy
+pattern, as a function of the decomposition's free parameters.  A small MLP
+(5 -> 128 -> 128 -> 128 -> 1, SiLU; hand-written kernels, ``Mlp``) is trained
+on labels that the batched GBD sweep itself generates, predicts log10 RMS for
+a dense candidate pool, and proposes the top candidates; plain GBD re-scores
+every proposal, so the method stays the arbiter.
+
+Inputs (standardised with the training set's mean and deviation):
+OF, waist/spacing ratio q, ln(beamlets across), F-number, ln(lambda).  In the
+ideal-lens focal-plane model with the grid in lambda*F units the label does
+not depend on F-number or lambda; the network has to learn that.
+
+Everything numeric runs in the HIP library: labels and re-scores through
+``gbd_eval_batch``, the reference pattern through ``gbd_airy``, the network's
+forward/backward/AdamW through ``gbd_mlp_*``.  This module only draws the
+seeded inputs, shuffles indices and books times.
+"""
+from __future__ import annotations
+
+import json
+import math
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import (GBD_MLP_BF16, Context, Mlp, beamlets_from_scene, gbd_airy, gbd_eval_batch, plane_from_scene,
+               scenes)
+
+D_PUPIL = 10e-3
+
+
+def draw_scene(of, q, na, fnum, lam, npix, span):
+    return scenes.airy_scene(int(na), D=D_PUPIL, fnum=float(fnum), lam=float(lam), OF=float(of), q=float(q),
+                             npix=int(npix), half_span_lamF=float(span))
+
+
+def score(ctx: Context, params: np.ndarray, npix: int = 256, span: float = 8.0, chunk: int = 1500):
+    """RMS (and peak) of |E/E(0)|^2 - Airy for each row (OF, q, n_across,
+    fnum, lam) of ``params``, by the batched GBD sweep in chunks."""
+    import torch
+    out = np.zeros((len(params), 2))
+    airy = None
+    for s in range(0, len(params), chunk):
+        rows = params[s:s + chunk]
+        sc = [draw_scene(*r, npix, span) for r in rows]
+        bs = [beamlets_from_scene(ctx, x) for x in sc]
+        ps = [plane_from_scene(ctx, x) for x in sc]
+        if airy is None:
+            m = sc[0].meta
+            # in lambda*F units the reference pattern is the same for every row
+            airy = gbd_airy(ctx, ps[0], m["D"], m["f"], sc[0].lam)
+        metrics, _ = gbd_eval_batch(ctx, bs, ps, airy=airy)
+        out[s:s + len(rows)] = metrics[:, :2]
+        del bs, ps
+    torch.cuda.synchronize()
+    return out
+
+
+def features(params: np.ndarray) -> np.ndarray:
+    p = np.asarray(params, np.float64)
+    return np.stack([p[:, 0], p[:, 1], np.log(p[:, 2]), p[:, 3], np.log(p[:, 4])], axis=1)
+
+
+@dataclass
+class Surrogate:
+    ctx: Context
+    width: int = 128
+    depth: int = 3
+    batch: int = 256
+    mode: int = GBD_MLP_BF16
+    mean: np.ndarray = None
+    std: np.ndarray = None
+    ymean: float = 0.0
+    ystd: float = 1.0
+    net: Mlp = None
+    history: list = field(default_factory=list)
+
+    def _x(self, params):
+        import torch
+        z = (features(params) - self.mean) / self.std
+        return torch.tensor(z.astype(np.float32), device=f"cuda:{self.ctx.device}")
+
+    def fit(self, params, log10_rms, epochs=200, lr=1e-3, weight_decay=1e-4, seed=0, init_params=None):
+        """AdamW with a cosine learning-rate schedule over shuffled
+        minibatches (shuffles drawn from numpy PCG64(seed))."""
+        import torch
+        f = features(params)
+        self.mean, self.std = f.mean(0), f.std(0) + 1e-12
+        self.ymean, self.ystd = float(np.mean(log10_rms)), float(np.std(log10_rms) + 1e-12)
+        X = self._x(params)
+        y = torch.tensor(((np.asarray(log10_rms) - self.ymean) / self.ystd).astype(np.float32), device=X.device)
+        self.net = Mlp(self.ctx, 5, self.width, self.depth, self.batch, self.mode)
+        if init_params is None:
+            raise ValueError("init_params (seeded initial weights) are required")
+        self.net.set_params(init_params)
+        rng = np.random.Generator(np.random.PCG64(seed))
+        n = len(params)
+        steps_per_epoch = max(1, n // self.batch)
+        total = epochs * steps_per_epoch
+        loss = torch.zeros(1, device=X.device)
+        step = 0
+        for ep in range(epochs):
+            perm = torch.tensor(rng.permutation(n).astype(np.int32), device=X.device)
+            acc = torch.zeros(1, device=X.device)
+            for s in range(steps_per_epoch):
+                rows = perm[s * self.batch:(s + 1) * self.batch]
+                self.net.backward(X, y, rows=rows, loss_out=loss)
+                cur = lr * 0.5 * (1.0 + math.cos(math.pi * step / total))
+                self.net.adamw(cur, weight_decay=weight_decay)
+                acc += loss
+                step += 1
+            if ep % 10 == 0 or ep == epochs - 1:
+                self.history.append((ep, float(acc.cpu()) / steps_per_epoch))
+        return self
+
+    def predict(self, params) -> np.ndarray:
+        import torch
+        X = self._x(params)
+        out = []
+        for s in range(0, X.shape[0], self.batch):
+            out.append(self.net.forward(X[s:s + self.batch]).cpu().numpy())
+        z = np.concatenate(out) if out else np.zeros(0)
+        return z.astype(np.float64) * self.ystd + self.ymean
+
+
+def init_params(width=128, depth=3, n_in=5, seed=0):
+    """Uniform(+-1/sqrt(fan_in)) initial weights and biases, numpy PCG64(seed)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out, prev = [], n_in
+    for l in range(depth + 1):
+        o = width if l < depth else 1
+        b = 1.0 / math.sqrt(prev)
+        out.append(rng.uniform(-b, b, o * prev))
+        out.append(rng.uniform(-b, b, o))
+        prev = width
+    return np.concatenate(out).astype(np.float32)
+
+
+def candidate_pool(n_of=41, n_q=31, nacross=scenes.SWEEP_NACROSS, fnum=10.0, lam=1e-6):
+    of = np.linspace(1.0, 3.0, n_of)
+    q = np.linspace(0.5, 2.0, n_q)
+    rows = [(a, b, c, fnum, lam) for c in nacross for a in of for b in q]
+    return np.array(rows, np.float64)
+
+
+def run(n_train=20000, epochs=200, pool=None, top=32, label_npix=256, rescore_npix=512, span=8.0, seed=12454,
+        exhaustive=True, random_baselines=3):
+    """The full pipeline; returns a JSON-able record of accuracy and times."""
+    import torch
+    ctx = Context(0)
+    rec = {}
+    draws = scenes.surrogate_draws(n_train, seed)
+    t0 = time.perf_counter()
+    lab = score(ctx, draws, label_npix, span)
+    rec["label_s"] = time.perf_counter() - t0
+    y = np.log10(lab[:, 0])
+    split = np.random.Generator(np.random.PCG64(1)).permutation(n_train)
+    nval = n_train // 10
+    val, tr = split[:nval], split[nval:]
+    t0 = time.perf_counter()
+    sur = Surrogate(ctx).fit(draws[tr], y[tr], epochs=epochs, init_params=init_params(seed=0))
+    torch.cuda.synchronize()
+    rec["train_s"] = time.perf_counter() - t0
+    pv = sur.predict(draws[val])
+    rec["val_rmse_log10"] = float(np.sqrt(np.mean((pv - y[val]) ** 2)))
+    rec["val_r2"] = float(1 - np.mean((pv - y[val]) ** 2) / np.var(y[val]))
+    pool = candidate_pool() if pool is None else pool
+    rec["pool"] = int(len(pool))
+    t0 = time.perf_counter()
+    pred = sur.predict(pool)
+    pick = np.argsort(pred)[:top]
+    got = score(ctx, pool[pick], rescore_npix, span)
+    rec["online_s"] = time.perf_counter() - t0
+    best_i = int(pick[np.argmin(got[:, 0])])
+    rec["surrogate_best"] = dict(params=pool[best_i].tolist(), rms=float(got[:, 0].min()))
+    rng = np.random.Generator(np.random.PCG64(seed + 1))
+    rb = []
+    for _ in range(random_baselines):
+        rp = rng.choice(len(pool), top, replace=False)
+        rb.append(float(score(ctx, pool[rp], rescore_npix, span)[:, 0].min()))
+    rec["random32_best_rms"] = rb
+    if exhaustive:
+        t0 = time.perf_counter()
+        full = score(ctx, pool, rescore_npix, span)
+        rec["exhaustive_s"] = time.perf_counter() - t0
+        ex_i = int(np.argmin(full[:, 0]))
+        rec["exhaustive_best"] = dict(params=pool[ex_i].tolist(), rms=float(full[ex_i, 0]))
+        rec["same_optimum"] = bool(ex_i == best_i)
+        rec["rms_ratio_to_optimum"] = rec["surrogate_best"]["rms"] / rec["exhaustive_best"]["rms"]
+        rec["exhaustive_rank_of_pick"] = int(np.sum(full[:, 0] < rec["surrogate_best"]["rms"]))
+        rec["speedup_online"] = rec["exhaustive_s"] / rec["online_s"]
+    rec["loss_history"] = sur.history
+    return rec
+
+
+if __name__ == "__main__":
+    import sys
+    ints = {"n_train", "epochs", "top", "label_npix", "rescore_npix", "seed", "random_baselines"}
+    kw = {}
+    for a in sys.argv[1:]:
+        k, v = a.split("=", 1)
+        kw[k] = int(v) if k in ints else (v.lower() == "true") if k == "exhaustive" else float(v)
+    print(json.dumps(run(**kw)), flush=True)

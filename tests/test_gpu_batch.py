@@ -55,11 +55,12 @@ def test_batch_fields_bitwise_equal_single_instance(ctx):
     insts = small_instances()
     bs = [gbd.beamlets_from_scene(ctx, s) for s in insts]
     ps = [gbd.plane_from_scene(ctx, s) for s in insts]
-    _, fields = gbd.gbd_eval_batch(ctx, bs, ps, fields=True, opts=dict(rows_per_lane=4, waves=2))
-    for s, b, p, F in zip(insts, bs, ps, fields):
-        E = gbd.gbd_eval(ctx, b, p, gbd.GBD_MIXED, opts=dict(rows_per_lane=4, waves=2, segments=1))
-        torch.cuda.synchronize()
-        assert torch.equal(F.cpu().view(torch.float32), E.cpu().view(torch.float32))
+    for variant in (1, 2):
+        _, fields = gbd.gbd_eval_batch(ctx, bs, ps, fields=True, opts=dict(rows_per_lane=4, waves=2, variant=variant))
+        for s, b, p, F in zip(insts, bs, ps, fields):
+            E = gbd.gbd_eval(ctx, b, p, gbd.GBD_MIXED, opts=dict(rows_per_lane=4, waves=2, segments=1, variant=variant))
+            torch.cuda.synchronize()
+            assert torch.equal(F.cpu().view(torch.float32), E.cpu().view(torch.float32)), variant
 
 
 def test_batch_metrics_match_oracle(ctx):

@@ -130,7 +130,7 @@ def test_training_reduces_loss(ctx):
             if first is None:
                 torch.cuda.synchronize()
                 first = float(loss.cpu())
-    pred = net.forward(Xd).cpu().numpy()
+    pred = np.concatenate([net.forward(Xd[s:s + 256]).cpu().numpy() for s in range(0, 2048, 256)])
     final = float(np.mean((pred - y) ** 2))
     print("training", first, final, flush=True)
     assert final < 0.05 * first

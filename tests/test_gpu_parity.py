@@ -68,8 +68,37 @@ def test_every_launch_shape_matches_oracle(ctx, precision):
     sc = scenes.zernike_scene(99, n_across=20, npix=70, half_span=40e-6)
     sc.plane.ny = 45
     ref = oracle.eval_field(sc)
-    for o in SHAPES:
-        check(run(ctx, sc, precision, opts=o), ref, precision, f"shape {o}")
+    variants = (1, 2) if precision == gbd.GBD_MIXED else (0,)
+    shapes = SHAPES + ([dict(rows_per_lane=16, waves=w, segments=s) for w in (1, 2, 4) for s in (1, 3)]
+                       if precision == gbd.GBD_MIXED else [])
+    for v in variants:
+        for o in shapes:
+            check(run(ctx, sc, precision, opts=dict(o, variant=v)), ref, precision, f"shape {o} variant {v}")
+
+
+@pytest.mark.parametrize("name", ["airy32_64", "zern128_1024"])
+def test_stepped_variant_is_chosen_and_matches_direct(ctx, name):
+    """On well-sampled grids the automatic mixed form is the stepped one; it
+    agrees with the direct form and with the oracle."""
+    import torch
+    sc = scenes.config(name)
+    b = gbd.beamlets_from_scene(ctx, sc)
+    p = gbd.plane_from_scene(ctx, sc)
+    plan = gbd.Plan(ctx, sc.n).setup(b, p)
+    assert plan.shape(gbd.GBD_MIXED)["variant"] == 2
+    E2 = plan.eval(gbd.GBD_MIXED).cpu().numpy()
+    E1 = plan.eval(gbd.GBD_MIXED, opts=dict(variant=1)).cpu().numpy()
+    print(name, "stepped vs direct", rel_l2(E2, E1), flush=True)
+    assert rel_l2(E2, E1) < 1e-5
+    if sc.plane.npix <= 4096:
+        check(E2, oracle.eval_field(sc), gbd.GBD_MIXED, name + " stepped")
+
+
+def test_steep_grid_falls_back_to_direct(ctx):
+    tail = scenes.airy_scene(1, npix=16, half_span_lamF=30.0)
+    plan = gbd.Plan(ctx, 1).setup(gbd.beamlets_from_scene(ctx, tail), gbd.plane_from_scene(ctx, tail))
+    assert plan.shape(gbd.GBD_MIXED)["variant"] == 1
+    assert plan.shape(gbd.GBD_MIXED, opts=dict(variant=2))["variant"] == 1
 
 
 @pytest.mark.parametrize("precision", BOTH)
@@ -120,7 +149,7 @@ def test_plan_reuse_and_shape(ctx):
     plan = gbd.gbd_plan_create(ctx, sc.n)
     plan.setup(b, p)
     shp = plan.shape(gbd.GBD_MIXED)
-    assert shp["rows_per_lane"] in (1, 2, 4, 8) and shp["segments"] >= 1
+    assert shp["rows_per_lane"] in (1, 2, 4, 8, 16) and shp["segments"] >= 1
     E1 = plan.eval(gbd.GBD_FP64)
     E2 = plan.eval(gbd.GBD_FP64, opts=dict(rows_per_lane=2, waves=1, segments=5))
     torch.cuda.synchronize()

@@ -1,0 +1,45 @@
+"""GPU test of the surrogate-pruned search (reduced sizes): labels from the
+batched GBD sweep, training on the device, top-32 proposals re-scored by
+plain GBD, compared with the exhaustive sweep of the same candidate pool and
+with randomly chosen candidates."""
+import numpy as np
+import pytest
+
+from paper_2404_12454_amd import surrogate
+from gbd_testutil import ensure_library
+
+pytestmark = pytest.mark.gpu
+
+
+def test_surrogate_prunes_the_search():
+    ensure_library()
+    pool = surrogate.candidate_pool(n_of=11, n_q=9, nacross=(24, 48, 96))
+    rec = surrogate.run(n_train=3000, epochs=60, pool=pool, top=32, label_npix=128, rescore_npix=128, span=8.0,
+                        random_baselines=5)
+    print({k: v for k, v in rec.items() if k != "loss_history"}, flush=True)
+    assert rec["val_r2"] > 0.9
+    # the proposal re-scored by GBD is at (or within 5% of) the exhaustive optimum
+    assert rec["rms_ratio_to_optimum"] <= 1.05
+    # and beats the best of 32 random candidates in most draws
+    assert sum(rec["surrogate_best"]["rms"] <= r for r in rec["random32_best_rms"]) >= 4
+    assert rec["online_s"] < rec["exhaustive_s"]
+
+
+def test_surrogate_is_flat_in_fnumber_and_wavelength():
+    """In lambda*F units the figure of merit does not depend on F# or lambda;
+    the trained network's predictions must vary little along them."""
+    import paper_2404_12454_amd as gbd
+    ctx = gbd.Context(0)
+    from paper_2404_12454_amd import scenes
+    draws = scenes.surrogate_draws(3000, 7)
+    y = np.log10(surrogate.score(ctx, draws, 128, 8.0)[:, 0])
+    sur = surrogate.Surrogate(ctx).fit(draws, y, epochs=60, init_params=surrogate.init_params(seed=0))
+    base = np.array([1.6, 1.0, 48, 10.0, 1e-6])
+    grid = []
+    for fn in np.linspace(4, 20, 9):
+        for lam in np.exp(np.linspace(np.log(0.4e-6), np.log(2e-6), 9)):
+            grid.append([base[0], base[1], base[2], fn, lam])
+    p = sur.predict(np.array(grid))
+    spread = p.max() - p.min()
+    print("spread along F#, lambda:", spread, "label range:", np.ptp(y), flush=True)
+    assert spread < 0.15 * np.ptp(y)
