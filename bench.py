@@ -67,6 +67,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="airy256_512")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the 441-instance batched sweep figure")
     ap.add_argument("--fp64-steps", type=int, default=5)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 256 MiB device copy (a known-size kernel for HBM counters)")
@@ -175,9 +176,41 @@ def main():
         "wall_s_timed": wall,
     }
 
+    if not args.no_sweep:
+        rec["sweep"] = sweep(ctx)
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(sc, E32, E64)
     print(json.dumps(rec), flush=True)
+
+
+def sweep(ctx, reps=3):
+    """The parameter sweep in one persistent launch: 441 (OF, q, beamlets
+    across) instances, 256 x 256 pixels over +-8 lambda F each, RMS and peak
+    error against the Airy pattern per instance (host wall time per call,
+    setup and metric read-back included)."""
+    import numpy as np
+    import torch
+    import paper_2404_12454_amd as gbd
+    from paper_2404_12454_amd import scenes
+    insts = [scenes.airy_scene(na, OF=of, q=q, npix=256, half_span_lamF=8.0) for of, q, na in scenes.sweep_grid()]
+    bs = [gbd.beamlets_from_scene(ctx, s) for s in insts]
+    ps = [gbd.plane_from_scene(ctx, s) for s in insts]
+    m = insts[0].meta
+    airy = gbd.gbd_airy(ctx, ps[0], m["D"], m["f"], insts[0].lam)
+    metrics, _ = gbd.gbd_eval_batch(ctx, bs, ps, airy=airy)
+    torch.cuda.synchronize()
+    t = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        metrics, _ = gbd.gbd_eval_batch(ctx, bs, ps, airy=airy)
+        t.append(time.perf_counter() - t0)
+    dt = float(np.median(t))
+    pairs = sum(s.n for s in insts) * 256 * 256
+    best = int(np.argmin(metrics[:, 0]))
+    of, q, na = scenes.sweep_grid()[best]
+    return {"instances": len(insts), "pairs": pairs, "ms": dt * 1e3, "evals_per_s": pairs / dt,
+            "best": {"OF": of, "q": q, "n_across": na, "rms": float(metrics[best, 0]),
+                     "peak": float(metrics[best, 1])}}
 
 
 def cpu_baseline(sc, E32, E64):

@@ -140,6 +140,32 @@ def init_params(width=128, depth=3, n_in=5, seed=0):
     return np.concatenate(out).astype(np.float32)
 
 
+def propose(pred: np.ndarray, pool: np.ndarray, top: int = 32, stratify: bool = True) -> np.ndarray:
+    """Indices of the candidates to re-score.  The figure of merit varies
+    irregularly with the integer beamlet count (how the clipped square grid
+    samples the pupil edge), which a smooth network over ln(n_across) cannot
+    resolve, while along (OF, q) at one count it is smooth.  Stratified
+    proposal therefore takes the network's best (OF, q) for every beamlet
+    count in the pool (top // counts each) and fills the rest globally."""
+    order = np.argsort(pred)
+    if not stratify:
+        return order[:top]
+    counts = np.unique(pool[:, 2])
+    per = max(1, top // len(counts))
+    pick = []
+    for c in counts:
+        idx = np.where(pool[:, 2] == c)[0]
+        pick.extend(idx[np.argsort(pred[idx])[:per]].tolist())
+    chosen = set(pick)
+    for i in order:
+        if len(pick) >= top:
+            break
+        if i not in chosen:
+            pick.append(int(i))
+            chosen.add(int(i))
+    return np.array(pick[:top])
+
+
 def candidate_pool(n_of=41, n_q=31, nacross=scenes.SWEEP_NACROSS, fnum=10.0, lam=1e-6):
     of = np.linspace(1.0, 3.0, n_of)
     q = np.linspace(0.5, 2.0, n_q)
@@ -148,7 +174,7 @@ def candidate_pool(n_of=41, n_q=31, nacross=scenes.SWEEP_NACROSS, fnum=10.0, lam
 
 
 def run(n_train=20000, epochs=200, pool=None, top=32, label_npix=256, rescore_npix=512, span=8.0, seed=12454,
-        exhaustive=True, random_baselines=3):
+        exhaustive=True, random_baselines=3, stratify=True):
     """The full pipeline; returns a JSON-able record of accuracy and times."""
     import torch
     ctx = Context(0)
@@ -172,7 +198,7 @@ def run(n_train=20000, epochs=200, pool=None, top=32, label_npix=256, rescore_np
     rec["pool"] = int(len(pool))
     t0 = time.perf_counter()
     pred = sur.predict(pool)
-    pick = np.argsort(pred)[:top]
+    pick = propose(pred, pool, top, stratify)
     got = score(ctx, pool[pick], rescore_npix, span)
     rec["online_s"] = time.perf_counter() - t0
     best_i = int(pick[np.argmin(got[:, 0])])
@@ -193,6 +219,11 @@ def run(n_train=20000, epochs=200, pool=None, top=32, label_npix=256, rescore_np
         rec["rms_ratio_to_optimum"] = rec["surrogate_best"]["rms"] / rec["exhaustive_best"]["rms"]
         rec["exhaustive_rank_of_pick"] = int(np.sum(full[:, 0] < rec["surrogate_best"]["rms"]))
         rec["speedup_online"] = rec["exhaustive_s"] / rec["online_s"]
+        rec["random32_ratio_to_optimum"] = [r / rec["exhaustive_best"]["rms"] for r in rb]
+        # the same network with plain (unstratified) top-k, re-scored
+        plain = np.argsort(pred)[:top]
+        rec["plain_topk_ratio_to_optimum"] = float(full[plain, 0].min() / full[ex_i, 0])
+        rec["stratified"] = bool(stratify)
     rec["loss_history"] = sur.history
     return rec
 
@@ -203,5 +234,5 @@ if __name__ == "__main__":
     kw = {}
     for a in sys.argv[1:]:
         k, v = a.split("=", 1)
-        kw[k] = int(v) if k in ints else (v.lower() == "true") if k == "exhaustive" else float(v)
+        kw[k] = int(v) if k in ints else (v.lower() == "true") if k in ("exhaustive", "stratify") else float(v)
     print(json.dumps(run(**kw)), flush=True)
