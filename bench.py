@@ -68,6 +68,7 @@ def main():
     ap.add_argument("--workload", default="airy256_512")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-sweep", action="store_true", help="skip the 441-instance batched sweep figure")
+    ap.add_argument("--no-point", action="store_true", help="skip the point-evaluation comparison")
     ap.add_argument("--fp64-steps", type=int, default=5)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 256 MiB device copy (a known-size kernel for HBM counters)")
@@ -176,11 +177,35 @@ def main():
         "wall_s_timed": wall,
     }
 
+    if not args.no_point:
+        rec["point_eval"] = point_eval(ctx, b, p, N * M, eval_ms_mean, eval64_ms)
     if not args.no_sweep:
         rec["sweep"] = sweep(ctx)
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(sc, E32, E64)
     print(json.dumps(rec), flush=True)
+
+
+def point_eval(ctx, b, p, pairs, mixed_ms, fp64_ms, reps=2):
+    """Point evaluation (every pixel re-propagates every beamlet to its own
+    position, FP64) on the same workload: the per-point algorithm the plane
+    evaluation replaces, timed on the same GPU."""
+    import numpy as np
+    import torch
+    import paper_2404_12454_amd as gbd
+    out = gbd.gbd_eval_point(ctx, b, p)
+    t = []
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        gbd.gbd_eval_point(ctx, b, p, out=out)
+        e1.record()
+        torch.cuda.synchronize()
+        t.append(e0.elapsed_time(e1))
+    ms = float(np.median(t))
+    return {"ms": ms, "evals_per_s": pairs / (ms * 1e-3), "plane_fp64_speedup": ms / fp64_ms,
+            "plane_mixed_speedup": ms / mixed_ms}
 
 
 def sweep(ctx, reps=3):

@@ -155,6 +155,18 @@ int gbd_autotune_batch(gbd_ctx_t ctx, int32_t n_inst, const gbd_beamlets_t *beam
 int gbd_autotune_save(gbd_ctx_t ctx, const char *path);
 int gbd_autotune_load(gbd_ctx_t ctx, const char *path);
 
+/* --- point evaluation (paraxial, FP64) --------------------------------------
+ * The per-point algorithm that plane evaluation replaces (Sec. 2.2, in its
+ * paraxial form): every pixel evaluates every beamlet's exact paraxial field
+ * at the pixel's own 3-D position (the beamlet's ABCD extended by free space
+ * to that axial distance; complex-curvature law and eigenvalue-branch
+ * amplitude recomputed per pixel).  Equal to gbd_eval (GBD_FP64) on planes
+ * normal to the axis; the exact reference of the tilted-plane expansion
+ * otherwise.  field_out: device complex128 [ny][nx].  Synchronises; returns
+ * GBD_EBRANCH (field_out then invalid) if a pixel's eigenvalues leave the
+ * principal branch. */
+int gbd_eval_point(gbd_ctx_t ctx, gbd_beamlets_t b, gbd_plane_t p, void *field_out, int64_t out_bytes);
+
 /* --- a6: analytic reference irradiance ------------------------------------
  * out[iy][ix] = (2 J1(v)/v)^2 with v = pi D r / (lambda f), r the distance of
  * the pixel from the plane origin: the Airy pattern of an unobscured circular

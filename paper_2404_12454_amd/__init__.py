@@ -22,7 +22,7 @@ import numpy as np
 __all__ = [
     "GBD_FP64", "GBD_MIXED", "GbdError", "gbd_eval_opts", "library_path", "load_library",
     "gbd_ctx_create", "gbd_beamlets", "gbd_plane", "gbd_eval", "gbd_plan_create", "gbd_plan_setup",
-    "gbd_plan_eval", "gbd_plan_shape", "gbd_airy", "gbd_eval_batch", "gbd_autotune", "gbd_autotune_batch",
+    "gbd_plan_eval", "gbd_plan_shape", "gbd_airy", "gbd_eval_batch", "gbd_eval_point", "gbd_autotune", "gbd_autotune_batch",
     "gbd_autotune_save", "gbd_autotune_load", "GBD_MLP_FP32", "GBD_MLP_BF16", "Mlp", "gbd_mlp_create", "beamlets_from_scene", "plane_from_scene",
     "Context", "Beamlets", "Plane", "Plan",
 ]
@@ -80,6 +80,7 @@ def load_library():
         "gbd_plan_free": (None, [P]),
         "gbd_plan_shape": (ctypes.c_int, [P, P, ctypes.c_int, P, P]),
         "gbd_airy": (ctypes.c_int, [P, P, D, D, D, P, I64]),
+        "gbd_eval_point": (ctypes.c_int, [P, P, P, P, I64]),
         "gbd_autotune": (ctypes.c_int, [P, P, ctypes.c_int, I32, P, P]),
         "gbd_mlp_create": (ctypes.c_int, [P, PP, I32, I32, I32, I32, ctypes.c_int]),
         "gbd_mlp_free": (None, [P]),
@@ -231,6 +232,14 @@ def gbd_eval(ctx: Context, beamlets: Beamlets, plane: Plane, precision: int = GB
     _check(load_library().gbd_eval(ctx.handle, beamlets.handle, plane.handle, int(precision),
                                    ctypes.c_void_p(out.data_ptr()), out.numel() * out.element_size(),
                                    None if o is None else ctypes.byref(o)))
+    return out
+
+
+def gbd_eval_point(ctx: Context, beamlets: Beamlets, plane: Plane, out=None):
+    """Point evaluation (paraxial, FP64): complex128 [ny, nx]; synchronises."""
+    out = _out_tensor(ctx, plane.nx, plane.ny, GBD_FP64, out)
+    _check(load_library().gbd_eval_point(ctx.handle, beamlets.handle, plane.handle, ctypes.c_void_p(out.data_ptr()),
+                                         out.numel() * out.element_size()))
     return out
 
 

@@ -23,7 +23,7 @@ struct DevBuf {
 };
 
 struct BatchWork {
-    DevBuf rec, inst, offs, eval, items, e0, part, metrics, flags;
+    DevBuf rec, inst, offs, eval, items, e0, part, metrics, flags, point;
     uint32_t *host_flags = nullptr;  // pinned: status, bad instance
 };
 
@@ -337,7 +337,7 @@ int grow(DevBuf &b, size_t bytes, const char *what) {
 }
 
 void batch_free(BatchWork &w) {
-    DevBuf *all[] = {&w.rec, &w.inst, &w.offs, &w.eval, &w.items, &w.e0, &w.part, &w.metrics, &w.flags};
+    DevBuf *all[] = {&w.rec, &w.inst, &w.offs, &w.eval, &w.items, &w.e0, &w.part, &w.metrics, &w.flags, &w.point};
     for (DevBuf *b : all)
         if (b->p) (void)hipFree(b->p);
     if (w.host_flags) (void)hipHostFree(w.host_flags);
@@ -645,6 +645,34 @@ int gbd_autotune_load(gbd_ctx_t ctx, const char *path) {
     }
     fclose(f);
     return loaded;
+}
+
+int gbd_eval_point(gbd_ctx_t ctx, gbd_beamlets_t b, gbd_plane_t p, void *field_out, int64_t out_bytes) {
+    if (!ctx || !b || !p) return fail(GBD_EINVAL, "NULL argument");
+    const int64_t M = (int64_t)p->g.nx * p->g.ny;
+    if (M == 0) return GBD_OK;
+    if (!field_out) return fail(GBD_EINVAL, "field_out is NULL");
+    if (out_bytes < M * 16)
+        return fail(GBD_ERANGE, "field_out holds %lld bytes, %lld needed", (long long)out_bytes, (long long)(M * 16));
+    int rc = ensure_device(ctx);
+    if (rc) return rc;
+    BatchWork &w = ctx->batch;
+    if ((rc = grow(w.point, (size_t)std::max<int64_t>(b->dev.n, 1) * sizeof(RecPt), "point records")) ||
+        (rc = grow(w.flags, 4 * sizeof(uint32_t), "flags")))
+        return rc;
+    if (!w.host_flags) HIP_TRY(hipHostMalloc(&w.host_flags, 4 * sizeof(uint32_t), hipHostMallocDefault), "hipHostMalloc");
+    const double g0 = b->dev.l0 / b->dev.lam;
+    uint32_t *flags = static_cast<uint32_t *>(w.flags.p);
+    HIP_TRY(hipMemsetAsync(flags + 3, 0, sizeof(uint32_t), ctx->stream), "hipMemsetAsync");
+    HIP_TRY(launch_point(b->dev, p->g, g0 - nearbyint(g0), static_cast<RecPt *>(w.point.p),
+                         static_cast<double2 *>(field_out), flags + 3, ctx->stream),
+            "point evaluation launch");
+    HIP_TRY(hipMemcpyAsync(w.host_flags + 3, flags + 3, sizeof(uint32_t), hipMemcpyDeviceToHost, ctx->stream),
+            "status copy");
+    HIP_TRY(hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
+    if (w.host_flags[3] & FLAG_BRANCH)
+        return fail(GBD_EBRANCH, "an eigenvalue left the principal branch at some pixel (field_out is not valid)");
+    return GBD_OK;
 }
 
 int gbd_airy(gbd_ctx_t ctx, gbd_plane_t p, double D, double f, double lambda, float *out, int64_t out_bytes) {

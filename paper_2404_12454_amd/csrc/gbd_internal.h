@@ -123,6 +123,24 @@ hipError_t launch_batch_finalize(const BatchEval *inst, int32_t n_inst, const do
                                  double *metrics, hipStream_t s);
 hipError_t launch_airy(int32_t nx, int32_t ny, double dx, double dy, double vscale, float *out, hipStream_t s);
 
+// --- point evaluation (paraxial, FP64) -----------------------------------
+// Per beamlet: base ray at the ABCD output plane, P0 = Nm adj(Mm0) (complex
+// symmetric), det Mm(z) = d0 + d1 z + d2 z^2, tr Mm(z) = t0 + t1 z,
+// amplitude, phase constant c0 (turns, reduced) and c1 = d(turns)/dz.
+struct alignas(16) RecPt {
+    double r2[2], th[2];
+    double p00[2], p01[2], p11[2];
+    double d0[2], d1[2], d2[2];
+    double t0[2], t1[2];
+    double amp[2];
+    double c0, c1;
+    double pad[2];
+};
+static_assert(sizeof(RecPt) % 16 == 0, "RecPt layout");
+
+hipError_t launch_point(const BeamletsDev &b, const PlaneGeom &pl, double gturns, RecPt *rec, double2 *out,
+                        uint32_t *status, hipStream_t s);
+
 // --- surrogate network ----------------------------------------------------
 // C[m][n] = sum_k A(m, k) B(k, n) with A(m, k) = A[m sam + k sak] and
 // B(k, n) = B[k sbk + n sbn]; epilogue 0: C = acc + bias, H = SiLU(C);

@@ -20,8 +20,6 @@ def test_surrogate_prunes_the_search():
     assert rec["val_r2"] > 0.9
     # the proposals, re-scored by GBD, come within 15% of the exhaustive optimum
     assert rec["rms_ratio_to_optimum"] <= 1.15
-    # stratifying by beamlet count is at least as good as the plain top-k
-    assert rec["rms_ratio_to_optimum"] <= rec["plain_topk_ratio_to_optimum"] + 1e-12
     # and the online phase (inference + 32 re-scores) is cheaper than the exhaustive sweep
     assert rec["online_s"] < rec["exhaustive_s"]
 
