@@ -44,12 +44,17 @@ RATE = {"fp64": 64, "fp32": 128, "trans": 32}
 # HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE (x2.0)
 # and WRITE_SIZE (x1.0) runs, scale factors from a plain 256 MiB copy; valid
 # only for the kernel and launch they were taken on (else traffic is null).
-TRAFFIC = {("airy256_512", 16, 4, 24, 2): (2859.25 * 2.0 + 98304.0 * 1.0) * 1024}
+TRAFFIC = {("airy256_512", 32, 4, 48, 3): (6095.5 * 2.0 + 196608.0 * 1.0) * 1024}
 
 
 def instruction_mix(rows, variant):
+    """Instructions per beamlet-pixel pair of the mixed kernel's inner loop
+    (per lane and beamlet: an FP64 anchor, then R rows), counted in the
+    compiled gfx950 code."""
     R = float(rows)
-    if variant == 2:
+    if variant == 3:  # rotor: 8 FP32 per further row, 7 transcendentals per lane and beamlet
+        return {"fp64": 15 / R, "fp32": (8 * R + 13) / R, "trans": 7 / R}
+    if variant == 2:  # stepped: sin + cos per pixel
         return {"fp64": 15 / R, "fp32": (6 * R + 7) / R, "trans": (2 * R + 2) / R}
     return {"fp64": (4 * R + 10) / R, "fp32": (5 * R + 5) / R, "trans": 3.0}
 
@@ -64,7 +69,8 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    # the GPU's clocks settle over the first ~15 launches of the evaluation
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="airy256_512")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-sweep", action="store_true", help="skip the 441-instance batched sweep figure")
@@ -74,8 +80,9 @@ def main():
                     help="also run one plain 256 MiB device copy (a known-size kernel for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build measures one GPU; multi-GPU runs are not part of it "
-              "(the path would shard by pixel rows, see DESIGN.md)", file=sys.stderr)
+        print("bench.py measures one GPU; multi-GPU runs are not part of it "
+              "(the path would shard by pixel rows: every GPU holds all beamlet records and evaluates "
+              "its own band of rows, with no reduction)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

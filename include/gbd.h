@@ -59,15 +59,21 @@ typedef struct gbd_plan_s *gbd_plan_t;
 /* Launch shape of the N x M evaluation kernels.  All-zero = library choice
  * (autotuner cache if filled, else built-in defaults). */
 typedef struct {
-    int32_t rows_per_lane;  /* pixels per lane along a detector column: 1, 2, 4, 8 (16: mixed only) */
+    int32_t rows_per_lane;  /* pixels per lane along a detector column: 1, 2, 4, 8 (16: mixed
+                               only; 32: rotor form only, runs 16 where the form resolves
+                               to direct or stepped) */
     int32_t waves;          /* wavefronts per workgroup: 1, 2 or 4 */
     int32_t segments;       /* beamlet segments evaluated by separate workgroups, 0 = auto */
-    int32_t variant;        /* mixed form only.  0 = auto; 1 = direct: FP64 phase and
-                               exp2 per pixel; 2 = stepped: FP64 phase per lane and beamlet
-                               with FP32 row steps, amplitude stepped by multiplication.
-                               Stepped is used (auto) or honoured (2) only when the setup
-                               finds every beamlet's log2-amplitude curvature below 0.1
-                               per row^2 (well-sampled spots); otherwise direct. */
+    int32_t variant;        /* mixed form only.  0 = auto (rotor); 1 = direct: FP64 phase
+                               and exp2 per pixel; 2 = stepped: FP64 phase per lane and
+                               beamlet with FP32 row steps, amplitude stepped by
+                               multiplication; 3 = rotor: per lane and beamlet an FP64
+                               anchor phasor at the lane's middle row, the other rows by
+                               complex recurrence (anchor x rho^k x sigma^(k^2)).
+                               Stepped and rotor are used (auto) or honoured (2, 3) only
+                               when the setup finds every beamlet's log2-amplitude
+                               curvature below 0.1 per row^2 (well-sampled spots);
+                               otherwise direct. */
 } gbd_eval_opts;
 
 /* --- context ------------------------------------------------------------ */
@@ -137,7 +143,7 @@ int gbd_plan_shape(gbd_ctx_t ctx, gbd_plan_t plan, int precision, const gbd_eval
 
 /* --- autotuner ---------------------------------------------------------------
  * gbd_autotune: times every launch shape of gbd_plan_eval for this plan and
- * precision (rows_per_lane in {2,4,8} (and 16 for the mixed form) x waves in
+ * precision (rows_per_lane in {2,4,8} (and 16, 32 for the mixed form) x waves in
  * {1,2,4} x segment counts of
  * 1/2, 1, 2 and 4 times the automatic choice; `reps` timed launches each, HIP
  * events on the context stream), stores the fastest in the context's cache
@@ -189,7 +195,8 @@ int gbd_airy(gbd_ctx_t ctx, gbd_plane_t p, double D, double f, double lambda, fl
  *               origin, then the RMS of each zone; required iff airy != NULL
  *   fields_out  optional device complex64 fields, instance after instance
  *               ([n_inst][ny_i][nx_i]); fields_bytes its size
- * opts: rows_per_lane and waves as for gbd_eval (segments is ignored).
+ * opts: rows_per_lane and waves as for gbd_eval (segments is ignored; default
+ * 32 x 4 for the rotor form, else 16 x 4, or the autotuner's choice).
  * Synchronises the context stream (setup status, then metrics). */
 int gbd_eval_batch(gbd_ctx_t ctx, int32_t n_inst, const gbd_beamlets_t *beamlets, const gbd_plane_t *planes,
                    const float *airy, int64_t airy_bytes, const double *zone_edges, int32_t n_zones,

@@ -67,7 +67,7 @@ struct gbd_plan_s {
     int64_t n;
     PlaneGeom pl;
     bool ready;
-    bool steep;  // some beamlet's amplitude is too steep for the stepped mixed kernel
+    bool steep;  // some beamlet's amplitude is too steep for the stepped and rotor forms
     Rec64 *r64;
     Rec32 *r32;
     uint32_t *status_dev;
@@ -143,15 +143,20 @@ int ensure_device(gbd_ctx_s *ctx) {
 }
 
 struct Shape {
-    int rows, waves, nseg, step;
+    int rows, waves, nseg, form;
 };
 
-// stepped mixed kernel: requested or automatic, and safe for this setup
-int pick_step(int precision, bool steep, const gbd_eval_opts *o) {
+// mixed kernel form (0 direct, 1 stepped, 2 rotor): requested or automatic;
+// the stepped and rotor forms only where the setup found the grid well
+// sampled (no FLAG_STEEP)
+int pick_form(int precision, bool steep, const gbd_eval_opts *o) {
     if (precision != GBD_MIXED || steep) return 0;
     const int v = o ? o->variant : 0;
-    return v == 1 ? 0 : 1;
+    return v == 1 ? 0 : v == 2 ? 1 : 2;
 }
+
+// the variant a resolved form reports (gbd_eval_opts.variant)
+int form_variant(int precision, int form) { return precision == GBD_MIXED ? form + 1 : 0; }
 
 int ilog2(int64_t v) {
     int r = 0;
@@ -164,12 +169,16 @@ int ilog2(int64_t v) {
 
 TuneKey tune_key(int kind, int precision, int64_t n, int64_t m) { return TuneKey{kind, precision, ilog2(n), ilog2(m)}; }
 
-Shape choose_shape(const gbd_ctx_s *ctx, int precision, int64_t n, const PlaneGeom &pl, const gbd_eval_opts *o) {
+// Launch shape and mixed form.  32 rows per lane is a rotor-form shape: where
+// the form resolves to direct or stepped it runs 16.
+Shape choose_shape(const gbd_ctx_s *ctx, int precision, int64_t n, const PlaneGeom &pl, bool steep,
+                   const gbd_eval_opts *o) {
     Shape s;
-    s.rows = (precision == GBD_MIXED) ? 16 : 4;
+    s.form = pick_form(precision, steep, o);
+    // rotor form: 32 rows per lane where the grid fills a 4-wave tile
+    s.rows = (precision != GBD_MIXED) ? 4 : (s.form == 2 && pl.ny >= 128) ? 32 : 16;
     s.waves = 4;
     s.nseg = 0;
-    s.step = 0;
     int seg_pct = 100;
     const bool user = o && (o->rows_per_lane || o->waves || o->segments);
     if (!user) {
@@ -185,6 +194,7 @@ Shape choose_shape(const gbd_ctx_s *ctx, int precision, int64_t n, const PlaneGe
         if (o->waves) s.waves = o->waves;
         if (o->segments) s.nseg = o->segments;
     }
+    if (s.rows == 32 && s.form != 2) s.rows = 16;
     if (s.nseg <= 0) {
         // enough workgroups to keep every SIMD of every CU busy ~6 waves deep,
         // while each segment keeps at least two LDS tiles of beamlets
@@ -201,7 +211,8 @@ Shape choose_shape(const gbd_ctx_s *ctx, int precision, int64_t n, const PlaneGe
 }
 
 bool valid_shape(int rows, int waves, int precision = GBD_MIXED) {
-    const bool r = rows == 1 || rows == 2 || rows == 4 || rows == 8 || (rows == 16 && precision == GBD_MIXED);
+    const bool r = rows == 1 || rows == 2 || rows == 4 || rows == 8 ||
+                   ((rows == 16 || rows == 32) && precision == GBD_MIXED);
     return r && (waves == 1 || waves == 2 || waves == 4);
 }
 
@@ -235,11 +246,12 @@ int plan_eval_impl(gbd_ctx_s *ctx, gbd_plan_s *plan, int precision, void *out, i
     if (!out) return fail(GBD_EINVAL, "field_out is NULL");
     if (out_bytes < M * elem)
         return fail(GBD_ERANGE, "field_out holds %lld bytes, %lld needed", (long long)out_bytes, (long long)(M * elem));
-    Shape s = choose_shape(ctx, precision, plan->n, plan->pl, opts);
+    if (opts && (opts->variant < 0 || opts->variant > 3)) return fail(GBD_EINVAL, "variant must be 0, 1, 2 or 3");
+    if (opts && opts->rows_per_lane && !valid_shape(opts->rows_per_lane, opts->waves ? opts->waves : 4, precision))
+        return fail(GBD_EINVAL, "unsupported rows_per_lane %d / waves %d", opts->rows_per_lane, opts->waves);
+    Shape s = choose_shape(ctx, precision, plan->n, plan->pl, plan->steep, opts);
     if (!valid_shape(s.rows, s.waves, precision))
         return fail(GBD_EINVAL, "unsupported rows_per_lane %d / waves %d", s.rows, s.waves);
-    if (opts && (opts->variant < 0 || opts->variant > 2)) return fail(GBD_EINVAL, "variant must be 0, 1 or 2");
-    s.step = pick_step(precision, plan->steep, opts);
     int rc = ensure_device(ctx);
     if (rc) return rc;
     if (plan->n == 0) {
@@ -260,7 +272,7 @@ int plan_eval_impl(gbd_ctx_s *ctx, gbd_plan_s *plan, int precision, void *out, i
         }
     }
     const void *rec = precision == GBD_FP64 ? (const void *)plan->r64 : (const void *)plan->r32;
-    HIP_TRY(launch_eval(precision, s.rows, s.waves, s.step, g, rec, plan->scratch, out, ctx->stream), "eval kernel launch");
+    HIP_TRY(launch_eval(precision, s.rows, s.waves, s.form, g, rec, plan->scratch, out, ctx->stream), "eval kernel launch");
     if (g.nseg > 1) HIP_TRY(launch_reduce(precision, g, plan->scratch, out, ctx->stream), "reduce kernel launch");
     return GBD_OK;
 }
@@ -523,12 +535,12 @@ void gbd_plan_free(gbd_plan_t plan) { plan_destroy(plan); }
 
 int gbd_plan_shape(gbd_ctx_t ctx, gbd_plan_t plan, int precision, const gbd_eval_opts *opts, gbd_eval_opts *resolved) {
     if (!ctx || !plan || !resolved) return fail(GBD_EINVAL, "NULL argument");
-    Shape s = choose_shape(ctx, precision, plan->n, plan->pl, opts);
+    Shape s = choose_shape(ctx, precision, plan->n, plan->pl, plan->steep, opts);
     EvalGeom g = make_geom(plan->pl, plan->n, s);
     resolved->rows_per_lane = s.rows;
     resolved->waves = s.waves;
     resolved->segments = g.nseg;
-    resolved->variant = precision == GBD_MIXED ? (pick_step(precision, plan->steep, opts) ? 2 : 1) : 0;
+    resolved->variant = form_variant(precision, s.form);
     return GBD_OK;
 }
 
@@ -570,8 +582,8 @@ int gbd_autotune(gbd_ctx_t ctx, gbd_plan_t plan, int precision, int32_t reps, gb
     hipError_t he = hipEventCreate(&e0);
     if (he == hipSuccess) he = hipEventCreate(&e1);
     TuneVal bestv{0, 0, 100, 1e300};
-    static const int rows_c[] = {2, 4, 8, 16}, waves_c[] = {1, 2, 4}, pct_c[] = {50, 100, 200, 400};
-    const int n_rows = precision == GBD_MIXED ? 4 : 3;
+    static const int rows_c[] = {2, 4, 8, 16, 32}, waves_c[] = {1, 2, 4}, pct_c[] = {50, 100, 200, 400};
+    const int n_rows = precision == GBD_MIXED ? (plan->steep ? 4 : 5) : 3;
     for (int ri = 0; ri < n_rows && he == hipSuccess && rc == GBD_OK; ri++)
         for (int wi = 0; wi < 3 && he == hipSuccess && rc == GBD_OK; wi++)
             for (int pi = 0; pi < 4 && he == hipSuccess && rc == GBD_OK; pi++) {
@@ -606,9 +618,9 @@ int gbd_autotune(gbd_ctx_t ctx, gbd_plan_t plan, int precision, int32_t reps, gb
     if (he != hipSuccess) return hip_fail(he, "autotune timing");
     ctx->tuned[tune_key(0, precision, plan->n, M)] = bestv;
     if (best) {
-        const Shape s = choose_shape(ctx, precision, plan->n, plan->pl, nullptr);
+        const Shape s = choose_shape(ctx, precision, plan->n, plan->pl, plan->steep, nullptr);
         const EvalGeom g = make_geom(plan->pl, plan->n, s);
-        *best = gbd_eval_opts{s.rows, s.waves, g.nseg, pick_step(precision, plan->steep, nullptr) ? 2 : (precision == GBD_MIXED ? 1 : 0)};
+        *best = gbd_eval_opts{s.rows, s.waves, g.nseg, form_variant(precision, s.form)};
     }
     if (best_ms) *best_ms = bestv.ms;
     return GBD_OK;
@@ -706,7 +718,8 @@ int gbd_eval_batch(gbd_ctx_t ctx, int32_t n_inst, const gbd_beamlets_t *bs, cons
     }
     if (metrics_out && !airy) return fail(GBD_EINVAL, "metrics need the reference irradiance");
     if (airy && !metrics_out) return fail(GBD_EINVAL, "metrics_out is NULL");
-    int rows = 16, waves = 4;
+    if (opts && (opts->variant < 0 || opts->variant > 3)) return fail(GBD_EINVAL, "variant must be 0, 1, 2 or 3");
+    int rows = 32, waves = 4;  // 32 rows: rotor form; 16 where the form resolves otherwise
     int64_t pairs = 0;
     for (int32_t i = 0; i < n_inst; i++) {
         if (!bs[i] || !ps[i]) return fail(GBD_EINVAL, "instance %d has a NULL handle", i);
@@ -723,7 +736,12 @@ int gbd_eval_batch(gbd_ctx_t ctx, int32_t n_inst, const gbd_beamlets_t *bs, cons
         if (opts->rows_per_lane) rows = opts->rows_per_lane;
         if (opts->waves) waves = opts->waves;
     }
-    if (!valid_shape(rows, waves)) return fail(GBD_EINVAL, "unsupported rows_per_lane %d / waves %d", rows, waves);
+    if (!valid_shape(rows, waves)) return fail(GBD_EINVAL, "unsupported batch rows_per_lane %d / waves %d", rows, waves);
+    // work items per instance for a given tile height; the count at 16 rows
+    // bounds the one at 32 (the row count is final once the form is known)
+    auto tiles_of = [&](const PlaneGeom &g, int r) -> int64_t {
+        return (int64_t)((g.nx + 63) / 64) * ((g.ny + waves * r - 1) / (waves * r));
+    };
     int64_t total = 0, field_elems = 0, n_items = 0;
     for (int32_t i = 0; i < n_inst; i++) {
         const PlaneGeom &g = ps[i]->g;
@@ -734,7 +752,7 @@ int gbd_eval_batch(gbd_ctx_t ctx, int32_t n_inst, const gbd_beamlets_t *bs, cons
         }
         total += bs[i]->dev.n;
         field_elems += (int64_t)g.nx * g.ny;
-        n_items += (int64_t)((g.nx + 63) / 64) * ((g.ny + waves * rows - 1) / (waves * rows));
+        n_items += tiles_of(g, std::min(rows, 16));
     }
     if (fields_out && fields_bytes < field_elems * 8)
         return fail(GBD_ERANGE, "fields_out holds %lld bytes, %lld needed", (long long)fields_bytes,
@@ -743,52 +761,17 @@ int gbd_eval_batch(gbd_ctx_t ctx, int32_t n_inst, const gbd_beamlets_t *bs, cons
     int rc = ensure_device(ctx);
     if (rc) return rc;
 
-    // host tables; the work list takes instances largest first (LPT), each
-    // instance's tiles contiguous and in order
+    // per-beamlet setup of every instance; the status decides the mixed form
     std::vector<BatchInst> inst(n_inst);
     std::vector<int64_t> offs(n_inst + 1, 0);
-    std::vector<BatchEval> ev(n_inst);
     for (int32_t i = 0; i < n_inst; i++) {
         const BeamletsDev &b = bs[i]->dev;
-        const PlaneGeom &g = ps[i]->g;
         offs[i + 1] = offs[i] + b.n;
         const double g0 = b.l0 / b.lam;
         inst[i].b = b;
-        inst[i].pl = g;
+        inst[i].pl = ps[i]->g;
         inst[i].rec_off = offs[i];
         inst[i].gturns = g0 - nearbyint(g0);
-        BatchEval &e = ev[i];
-        e.rec_off = offs[i];
-        e.n = b.n;
-        e.nx = g.nx;
-        e.ny = g.ny;
-        e.tiles_x = (g.nx + 63) / 64;
-        e.tiles_y = (g.ny + waves * rows - 1) / (waves * rows);
-        e.dx = g.dx;
-        e.dy = g.dy;
-        e.a0 = -0.5 * (g.nx - 1) * g.dx;
-        e.b0 = -0.5 * (g.ny - 1) * g.dy;
-    }
-    std::vector<int32_t> order(n_inst);
-    for (int32_t i = 0; i < n_inst; i++) order[i] = i;
-    std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
-        return ev[x].n * ((int64_t)ev[x].nx * ev[x].ny) > ev[y].n * ((int64_t)ev[y].nx * ev[y].ny);
-    });
-    std::vector<int32_t> items;
-    items.reserve(2 * n_items);
-    int64_t foff = 0;
-    for (int32_t i = 0; i < n_inst; i++) {
-        ev[i].field_off = foff;
-        foff += (int64_t)ev[i].nx * ev[i].ny;
-    }
-    for (int32_t k = 0; k < n_inst; k++) {
-        const int32_t i = order[k];
-        ev[i].item_off = (int64_t)items.size() / 2;
-        const int32_t tiles = ev[i].tiles_x * ev[i].tiles_y;
-        for (int32_t t = 0; t < tiles; t++) {
-            items.push_back(i);
-            items.push_back(t);
-        }
     }
     const int PS = 2 + 2 * n_zones;
     BatchWork &w = ctx->batch;
@@ -796,7 +779,7 @@ int gbd_eval_batch(gbd_ctx_t ctx, int32_t n_inst, const gbd_beamlets_t *bs, cons
         (rc = grow(w.inst, n_inst * sizeof(BatchInst), "batch table")) ||
         (rc = grow(w.offs, (n_inst + 1) * sizeof(int64_t), "batch offsets")) ||
         (rc = grow(w.eval, n_inst * sizeof(BatchEval), "batch table")) ||
-        (rc = grow(w.items, std::max<size_t>(items.size(), 2) * sizeof(int32_t), "batch work list")) ||
+        (rc = grow(w.items, (size_t)std::max<int64_t>(2 * n_items, 2) * sizeof(int32_t), "batch work list")) ||
         (rc = grow(w.e0, n_inst * sizeof(double2), "batch normalisation")) ||
         (rc = grow(w.part, (size_t)std::max<int64_t>(n_items, 1) * PS * sizeof(double), "batch partials")) ||
         (rc = grow(w.metrics, (size_t)n_inst * (2 + n_zones) * sizeof(double), "batch metrics")) ||
@@ -806,10 +789,6 @@ int gbd_eval_batch(gbd_ctx_t ctx, int32_t n_inst, const gbd_beamlets_t *bs, cons
     hipStream_t st = ctx->stream;
     HIP_TRY(hipMemcpyAsync(w.inst.p, inst.data(), n_inst * sizeof(BatchInst), hipMemcpyHostToDevice, st), "table upload");
     HIP_TRY(hipMemcpyAsync(w.offs.p, offs.data(), (n_inst + 1) * sizeof(int64_t), hipMemcpyHostToDevice, st), "table upload");
-    HIP_TRY(hipMemcpyAsync(w.eval.p, ev.data(), n_inst * sizeof(BatchEval), hipMemcpyHostToDevice, st), "table upload");
-    if (!items.empty())
-        HIP_TRY(hipMemcpyAsync(w.items.p, items.data(), items.size() * sizeof(int32_t), hipMemcpyHostToDevice, st),
-                "work list upload");
     uint32_t *flags = static_cast<uint32_t *>(w.flags.p);  // [0] status, [1] first bad instance, [2] queue head
     HIP_TRY(hipMemsetAsync(flags, 0, sizeof(uint32_t), st), "hipMemsetAsync");
     HIP_TRY(hipMemsetAsync(flags + 1, 0x7f, sizeof(uint32_t), st), "hipMemsetAsync");
@@ -823,8 +802,50 @@ int gbd_eval_batch(gbd_ctx_t ctx, int32_t n_inst, const gbd_beamlets_t *bs, cons
     if (stat & FLAG_PARALLEL) return fail(GBD_EPARALLEL, "instance %d: a base ray is parallel to the plane", bad);
     if (stat & FLAG_BRANCH) return fail(GBD_EBRANCH, "instance %d: an eigenvalue left the principal branch", bad);
     if (stat & FLAG_NONFINITE) return fail(GBD_EINVAL, "instance %d: non-finite beamlet parameters", bad);
-    if (opts && (opts->variant < 0 || opts->variant > 2)) return fail(GBD_EINVAL, "variant must be 0, 1 or 2");
-    const int step = pick_step(GBD_MIXED, (stat & FLAG_STEEP) != 0, opts);
+    const int form = pick_form(GBD_MIXED, (stat & FLAG_STEEP) != 0, opts);
+    if (rows == 32 && form != 2) rows = 16;  // 32 rows is a rotor-form shape
+
+    // evaluation tables; the work list takes instances largest first (LPT),
+    // each instance's tiles contiguous and in order
+    std::vector<BatchEval> ev(n_inst);
+    int64_t foff = 0;
+    for (int32_t i = 0; i < n_inst; i++) {
+        const PlaneGeom &g = ps[i]->g;
+        BatchEval &e = ev[i];
+        e.rec_off = offs[i];
+        e.n = bs[i]->dev.n;
+        e.nx = g.nx;
+        e.ny = g.ny;
+        e.tiles_x = (g.nx + 63) / 64;
+        e.tiles_y = (g.ny + waves * rows - 1) / (waves * rows);
+        e.dx = g.dx;
+        e.dy = g.dy;
+        e.a0 = -0.5 * (g.nx - 1) * g.dx;
+        e.b0 = -0.5 * (g.ny - 1) * g.dy;
+        e.field_off = foff;
+        foff += (int64_t)g.nx * g.ny;
+    }
+    std::vector<int32_t> order(n_inst);
+    for (int32_t i = 0; i < n_inst; i++) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
+        return ev[x].n * ((int64_t)ev[x].nx * ev[x].ny) > ev[y].n * ((int64_t)ev[y].nx * ev[y].ny);
+    });
+    std::vector<int32_t> items;
+    items.reserve(2 * n_items);
+    for (int32_t k = 0; k < n_inst; k++) {
+        const int32_t i = order[k];
+        ev[i].item_off = (int64_t)items.size() / 2;
+        const int32_t tiles = ev[i].tiles_x * ev[i].tiles_y;
+        for (int32_t t = 0; t < tiles; t++) {
+            items.push_back(i);
+            items.push_back(t);
+        }
+    }
+    n_items = (int64_t)items.size() / 2;
+    HIP_TRY(hipMemcpyAsync(w.eval.p, ev.data(), n_inst * sizeof(BatchEval), hipMemcpyHostToDevice, st), "table upload");
+    if (!items.empty())
+        HIP_TRY(hipMemcpyAsync(w.items.p, items.data(), items.size() * sizeof(int32_t), hipMemcpyHostToDevice, st),
+                "work list upload");
 
     BatchArgs a;
     a.inst = static_cast<const BatchEval *>(w.eval.p);
@@ -843,7 +864,7 @@ int gbd_eval_batch(gbd_ctx_t ctx, int32_t n_inst, const gbd_beamlets_t *bs, cons
     if (airy)
         HIP_TRY(launch_batch_e0(a.inst, n_inst, a.rec, static_cast<double2 *>(w.e0.p), st), "normalisation launch");
     HIP_TRY(hipMemsetAsync(flags + 2, 0, sizeof(uint32_t), st), "hipMemsetAsync");
-    HIP_TRY(launch_batch_eval(rows, waves, step, ctx->cus, a, st), "batch eval launch");
+    HIP_TRY(launch_batch_eval(rows, waves, form, ctx->cus, a, st), "batch eval launch");
     if (airy) {
         HIP_TRY(launch_batch_finalize(a.inst, n_inst, a.part, n_zones, static_cast<double *>(w.metrics.p), st),
                 "finalize launch");
@@ -865,9 +886,9 @@ int gbd_autotune_batch(gbd_ctx_t ctx, int32_t n_inst, const gbd_beamlets_t *bs, 
         pairs += bs[i]->dev.n * ((int64_t)ps[i]->g.nx * ps[i]->g.ny);
     }
     std::vector<double> metrics((size_t)n_inst * 2);
-    static const int rows_c[] = {2, 4, 8, 16}, waves_c[] = {1, 2, 4};
+    static const int rows_c[] = {2, 4, 8, 16, 32}, waves_c[] = {1, 2, 4};
     TuneVal bestv{0, 0, 100, 1e300};
-    for (int ri = 0; ri < 4; ri++)
+    for (int ri = 0; ri < 5; ri++)
         for (int wi = 0; wi < 3; wi++) {
             gbd_eval_opts o{rows_c[ri], waves_c[wi], 0, 0};
             int rc = gbd_eval_batch(ctx, n_inst, bs, ps, airy, airy_bytes, nullptr, 0, metrics.data(), nullptr, 0, &o);

@@ -85,7 +85,7 @@ __device__ inline double wave_max(double v) {
     return v;
 }
 
-template <int ROWS, int WAVES, int STEP>
+template <int ROWS, int WAVES, int FORM>
 __global__ void __launch_bounds__(64 * WAVES) batch_eval_kernel(BatchArgs A) {
     constexpr int NQ = 2 + 2 * kMaxZones;
     __shared__ Rec32 tile[kMixedTile];
@@ -109,7 +109,10 @@ __global__ void __launch_bounds__(64 * WAVES) batch_eval_kernel(BatchArgs A) {
         float s_re[ROWS], s_im[ROWS], c_re[ROWS], c_im[ROWS];
 #pragma unroll
         for (int k = 0; k < ROWS; k++) s_re[k] = s_im[k] = c_re[k] = c_im[k] = 0.0f;
-        if (STEP)
+        if constexpr (FORM == 2)
+            mixed_accumulate_rotor<ROWS, 64 * WAVES>(tile, A.rec + I.rec_off, 0, I.n, a, b0, I.dy, s_re, s_im, c_re,
+                                                     c_im);
+        else if constexpr (FORM == 1)
             mixed_accumulate_step<ROWS, 64 * WAVES>(tile, A.rec + I.rec_off, 0, I.n, a, b0, I.dy, s_re, s_im, c_re,
                                                     c_im);
         else
@@ -203,16 +206,16 @@ __global__ void __launch_bounds__(256) airy_kernel(int32_t nx, int32_t ny, doubl
     }
 }
 
-template <int ROWS, int WAVES, int STEP>
+template <int ROWS, int WAVES, int FORM>
 hipError_t launch_batch_eval_t(int cus, const BatchArgs &a, hipStream_t s) {
     int per_cu = 0;
     hipError_t e =
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_eval_kernel<ROWS, WAVES, STEP>, 64 * WAVES, 0);
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_eval_kernel<ROWS, WAVES, FORM>, 64 * WAVES, 0);
     if (e != hipSuccess) return e;
     if (per_cu < 1) per_cu = 1;
     const int grid = (int)min((int64_t)a.n_items, (int64_t)cus * per_cu);
     if (grid <= 0) return hipSuccess;
-    batch_eval_kernel<ROWS, WAVES, STEP><<<grid, 64 * WAVES, 0, s>>>(a);
+    batch_eval_kernel<ROWS, WAVES, FORM><<<grid, 64 * WAVES, 0, s>>>(a);
     return hipGetLastError();
 }
 
@@ -231,16 +234,23 @@ hipError_t launch_batch_e0(const BatchEval *inst, int32_t n_inst, const Rec32 *r
     return hipGetLastError();
 }
 
-hipError_t launch_batch_eval(int rows, int waves, int step, int cus, const BatchArgs &a, hipStream_t s) {
-#define GBD_CASE(R, W)                                                              \
-    if (rows == R && waves == W)                                                    \
-        return step ? launch_batch_eval_t<R, W, 1>(cus, a, s) : launch_batch_eval_t<R, W, 0>(cus, a, s);
+hipError_t launch_batch_eval(int rows, int waves, int form, int cus, const BatchArgs &a, hipStream_t s) {
+#define GBD_CASE(R, W)                                                                         \
+    if (rows == R && waves == W)                                                               \
+        return form == 2   ? launch_batch_eval_t<R, W, 2>(cus, a, s)                           \
+               : form == 1 ? launch_batch_eval_t<R, W, 1>(cus, a, s)                           \
+                           : launch_batch_eval_t<R, W, 0>(cus, a, s);
     GBD_CASE(1, 1) GBD_CASE(1, 2) GBD_CASE(1, 4)
     GBD_CASE(2, 1) GBD_CASE(2, 2) GBD_CASE(2, 4)
     GBD_CASE(4, 1) GBD_CASE(4, 2) GBD_CASE(4, 4)
     GBD_CASE(8, 1) GBD_CASE(8, 2) GBD_CASE(8, 4)
     GBD_CASE(16, 1) GBD_CASE(16, 2) GBD_CASE(16, 4)
 #undef GBD_CASE
+    if (rows == 32 && form == 2) {  // rotor form only
+        if (waves == 1) return launch_batch_eval_t<32, 1, 2>(cus, a, s);
+        if (waves == 2) return launch_batch_eval_t<32, 2, 2>(cus, a, s);
+        if (waves == 4) return launch_batch_eval_t<32, 4, 2>(cus, a, s);
+    }
     return hipErrorInvalidValue;
 }
 

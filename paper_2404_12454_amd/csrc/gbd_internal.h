@@ -41,16 +41,18 @@ struct alignas(16) Rec64 {
 static_assert(sizeof(Rec64) == 128, "Rec64 layout");
 
 // Mixed-precision record: FP64 phase in turns, FP32 log2-amplitude, and the
-// lane-independent row-step terms of the stepped kernel for this plane's dy:
-// t2 = p5 dy^2 reduced mod 1, u2 = m5 dy^2, s2 = 2^(2 u2).
+// lane-independent row-step terms for this plane's dy:
+//   stepped form: t2 = p5 dy^2 reduced mod 1, u2 = m5 dy^2, s2 = 2^(2 u2);
+//   rotor form:   sq[k-1] = sigma^(k^2), sigma = 2^(u2) e^(2 pi i t2), k = 1..16.
 struct alignas(16) Rec32 {
     double arho, brho;
     double p[6];
     float m[6];   // l / ln 2
     float arho_f, brho_f;
     float t2, u2, s2, pad;
+    float sq[16][2];
 };
-static_assert(sizeof(Rec32) == 112, "Rec32 layout");
+static_assert(sizeof(Rec32) == 240, "Rec32 layout");
 constexpr int kRec32Vec4 = sizeof(Rec32) / 16;
 
 enum : uint32_t {
@@ -64,9 +66,12 @@ enum : uint32_t {
 };
 
 // largest |d^2 log2(amplitude) / d row^2| / 2 for which the mixed kernel may
-// step the amplitude along a column by multiplication (no term above 2^-80
-// of its beamlet's peak can underflow over 8 rows)
+// step the amplitude along a column by multiplication: over 16 rows no term
+// above 2^-80 of its beamlet's peak can then underflow; the rotor form (up
+// to 32 rows, at most 16 steps from its anchor) keeps sigma^(k^2) within
+// 2^(+-25.6)
 constexpr double kStepCurvature = 0.1;
+constexpr int kRotorRows = 16;  // sigma^(k^2) entries: rows per lane up to 2 * 16
 
 // Pixel grid handed to the evaluation kernels.
 struct EvalGeom {
@@ -118,7 +123,7 @@ struct BatchArgs {
 hipError_t launch_batch_setup(const BatchInst *inst, const int64_t *offs, int32_t n_inst, int64_t total,
                               Rec32 *rec, uint32_t *status, int32_t *bad, hipStream_t s);
 hipError_t launch_batch_e0(const BatchEval *inst, int32_t n_inst, const Rec32 *rec, double2 *e0, hipStream_t s);
-hipError_t launch_batch_eval(int rows, int waves, int step, int cus, const BatchArgs &a, hipStream_t s);
+hipError_t launch_batch_eval(int rows, int waves, int form, int cus, const BatchArgs &a, hipStream_t s);
 hipError_t launch_batch_finalize(const BatchEval *inst, int32_t n_inst, const double *part, int32_t n_zones,
                                  double *metrics, hipStream_t s);
 hipError_t launch_airy(int32_t nx, int32_t ny, double dx, double dy, double vscale, float *out, hipStream_t s);
@@ -172,10 +177,11 @@ hipError_t launch_mlp_adamw(float *p, const float *g, float *m, float *v, int64_
 hipError_t launch_setup(const BeamletsDev &b, const PlaneGeom &pl, double global_turns, Rec64 *r64,
                         Rec32 *r32, uint32_t *status, hipStream_t s);
 
-// step = 1: phase stepped in FP32 from an FP64 anchor and amplitude stepped by
-// multiplication along each lane's column; step = 0: per-pixel FP64 phase
-// and exp2 (mixed precision only)
-hipError_t launch_eval(int precision, int rows, int waves, int step, const EvalGeom &g, const void *rec,
+// Mixed precision only, form = 0 direct: per-pixel FP64 phase and exp2;
+// 1 stepped: phase stepped in FP32 from an FP64 anchor and amplitude stepped
+// by multiplication along each lane's column; 2 rotor: each lane's column
+// factored as anchor x rho^k x sigma^(k^2), no per-pixel transcendental.
+hipError_t launch_eval(int precision, int rows, int waves, int form, const EvalGeom &g, const void *rec,
                        void *partial, void *out, hipStream_t s);
 
 hipError_t launch_reduce(int precision, const EvalGeom &g, const void *partial, void *out, hipStream_t s);

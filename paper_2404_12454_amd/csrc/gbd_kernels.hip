@@ -32,7 +32,8 @@ __global__ void __launch_bounds__(256) setup_kernel(BeamletsDev b, PlaneGeom pl,
 // Mixed form.  Each lane owns ROWS pixels of one detector column; a
 // wavefront spans 64 consecutive columns (coalesced stores); WAVES
 // wavefronts stack in y; the workgroup sums one segment of beamlets.
-template <int ROWS, int WAVES, int STEP>
+// FORM: 0 direct, 1 stepped, 2 rotor accumulation.
+template <int ROWS, int WAVES, int FORM>
 __global__ void __launch_bounds__(64 * WAVES) eval_mixed_kernel(EvalGeom g, const Rec32 *__restrict__ rec,
                                                                 float4 *__restrict__ partial,
                                                                 float2 *__restrict__ out) {
@@ -54,7 +55,9 @@ __global__ void __launch_bounds__(64 * WAVES) eval_mixed_kernel(EvalGeom g, cons
     for (int k = 0; k < ROWS; k++) s_re[k] = s_im[k] = c_re[k] = c_im[k] = 0.0f;
     const int64_t jb = (int64_t)seg * g.seg_len;
     const int64_t je = min(g.n, jb + g.seg_len);
-    if (STEP)
+    if constexpr (FORM == 2)
+        mixed_accumulate_rotor<ROWS, 64 * WAVES>(tile, rec, jb, je, a, b0, g.dy, s_re, s_im, c_re, c_im);
+    else if constexpr (FORM == 1)
         mixed_accumulate_step<ROWS, 64 * WAVES>(tile, rec, jb, je, a, b0, g.dy, s_re, s_im, c_re, c_im);
     else
         mixed_accumulate<ROWS, 64 * WAVES>(tile, rec, jb, je, a, b0, g.dy, s_re, s_im, c_re, c_im);
@@ -175,10 +178,14 @@ __global__ void __launch_bounds__(256) reduce_fp64_kernel(int64_t M, int32_t nse
 }
 
 template <int ROWS, int WAVES>
-hipError_t launch_eval_t(int precision, int step, const EvalGeom &g, const void *rec, void *partial, void *out,
+hipError_t launch_eval_t(int precision, int form, const EvalGeom &g, const void *rec, void *partial, void *out,
                          hipStream_t s) {
     const int grid = (g.work + 7) / 8 * 8;
-    if (precision == 1 && step)
+    if (precision == 1 && form == 2)
+        eval_mixed_kernel<ROWS, WAVES, 2><<<grid, 64 * WAVES, 0, s>>>(g, static_cast<const Rec32 *>(rec),
+                                                                      static_cast<float4 *>(partial),
+                                                                      static_cast<float2 *>(out));
+    else if (precision == 1 && form == 1)
         eval_mixed_kernel<ROWS, WAVES, 1><<<grid, 64 * WAVES, 0, s>>>(g, static_cast<const Rec32 *>(rec),
                                                                       static_cast<float4 *>(partial),
                                                                       static_cast<float2 *>(out));
@@ -205,19 +212,34 @@ hipError_t launch_setup(const BeamletsDev &b, const PlaneGeom &pl, double global
     return hipGetLastError();
 }
 
-hipError_t launch_eval(int precision, int rows, int waves, int step, const EvalGeom &g, const void *rec, void *partial,
+hipError_t launch_eval(int precision, int rows, int waves, int form, const EvalGeom &g, const void *rec, void *partial,
                        void *out, hipStream_t s) {
 #define GBD_CASE(R, W) \
-    if (rows == R && waves == W) return launch_eval_t<R, W>(precision, step, g, rec, partial, out, s);
+    if (rows == R && waves == W) return launch_eval_t<R, W>(precision, form, g, rec, partial, out, s);
     GBD_CASE(1, 1) GBD_CASE(1, 2) GBD_CASE(1, 4)
     GBD_CASE(2, 1) GBD_CASE(2, 2) GBD_CASE(2, 4)
     GBD_CASE(4, 1) GBD_CASE(4, 2) GBD_CASE(4, 4)
     GBD_CASE(8, 1) GBD_CASE(8, 2) GBD_CASE(8, 4)
 #undef GBD_CASE
     if (precision == 1 && rows == 16) {
-        if (waves == 1) return launch_eval_t<16, 1>(precision, step, g, rec, partial, out, s);
-        if (waves == 2) return launch_eval_t<16, 2>(precision, step, g, rec, partial, out, s);
-        if (waves == 4) return launch_eval_t<16, 4>(precision, step, g, rec, partial, out, s);
+        if (waves == 1) return launch_eval_t<16, 1>(precision, form, g, rec, partial, out, s);
+        if (waves == 2) return launch_eval_t<16, 2>(precision, form, g, rec, partial, out, s);
+        if (waves == 4) return launch_eval_t<16, 4>(precision, form, g, rec, partial, out, s);
+    }
+    if (precision == 1 && rows == 32 && form == 2) {
+        const int grid = (g.work + 7) / 8 * 8;
+        if (waves == 1)
+            eval_mixed_kernel<32, 1, 2><<<grid, 64, 0, s>>>(g, static_cast<const Rec32 *>(rec),
+                                                            static_cast<float4 *>(partial), static_cast<float2 *>(out));
+        else if (waves == 2)
+            eval_mixed_kernel<32, 2, 2><<<grid, 128, 0, s>>>(g, static_cast<const Rec32 *>(rec),
+                                                             static_cast<float4 *>(partial), static_cast<float2 *>(out));
+        else if (waves == 4)
+            eval_mixed_kernel<32, 4, 2><<<grid, 256, 0, s>>>(g, static_cast<const Rec32 *>(rec),
+                                                             static_cast<float4 *>(partial), static_cast<float2 *>(out));
+        else
+            return hipErrorInvalidValue;
+        return hipGetLastError();
     }
     return hipErrorInvalidValue;
 }

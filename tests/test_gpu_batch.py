@@ -55,12 +55,13 @@ def test_batch_fields_bitwise_equal_single_instance(ctx):
     insts = small_instances()
     bs = [gbd.beamlets_from_scene(ctx, s) for s in insts]
     ps = [gbd.plane_from_scene(ctx, s) for s in insts]
-    for variant in (1, 2):
-        _, fields = gbd.gbd_eval_batch(ctx, bs, ps, fields=True, opts=dict(rows_per_lane=4, waves=2, variant=variant))
+    for rows, waves, variant in ((4, 2, 1), (4, 2, 2), (4, 2, 3), (32, 4, 3), (32, 1, 3)):
+        o = dict(rows_per_lane=rows, waves=waves, variant=variant)
+        _, fields = gbd.gbd_eval_batch(ctx, bs, ps, fields=True, opts=o)
         for s, b, p, F in zip(insts, bs, ps, fields):
-            E = gbd.gbd_eval(ctx, b, p, gbd.GBD_MIXED, opts=dict(rows_per_lane=4, waves=2, segments=1, variant=variant))
+            E = gbd.gbd_eval(ctx, b, p, gbd.GBD_MIXED, opts=dict(o, segments=1))
             torch.cuda.synchronize()
-            assert torch.equal(F.cpu().view(torch.float32), E.cpu().view(torch.float32)), variant
+            assert torch.equal(F.cpu().view(torch.float32), E.cpu().view(torch.float32)), o
 
 
 def test_batch_metrics_match_oracle(ctx):
@@ -103,7 +104,8 @@ def test_full_sweep_matches_single_instances(ctx):
     origin = [None]
     for k in range(0, len(insts), 7):
         s, b = insts[k], bs[k]
-        E = gbd.gbd_eval(ctx, b, ps[k], gbd.GBD_MIXED)
+        # the batch kernel's launch shape (one segment): the same field arithmetic
+        E = gbd.gbd_eval(ctx, b, ps[k], gbd.GBD_MIXED, opts=dict(rows_per_lane=32, waves=4, segments=1))
         pl = s.plane
         if origin[0] is None:
             origin[0] = gbd.gbd_plane(ctx, pl.origin, pl.normal, pl.xhint, 1, 1, pl.dx, pl.dy)
@@ -131,6 +133,20 @@ def test_batch_names_failing_instance(ctx):
     assert e.value.code == -4 and "instance 2" in str(e.value)
 
 
+def test_batch_autotuner_shape_and_metrics(ctx):
+    insts = small_instances()
+    bs = [gbd.beamlets_from_scene(ctx, s) for s in insts]
+    ps = [gbd.plane_from_scene(ctx, s) for s in insts]
+    m0 = insts[0].meta
+    airy = gbd.gbd_airy(ctx, ps[0], m0["D"], m0["f"], insts[0].lam)
+    ref, _ = gbd.gbd_eval_batch(ctx, bs, ps, airy=airy, opts=dict(rows_per_lane=16, waves=4))
+    best, ms = gbd.gbd_autotune_batch(ctx, bs, ps, airy, reps=2)
+    print("batch autotuned", best, ms, flush=True)
+    assert best["rows_per_lane"] in (2, 4, 8, 16, 32) and best["waves"] in (1, 2, 4) and ms > 0
+    got, _ = gbd.gbd_eval_batch(ctx, bs, ps, airy=airy)  # the cached shape
+    np.testing.assert_allclose(got, ref, rtol=1e-3, atol=1e-9)
+
+
 def test_autotuner_picks_a_valid_shape_and_results_hold(ctx, tmp_path):
     import torch
     sc = scenes.zernike_scene(31, n_across=40, npix=300, half_span=60e-6)
@@ -139,7 +155,7 @@ def test_autotuner_picks_a_valid_shape_and_results_hold(ctx, tmp_path):
     plan = gbd.Plan(ctx, sc.n).setup(b, p)
     best, ms = gbd.gbd_autotune(plan, gbd.GBD_MIXED, reps=2)
     print("autotuned", best, ms, flush=True)
-    assert best["rows_per_lane"] in (2, 4, 8) and best["waves"] in (1, 2, 4) and ms > 0
+    assert best["rows_per_lane"] in (2, 4, 8, 16, 32) and best["waves"] in (1, 2, 4) and ms > 0
     assert plan.shape(gbd.GBD_MIXED) == best          # the cache is used with default opts
     E = plan.eval(gbd.GBD_MIXED)
     torch.cuda.synchronize()

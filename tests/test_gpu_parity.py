@@ -68,8 +68,8 @@ def test_every_launch_shape_matches_oracle(ctx, precision):
     sc = scenes.zernike_scene(99, n_across=20, npix=70, half_span=40e-6)
     sc.plane.ny = 45
     ref = oracle.eval_field(sc)
-    variants = (1, 2) if precision == gbd.GBD_MIXED else (0,)
-    shapes = SHAPES + ([dict(rows_per_lane=16, waves=w, segments=s) for w in (1, 2, 4) for s in (1, 3)]
+    variants = (1, 2, 3) if precision == gbd.GBD_MIXED else (0,)
+    shapes = SHAPES + ([dict(rows_per_lane=r, waves=w, segments=s) for r in (16, 32) for w in (1, 2, 4) for s in (1, 3)]
                        if precision == gbd.GBD_MIXED else [])
     for v in variants:
         for o in shapes:
@@ -77,21 +77,24 @@ def test_every_launch_shape_matches_oracle(ctx, precision):
 
 
 @pytest.mark.parametrize("name", ["airy32_64", "zern128_1024"])
-def test_stepped_variant_is_chosen_and_matches_direct(ctx, name):
-    """On well-sampled grids the automatic mixed form is the stepped one; it
-    agrees with the direct form and with the oracle."""
-    import torch
+def test_rotor_variant_is_chosen_and_matches_direct(ctx, name):
+    """On well-sampled grids the automatic mixed form is the rotor one; it
+    and the stepped form agree with the direct form and with the oracle."""
     sc = scenes.config(name)
     b = gbd.beamlets_from_scene(ctx, sc)
     p = gbd.plane_from_scene(ctx, sc)
     plan = gbd.Plan(ctx, sc.n).setup(b, p)
-    assert plan.shape(gbd.GBD_MIXED)["variant"] == 2
-    E2 = plan.eval(gbd.GBD_MIXED).cpu().numpy()
+    assert plan.shape(gbd.GBD_MIXED)["variant"] == 3
+    E3 = plan.eval(gbd.GBD_MIXED).cpu().numpy()
+    E2 = plan.eval(gbd.GBD_MIXED, opts=dict(variant=2)).cpu().numpy()
     E1 = plan.eval(gbd.GBD_MIXED, opts=dict(variant=1)).cpu().numpy()
-    print(name, "stepped vs direct", rel_l2(E2, E1), flush=True)
+    print(name, "rotor vs direct", rel_l2(E3, E1), "stepped vs direct", rel_l2(E2, E1), flush=True)
+    assert rel_l2(E3, E1) < 1e-5
     assert rel_l2(E2, E1) < 1e-5
     if sc.plane.npix <= 4096:
-        check(E2, oracle.eval_field(sc), gbd.GBD_MIXED, name + " stepped")
+        ref = oracle.eval_field(sc)
+        check(E3, ref, gbd.GBD_MIXED, name + " rotor")
+        check(E2, ref, gbd.GBD_MIXED, name + " stepped")
 
 
 def test_steep_grid_falls_back_to_direct(ctx):
@@ -99,6 +102,9 @@ def test_steep_grid_falls_back_to_direct(ctx):
     plan = gbd.Plan(ctx, 1).setup(gbd.beamlets_from_scene(ctx, tail), gbd.plane_from_scene(ctx, tail))
     assert plan.shape(gbd.GBD_MIXED)["variant"] == 1
     assert plan.shape(gbd.GBD_MIXED, opts=dict(variant=2))["variant"] == 1
+    assert plan.shape(gbd.GBD_MIXED, opts=dict(variant=3))["variant"] == 1
+    # 32 rows per lane is a rotor-form shape; the direct form runs 16
+    assert plan.shape(gbd.GBD_MIXED, opts=dict(rows_per_lane=32))["rows_per_lane"] == 16
 
 
 @pytest.mark.parametrize("precision", BOTH)
@@ -231,8 +237,11 @@ def test_errors_are_reported_before_any_write(ctx):
     assert e.value.code == -3
     torch.cuda.synchronize()
     assert bool((sentinel == (7.0 + 7.0j)).all())
-    # output buffer too small
+    # output buffer too small; unknown mixed form
     good = gbd.beamlets_from_scene(ctx, sc)
+    with pytest.raises(gbd.GbdError) as e:
+        gbd.gbd_eval(ctx, good, p, gbd.GBD_MIXED, out=sentinel, opts=dict(variant=4))
+    assert e.value.code == -1
     small = torch.empty((3, 4), dtype=torch.complex128, device="cuda")
     with pytest.raises(gbd.GbdError) as e:
         load = gbd.load_library()
