@@ -8,10 +8,17 @@ inputs already resident in HBM.  Workload: 51,468 beamlets (256 across a
 10 mm f/10 pupil, OF 1.7) onto a 512 x 512 focal-plane detector spanning
 +-20 lambda F.  value = N * M / (time per step), beamlet-pixel evaluations/s.
 
+The mixed evaluation takes the library's automatic form: on this workload
+(a rotationally symmetric system on a plane normal to the axis, so no
+beamlet's phasor has a cross term) the separable matrix form on FP32 MFMA,
+whose roofline is the MFMA peak; the rotor form, which any plane with cross
+terms gets, is timed on the same workload beside it (general_form) with its
+instruction-mix roofline.
+
 Also reported: the FP64 form on the same workload (and the mixed/FP64
-speed-up), the instruction-mix roofline of the dominant kernel with its live
-HIP-event duration, and the FP64 CPU oracle timed on a bounded pixel sample
-(which also gives the mixed form's error against the oracle on that sample).
+speed-up), the dominant kernel's live HIP-event duration, point evaluation,
+the 441-instance sweep, and the FP64 CPU oracle timed on a bounded pixel
+sample (which also gives the mixed form's error against the oracle there).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 """
@@ -63,6 +70,28 @@ def roofline_peak(rows, variant):
     mix = instruction_mix(rows, variant)
     cycles = sum(n / RATE[k] for k, n in mix.items())
     return CUS * CLOCK_HZ / cycles, cycles, mix
+
+
+# Separable (matrix) form: the contraction E = V^T U over beamlets, 4 real
+# FP32 MFMA multiply-adds (8 flops) per beamlet-pixel pair; FP32 MFMA peak.
+MFMA_FP32_TFLOPS = 157.3
+SEP_FLOPS_PER_PAIR = 8.0
+# factor evaluation per lane per 4 beamlets and 64 x 64 pixels, counted in the
+# compiled loop: 40 FP64, 109 FP32, 24 transcendental, 64 MFMA 16x16x4
+SEP_VALU_PER_PAIR = {"fp64": 40 / 256, "fp32": 109 / 256, "trans": 24 / 256, "mfma_16x16x4": 64 / 16384}
+
+
+def roofline(shape, N, M, kernel_ms):
+    if shape["variant"] == 4:
+        achieved = SEP_FLOPS_PER_PAIR * N * M / (kernel_ms * 1e-3) / 1e12
+        return {"bound": "mfma", "achieved": achieved, "peak": MFMA_FP32_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / MFMA_FP32_TFLOPS, "kernel": "eval_sep_kernel", "kernel_ms": kernel_ms,
+                "flops_per_pair": SEP_FLOPS_PER_PAIR, "instructions_per_pair": SEP_VALU_PER_PAIR}
+    achieved = N * M / (kernel_ms * 1e-3)
+    peak, cycles, mix = roofline_peak(shape["rows_per_lane"], shape["variant"])
+    return {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "evals/s", "frac": achieved / peak,
+            "kernel": "eval_mixed_kernel", "kernel_ms": kernel_ms, "cu_cycles_per_pair": cycles,
+            "instructions_per_pair": mix}
 
 
 def main():
@@ -153,8 +182,9 @@ def main():
     mixed_vs_fp64 = float(np.linalg.norm(E32 - E64) / np.linalg.norm(E64))
 
     shape = plan.shape(gbd.GBD_MIXED)
-    achieved = N * M / (eval_ms_mean * 1e-3)
-    peak, cycles, mix = roofline_peak(shape["rows_per_lane"], shape["variant"])
+    roof = roofline(shape, N, M, eval_ms_mean)
+    roof["traffic"] = TRAFFIC.get((args.workload, shape["rows_per_lane"], shape["waves"], shape["segments"],
+                                   shape["variant"]))
     rec = {
         "metric": METRIC,
         "value": value,
@@ -171,12 +201,7 @@ def main():
         "config": {"workload": f"{args.workload}: {N} beamlets x {sc.plane.nx}x{sc.plane.ny} px, f/10, "
                                f"+-{sc.meta.get('half_span_lamF', 0):g} lamF, mixed precision",
                    "n_beamlets": N, "n_pixels": M, "launch": shape},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "evals/s",
-                     "frac": achieved / peak,
-                     "traffic": TRAFFIC.get((args.workload, shape["rows_per_lane"], shape["waves"],
-                                             shape["segments"], shape["variant"])),
-                     "kernel": "eval_mixed_kernel",
-                     "kernel_ms": eval_ms_mean, "cu_cycles_per_pair": cycles, "instructions_per_pair": mix},
+        "roofline": roof,
         "setup_ms": ms_step - eval_ms_mean,
         "fp64": {"value": N * M / (eval64_ms * 1e-3), "eval_ms": eval64_ms,
                  "speedup_mixed_over_fp64": eval64_ms / eval_ms_mean},
@@ -184,6 +209,8 @@ def main():
         "wall_s_timed": wall,
     }
 
+    if shape["variant"] == 4:
+        rec["general_form"] = general_form(plan, N, M, out, stream)
     if not args.no_point:
         rec["point_eval"] = point_eval(ctx, b, p, N * M, eval_ms_mean, eval64_ms)
     if not args.no_sweep:
@@ -191,6 +218,28 @@ def main():
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(sc, E32, E64)
     print(json.dumps(rec), flush=True)
+
+
+def general_form(plan, N, M, out, stream, reps=20):
+    """The same workload through the form that needs no separability (rotor,
+    variant 3): what any plane with cross terms (tilted, astigmatic) gets."""
+    import numpy as np
+    import torch
+    import paper_2404_12454_amd as gbd
+    o = dict(variant=3)
+    for _ in range(reps):
+        plan.eval(gbd.GBD_MIXED, out, opts=o)
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for a, z in evs:
+        a.record(stream)
+        plan.eval(gbd.GBD_MIXED, out, opts=o)
+        z.record(stream)
+    torch.cuda.synchronize()
+    ms = float(np.mean([a.elapsed_time(z) for a, z in evs]))
+    shape = plan.shape(gbd.GBD_MIXED, opts=o)
+    r = roofline(shape, N, M, ms)
+    return {"launch": shape, "eval_ms": ms, "evals_per_s": N * M / (ms * 1e-3), "roofline_frac": r["frac"],
+            "roofline_peak": r["peak"]}
 
 
 def point_eval(ctx, b, p, pairs, mixed_ms, fp64_ms, reps=2):

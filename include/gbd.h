@@ -64,16 +64,21 @@ typedef struct {
                                to direct or stepped) */
     int32_t waves;          /* wavefronts per workgroup: 1, 2 or 4 */
     int32_t segments;       /* beamlet segments evaluated by separate workgroups, 0 = auto */
-    int32_t variant;        /* mixed form only.  0 = auto (rotor); 1 = direct: FP64 phase
-                               and exp2 per pixel; 2 = stepped: FP64 phase per lane and
-                               beamlet with FP32 row steps, amplitude stepped by
-                               multiplication; 3 = rotor: per lane and beamlet an FP64
-                               anchor phasor at the lane's middle row, the other rows by
-                               complex recurrence (anchor x rho^k x sigma^(k^2)).
-                               Stepped and rotor are used (auto) or honoured (2, 3) only
-                               when the setup finds every beamlet's log2-amplitude
-                               curvature below 0.1 per row^2 (well-sampled spots);
-                               otherwise direct. */
+    int32_t variant;        /* mixed form only.  0 = auto; 1 = direct: FP64 phase and exp2
+                               per pixel; 2 = stepped: FP64 phase per lane and beamlet
+                               with FP32 row steps, amplitude stepped by multiplication;
+                               3 = rotor: per lane and beamlet an FP64 anchor phasor at
+                               the lane's middle row, the other rows by complex
+                               recurrence (anchor x rho^k x sigma^(k^2)); 4 = separable:
+                               E = sum_j U_j(x) V_j(y) as a complex matrix product on
+                               FP32 MFMA (rows_per_lane and waves do not apply).
+                               Separable is used (auto) or honoured (4) when no beamlet's
+                               phasor has a cross term (rotationally symmetric systems on
+                               a plane normal to the axis); stepped and rotor when the
+                               setup finds every beamlet's log2-amplitude curvature below
+                               0.1 per row^2 (well-sampled spots).  Auto: separable, else
+                               rotor, else direct; a request that does not apply falls
+                               back to auto's choice among the others. */
 } gbd_eval_opts;
 
 /* --- context ------------------------------------------------------------ */

@@ -12,12 +12,16 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgbd.so")
-SOURCES = ["gbd_api.hip", "gbd_kernels.hip", "gbd_batch.hip", "gbd_mlp.hip", "gbd_point.hip"]
+SOURCES = ["gbd_api.hip", "gbd_kernels.hip", "gbd_sep.hip", "gbd_batch.hip", "gbd_mlp.hip", "gbd_point.hip"]
 ARCH = os.environ.get("GBD_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # MFMA accumulators in ordinary VGPRs: with the accumulation registers the
+    # register allocator permutes the loop-carried accumulators of the
+    # separable form every iteration (v_accvgpr moves per MFMA)
+    "-mllvm", "-amdgpu-mfma-vgpr-form",
     "-Wall", "-Wno-unused-function",
 ]
 

@@ -67,7 +67,7 @@ struct gbd_plan_s {
     int64_t n;
     PlaneGeom pl;
     bool ready;
-    bool steep;  // some beamlet's amplitude is too steep for the stepped and rotor forms
+    uint32_t flags;  // FLAG_STEEP / FLAG_CROSS of the last setup (which mixed forms apply)
     Rec64 *r64;
     Rec32 *r32;
     uint32_t *status_dev;
@@ -146,13 +146,20 @@ struct Shape {
     int rows, waves, nseg, form;
 };
 
-// mixed kernel form (0 direct, 1 stepped, 2 rotor): requested or automatic;
-// the stepped and rotor forms only where the setup found the grid well
-// sampled (no FLAG_STEEP)
-int pick_form(int precision, bool steep, const gbd_eval_opts *o) {
-    if (precision != GBD_MIXED || steep) return 0;
+// mixed kernel form (0 direct, 1 stepped, 2 rotor, 3 separable): requested
+// or automatic.  The stepped and rotor forms need a well-sampled grid (no
+// FLAG_STEEP), the separable form phasors without cross terms (no
+// FLAG_CROSS); a request that does not apply falls back to the automatic
+// choice among the others.
+int pick_form(int precision, uint32_t flags, const gbd_eval_opts *o, bool allow_sep = true) {
+    if (precision != GBD_MIXED) return 0;
+    const bool steep = (flags & FLAG_STEEP) != 0;
+    const bool sep = allow_sep && !(flags & FLAG_CROSS);
     const int v = o ? o->variant : 0;
-    return v == 1 ? 0 : v == 2 ? 1 : 2;
+    if (v == 1) return 0;
+    if (v == 2) return steep ? 0 : 1;
+    if (v == 3) return steep ? 0 : 2;
+    return sep ? 3 : steep ? 0 : 2;
 }
 
 // the variant a resolved form reports (gbd_eval_opts.variant)
@@ -171,10 +178,27 @@ TuneKey tune_key(int kind, int precision, int64_t n, int64_t m) { return TuneKey
 
 // Launch shape and mixed form.  32 rows per lane is a rotor-form shape: where
 // the form resolves to direct or stepped it runs 16.
-Shape choose_shape(const gbd_ctx_s *ctx, int precision, int64_t n, const PlaneGeom &pl, bool steep,
+Shape choose_shape(const gbd_ctx_s *ctx, int precision, int64_t n, const PlaneGeom &pl, uint32_t flags,
                    const gbd_eval_opts *o) {
     Shape s;
-    s.form = pick_form(precision, steep, o);
+    s.form = pick_form(precision, flags, o);
+    if (s.form == 3) {
+        // separable form: fixed 64 x 64 pixel tile per wavefront; the row and
+        // wavefront options of the other forms do not apply
+        s.rows = kSepTile;
+        s.waves = kSepWavesX * kSepWavesY;
+        s.nseg = (o && o->segments > 0) ? o->segments : 0;
+        if (s.nseg <= 0) {
+            // three 4-wavefront workgroups per CU
+            const int64_t tiles = std::max<int64_t>(
+                1, (int64_t)((pl.nx + kSepTile * kSepWavesX - 1) / (kSepTile * kSepWavesX)) *
+                       ((pl.ny + kSepTile * kSepWavesY - 1) / (kSepTile * kSepWavesY)));
+            int64_t seg = ((int64_t)ctx->cus * 3 + tiles - 1) / tiles;
+            seg = std::min<int64_t>(seg, std::max<int64_t>(1, n / 256));
+            s.nseg = (int)std::max<int64_t>(1, std::min<int64_t>(seg, 1024));
+        }
+        return s;
+    }
     // rotor form: 32 rows per lane where the grid fills a 4-wave tile
     s.rows = (precision != GBD_MIXED) ? 4 : (s.form == 2 && pl.ny >= 128) ? 32 : 16;
     s.waves = 4;
@@ -224,8 +248,13 @@ EvalGeom make_geom(const PlaneGeom &pl, int64_t n, const Shape &s) {
     g.dy = pl.dy;
     g.a0 = -0.5 * (pl.nx - 1) * pl.dx;
     g.b0 = -0.5 * (pl.ny - 1) * pl.dy;
-    g.tiles_x = (pl.nx + 63) / 64;
-    g.tiles_y = (pl.ny + s.waves * s.rows - 1) / (s.waves * s.rows);
+    if (s.form == 3) {
+        g.tiles_x = (pl.nx + kSepTile * kSepWavesX - 1) / (kSepTile * kSepWavesX);
+        g.tiles_y = (pl.ny + kSepTile * kSepWavesY - 1) / (kSepTile * kSepWavesY);
+    } else {
+        g.tiles_x = (pl.nx + 63) / 64;
+        g.tiles_y = (pl.ny + s.waves * s.rows - 1) / (s.waves * s.rows);
+    }
     g.n = n;
     int64_t nseg = std::max<int64_t>(1, std::min<int64_t>(s.nseg, std::max<int64_t>(1, n)));
     g.seg_len = (n + nseg - 1) / nseg;
@@ -246,11 +275,11 @@ int plan_eval_impl(gbd_ctx_s *ctx, gbd_plan_s *plan, int precision, void *out, i
     if (!out) return fail(GBD_EINVAL, "field_out is NULL");
     if (out_bytes < M * elem)
         return fail(GBD_ERANGE, "field_out holds %lld bytes, %lld needed", (long long)out_bytes, (long long)(M * elem));
-    if (opts && (opts->variant < 0 || opts->variant > 3)) return fail(GBD_EINVAL, "variant must be 0, 1, 2 or 3");
+    if (opts && (opts->variant < 0 || opts->variant > 4)) return fail(GBD_EINVAL, "variant must be 0 ... 4");
     if (opts && opts->rows_per_lane && !valid_shape(opts->rows_per_lane, opts->waves ? opts->waves : 4, precision))
         return fail(GBD_EINVAL, "unsupported rows_per_lane %d / waves %d", opts->rows_per_lane, opts->waves);
-    Shape s = choose_shape(ctx, precision, plan->n, plan->pl, plan->steep, opts);
-    if (!valid_shape(s.rows, s.waves, precision))
+    Shape s = choose_shape(ctx, precision, plan->n, plan->pl, plan->flags, opts);
+    if (s.form != 3 && !valid_shape(s.rows, s.waves, precision))
         return fail(GBD_EINVAL, "unsupported rows_per_lane %d / waves %d", s.rows, s.waves);
     int rc = ensure_device(ctx);
     if (rc) return rc;
@@ -272,7 +301,13 @@ int plan_eval_impl(gbd_ctx_s *ctx, gbd_plan_s *plan, int precision, void *out, i
         }
     }
     const void *rec = precision == GBD_FP64 ? (const void *)plan->r64 : (const void *)plan->r32;
-    HIP_TRY(launch_eval(precision, s.rows, s.waves, s.form, g, rec, plan->scratch, out, ctx->stream), "eval kernel launch");
+    if (s.form == 3)
+        HIP_TRY(launch_eval_sep(g, plan->r32, static_cast<float4 *>(plan->scratch), static_cast<float2 *>(out),
+                                ctx->stream),
+                "eval kernel launch");
+    else
+        HIP_TRY(launch_eval(precision, s.rows, s.waves, s.form, g, rec, plan->scratch, out, ctx->stream),
+                "eval kernel launch");
     if (g.nseg > 1) HIP_TRY(launch_reduce(precision, g, plan->scratch, out, ctx->stream), "reduce kernel launch");
     return GBD_OK;
 }
@@ -283,7 +318,7 @@ int plan_setup_impl(gbd_ctx_s *ctx, gbd_plan_s *plan, gbd_beamlets_s *b, gbd_pla
     int rc = ensure_device(ctx);
     if (rc) return rc;
     plan->ready = false;
-    plan->steep = false;
+    plan->flags = 0;
     plan->n = b->dev.n;
     plan->pl = p->g;
     if (b->dev.n > 0) {
@@ -302,7 +337,7 @@ int plan_setup_impl(gbd_ctx_s *ctx, gbd_plan_s *plan, gbd_beamlets_s *b, gbd_pla
         if (st & FLAG_BRANCH)
             return fail(GBD_EBRANCH, "an eigenvalue of A + B Q1^-1 lies off the principal branch (inverting system)");
         if (st & FLAG_NONFINITE) return fail(GBD_EINVAL, "non-finite beamlet parameters after propagation");
-        plan->steep = (st & FLAG_STEEP) != 0;
+        plan->flags = st & (FLAG_STEEP | FLAG_CROSS);
     }
     plan->ready = true;
     return GBD_OK;
@@ -535,7 +570,7 @@ void gbd_plan_free(gbd_plan_t plan) { plan_destroy(plan); }
 
 int gbd_plan_shape(gbd_ctx_t ctx, gbd_plan_t plan, int precision, const gbd_eval_opts *opts, gbd_eval_opts *resolved) {
     if (!ctx || !plan || !resolved) return fail(GBD_EINVAL, "NULL argument");
-    Shape s = choose_shape(ctx, precision, plan->n, plan->pl, plan->steep, opts);
+    Shape s = choose_shape(ctx, precision, plan->n, plan->pl, plan->flags, opts);
     EvalGeom g = make_geom(plan->pl, plan->n, s);
     resolved->rows_per_lane = s.rows;
     resolved->waves = s.waves;
@@ -583,7 +618,7 @@ int gbd_autotune(gbd_ctx_t ctx, gbd_plan_t plan, int precision, int32_t reps, gb
     if (he == hipSuccess) he = hipEventCreate(&e1);
     TuneVal bestv{0, 0, 100, 1e300};
     static const int rows_c[] = {2, 4, 8, 16, 32}, waves_c[] = {1, 2, 4}, pct_c[] = {50, 100, 200, 400};
-    const int n_rows = precision == GBD_MIXED ? (plan->steep ? 4 : 5) : 3;
+    const int n_rows = precision == GBD_MIXED ? ((plan->flags & FLAG_STEEP) ? 4 : 5) : 3;
     for (int ri = 0; ri < n_rows && he == hipSuccess && rc == GBD_OK; ri++)
         for (int wi = 0; wi < 3 && he == hipSuccess && rc == GBD_OK; wi++)
             for (int pi = 0; pi < 4 && he == hipSuccess && rc == GBD_OK; pi++) {
@@ -618,7 +653,7 @@ int gbd_autotune(gbd_ctx_t ctx, gbd_plan_t plan, int precision, int32_t reps, gb
     if (he != hipSuccess) return hip_fail(he, "autotune timing");
     ctx->tuned[tune_key(0, precision, plan->n, M)] = bestv;
     if (best) {
-        const Shape s = choose_shape(ctx, precision, plan->n, plan->pl, plan->steep, nullptr);
+        const Shape s = choose_shape(ctx, precision, plan->n, plan->pl, plan->flags, nullptr);
         const EvalGeom g = make_geom(plan->pl, plan->n, s);
         *best = gbd_eval_opts{s.rows, s.waves, g.nseg, form_variant(precision, s.form)};
     }
@@ -718,7 +753,7 @@ int gbd_eval_batch(gbd_ctx_t ctx, int32_t n_inst, const gbd_beamlets_t *bs, cons
     }
     if (metrics_out && !airy) return fail(GBD_EINVAL, "metrics need the reference irradiance");
     if (airy && !metrics_out) return fail(GBD_EINVAL, "metrics_out is NULL");
-    if (opts && (opts->variant < 0 || opts->variant > 3)) return fail(GBD_EINVAL, "variant must be 0, 1, 2 or 3");
+    if (opts && (opts->variant < 0 || opts->variant > 4)) return fail(GBD_EINVAL, "variant must be 0 ... 4");
     int rows = 32, waves = 4;  // 32 rows: rotor form; 16 where the form resolves otherwise
     int64_t pairs = 0;
     for (int32_t i = 0; i < n_inst; i++) {
@@ -802,7 +837,7 @@ int gbd_eval_batch(gbd_ctx_t ctx, int32_t n_inst, const gbd_beamlets_t *bs, cons
     if (stat & FLAG_PARALLEL) return fail(GBD_EPARALLEL, "instance %d: a base ray is parallel to the plane", bad);
     if (stat & FLAG_BRANCH) return fail(GBD_EBRANCH, "instance %d: an eigenvalue left the principal branch", bad);
     if (stat & FLAG_NONFINITE) return fail(GBD_EINVAL, "instance %d: non-finite beamlet parameters", bad);
-    const int form = pick_form(GBD_MIXED, (stat & FLAG_STEEP) != 0, opts);
+    const int form = pick_form(GBD_MIXED, stat, opts, false);  // no separable batch kernel
     if (rows == 32 && form != 2) rows = 16;  // 32 rows is a rotor-form shape
 
     // evaluation tables; the work list takes instances largest first (LPT),

@@ -184,6 +184,7 @@ __device__ inline uint32_t setup_one(const BeamletsDev &b, const PlaneGeom &pl, 
         for (int i = 0; i < 6; i++) fin = fin && isfinite(p[i]) && (i == 0 || isfinite(l[i]));
         if (!fin) flag |= FLAG_NONFINITE;
         if (fabs(l[5]) * il2_dev() * pl.dy * pl.dy > kStepCurvature) flag |= FLAG_STEEP;
+        if (p[4] != 0.0 || l[4] != 0.0) flag |= FLAG_CROSS;
         o64.arho = arho;
         o64.brho = brho;
         o32.arho = arho;

@@ -63,6 +63,9 @@ enum : uint32_t {
     // not an error: the log2-amplitude curvature along a column exceeds
     // kStepCurvature per row^2, so the amplitude recurrence is not used
     FLAG_STEEP = 16u,
+    // not an error: the phasor has a cross term (p4 or l4 nonzero), so the
+    // plane's two axes do not separate
+    FLAG_CROSS = 32u,
 };
 
 // largest |d^2 log2(amplitude) / d row^2| / 2 for which the mixed kernel may
@@ -185,5 +188,11 @@ hipError_t launch_eval(int precision, int rows, int waves, int form, const EvalG
                        void *partial, void *out, hipStream_t s);
 
 hipError_t launch_reduce(int precision, const EvalGeom &g, const void *partial, void *out, hipStream_t s);
+
+// Separable (matrix) form on FP32 MFMA: workgroups of kSepWavesX x kSepWavesY
+// wavefronts, each wavefront a 64 x 64 pixel tile; partials as float4 (re, im, 0, 0).
+constexpr int kSepWavesX = 2, kSepWavesY = 2;
+constexpr int kSepTile = 64;
+hipError_t launch_eval_sep(const EvalGeom &g, const Rec32 *rec, float4 *partial, float2 *out, hipStream_t s);
 
 }  // namespace gbd

@@ -105,7 +105,7 @@ def test_full_sweep_matches_single_instances(ctx):
     for k in range(0, len(insts), 7):
         s, b = insts[k], bs[k]
         # the batch kernel's launch shape (one segment): the same field arithmetic
-        E = gbd.gbd_eval(ctx, b, ps[k], gbd.GBD_MIXED, opts=dict(rows_per_lane=32, waves=4, segments=1))
+        E = gbd.gbd_eval(ctx, b, ps[k], gbd.GBD_MIXED, opts=dict(rows_per_lane=32, waves=4, segments=1, variant=3))
         pl = s.plane
         if origin[0] is None:
             origin[0] = gbd.gbd_plane(ctx, pl.origin, pl.normal, pl.xhint, 1, 1, pl.dx, pl.dy)

@@ -78,14 +78,15 @@ def test_every_launch_shape_matches_oracle(ctx, precision):
 
 @pytest.mark.parametrize("name", ["airy32_64", "zern128_1024"])
 def test_rotor_variant_is_chosen_and_matches_direct(ctx, name):
-    """On well-sampled grids the automatic mixed form is the rotor one; it
-    and the stepped form agree with the direct form and with the oracle."""
+    """On well-sampled grids with cross terms the automatic mixed form is the
+    rotor one (the Airy scene has none and goes to the separable form); the
+    rotor and stepped forms agree with the direct form and with the oracle."""
     sc = scenes.config(name)
     b = gbd.beamlets_from_scene(ctx, sc)
     p = gbd.plane_from_scene(ctx, sc)
     plan = gbd.Plan(ctx, sc.n).setup(b, p)
-    assert plan.shape(gbd.GBD_MIXED)["variant"] == 3
-    E3 = plan.eval(gbd.GBD_MIXED).cpu().numpy()
+    assert plan.shape(gbd.GBD_MIXED)["variant"] == (4 if name.startswith("airy") else 3)
+    E3 = plan.eval(gbd.GBD_MIXED, opts=dict(variant=3)).cpu().numpy()
     E2 = plan.eval(gbd.GBD_MIXED, opts=dict(variant=2)).cpu().numpy()
     E1 = plan.eval(gbd.GBD_MIXED, opts=dict(variant=1)).cpu().numpy()
     print(name, "rotor vs direct", rel_l2(E3, E1), "stepped vs direct", rel_l2(E2, E1), flush=True)
@@ -97,22 +98,62 @@ def test_rotor_variant_is_chosen_and_matches_direct(ctx, name):
         check(E2, ref, gbd.GBD_MIXED, name + " stepped")
 
 
+def test_separable_form_is_chosen_and_matches_oracle(ctx):
+    """A rotationally symmetric system on a plane normal to the axis has no
+    cross terms: the automatic mixed form is the separable (MFMA) one; it
+    agrees with the oracle and with the rotor form."""
+    sc = scenes.config("airy32_64")
+    b = gbd.beamlets_from_scene(ctx, sc)
+    p = gbd.plane_from_scene(ctx, sc)
+    plan = gbd.Plan(ctx, sc.n).setup(b, p)
+    assert plan.shape(gbd.GBD_MIXED)["variant"] == 4
+    E4 = plan.eval(gbd.GBD_MIXED).cpu().numpy()
+    E3 = plan.eval(gbd.GBD_MIXED, opts=dict(variant=3)).cpu().numpy()
+    print("separable vs rotor", rel_l2(E4, E3), flush=True)
+    assert rel_l2(E4, E3) < 1e-5
+    check(E4, oracle.eval_field(sc), gbd.GBD_MIXED, "airy32_64 separable")
+
+
+@pytest.mark.parametrize("nx,ny,seg", [(70, 45, 1), (70, 45, 3), (129, 200, 0), (1, 1, 1), (65, 1, 2), (1, 70, 0)])
+def test_separable_form_ragged_defocused_off_axis(ctx, nx, ny, seg):
+    """Grids that leave every 16 x 16 block, wavefront and workgroup tile
+    partly empty, beamlet counts not a multiple of the MFMA's K = 4, a field
+    angle and a defocused plane (strong per-beamlet phase slopes)."""
+    sc = scenes.airy_scene(21, npix=nx, npix_y=ny, half_span_lamF=6.0, field_angle=(1e-3, -5e-4), z0=30e-6)
+    assert sc.n % 4 != 0
+    b = gbd.beamlets_from_scene(ctx, sc)
+    p = gbd.plane_from_scene(ctx, sc)
+    plan = gbd.Plan(ctx, sc.n).setup(b, p)
+    o = dict(segments=seg)
+    assert plan.shape(gbd.GBD_MIXED, opts=o)["variant"] == 4
+    check(plan.eval(gbd.GBD_MIXED, opts=o).cpu().numpy(), oracle.eval_field(sc), gbd.GBD_MIXED,
+          f"separable {nx}x{ny} seg {seg}")
+
+
+def test_cross_terms_rule_out_the_separable_form(ctx):
+    sc = scenes.zernike_scene(7, n_across=12, npix=40, half_span=30e-6)
+    plan = gbd.Plan(ctx, sc.n).setup(gbd.beamlets_from_scene(ctx, sc), gbd.plane_from_scene(ctx, sc))
+    assert plan.shape(gbd.GBD_MIXED)["variant"] == 3
+    assert plan.shape(gbd.GBD_MIXED, opts=dict(variant=4))["variant"] == 3
+
+
 def test_steep_grid_falls_back_to_direct(ctx):
     tail = scenes.airy_scene(1, npix=16, half_span_lamF=30.0)
     plan = gbd.Plan(ctx, 1).setup(gbd.beamlets_from_scene(ctx, tail), gbd.plane_from_scene(ctx, tail))
-    assert plan.shape(gbd.GBD_MIXED)["variant"] == 1
+    # no cross terms: the separable form, which needs no curvature bound
+    assert plan.shape(gbd.GBD_MIXED)["variant"] == 4
     assert plan.shape(gbd.GBD_MIXED, opts=dict(variant=2))["variant"] == 1
     assert plan.shape(gbd.GBD_MIXED, opts=dict(variant=3))["variant"] == 1
     # 32 rows per lane is a rotor-form shape; the direct form runs 16
-    assert plan.shape(gbd.GBD_MIXED, opts=dict(rows_per_lane=32))["rows_per_lane"] == 16
+    assert plan.shape(gbd.GBD_MIXED, opts=dict(rows_per_lane=32, variant=1))["rows_per_lane"] == 16
 
 
 @pytest.mark.parametrize("precision", BOTH)
 def test_bitwise_run_to_run(ctx, precision):
-    sc = scenes.zernike_scene(5, n_across=24, npix=96)
-    a = run(ctx, sc, precision)
-    b = run(ctx, sc, precision)
-    assert np.array_equal(a.view(np.uint8), b.view(np.uint8))
+    for sc in (scenes.zernike_scene(5, n_across=24, npix=96), scenes.airy_scene(24, npix=96)):
+        a = run(ctx, sc, precision)
+        b = run(ctx, sc, precision)
+        assert np.array_equal(a.view(np.uint8), b.view(np.uint8))
 
 
 def sample_pixels(nx, ny, count, seed):
@@ -155,7 +196,7 @@ def test_plan_reuse_and_shape(ctx):
     plan = gbd.gbd_plan_create(ctx, sc.n)
     plan.setup(b, p)
     shp = plan.shape(gbd.GBD_MIXED)
-    assert shp["rows_per_lane"] in (1, 2, 4, 8, 16) and shp["segments"] >= 1
+    assert shp["rows_per_lane"] in (1, 2, 4, 8, 16, 32, 64) and shp["segments"] >= 1
     E1 = plan.eval(gbd.GBD_FP64)
     E2 = plan.eval(gbd.GBD_FP64, opts=dict(rows_per_lane=2, waves=1, segments=5))
     torch.cuda.synchronize()
@@ -240,7 +281,7 @@ def test_errors_are_reported_before_any_write(ctx):
     # output buffer too small; unknown mixed form
     good = gbd.beamlets_from_scene(ctx, sc)
     with pytest.raises(gbd.GbdError) as e:
-        gbd.gbd_eval(ctx, good, p, gbd.GBD_MIXED, out=sentinel, opts=dict(variant=4))
+        gbd.gbd_eval(ctx, good, p, gbd.GBD_MIXED, out=sentinel, opts=dict(variant=5))
     assert e.value.code == -1
     small = torch.empty((3, 4), dtype=torch.complex128, device="cuda")
     with pytest.raises(gbd.GbdError) as e:
