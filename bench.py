@@ -51,7 +51,8 @@ RATE = {"fp64": 64, "fp32": 128, "trans": 32}
 # HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE (x2.0)
 # and WRITE_SIZE (x1.0) runs, scale factors from a plain 256 MiB copy; valid
 # only for the kernel and launch they were taken on (else traffic is null).
-TRAFFIC = {("airy256_512", 32, 4, 48, 3): (6095.5 * 2.0 + 196608.0 * 1.0) * 1024}
+TRAFFIC = {("airy256_512", 32, 4, 48, 3): (6095.5 * 2.0 + 196608.0 * 1.0) * 1024,
+           ("airy256_512", 64, 4, 48, 4): (5331.8 * 2.0 + 196608.0 * 1.0) * 1024}
 
 
 def instruction_mix(rows, variant):
@@ -76,9 +77,11 @@ def roofline_peak(rows, variant):
 # FP32 MFMA multiply-adds (8 flops) per beamlet-pixel pair; FP32 MFMA peak.
 MFMA_FP32_TFLOPS = 157.3
 SEP_FLOPS_PER_PAIR = 8.0
-# factor evaluation per lane per 4 beamlets and 64 x 64 pixels, counted in the
-# compiled loop: 40 FP64, 109 FP32, 24 transcendental, 64 MFMA 16x16x4
-SEP_VALU_PER_PAIR = {"fp64": 40 / 256, "fp32": 109 / 256, "trans": 24 / 256, "mfma_16x16x4": 64 / 16384}
+# per lane and step (4 beamlets x 64 x 64 pixels of one wavefront), counted in
+# the compiled loop: 20 FP64, 23 FP32, 12 transcendental and 32 other VALU
+# instructions (the factors shared by 4 wavefronts), 64 MFMA 16x16x4
+SEP_VALU_PER_PAIR = {"fp64": 20 / 256, "fp32": 23 / 256, "trans": 12 / 256, "other": 32 / 256,
+                     "mfma_16x16x4": 64 / 16384}
 
 
 def roofline(shape, N, M, kernel_ms):

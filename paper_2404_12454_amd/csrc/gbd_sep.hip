@@ -16,10 +16,15 @@
 //
 // Tiling: a wavefront owns a 64 x 64 pixel tile as 4 x 4 blocks of 16 x 16
 // and walks its segment of beamlets four at a time (the MFMA's K = 4): lane l
-// forms U and V of beamlet j0 + l / 16 at the 4 + 4 coordinates l % 16 + 16 b
-// it feeds the MFMA, so the factors cost 8 phasors per lane per 4 beamlets
-// against 64 MFMAs (16 blocks x {Re, Im} x 2 real products).  Accumulators
-// stay in FP32 over the segment; segments are summed in FP64 by the reduction.
+// feeds the MFMA U and V of beamlet j0 + l / 16 at the coordinates l % 16 + 16 b
+// of its 4 + 4 blocks, 64 MFMAs per step (16 blocks x {Re, Im} x 2 real
+// products).  Four wavefronts (2 x 2 tiles) share the factors through LDS, so
+// each lane forms 4 phasors per step instead of 8: on gfx950 VALU and MFMA
+// issue from one SIMD do not overlap, so every VALU instruction per MFMA is
+// time lost from the matrix pipe.  The record fields of the next step are
+// loaded while the current one computes.  Accumulators stay in FP32 over the
+// segment; segments are summed in FP64 by the reduction.  The host sizes
+// segments so that every one is non-empty (jb < je <= N).
 #include "gbd_device.h"
 
 namespace gbd {
@@ -43,6 +48,32 @@ __device__ inline void factor(double d, float df, double c0, double c1, double c
     im = m * __builtin_amdgcn_sinf(ph);
 }
 
+// The record fields one lane's factors need; a beamlet index past the
+// segment end gets the amplitude exponent -inf (factor 0).
+struct Fields {
+    double arho, brho, p0, p1, p2, p3, p5;
+    float m0, m1, m2, m3, m5, arf, brf;
+};
+__device__ inline Fields load_fields(const Rec32 *__restrict__ rec, int64_t j, int64_t jb, int64_t je) {
+    const Rec32 *rp = rec + (j < je ? j : jb);
+    Fields f;
+    f.arho = rp->arho;
+    f.brho = rp->brho;
+    f.p0 = rp->p[0];
+    f.p1 = rp->p[1];
+    f.p2 = rp->p[2];
+    f.p3 = rp->p[3];
+    f.p5 = rp->p[5];
+    f.m0 = rp->m[0] + (j < je ? 0.0f : -INFINITY);
+    f.m1 = rp->m[1];
+    f.m2 = rp->m[2];
+    f.m3 = rp->m[3];
+    f.m5 = rp->m[5];
+    f.arf = rp->arho_f;
+    f.brf = rp->brho_f;
+    return f;
+}
+
 template <int WX, int WY>
 __global__ void __launch_bounds__(64 * WX * WY) eval_sep_kernel(EvalGeom g, const Rec32 *__restrict__ rec,
                                                                  float4 *__restrict__ partial,
@@ -59,20 +90,36 @@ __global__ void __launch_bounds__(64 * WX * WY) eval_sep_kernel(EvalGeom g, cons
     const int x0 = (tx * WX + wx) * 16 * NB, y0 = (ty * WY + wy) * 16 * NB;
     const int li = lane & 15, lk = lane >> 4;
 
-    // plane coordinates this lane evaluates its factors at; a coordinate off
-    // the grid gets the amplitude exponent -inf (factor 0), so no branches
-    double ax[NB], by[NB];
-    float axf[NB], byf[NB], mx[NB], my[NB];
+    // Factor sharing: U over this workgroup's x range wx is needed by the two
+    // wavefronts (wx, 0), (wx, 1), V over y range wy by (0, wy), (1, wy).
+    // Wavefront (wx, wy) forms U blocks 2 wy, 2 wy + 1 of range wx and V blocks
+    // 2 wx, 2 wx + 1 of range wy and publishes them in LDS (double-buffered,
+    // one barrier per step); each lane's value sits where the same lane of the
+    // partner wavefront reads it (same beamlet and in-block position).
+    static_assert(WX == 2 && WY == 2, "factor sharing assumes 2 x 2 wavefronts");
+    __shared__ float2 lu[2][2][NB][64], lv[2][2][NB][64];  // [buffer][range][block][lane]
+    double ax[2], by[2];
+    float axf[2], byf[2], mx[2], my[2];
 #pragma unroll
-    for (int b = 0; b < NB; b++) {
-        const int ix = x0 + 16 * b + li, iy = y0 + 16 * b + li;
-        mx[b] = ix < g.nx ? 0.0f : -INFINITY;
-        my[b] = iy < g.ny ? 0.0f : -INFINITY;
-        ax[b] = g.a0 + ix * g.dx;
-        by[b] = g.b0 + iy * g.dy;
-        axf[b] = (float)ax[b];
-        byf[b] = (float)by[b];
+    for (int h = 0; h < 2; h++) {
+        const int ix = x0 + 16 * (2 * wy + h) + li, iy = y0 + 16 * (2 * wx + h) + li;
+        mx[h] = ix < g.nx ? 0.0f : -INFINITY;
+        my[h] = iy < g.ny ? 0.0f : -INFINITY;
+        ax[h] = g.a0 + ix * g.dx;
+        by[h] = g.b0 + iy * g.dy;
+        axf[h] = (float)ax[h];
+        byf[h] = (float)by[h];
     }
+    auto publish = [&](const Fields &f, int buf) {
+#pragma unroll
+        for (int h = 0; h < 2; h++) {
+            float ur, ui, vr, vi;
+            factor(ax[h] - f.arho, axf[h] - f.arf, f.p0, f.p1, f.p3, f.m0 + mx[h], f.m1, f.m3, ur, ui);
+            factor(by[h] - f.brho, byf[h] - f.brf, 0.0, f.p2, f.p5, my[h], f.m2, f.m5, vr, vi);
+            lu[buf][wx][2 * wy + h][lane] = make_float2(ur, ui);
+            lv[buf][wy][2 * wx + h][lane] = make_float2(vr, vi);
+        }
+    };
 
     // accR/accI[p][q]: rows of the product are y (A operand = V), columns x (B = U)
     f4 accR[NB][NB], accI[NB][NB];
@@ -83,20 +130,23 @@ __global__ void __launch_bounds__(64 * WX * WY) eval_sep_kernel(EvalGeom g, cons
 
     const int64_t jb = (int64_t)seg * g.seg_len;
     const int64_t je = min(g.n, jb + g.seg_len);
+    publish(load_fields(rec, jb + lk, jb, je), 0);
+    Fields nxt = load_fields(rec, jb + 4 + lk, jb, je);
+    __syncthreads();
+    int buf = 0;
     for (int64_t j0 = jb; j0 < je; j0 += 4) {
-        const int64_t j = j0 + lk;
-        const Rec32 *rp = rec + (j < je ? j : jb);
-        const float dead = j < je ? 0.0f : -INFINITY;  // past the segment end: factor 0
-        const double arho = rp->arho, brho = rp->brho;
-        const double p0 = rp->p[0], p1 = rp->p[1], p2 = rp->p[2], p3 = rp->p[3], p5 = rp->p[5];
-        const float m0 = rp->m[0] + dead, m1 = rp->m[1], m2 = rp->m[2], m3 = rp->m[3], m5 = rp->m[5];
-        const float arf = rp->arho_f, brf = rp->brho_f;
+        const Fields f = nxt;
+        nxt = load_fields(rec, j0 + 8 + lk, jb, je);
+        if (j0 + 4 < je) publish(f, buf ^ 1);
         float ur[NB], ui[NB], vr[NB], vi[NB], vn[NB];
 #pragma unroll
         for (int b = 0; b < NB; b++) {
-            factor(ax[b] - arho, axf[b] - arf, p0, p1, p3, m0 + mx[b], m1, m3, ur[b], ui[b]);
-            factor(by[b] - brho, byf[b] - brf, 0.0, p2, p5, my[b], m2, m5, vr[b], vi[b]);
-            vn[b] = -vi[b];
+            const float2 u = lu[buf][wx][b][lane], v = lv[buf][wy][b][lane];
+            ur[b] = u.x;
+            ui[b] = u.y;
+            vr[b] = v.x;
+            vi[b] = v.y;
+            vn[b] = -v.y;
         }
         // Re += Vr Ur - Vi Ui ; Im += Vr Ui + Vi Ur
 #pragma unroll
@@ -113,6 +163,8 @@ __global__ void __launch_bounds__(64 * WX * WY) eval_sep_kernel(EvalGeom g, cons
                 accR[p][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(vn[p], ui[q], accR[p][q], 0, 0, 0);
                 accI[p][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(vi[p], ur[q], accI[p][q], 0, 0, 0);
             }
+        __syncthreads();
+        buf ^= 1;
     }
 
     // D[row][col] of a 16 x 16 block: lane l holds rows 4 (l / 16) + e, column l % 16
