@@ -7,7 +7,9 @@ only common module is the seeded input generator, which holds no propagation
 arithmetic.
 
 ``gbd_oracle.c`` is a plain, slow, direct FP64 implementation (libm exp/sin/
-cos, no fast-math, OpenMP over pixels).  ``metrics`` and ``mlp`` hold the FP64
+cos, no fast-math, OpenMP over pixels); ``raytrace.c`` the plain FP64
+sequential real-ray trace through conic mirrors that gives traced base rays
+and differential ABCD matrices.  ``metrics`` and ``mlp`` hold the FP64
 figures of merit and the surrogate's reference network in numpy.
 """
 from __future__ import annotations
@@ -21,6 +23,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "gbd_oracle.c")
+_SRCS = [_SRC, os.path.join(_HERE, "raytrace.c")]
 _LIB = os.path.join(_HERE, "libgbd_oracle.so")
 _lib = None
 
@@ -35,10 +38,10 @@ class OracleError(RuntimeError):
 
 def build(force: bool = False) -> str:
     """Compile the C oracle with gcc -O2 -fopenmp (no fast-math)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    if force or not os.path.exists(_LIB) or any(os.path.getmtime(_LIB) < os.path.getmtime(f) for f in _SRCS):
         tmp = _LIB + f".tmp{os.getpid()}"
         subprocess.check_call(["gcc", "-O2", "-std=c99", "-D_GNU_SOURCE", "-fopenmp", "-fPIC", "-shared",
-                               "-Wall", "-Wno-unknown-pragmas", _SRC, "-o", tmp, "-lm"])
+                               "-Wall", "-Wno-unknown-pragmas", *_SRCS, "-o", tmp, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -53,6 +56,14 @@ def _load():
         lib.oracle_eval.argtypes = [ctypes.c_int64, ctypes.c_double, ctypes.c_double, P, P, P, ctypes.c_int64,
                                     P, P, P, ctypes.c_int, P, P, P, ctypes.c_int32, ctypes.c_int32,
                                     ctypes.c_double, ctypes.c_double, ctypes.c_int64, P, P, ctypes.c_int, P, P, P]
+        lib.oracle_eval_base.restype = ctypes.c_int
+        lib.oracle_eval_base.argtypes = [ctypes.c_int64, ctypes.c_double, ctypes.c_double, P, P, P, ctypes.c_int64,
+                                         P, P, P, ctypes.c_int, P, ctypes.c_double, P, P, P, ctypes.c_int32,
+                                         ctypes.c_int32, ctypes.c_double, ctypes.c_double, ctypes.c_int64, P, P,
+                                         ctypes.c_int, P, P, P]
+        lib.oracle_trace.restype = ctypes.c_int
+        lib.oracle_trace.argtypes = [ctypes.c_int32, P, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                     ctypes.c_int64, P, P, ctypes.c_double, ctypes.c_double, P, P, P]
         lib.oracle_beamlet.restype = ctypes.c_int
         lib.oracle_beamlet.argtypes = [ctypes.c_double, P, P, ctypes.c_double, ctypes.c_double, P,
                                        ctypes.c_double, P]
@@ -98,10 +109,12 @@ def eval_field(scene, model: int = 0, pixels: Optional[tuple] = None, extra_poin
     oe = np.zeros(2) if ep is not None else None
     if threads is not None:
         lib.oracle_set_threads(int(threads))
-    rc = lib.oracle_eval(scene.n, scene.lam, scene.l0, _ptr(r1), _ptr(th1), _ptr(w0), w0.size, _ptr(amp),
-                         _ptr(path), _ptr(abcd), shared, _ptr(_f64(pl.origin)), _ptr(_f64(pl.normal)),
-                         _ptr(_f64(pl.xhint)), pl.nx, pl.ny, pl.dx, pl.dy, m, _ptr(ix), _ptr(iy), model,
-                         _ptr(out), _ptr(ep), _ptr(oe))
+    base = _f64(getattr(scene, "base", None))
+    tol = getattr(scene, "sympl_tol", None) or 1e-10
+    rc = lib.oracle_eval_base(scene.n, scene.lam, scene.l0, _ptr(r1), _ptr(th1), _ptr(w0), w0.size, _ptr(amp),
+                              _ptr(path), _ptr(abcd), shared, _ptr(base), float(tol), _ptr(_f64(pl.origin)),
+                              _ptr(_f64(pl.normal)), _ptr(_f64(pl.xhint)), pl.nx, pl.ny, pl.dx, pl.dy, m,
+                              _ptr(ix), _ptr(iy), model, _ptr(out), _ptr(ep), _ptr(oe))
     if rc != 0:
         raise OracleError(rc)
     E = out.view(np.complex128)
@@ -132,3 +145,27 @@ def set_threads(n: int = 0) -> int:
 
 def symplectic_ok(abcd) -> bool:
     return bool(_load().oracle_symplectic_ok(_ptr(_f64(np.asarray(abcd).reshape(16)))))
+
+
+TRACE_FLAGS = {1: "vignetted", 2: "missed", 4: "backward"}
+
+
+def trace(mirrors, z_in: float, z_out: float, l0: float, r1, th1=None, dr: float = 1e-5, dth: float = 1e-7):
+    """Real-ray trace through conic mirrors (rows (z_vertex, R, k, r_min,
+    r_max)): returns base [n,5] = (x2, y2, l2, m2, optical path - l0) on the
+    plane z_out, the central-difference differential matrices abcd [n,16]
+    (parabasal offsets dr in position, dth in direction cosine) and the
+    per-ray flags [n] (TRACE_FLAGS bits)."""
+    lib = _load()
+    mir = _f64(np.asarray(mirrors, np.float64).reshape(-1, 5))
+    r1 = _f64(np.asarray(r1).reshape(-1, 2))
+    n = r1.shape[0]
+    th = None if th1 is None else _f64(np.asarray(th1).reshape(-1, 2))
+    base = np.empty((n, 5))
+    abcd = np.empty((n, 16))
+    flags = np.empty(n, np.int32)
+    rc = lib.oracle_trace(mir.shape[0], _ptr(mir), float(z_in), float(z_out), float(l0), n, _ptr(r1), _ptr(th),
+                          float(dr), float(dth), _ptr(base), _ptr(abcd), _ptr(flags))
+    if rc != 0:
+        raise OracleError(rc)
+    return base, abcd, flags

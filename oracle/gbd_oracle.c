@@ -18,6 +18,9 @@
  *  1. Q1^-1 = -i lambda / (pi w0^2) I                    (complex-q equation)
  *  2. base ray  r2M = A r1M + B th1M,  th2M = C r1M + D th1M
  *                                                      (Appendix A, ab/cd laws)
+ *     or, for ray-traced inputs (Sec. 2.2: base and parabasal rays give the
+ *     differential ABCD), the traced base ray at the output plane, whose
+ *     optical path beyond l0 replaces the eikonal term of step 5
  *  3. the base ray (r2M + z th2M, z) meets the detector plane at plane
  *     coordinates (a_rho, b_rho) and axial offset z_rho; the system is
  *     extended by free space z_rho: A' = A + z C, B' = B + z D
@@ -97,8 +100,9 @@ static int branch_ok(cplx mu) {
     return 1;
 }
 
-/* Symplectic relations of the ABCD blocks (Sec. 2.1, symplectic equations). */
-static int symplectic_ok(const double *M) {
+/* Symplectic relations of the ABCD blocks (Sec. 2.1, symplectic equations),
+ * to relative tolerance tol. */
+static int symplectic_ok(const double *M, double tol) {
     double A[2][2], B[2][2], C[2][2], D[2][2];
     for (int i = 0; i < 2; i++)
         for (int j = 0; j < 2; j++) {
@@ -140,7 +144,7 @@ static int symplectic_ok(const double *M) {
             e = fabs(x5 - (i == j ? 1.0 : 0.0)) / (s5 + 1.0);
             if (e > worst) worst = e;
         }
-    return worst <= 1e-10;
+    return worst <= tol;
 }
 
 /* ---- detector plane ---- */
@@ -183,6 +187,8 @@ typedef struct {
     double r1[2], th1[2], w0, W;
     cplx a;
     const double *M;
+    const double *base; /* NULL, or a traced base ray at the ABCD output plane:
+                           (x, y, l, m, optical path - l0) */
 } or_in;
 
 static int propagate(const or_in *b, double z, or_prop *out) {
@@ -194,11 +200,16 @@ static int propagate(const or_in *b, double z, or_prop *out) {
             C[i][j] = b->M[4 * (i + 2) + j];
             D[i][j] = b->M[4 * (i + 2) + j + 2];
         }
-    /* base ray at the ABCD output plane */
+    /* base ray at the ABCD output plane: the ab/cd laws, or a traced ray */
     double r2M[2], th2M[2];
     for (int i = 0; i < 2; i++) {
-        r2M[i] = A[i][0] * b->r1[0] + A[i][1] * b->r1[1] + B[i][0] * b->th1[0] + B[i][1] * b->th1[1];
-        th2M[i] = C[i][0] * b->r1[0] + C[i][1] * b->r1[1] + D[i][0] * b->th1[0] + D[i][1] * b->th1[1];
+        if (b->base) {
+            r2M[i] = b->base[i];
+            th2M[i] = b->base[2 + i];
+        } else {
+            r2M[i] = A[i][0] * b->r1[0] + A[i][1] * b->r1[1] + B[i][0] * b->th1[0] + B[i][1] * b->th1[1];
+            th2M[i] = C[i][0] * b->r1[0] + C[i][1] * b->r1[1] + D[i][0] * b->th1[0] + D[i][1] * b->th1[1];
+        }
     }
     /* free-space extension by z */
     double Ap[2][2], Bp[2][2];
@@ -227,7 +238,13 @@ static int propagate(const or_in *b, double z, or_prop *out) {
         out->r2[i] = r2M[i] + z * th2M[i];
         out->th2[i] = th2M[i];
     }
-    double S = 0.5 * (th2M[0] * out->r2[0] + th2M[1] * out->r2[1] - b->th1[0] * b->r1[0] - b->th1[1] * b->r1[1]);
+    /* eikonal along the base ray beyond l0: Euler's relation for the point
+     * eikonal, or the traced optical path; then the free-space extension */
+    double S;
+    if (b->base)
+        S = b->base[4] + 0.5 * z * (th2M[0] * th2M[0] + th2M[1] * th2M[1]);
+    else
+        S = 0.5 * (th2M[0] * out->r2[0] + th2M[1] * out->r2[1] - b->th1[0] * b->r1[0] - b->th1[1] * b->r1[1]);
     out->tau = (z + b->W + S) / b->lam;
     return OR_OK;
 }
@@ -311,7 +328,7 @@ static int field_point_exact(const or_in *b, const double X[3], cplx *E) {
 
 static or_in load_in(int64_t j, double lam, double l0, const double *r1, const double *th1,
                      const double *w0, int64_t nw0, const double *amp, const double *path,
-                     const double *abcd, int shared) {
+                     const double *abcd, int shared, const double *base) {
     or_in b;
     b.lam = lam;
     b.l0 = l0;
@@ -323,12 +340,13 @@ static or_in load_in(int64_t j, double lam, double l0, const double *r1, const d
     b.W = path ? path[j] : 0.0;
     b.a = amp ? (amp[2 * j] + I * amp[2 * j + 1]) : 1.0;
     b.M = shared ? abcd : abcd + 16 * j;
+    b.base = base ? base + 5 * j : NULL;
     return b;
 }
 
 static int valid_inputs(int64_t n, double lam, double l0, const double *r1, const double *th1,
                         const double *w0, int64_t nw0, const double *amp, const double *path,
-                        const double *abcd, int shared) {
+                        const double *abcd, int shared, const double *base, double tol) {
     if (n < 0 || !(lam > 0.0) || !isfinite(lam) || !isfinite(l0)) return OR_EINVAL;
     if (n == 0) return OR_OK;
     if (!r1 || !w0 || !abcd || !(nw0 == 1 || nw0 == n)) return OR_EINVAL;
@@ -337,6 +355,9 @@ static int valid_inputs(int64_t n, double lam, double l0, const double *r1, cons
         if (th1 && (!isfinite(th1[2 * j]) || !isfinite(th1[2 * j + 1]))) return OR_EINVAL;
         if (amp && (!isfinite(amp[2 * j]) || !isfinite(amp[2 * j + 1]))) return OR_EINVAL;
         if (path && !isfinite(path[j])) return OR_EINVAL;
+        if (base)
+            for (int e = 0; e < 5; e++)
+                if (!isfinite(base[5 * j + e])) return OR_EINVAL;
     }
     for (int64_t j = 0; j < nw0; j++)
         if (!(w0[j] > 0.0) || !isfinite(w0[j])) return OR_EINVAL;
@@ -344,7 +365,7 @@ static int valid_inputs(int64_t n, double lam, double l0, const double *r1, cons
     for (int64_t j = 0; j < nm; j++) {
         for (int e = 0; e < 16; e++)
             if (!isfinite(abcd[16 * j + e])) return OR_EINVAL;
-        if (!symplectic_ok(abcd + 16 * j)) return OR_ENOTSYMPLECTIC;
+        if (!symplectic_ok(abcd + 16 * j, tol)) return OR_ENOTSYMPLECTIC;
     }
     return OR_OK;
 }
@@ -359,14 +380,15 @@ static int valid_inputs(int64_t n, double lam, double l0, const double *r1, cons
  *   into out_extra (used for the on-axis normalisation of the Airy metric).
  * Returns 0 or a negative OR_E* code; on error out is left untouched.
  */
-int oracle_eval(int64_t n, double lam, double l0, const double *r1, const double *th1,
-                const double *w0, int64_t nw0, const double *amp, const double *path,
-                const double *abcd, int shared_abcd,
-                const double *origin, const double *normal, const double *xhint,
-                int32_t nx, int32_t ny, double dx, double dy,
-                int64_t npix, const int32_t *pix_ix, const int32_t *pix_iy,
-                int model, double *out, const double *extra_point, double *out_extra) {
-    int rc = valid_inputs(n, lam, l0, r1, th1, w0, nw0, amp, path, abcd, shared_abcd);
+int oracle_eval_base(int64_t n, double lam, double l0, const double *r1, const double *th1,
+                     const double *w0, int64_t nw0, const double *amp, const double *path,
+                     const double *abcd, int shared_abcd, const double *base, double sympl_tol,
+                     const double *origin, const double *normal, const double *xhint,
+                     int32_t nx, int32_t ny, double dx, double dy,
+                     int64_t npix, const int32_t *pix_ix, const int32_t *pix_iy,
+                     int model, double *out, const double *extra_point, double *out_extra) {
+    if (!(sympl_tol > 0.0)) return OR_EINVAL;
+    int rc = valid_inputs(n, lam, l0, r1, th1, w0, nw0, amp, path, abcd, shared_abcd, base, sympl_tol);
     if (rc) return rc;
     or_plane pl;
     rc = make_plane(origin, normal, xhint, nx, ny, dx, dy, &pl);
@@ -382,7 +404,7 @@ int oracle_eval(int64_t n, double lam, double l0, const double *r1, const double
     or_beam_on_plane *bp = (or_beam_on_plane *)malloc(sizeof(or_beam_on_plane) * (size_t)(n > 0 ? n : 1));
     if (!bp) return OR_EINVAL;
     for (int64_t j = 0; j < n; j++) {
-        or_in b = load_in(j, lam, l0, r1, th1, w0, nw0, amp, path, abcd, shared_abcd);
+        or_in b = load_in(j, lam, l0, r1, th1, w0, nw0, amp, path, abcd, shared_abcd, base);
         rc = beam_on_plane(&b, &pl, &bp[j]);
         if (rc) { free(bp); return rc; }
     }
@@ -402,7 +424,7 @@ int oracle_eval(int64_t n, double lam, double l0, const double *r1, const double
             double X[3];
             for (int i = 0; i < 3; i++) X[i] = pl.O[i] + a * pl.e1[i] + bb * pl.e2[i];
             for (int64_t j = 0; j < n; j++) {
-                or_in b = load_in(j, lam, l0, r1, th1, w0, nw0, amp, path, abcd, shared_abcd);
+                or_in b = load_in(j, lam, l0, r1, th1, w0, nw0, amp, path, abcd, shared_abcd, base);
                 cplx Ej;
                 if (field_point_exact(&b, X, &Ej)) {
 #pragma omp atomic write
@@ -427,6 +449,19 @@ int oracle_eval(int64_t n, double lam, double l0, const double *r1, const double
     return err ? OR_EBRANCH : OR_OK;
 }
 
+/* oracle_eval: the same without traced base rays, symplectic tolerance 1e-10 */
+int oracle_eval(int64_t n, double lam, double l0, const double *r1, const double *th1,
+                const double *w0, int64_t nw0, const double *amp, const double *path,
+                const double *abcd, int shared_abcd,
+                const double *origin, const double *normal, const double *xhint,
+                int32_t nx, int32_t ny, double dx, double dy,
+                int64_t npix, const int32_t *pix_ix, const int32_t *pix_iy,
+                int model, double *out, const double *extra_point, double *out_extra) {
+    return oracle_eval_base(n, lam, l0, r1, th1, w0, nw0, amp, path, abcd, shared_abcd, NULL, 1e-10, origin,
+                            normal, xhint, nx, ny, dx, dy, npix, pix_ix, pix_iy, model, out, extra_point,
+                            out_extra);
+}
+
 /*
  * oracle_beamlet: one beamlet propagated by its ABCD extended with free space
  * z (no plane).  out[0..7] = Q^-1 (row-major, re/im interleaved), out[8..9] =
@@ -435,9 +470,9 @@ int oracle_eval(int64_t n, double lam, double l0, const double *r1, const double
  */
 int oracle_beamlet(double lam, const double *r1, const double *th1, double w0, double W,
                    const double *abcd, double z, double *out) {
-    int rc = valid_inputs(1, lam, 0.0, r1, th1, &w0, 1, NULL, &W, abcd, 1);
+    int rc = valid_inputs(1, lam, 0.0, r1, th1, &w0, 1, NULL, &W, abcd, 1, NULL, 1e-10);
     if (rc) return rc;
-    or_in b = load_in(0, lam, 0.0, r1, th1, &w0, 1, NULL, &W, abcd, 1);
+    or_in b = load_in(0, lam, 0.0, r1, th1, &w0, 1, NULL, &W, abcd, 1, NULL);
     or_prop P;
     rc = propagate(&b, z, &P);
     if (rc) return rc;
@@ -471,4 +506,4 @@ int oracle_set_threads(int n) {
 }
 
 /* symplectic check exposed for the input-validation tests */
-int oracle_symplectic_ok(const double *abcd) { return symplectic_ok(abcd); }
+int oracle_symplectic_ok(const double *abcd) { return symplectic_ok(abcd, 1e-10); }

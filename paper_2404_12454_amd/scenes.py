@@ -34,7 +34,7 @@ import numpy as np
 __all__ = [
     "Scene", "Plane", "pupil_grid", "lens_then_distance", "thin_plate",
     "airy_scene", "zernike_scene", "config", "sweep_grid", "surrogate_draws",
-    "NOLL", "zernike_poly",
+    "NOLL", "zernike_poly", "hst_rc", "annulus_grid", "rc_scene",
 ]
 
 
@@ -61,6 +61,7 @@ class Scene:
     """Beamlet decomposition handed to both the library and the oracle.
 
     r1   [n,2]  beamlet centres in the input plane (m)
+    (abcd and base may come from a ray tracer: rc_scene leaves them None)
     th1  [n,2]  beamlet base-ray slopes in the input plane (rad, paraxial)
     w0   [n]    1/e field waist radius in the input plane (m)
     amp  [n,2]  complex amplitude (re, im)
@@ -74,9 +75,14 @@ class Scene:
     w0: np.ndarray
     amp: np.ndarray
     path: np.ndarray
-    abcd: np.ndarray
+    abcd: Optional[np.ndarray]
     plane: Plane
     meta: dict = field(default_factory=dict)
+    # traced inputs (filled by a ray tracer, not by this module):
+    # base [n,5] = output-plane base ray (x, y, l, m, optical path - l0), and the
+    # symplectic tolerance the differential (finite-difference) matrices get
+    base: Optional[np.ndarray] = None
+    sympl_tol: Optional[float] = None
 
     @property
     def n(self) -> int:
@@ -273,3 +279,55 @@ def surrogate_draws(n: int = 20000, seed: int = 12454):
     fn = rng.uniform(4.0, 20.0, n)
     lam = np.exp(rng.uniform(math.log(0.4e-6), math.log(2.0e-6), n))
     return np.stack([of, q, na, fn, lam], axis=1)
+
+
+# --- Appendix B telescope (ray-traced inputs) --------------------------------
+
+def hst_rc(k1: float = -1.00230, k2: float = -1.49686, z_in: float = -5.0) -> dict:
+    """The Ritchey-Chretien telescope of Appendix B in the global frame (z the
+    axis, light from -z; radii signed by where the centre of curvature lies:
+    R < 0 means it is on the -z side of the vertex).  The table gives the
+    primary as concave (R 11.04 m) and the secondary as convex (R 1.358 m)
+    towards the light that reaches them; the primary faces -z, the secondary
+    +z, so both centres of curvature lie on the -z side: R1 = -11.04,
+    R2 = -1.358.  Secondary 4.90607 m in front of the primary, image 6.40620 m
+    behind the secondary; clear diameters 2.4 m and 0.28112 m.  The
+    decomposition plane z_in sits in front of the secondary; mirrors are rows
+    (z_vertex, R, k, r_min, r_max)."""
+    z2 = -4.90607
+    z_img = z2 + 6.40620
+    D, d2 = 2.4, 0.28112
+    mirrors = np.array([[0.0, -11.0400, k1, 0.0, D / 2.0],
+                        [z2, -1.35800, k2, 0.0, d2 / 2.0]], np.float64)
+    return dict(mirrors=mirrors, z_in=float(z_in), z_out=float(z_img), D=D, r_obs=d2 / 2.0,
+                l0=float((0.0 - z_in) + (0.0 - z2) + (z_img - z2)))
+
+
+def annulus_grid(n_across: int, D: float, r_in: float) -> tuple[np.ndarray, float]:
+    """The cell-centred square grid of pupil_grid, keeping r_in <= r <= D/2."""
+    r1, s = pupil_grid(n_across, D)
+    rr = np.hypot(r1[:, 0], r1[:, 1])
+    return np.ascontiguousarray(r1[rr >= r_in]), s
+
+
+def rc_scene(n_across: int = 128, *, lam: float = 1e-6, OF: float = 1.7, field_angle=(0.0, 0.0),
+             npix: int = 512, half_span_lamF: float = 16.0, system: Optional[dict] = None) -> Scene:
+    """Beamlets on the annular entrance pupil of the Appendix B telescope
+    (outer diameter 2.4 m, obscured by the secondary's 0.28112 m), unit
+    amplitudes, w0 = OF s / 2, base-ray direction cosines = field angle;
+    the detector is the image plane (the trace's output plane), normal to
+    the axis, npix^2 pixels over +-half_span_lamF lambda F with F the
+    nominal f/24.  abcd and base are left to a ray tracer."""
+    sys_ = system or hst_rc()
+    r1, s = annulus_grid(n_across, sys_["D"], sys_["r_obs"])
+    n = r1.shape[0]
+    th1 = np.tile(np.asarray(field_angle, np.float64), (n, 1))
+    w0 = np.full(n, OF * s / 2.0)
+    amp = np.zeros((n, 2))
+    amp[:, 0] = 1.0
+    lamF = lam * 24.0
+    pitch = 2.0 * half_span_lamF * lamF / npix
+    pl = _plane([0.0, 0.0, 0.0], [0.0, 0.0, 1.0], [1.0, 0.0, 0.0], npix, npix, pitch, pitch)
+    return Scene(lam, sys_["l0"], r1, th1, w0, amp, np.zeros(n), None, pl,
+                 meta=dict(n_across=n_across, OF=OF, D=sys_["D"], r_obs=sys_["r_obs"], fnum=24.0,
+                           half_span_lamF=half_span_lamF, system=sys_, field_angle=tuple(field_angle)))
