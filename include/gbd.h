@@ -108,6 +108,41 @@ const char *gbd_last_error(void);
 int gbd_beamlets(gbd_ctx_t ctx, gbd_beamlets_t *out, int64_t n, double lambda, double l0,
                  const double *r1, const double *th1, const double *w0, int64_t n_w0,
                  const double *amp, const double *path, const double *abcd, int64_t n_abcd);
+
+/* --- ray-traced inputs (Sec. 2.2: beamlets carried by a base ray and
+ * parabasal rays through the system; Appendix B's telescope is two conic
+ * mirrors) -------------------------------------------------------------------
+ * gbd_trace: real-ray trace, FP64 on the device, of n base rays through
+ * n_mirrors (<= 8) conic mirrors, each a row (z_vertex, R, k, r_min, r_max)
+ * of `mirrors`: vertex on the axis, vertex radius of curvature signed in the
+ * global frame (the centre of curvature at z_vertex + R; 0 = plane mirror),
+ * conic constant, clear annulus (m).  Rays start on the plane z = z_in at
+ * r1 [n][2] with x, y direction cosines th1 [n][2] (NULL = along +z) and end
+ * on the plane z = z_out; after an odd number of reflections the output frame
+ * is the global one turned by pi about x.  Every input coordinate is also
+ * perturbed by -/+ dr (positions) or dth (direction cosines) and the central
+ * differences give the differential matrix.  Writes (host arrays, caller-
+ * owned): base_out [n][5] = (x, y, l, m, optical path - l0) at z_out,
+ * abcd_out [n][16] row-major [[A, B], [C, D]] = d(x, y, l, m)_out /
+ * d(x, y, l, m)_in, flags_out [n] = bits 1 vignetted (a hit outside a
+ * mirror's annulus), 2 missed, 4 the output plane behind the ray, over the
+ * base ray and its eight parabasal rays.  Synchronises the context stream.
+ * gbd_beamlets_traced: as gbd_beamlets with per-beamlet traced inputs: abcd
+ * [n][16] the differential matrices, base [n][5] the traced base rays, which
+ * replace the ab/cd-law base ray and whose path (beyond l0) replaces the
+ * eikonal term of the misalignment phase.  Finite-difference matrices carry
+ * truncation and rounding error and can have a vanishing block (A at a
+ * focus), so the symplectic relations are checked scale-free: with the
+ * symplectic balancing M' = diag(1/s, 1/s, s, s) M diag(s, s, 1/s, 1/s),
+ * s^2 = sqrt(|B|_F / |C|_F), every entry of M'^T J M' - J must lie within
+ * sympl_tol * max(1, max|M'|)^2, sympl_tol in (0, 1e-3] (1e-7 suits
+ * gbd_trace's output at dr = 1e-5 m, dth = 1e-7), else GBD_ENOTSYMPLECTIC. */
+int gbd_trace(gbd_ctx_t ctx, int32_t n_mirrors, const double *mirrors, double z_in, double z_out, double l0,
+              int64_t n, const double *r1, const double *th1, double dr, double dth, double *base_out,
+              double *abcd_out, int32_t *flags_out);
+int gbd_beamlets_traced(gbd_ctx_t ctx, gbd_beamlets_t *out, int64_t n, double lambda, double l0, const double *r1,
+                        const double *th1, const double *w0, int64_t n_w0, const double *amp, const double *path,
+                        const double *abcd, const double *base, double sympl_tol);
 void gbd_beamlets_free(gbd_beamlets_t b);
 
 /* --- detector plane (Sec. 3: the common evaluation plane) ----------------

@@ -147,6 +147,40 @@ static int symplectic_ok(const double *M, double tol) {
     return worst <= tol;
 }
 
+/* Differential matrices from ray tracing can have a vanishing block (A at a
+ * focus), where entry-wise relative residuals mean nothing.  Scale positions
+ * by s and angles by 1/s with s^2 = sqrt(|B|_F / |C|_F), a symplectic change of
+ * variables that leaves A and D and gives B and C equal norms, and require
+ * every entry of M'^T J M' - J within tol * max(1, max|M'|)^2. */
+static int symplectic_scaled_ok(const double *M, double tol) {
+    double nb = 0.0, nc = 0.0;
+    for (int i = 0; i < 2; i++)
+        for (int j = 0; j < 2; j++) {
+            nb += M[4 * i + j + 2] * M[4 * i + j + 2];
+            nc += M[4 * (i + 2) + j] * M[4 * (i + 2) + j];
+        }
+    double s2 = 1.0;
+    if (nb > 0.0 && nc > 0.0) s2 = sqrt(sqrt(nb / nc));
+    double P[4][4], top = 1.0;
+    for (int i = 0; i < 4; i++)
+        for (int j = 0; j < 4; j++) {
+            double v = M[4 * i + j];
+            if (i < 2 && j >= 2) v = v / s2;
+            else if (i >= 2 && j < 2) v = v * s2;
+            P[i][j] = v;
+            if (fabs(v) > top) top = fabs(v);
+        }
+    /* M'^T J M' with J = [[0, I], [-I, 0]]: entry (r, c) = sum_k P[k][r] P[k+2][c] - P[k+2][r] P[k][c] */
+    for (int r = 0; r < 4; r++)
+        for (int c = 0; c < 4; c++) {
+            double v = 0.0;
+            for (int k = 0; k < 2; k++) v += P[k][r] * P[k + 2][c] - P[k + 2][r] * P[k][c];
+            double want = (r < 2 && c == r + 2) ? 1.0 : (r >= 2 && c == r - 2) ? -1.0 : 0.0;
+            if (!(fabs(v - want) <= tol * top * top)) return 0;
+        }
+    return 1;
+}
+
 /* ---- detector plane ---- */
 typedef struct {
     double O[3], n[3], e1[3], e2[3];
@@ -365,7 +399,8 @@ static int valid_inputs(int64_t n, double lam, double l0, const double *r1, cons
     for (int64_t j = 0; j < nm; j++) {
         for (int e = 0; e < 16; e++)
             if (!isfinite(abcd[16 * j + e])) return OR_EINVAL;
-        if (!symplectic_ok(abcd + 16 * j, tol)) return OR_ENOTSYMPLECTIC;
+        if (!(base ? symplectic_scaled_ok(abcd + 16 * j, tol) : symplectic_ok(abcd + 16 * j, tol)))
+            return OR_ENOTSYMPLECTIC;
     }
     return OR_OK;
 }

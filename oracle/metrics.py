@@ -27,6 +27,22 @@ def airy_irradiance(plane, D, f, lam):
     return amp * amp
 
 
+def annular_airy_irradiance(plane, D, f, lam, eps):
+    """Peak-normalised irradiance of a uniformly lit annulus of outer
+    diameter D and obscuration ratio eps (inner / outer radius) in the focal
+    plane of focal length f: the field is the outer disc's Airy amplitude
+    minus the inner disc's, each 2 J1(u) / u scaled by its area,
+    [(2 J1(v)/v - eps^2 2 J1(eps v)/(eps v)) / (1 - eps^2)]^2, v = pi D r / (lam f)."""
+    v = np.pi * D * plane_radius(plane) / (lam * f)
+
+    def disc(u):
+        with np.errstate(invalid="ignore", divide="ignore"):
+            return np.where(u > 0, 2.0 * scipy.special.j1(u) / u, 1.0)
+
+    amp = (disc(v) - eps * eps * disc(eps * v)) / (1.0 - eps * eps)
+    return amp * amp
+
+
 def airy_metrics(E, E0, airy, radius=None, zone_edges=None):
     d = np.abs(E) ** 2 / abs(E0) ** 2 - airy
     out = [float(np.sqrt(np.mean(d * d))), float(np.abs(d).max())]

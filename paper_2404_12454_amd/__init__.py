@@ -24,6 +24,7 @@ __all__ = [
     "gbd_ctx_create", "gbd_beamlets", "gbd_plane", "gbd_eval", "gbd_plan_create", "gbd_plan_setup",
     "gbd_plan_eval", "gbd_plan_shape", "gbd_airy", "gbd_eval_batch", "gbd_eval_point", "gbd_autotune", "gbd_autotune_batch",
     "gbd_autotune_save", "gbd_autotune_load", "GBD_MLP_FP32", "GBD_MLP_BF16", "Mlp", "gbd_mlp_create", "beamlets_from_scene", "plane_from_scene",
+    "gbd_trace", "gbd_beamlets_traced",
     "Context", "Beamlets", "Plane", "Plan",
 ]
 
@@ -68,6 +69,8 @@ def load_library():
         "gbd_ctx_create": (ctypes.c_int, [PP, ctypes.c_int, P]),
         "gbd_ctx_set_stream": (ctypes.c_int, [P, P]),
         "gbd_ctx_destroy": (None, [P]),
+        "gbd_trace": (ctypes.c_int, [P, I32, P, D, D, D, I64, P, P, D, D, P, P, P]),
+        "gbd_beamlets_traced": (ctypes.c_int, [P, PP, I64, D, D, P, P, P, I64, P, P, P, P, D]),
         "gbd_last_error": (ctypes.c_char_p, []),
         "gbd_beamlets": (ctypes.c_int, [P, PP, I64, D, D, P, P, P, I64, P, P, P, I64]),
         "gbd_beamlets_free": (None, [P]),
@@ -196,7 +199,38 @@ def gbd_plane(ctx: Context, origin, normal, xhint, nx: int, ny: int, dx: float, 
     return Plane(h, int(nx), int(ny))
 
 
+def gbd_trace(ctx: Context, mirrors, z_in: float, z_out: float, l0: float, r1, th1=None, dr: float = 1e-5,
+              dth: float = 1e-7):
+    """Real-ray trace through conic mirrors on the device (see gbd.h): returns
+    base [n,5], abcd [n,16] and flags [n] as host arrays."""
+    mir = _f64(np.asarray(mirrors, np.float64).reshape(-1, 5))
+    r1 = _f64(np.asarray(r1).reshape(-1, 2))
+    th = None if th1 is None else _f64(np.asarray(th1).reshape(-1, 2))
+    n = r1.shape[0]
+    base = np.empty((n, 5))
+    abcd = np.empty((n, 16))
+    flags = np.empty(n, np.int32)
+    _check(load_library().gbd_trace(ctx.handle, mir.shape[0], _p(mir), float(z_in), float(z_out), float(l0), n,
+                                    _p(r1), _p(th), float(dr), float(dth), _p(base), _p(abcd), _p(flags)))
+    return base, abcd, flags
+
+
+def gbd_beamlets_traced(ctx: Context, n: int, lam: float, l0: float, r1, th1, w0, amp, path, abcd, base,
+                        sympl_tol: float = 1e-7) -> Beamlets:
+    """Beamlets with traced base rays and differential matrices (see gbd.h)."""
+    r1, th1, w0, amp, path, abcd, base = map(_f64, (r1, th1, w0, amp, path, abcd, base))
+    w0 = np.atleast_1d(w0)
+    h = ctypes.c_void_p()
+    _check(load_library().gbd_beamlets_traced(ctx.handle, ctypes.byref(h), int(n), float(lam), float(l0), _p(r1),
+                                              _p(th1), _p(w0), w0.size, _p(amp), _p(path),
+                                              _p(abcd.reshape(-1, 16)), _p(base.reshape(-1, 5)), float(sympl_tol)))
+    return Beamlets(h, int(n))
+
+
 def beamlets_from_scene(ctx: Context, s) -> Beamlets:
+    if getattr(s, "base", None) is not None:
+        return gbd_beamlets_traced(ctx, s.n, s.lam, s.l0, s.r1, s.th1, s.w0, s.amp, s.path, s.abcd, s.base,
+                                   s.sympl_tol or 1e-7)
     return gbd_beamlets(ctx, s.n, s.lam, s.l0, s.r1, s.th1, s.w0, s.amp, s.path, s.abcd)
 
 

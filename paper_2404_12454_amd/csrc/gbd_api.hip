@@ -115,7 +115,7 @@ int hip_fail(hipError_t e, const char *what) {
 
 // Ray-transfer matrices must be symplectic: M^T J M = J with
 // J = [[0, I], [-I, 0]] (equivalent to the block relations of Sec. 2.1).
-bool symplectic(const double *m) {
+bool symplectic(const double *m, double tol = 1e-10) {
     static const double J[4][4] = {{0, 0, 1, 0}, {0, 0, 0, 1}, {-1, 0, 0, 0}, {0, -1, 0, 0}};
     for (int r = 0; r < 4; r++)
         for (int c = 0; c < 4; c++) {
@@ -126,7 +126,40 @@ bool symplectic(const double *m) {
                     v += t;
                     mag += fabs(t);
                 }
-            if (fabs(v - J[r][c]) > 1e-10 * (mag + fabs(J[r][c]))) return false;
+            if (fabs(v - J[r][c]) > tol * (mag + fabs(J[r][c]))) return false;
+        }
+    return true;
+}
+
+// Traced (finite-difference) matrices: a block can vanish (A at a focus), so
+// entry-wise relative residuals are ill-posed.  Balance with the symplectic
+// similarity diag(1/s, 1/s, s, s) M diag(s, s, 1/s, 1/s), s^2 = sqrt(|B| / |C|)
+// (Frobenius norms), which leaves A and D and scales B, C to equal norms, and
+// bound max |M'^T J M' - J| by tol * max(1, max |M'|)^2.
+bool symplectic_balanced(const double *m, double tol) {
+    double nb = 0.0, nc = 0.0;
+    for (int r = 0; r < 2; r++)
+        for (int c = 0; c < 2; c++) {
+            nb += m[4 * r + c + 2] * m[4 * r + c + 2];
+            nc += m[4 * (r + 2) + c] * m[4 * (r + 2) + c];
+        }
+    const double s2 = (nb > 0.0 && nc > 0.0) ? sqrt(sqrt(nb) / sqrt(nc)) : 1.0;
+    double b[16], big = 1.0;
+    for (int r = 0; r < 4; r++)
+        for (int c = 0; c < 4; c++) {
+            double v = m[4 * r + c];
+            if (r < 2 && c >= 2) v /= s2;
+            if (r >= 2 && c < 2) v *= s2;
+            b[4 * r + c] = v;
+            big = fmax(big, fabs(v));
+        }
+    static const double J[4][4] = {{0, 0, 1, 0}, {0, 0, 0, 1}, {-1, 0, 0, 0}, {0, -1, 0, 0}};
+    for (int r = 0; r < 4; r++)
+        for (int c = 0; c < 4; c++) {
+            double v = 0.0;
+            for (int i = 0; i < 4; i++)
+                for (int k = 0; k < 4; k++) v += b[4 * i + r] * J[i][k] * b[4 * k + c];
+            if (!(fabs(v - J[r][c]) <= tol * big * big)) return false;
         }
     return true;
 }
@@ -429,10 +462,11 @@ void gbd_ctx_destroy(gbd_ctx_t ctx) {
     delete ctx;
 }
 
-int gbd_beamlets(gbd_ctx_t ctx, gbd_beamlets_t *out, int64_t n, double lambda, double l0, const double *r1,
-                 const double *th1, const double *w0, int64_t n_w0, const double *amp, const double *path,
-                 const double *abcd, int64_t n_abcd) {
+static int beamlets_impl(gbd_ctx_t ctx, gbd_beamlets_t *out, int64_t n, double lambda, double l0, const double *r1,
+                  const double *th1, const double *w0, int64_t n_w0, const double *amp, const double *path,
+                  const double *abcd, int64_t n_abcd, const double *base, double sympl_tol) {
     if (!ctx || !out) return fail(GBD_EINVAL, "ctx/out is NULL");
+    if (!(sympl_tol > 0.0 && sympl_tol <= 1e-3)) return fail(GBD_EINVAL, "sympl_tol must be in (0, 1e-3]");
     if (n < 0) return fail(GBD_EINVAL, "n < 0");
     if (!(lambda > 0.0) || !std::isfinite(lambda)) return fail(GBD_EINVAL, "lambda must be finite and > 0");
     if (!std::isfinite(l0)) return fail(GBD_EINVAL, "l0 must be finite");
@@ -441,23 +475,25 @@ int gbd_beamlets(gbd_ctx_t ctx, gbd_beamlets_t *out, int64_t n, double lambda, d
         if (!(n_w0 == 1 || n_w0 == n)) return fail(GBD_EINVAL, "n_w0 must be 1 or n");
         if (!(n_abcd == 1 || n_abcd == n)) return fail(GBD_EINVAL, "n_abcd must be 1 or n");
         if (!finite_all(r1, 2 * n) || (th1 && !finite_all(th1, 2 * n)) || (amp && !finite_all(amp, 2 * n)) ||
-            (path && !finite_all(path, n)) || !finite_all(abcd, 16 * n_abcd))
+            (path && !finite_all(path, n)) || !finite_all(abcd, 16 * n_abcd) || (base && !finite_all(base, 5 * n)))
             return fail(GBD_EINVAL, "non-finite input");
         for (int64_t i = 0; i < n_w0; i++)
             if (!(w0[i] > 0.0) || !std::isfinite(w0[i])) return fail(GBD_EINVAL, "w0[%lld] must be finite and > 0", (long long)i);
         for (int64_t i = 0; i < n_abcd; i++)
-            if (!symplectic(abcd + 16 * i))
+            if (!(base ? symplectic_balanced(abcd + 16 * i, sympl_tol) : symplectic(abcd + 16 * i, sympl_tol)))
                 return fail(GBD_ENOTSYMPLECTIC, "abcd[%lld] is not symplectic", (long long)i);
     } else {
         n_w0 = 1;
         n_abcd = 1;
+        base = nullptr;
     }
     int rc = ensure_device(ctx);
     if (rc) return rc;
-    // one device block: r1, th1, amp [n][2]; w0 [n_w0]; path [n]; abcd [n_abcd][16]
+    // one device block: r1, th1, amp [n][2]; w0 [n_w0]; path [n]; abcd [n_abcd][16]; base [n][5]
     const size_t nn = (size_t)std::max<int64_t>(n, 1);
     const size_t off_r1 = 0, off_th1 = off_r1 + 2 * nn, off_amp = off_th1 + 2 * nn, off_w0 = off_amp + 2 * nn,
-                 off_path = off_w0 + (size_t)n_w0, off_abcd = off_path + nn, total = off_abcd + 16 * (size_t)n_abcd;
+                 off_path = off_w0 + (size_t)n_w0, off_abcd = off_path + nn, off_base = off_abcd + 16 * (size_t)n_abcd,
+                 total = off_base + (base ? 5 * nn : 0);
     std::vector<double> host(total, 0.0);
     if (n > 0) {
         memcpy(&host[off_r1], r1, 2 * n * sizeof(double));
@@ -469,6 +505,7 @@ int gbd_beamlets(gbd_ctx_t ctx, gbd_beamlets_t *out, int64_t n, double lambda, d
         memcpy(&host[off_w0], w0, n_w0 * sizeof(double));
         if (path) memcpy(&host[off_path], path, n * sizeof(double));
         memcpy(&host[off_abcd], abcd, 16 * n_abcd * sizeof(double));
+        if (base) memcpy(&host[off_base], base, 5 * n * sizeof(double));
     } else {
         host[off_w0] = 1.0;
         for (int i = 0; i < 4; i++) host[off_abcd + 5 * i] = 1.0;
@@ -500,7 +537,67 @@ int gbd_beamlets(gbd_ctx_t ctx, gbd_beamlets_t *out, int64_t n, double lambda, d
     b->dev.w0 = d + off_w0;
     b->dev.path = d + off_path;
     b->dev.abcd = d + off_abcd;
+    b->dev.base = base ? d + off_base : nullptr;
     *out = b;
+    return GBD_OK;
+}
+
+int gbd_beamlets(gbd_ctx_t ctx, gbd_beamlets_t *out, int64_t n, double lambda, double l0, const double *r1,
+                 const double *th1, const double *w0, int64_t n_w0, const double *amp, const double *path,
+                 const double *abcd, int64_t n_abcd) {
+    return beamlets_impl(ctx, out, n, lambda, l0, r1, th1, w0, n_w0, amp, path, abcd, n_abcd, nullptr, 1e-10);
+}
+
+int gbd_beamlets_traced(gbd_ctx_t ctx, gbd_beamlets_t *out, int64_t n, double lambda, double l0, const double *r1,
+                        const double *th1, const double *w0, int64_t n_w0, const double *amp, const double *path,
+                        const double *abcd, const double *base, double sympl_tol) {
+    if (n > 0 && !base) return fail(GBD_EINVAL, "base is NULL");
+    return beamlets_impl(ctx, out, n, lambda, l0, r1, th1, w0, n_w0, amp, path, abcd, n, base, sympl_tol);
+}
+
+int gbd_trace(gbd_ctx_t ctx, int32_t n_mirrors, const double *mirrors, double z_in, double z_out, double l0,
+              int64_t n, const double *r1, const double *th1, double dr, double dth, double *base_out,
+              double *abcd_out, int32_t *flags_out) {
+    if (!ctx) return fail(GBD_EINVAL, "ctx is NULL");
+    if (n_mirrors < 0 || n_mirrors > kMaxMirrors) return fail(GBD_EINVAL, "n_mirrors must be in [0, %d]", kMaxMirrors);
+    if (n < 0) return fail(GBD_EINVAL, "n < 0");
+    if (!(dr > 0.0) || !(dth > 0.0) || !std::isfinite(dr) || !std::isfinite(dth))
+        return fail(GBD_EINVAL, "dr and dth must be finite and > 0");
+    if (!std::isfinite(z_in) || !std::isfinite(z_out) || !std::isfinite(l0)) return fail(GBD_EINVAL, "non-finite plane");
+    if (n_mirrors > 0 && !mirrors) return fail(GBD_EINVAL, "mirrors is NULL");
+    if (n > 0 && (!r1 || !base_out || !abcd_out || !flags_out)) return fail(GBD_EINVAL, "NULL array");
+    TraceSystem S;
+    S.n = n_mirrors;
+    S.z_in = z_in;
+    S.z_out = z_out;
+    S.l0 = l0;
+    for (int i = 0; i < n_mirrors; i++) {
+        const double *e = mirrors + 5 * i;
+        if (!finite_all(e, 5)) return fail(GBD_EINVAL, "non-finite mirror %d", i);
+        S.m[i] = TraceMirror{e[0], e[1] == 0.0 ? 0.0 : 1.0 / e[1], e[2], e[3], e[4]};
+    }
+    if (n > 0 && (!finite_all(r1, 2 * n) || (th1 && !finite_all(th1, 2 * n))))
+        return fail(GBD_EINVAL, "non-finite ray");
+    if (n == 0) return GBD_OK;
+    int rc = ensure_device(ctx);
+    if (rc) return rc;
+    // device block: r1 [n][2], th1 [n][2], base [n][5], abcd [n][16], flags [n] (int32)
+    const size_t nd = (size_t)n;
+    const size_t off_th = 2 * nd, off_base = 4 * nd, off_abcd = 9 * nd, off_flags = 25 * nd;
+    void *mem = nullptr;
+    HIP_TRY(hipMalloc(&mem, off_flags * sizeof(double) + nd * sizeof(int32_t)), "hipMalloc(trace)");
+    double *d = static_cast<double *>(mem);
+    int32_t *dflags = reinterpret_cast<int32_t *>(d + off_flags);
+    hipError_t e = hipMemcpyAsync(d, r1, 2 * nd * sizeof(double), hipMemcpyHostToDevice, ctx->stream);
+    if (e == hipSuccess && th1) e = hipMemcpyAsync(d + off_th, th1, 2 * nd * sizeof(double), hipMemcpyHostToDevice, ctx->stream);
+    if (e == hipSuccess)
+        e = launch_trace(S, n, d, th1 ? d + off_th : nullptr, dr, dth, d + off_base, d + off_abcd, dflags, ctx->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(base_out, d + off_base, 5 * nd * sizeof(double), hipMemcpyDeviceToHost, ctx->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(abcd_out, d + off_abcd, 16 * nd * sizeof(double), hipMemcpyDeviceToHost, ctx->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(flags_out, dflags, nd * sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    (void)hipFree(mem);
+    if (e != hipSuccess) return hip_fail(e, "trace");
     return GBD_OK;
 }
 

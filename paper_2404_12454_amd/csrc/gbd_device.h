@@ -77,12 +77,19 @@ __device__ inline uint32_t setup_one(const BeamletsDev &b, const PlaneGeom &pl, 
     const double W = b.path[j];
     const double lam = b.lam;
 
-    // base ray at the ABCD output plane (Appendix A, ab/cd laws)
+    // base ray at the ABCD output plane (Appendix A, ab/cd laws), or the
+    // traced one of ray-traced inputs
     double r2M[2], th[2];
+    const double *tb = b.base ? b.base + 5 * j : nullptr;
 #pragma unroll
     for (int r = 0; r < 2; r++) {
-        r2M[r] = A[r][0] * r1[0] + A[r][1] * r1[1] + B[r][0] * t1[0] + B[r][1] * t1[1];
-        th[r] = C[r][0] * r1[0] + C[r][1] * r1[1] + D[r][0] * t1[0] + D[r][1] * t1[1];
+        if (tb) {
+            r2M[r] = tb[r];
+            th[r] = tb[2 + r];
+        } else {
+            r2M[r] = A[r][0] * r1[0] + A[r][1] * r1[1] + B[r][0] * t1[0] + B[r][1] * t1[1];
+            th[r] = C[r][0] * r1[0] + C[r][1] * r1[1] + D[r][0] * t1[0] + D[r][1] * t1[1];
+        }
     }
     // where the base ray (r2M + z th, z) meets the plane
     const double nd = pl.n[0] * th[0] + pl.n[1] * th[1] + pl.n[2];
@@ -130,9 +137,12 @@ __device__ inline uint32_t setup_one(const BeamletsDev &b, const PlaneGeom &pl, 
         if (!on_branch(mu1) || !on_branch(mu2)) flag |= FLAG_BRANCH;
         const cd gamma = cdiv(mk(1.0, 0.0), mul(csqrt_p(mu1), csqrt_p(mu2)));
 
-        // misalignment phase at the hit point, in turns (l0 handled by the host)
+        // misalignment phase at the hit point, in turns (l0 handled by the
+        // host): Euler's relation for the eikonal, or the traced optical path
+        // plus the free-space extension
         const double r2[2] = {r2M[0] + z * th[0], r2M[1] + z * th[1]};
-        const double S = 0.5 * (th[0] * r2[0] + th[1] * r2[1] - t1[0] * r1[0] - t1[1] * r1[1]);
+        const double S = tb ? tb[4] + 0.5 * z * (th[0] * th[0] + th[1] * th[1])
+                            : 0.5 * (th[0] * r2[0] + th[1] * r2[1] - t1[0] * r1[0] - t1[1] * r1[1]);
         const double tau = (z + W + S) / lam;
 
         // plane basis seen from the beamlet: w = Pm d, zeta = ez . d

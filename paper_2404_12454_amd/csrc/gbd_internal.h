@@ -26,6 +26,8 @@ struct BeamletsDev {
     const double *amp;   // [n][2]
     const double *path;  // [n]
     const double *abcd;  // [n_abcd][16]
+    const double *base;  // [n][5] traced base ray at the output plane (x, y, l, m,
+                         // optical path - l0), or null: the ab/cd laws
 };
 
 // Per-beamlet phasor on the plane, about the base-ray hit point (a_rho, b_rho):
@@ -130,6 +132,20 @@ hipError_t launch_batch_eval(int rows, int waves, int form, int cus, const Batch
 hipError_t launch_batch_finalize(const BatchEval *inst, int32_t n_inst, const double *part, int32_t n_zones,
                                  double *metrics, hipStream_t s);
 hipError_t launch_airy(int32_t nx, int32_t ny, double dx, double dy, double vscale, float *out, hipStream_t s);
+
+// --- real-ray trace through conic mirrors ----------------------------------
+constexpr int kMaxMirrors = 8;
+struct TraceMirror {
+    double zv, c, k, r_min, r_max;  // vertex, curvature 1/R (0: plane), conic, clear annulus
+};
+struct TraceSystem {
+    int32_t n;
+    double z_in, z_out, l0;
+    TraceMirror m[kMaxMirrors];
+};
+enum : uint32_t { TRACE_VIGNETTED = 1u, TRACE_MISSED = 2u, TRACE_BACKWARD = 4u };
+hipError_t launch_trace(const TraceSystem &S, int64_t n, const double *r1, const double *th1, double h_r,
+                        double h_t, double *base, double *abcd, int32_t *flags, hipStream_t s);
 
 // --- point evaluation (paraxial, FP64) -----------------------------------
 // Per beamlet: base ray at the ABCD output plane, P0 = Nm adj(Mm0) (complex

@@ -36,10 +36,11 @@ __global__ void __launch_bounds__(256) point_setup_kernel(BeamletsDev b, double 
     const double w0 = b.w0[b.n_w0 == 1 ? 0 : j];
     const double kappa = b.lam / (kPi * w0 * w0);
     RecPt o;
+    const double *tb = b.base ? b.base + 5 * j : nullptr;  // traced base ray, if any
 #pragma unroll
     for (int r = 0; r < 2; r++) {
-        o.r2[r] = A[r][0] * r1[0] + A[r][1] * r1[1] + B[r][0] * t1[0] + B[r][1] * t1[1];
-        o.th[r] = C[r][0] * r1[0] + C[r][1] * r1[1] + D[r][0] * t1[0] + D[r][1] * t1[1];
+        o.r2[r] = tb ? tb[r] : A[r][0] * r1[0] + A[r][1] * r1[1] + B[r][0] * t1[0] + B[r][1] * t1[1];
+        o.th[r] = tb ? tb[2 + r] : C[r][0] * r1[0] + C[r][1] * r1[1] + D[r][0] * t1[0] + D[r][1] * t1[1];
     }
     cd M0[2][2], N[2][2];
 #pragma unroll
@@ -77,7 +78,7 @@ __global__ void __launch_bounds__(256) point_setup_kernel(BeamletsDev b, double 
     o.amp[0] = b.amp[2 * j];
     o.amp[1] = b.amp[2 * j + 1];
     // turns: l0/lambda (reduced on the host) + (W + S0)/lambda, and per unit z
-    const double S0 = 0.5 * (o.th[0] * o.r2[0] + o.th[1] * o.r2[1] - t1[0] * r1[0] - t1[1] * r1[1]);
+    const double S0 = tb ? tb[4] : 0.5 * (o.th[0] * o.r2[0] + o.th[1] * o.r2[1] - t1[0] * r1[0] - t1[1] * r1[1]);
     const double c0 = (b.path[j] + S0) / b.lam;
     const double c0r = (c0 - rint(c0)) + gturns;
     o.c0 = c0r - rint(c0r);

@@ -150,3 +150,20 @@ def test_base_override_with_paraxial_values_reproduces_the_abcd_field():
     sc.base[3, 4] += 0.5 * sc.lam
     E2 = oracle.eval_field(sc)
     assert np.linalg.norm(E2 - E0) / np.linalg.norm(E0) > 1e-3
+
+
+def test_annular_airy_reference_reduces_to_the_airy_pattern():
+    """The obscured-aperture reference at eps -> 0 is the Airy pattern, its
+    first zero moves inwards with the obscuration (v = 3.8317 at eps = 0),
+    and it is 1 on axis."""
+    from oracle import metrics as om
+    pl = scenes.airy_scene(8, npix=65, half_span_lamF=6.0).plane
+    a = om.airy_irradiance(pl, 10e-3, 100e-3, 1e-6)
+    np.testing.assert_allclose(om.annular_airy_irradiance(pl, 10e-3, 100e-3, 1e-6, 0.0), a, atol=1e-15)
+    import scipy.optimize, scipy.special
+    f = lambda v, e: (2 * scipy.special.j1(v) / v - e * e * 2 * scipy.special.j1(e * v) / (e * v))
+    z0 = scipy.optimize.brentq(lambda v: f(v, 1e-9), 3.0, 4.5)
+    z1 = scipy.optimize.brentq(lambda v: f(v, 0.33), 3.0, 4.5)
+    assert abs(z0 - 3.8317) < 1e-4 and z1 < z0
+    c = pl.nx // 2
+    assert abs(om.annular_airy_irradiance(pl, 10e-3, 100e-3, 1e-6, 0.3)[c, c] - 1.0) < 1e-12
