@@ -58,7 +58,7 @@ def _load():
                                     ctypes.c_double, ctypes.c_double, ctypes.c_int64, P, P, ctypes.c_int, P, P, P]
         lib.oracle_eval_base.restype = ctypes.c_int
         lib.oracle_eval_base.argtypes = [ctypes.c_int64, ctypes.c_double, ctypes.c_double, P, P, P, ctypes.c_int64,
-                                         P, P, P, ctypes.c_int, P, ctypes.c_double, P, P, P, ctypes.c_int32,
+                                         P, P, P, ctypes.c_int, P, ctypes.c_double, P, P, P, P, ctypes.c_int32,
                                          ctypes.c_int32, ctypes.c_double, ctypes.c_double, ctypes.c_int64, P, P,
                                          ctypes.c_int, P, P, P]
         lib.oracle_trace.restype = ctypes.c_int
@@ -111,8 +111,11 @@ def eval_field(scene, model: int = 0, pixels: Optional[tuple] = None, extra_poin
         lib.oracle_set_threads(int(threads))
     base = _f64(getattr(scene, "base", None))
     tol = getattr(scene, "sympl_tol", None) or 1e-10
+    order = getattr(scene, "order", None)
+    order = None if order is None else np.ascontiguousarray(order, dtype=np.int32).reshape(-1, 2)
     rc = lib.oracle_eval_base(scene.n, scene.lam, scene.l0, _ptr(r1), _ptr(th1), _ptr(w0), w0.size, _ptr(amp),
-                              _ptr(path), _ptr(abcd), shared, _ptr(base), float(tol), _ptr(_f64(pl.origin)),
+                              _ptr(path), _ptr(abcd), shared, _ptr(base), float(tol), _ptr(order),
+                              _ptr(_f64(pl.origin)),
                               _ptr(_f64(pl.normal)), _ptr(_f64(pl.xhint)), pl.nx, pl.ny, pl.dx, pl.dy, m,
                               _ptr(ix), _ptr(iy), model, _ptr(out), _ptr(ep), _ptr(oe))
     if rc != 0:

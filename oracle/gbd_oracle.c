@@ -43,6 +43,16 @@
  *     setting) and the second-order expansion about the hit point of the
  *     exact paraxial beamlet field for a tilted plane.
  *  7. E = sum_j E_j, in beamlet index order.
+ * Higher-order beamlets (the Hermite solutions of the reduced Collins
+ * integral that Sec. 2.1 lists as usable in beamlet decomposition): the
+ * elegant Hermite-Gaussian input H_m(u_x) H_n(u_y) e^(-|u|^2)
+ * e^(-i k th1 . (r - c)), u = (r - c) / w0, is w0^(m+n) times the
+ * derivative d^(m+n) / dc_x^m dc_y^n of the Gaussian envelope with the tilt
+ * phase held fixed, and propagation commutes with that derivative; so the
+ * output is the Gaussian beamlet's field times a polynomial in
+ * g = L w (L = -i k (C^T - A'^T Q), linear in the offset w from the base
+ * ray) and the constant H = i k (C^T A' - A'^T Q A'), exact on planes normal
+ * to the axis.
  * The point-evaluation form (model 1) instead extends the system to every
  * pixel's own axial position and evaluates steps 4-6 there exactly.
  */
@@ -214,6 +224,10 @@ typedef struct {
     double r2[2];    /* base-ray position at the output (r2M + z th2M) */
     double th2[2];   /* base-ray slope */
     double tau;      /* (z + W + S') / lambda in turns, l0 excluded */
+    /* higher-order (elegant Hermite-Gaussian) beamlets: the envelope's
+     * d log E / dc = L w and d^2 log E / dc dc^T = H, c the input centre,
+     * w = r - r2 */
+    cplx L[2][2], H[2][2];
 } or_prop;
 
 typedef struct {
@@ -223,6 +237,7 @@ typedef struct {
     const double *M;
     const double *base; /* NULL, or a traced base ray at the ABCD output plane:
                            (x, y, l, m, optical path - l0) */
+    int hm, hn;         /* elegant Hermite-Gaussian orders (0, 0 = Gaussian) */
 } or_in;
 
 static int propagate(const or_in *b, double z, or_prop *out) {
@@ -280,7 +295,60 @@ static int propagate(const or_in *b, double z, or_prop *out) {
     else
         S = 0.5 * (th2M[0] * out->r2[0] + th2M[1] * out->r2[1] - b->th1[0] * b->r1[0] - b->th1[1] * b->r1[1]);
     out->tau = (z + b->W + S) / b->lam;
+    /* Derivatives with respect to the input centre c of the envelope (th1
+     * and the tilt phase's reference fixed).  With log E = -i k [S + th2 . w
+     * + w^T Q w / 2] + const, r2 = A' c + B' th1, th2 = C c + D th1,
+     * w = r - r2, and dS/dc = A'^T th2 - th1 (the eikonal's end-point
+     * derivatives), d log E / dc = -i k [(C^T - A'^T Q) w - th1]; the -th1
+     * is the tilt phase's own dependence on c, removed by holding its
+     * reference fixed:
+     *   g = L w, L = -i k (C^T - A'^T Q),
+     *   H = d g / dc = i k (C^T A' - A'^T Q A')  (C^T A' symmetric) */
+    const double k = 2.0 * M_PI / b->lam;
+    for (int i = 0; i < 2; i++)
+        for (int j = 0; j < 2; j++) {
+            cplx AQ = 0.0; /* (A'^T Q)_ij */
+            for (int r = 0; r < 2; r++) AQ += Ap[r][i] * Q.m[r][j];
+            out->L[i][j] = -I * k * (C[j][i] - AQ);
+        }
+    for (int i = 0; i < 2; i++)
+        for (int j = 0; j < 2; j++) {
+            cplx v = 0.0;
+            for (int r = 0; r < 2; r++) {
+                v += C[r][i] * Ap[r][j];
+                for (int t = 0; t < 2; t++) v -= Ap[r][i] * Q.m[r][t] * Ap[t][j];
+            }
+            out->H[i][j] = I * k * v;
+        }
     return OR_OK;
+}
+
+/* Elegant Hermite-Gaussian factor of orders (m, n) <= 2: the derivative
+ * d^(m+n) E / dc_x^m dc_y^n divided by E, from g = d log E / dc and the
+ * constant H = d^2 log E / dc^2 (Faa di Bruno for the exponential of a
+ * quadratic in c). */
+static cplx hermite_factor(int m, int n, const cplx g[2], cplx H[2][2]) {
+    const cplx gx = g[0], gy = g[1], hxx = H[0][0], hyy = H[1][1], hxy = 0.5 * (H[0][1] + H[1][0]);
+    switch (3 * m + n) {
+    case 0: return 1.0;
+    case 1: return gy;
+    case 2: return gy * gy + hyy;
+    case 3: return gx;
+    case 4: return gx * gy + hxy;
+    case 5: return gx * gy * gy + 2.0 * hxy * gy + hyy * gx;
+    case 6: return gx * gx + hxx;
+    case 7: return gx * gx * gy + 2.0 * hxy * gx + hxx * gy;
+    case 8: return gx * gx * gy * gy + 4.0 * hxy * gx * gy + hyy * gx * gx + hxx * gy * gy + hxx * hyy + 2.0 * hxy * hxy;
+    }
+    return NAN;
+}
+
+static cplx higher_order(const or_in *b, const or_prop *P, const double w[2]) {
+    if (b->hm == 0 && b->hn == 0) return 1.0;
+    cplx g[2];
+    for (int i = 0; i < 2; i++) g[i] = P->L[i][0] * w[0] + P->L[i][1] * w[1];
+    cplx H[2][2] = {{P->H[0][0], P->H[0][1]}, {P->H[1][0], P->H[1][1]}};
+    return pow(b->w0, b->hm + b->hn) * hermite_factor(b->hm, b->hn, g, H);
 }
 
 /* the base-ray hit point on the plane: a_rho, b_rho, z_rho */
@@ -311,6 +379,7 @@ typedef struct {
     double Pm[2][2]; /* columns i: e_i,perp - e_iz th2M */
     double ez[2];
     cplx pref;       /* a_j gamma exp(-2 pi i (tau - rint tau)) */
+    or_in in;        /* the beamlet's inputs (orders, waist) */
 } or_beam_on_plane;
 
 static int beam_on_plane(const or_in *b, const or_plane *p, or_beam_on_plane *o) {
@@ -325,6 +394,7 @@ static int beam_on_plane(const or_in *b, const or_plane *p, or_beam_on_plane *o)
         for (int r = 0; r < 2; r++) o->Pm[r][c] = e[c][r] - e[c][2] * o->P.th2[r];
     }
     o->pref = b->a * o->P.gamma * cexp(-2.0 * M_PI * I * reduce_turns(o->P.tau));
+    o->in = *b;
     return OR_OK;
 }
 
@@ -343,7 +413,7 @@ static cplx field_plane_model(const or_beam_on_plane *o, double lam, double a, d
     cplx logE = -I * k * ((1.0 + 0.5 * th2) * zeta + th[0] * w[0] + th[1] * w[1])
                 - 0.5 * trQ * zeta + 0.25 * trQ2 * zeta * zeta
                 - 0.5 * I * k * wQw;
-    return o->pref * cexp(logE);
+    return o->pref * cexp(logE) * higher_order(&o->in, &o->P, w);
 }
 
 /* exact paraxial field of one beamlet at the 3-D point X (point evaluation) */
@@ -356,13 +426,13 @@ static int field_point_exact(const or_in *b, const double X[3], cplx *E) {
     const cm2 *Q = &P.Qinv;
     cplx wQw = w[0] * (Q->m[0][0] * w[0] + Q->m[0][1] * w[1]) + w[1] * (Q->m[1][0] * w[0] + Q->m[1][1] * w[1]);
     cplx logE = -I * k * (P.th2[0] * w[0] + P.th2[1] * w[1]) - 0.5 * I * k * wQw;
-    *E = b->a * P.gamma * cexp(-2.0 * M_PI * I * reduce_turns(P.tau)) * cexp(logE);
+    *E = b->a * P.gamma * cexp(-2.0 * M_PI * I * reduce_turns(P.tau)) * cexp(logE) * higher_order(b, &P, w);
     return OR_OK;
 }
 
 static or_in load_in(int64_t j, double lam, double l0, const double *r1, const double *th1,
                      const double *w0, int64_t nw0, const double *amp, const double *path,
-                     const double *abcd, int shared, const double *base) {
+                     const double *abcd, int shared, const double *base, const int32_t *order) {
     or_in b;
     b.lam = lam;
     b.l0 = l0;
@@ -375,6 +445,8 @@ static or_in load_in(int64_t j, double lam, double l0, const double *r1, const d
     b.a = amp ? (amp[2 * j] + I * amp[2 * j + 1]) : 1.0;
     b.M = shared ? abcd : abcd + 16 * j;
     b.base = base ? base + 5 * j : NULL;
+    b.hm = order ? order[2 * j] : 0;
+    b.hn = order ? order[2 * j + 1] : 0;
     return b;
 }
 
@@ -418,11 +490,15 @@ static int valid_inputs(int64_t n, double lam, double l0, const double *r1, cons
 int oracle_eval_base(int64_t n, double lam, double l0, const double *r1, const double *th1,
                      const double *w0, int64_t nw0, const double *amp, const double *path,
                      const double *abcd, int shared_abcd, const double *base, double sympl_tol,
+                     const int32_t *order,
                      const double *origin, const double *normal, const double *xhint,
                      int32_t nx, int32_t ny, double dx, double dy,
                      int64_t npix, const int32_t *pix_ix, const int32_t *pix_iy,
                      int model, double *out, const double *extra_point, double *out_extra) {
     if (!(sympl_tol > 0.0)) return OR_EINVAL;
+    if (order)
+        for (int64_t j = 0; j < 2 * n; j++)
+            if (order[j] < 0 || order[j] > 2) return OR_EINVAL;
     int rc = valid_inputs(n, lam, l0, r1, th1, w0, nw0, amp, path, abcd, shared_abcd, base, sympl_tol);
     if (rc) return rc;
     or_plane pl;
@@ -439,8 +515,12 @@ int oracle_eval_base(int64_t n, double lam, double l0, const double *r1, const d
     or_beam_on_plane *bp = (or_beam_on_plane *)malloc(sizeof(or_beam_on_plane) * (size_t)(n > 0 ? n : 1));
     if (!bp) return OR_EINVAL;
     for (int64_t j = 0; j < n; j++) {
-        or_in b = load_in(j, lam, l0, r1, th1, w0, nw0, amp, path, abcd, shared_abcd, base);
+        or_in b = load_in(j, lam, l0, r1, th1, w0, nw0, amp, path, abcd, shared_abcd, base, order);
         rc = beam_on_plane(&b, &pl, &bp[j]);
+        /* a higher-order beamlet's plane-evaluation field is the exact
+         * paraxial one only on planes normal to the axis */
+        if (!rc && (b.hm || b.hn) && (model == 0 || extra_point) && (bp[j].ez[0] != 0.0 || bp[j].ez[1] != 0.0))
+            rc = OR_EINVAL;
         if (rc) { free(bp); return rc; }
     }
     /* the exact model must also be valid at every pixel's own axial position */
@@ -459,7 +539,7 @@ int oracle_eval_base(int64_t n, double lam, double l0, const double *r1, const d
             double X[3];
             for (int i = 0; i < 3; i++) X[i] = pl.O[i] + a * pl.e1[i] + bb * pl.e2[i];
             for (int64_t j = 0; j < n; j++) {
-                or_in b = load_in(j, lam, l0, r1, th1, w0, nw0, amp, path, abcd, shared_abcd, base);
+                or_in b = load_in(j, lam, l0, r1, th1, w0, nw0, amp, path, abcd, shared_abcd, base, order);
                 cplx Ej;
                 if (field_point_exact(&b, X, &Ej)) {
 #pragma omp atomic write
@@ -492,7 +572,7 @@ int oracle_eval(int64_t n, double lam, double l0, const double *r1, const double
                 int32_t nx, int32_t ny, double dx, double dy,
                 int64_t npix, const int32_t *pix_ix, const int32_t *pix_iy,
                 int model, double *out, const double *extra_point, double *out_extra) {
-    return oracle_eval_base(n, lam, l0, r1, th1, w0, nw0, amp, path, abcd, shared_abcd, NULL, 1e-10, origin,
+    return oracle_eval_base(n, lam, l0, r1, th1, w0, nw0, amp, path, abcd, shared_abcd, NULL, 1e-10, NULL, origin,
                             normal, xhint, nx, ny, dx, dy, npix, pix_ix, pix_iy, model, out, extra_point,
                             out_extra);
 }
@@ -507,7 +587,7 @@ int oracle_beamlet(double lam, const double *r1, const double *th1, double w0, d
                    const double *abcd, double z, double *out) {
     int rc = valid_inputs(1, lam, 0.0, r1, th1, &w0, 1, NULL, &W, abcd, 1, NULL, 1e-10);
     if (rc) return rc;
-    or_in b = load_in(0, lam, 0.0, r1, th1, &w0, 1, NULL, &W, abcd, 1, NULL);
+    or_in b = load_in(0, lam, 0.0, r1, th1, &w0, 1, NULL, &W, abcd, 1, NULL, NULL);
     or_prop P;
     rc = propagate(&b, z, &P);
     if (rc) return rc;

@@ -83,6 +83,8 @@ class Scene:
     # symplectic tolerance the differential (finite-difference) matrices get
     base: Optional[np.ndarray] = None
     sympl_tol: Optional[float] = None
+    # elegant Hermite-Gaussian orders [n,2] (m, n) in 0..2 per beamlet, or None (Gaussian)
+    order: Optional[np.ndarray] = None
 
     @property
     def n(self) -> int:
