@@ -143,6 +143,27 @@ int gbd_trace(gbd_ctx_t ctx, int32_t n_mirrors, const double *mirrors, double z_
 int gbd_beamlets_traced(gbd_ctx_t ctx, gbd_beamlets_t *out, int64_t n, double lambda, double l0, const double *r1,
                         const double *th1, const double *w0, int64_t n_w0, const double *amp, const double *path,
                         const double *abcd, const double *base, double sympl_tol);
+/* --- higher-order beamlets (Sec. 2.1: the Hermite-Gaussian solutions of the
+ * reduced Collins integral serve in beamlet decomposition like the
+ * fundamental one; Sec. 7.1: higher-order beams through a system) ---------
+ * As gbd_beamlets, plus order [n][2] (int32, host, required for n > 0): the
+ * orders (m, n), each in 0 ... 2 (else GBD_EINVAL), of elegant
+ * Hermite-Gaussian beamlets launched as
+ *   H_m(u_x) H_n(u_y) exp(-|u|^2) exp(-i k th1 . (r - r1)),  u = (r - r1) / w0,
+ * H the physicists' Hermite polynomials: the Gaussian beamlet's envelope
+ * differentiated m times along x and n times along y with respect to its
+ * centre (times w0^(m+n)), its tilt phase held.  Propagation commutes with
+ * that derivative, so on the detector the beamlet is its Gaussian field
+ * times a polynomial in the offset from the base ray.  Evaluation
+ * (gbd_eval, gbd_plan_eval) takes such beamlets on planes normal to the axis
+ * only (else GBD_EINVAL from the setup), in FP64 or in the mixed direct or
+ * separable form (a request for the stepped or rotor form resolves to the
+ * direct one; the separable form where no beamlet's factor has cross
+ * terms).  gbd_eval_point and gbd_eval_batch refuse beamlets with a nonzero
+ * order (GBD_EINVAL).  Orders all (0, 0) give the fundamental beamlets. */
+int gbd_beamlets_hg(gbd_ctx_t ctx, gbd_beamlets_t *out, int64_t n, double lambda, double l0, const double *r1,
+                    const double *th1, const double *w0, int64_t n_w0, const double *amp, const double *path,
+                    const double *abcd, int64_t n_abcd, const int32_t *order);
 void gbd_beamlets_free(gbd_beamlets_t b);
 
 /* --- detector plane (Sec. 3: the common evaluation plane) ----------------

@@ -24,7 +24,7 @@ __all__ = [
     "gbd_ctx_create", "gbd_beamlets", "gbd_plane", "gbd_eval", "gbd_plan_create", "gbd_plan_setup",
     "gbd_plan_eval", "gbd_plan_shape", "gbd_airy", "gbd_eval_batch", "gbd_eval_point", "gbd_autotune", "gbd_autotune_batch",
     "gbd_autotune_save", "gbd_autotune_load", "GBD_MLP_FP32", "GBD_MLP_BF16", "Mlp", "gbd_mlp_create", "beamlets_from_scene", "plane_from_scene",
-    "gbd_trace", "gbd_beamlets_traced",
+    "gbd_trace", "gbd_beamlets_traced", "gbd_beamlets_hg",
     "Context", "Beamlets", "Plane", "Plan",
 ]
 
@@ -73,6 +73,7 @@ def load_library():
         "gbd_beamlets_traced": (ctypes.c_int, [P, PP, I64, D, D, P, P, P, I64, P, P, P, P, D]),
         "gbd_last_error": (ctypes.c_char_p, []),
         "gbd_beamlets": (ctypes.c_int, [P, PP, I64, D, D, P, P, P, I64, P, P, P, I64]),
+        "gbd_beamlets_hg": (ctypes.c_int, [P, PP, I64, D, D, P, P, P, I64, P, P, P, I64, P]),
         "gbd_beamlets_free": (None, [P]),
         "gbd_plane": (ctypes.c_int, [P, PP, P, P, P, I32, I32, D, D]),
         "gbd_plane_free": (None, [P]),
@@ -191,6 +192,19 @@ def gbd_beamlets(ctx: Context, n: int, lam: float, l0: float, r1, th1=None, w0=N
     return Beamlets(h, int(n))
 
 
+def gbd_beamlets_hg(ctx: Context, n: int, lam: float, l0: float, r1, th1, w0, amp, path, abcd, order) -> Beamlets:
+    """Elegant Hermite-Gaussian beamlets of orders order [n,2] in 0..2 (see gbd.h)."""
+    r1, th1, w0, amp, path, abcd = map(_f64, (r1, th1, w0, amp, path, abcd))
+    w0 = np.atleast_1d(w0) if w0 is not None else None
+    abcd = None if abcd is None else abcd.reshape(-1, 16)
+    order = None if order is None else np.ascontiguousarray(np.asarray(order).reshape(-1, 2), dtype=np.int32)
+    h = ctypes.c_void_p()
+    _check(load_library().gbd_beamlets_hg(ctx.handle, ctypes.byref(h), int(n), float(lam), float(l0), _p(r1),
+                                          _p(th1), _p(w0), 0 if w0 is None else w0.size, _p(amp), _p(path),
+                                          _p(abcd), 0 if abcd is None else abcd.shape[0], _p(order)))
+    return Beamlets(h, int(n))
+
+
 def gbd_plane(ctx: Context, origin, normal, xhint, nx: int, ny: int, dx: float, dy: float) -> Plane:
     o, n, x = _f64(origin), _f64(normal), _f64(xhint)
     h = ctypes.c_void_p()
@@ -228,6 +242,10 @@ def gbd_beamlets_traced(ctx: Context, n: int, lam: float, l0: float, r1, th1, w0
 
 
 def beamlets_from_scene(ctx: Context, s) -> Beamlets:
+    if getattr(s, "order", None) is not None:
+        if getattr(s, "base", None) is not None:
+            raise ValueError("traced inputs of higher-order beamlets are not supported")
+        return gbd_beamlets_hg(ctx, s.n, s.lam, s.l0, s.r1, s.th1, s.w0, s.amp, s.path, s.abcd, s.order)
     if getattr(s, "base", None) is not None:
         return gbd_beamlets_traced(ctx, s.n, s.lam, s.l0, s.r1, s.th1, s.w0, s.amp, s.path, s.abcd, s.base,
                                    s.sympl_tol or 1e-7)

@@ -55,6 +55,7 @@ struct gbd_beamlets_s {
     gbd_ctx_s *ctx;
     BeamletsDev dev;
     void *mem;
+    bool higher_order;  // some beamlet has a nonzero Hermite-Gaussian order
 };
 
 struct gbd_plane_s {
@@ -67,9 +68,11 @@ struct gbd_plan_s {
     int64_t n;
     PlaneGeom pl;
     bool ready;
-    uint32_t flags;  // FLAG_STEEP / FLAG_CROSS of the last setup (which mixed forms apply)
+    uint32_t flags;  // FLAG_STEEP / FLAG_CROSS / FLAG_HG of the last setup (which mixed forms apply)
     Rec64 *r64;
     Rec32 *r32;
+    RecHG64 *h64;  // Hermite-Gaussian factors, allocated at the first setup of higher-order beamlets
+    RecHG32 *h32;
     uint32_t *status_dev;
     uint32_t *status_host;  // pinned
     void *scratch;
@@ -186,7 +189,9 @@ struct Shape {
 // choice among the others.
 int pick_form(int precision, uint32_t flags, const gbd_eval_opts *o, bool allow_sep = true) {
     if (precision != GBD_MIXED) return 0;
-    const bool steep = (flags & FLAG_STEEP) != 0;
+    // higher-order beamlets: direct or separable form (their factor is not
+    // carried by the stepped and rotor recurrences)
+    const bool steep = (flags & (FLAG_STEEP | FLAG_HG)) != 0;
     const bool sep = allow_sep && !(flags & FLAG_CROSS);
     const int v = o ? o->variant : 0;
     if (v == 1) return 0;
@@ -334,12 +339,14 @@ int plan_eval_impl(gbd_ctx_s *ctx, gbd_plan_s *plan, int precision, void *out, i
         }
     }
     const void *rec = precision == GBD_FP64 ? (const void *)plan->r64 : (const void *)plan->r32;
+    const bool hg = (plan->flags & FLAG_HG) != 0;
+    const void *hrec = !hg ? nullptr : precision == GBD_FP64 ? (const void *)plan->h64 : (const void *)plan->h32;
     if (s.form == 3)
-        HIP_TRY(launch_eval_sep(g, plan->r32, static_cast<float4 *>(plan->scratch), static_cast<float2 *>(out),
-                                ctx->stream),
+        HIP_TRY(launch_eval_sep(g, plan->r32, static_cast<const RecHG32 *>(hrec), static_cast<float4 *>(plan->scratch),
+                                static_cast<float2 *>(out), ctx->stream),
                 "eval kernel launch");
     else
-        HIP_TRY(launch_eval(precision, s.rows, s.waves, s.form, g, rec, plan->scratch, out, ctx->stream),
+        HIP_TRY(launch_eval(precision, s.rows, s.waves, s.form, g, rec, hrec, plan->scratch, out, ctx->stream),
                 "eval kernel launch");
     if (g.nseg > 1) HIP_TRY(launch_reduce(precision, g, plan->scratch, out, ctx->stream), "reduce kernel launch");
     return GBD_OK;
@@ -354,12 +361,19 @@ int plan_setup_impl(gbd_ctx_s *ctx, gbd_plan_s *plan, gbd_beamlets_s *b, gbd_pla
     plan->flags = 0;
     plan->n = b->dev.n;
     plan->pl = p->g;
+    if (b->dev.order && (!plan->h64 || !plan->h32)) {
+        const size_t cap = (size_t)std::max<int64_t>(1, plan->capacity);
+        if (!plan->h64) HIP_TRY(hipMalloc(&plan->h64, cap * sizeof(RecHG64)), "hipMalloc(Hermite-Gaussian records)");
+        if (!plan->h32) HIP_TRY(hipMalloc(&plan->h32, cap * sizeof(RecHG32)), "hipMalloc(Hermite-Gaussian records)");
+    }
     if (b->dev.n > 0) {
         // the axial term l0 / lambda is common to every beamlet: reduce it once
         const double g0 = b->dev.l0 / b->dev.lam;
         const double gturns = g0 - nearbyint(g0);
         HIP_TRY(hipMemsetAsync(plan->status_dev, 0, sizeof(uint32_t), ctx->stream), "hipMemsetAsync(status)");
-        HIP_TRY(launch_setup(b->dev, p->g, gturns, plan->r64, plan->r32, plan->status_dev, ctx->stream),
+        const bool hg = b->dev.order != nullptr;
+        HIP_TRY(launch_setup(b->dev, p->g, gturns, plan->r64, plan->r32, hg ? plan->h64 : nullptr,
+                             hg ? plan->h32 : nullptr, plan->status_dev, ctx->stream),
                 "setup kernel launch");
         HIP_TRY(hipMemcpyAsync(plan->status_host, plan->status_dev, sizeof(uint32_t), hipMemcpyDeviceToHost,
                                ctx->stream),
@@ -370,7 +384,9 @@ int plan_setup_impl(gbd_ctx_s *ctx, gbd_plan_s *plan, gbd_beamlets_s *b, gbd_pla
         if (st & FLAG_BRANCH)
             return fail(GBD_EBRANCH, "an eigenvalue of A + B Q1^-1 lies off the principal branch (inverting system)");
         if (st & FLAG_NONFINITE) return fail(GBD_EINVAL, "non-finite beamlet parameters after propagation");
-        plan->flags = st & (FLAG_STEEP | FLAG_CROSS);
+        if (st & FLAG_HG_TILT)
+            return fail(GBD_EINVAL, "higher-order beamlets need a detector plane normal to the axis");
+        plan->flags = st & (FLAG_STEEP | FLAG_CROSS | FLAG_HG);
     }
     plan->ready = true;
     return GBD_OK;
@@ -380,6 +396,8 @@ void plan_destroy(gbd_plan_s *plan) {
     if (!plan) return;
     if (plan->r64) (void)hipFree(plan->r64);
     if (plan->r32) (void)hipFree(plan->r32);
+    if (plan->h64) (void)hipFree(plan->h64);
+    if (plan->h32) (void)hipFree(plan->h32);
     if (plan->status_dev) (void)hipFree(plan->status_dev);
     if (plan->status_host) (void)hipHostFree(plan->status_host);
     if (plan->scratch) (void)hipFree(plan->scratch);
@@ -464,7 +482,8 @@ void gbd_ctx_destroy(gbd_ctx_t ctx) {
 
 static int beamlets_impl(gbd_ctx_t ctx, gbd_beamlets_t *out, int64_t n, double lambda, double l0, const double *r1,
                   const double *th1, const double *w0, int64_t n_w0, const double *amp, const double *path,
-                  const double *abcd, int64_t n_abcd, const double *base, double sympl_tol) {
+                  const double *abcd, int64_t n_abcd, const double *base, double sympl_tol,
+                  const int32_t *order = nullptr) {
     if (!ctx || !out) return fail(GBD_EINVAL, "ctx/out is NULL");
     if (!(sympl_tol > 0.0 && sympl_tol <= 1e-3)) return fail(GBD_EINVAL, "sympl_tol must be in (0, 1e-3]");
     if (n < 0) return fail(GBD_EINVAL, "n < 0");
@@ -482,18 +501,28 @@ static int beamlets_impl(gbd_ctx_t ctx, gbd_beamlets_t *out, int64_t n, double l
         for (int64_t i = 0; i < n_abcd; i++)
             if (!(base ? symplectic_balanced(abcd + 16 * i, sympl_tol) : symplectic(abcd + 16 * i, sympl_tol)))
                 return fail(GBD_ENOTSYMPLECTIC, "abcd[%lld] is not symplectic", (long long)i);
+        if (order)
+            for (int64_t i = 0; i < 2 * n; i++)
+                if (order[i] < 0 || order[i] > 2)
+                    return fail(GBD_EINVAL, "order[%lld][%lld] = %d is outside 0 ... 2", (long long)(i / 2),
+                                (long long)(i % 2), order[i]);
     } else {
         n_w0 = 1;
         n_abcd = 1;
         base = nullptr;
+        order = nullptr;
     }
+    bool higher = false;
+    if (order)
+        for (int64_t i = 0; i < 2 * n && !higher; i++) higher = order[i] != 0;
     int rc = ensure_device(ctx);
     if (rc) return rc;
     // one device block: r1, th1, amp [n][2]; w0 [n_w0]; path [n]; abcd [n_abcd][16]; base [n][5]
     const size_t nn = (size_t)std::max<int64_t>(n, 1);
     const size_t off_r1 = 0, off_th1 = off_r1 + 2 * nn, off_amp = off_th1 + 2 * nn, off_w0 = off_amp + 2 * nn,
                  off_path = off_w0 + (size_t)n_w0, off_abcd = off_path + nn, off_base = off_abcd + 16 * (size_t)n_abcd,
-                 total = off_base + (base ? 5 * nn : 0);
+                 off_order = off_base + (base ? 5 * nn : 0), total = off_order + (order ? nn : 0);
+    // orders: [n][2] int32 packed into the trailing n doubles
     std::vector<double> host(total, 0.0);
     if (n > 0) {
         memcpy(&host[off_r1], r1, 2 * n * sizeof(double));
@@ -506,6 +535,7 @@ static int beamlets_impl(gbd_ctx_t ctx, gbd_beamlets_t *out, int64_t n, double l
         if (path) memcpy(&host[off_path], path, n * sizeof(double));
         memcpy(&host[off_abcd], abcd, 16 * n_abcd * sizeof(double));
         if (base) memcpy(&host[off_base], base, 5 * n * sizeof(double));
+        if (order) memcpy(&host[off_order], order, 2 * n * sizeof(int32_t));
     } else {
         host[off_w0] = 1.0;
         for (int i = 0; i < 4; i++) host[off_abcd + 5 * i] = 1.0;
@@ -538,6 +568,8 @@ static int beamlets_impl(gbd_ctx_t ctx, gbd_beamlets_t *out, int64_t n, double l
     b->dev.path = d + off_path;
     b->dev.abcd = d + off_abcd;
     b->dev.base = base ? d + off_base : nullptr;
+    b->dev.order = order ? reinterpret_cast<const int32_t *>(d + off_order) : nullptr;
+    b->higher_order = higher;
     *out = b;
     return GBD_OK;
 }
@@ -553,6 +585,13 @@ int gbd_beamlets_traced(gbd_ctx_t ctx, gbd_beamlets_t *out, int64_t n, double la
                         const double *abcd, const double *base, double sympl_tol) {
     if (n > 0 && !base) return fail(GBD_EINVAL, "base is NULL");
     return beamlets_impl(ctx, out, n, lambda, l0, r1, th1, w0, n_w0, amp, path, abcd, n, base, sympl_tol);
+}
+
+int gbd_beamlets_hg(gbd_ctx_t ctx, gbd_beamlets_t *out, int64_t n, double lambda, double l0, const double *r1,
+                    const double *th1, const double *w0, int64_t n_w0, const double *amp, const double *path,
+                    const double *abcd, int64_t n_abcd, const int32_t *order) {
+    if (n > 0 && !order) return fail(GBD_EINVAL, "order is NULL");
+    return beamlets_impl(ctx, out, n, lambda, l0, r1, th1, w0, n_w0, amp, path, abcd, n_abcd, nullptr, 1e-10, order);
 }
 
 int gbd_trace(gbd_ctx_t ctx, int32_t n_mirrors, const double *mirrors, double z_in, double z_out, double l0,
@@ -793,6 +832,7 @@ int gbd_autotune_load(gbd_ctx_t ctx, const char *path) {
 
 int gbd_eval_point(gbd_ctx_t ctx, gbd_beamlets_t b, gbd_plane_t p, void *field_out, int64_t out_bytes) {
     if (!ctx || !b || !p) return fail(GBD_EINVAL, "NULL argument");
+    if (b->higher_order) return fail(GBD_EINVAL, "point evaluation takes fundamental Gaussian beamlets only");
     const int64_t M = (int64_t)p->g.nx * p->g.ny;
     if (M == 0) return GBD_OK;
     if (!field_out) return fail(GBD_EINVAL, "field_out is NULL");
@@ -855,6 +895,8 @@ int gbd_eval_batch(gbd_ctx_t ctx, int32_t n_inst, const gbd_beamlets_t *bs, cons
     int64_t pairs = 0;
     for (int32_t i = 0; i < n_inst; i++) {
         if (!bs[i] || !ps[i]) return fail(GBD_EINVAL, "instance %d has a NULL handle", i);
+        if (bs[i]->higher_order)
+            return fail(GBD_EINVAL, "instance %d: the batched sweep takes fundamental Gaussian beamlets only", i);
         pairs += bs[i]->dev.n * ((int64_t)ps[i]->g.nx * ps[i]->g.ny);
     }
     if (!(opts && (opts->rows_per_lane || opts->waves))) {

@@ -57,8 +57,11 @@ __device__ inline double il2_dev() { return 1.4426950408889634074; }  // 1 / ln 
 
 // One beamlet propagated onto the plane; writes its phasor records (either
 // pointer may be null) and returns FLAG_* bits (0 = fine).
+// Higher-order beamlets: h64 / h32 (either may be null) receive the
+// Hermite-Gaussian factor's coefficients of every beamlet (orders (0, 0)
+// give the factor 1).
 __device__ inline uint32_t setup_one(const BeamletsDev &b, const PlaneGeom &pl, double gturns, int64_t j,
-                                     Rec64 *r64, Rec32 *r32) {
+                                     Rec64 *r64, Rec32 *r32, RecHG64 *h64 = nullptr, RecHG32 *h32 = nullptr) {
     const double *M = b.abcd + (b.n_abcd == 1 ? 0 : 16 * j);
     double A[2][2], B[2][2], C[2][2], D[2][2];
 #pragma unroll
@@ -96,6 +99,7 @@ __device__ inline uint32_t setup_one(const BeamletsDev &b, const PlaneGeom &pl, 
     const double dl = sqrt(th[0] * th[0] + th[1] * th[1] + 1.0);
     Rec64 o64 = {};
     Rec32 o32 = {};
+    RecHG64 oh = {};
     uint32_t flag = 0;
     if (!(fabs(nd) > 1e-6 * dl)) {
         flag |= FLAG_PARALLEL;
@@ -192,6 +196,73 @@ __device__ inline uint32_t setup_one(const BeamletsDev &b, const PlaneGeom &pl, 
         bool fin = isfinite(arho) && isfinite(brho) && isfinite(ag.re) && isfinite(ag.im);
 #pragma unroll
         for (int i = 0; i < 6; i++) fin = fin && isfinite(p[i]) && (i == 0 || isfinite(l[i]));
+        if (h64 || h32) {
+            // elegant Hermite-Gaussian factor: with A' = A + z C, the
+            // derivatives of the envelope's log E with respect to the input
+            // centre are L w (L = -i k (C^T - A'^T Q)) and the constant
+            // H = i k (C^T A' - A'^T Q A'); on the plane w = Pm d, so
+            // g = w0 L Pm d and h = w0^2 H
+            const int hm = b.order ? b.order[2 * j] : 0, hn = b.order ? b.order[2 * j + 1] : 0;
+            const double k = 2.0 * kPi / lam, w2 = w0 * w0;
+            double Ap[2][2];
+#pragma unroll
+            for (int r = 0; r < 2; r++)
+#pragma unroll
+                for (int c = 0; c < 2; c++) Ap[r][c] = A[r][c] + z * C[r][c];
+            cd AQ[2][2], Lm[2][2], Hm[2][2];  // A'^T Q, L, H
+#pragma unroll
+            for (int r = 0; r < 2; r++)
+#pragma unroll
+                for (int c = 0; c < 2; c++) AQ[r][c] = add(scl(Q[0][c], Ap[0][r]), scl(Q[1][c], Ap[1][r]));
+#pragma unroll
+            for (int r = 0; r < 2; r++)
+#pragma unroll
+                for (int c = 0; c < 2; c++) {
+                    const cd v = sub(mk(C[c][r], 0.0), AQ[r][c]);
+                    Lm[r][c] = mk(k * v.im, -k * v.re);
+                    const cd u = sub(mk(C[0][r] * Ap[0][c] + C[1][r] * Ap[1][c], 0.0),
+                                     add(scl(AQ[r][0], Ap[0][c]), scl(AQ[r][1], Ap[1][c])));
+                    Hm[r][c] = mk(-k * u.im, k * u.re);
+                }
+            cd Gh[2][2];
+#pragma unroll
+            for (int r = 0; r < 2; r++)
+#pragma unroll
+                for (int c = 0; c < 2; c++) {
+                    Gh[r][c] = scl(add(scl(Lm[r][0], Pm[0][c]), scl(Lm[r][1], Pm[1][c])), w0);
+                    oh.g[r][c][0] = Gh[r][c].re;
+                    oh.g[r][c][1] = Gh[r][c].im;
+                }
+            const cd hxx = scl(Hm[0][0], w2), hyy = scl(Hm[1][1], w2);
+            const cd hxy = scl(add(Hm[0][1], Hm[1][0]), 0.5 * w2);
+            oh.cx0[0] = hm == 0 ? 1.0 : hm == 2 ? hxx.re : 0.0;
+            oh.cx0[1] = hm == 2 ? hxx.im : 0.0;
+            oh.cy0[0] = hn == 0 ? 1.0 : hn == 2 ? hyy.re : 0.0;
+            oh.cy0[1] = hn == 2 ? hyy.im : 0.0;
+            oh.cx1 = hm == 1 ? 1.0 : 0.0;
+            oh.cx2 = hm == 2 ? 1.0 : 0.0;
+            oh.cy1 = hn == 1 ? 1.0 : 0.0;
+            oh.cy2 = hn == 2 ? 1.0 : 0.0;
+            oh.ex0 = hm == 2 ? 0.0 : 1.0;
+            oh.ex1 = hm == 2 ? 1.0 : 0.0;
+            oh.ey0 = hn == 2 ? 0.0 : 1.0;
+            oh.ey1 = hn == 2 ? 1.0 : 0.0;
+            const cd k1 = scl(hxy, (double)(hm * hn));
+            const cd k0 = (hm == 2 && hn == 2) ? scl(mul(hxy, hxy), 2.0) : mk(0.0, 0.0);
+            oh.k1[0] = k1.re;
+            oh.k1[1] = k1.im;
+            oh.k0[0] = k0.re;
+            oh.k0[1] = k0.im;
+            if (hm | hn) {
+                flag |= FLAG_HG;
+                if (ez[0] != 0.0 || ez[1] != 0.0) flag |= FLAG_HG_TILT;
+                const bool off = (hm && (Gh[0][1].re != 0.0 || Gh[0][1].im != 0.0)) ||
+                                 (hn && (Gh[1][0].re != 0.0 || Gh[1][0].im != 0.0));
+                if (off || k1.re != 0.0 || k1.im != 0.0) flag |= FLAG_CROSS;
+            }
+            const double *hv = &oh.g[0][0][0];
+            for (int i = 0; i < (int)(sizeof(RecHG64) / sizeof(double)); i++) fin = fin && isfinite(hv[i]);
+        }
         if (!fin) flag |= FLAG_NONFINITE;
         if (fabs(l[5]) * il2_dev() * pl.dy * pl.dy > kStepCurvature) flag |= FLAG_STEEP;
         if (p[4] != 0.0 || l[4] != 0.0) flag |= FLAG_CROSS;
@@ -238,7 +309,46 @@ __device__ inline uint32_t setup_one(const BeamletsDev &b, const PlaneGeom &pl, 
     }
     if (r64) r64[j] = o64;
     if (r32) r32[j] = o32;
+    if (h64) h64[j] = oh;
+    if (h32) {
+        RecHG32 o;
+        const double *src = &oh.g[0][0][0];
+        float *dst = &o.g[0][0][0];
+#pragma unroll
+        for (int i = 0; i < (int)(sizeof(RecHG32) / sizeof(float)); i++) dst[i] = (float)src[i];
+        h32[j] = o;
+    }
     return flag;
+}
+
+// Hermite-Gaussian factor P (the polynomial of RecHG64) at the pixel offset
+// (da, db), FP64.
+__device__ inline cd hg_factor(const RecHG64 &h, double da, double db) {
+    const cd gx = mk(h.g[0][0][0] * da + h.g[0][1][0] * db, h.g[0][0][1] * da + h.g[0][1][1] * db);
+    const cd gy = mk(h.g[1][0][0] * da + h.g[1][1][0] * db, h.g[1][0][1] * da + h.g[1][1][1] * db);
+    const cd px = add(mk(h.cx0[0], h.cx0[1]), mul(gx, mk(h.cx1 + h.cx2 * gx.re, h.cx2 * gx.im)));
+    const cd py = add(mk(h.cy0[0], h.cy0[1]), mul(gy, mk(h.cy1 + h.cy2 * gy.re, h.cy2 * gy.im)));
+    const cd ax = mk(h.ex0 + h.ex1 * gx.re, h.ex1 * gx.im);
+    const cd ay = mk(h.ey0 + h.ey1 * gy.re, h.ey1 * gy.im);
+    return add(add(mul(px, py), mul(mk(h.k1[0], h.k1[1]), mul(ax, ay))), mk(h.k0[0], h.k0[1]));
+}
+
+// The same factor in FP32 with the x part of g = G d already formed for the
+// lane's column (gxa = G[.][0] da): only the row offset db varies.
+__device__ inline float2 hg_factor32(const RecHG32 &h, float gxa_r, float gxa_i, float gya_r, float gya_i, float db) {
+    const float gxr = fmaf(h.g[0][1][0], db, gxa_r), gxi = fmaf(h.g[0][1][1], db, gxa_i);
+    const float gyr = fmaf(h.g[1][1][0], db, gya_r), gyi = fmaf(h.g[1][1][1], db, gya_i);
+    // Px = cx0 + gx (cx1 + cx2 gx), likewise Py
+    const float txr = fmaf(h.cx2, gxr, h.cx1), txi = h.cx2 * gxi;
+    const float pxr = h.cx0[0] + (gxr * txr - gxi * txi), pxi = h.cx0[1] + (gxr * txi + gxi * txr);
+    const float tyr = fmaf(h.cy2, gyr, h.cy1), tyi = h.cy2 * gyi;
+    const float pyr = h.cy0[0] + (gyr * tyr - gyi * tyi), pyi = h.cy0[1] + (gyr * tyi + gyi * tyr);
+    const float axr = fmaf(h.ex1, gxr, h.ex0), axi = h.ex1 * gxi;
+    const float ayr = fmaf(h.ey1, gyr, h.ey0), ayi = h.ey1 * gyi;
+    const float cr = axr * ayr - axi * ayi, ci = axr * ayi + axi * ayr;
+    const float re = (pxr * pyr - pxi * pyi) + (h.k1[0] * cr - h.k1[1] * ci) + h.k0[0];
+    const float im = (pxr * pyi + pxi * pyr) + (h.k1[0] * ci + h.k1[1] * cr) + h.k0[1];
+    return make_float2(re, im);
 }
 
 __device__ inline void kahan(float &s, float &c, float x) {
@@ -258,10 +368,13 @@ constexpr int kMixedTile = 128;  // Rec32 records staged per LDS tile (30 KiB)
 // take revolutions.  Per-tile FP32 sums are folded into Kahan-compensated
 // (s, c) accumulators, value = s - c.  All threads of the workgroup must call
 // this together (it synchronises on the LDS tile).
-template <int ROWS, int NT>
+// With HG, each beamlet's phasor is multiplied by its Hermite-Gaussian
+// factor (records hg, staged in htile beside the phasor records).
+template <int ROWS, int NT, bool HG = false>
 __device__ inline void mixed_accumulate(Rec32 *tile, const Rec32 *__restrict__ rec, int64_t jb, int64_t je,
                                         double a, double b0, double dy, float (&s_re)[ROWS], float (&s_im)[ROWS],
-                                        float (&c_re)[ROWS], float (&c_im)[ROWS]) {
+                                        float (&c_re)[ROWS], float (&c_im)[ROWS], RecHG32 *htile = nullptr,
+                                        const RecHG32 *__restrict__ hg = nullptr) {
     const double dy2 = dy * dy;
     const float af = (float)a, b0f = (float)b0, dyf = (float)dy;
     float acc_re[ROWS], acc_im[ROWS];
@@ -274,6 +387,11 @@ __device__ inline void mixed_accumulate(Rec32 *tile, const Rec32 *__restrict__ r
             const float4 *src = reinterpret_cast<const float4 *>(rec + j0);
             float4 *dst = reinterpret_cast<float4 *>(tile);
             for (int i = threadIdx.x; i < cnt * kRec32Vec4; i += NT) dst[i] = src[i];
+            if constexpr (HG) {
+                const float4 *hs = reinterpret_cast<const float4 *>(hg + j0);
+                float4 *hd = reinterpret_cast<float4 *>(htile);
+                for (int i = threadIdx.x; i < cnt * (int)(sizeof(RecHG32) / 16); i += NT) hd[i] = hs[i];
+            }
         }
         __syncthreads();
         for (int jj = 0; jj < cnt; jj++) {
@@ -288,6 +406,14 @@ __device__ inline void mixed_accumulate(Rec32 *tile, const Rec32 *__restrict__ r
             const float daf = af - r.arho_f, dbf0 = b0f - r.brho_f;
             const float qf = r.m[2] + r.m[4] * daf;
             const float Uc = r.m[0] + daf * (r.m[1] + r.m[3] * daf);
+            float gxa_r = 0.0f, gxa_i = 0.0f, gya_r = 0.0f, gya_i = 0.0f;
+            if constexpr (HG) {
+                const RecHG32 &h = htile[jj];
+                gxa_r = h.g[0][0][0] * daf;
+                gxa_i = h.g[0][0][1] * daf;
+                gya_r = h.g[1][0][0] * daf;
+                gya_i = h.g[1][0][1] * daf;
+            }
 #pragma unroll
             for (int k = 0; k < ROWS; k++) {
                 const double th = T0 + (double)k * (T1 + (double)k * T2);
@@ -295,8 +421,15 @@ __device__ inline void mixed_accumulate(Rec32 *tile, const Rec32 *__restrict__ r
                 const float dbf = fmaf((float)k, dyf, dbf0);
                 const float L = Uc + dbf * (qf + r.m[5] * dbf);
                 const float m = __builtin_amdgcn_exp2f(L);
-                acc_re[k] = fmaf(m, __builtin_amdgcn_cosf(ph), acc_re[k]);
-                acc_im[k] = fmaf(m, __builtin_amdgcn_sinf(ph), acc_im[k]);
+                if constexpr (HG) {
+                    const float cr = m * __builtin_amdgcn_cosf(ph), ci = m * __builtin_amdgcn_sinf(ph);
+                    const float2 P = hg_factor32(htile[jj], gxa_r, gxa_i, gya_r, gya_i, dbf);
+                    acc_re[k] += cr * P.x - ci * P.y;
+                    acc_im[k] += cr * P.y + ci * P.x;
+                } else {
+                    acc_re[k] = fmaf(m, __builtin_amdgcn_cosf(ph), acc_re[k]);
+                    acc_im[k] = fmaf(m, __builtin_amdgcn_sinf(ph), acc_im[k]);
+                }
             }
         }
 #pragma unroll

@@ -28,6 +28,7 @@ struct BeamletsDev {
     const double *abcd;  // [n_abcd][16]
     const double *base;  // [n][5] traced base ray at the output plane (x, y, l, m,
                          // optical path - l0), or null: the ab/cd laws
+    const int32_t *order;  // [n][2] elegant Hermite-Gaussian orders (m, n) in 0..2, or null
 };
 
 // Per-beamlet phasor on the plane, about the base-ray hit point (a_rho, b_rho):
@@ -57,17 +58,52 @@ struct alignas(16) Rec32 {
 static_assert(sizeof(Rec32) == 240, "Rec32 layout");
 constexpr int kRec32Vec4 = sizeof(Rec32) / 16;
 
+// Elegant Hermite-Gaussian factor of a higher-order beamlet on a plane
+// normal to the axis, as a polynomial in the pixel offset d = (da, db) from
+// the base-ray hit point:
+//   g = G d  (complex 2 x 2; w0 times the derivative of log E with respect
+//            to the input centre, linear in the offset),
+//   P = Px(gx) Py(gy) + k1 ax ay + k0,
+//   Px = cx0 + gx (cx1 + cx2 gx),  ax = ex0 + ex1 gx  (likewise y),
+// with the coefficients chosen by the orders (m, n): for m = 0, 1, 2,
+// (cx0, cx1, cx2) = (1, 0, 0), (0, 1, 0), (hxx, 0, 1) and (ex0, ex1) = (1, 0)
+// or (0, 1) for m = 2; k1 = m n hxy and k0 = 2 hxy^2 for m = n = 2, else 0;
+// h = w0^2 times the constant second derivative.  The beamlet's field is its
+// Gaussian phasor times P.
+struct alignas(16) RecHG64 {
+    double g[2][2][2];  // G[r][c] (re, im)
+    double cx0[2], cy0[2];
+    double cx1, cx2, cy1, cy2;
+    double k1[2], k0[2];
+    double ex0, ex1, ey0, ey1;
+};
+static_assert(sizeof(RecHG64) == 192, "RecHG64 layout");
+struct alignas(16) RecHG32 {
+    float g[2][2][2];
+    float cx0[2], cy0[2];
+    float cx1, cx2, cy1, cy2;
+    float k1[2], k0[2];
+    float ex0, ex1, ey0, ey1;
+};
+static_assert(sizeof(RecHG32) == 96, "RecHG32 layout");
+
 enum : uint32_t {
     FLAG_PARALLEL = 1u,
     FLAG_BRANCH = 2u,
     FLAG_NONFINITE = 4u,
-    FLAG_ERRORS = 7u,
+    // a higher-order beamlet on a plane tilted against the axis, where its
+    // plane-evaluation field is not the exact paraxial one
+    FLAG_HG_TILT = 8u,
+    FLAG_ERRORS = 15u,
     // not an error: the log2-amplitude curvature along a column exceeds
     // kStepCurvature per row^2, so the amplitude recurrence is not used
     FLAG_STEEP = 16u,
     // not an error: the phasor has a cross term (p4 or l4 nonzero), so the
     // plane's two axes do not separate
     FLAG_CROSS = 32u,
+    // not an error: some beamlet is of higher order, so the evaluation
+    // multiplies its Hermite-Gaussian factor in (direct and separable forms)
+    FLAG_HG = 64u,
 };
 
 // largest |d^2 log2(amplitude) / d row^2| / 2 for which the mixed kernel may
@@ -194,14 +230,16 @@ hipError_t launch_mlp_adamw(float *p, const float *g, float *m, float *v, int64_
                             float eps, float wd, float c1, float c2, hipStream_t s);
 
 hipError_t launch_setup(const BeamletsDev &b, const PlaneGeom &pl, double global_turns, Rec64 *r64,
-                        Rec32 *r32, uint32_t *status, hipStream_t s);
+                        Rec32 *r32, RecHG64 *h64, RecHG32 *h32, uint32_t *status, hipStream_t s);
 
 // Mixed precision only, form = 0 direct: per-pixel FP64 phase and exp2;
 // 1 stepped: phase stepped in FP32 from an FP64 anchor and amplitude stepped
 // by multiplication along each lane's column; 2 rotor: each lane's column
 // factored as anchor x rho^k x sigma^(k^2), no per-pixel transcendental.
+// hg: RecHG64 / RecHG32 records of higher-order beamlets (direct and FP64
+// forms only), or null.
 hipError_t launch_eval(int precision, int rows, int waves, int form, const EvalGeom &g, const void *rec,
-                       void *partial, void *out, hipStream_t s);
+                       const void *hg, void *partial, void *out, hipStream_t s);
 
 hipError_t launch_reduce(int precision, const EvalGeom &g, const void *partial, void *out, hipStream_t s);
 
@@ -209,6 +247,8 @@ hipError_t launch_reduce(int precision, const EvalGeom &g, const void *partial, 
 // wavefronts, each wavefront a 64 x 64 pixel tile; partials as float4 (re, im, 0, 0).
 constexpr int kSepWavesX = 2, kSepWavesY = 2;
 constexpr int kSepTile = 64;
-hipError_t launch_eval_sep(const EvalGeom &g, const Rec32 *rec, float4 *partial, float2 *out, hipStream_t s);
+// hg: higher-order factors without cross terms (k1 = k0 = 0, G diagonal), or null.
+hipError_t launch_eval_sep(const EvalGeom &g, const Rec32 *rec, const RecHG32 *hg, float4 *partial, float2 *out,
+                           hipStream_t s);
 
 }  // namespace gbd

@@ -22,22 +22,27 @@ using namespace dev;
 
 __global__ void __launch_bounds__(256) setup_kernel(BeamletsDev b, PlaneGeom pl, double gturns,
                                                     Rec64 *__restrict__ r64, Rec32 *__restrict__ r32,
+                                                    RecHG64 *__restrict__ h64, RecHG32 *__restrict__ h32,
                                                     uint32_t *__restrict__ status) {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= b.n) return;
-    const uint32_t flag = setup_one(b, pl, gturns, j, r64, r32);
+    const uint32_t flag = setup_one(b, pl, gturns, j, r64, r32, h64, h32);
     if (flag) atomicOr(status, flag);
 }
 
 // Mixed form.  Each lane owns ROWS pixels of one detector column; a
 // wavefront spans 64 consecutive columns (coalesced stores); WAVES
 // wavefronts stack in y; the workgroup sums one segment of beamlets.
-// FORM: 0 direct, 1 stepped, 2 rotor accumulation.
-template <int ROWS, int WAVES, int FORM>
+// FORM: 0 direct, 1 stepped, 2 rotor accumulation; HG (direct form only):
+// higher-order beamlets, records hg.
+template <int ROWS, int WAVES, int FORM, bool HG = false>
 __global__ void __launch_bounds__(64 * WAVES) eval_mixed_kernel(EvalGeom g, const Rec32 *__restrict__ rec,
                                                                 float4 *__restrict__ partial,
-                                                                float2 *__restrict__ out) {
+                                                                float2 *__restrict__ out,
+                                                                const RecHG32 *__restrict__ hg = nullptr) {
+    static_assert(!HG || FORM == 0, "higher-order beamlets: direct form only");
     __shared__ Rec32 tile[kMixedTile];
+    __shared__ RecHG32 htile[HG ? kMixedTile : 1];
     const int w = work_item(blockIdx.x, gridDim.x);
     if (w >= g.work) return;
     const int tiles = g.tiles_x * g.tiles_y;
@@ -60,7 +65,7 @@ __global__ void __launch_bounds__(64 * WAVES) eval_mixed_kernel(EvalGeom g, cons
     else if constexpr (FORM == 1)
         mixed_accumulate_step<ROWS, 64 * WAVES>(tile, rec, jb, je, a, b0, g.dy, s_re, s_im, c_re, c_im);
     else
-        mixed_accumulate<ROWS, 64 * WAVES>(tile, rec, jb, je, a, b0, g.dy, s_re, s_im, c_re, c_im);
+        mixed_accumulate<ROWS, 64 * WAVES, HG>(tile, rec, jb, je, a, b0, g.dy, s_re, s_im, c_re, c_im, htile, hg);
 
     if (ix >= g.nx) return;
     const int64_t M = (int64_t)g.nx * g.ny;
@@ -78,13 +83,16 @@ __global__ void __launch_bounds__(64 * WAVES) eval_mixed_kernel(EvalGeom g, cons
 }
 
 // FP64 form: the same phasor in FP64 throughout (sincospi and exp from the
-// device math library), plain FP64 accumulation.
-template <int ROWS, int WAVES>
+// device math library), plain FP64 accumulation; HG: times each beamlet's
+// Hermite-Gaussian factor.
+template <int ROWS, int WAVES, bool HG = false>
 __global__ void __launch_bounds__(64 * WAVES) eval_fp64_kernel(EvalGeom g, const Rec64 *__restrict__ rec,
                                                                double2 *__restrict__ partial,
-                                                               double2 *__restrict__ out) {
-    constexpr int CH = 64;  // records per LDS tile (8 KiB)
+                                                               double2 *__restrict__ out,
+                                                               const RecHG64 *__restrict__ hg = nullptr) {
+    constexpr int CH = 64;  // records per LDS tile (8 KiB, and 12 KiB of factors)
     __shared__ Rec64 tile[CH];
+    __shared__ RecHG64 htile[HG ? CH : 1];
     const int w = work_item(blockIdx.x, gridDim.x);
     if (w >= g.work) return;
     const int tiles = g.tiles_x * g.tiles_y;
@@ -111,6 +119,11 @@ __global__ void __launch_bounds__(64 * WAVES) eval_fp64_kernel(EvalGeom g, const
             const double2 *src = reinterpret_cast<const double2 *>(rec + j0);
             double2 *dst = reinterpret_cast<double2 *>(tile);
             for (int i = threadIdx.x; i < cnt * 8; i += 64 * WAVES) dst[i] = src[i];
+            if constexpr (HG) {
+                const double2 *hs = reinterpret_cast<const double2 *>(hg + j0);
+                double2 *hd = reinterpret_cast<double2 *>(htile);
+                for (int i = threadIdx.x; i < cnt * (int)(sizeof(RecHG64) / 16); i += 64 * WAVES) hd[i] = hs[i];
+            }
         }
         __syncthreads();
         for (int jj = 0; jj < cnt; jj++) {
@@ -130,8 +143,15 @@ __global__ void __launch_bounds__(64 * WAVES) eval_fp64_kernel(EvalGeom g, const
                 sincospi(2.0 * rr, &s, &c);
                 const double dbk = fma((double)k, dy, db);
                 const double m = exp(Vc + dbk * (ql + r.l[5] * dbk));
-                acc_re[k] = fma(m, c, acc_re[k]);
-                acc_im[k] = fma(m, s, acc_im[k]);
+                if constexpr (HG) {
+                    const cd P = hg_factor(htile[jj], da, dbk);
+                    const double er = m * c, ei = m * s;
+                    acc_re[k] += er * P.re - ei * P.im;
+                    acc_im[k] += er * P.im + ei * P.re;
+                } else {
+                    acc_re[k] = fma(m, c, acc_re[k]);
+                    acc_im[k] = fma(m, s, acc_im[k]);
+                }
             }
         }
     }
@@ -178,9 +198,23 @@ __global__ void __launch_bounds__(256) reduce_fp64_kernel(int64_t M, int32_t nse
 }
 
 template <int ROWS, int WAVES>
-hipError_t launch_eval_t(int precision, int form, const EvalGeom &g, const void *rec, void *partial, void *out,
-                         hipStream_t s) {
+hipError_t launch_eval_t(int precision, int form, const EvalGeom &g, const void *rec, const void *hg, void *partial,
+                         void *out, hipStream_t s) {
     const int grid = (g.work + 7) / 8 * 8;
+    if (hg) {
+        if (precision == 1 && form == 0)
+            eval_mixed_kernel<ROWS, WAVES, 0, true><<<grid, 64 * WAVES, 0, s>>>(
+                g, static_cast<const Rec32 *>(rec), static_cast<float4 *>(partial), static_cast<float2 *>(out),
+                static_cast<const RecHG32 *>(hg));
+        else if constexpr (ROWS <= 8) {
+            if (precision != 0) return hipErrorInvalidValue;
+            eval_fp64_kernel<ROWS, WAVES, true><<<grid, 64 * WAVES, 0, s>>>(
+                g, static_cast<const Rec64 *>(rec), static_cast<double2 *>(partial), static_cast<double2 *>(out),
+                static_cast<const RecHG64 *>(hg));
+        } else
+            return hipErrorInvalidValue;
+        return hipGetLastError();
+    }
     if (precision == 1 && form == 2)
         eval_mixed_kernel<ROWS, WAVES, 2><<<grid, 64 * WAVES, 0, s>>>(g, static_cast<const Rec32 *>(rec),
                                                                       static_cast<float4 *>(partial),
@@ -205,28 +239,28 @@ hipError_t launch_eval_t(int precision, int form, const EvalGeom &g, const void 
 }  // namespace
 
 hipError_t launch_setup(const BeamletsDev &b, const PlaneGeom &pl, double global_turns, Rec64 *r64, Rec32 *r32,
-                        uint32_t *status, hipStream_t s) {
+                        RecHG64 *h64, RecHG32 *h32, uint32_t *status, hipStream_t s) {
     if (b.n == 0) return hipSuccess;
     const int64_t blocks = (b.n + 255) / 256;
-    setup_kernel<<<(unsigned)blocks, 256, 0, s>>>(b, pl, global_turns, r64, r32, status);
+    setup_kernel<<<(unsigned)blocks, 256, 0, s>>>(b, pl, global_turns, r64, r32, h64, h32, status);
     return hipGetLastError();
 }
 
-hipError_t launch_eval(int precision, int rows, int waves, int form, const EvalGeom &g, const void *rec, void *partial,
-                       void *out, hipStream_t s) {
+hipError_t launch_eval(int precision, int rows, int waves, int form, const EvalGeom &g, const void *rec, const void *hg,
+                       void *partial, void *out, hipStream_t s) {
 #define GBD_CASE(R, W) \
-    if (rows == R && waves == W) return launch_eval_t<R, W>(precision, form, g, rec, partial, out, s);
+    if (rows == R && waves == W) return launch_eval_t<R, W>(precision, form, g, rec, hg, partial, out, s);
     GBD_CASE(1, 1) GBD_CASE(1, 2) GBD_CASE(1, 4)
     GBD_CASE(2, 1) GBD_CASE(2, 2) GBD_CASE(2, 4)
     GBD_CASE(4, 1) GBD_CASE(4, 2) GBD_CASE(4, 4)
     GBD_CASE(8, 1) GBD_CASE(8, 2) GBD_CASE(8, 4)
 #undef GBD_CASE
     if (precision == 1 && rows == 16) {
-        if (waves == 1) return launch_eval_t<16, 1>(precision, form, g, rec, partial, out, s);
-        if (waves == 2) return launch_eval_t<16, 2>(precision, form, g, rec, partial, out, s);
-        if (waves == 4) return launch_eval_t<16, 4>(precision, form, g, rec, partial, out, s);
+        if (waves == 1) return launch_eval_t<16, 1>(precision, form, g, rec, hg, partial, out, s);
+        if (waves == 2) return launch_eval_t<16, 2>(precision, form, g, rec, hg, partial, out, s);
+        if (waves == 4) return launch_eval_t<16, 4>(precision, form, g, rec, hg, partial, out, s);
     }
-    if (precision == 1 && rows == 32 && form == 2) {
+    if (precision == 1 && rows == 32 && form == 2 && !hg) {
         const int grid = (g.work + 7) / 8 * 8;
         if (waves == 1)
             eval_mixed_kernel<32, 1, 2><<<grid, 64, 0, s>>>(g, static_cast<const Rec32 *>(rec),

@@ -25,6 +25,10 @@
 // loaded while the current one computes.  Accumulators stay in FP32 over the
 // segment; segments are summed in FP64 by the reduction.  The host sizes
 // segments so that every one is non-empty (jb < je <= N).
+//
+// Higher-order (elegant Hermite-Gaussian) beamlets without cross terms keep
+// the factorisation: their Hermite-Gaussian factor is a product of one
+// polynomial in da and one in db, folded into U and V.
 #include "gbd_device.h"
 
 namespace gbd {
@@ -48,15 +52,48 @@ __device__ inline void factor(double d, float df, double c0, double c1, double c
     im = m * __builtin_amdgcn_sinf(ph);
 }
 
+// A higher-order beamlet's per-axis Hermite-Gaussian factor (no cross
+// terms): the factor times c0 + g (c1 + c2 g), g = G d along the axis.
+__device__ inline void hg_axis(float df, float gr0, float gi0, float c0r, float c0i, float c1, float c2, float &re,
+                               float &im) {
+    const float gr = gr0 * df, gi = gi0 * df;
+    const float tr = fmaf(c2, gr, c1), ti = c2 * gi;
+    const float pr = c0r + (gr * tr - gi * ti), pi = c0i + (gr * ti + gi * tr);
+    const float r = re * pr - im * pi;
+    im = re * pi + im * pr;
+    re = r;
+}
+
 // The record fields one lane's factors need; a beamlet index past the
-// segment end gets the amplitude exponent -inf (factor 0).
+// segment end gets the amplitude exponent -inf (factor 0).  With HG also
+// the diagonal of G and the per-axis polynomial coefficients.
 struct Fields {
     double arho, brho, p0, p1, p2, p3, p5;
     float m0, m1, m2, m3, m5, arf, brf;
+    float gxr, gxi, cx0r, cx0i, cx1, cx2;
+    float gyr, gyi, cy0r, cy0i, cy1, cy2;
 };
-__device__ inline Fields load_fields(const Rec32 *__restrict__ rec, int64_t j, int64_t jb, int64_t je) {
-    const Rec32 *rp = rec + (j < je ? j : jb);
+template <bool HG>
+__device__ inline Fields load_fields(const Rec32 *__restrict__ rec, const RecHG32 *__restrict__ hg, int64_t j,
+                                     int64_t jb, int64_t je) {
+    const int64_t jj = j < je ? j : jb;
+    const Rec32 *rp = rec + jj;
     Fields f;
+    if constexpr (HG) {
+        const RecHG32 *h = hg + jj;
+        f.gxr = h->g[0][0][0];
+        f.gxi = h->g[0][0][1];
+        f.cx0r = h->cx0[0];
+        f.cx0i = h->cx0[1];
+        f.cx1 = h->cx1;
+        f.cx2 = h->cx2;
+        f.gyr = h->g[1][1][0];
+        f.gyi = h->g[1][1][1];
+        f.cy0r = h->cy0[0];
+        f.cy0i = h->cy0[1];
+        f.cy1 = h->cy1;
+        f.cy2 = h->cy2;
+    }
     f.arho = rp->arho;
     f.brho = rp->brho;
     f.p0 = rp->p[0];
@@ -74,8 +111,9 @@ __device__ inline Fields load_fields(const Rec32 *__restrict__ rec, int64_t j, i
     return f;
 }
 
-template <int WX, int WY>
+template <int WX, int WY, bool HG>
 __global__ void __launch_bounds__(64 * WX * WY) eval_sep_kernel(EvalGeom g, const Rec32 *__restrict__ rec,
+                                                                 const RecHG32 *__restrict__ hg,
                                                                  float4 *__restrict__ partial,
                                                                  float2 *__restrict__ out) {
     constexpr int NB = kSepBlocks;
@@ -114,8 +152,13 @@ __global__ void __launch_bounds__(64 * WX * WY) eval_sep_kernel(EvalGeom g, cons
 #pragma unroll
         for (int h = 0; h < 2; h++) {
             float ur, ui, vr, vi;
-            factor(ax[h] - f.arho, axf[h] - f.arf, f.p0, f.p1, f.p3, f.m0 + mx[h], f.m1, f.m3, ur, ui);
-            factor(by[h] - f.brho, byf[h] - f.brf, 0.0, f.p2, f.p5, my[h], f.m2, f.m5, vr, vi);
+            const float dxf = axf[h] - f.arf, dyf = byf[h] - f.brf;
+            factor(ax[h] - f.arho, dxf, f.p0, f.p1, f.p3, f.m0 + mx[h], f.m1, f.m3, ur, ui);
+            factor(by[h] - f.brho, dyf, 0.0, f.p2, f.p5, my[h], f.m2, f.m5, vr, vi);
+            if constexpr (HG) {
+                hg_axis(dxf, f.gxr, f.gxi, f.cx0r, f.cx0i, f.cx1, f.cx2, ur, ui);
+                hg_axis(dyf, f.gyr, f.gyi, f.cy0r, f.cy0i, f.cy1, f.cy2, vr, vi);
+            }
             lu[buf][wx][2 * wy + h][lane] = make_float2(ur, ui);
             lv[buf][wy][2 * wx + h][lane] = make_float2(vr, vi);
         }
@@ -130,13 +173,13 @@ __global__ void __launch_bounds__(64 * WX * WY) eval_sep_kernel(EvalGeom g, cons
 
     const int64_t jb = (int64_t)seg * g.seg_len;
     const int64_t je = min(g.n, jb + g.seg_len);
-    publish(load_fields(rec, jb + lk, jb, je), 0);
-    Fields nxt = load_fields(rec, jb + 4 + lk, jb, je);
+    publish(load_fields<HG>(rec, hg, jb + lk, jb, je), 0);
+    Fields nxt = load_fields<HG>(rec, hg, jb + 4 + lk, jb, je);
     __syncthreads();
     int buf = 0;
     for (int64_t j0 = jb; j0 < je; j0 += 4) {
         const Fields f = nxt;
-        nxt = load_fields(rec, j0 + 8 + lk, jb, je);
+        nxt = load_fields<HG>(rec, hg, j0 + 8 + lk, jb, je);
         if (j0 + 4 < je) publish(f, buf ^ 1);
         float ur[NB], ui[NB], vr[NB], vi[NB], vn[NB];
 #pragma unroll
@@ -190,9 +233,15 @@ __global__ void __launch_bounds__(64 * WX * WY) eval_sep_kernel(EvalGeom g, cons
 
 }  // namespace
 
-hipError_t launch_eval_sep(const EvalGeom &g, const Rec32 *rec, float4 *partial, float2 *out, hipStream_t s) {
+hipError_t launch_eval_sep(const EvalGeom &g, const Rec32 *rec, const RecHG32 *hg, float4 *partial, float2 *out,
+                           hipStream_t s) {
     const int grid = (g.work + 7) / 8 * 8;
-    eval_sep_kernel<kSepWavesX, kSepWavesY><<<grid, 64 * kSepWavesX * kSepWavesY, 0, s>>>(g, rec, partial, out);
+    if (hg)
+        eval_sep_kernel<kSepWavesX, kSepWavesY, true>
+            <<<grid, 64 * kSepWavesX * kSepWavesY, 0, s>>>(g, rec, hg, partial, out);
+    else
+        eval_sep_kernel<kSepWavesX, kSepWavesY, false>
+            <<<grid, 64 * kSepWavesX * kSepWavesY, 0, s>>>(g, rec, nullptr, partial, out);
     return hipGetLastError();
 }
 

@@ -241,6 +241,40 @@ def zernike_scene(seed: int = 2404, *, n_across: int = 128, D: float = 10e-3, fn
 
 
 # --- Named workloads ---------------------------------------------------------
+def hermite_scene(n_across: int = 32, *, seed: int = 7, D: float = 10e-3, fnum: float = 10.0, lam: float = 1e-6,
+                  OF: float = 1.7, npix: int = 128, half_span_lamF: float = 8.0, cyl_f: Optional[float] = None,
+                  cyl_angle: float = 0.5, z0: float = 0.0, npix_y: Optional[int] = None,
+                  max_order: int = 2) -> Scene:
+    """Higher-order beamlets on the pupil grid of airy_scene: every beamlet
+    draws its Hermite-Gaussian orders (m, n) uniformly from 0..max_order and
+    a unit-modulus amplitude of uniform phase (seeded), through an ideal lens
+    of focal length fnum * D, detector normal to the axis at z0 from the
+    focal plane.  cyl_f adds a thin cylindrical lens of that focal length
+    whose power axis is turned by cyl_angle (rad), in contact with the
+    lens: the system is then astigmatic with non-diagonal blocks."""
+    f = fnum * D
+    r1, sp = pupil_grid(n_across, D)
+    n = r1.shape[0]
+    rng = np.random.default_rng(seed)
+    order = rng.integers(0, max_order + 1, size=(n, 2)).astype(np.int32)
+    ph = rng.uniform(0.0, 2.0 * np.pi, size=n)
+    amp = np.stack([np.cos(ph), np.sin(ph)], axis=1)
+    M = lens_then_distance(f, f)
+    if cyl_f is not None:
+        c, s_ = np.cos(cyl_angle), np.sin(cyl_angle)
+        R = np.array([[c, -s_], [s_, c]])
+        M = M @ thin_plate(-R @ np.diag([1.0 / cyl_f, 0.0]) @ R.T)
+    lamF = lam * fnum
+    ny = npix if npix_y is None else npix_y
+    plane = _plane((0.0, 0.0, z0), (0.0, 0.0, 1.0), (1.0, 0.0, 0.0), npix, ny,
+                   2.0 * half_span_lamF * lamF / npix, 2.0 * half_span_lamF * lamF / ny)
+    sc = Scene(lam, f, r1, np.zeros((n, 2)), np.full(n, OF * sp / 2.0), amp, np.zeros(n), M.reshape(1, 16), plane,
+               meta=dict(kind="hermite", n_across=n_across, D=D, f=f, fnum=fnum, OF=OF, seed=seed, cyl_f=cyl_f,
+                         half_span_lamF=half_span_lamF))
+    sc.order = order
+    return sc
+
+
 def config(name: str) -> Scene:
     """Named workloads:
 
