@@ -17,8 +17,10 @@ instruction-mix roofline.
 
 Also reported: the FP64 form on the same workload (and the mixed/FP64
 speed-up), the dominant kernel's live HIP-event duration, point evaluation,
-the 441-instance sweep, and the FP64 CPU oracle timed on a bounded pixel
-sample (which also gives the mixed form's error against the oracle there).
+the 441-instance sweep, the ray-traced telescope, higher-order
+(Hermite-Gaussian) beamlets on the same grid, and the FP64 CPU oracle timed
+on a bounded pixel sample (which also gives the mixed form's error against
+the oracle there).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 """
@@ -55,11 +57,15 @@ TRAFFIC = {("airy256_512", 32, 4, 48, 3): (6095.5 * 2.0 + 196608.0 * 1.0) * 1024
            ("airy256_512", 64, 4, 48, 4): (5331.8 * 2.0 + 196608.0 * 1.0) * 1024}
 
 
-def instruction_mix(rows, variant):
+def instruction_mix(rows, variant, hg=False):
     """Instructions per beamlet-pixel pair of the mixed kernel's inner loop
     (per lane and beamlet: an FP64 anchor, then R rows), counted in the
-    compiled gfx950 code."""
+    compiled gfx950 code.  hg: higher-order beamlets (rotor form: the
+    Hermite-Gaussian factor's degree-4 row polynomial, 159 FP32 per lane and
+    beamlet, then Horner's rule and one more complex product, 12 FP32 per row)."""
     R = float(rows)
+    if variant == 3 and hg:
+        return {"fp64": 15 / R, "fp32": (20 * R + 159) / R, "trans": 7 / R}
     if variant == 3:  # rotor: 8 FP32 per further row, 7 transcendentals per lane and beamlet
         return {"fp64": 15 / R, "fp32": (8 * R + 13) / R, "trans": 7 / R}
     if variant == 2:  # stepped: sin + cos per pixel
@@ -67,8 +73,8 @@ def instruction_mix(rows, variant):
     return {"fp64": (4 * R + 10) / R, "fp32": (5 * R + 5) / R, "trans": 3.0}
 
 
-def roofline_peak(rows, variant):
-    mix = instruction_mix(rows, variant)
+def roofline_peak(rows, variant, hg=False):
+    mix = instruction_mix(rows, variant, hg)
     cycles = sum(n / RATE[k] for k, n in mix.items())
     return CUS * CLOCK_HZ / cycles, cycles, mix
 
@@ -84,14 +90,14 @@ SEP_VALU_PER_PAIR = {"fp64": 20 / 256, "fp32": 23 / 256, "trans": 12 / 256, "oth
                      "mfma_16x16x4": 64 / 16384}
 
 
-def roofline(shape, N, M, kernel_ms):
+def roofline(shape, N, M, kernel_ms, hg=False):
     if shape["variant"] == 4:
         achieved = SEP_FLOPS_PER_PAIR * N * M / (kernel_ms * 1e-3) / 1e12
         return {"bound": "mfma", "achieved": achieved, "peak": MFMA_FP32_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved / MFMA_FP32_TFLOPS, "kernel": "eval_sep_kernel", "kernel_ms": kernel_ms,
                 "flops_per_pair": SEP_FLOPS_PER_PAIR, "instructions_per_pair": SEP_VALU_PER_PAIR}
     achieved = N * M / (kernel_ms * 1e-3)
-    peak, cycles, mix = roofline_peak(shape["rows_per_lane"], shape["variant"])
+    peak, cycles, mix = roofline_peak(shape["rows_per_lane"], shape["variant"], hg)
     return {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "evals/s", "frac": achieved / peak,
             "kernel": "eval_mixed_kernel", "kernel_ms": kernel_ms, "cu_cycles_per_pair": cycles,
             "instructions_per_pair": mix}
@@ -108,6 +114,7 @@ def main():
     ap.add_argument("--no-sweep", action="store_true", help="skip the 441-instance batched sweep figure")
     ap.add_argument("--no-point", action="store_true", help="skip the point-evaluation comparison")
     ap.add_argument("--no-telescope", action="store_true", help="skip the ray-traced telescope leg")
+    ap.add_argument("--no-hermite", action="store_true", help="skip the higher-order beamlet leg")
     ap.add_argument("--fp64-steps", type=int, default=5)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 256 MiB device copy (a known-size kernel for HBM counters)")
@@ -221,6 +228,8 @@ def main():
         rec["sweep"] = sweep(ctx)
     if not args.no_telescope:
         rec["telescope"] = telescope(ctx, stream)
+    if not args.no_hermite:
+        rec["hermite"] = hermite(ctx, stream, eval_ms_mean)
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(sc, E32, E64)
     print(json.dumps(rec), flush=True)
@@ -355,6 +364,46 @@ def telescope(ctx, stream, n_across=128, npix=512, reps=5):
             "trace_ms_host_roundtrip": 1e3 * float(np.median(t)), "trace_rays": 9 * sc.n,
             "eval_ms": ms, "evals_per_s": n * npix * npix / (ms * 1e-3), "launch": plan.shape(gbd.GBD_MIXED),
             "rms_vs_obscured_airy": float(np.sqrt(np.mean(d * d))), "peak_vs_obscured_airy": float(np.abs(d).max())}
+
+
+def hermite(ctx, stream, gauss_ms, n_across=256, npix=512, reps=10):
+    """Elegant Hermite-Gaussian beamlets (orders up to 2 per axis, drawn per
+    beamlet) on the headline grid: through the ideal lens (no cross terms:
+    the separable MFMA form with per-axis factors) and through an added
+    rotated cylindrical lens (cross terms: the rotor form with the factor's
+    row polynomial), mixed precision."""
+    import numpy as np
+    import torch
+    import paper_2404_12454_amd as gbd
+    from paper_2404_12454_amd import scenes
+    res = {}
+    for name, kw in (("focal", {}), ("astigmatic", dict(cyl_f=3.0))):
+        sc = scenes.hermite_scene(n_across, npix=npix, half_span_lamF=20.0, **kw)
+        b = gbd.beamlets_from_scene(ctx, sc)
+        p = gbd.plane_from_scene(ctx, sc)
+        plan = gbd.Plan(ctx, sc.n).setup(b, p)
+        out = torch.empty((npix, npix), dtype=torch.complex64, device="cuda")
+        for _ in range(reps):
+            plan.eval(gbd.GBD_MIXED, out)
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+        for a, z in evs:
+            a.record(stream)
+            plan.eval(gbd.GBD_MIXED, out)
+            z.record(stream)
+        torch.cuda.synchronize()
+        ms = float(np.mean([a.elapsed_time(z) for a, z in evs]))
+        shape = plan.shape(gbd.GBD_MIXED)
+        r = {"beamlets": sc.n, "npix": npix, "launch": shape, "eval_ms": ms,
+             "evals_per_s": sc.n * npix * npix / (ms * 1e-3)}
+        if shape["variant"] == 4:
+            r["mfma_frac"] = roofline(shape, sc.n, npix * npix, ms)["frac"]
+            r["cost_vs_fundamental"] = ms / gauss_ms
+        elif shape["variant"] == 3:
+            rf = roofline(shape, sc.n, npix * npix, ms, hg=True)
+            r["roofline_peak"] = rf["peak"]
+            r["roofline_frac"] = rf["frac"]
+        res[name] = r
+    return res
 
 
 def cpu_baseline(sc, E32, E64):

@@ -156,11 +156,12 @@ int gbd_beamlets_traced(gbd_ctx_t ctx, gbd_beamlets_t *out, int64_t n, double la
  * that derivative, so on the detector the beamlet is its Gaussian field
  * times a polynomial in the offset from the base ray.  Evaluation
  * (gbd_eval, gbd_plan_eval) takes such beamlets on planes normal to the axis
- * only (else GBD_EINVAL from the setup), in FP64 or in the mixed direct or
- * separable form (a request for the stepped or rotor form resolves to the
- * direct one; the separable form where no beamlet's factor has cross
- * terms).  gbd_eval_point and gbd_eval_batch refuse beamlets with a nonzero
- * order (GBD_EINVAL).  Orders all (0, 0) give the fundamental beamlets. */
+ * only (else GBD_EINVAL from the setup), in FP64 or in the mixed direct,
+ * rotor or separable form (a request for the stepped form resolves to the
+ * direct one; the separable form applies where no beamlet's factor has
+ * cross terms).  gbd_eval_point and gbd_eval_batch
+ * refuse beamlets with a nonzero order (GBD_EINVAL).  Orders all (0, 0)
+ * give the fundamental beamlets. */
 int gbd_beamlets_hg(gbd_ctx_t ctx, gbd_beamlets_t *out, int64_t n, double lambda, double l0, const double *r1,
                     const double *th1, const double *w0, int64_t n_w0, const double *amp, const double *path,
                     const double *abcd, int64_t n_abcd, const int32_t *order);

@@ -189,13 +189,12 @@ struct Shape {
 // choice among the others.
 int pick_form(int precision, uint32_t flags, const gbd_eval_opts *o, bool allow_sep = true) {
     if (precision != GBD_MIXED) return 0;
-    // higher-order beamlets: direct or separable form (their factor is not
-    // carried by the stepped and rotor recurrences)
-    const bool steep = (flags & (FLAG_STEEP | FLAG_HG)) != 0;
+    const bool steep = (flags & FLAG_STEEP) != 0;
     const bool sep = allow_sep && !(flags & FLAG_CROSS);
     const int v = o ? o->variant : 0;
     if (v == 1) return 0;
-    if (v == 2) return steep ? 0 : 1;
+    // higher-order beamlets: the stepped form does not carry their factor
+    if (v == 2) return (steep || (flags & FLAG_HG)) ? 0 : 1;
     if (v == 3) return steep ? 0 : 2;
     return sep ? 3 : steep ? 0 : 2;
 }

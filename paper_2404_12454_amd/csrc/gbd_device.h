@@ -351,6 +351,69 @@ __device__ inline float2 hg_factor32(const RecHG32 &h, float gxa_r, float gxa_i,
     return make_float2(re, im);
 }
 
+// The Hermite-Gaussian factor along a lane's column as a polynomial in the
+// row step k from the anchor row (plane offsets da, db there, row pitch dy):
+// gx = ax + k sx, gy = ay + k sy with ax = G[0][0] da + G[0][1] db,
+// sx = G[0][1] dy (likewise y); Px, Py are quadratics and ax, ay linear in
+// k, so P = Px Py + k1 ax ay + k0 has degree <= 4.  q[i] = (re, im) of the
+// coefficient of k^i.
+__device__ inline void hg_row_poly(const RecHG32 &h, float da, float db, float dy, float (&q)[5][2]) {
+    const float axr = fmaf(h.g[0][1][0], db, h.g[0][0][0] * da), axi = fmaf(h.g[0][1][1], db, h.g[0][0][1] * da);
+    const float ayr = fmaf(h.g[1][1][0], db, h.g[1][0][0] * da), ayi = fmaf(h.g[1][1][1], db, h.g[1][0][1] * da);
+    const float sxr = h.g[0][1][0] * dy, sxi = h.g[0][1][1] * dy;
+    const float syr = h.g[1][1][0] * dy, syi = h.g[1][1][1] * dy;
+    // Px = cx0 + cx1 g + cx2 g^2 at g = a + s k:
+    //   px0 = cx0 + a (cx1 + cx2 a), px1 = s (cx1 + 2 cx2 a), px2 = cx2 s^2
+    auto quad = [](float c0r, float c0i, float c1, float c2, float ar, float ai, float sr, float si,
+                   float (&p)[3][2]) {
+        const float tr = fmaf(c2, ar, c1), ti = c2 * ai;
+        p[0][0] = c0r + (ar * tr - ai * ti);
+        p[0][1] = c0i + (ar * ti + ai * tr);
+        const float ur = fmaf(2.0f * c2, ar, c1), ui = 2.0f * c2 * ai;
+        p[1][0] = sr * ur - si * ui;
+        p[1][1] = sr * ui + si * ur;
+        p[2][0] = c2 * (sr * sr - si * si);
+        p[2][1] = c2 * (2.0f * sr * si);
+    };
+    float px[3][2], py[3][2];
+    quad(h.cx0[0], h.cx0[1], h.cx1, h.cx2, axr, axi, sxr, sxi, px);
+    quad(h.cy0[0], h.cy0[1], h.cy1, h.cy2, ayr, ayi, syr, syi, py);
+    // Px Py (product of quadratics)
+#pragma unroll
+    for (int i = 0; i < 5; i++) q[i][0] = q[i][1] = 0.0f;
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int j = 0; j < 3; j++) {
+            q[i + j][0] += px[i][0] * py[j][0] - px[i][1] * py[j][1];
+            q[i + j][1] += px[i][0] * py[j][1] + px[i][1] * py[j][0];
+        }
+    // k1 ax ay + k0, ax = (ex0 + ex1 a) + ex1 s k
+    const float x0r = fmaf(h.ex1, axr, h.ex0), x0i = h.ex1 * axi, x1r = h.ex1 * sxr, x1i = h.ex1 * sxi;
+    const float y0r = fmaf(h.ey1, ayr, h.ey0), y0i = h.ey1 * ayi, y1r = h.ey1 * syr, y1i = h.ey1 * syi;
+    const float m0r = x0r * y0r - x0i * y0i, m0i = x0r * y0i + x0i * y0r;
+    const float m1r = (x0r * y1r - x0i * y1i) + (x1r * y0r - x1i * y0i);
+    const float m1i = (x0r * y1i + x0i * y1r) + (x1r * y0i + x1i * y0r);
+    const float m2r = x1r * y1r - x1i * y1i, m2i = x1r * y1i + x1i * y1r;
+    const float kr = h.k1[0], ki = h.k1[1];
+    q[0][0] += (kr * m0r - ki * m0i) + h.k0[0];
+    q[0][1] += (kr * m0i + ki * m0r) + h.k0[1];
+    q[1][0] += kr * m1r - ki * m1i;
+    q[1][1] += kr * m1i + ki * m1r;
+    q[2][0] += kr * m2r - ki * m2i;
+    q[2][1] += kr * m2i + ki * m2r;
+}
+
+// q0 + k (q1 + k (q2 + k (q3 + k q4))) for real k.
+__device__ inline float2 horner4(const float (&q)[5][2], float k) {
+    float re = fmaf(q[4][0], k, q[3][0]), im = fmaf(q[4][1], k, q[3][1]);
+    re = fmaf(re, k, q[2][0]);
+    im = fmaf(im, k, q[2][1]);
+    re = fmaf(re, k, q[1][0]);
+    im = fmaf(im, k, q[1][1]);
+    return make_float2(fmaf(re, k, q[0][0]), fmaf(im, k, q[0][1]));
+}
+
 __device__ inline void kahan(float &s, float &c, float x) {
     const float y = x - c;
     const float t = s + y;
@@ -521,10 +584,17 @@ __device__ inline void mixed_accumulate_step(Rec32 *tile, const Rec32 *__restric
 // FP32 addition (c stays zero), one rounding per 128-beamlet tile: measured
 // 20 % faster than the compensated fold there (204 against 249 registers) at
 // an unchanged error against FP64.
-template <int ROWS, int NT>
+//
+// With HG each beamlet's Hermite-Gaussian factor multiplies its phasor.
+// Along the column g = G d is linear in the row step k from the anchor, so
+// the factor is a polynomial of degree <= 4 in k; its coefficients are formed
+// once per (lane, beamlet) and evaluated by Horner's rule per row (8 FP32
+// instructions), centred on the anchor so |k| <= ROWS / 2.
+template <int ROWS, int NT, bool HG = false>
 __device__ inline void mixed_accumulate_rotor(Rec32 *tile, const Rec32 *__restrict__ rec, int64_t jb, int64_t je,
                                               double a, double b0, double dy, float (&s_re)[ROWS],
-                                              float (&s_im)[ROWS], float (&c_re)[ROWS], float (&c_im)[ROWS]) {
+                                              float (&s_im)[ROWS], float (&c_re)[ROWS], float (&c_im)[ROWS],
+                                              RecHG32 *htile = nullptr, const RecHG32 *__restrict__ hg = nullptr) {
     constexpr int H = ROWS / 2;
     static_assert(H <= kRotorRows, "rotor form: at most 2 * kRotorRows rows per lane");
     const double bh = b0 + H * dy;
@@ -539,6 +609,11 @@ __device__ inline void mixed_accumulate_rotor(Rec32 *tile, const Rec32 *__restri
             const float4 *src = reinterpret_cast<const float4 *>(rec + j0);
             float4 *dst = reinterpret_cast<float4 *>(tile);
             for (int i = threadIdx.x; i < cnt * kRec32Vec4; i += NT) dst[i] = src[i];
+            if constexpr (HG) {
+                const float4 *hs = reinterpret_cast<const float4 *>(hg + j0);
+                float4 *hd = reinterpret_cast<float4 *>(htile);
+                for (int i = threadIdx.x; i < cnt * (int)(sizeof(RecHG32) / 16); i += NT) hd[i] = hs[i];
+            }
         }
         __syncthreads();
         for (int jj = 0; jj < cnt; jj++) {
@@ -556,8 +631,16 @@ __device__ inline void mixed_accumulate_rotor(Rec32 *tile, const Rec32 *__restri
             const float m0 = L0 < -126.0f ? 0.0f : __builtin_amdgcn_exp2f(L0);
             const float zr = m0 * __builtin_amdgcn_cosf(base), zi = m0 * __builtin_amdgcn_sinf(base);
             const float c1 = __builtin_amdgcn_cosf(t1), s1 = __builtin_amdgcn_sinf(t1);
-            acc_re[H] += zr;
-            acc_im[H] += zi;
+            // Hermite-Gaussian factor P(k) = hq0 + k (hq1 + k (hq2 + k (hq3 + k hq4)))
+            [[maybe_unused]] float hq[5][2];
+            if constexpr (HG) hg_row_poly(htile[jj], daf, dbf, dyf, hq);
+            if constexpr (HG) {
+                acc_re[H] += zr * hq[0][0] - zi * hq[0][1];
+                acc_im[H] += zr * hq[0][1] + zi * hq[0][0];
+            } else {
+                acc_re[H] += zr;
+                acc_im[H] += zi;
+            }
             if (ROWS - 1 - H > 0) {
                 const float mu = __builtin_amdgcn_exp2f(U1);
                 const float ur = mu * c1, ui = mu * s1;
@@ -569,8 +652,15 @@ __device__ inline void mixed_accumulate_rotor(Rec32 *tile, const Rec32 *__restri
                     pr = nr;
                     pi = ni;
                     const float sr = r.sq[k - 1][0], si = r.sq[k - 1][1];
-                    acc_re[H + k] = fmaf(pr, sr, fmaf(-pi, si, acc_re[H + k]));
-                    acc_im[H + k] = fmaf(pr, si, fmaf(pi, sr, acc_im[H + k]));
+                    if constexpr (HG) {
+                        const float2 P = horner4(hq, (float)k);
+                        const float tr = fmaf(pr, sr, -(pi * si)), ti = fmaf(pr, si, pi * sr);
+                        acc_re[H + k] = fmaf(tr, P.x, fmaf(-ti, P.y, acc_re[H + k]));
+                        acc_im[H + k] = fmaf(tr, P.y, fmaf(ti, P.x, acc_im[H + k]));
+                    } else {
+                        acc_re[H + k] = fmaf(pr, sr, fmaf(-pi, si, acc_re[H + k]));
+                        acc_im[H + k] = fmaf(pr, si, fmaf(pi, sr, acc_im[H + k]));
+                    }
                 }
             }
             if (H > 0) {
@@ -584,8 +674,15 @@ __device__ inline void mixed_accumulate_rotor(Rec32 *tile, const Rec32 *__restri
                     pr = nr;
                     pi = ni;
                     const float sr = r.sq[k - 1][0], si = r.sq[k - 1][1];
-                    acc_re[H - k] = fmaf(pr, sr, fmaf(-pi, si, acc_re[H - k]));
-                    acc_im[H - k] = fmaf(pr, si, fmaf(pi, sr, acc_im[H - k]));
+                    if constexpr (HG) {
+                        const float2 P = horner4(hq, -(float)k);
+                        const float tr = fmaf(pr, sr, -(pi * si)), ti = fmaf(pr, si, pi * sr);
+                        acc_re[H - k] = fmaf(tr, P.x, fmaf(-ti, P.y, acc_re[H - k]));
+                        acc_im[H - k] = fmaf(tr, P.y, fmaf(ti, P.x, acc_im[H - k]));
+                    } else {
+                        acc_re[H - k] = fmaf(pr, sr, fmaf(-pi, si, acc_re[H - k]));
+                        acc_im[H - k] = fmaf(pr, si, fmaf(pi, sr, acc_im[H - k]));
+                    }
                 }
             }
         }

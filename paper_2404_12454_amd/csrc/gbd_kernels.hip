@@ -33,14 +33,14 @@ __global__ void __launch_bounds__(256) setup_kernel(BeamletsDev b, PlaneGeom pl,
 // Mixed form.  Each lane owns ROWS pixels of one detector column; a
 // wavefront spans 64 consecutive columns (coalesced stores); WAVES
 // wavefronts stack in y; the workgroup sums one segment of beamlets.
-// FORM: 0 direct, 1 stepped, 2 rotor accumulation; HG (direct form only):
-// higher-order beamlets, records hg.
+// FORM: 0 direct, 1 stepped, 2 rotor accumulation; HG (direct and rotor
+// forms): higher-order beamlets, records hg.
 template <int ROWS, int WAVES, int FORM, bool HG = false>
 __global__ void __launch_bounds__(64 * WAVES) eval_mixed_kernel(EvalGeom g, const Rec32 *__restrict__ rec,
                                                                 float4 *__restrict__ partial,
                                                                 float2 *__restrict__ out,
                                                                 const RecHG32 *__restrict__ hg = nullptr) {
-    static_assert(!HG || FORM == 0, "higher-order beamlets: direct form only");
+    static_assert(!HG || FORM == 0 || FORM == 2, "higher-order beamlets: direct or rotor form");
     __shared__ Rec32 tile[kMixedTile];
     __shared__ RecHG32 htile[HG ? kMixedTile : 1];
     const int w = work_item(blockIdx.x, gridDim.x);
@@ -61,7 +61,8 @@ __global__ void __launch_bounds__(64 * WAVES) eval_mixed_kernel(EvalGeom g, cons
     const int64_t jb = (int64_t)seg * g.seg_len;
     const int64_t je = min(g.n, jb + g.seg_len);
     if constexpr (FORM == 2)
-        mixed_accumulate_rotor<ROWS, 64 * WAVES>(tile, rec, jb, je, a, b0, g.dy, s_re, s_im, c_re, c_im);
+        mixed_accumulate_rotor<ROWS, 64 * WAVES, HG>(tile, rec, jb, je, a, b0, g.dy, s_re, s_im, c_re, c_im, htile,
+                                                     hg);
     else if constexpr (FORM == 1)
         mixed_accumulate_step<ROWS, 64 * WAVES>(tile, rec, jb, je, a, b0, g.dy, s_re, s_im, c_re, c_im);
     else
@@ -202,7 +203,11 @@ hipError_t launch_eval_t(int precision, int form, const EvalGeom &g, const void 
                          void *out, hipStream_t s) {
     const int grid = (g.work + 7) / 8 * 8;
     if (hg) {
-        if (precision == 1 && form == 0)
+        if (precision == 1 && form == 2)
+            eval_mixed_kernel<ROWS, WAVES, 2, true><<<grid, 64 * WAVES, 0, s>>>(
+                g, static_cast<const Rec32 *>(rec), static_cast<float4 *>(partial), static_cast<float2 *>(out),
+                static_cast<const RecHG32 *>(hg));
+        else if (precision == 1 && form == 0)
             eval_mixed_kernel<ROWS, WAVES, 0, true><<<grid, 64 * WAVES, 0, s>>>(
                 g, static_cast<const Rec32 *>(rec), static_cast<float4 *>(partial), static_cast<float2 *>(out),
                 static_cast<const RecHG32 *>(hg));
@@ -260,7 +265,23 @@ hipError_t launch_eval(int precision, int rows, int waves, int form, const EvalG
         if (waves == 2) return launch_eval_t<16, 2>(precision, form, g, rec, hg, partial, out, s);
         if (waves == 4) return launch_eval_t<16, 4>(precision, form, g, rec, hg, partial, out, s);
     }
-    if (precision == 1 && rows == 32 && form == 2 && !hg) {
+    if (precision == 1 && rows == 32 && form == 2 && hg) {
+        const int grid = (g.work + 7) / 8 * 8;
+        const Rec32 *r = static_cast<const Rec32 *>(rec);
+        const RecHG32 *h = static_cast<const RecHG32 *>(hg);
+        float4 *pt = static_cast<float4 *>(partial);
+        float2 *o = static_cast<float2 *>(out);
+        if (waves == 1)
+            eval_mixed_kernel<32, 1, 2, true><<<grid, 64, 0, s>>>(g, r, pt, o, h);
+        else if (waves == 2)
+            eval_mixed_kernel<32, 2, 2, true><<<grid, 128, 0, s>>>(g, r, pt, o, h);
+        else if (waves == 4)
+            eval_mixed_kernel<32, 4, 2, true><<<grid, 256, 0, s>>>(g, r, pt, o, h);
+        else
+            return hipErrorInvalidValue;
+        return hipGetLastError();
+    }
+    if (precision == 1 && rows == 32 && form == 2) {
         const int grid = (g.work + 7) / 8 * 8;
         if (waves == 1)
             eval_mixed_kernel<32, 1, 2><<<grid, 64, 0, s>>>(g, static_cast<const Rec32 *>(rec),

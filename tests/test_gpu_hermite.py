@@ -1,6 +1,6 @@
 """Higher-order (elegant Hermite-Gaussian) beamlets on the GPU against the
-FP64 oracle: FP64 and mixed precision, the direct and separable mixed forms
-in every launch shape, ragged grids, a full-size sampled case, and the
+FP64 oracle: FP64 and mixed precision, the direct, rotor and separable mixed
+forms in every launch shape, ragged grids, a full-size sampled case, and the
 refusals (tilted planes, orders outside 0..2, point evaluation and the
 batched sweep)."""
 import numpy as np
@@ -43,8 +43,10 @@ SCENES = {
     # rotationally symmetric: no cross terms, the separable form applies
     "focal": dict(n_across=20, npix=100, npix_y=77),
     "defocus": dict(n_across=20, npix=100, npix_y=77, z0=2e-3, half_span_lamF=14.0),
-    # rotated cylindrical lens: non-diagonal blocks, direct form
+    # rotated cylindrical lens: non-diagonal blocks, rotor form
     "astig": dict(n_across=20, npix=100, npix_y=77, cyl_f=3.0, half_span_lamF=12.0),
+    # astigmatic and defocused: the rotor form over broad spots
+    "astig_defocus": dict(n_across=20, npix=100, npix_y=77, cyl_f=3.0, half_span_lamF=16.0, z0=1.5e-3),
 }
 
 
@@ -64,15 +66,20 @@ def test_hermite_forms_resolve(ctx):
     sym = scenes.hermite_scene(12, npix=64)
     astig = scenes.hermite_scene(12, npix=64, cyl_f=3.0)
     assert resolved_variant(ctx, sym) == 4
-    assert resolved_variant(ctx, astig) == 1
-    # the stepped and rotor forms do not carry the Hermite-Gaussian factor
-    for v in (2, 3):
-        assert resolved_variant(ctx, sym, dict(variant=v)) == 1
-    assert resolved_variant(ctx, astig, dict(variant=4)) == 1
+    assert resolved_variant(ctx, astig) == 3
+    # the stepped form does not carry the Hermite-Gaussian factor
+    assert resolved_variant(ctx, sym, dict(variant=2)) == 1
+    assert resolved_variant(ctx, sym, dict(variant=3)) == 3
+    assert resolved_variant(ctx, astig, dict(variant=4)) == 3
+    b = gbd.beamlets_from_scene(ctx, astig)
+    plan = gbd.Plan(ctx, astig.n).setup(b, gbd.plane_from_scene(ctx, astig))
+    assert plan.shape(gbd.GBD_MIXED, dict(rows_per_lane=32, waves=4, variant=3))["rows_per_lane"] == 32
+    assert plan.shape(gbd.GBD_MIXED, dict(rows_per_lane=32, waves=4, variant=1))["rows_per_lane"] == 16
 
 
-@pytest.mark.parametrize("variant", [1, 4])
-@pytest.mark.parametrize("rows,waves,segments", [(1, 1, 1), (2, 2, 3), (4, 4, 2), (8, 1, 5), (16, 4, 1), (16, 2, 7)])
+@pytest.mark.parametrize("variant", [1, 3, 4])
+@pytest.mark.parametrize("rows,waves,segments", [(1, 1, 1), (2, 2, 3), (4, 4, 2), (8, 1, 5), (16, 4, 1), (16, 2, 7),
+                                                 (32, 4, 3), (32, 1, 1)])
 def test_hermite_mixed_shapes(ctx, variant, rows, waves, segments):
     sc = scenes.hermite_scene(14, npix=90, npix_y=70, seed=11)
     ref = oracle.eval_field(sc)
