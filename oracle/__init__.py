@@ -61,6 +61,11 @@ def _load():
                                          P, P, P, ctypes.c_int, P, ctypes.c_double, P, P, P, P, ctypes.c_int32,
                                          ctypes.c_int32, ctypes.c_double, ctypes.c_double, ctypes.c_int64, P, P,
                                          ctypes.c_int, P, P, P]
+        lib.oracle_trunc_terms.restype = ctypes.c_int
+        lib.oracle_trunc_terms.argtypes = [ctypes.c_int64, ctypes.c_double, ctypes.c_double, P, P, P,
+                                           ctypes.c_int64, P, P, P, ctypes.c_int, P, P, P, P, ctypes.c_int32,
+                                           ctypes.c_int32, ctypes.c_double, ctypes.c_double, ctypes.c_int64, P, P,
+                                           P, P]
         lib.oracle_trace.restype = ctypes.c_int
         lib.oracle_trace.argtypes = [ctypes.c_int32, P, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                      ctypes.c_int64, P, P, ctypes.c_double, ctypes.c_double, P, P, P]
@@ -83,6 +88,56 @@ def _f64(a):
     return None if a is None else np.ascontiguousarray(a, dtype=np.float64)
 
 
+def _subset(scene, keep):
+    """The scene restricted to the beamlets where keep is True."""
+    import copy
+    s = copy.copy(scene)
+    for name in ("r1", "th1", "amp", "path"):
+        setattr(s, name, np.ascontiguousarray(np.asarray(getattr(scene, name))[keep]))
+    w0 = np.atleast_1d(scene.w0)
+    s.w0 = np.ascontiguousarray(w0 if w0.size == 1 else w0[keep])
+    abcd = np.asarray(scene.abcd).reshape(-1, 16)
+    s.abcd = np.ascontiguousarray(abcd if abcd.shape[0] == 1 else abcd[keep])
+    s.edge = None
+    return s
+
+
+def _truncated_field(scene, edge, pixels, plane):
+    """Sum over truncated beamlets of E_j * erfc(zeta_j) / 2 (see
+    oracle_trunc_terms), formed with the scaled complex error function
+    erfcx(z) = e^(z^2) erfc(z) so that large |zeta| neither overflows nor
+    underflows: for Re zeta >= 0 the term is e^(log E - zeta^2) erfcx(zeta) / 2,
+    else E - e^(log E - zeta^2) erfcx(-zeta) / 2."""
+    import scipy.special
+    lib = _load()
+    r1, th1, w0, amp, path, abcd = (_f64(scene.r1), _f64(scene.th1), _f64(scene.w0), _f64(scene.amp),
+                                    _f64(scene.path), _f64(scene.abcd))
+    shared = 1 if abcd.shape[0] == 1 else 0
+    n = scene.n
+    if pixels is not None:
+        ix = np.ascontiguousarray(pixels[0], dtype=np.int32).ravel()
+        iy = np.ascontiguousarray(pixels[1], dtype=np.int32).ravel()
+        m = ix.size
+    else:
+        ix = iy = None
+        m = plane.nx * plane.ny
+    logE = np.empty((m, n, 2))
+    zeta = np.empty((m, n, 2))
+    rc = lib.oracle_trunc_terms(n, scene.lam, scene.l0, _ptr(r1), _ptr(th1), _ptr(w0), w0.size, _ptr(amp),
+                                _ptr(path), _ptr(abcd), shared, _ptr(_f64(edge)), _ptr(_f64(plane.origin)),
+                                _ptr(_f64(plane.normal)), _ptr(_f64(plane.xhint)), plane.nx, plane.ny, plane.dx,
+                                plane.dy, m, _ptr(ix), _ptr(iy), _ptr(logE), _ptr(zeta))
+    if rc != 0:
+        raise OracleError(rc)
+    lg = logE.view(np.complex128)[..., 0]
+    z = zeta.view(np.complex128)[..., 0]
+    pos = z.real >= 0
+    zz = np.where(pos, z, -z)
+    half = 0.5 * np.exp(lg - zz * zz) * scipy.special.erfcx(zz)
+    terms = np.where(pos, half, np.exp(lg) - half)
+    return terms.sum(axis=1)
+
+
 def eval_field(scene, model: int = 0, pixels: Optional[tuple] = None, extra_point=None,
                threads: Optional[int] = None):
     """Coherent field of ``scene`` on its detector plane, complex128.
@@ -90,7 +145,32 @@ def eval_field(scene, model: int = 0, pixels: Optional[tuple] = None, extra_poin
     model 0 = plane-evaluation, model 1 = exact paraxial point evaluation.
     pixels = (ix, iy) int arrays for a sample of pixels, else the full
     [ny][nx] grid.  extra_point = (a, b) plane coordinates also evaluated
-    (returned second)."""
+    (returned second).  Truncated beamlets (scene.edge rows with a nonzero
+    edge normal) are summed by _truncated_field, on planes normal to the
+    axis, where both models coincide."""
+    edge = getattr(scene, "edge", None)
+    if edge is not None:
+        edge = np.ascontiguousarray(edge, dtype=np.float64).reshape(-1, 3)
+        if getattr(scene, "order", None) is not None or getattr(scene, "base", None) is not None:
+            raise OracleError(-1)
+        cut = (edge[:, 0] != 0.0) | (edge[:, 1] != 0.0)
+        E = eval_field(_subset(scene, ~cut), model, pixels, None, threads) if (~cut).any() else None
+        Et = _truncated_field(_subset(scene, cut), edge[cut], pixels, scene.plane)
+        Et = Et.reshape(E.shape) if E is not None else (Et if pixels is not None else
+                                                         Et.reshape(scene.plane.ny, scene.plane.nx))
+        E = Et if E is None else E + Et
+        if extra_point is None:
+            return E
+        pl = scene.plane
+        e1 = np.asarray(pl.xhint, float) - np.dot(pl.xhint, pl.normal) / np.dot(pl.normal, pl.normal) * np.asarray(pl.normal, float)
+        e1 = e1 / np.linalg.norm(e1)
+        nrm = np.asarray(pl.normal, float) / np.linalg.norm(pl.normal)
+        e2 = np.cross(nrm, e1)
+        import copy
+        one = copy.copy(scene)
+        one.plane = type(pl)(np.asarray(pl.origin, float) + extra_point[0] * e1 + extra_point[1] * e2, pl.normal,
+                             pl.xhint, 1, 1, pl.dx, pl.dy)
+        return E, complex(eval_field(one, model, None, None, threads)[0, 0])
     lib = _load()
     pl = scene.plane
     r1, th1, w0, amp, path, abcd = (_f64(scene.r1), _f64(scene.th1), _f64(scene.w0), _f64(scene.amp),

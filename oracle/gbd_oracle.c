@@ -228,6 +228,10 @@ typedef struct {
      * d log E / dc = L w and d^2 log E / dc dc^T = H, c the input centre,
      * w = r - r2 */
     cplx L[2][2], H[2][2];
+    /* truncated beamlets: the envelope's derivatives with respect to the
+     * input slope th1 (centre fixed), d log E / d th1 = -i k lt w and
+     * d^2 log E / d th1^2 = i k ht */
+    cplx lt[2][2], ht[2][2];
 } or_prop;
 
 typedef struct {
@@ -319,6 +323,22 @@ static int propagate(const or_in *b, double z, or_prop *out) {
                 for (int t = 0; t < 2; t++) v -= Ap[r][i] * Q.m[r][t] * Ap[t][j];
             }
             out->H[i][j] = I * k * v;
+        }
+    /* Derivatives with respect to the input slope th1 (centre fixed): with
+     * dr2/dth1 = B', dth2/dth1 = D and dS/dth1 = B'^T th2 (the eikonal's
+     * end-point derivative), d log E / dth1 = -i k (D^T - B'^T Q) w, with no
+     * constant term, and its derivative -i k (D^T - B'^T Q)(-B'):
+     *   lt = D^T - B'^T Q,  ht = D^T B' - B'^T Q B' */
+    for (int i = 0; i < 2; i++)
+        for (int j = 0; j < 2; j++) {
+            cplx BQ = 0.0, v = 0.0; /* (B'^T Q)_ij, (D^T B' - B'^T Q B')_ij */
+            for (int r = 0; r < 2; r++) {
+                BQ += Bp[r][i] * Q.m[r][j];
+                v += D[r][i] * Bp[r][j];
+                for (int t = 0; t < 2; t++) v -= Bp[r][i] * Q.m[r][t] * Bp[t][j];
+            }
+            out->lt[i][j] = D[j][i] - BQ;
+            out->ht[i][j] = v;
         }
     return OR_OK;
 }
@@ -565,6 +585,99 @@ int oracle_eval_base(int64_t n, double lam, double l0, const double *r1, const d
 }
 
 /* oracle_eval: the same without traced base rays, symplectic tolerance 1e-10 */
+/*
+ * Truncated beamlets (Sec. 2.1 names truncated-beam solutions of the reduced
+ * Collins integral as usable in beamlet decomposition): the input envelope is
+ * cut by a straight edge, kept where e . r <= t (e a unit vector in the input
+ * plane).  The step function is a superposition of plane-wave tilts,
+ * H(t - e.r) = (1/2 pi) int ds int dkappa e^(i kappa (s - e.r)) over s <= t,
+ * and each tilted copy of the Gaussian propagates as a Gaussian whose log is
+ * quadratic in the tilt (derivatives lt, ht above); the two Gaussian
+ * integrals leave the factor
+ *     Phi = erfc(zeta) / 2,
+ *     zeta = (e . c - t + e^T lt w) / sqrt(-2 i e^T ht e / k)   (principal root),
+ * c the beamlet centre, w the offset from the base ray, so the truncated
+ * beamlet is its Gaussian field times Phi.
+ *
+ * oracle_trunc_terms writes, for every listed pixel p and beamlet j of the
+ * inputs (all taken as truncated, edge[j] = (e_x, e_y, t)), the complex log of
+ * the Gaussian term log E_jp (global phase l0 / lambda included) and zeta_jp,
+ * [npix][n][2] each, on a plane normal to the axis (plane evaluation is exact
+ * there; other planes: OR_EINVAL).  The caller forms E_jp Phi_jp with a
+ * complex error function.
+ */
+int oracle_trunc_terms(int64_t n, double lam, double l0, const double *r1, const double *th1,
+                       const double *w0, int64_t nw0, const double *amp, const double *path,
+                       const double *abcd, int shared_abcd, const double *edge,
+                       const double *origin, const double *normal, const double *xhint,
+                       int32_t nx, int32_t ny, double dx, double dy,
+                       int64_t npix, const int32_t *pix_ix, const int32_t *pix_iy,
+                       double *log_out, double *zeta_out) {
+    int rc = valid_inputs(n, lam, l0, r1, th1, w0, nw0, amp, path, abcd, shared_abcd, NULL, 1e-10);
+    if (rc) return rc;
+    if (n > 0 && !edge) return OR_EINVAL;
+    for (int64_t j = 0; j < n; j++) {
+        const double ex = edge[3 * j], ey = edge[3 * j + 1];
+        if (!isfinite(edge[3 * j + 2]) || fabs(ex * ex + ey * ey - 1.0) > 1e-12) return OR_EINVAL;
+    }
+    or_plane pl;
+    rc = make_plane(origin, normal, xhint, nx, ny, dx, dy, &pl);
+    if (rc) return rc;
+    int64_t m = pix_ix ? npix : (int64_t)nx * ny;
+    if (pix_ix) {
+        if (!pix_iy || npix < 0) return OR_EINVAL;
+        for (int64_t p = 0; p < npix; p++)
+            if (pix_ix[p] < 0 || pix_ix[p] >= nx || pix_iy[p] < 0 || pix_iy[p] >= ny) return OR_EINVAL;
+    }
+    or_beam_on_plane *bp = (or_beam_on_plane *)malloc(sizeof(or_beam_on_plane) * (size_t)(n > 0 ? n : 1));
+    cplx *zs = (cplx *)malloc(sizeof(cplx) * (size_t)(n > 0 ? n : 1));
+    if (!bp || !zs) { free(bp); free(zs); return OR_EINVAL; }
+    const double k = 2.0 * M_PI / lam;
+    for (int64_t j = 0; j < n; j++) {
+        or_in b = load_in(j, lam, l0, r1, th1, w0, nw0, amp, path, abcd, shared_abcd, NULL, NULL);
+        rc = beam_on_plane(&b, &pl, &bp[j]);
+        if (!rc && (bp[j].ez[0] != 0.0 || bp[j].ez[1] != 0.0)) rc = OR_EINVAL;
+        if (rc) { free(bp); free(zs); return rc; }
+        const double e[2] = {edge[3 * j], edge[3 * j + 1]};
+        cplx q = 0.0;
+        for (int r = 0; r < 2; r++)
+            for (int c = 0; c < 2; c++) q += e[r] * bp[j].P.ht[r][c] * e[c];
+        zs[j] = csqrt(-2.0 * I * q / k);
+    }
+    const cplx global = -2.0 * M_PI * I * reduce_turns(l0 / lam);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t p = 0; p < m; p++) {
+        int32_t ix = pix_ix ? pix_ix[p] : (int32_t)(p % nx);
+        int32_t iy = pix_ix ? pix_iy[p] : (int32_t)(p / nx);
+        double a = (ix - 0.5 * (nx - 1)) * dx;
+        double bb = (iy - 0.5 * (ny - 1)) * dy;
+        for (int64_t j = 0; j < n; j++) {
+            const or_beam_on_plane *o = &bp[j];
+            double d[2] = {a - o->arho, bb - o->brho};
+            double w[2] = {o->Pm[0][0] * d[0] + o->Pm[0][1] * d[1], o->Pm[1][0] * d[0] + o->Pm[1][1] * d[1]};
+            const double *th = o->P.th2;
+            const cm2 *Q = &o->P.Qinv;
+            cplx wQw = w[0] * (Q->m[0][0] * w[0] + Q->m[0][1] * w[1]) + w[1] * (Q->m[1][0] * w[0] + Q->m[1][1] * w[1]);
+            /* normal plane: zeta-free form of the plane-evaluation exponent */
+            cplx logE = clog(o->pref) - I * k * (th[0] * w[0] + th[1] * w[1]) - 0.5 * I * k * wQw + global;
+            const double e[2] = {edge[3 * j], edge[3 * j + 1]};
+            const double c[2] = {r1[2 * j], r1[2 * j + 1]};
+            cplx num = e[0] * c[0] + e[1] * c[1] - edge[3 * j + 2];
+            for (int r = 0; r < 2; r++)
+                for (int cc = 0; cc < 2; cc++) num += e[r] * o->P.lt[r][cc] * w[cc];
+            const cplx zeta = num / zs[j];
+            const int64_t at = 2 * (p * n + j);
+            log_out[at] = creal(logE);
+            log_out[at + 1] = cimag(logE);
+            zeta_out[at] = creal(zeta);
+            zeta_out[at + 1] = cimag(zeta);
+        }
+    }
+    free(bp);
+    free(zs);
+    return OR_OK;
+}
+
 int oracle_eval(int64_t n, double lam, double l0, const double *r1, const double *th1,
                 const double *w0, int64_t nw0, const double *amp, const double *path,
                 const double *abcd, int shared_abcd,

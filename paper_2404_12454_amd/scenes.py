@@ -85,6 +85,9 @@ class Scene:
     sympl_tol: Optional[float] = None
     # elegant Hermite-Gaussian orders [n,2] (m, n) in 0..2 per beamlet, or None (Gaussian)
     order: Optional[np.ndarray] = None
+    # truncating edges [n,3] = (e_x, e_y, t): beamlet j keeps e . r <= t of its input
+    # envelope (e a unit vector; e = (0, 0) leaves the beamlet whole), or None
+    edge: Optional[np.ndarray] = None
 
     @property
     def n(self) -> int:
