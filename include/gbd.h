@@ -165,6 +165,28 @@ int gbd_beamlets_traced(gbd_ctx_t ctx, gbd_beamlets_t *out, int64_t n, double la
 int gbd_beamlets_hg(gbd_ctx_t ctx, gbd_beamlets_t *out, int64_t n, double lambda, double l0, const double *r1,
                     const double *th1, const double *w0, int64_t n_w0, const double *amp, const double *path,
                     const double *abcd, int64_t n_abcd, const int32_t *order);
+/* --- truncated beamlets (Sec. 2.1: truncated-beam solutions of the reduced
+ * Collins integral serve in beamlet decomposition; Sec. 7.1: truncated
+ * beamlets for the hard edges of apertures) ------------------------------
+ * As gbd_beamlets, plus edge [n][3] (host, required for n > 0): beamlet j's
+ * input envelope is kept where e . r <= t, edge[j] = (e_x, e_y, t), e a unit
+ * vector (|e|^2 within 1e-12 of 1, else GBD_EINVAL) and t in metres in the
+ * input plane; e = (0, 0) leaves the beamlet whole.  On the detector a cut
+ * beamlet is its Gaussian field times erfc(zeta) / 2, zeta complex and
+ * linear in the offset from the base ray (the step function written as a
+ * superposition of tilts, each propagated as a Gaussian).  The library keeps
+ * the cut beamlets after the whole ones: the whole ones are evaluated in the
+ * chosen form (FP64, direct, stepped, rotor or separable), the cut ones by a
+ * direct-form kernel with the complex error function (Weideman's rational
+ * approximation of the Faddeeva function, N = 40 in FP64 and 20 in the mixed
+ * form), both into the same ordered segment sums.  Planes normal to the axis
+ * only (else GBD_EINVAL from the setup); a plane through an exact image of
+ * the input plane (B' = 0, an infinitely sharp edge) gives GBD_EINVAL
+ * (non-finite factor).  gbd_eval_point and gbd_eval_batch refuse cut
+ * beamlets (GBD_EINVAL). */
+int gbd_beamlets_truncated(gbd_ctx_t ctx, gbd_beamlets_t *out, int64_t n, double lambda, double l0,
+                           const double *r1, const double *th1, const double *w0, int64_t n_w0, const double *amp,
+                           const double *path, const double *abcd, int64_t n_abcd, const double *edge);
 void gbd_beamlets_free(gbd_beamlets_t b);
 
 /* --- detector plane (Sec. 3: the common evaluation plane) ----------------

@@ -24,7 +24,7 @@ __all__ = [
     "gbd_ctx_create", "gbd_beamlets", "gbd_plane", "gbd_eval", "gbd_plan_create", "gbd_plan_setup",
     "gbd_plan_eval", "gbd_plan_shape", "gbd_airy", "gbd_eval_batch", "gbd_eval_point", "gbd_autotune", "gbd_autotune_batch",
     "gbd_autotune_save", "gbd_autotune_load", "GBD_MLP_FP32", "GBD_MLP_BF16", "Mlp", "gbd_mlp_create", "beamlets_from_scene", "plane_from_scene",
-    "gbd_trace", "gbd_beamlets_traced", "gbd_beamlets_hg",
+    "gbd_trace", "gbd_beamlets_traced", "gbd_beamlets_hg", "gbd_beamlets_truncated",
     "Context", "Beamlets", "Plane", "Plan",
 ]
 
@@ -74,6 +74,7 @@ def load_library():
         "gbd_last_error": (ctypes.c_char_p, []),
         "gbd_beamlets": (ctypes.c_int, [P, PP, I64, D, D, P, P, P, I64, P, P, P, I64]),
         "gbd_beamlets_hg": (ctypes.c_int, [P, PP, I64, D, D, P, P, P, I64, P, P, P, I64, P]),
+        "gbd_beamlets_truncated": (ctypes.c_int, [P, PP, I64, D, D, P, P, P, I64, P, P, P, I64, P]),
         "gbd_beamlets_free": (None, [P]),
         "gbd_plane": (ctypes.c_int, [P, PP, P, P, P, I32, I32, D, D]),
         "gbd_plane_free": (None, [P]),
@@ -205,6 +206,21 @@ def gbd_beamlets_hg(ctx: Context, n: int, lam: float, l0: float, r1, th1, w0, am
     return Beamlets(h, int(n))
 
 
+def gbd_beamlets_truncated(ctx: Context, n: int, lam: float, l0: float, r1, th1, w0, amp, path, abcd,
+                           edge) -> Beamlets:
+    """Beamlets whose input envelopes are cut by straight edges, edge [n,3] =
+    (e_x, e_y, t) keeping e . r <= t (e = (0, 0): whole) (see gbd.h)."""
+    r1, th1, w0, amp, path, abcd, edge = map(_f64, (r1, th1, w0, amp, path, abcd, edge))
+    w0 = np.atleast_1d(w0) if w0 is not None else None
+    abcd = None if abcd is None else abcd.reshape(-1, 16)
+    edge = None if edge is None else edge.reshape(-1, 3)
+    h = ctypes.c_void_p()
+    _check(load_library().gbd_beamlets_truncated(ctx.handle, ctypes.byref(h), int(n), float(lam), float(l0), _p(r1),
+                                                 _p(th1), _p(w0), 0 if w0 is None else w0.size, _p(amp), _p(path),
+                                                 _p(abcd), 0 if abcd is None else abcd.shape[0], _p(edge)))
+    return Beamlets(h, int(n))
+
+
 def gbd_plane(ctx: Context, origin, normal, xhint, nx: int, ny: int, dx: float, dy: float) -> Plane:
     o, n, x = _f64(origin), _f64(normal), _f64(xhint)
     h = ctypes.c_void_p()
@@ -242,6 +258,10 @@ def gbd_beamlets_traced(ctx: Context, n: int, lam: float, l0: float, r1, th1, w0
 
 
 def beamlets_from_scene(ctx: Context, s) -> Beamlets:
+    if getattr(s, "edge", None) is not None:
+        if getattr(s, "base", None) is not None or getattr(s, "order", None) is not None:
+            raise ValueError("truncated beamlets take neither traced inputs nor higher orders")
+        return gbd_beamlets_truncated(ctx, s.n, s.lam, s.l0, s.r1, s.th1, s.w0, s.amp, s.path, s.abcd, s.edge)
     if getattr(s, "order", None) is not None:
         if getattr(s, "base", None) is not None:
             raise ValueError("traced inputs of higher-order beamlets are not supported")

@@ -73,6 +73,9 @@ struct gbd_plan_s {
     Rec32 *r32;
     RecHG64 *h64;  // Hermite-Gaussian factors, allocated at the first setup of higher-order beamlets
     RecHG32 *h32;
+    RecCut64 *c64;  // truncation factors, allocated at the first setup of truncated beamlets
+    RecCut32 *c32;
+    int64_t n_cut;  // truncated beamlets of the last setup (the last n_cut records)
     uint32_t *status_dev;
     uint32_t *status_host;  // pinned
     void *scratch;
@@ -302,6 +305,55 @@ EvalGeom make_geom(const PlaneGeom &pl, int64_t n, const Shape &s) {
     return g;
 }
 
+// Weideman's coefficients for the Faddeeva function (FaddeevaCoef): a_n,
+// n = 1..N, are the Fourier coefficients of the even, 2 pi-periodic
+// F(theta) = e^(-s^2) (L^2 + s^2), s = L tan(theta / 2), taken by the
+// midpoint rule (spectrally accurate for a smooth periodic integrand).
+void weideman(int N, double *L, double *a) {
+    *L = std::sqrt(N / std::sqrt(2.0));
+    const int K = 4096;
+    const double pi = 3.14159265358979323846;
+    for (int n = 1; n <= N; n++) {
+        double acc = 0.0;
+        for (int i = 0; i < K; i++) {
+            const double th = -pi + (i + 0.5) * 2.0 * pi / K;
+            const double t = *L * std::tan(0.5 * th);
+            acc += std::exp(-t * t) * (*L * *L + t * t) * std::cos(n * th);
+        }
+        a[n - 1] = acc / K;
+    }
+}
+
+const FaddeevaCoef &faddeeva_coef() {
+    static const FaddeevaCoef fc = [] {
+        FaddeevaCoef f{};
+        weideman(kFaddeevaN64, &f.L64, f.a64);
+        double L32, a32[kFaddeevaN32];
+        weideman(kFaddeevaN32, &L32, a32);
+        f.L32 = (float)L32;
+        for (int i = 0; i < kFaddeevaN32; i++) f.a32[i] = (float)a32[i];
+        return f;
+    }();
+    return fc;
+}
+
+// Launch geometry of the truncated-beamlet kernel: 64-column tiles of
+// 4 wavefronts x kCutRows rows, segments for ~6 wavefronts per SIMD, each
+// segment at least 32 beamlets.
+EvalGeom cut_geom(const gbd_ctx_s *ctx, int precision, const PlaneGeom &pl, int64_t n_cut) {
+    Shape s;
+    s.form = 0;
+    s.waves = 4;
+    s.rows = precision == GBD_MIXED ? kCutRows32 : kCutRows64;
+    const int64_t tx = (pl.nx + 63) / 64;
+    const int64_t ty = (pl.ny + s.waves * s.rows - 1) / (s.waves * s.rows);
+    const int64_t tiles = std::max<int64_t>(1, tx * ty);
+    int64_t seg = ((int64_t)ctx->cus * 6 + tiles - 1) / tiles;
+    seg = std::min<int64_t>(seg, std::max<int64_t>(1, n_cut / 32));
+    s.nseg = (int)std::max<int64_t>(1, std::min<int64_t>(seg, 1024));
+    return make_geom(pl, n_cut, s);
+}
+
 int plan_eval_impl(gbd_ctx_s *ctx, gbd_plan_s *plan, int precision, void *out, int64_t out_bytes,
                    const gbd_eval_opts *opts) {
     if (!plan->ready) return fail(GBD_EINVAL, "gbd_plan_eval: plan has no valid setup");
@@ -315,7 +367,7 @@ int plan_eval_impl(gbd_ctx_s *ctx, gbd_plan_s *plan, int precision, void *out, i
     if (opts && (opts->variant < 0 || opts->variant > 4)) return fail(GBD_EINVAL, "variant must be 0 ... 4");
     if (opts && opts->rows_per_lane && !valid_shape(opts->rows_per_lane, opts->waves ? opts->waves : 4, precision))
         return fail(GBD_EINVAL, "unsupported rows_per_lane %d / waves %d", opts->rows_per_lane, opts->waves);
-    Shape s = choose_shape(ctx, precision, plan->n, plan->pl, plan->flags, opts);
+    Shape s = choose_shape(ctx, precision, plan->n - plan->n_cut, plan->pl, plan->flags, opts);
     if (s.form != 3 && !valid_shape(s.rows, s.waves, precision))
         return fail(GBD_EINVAL, "unsupported rows_per_lane %d / waves %d", s.rows, s.waves);
     int rc = ensure_device(ctx);
@@ -324,11 +376,27 @@ int plan_eval_impl(gbd_ctx_s *ctx, gbd_plan_s *plan, int precision, void *out, i
         HIP_TRY(hipMemsetAsync(out, 0, (size_t)(M * elem), ctx->stream), "hipMemsetAsync");
         return GBD_OK;
     }
-    EvalGeom g = make_geom(plan->pl, plan->n, s);
-    if ((int64_t)g.tiles_x * g.tiles_y * g.nseg > (int64_t)0x7fffffff - 8)
-        return fail(GBD_ERANGE, "grid too large");
-    if (g.nseg > 1) {
-        const size_t need = (size_t)g.nseg * (size_t)M * 16;
+    // the whole beamlets [0, n_main) in the chosen form; truncated ones
+    // [n_main, n) by their own kernel into the following segments
+    const int64_t n_main = plan->n - plan->n_cut;
+    EvalGeom g{}, gc{};
+    int32_t nseg_main = 0, nseg_cut = 0;
+    if (n_main > 0) {
+        g = make_geom(plan->pl, n_main, s);
+        if ((int64_t)g.tiles_x * g.tiles_y * g.nseg > (int64_t)0x7fffffff - 8)
+            return fail(GBD_ERANGE, "grid too large");
+        nseg_main = g.nseg;
+    }
+    if (plan->n_cut > 0) {
+        gc = cut_geom(ctx, precision, plan->pl, plan->n_cut);
+        if ((int64_t)gc.tiles_x * gc.tiles_y * gc.nseg > (int64_t)0x7fffffff - 8)
+            return fail(GBD_ERANGE, "grid too large");
+        nseg_cut = gc.nseg;
+    }
+    const int32_t total = nseg_main + nseg_cut;
+    const bool reduce = total > 1 || nseg_cut > 0;
+    if (reduce) {
+        const size_t need = (size_t)total * (size_t)M * 16;
         if (need > plan->scratch_bytes) {
             if (plan->scratch) (void)hipFree(plan->scratch);
             plan->scratch = nullptr;
@@ -337,17 +405,31 @@ int plan_eval_impl(gbd_ctx_s *ctx, gbd_plan_s *plan, int precision, void *out, i
             plan->scratch_bytes = need;
         }
     }
-    const void *rec = precision == GBD_FP64 ? (const void *)plan->r64 : (const void *)plan->r32;
-    const bool hg = (plan->flags & FLAG_HG) != 0;
-    const void *hrec = !hg ? nullptr : precision == GBD_FP64 ? (const void *)plan->h64 : (const void *)plan->h32;
-    if (s.form == 3)
-        HIP_TRY(launch_eval_sep(g, plan->r32, static_cast<const RecHG32 *>(hrec), static_cast<float4 *>(plan->scratch),
-                                static_cast<float2 *>(out), ctx->stream),
-                "eval kernel launch");
-    else
-        HIP_TRY(launch_eval(precision, s.rows, s.waves, s.form, g, rec, hrec, plan->scratch, out, ctx->stream),
-                "eval kernel launch");
-    if (g.nseg > 1) HIP_TRY(launch_reduce(precision, g, plan->scratch, out, ctx->stream), "reduce kernel launch");
+    if (n_main > 0) {
+        const void *rec = precision == GBD_FP64 ? (const void *)plan->r64 : (const void *)plan->r32;
+        const bool hg = (plan->flags & FLAG_HG) != 0;
+        const void *hrec = !hg ? nullptr : precision == GBD_FP64 ? (const void *)plan->h64 : (const void *)plan->h32;
+        EvalGeom gl = g;
+        if (reduce) gl.nseg = std::max<int32_t>(total, 2);  // segment partials, never the output
+        if (s.form == 3)
+            HIP_TRY(launch_eval_sep(gl, plan->r32, static_cast<const RecHG32 *>(hrec),
+                                    static_cast<float4 *>(plan->scratch), static_cast<float2 *>(out), ctx->stream),
+                    "eval kernel launch");
+        else
+            HIP_TRY(launch_eval(precision, s.rows, s.waves, s.form, gl, rec, hrec, plan->scratch, out, ctx->stream),
+                    "eval kernel launch");
+    }
+    if (nseg_cut > 0) {
+        const void *rec = precision == GBD_FP64 ? (const void *)(plan->r64 + n_main) : (const void *)(plan->r32 + n_main);
+        const void *crec = precision == GBD_FP64 ? (const void *)plan->c64 : (const void *)plan->c32;
+        HIP_TRY(launch_eval_cut(precision, gc, rec, crec, faddeeva_coef(), nseg_main, plan->scratch, ctx->stream),
+                "truncated-beamlet kernel launch");
+    }
+    if (reduce) {
+        EvalGeom gr = n_main > 0 ? g : gc;
+        gr.nseg = total;
+        HIP_TRY(launch_reduce(precision, gr, plan->scratch, out, ctx->stream), "reduce kernel launch");
+    }
     return GBD_OK;
 }
 
@@ -360,6 +442,12 @@ int plan_setup_impl(gbd_ctx_s *ctx, gbd_plan_s *plan, gbd_beamlets_s *b, gbd_pla
     plan->flags = 0;
     plan->n = b->dev.n;
     plan->pl = p->g;
+    plan->n_cut = b->dev.n_cut;
+    if (b->dev.n_cut > 0 && (!plan->c64 || !plan->c32)) {
+        const size_t cap = (size_t)std::max<int64_t>(1, plan->capacity);
+        if (!plan->c64) HIP_TRY(hipMalloc(&plan->c64, cap * sizeof(RecCut64)), "hipMalloc(truncation records)");
+        if (!plan->c32) HIP_TRY(hipMalloc(&plan->c32, cap * sizeof(RecCut32)), "hipMalloc(truncation records)");
+    }
     if (b->dev.order && (!plan->h64 || !plan->h32)) {
         const size_t cap = (size_t)std::max<int64_t>(1, plan->capacity);
         if (!plan->h64) HIP_TRY(hipMalloc(&plan->h64, cap * sizeof(RecHG64)), "hipMalloc(Hermite-Gaussian records)");
@@ -371,8 +459,10 @@ int plan_setup_impl(gbd_ctx_s *ctx, gbd_plan_s *plan, gbd_beamlets_s *b, gbd_pla
         const double gturns = g0 - nearbyint(g0);
         HIP_TRY(hipMemsetAsync(plan->status_dev, 0, sizeof(uint32_t), ctx->stream), "hipMemsetAsync(status)");
         const bool hg = b->dev.order != nullptr;
+        const bool cut = b->dev.n_cut > 0;
         HIP_TRY(launch_setup(b->dev, p->g, gturns, plan->r64, plan->r32, hg ? plan->h64 : nullptr,
-                             hg ? plan->h32 : nullptr, plan->status_dev, ctx->stream),
+                             hg ? plan->h32 : nullptr, cut ? plan->c64 : nullptr, cut ? plan->c32 : nullptr,
+                             plan->status_dev, ctx->stream),
                 "setup kernel launch");
         HIP_TRY(hipMemcpyAsync(plan->status_host, plan->status_dev, sizeof(uint32_t), hipMemcpyDeviceToHost,
                                ctx->stream),
@@ -384,7 +474,7 @@ int plan_setup_impl(gbd_ctx_s *ctx, gbd_plan_s *plan, gbd_beamlets_s *b, gbd_pla
             return fail(GBD_EBRANCH, "an eigenvalue of A + B Q1^-1 lies off the principal branch (inverting system)");
         if (st & FLAG_NONFINITE) return fail(GBD_EINVAL, "non-finite beamlet parameters after propagation");
         if (st & FLAG_HG_TILT)
-            return fail(GBD_EINVAL, "higher-order beamlets need a detector plane normal to the axis");
+            return fail(GBD_EINVAL, "higher-order and truncated beamlets need a detector plane normal to the axis");
         plan->flags = st & (FLAG_STEEP | FLAG_CROSS | FLAG_HG);
     }
     plan->ready = true;
@@ -397,6 +487,8 @@ void plan_destroy(gbd_plan_s *plan) {
     if (plan->r32) (void)hipFree(plan->r32);
     if (plan->h64) (void)hipFree(plan->h64);
     if (plan->h32) (void)hipFree(plan->h32);
+    if (plan->c64) (void)hipFree(plan->c64);
+    if (plan->c32) (void)hipFree(plan->c32);
     if (plan->status_dev) (void)hipFree(plan->status_dev);
     if (plan->status_host) (void)hipHostFree(plan->status_host);
     if (plan->scratch) (void)hipFree(plan->scratch);
@@ -482,7 +574,7 @@ void gbd_ctx_destroy(gbd_ctx_t ctx) {
 static int beamlets_impl(gbd_ctx_t ctx, gbd_beamlets_t *out, int64_t n, double lambda, double l0, const double *r1,
                   const double *th1, const double *w0, int64_t n_w0, const double *amp, const double *path,
                   const double *abcd, int64_t n_abcd, const double *base, double sympl_tol,
-                  const int32_t *order = nullptr) {
+                  const int32_t *order = nullptr, const double *edge = nullptr) {
     if (!ctx || !out) return fail(GBD_EINVAL, "ctx/out is NULL");
     if (!(sympl_tol > 0.0 && sympl_tol <= 1e-3)) return fail(GBD_EINVAL, "sympl_tol must be in (0, 1e-3]");
     if (n < 0) return fail(GBD_EINVAL, "n < 0");
@@ -505,36 +597,72 @@ static int beamlets_impl(gbd_ctx_t ctx, gbd_beamlets_t *out, int64_t n, double l
                 if (order[i] < 0 || order[i] > 2)
                     return fail(GBD_EINVAL, "order[%lld][%lld] = %d is outside 0 ... 2", (long long)(i / 2),
                                 (long long)(i % 2), order[i]);
+        if (edge) {
+            if (!finite_all(edge, 3 * n)) return fail(GBD_EINVAL, "non-finite edge");
+            for (int64_t i = 0; i < n; i++) {
+                const double ex = edge[3 * i], ey = edge[3 * i + 1];
+                if ((ex != 0.0 || ey != 0.0) && !(std::fabs(ex * ex + ey * ey - 1.0) <= 1e-12))
+                    return fail(GBD_EINVAL, "edge[%lld]: the normal (e_x, e_y) must have unit length", (long long)i);
+            }
+        }
     } else {
         n_w0 = 1;
         n_abcd = 1;
         base = nullptr;
         order = nullptr;
+        edge = nullptr;
+    }
+    // truncated beamlets are stored last (stable order otherwise): the
+    // evaluation gives them a kernel of their own
+    std::vector<int64_t> perm((size_t)std::max<int64_t>(n, 0));
+    int64_t n_cut = 0;
+    {
+        size_t at = 0;
+        for (int64_t i = 0; i < n; i++)
+            if (!edge || (edge[3 * i] == 0.0 && edge[3 * i + 1] == 0.0)) perm[at++] = i;
+        for (int64_t i = 0; i < n; i++)
+            if (edge && (edge[3 * i] != 0.0 || edge[3 * i + 1] != 0.0)) {
+                perm[at++] = i;
+                n_cut++;
+            }
     }
     bool higher = false;
     if (order)
         for (int64_t i = 0; i < 2 * n && !higher; i++) higher = order[i] != 0;
     int rc = ensure_device(ctx);
     if (rc) return rc;
-    // one device block: r1, th1, amp [n][2]; w0 [n_w0]; path [n]; abcd [n_abcd][16]; base [n][5]
+    // one device block: r1, th1, amp [n][2]; w0 [n_w0]; path [n]; abcd [n_abcd][16]; base [n][5];
+    // edge [n][3]; orders [n][2] int32 packed into the trailing n doubles
     const size_t nn = (size_t)std::max<int64_t>(n, 1);
     const size_t off_r1 = 0, off_th1 = off_r1 + 2 * nn, off_amp = off_th1 + 2 * nn, off_w0 = off_amp + 2 * nn,
                  off_path = off_w0 + (size_t)n_w0, off_abcd = off_path + nn, off_base = off_abcd + 16 * (size_t)n_abcd,
-                 off_order = off_base + (base ? 5 * nn : 0), total = off_order + (order ? nn : 0);
-    // orders: [n][2] int32 packed into the trailing n doubles
+                 off_edge = off_base + (base ? 5 * nn : 0), off_order = off_edge + (edge ? 3 * nn : 0),
+                 total = off_order + (order ? nn : 0);
     std::vector<double> host(total, 0.0);
     if (n > 0) {
-        memcpy(&host[off_r1], r1, 2 * n * sizeof(double));
-        if (th1) memcpy(&host[off_th1], th1, 2 * n * sizeof(double));
-        if (amp)
-            memcpy(&host[off_amp], amp, 2 * n * sizeof(double));
-        else
-            for (int64_t j = 0; j < n; j++) host[off_amp + 2 * j] = 1.0;
-        memcpy(&host[off_w0], w0, n_w0 * sizeof(double));
-        if (path) memcpy(&host[off_path], path, n * sizeof(double));
-        memcpy(&host[off_abcd], abcd, 16 * n_abcd * sizeof(double));
-        if (base) memcpy(&host[off_base], base, 5 * n * sizeof(double));
-        if (order) memcpy(&host[off_order], order, 2 * n * sizeof(int32_t));
+        int32_t *ord = reinterpret_cast<int32_t *>(&host[off_order]);
+        if (n_w0 == 1) host[off_w0] = w0[0];
+        if (n_abcd == 1) memcpy(&host[off_abcd], abcd, 16 * sizeof(double));
+        for (int64_t i = 0; i < n; i++) {
+            const int64_t j = perm[i];
+            host[off_r1 + 2 * i] = r1[2 * j];
+            host[off_r1 + 2 * i + 1] = r1[2 * j + 1];
+            if (th1) {
+                host[off_th1 + 2 * i] = th1[2 * j];
+                host[off_th1 + 2 * i + 1] = th1[2 * j + 1];
+            }
+            host[off_amp + 2 * i] = amp ? amp[2 * j] : 1.0;
+            host[off_amp + 2 * i + 1] = amp ? amp[2 * j + 1] : 0.0;
+            if (n_w0 == n) host[off_w0 + i] = w0[j];
+            if (path) host[off_path + i] = path[j];
+            if (n_abcd == n) memcpy(&host[off_abcd + 16 * i], abcd + 16 * j, 16 * sizeof(double));
+            if (base) memcpy(&host[off_base + 5 * i], base + 5 * j, 5 * sizeof(double));
+            if (edge) memcpy(&host[off_edge + 3 * i], edge + 3 * j, 3 * sizeof(double));
+            if (order) {
+                ord[2 * i] = order[2 * j];
+                ord[2 * i + 1] = order[2 * j + 1];
+            }
+        }
     } else {
         host[off_w0] = 1.0;
         for (int i = 0; i < 4; i++) host[off_abcd + 5 * i] = 1.0;
@@ -568,6 +696,8 @@ static int beamlets_impl(gbd_ctx_t ctx, gbd_beamlets_t *out, int64_t n, double l
     b->dev.abcd = d + off_abcd;
     b->dev.base = base ? d + off_base : nullptr;
     b->dev.order = order ? reinterpret_cast<const int32_t *>(d + off_order) : nullptr;
+    b->dev.edge = edge ? d + off_edge : nullptr;
+    b->dev.n_cut = n_cut;
     b->higher_order = higher;
     *out = b;
     return GBD_OK;
@@ -591,6 +721,14 @@ int gbd_beamlets_hg(gbd_ctx_t ctx, gbd_beamlets_t *out, int64_t n, double lambda
                     const double *abcd, int64_t n_abcd, const int32_t *order) {
     if (n > 0 && !order) return fail(GBD_EINVAL, "order is NULL");
     return beamlets_impl(ctx, out, n, lambda, l0, r1, th1, w0, n_w0, amp, path, abcd, n_abcd, nullptr, 1e-10, order);
+}
+
+int gbd_beamlets_truncated(gbd_ctx_t ctx, gbd_beamlets_t *out, int64_t n, double lambda, double l0,
+                           const double *r1, const double *th1, const double *w0, int64_t n_w0, const double *amp,
+                           const double *path, const double *abcd, int64_t n_abcd, const double *edge) {
+    if (n > 0 && !edge) return fail(GBD_EINVAL, "edge is NULL");
+    return beamlets_impl(ctx, out, n, lambda, l0, r1, th1, w0, n_w0, amp, path, abcd, n_abcd, nullptr, 1e-10,
+                         nullptr, edge);
 }
 
 int gbd_trace(gbd_ctx_t ctx, int32_t n_mirrors, const double *mirrors, double z_in, double z_out, double l0,
@@ -705,8 +843,8 @@ void gbd_plan_free(gbd_plan_t plan) { plan_destroy(plan); }
 
 int gbd_plan_shape(gbd_ctx_t ctx, gbd_plan_t plan, int precision, const gbd_eval_opts *opts, gbd_eval_opts *resolved) {
     if (!ctx || !plan || !resolved) return fail(GBD_EINVAL, "NULL argument");
-    Shape s = choose_shape(ctx, precision, plan->n, plan->pl, plan->flags, opts);
-    EvalGeom g = make_geom(plan->pl, plan->n, s);
+    Shape s = choose_shape(ctx, precision, plan->n - plan->n_cut, plan->pl, plan->flags, opts);
+    EvalGeom g = make_geom(plan->pl, plan->n - plan->n_cut, s);
     resolved->rows_per_lane = s.rows;
     resolved->waves = s.waves;
     resolved->segments = g.nseg;
@@ -788,8 +926,8 @@ int gbd_autotune(gbd_ctx_t ctx, gbd_plan_t plan, int precision, int32_t reps, gb
     if (he != hipSuccess) return hip_fail(he, "autotune timing");
     ctx->tuned[tune_key(0, precision, plan->n, M)] = bestv;
     if (best) {
-        const Shape s = choose_shape(ctx, precision, plan->n, plan->pl, plan->flags, nullptr);
-        const EvalGeom g = make_geom(plan->pl, plan->n, s);
+        const Shape s = choose_shape(ctx, precision, plan->n - plan->n_cut, plan->pl, plan->flags, nullptr);
+        const EvalGeom g = make_geom(plan->pl, plan->n - plan->n_cut, s);
         *best = gbd_eval_opts{s.rows, s.waves, g.nseg, form_variant(precision, s.form)};
     }
     if (best_ms) *best_ms = bestv.ms;
@@ -831,7 +969,8 @@ int gbd_autotune_load(gbd_ctx_t ctx, const char *path) {
 
 int gbd_eval_point(gbd_ctx_t ctx, gbd_beamlets_t b, gbd_plane_t p, void *field_out, int64_t out_bytes) {
     if (!ctx || !b || !p) return fail(GBD_EINVAL, "NULL argument");
-    if (b->higher_order) return fail(GBD_EINVAL, "point evaluation takes fundamental Gaussian beamlets only");
+    if (b->higher_order || b->dev.n_cut > 0)
+        return fail(GBD_EINVAL, "point evaluation takes whole fundamental Gaussian beamlets only");
     const int64_t M = (int64_t)p->g.nx * p->g.ny;
     if (M == 0) return GBD_OK;
     if (!field_out) return fail(GBD_EINVAL, "field_out is NULL");
@@ -894,8 +1033,8 @@ int gbd_eval_batch(gbd_ctx_t ctx, int32_t n_inst, const gbd_beamlets_t *bs, cons
     int64_t pairs = 0;
     for (int32_t i = 0; i < n_inst; i++) {
         if (!bs[i] || !ps[i]) return fail(GBD_EINVAL, "instance %d has a NULL handle", i);
-        if (bs[i]->higher_order)
-            return fail(GBD_EINVAL, "instance %d: the batched sweep takes fundamental Gaussian beamlets only", i);
+        if (bs[i]->higher_order || bs[i]->dev.n_cut > 0)
+            return fail(GBD_EINVAL, "instance %d: the batched sweep takes whole fundamental Gaussian beamlets only", i);
         pairs += bs[i]->dev.n * ((int64_t)ps[i]->g.nx * ps[i]->g.ny);
     }
     if (!(opts && (opts->rows_per_lane || opts->waves))) {

@@ -59,9 +59,13 @@ __device__ inline double il2_dev() { return 1.4426950408889634074; }  // 1 / ln 
 // pointer may be null) and returns FLAG_* bits (0 = fine).
 // Higher-order beamlets: h64 / h32 (either may be null) receive the
 // Hermite-Gaussian factor's coefficients of every beamlet (orders (0, 0)
-// give the factor 1).
+// give the factor 1).  Truncated beamlets (j >= n - n_cut): c64 / c32
+// receive the truncation factor's coefficients at j - (n - n_cut); their
+// FLAG_STEEP / FLAG_CROSS are not reported (they are evaluated by the
+// direct form of their own kernel).
 __device__ inline uint32_t setup_one(const BeamletsDev &b, const PlaneGeom &pl, double gturns, int64_t j,
-                                     Rec64 *r64, Rec32 *r32, RecHG64 *h64 = nullptr, RecHG32 *h32 = nullptr) {
+                                     Rec64 *r64, Rec32 *r32, RecHG64 *h64 = nullptr, RecHG32 *h32 = nullptr,
+                                     RecCut64 *c64 = nullptr, RecCut32 *c32 = nullptr) {
     const double *M = b.abcd + (b.n_abcd == 1 ? 0 : 16 * j);
     double A[2][2], B[2][2], C[2][2], D[2][2];
 #pragma unroll
@@ -100,6 +104,9 @@ __device__ inline uint32_t setup_one(const BeamletsDev &b, const PlaneGeom &pl, 
     Rec64 o64 = {};
     Rec32 o32 = {};
     RecHG64 oh = {};
+    RecCut64 oc = {};
+    const int64_t cut0 = b.n - b.n_cut;
+    const bool is_cut = b.edge && j >= cut0;
     uint32_t flag = 0;
     if (!(fabs(nd) > 1e-6 * dl)) {
         flag |= FLAG_PARALLEL;
@@ -263,9 +270,60 @@ __device__ inline uint32_t setup_one(const BeamletsDev &b, const PlaneGeom &pl, 
             const double *hv = &oh.g[0][0][0];
             for (int i = 0; i < (int)(sizeof(RecHG64) / sizeof(double)); i++) fin = fin && isfinite(hv[i]);
         }
+        if (is_cut) {
+            // truncation by the edge e . r <= t: with B' = B + z D the envelope's
+            // slope derivatives are lt = D^T - B'^T Q and ht = D^T B' - B'^T Q B';
+            // zeta = (e . c - t + e^T lt w) / sqrt(-2 i e^T ht e / k), w = Pm d
+            const double *ed = b.edge + 3 * j;
+            const double e[2] = {ed[0], ed[1]};
+            const double k = 2.0 * kPi / lam;
+            double Bp[2][2];
+#pragma unroll
+            for (int r = 0; r < 2; r++)
+#pragma unroll
+                for (int c = 0; c < 2; c++) Bp[r][c] = B[r][c] + z * D[r][c];
+            cd lt[2][2], ht[2][2];
+#pragma unroll
+            for (int r = 0; r < 2; r++)
+#pragma unroll
+                for (int c = 0; c < 2; c++) {
+                    // (B'^T Q)_rc and (B'^T Q B')_rc
+                    const cd bq = add(scl(Q[0][c], Bp[0][r]), scl(Q[1][c], Bp[1][r]));
+                    lt[r][c] = sub(mk(D[c][r], 0.0), bq);
+                    cd bqb = mk(0.0, 0.0);
+#pragma unroll
+                    for (int t = 0; t < 2; t++)
+                        bqb = add(bqb, scl(add(scl(Q[0][t], Bp[0][r]), scl(Q[1][t], Bp[1][r])), Bp[t][c]));
+                    ht[r][c] = sub(mk(D[0][r] * Bp[0][c] + D[1][r] * Bp[1][c], 0.0), bqb);
+                }
+            cd q = mk(0.0, 0.0);
+#pragma unroll
+            for (int r = 0; r < 2; r++)
+#pragma unroll
+                for (int c = 0; c < 2; c++) q = add(q, scl(ht[r][c], e[r] * e[c]));
+            const cd sq = csqrt_p(mk(2.0 * q.im / k, -2.0 * q.re / k));
+            const cd n0 = mk(e[0] * r1[0] + e[1] * r1[1] - ed[2], 0.0);
+            cd na = mk(0.0, 0.0), nb = mk(0.0, 0.0);
+#pragma unroll
+            for (int r = 0; r < 2; r++)
+#pragma unroll
+                for (int c = 0; c < 2; c++) {
+                    na = add(na, scl(lt[r][c], e[r] * Pm[c][0]));
+                    nb = add(nb, scl(lt[r][c], e[r] * Pm[c][1]));
+                }
+            const cd z0 = cdiv(n0, sq), za = cdiv(na, sq), zb = cdiv(nb, sq);
+            oc.z0[0] = z0.re;
+            oc.z0[1] = z0.im;
+            oc.za[0] = za.re;
+            oc.za[1] = za.im;
+            oc.zb[0] = zb.re;
+            oc.zb[1] = zb.im;
+            for (int i = 0; i < 6; i++) fin = fin && isfinite((&oc.z0[0])[i]);
+            if (ez[0] != 0.0 || ez[1] != 0.0) flag |= FLAG_HG_TILT;
+        }
         if (!fin) flag |= FLAG_NONFINITE;
-        if (fabs(l[5]) * il2_dev() * pl.dy * pl.dy > kStepCurvature) flag |= FLAG_STEEP;
-        if (p[4] != 0.0 || l[4] != 0.0) flag |= FLAG_CROSS;
+        if (!is_cut && fabs(l[5]) * il2_dev() * pl.dy * pl.dy > kStepCurvature) flag |= FLAG_STEEP;
+        if (!is_cut && (p[4] != 0.0 || l[4] != 0.0)) flag |= FLAG_CROSS;
         o64.arho = arho;
         o64.brho = brho;
         o32.arho = arho;
@@ -309,6 +367,18 @@ __device__ inline uint32_t setup_one(const BeamletsDev &b, const PlaneGeom &pl, 
     }
     if (r64) r64[j] = o64;
     if (r32) r32[j] = o32;
+    if (is_cut && c64) c64[j - cut0] = oc;
+    if (is_cut && c32) {
+        RecCut32 o;
+#pragma unroll
+        for (int i = 0; i < 2; i++) {
+            o.z0[i] = (float)oc.z0[i];
+            o.za[i] = (float)oc.za[i];
+            o.zb[i] = (float)oc.zb[i];
+            o.pad[i] = 0.0f;
+        }
+        c32[j - cut0] = o;
+    }
     if (h64) h64[j] = oh;
     if (h32) {
         RecHG32 o;

@@ -29,6 +29,8 @@ struct BeamletsDev {
     const double *base;  // [n][5] traced base ray at the output plane (x, y, l, m,
                          // optical path - l0), or null: the ab/cd laws
     const int32_t *order;  // [n][2] elegant Hermite-Gaussian orders (m, n) in 0..2, or null
+    const double *edge;    // [n][3] truncating edges (e_x, e_y, t): keep e . r <= t, or null
+    int64_t n_cut;         // truncated beamlets; they are stored last, [n - n_cut, n)
 };
 
 // Per-beamlet phasor on the plane, about the base-ray hit point (a_rho, b_rho):
@@ -87,12 +89,40 @@ struct alignas(16) RecHG32 {
 };
 static_assert(sizeof(RecHG32) == 96, "RecHG32 layout");
 
+// Truncation factor of a cut beamlet (Gaussian envelope kept on one side of
+// a straight edge) on a plane normal to the axis: erfc(zeta) / 2 with
+//   zeta = z0 + za da + zb db,  d = (da, db) the offset from the hit point.
+struct alignas(16) RecCut64 {
+    double z0[2], za[2], zb[2];
+    double pad[2];
+};
+static_assert(sizeof(RecCut64) == 64, "RecCut64 layout");
+struct alignas(16) RecCut32 {
+    float z0[2], za[2], zb[2];
+    float pad[2];
+};
+static_assert(sizeof(RecCut32) == 32, "RecCut32 layout");
+
+// Weideman's rational approximation of the Faddeeva function
+// w(u) = e^(-u^2) erfc(-i u), Im u >= 0:
+//   w(u) = 2 p(Z) / (L - i u)^2 + 1 / (sqrt(pi) (L - i u)),  Z = (L + i u) / (L - i u),
+//   p(Z) = sum_{n < N} a_{n+1} Z^n,  L = sqrt(N / sqrt 2),
+// a_n the Fourier coefficients of e^(-s^2) (L^2 + s^2), s = L tan(theta / 2).
+// N = 40 for FP64 (relative error ~2e-14), 20 for the mixed form (~1e-8 in
+// exact arithmetic, FP32 rounding dominates).
+constexpr int kFaddeevaN64 = 40, kFaddeevaN32 = 20;
+constexpr int kCutRows32 = 8, kCutRows64 = 4;  // rows per lane of the truncated-beamlet kernels (4 wavefronts)
+struct FaddeevaCoef {
+    double L64, a64[kFaddeevaN64];
+    float L32, a32[kFaddeevaN32];
+};
+
 enum : uint32_t {
     FLAG_PARALLEL = 1u,
     FLAG_BRANCH = 2u,
     FLAG_NONFINITE = 4u,
-    // a higher-order beamlet on a plane tilted against the axis, where its
-    // plane-evaluation field is not the exact paraxial one
+    // a higher-order or truncated beamlet on a plane tilted against the axis,
+    // where its plane-evaluation field is not the exact paraxial one
     FLAG_HG_TILT = 8u,
     FLAG_ERRORS = 15u,
     // not an error: the log2-amplitude curvature along a column exceeds
@@ -230,7 +260,15 @@ hipError_t launch_mlp_adamw(float *p, const float *g, float *m, float *v, int64_
                             float eps, float wd, float c1, float c2, hipStream_t s);
 
 hipError_t launch_setup(const BeamletsDev &b, const PlaneGeom &pl, double global_turns, Rec64 *r64,
-                        Rec32 *r32, RecHG64 *h64, RecHG32 *h32, uint32_t *status, hipStream_t s);
+                        Rec32 *r32, RecHG64 *h64, RecHG32 *h32, RecCut64 *c64, RecCut32 *c32, uint32_t *status,
+                        hipStream_t s);
+
+// Truncated beamlets (direct form with the complex error function): the n
+// beamlets of g (records rec / cut, both starting at the first truncated
+// beamlet) summed per segment into partial segments seg_base + s; precision
+// 0 FP64 (double2 partials), 1 mixed (float4 (sum, compensation)).
+hipError_t launch_eval_cut(int precision, const EvalGeom &g, const void *rec, const void *cut,
+                           const FaddeevaCoef &fc, int32_t seg_base, void *partial, hipStream_t s);
 
 // Mixed precision only, form = 0 direct: per-pixel FP64 phase and exp2;
 // 1 stepped: phase stepped in FP32 from an FP64 anchor and amplitude stepped

@@ -23,10 +23,11 @@ using namespace dev;
 __global__ void __launch_bounds__(256) setup_kernel(BeamletsDev b, PlaneGeom pl, double gturns,
                                                     Rec64 *__restrict__ r64, Rec32 *__restrict__ r32,
                                                     RecHG64 *__restrict__ h64, RecHG32 *__restrict__ h32,
+                                                    RecCut64 *__restrict__ c64, RecCut32 *__restrict__ c32,
                                                     uint32_t *__restrict__ status) {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= b.n) return;
-    const uint32_t flag = setup_one(b, pl, gturns, j, r64, r32, h64, h32);
+    const uint32_t flag = setup_one(b, pl, gturns, j, r64, r32, h64, h32, c64, c32);
     if (flag) atomicOr(status, flag);
 }
 
@@ -244,10 +245,10 @@ hipError_t launch_eval_t(int precision, int form, const EvalGeom &g, const void 
 }  // namespace
 
 hipError_t launch_setup(const BeamletsDev &b, const PlaneGeom &pl, double global_turns, Rec64 *r64, Rec32 *r32,
-                        RecHG64 *h64, RecHG32 *h32, uint32_t *status, hipStream_t s) {
+                        RecHG64 *h64, RecHG32 *h32, RecCut64 *c64, RecCut32 *c32, uint32_t *status, hipStream_t s) {
     if (b.n == 0) return hipSuccess;
     const int64_t blocks = (b.n + 255) / 256;
-    setup_kernel<<<(unsigned)blocks, 256, 0, s>>>(b, pl, global_turns, r64, r32, h64, h32, status);
+    setup_kernel<<<(unsigned)blocks, 256, 0, s>>>(b, pl, global_turns, r64, r32, h64, h32, c64, c32, status);
     return hipGetLastError();
 }
 

@@ -278,6 +278,44 @@ def hermite_scene(n_across: int = 32, *, seed: int = 7, D: float = 10e-3, fnum: 
     return sc
 
 
+def truncated_airy_scene(n_across: int, *, D: float = 10e-3, fnum: float = 10.0, lam: float = 1e-6,
+                         OF: float = 1.7, npix: int = 64, half_span_lamF: float = 5.0, reach: float = 1.5,
+                         z0: float = 0.0, npix_y: Optional[int] = None) -> Scene:
+    """The Airy experiment with a hard-edged pupil: the cell-centred grid of
+    airy_scene extended to centres within reach * w0 outside the aperture,
+    and every beamlet whose centre lies within reach * w0 of the rim cut by
+    the rim's tangent at the nearest rim point (edge normal r / |r|, t = D/2).
+    Unit amplitudes, ideal lens, detector at z0 from the focal plane."""
+    f = fnum * D
+    s = D / n_across
+    w0 = OF * s / 2.0
+    K = int(np.ceil(reach * w0 / s)) + 1      # lattice rows beyond the pupil grid
+    c = (np.arange(-K, n_across + K) - (n_across - 1) / 2.0) * s
+    yy, xx = np.meshgrid(c, c, indexing="ij")
+    rr = np.hypot(xx, yy)
+    keep = rr <= D / 2.0 + reach * w0
+    r1 = np.ascontiguousarray(np.stack([xx[keep], yy[keep]], axis=1))
+    rho = rr[keep]
+    n = r1.shape[0]
+    edge = np.zeros((n, 3))
+    cut = rho > D / 2.0 - reach * w0
+    edge[cut, 0] = r1[cut, 0] / rho[cut]
+    edge[cut, 1] = r1[cut, 1] / rho[cut]
+    edge[cut, 2] = D / 2.0
+    amp = np.zeros((n, 2))
+    amp[:, 0] = 1.0
+    lamF = lam * fnum
+    ny = npix if npix_y is None else npix_y
+    plane = _plane((0.0, 0.0, z0), (0.0, 0.0, 1.0), (1.0, 0.0, 0.0), npix, ny,
+                   2.0 * half_span_lamF * lamF / npix, 2.0 * half_span_lamF * lamF / ny)
+    sc = Scene(lam, f, r1, np.zeros((n, 2)), np.full(n, w0), amp, np.zeros(n),
+               lens_then_distance(f, f).reshape(1, 16), plane,
+               meta=dict(kind="truncated_airy", n_across=n_across, D=D, f=f, fnum=fnum, OF=OF, s=s, reach=reach,
+                         half_span_lamF=half_span_lamF, n_cut=int(cut.sum())))
+    sc.edge = edge
+    return sc
+
+
 def config(name: str) -> Scene:
     """Named workloads:
 

@@ -183,3 +183,23 @@ def test_t5_invalid_edges_and_planes():
     sc.order = np.array([[1, 0]], np.int32)
     with pytest.raises(RuntimeError):
         oracle.eval_field(sc)
+
+
+# ---------------------------------------------------------------- T6 ----------
+@pytest.mark.parametrize("n_across,OF", [(16, 1.7), (32, 1.2), (32, 2.2)])
+def test_t6_cut_beamlets_at_the_rim_approach_the_airy_pattern(n_across, OF):
+    """A hard-edged circular pupil decomposed with the beamlets near the rim
+    cut by the rim's tangent (and the grid extended past the rim) images
+    much closer to the Airy pattern (scipy's J1) than the plain
+    decomposition of the same pupil, OF and count: what truncated beamlets
+    are for (Sec. 7.1)."""
+    from oracle import metrics as om
+    plain = scenes.airy_scene(n_across, OF=OF, npix=64, half_span_lamF=8.0)
+    m = plain.meta
+    ref = om.airy_irradiance(plain.plane, m["D"], m["f"], plain.lam)
+    E, E0 = oracle.eval_field(plain, extra_point=(0.0, 0.0))
+    cut = scenes.truncated_airy_scene(n_across, OF=OF, npix=64, half_span_lamF=8.0)
+    Et, Et0 = oracle.eval_field(cut, extra_point=(0.0, 0.0))
+    rms_plain = om.airy_metrics(E, E0, ref)[0]
+    rms_cut = om.airy_metrics(Et, Et0, ref)[0]
+    assert rms_cut < rms_plain / 5, (rms_plain, rms_cut)
