@@ -18,8 +18,8 @@ instruction-mix roofline.
 Also reported: the FP64 form on the same workload (and the mixed/FP64
 speed-up), the dominant kernel's live HIP-event duration, point evaluation,
 the 441-instance sweep, the ray-traced telescope, higher-order
-(Hermite-Gaussian) beamlets on the same grid, and the FP64 CPU oracle timed
-on a bounded pixel sample (which also gives the mixed form's error against
+(Hermite-Gaussian) and truncated (rim-cut) beamlets on the same grid, and
+the FP64 CPU oracle timed on a bounded pixel sample (which also gives the mixed form's error against
 the oracle there).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
@@ -115,6 +115,7 @@ def main():
     ap.add_argument("--no-point", action="store_true", help="skip the point-evaluation comparison")
     ap.add_argument("--no-telescope", action="store_true", help="skip the ray-traced telescope leg")
     ap.add_argument("--no-hermite", action="store_true", help="skip the higher-order beamlet leg")
+    ap.add_argument("--no-truncated", action="store_true", help="skip the truncated-beamlet leg")
     ap.add_argument("--fp64-steps", type=int, default=5)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 256 MiB device copy (a known-size kernel for HBM counters)")
@@ -230,6 +231,8 @@ def main():
         rec["telescope"] = telescope(ctx, stream)
     if not args.no_hermite:
         rec["hermite"] = hermite(ctx, stream, eval_ms_mean)
+    if not args.no_truncated:
+        rec["truncated"] = truncated(ctx, stream, eval_ms_mean)
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(sc, E32, E64)
     print(json.dumps(rec), flush=True)
@@ -403,6 +406,57 @@ def hermite(ctx, stream, gauss_ms, n_across=256, npix=512, reps=10):
             r["roofline_peak"] = rf["peak"]
             r["roofline_frac"] = rf["frac"]
         res[name] = r
+    return res
+
+
+# Truncated-beamlet kernel (eval_cut_mixed_kernel, 8 rows x 4 wavefronts,
+# Faddeeva function with N = 16): per lane and beamlet, counted in the
+# compiled loop: 839 FP32, 43 FP64, 56 transcendental (exp2, sin, cos twice
+# and one reciprocal per pixel) and 40 other VALU instructions for 8 pixels.
+CUT_MIX = {"fp64": 43 / 8, "fp32": (839 + 40) / 8, "trans": 56 / 8}
+
+
+def truncated(ctx, stream, gauss_ms, n_across=256, npix=512, reps=10):
+    """The headline pupil with its rim cut: the grid extended past the rim
+    and every beamlet within 1.5 w0 of it cut by the rim's tangent.  One
+    evaluation = the whole beamlets in their form (separable) + the cut ones
+    in their own kernel (complex error function) + the segment reduction.
+    Also the RMS error against the Airy pattern, plain grid vs cut rim."""
+    import numpy as np
+    import torch
+    import paper_2404_12454_amd as gbd
+    from paper_2404_12454_amd import scenes
+    res = {}
+    for kind in ("plain", "cut"):
+        sc = (scenes.airy_scene(n_across, npix=npix, half_span_lamF=20.0) if kind == "plain" else
+              scenes.truncated_airy_scene(n_across, npix=npix, half_span_lamF=20.0))
+        b = gbd.beamlets_from_scene(ctx, sc)
+        p = gbd.plane_from_scene(ctx, sc)
+        plan = gbd.Plan(ctx, sc.n).setup(b, p)
+        out = torch.empty((npix, npix), dtype=torch.complex64, device="cuda")
+        for _ in range(reps):
+            plan.eval(gbd.GBD_MIXED, out)
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+        for a, z in evs:
+            a.record(stream)
+            plan.eval(gbd.GBD_MIXED, out)
+            z.record(stream)
+        torch.cuda.synchronize()
+        ms = float(np.mean([a.elapsed_time(z) for a, z in evs]))
+        m = sc.meta
+        airy = gbd.gbd_airy(ctx, p, m["D"], m["f"], sc.lam).cpu().numpy().astype(np.float64)
+        o = gbd.gbd_plane(ctx, sc.plane.origin, sc.plane.normal, sc.plane.xhint, 1, 1, 1e-6, 1e-6)
+        E0 = complex(gbd.gbd_eval(ctx, b, o, gbd.GBD_FP64).cpu().numpy()[0, 0])
+        d = np.abs(out.cpu().numpy().astype(np.complex128)) ** 2 / abs(E0) ** 2 - airy
+        r = {"beamlets": sc.n, "eval_ms": ms, "evals_per_s": sc.n * npix * npix / (ms * 1e-3),
+             "rms_vs_airy": float(np.sqrt(np.mean(d * d))), "peak_vs_airy": float(np.abs(d).max())}
+        if kind == "cut":
+            n_cut = int(m["n_cut"])
+            cycles = sum(v / RATE[k] for k, v in CUT_MIX.items())
+            r.update({"cut_beamlets": n_cut, "cut_pairs": n_cut * npix * npix,
+                      "cut_kernel_roofline_evals_per_s": CUS * CLOCK_HZ / cycles,
+                      "cost_vs_fundamental": ms / gauss_ms})
+        res[kind] = r
     return res
 
 

@@ -108,9 +108,9 @@ static_assert(sizeof(RecCut32) == 32, "RecCut32 layout");
 //   w(u) = 2 p(Z) / (L - i u)^2 + 1 / (sqrt(pi) (L - i u)),  Z = (L + i u) / (L - i u),
 //   p(Z) = sum_{n < N} a_{n+1} Z^n,  L = sqrt(N / sqrt 2),
 // a_n the Fourier coefficients of e^(-s^2) (L^2 + s^2), s = L tan(theta / 2).
-// N = 40 for FP64 (relative error ~2e-14), 20 for the mixed form (~1e-8 in
-// exact arithmetic, FP32 rounding dominates).
-constexpr int kFaddeevaN64 = 40, kFaddeevaN32 = 20;
+// N = 40 for FP64 (relative error 2e-14 over the upper half plane), 16 for
+// the mixed form (4e-7 in exact arithmetic, 5e-7 with FP32 rounding).
+constexpr int kFaddeevaN64 = 40, kFaddeevaN32 = 16;
 constexpr int kCutRows32 = 8, kCutRows64 = 4;  // rows per lane of the truncated-beamlet kernels (4 wavefronts)
 struct FaddeevaCoef {
     double L64, a64[kFaddeevaN64];
