@@ -21,10 +21,10 @@
 // products).  Four wavefronts (2 x 2 tiles) share the factors through LDS, so
 // each lane forms 4 phasors per step instead of 8: on gfx950 VALU and MFMA
 // issue from one SIMD do not overlap, so every VALU instruction per MFMA is
-// time lost from the matrix pipe.  The record fields of the next step are
-// loaded while the current one computes.  Accumulators stay in FP32 over the
-// segment; segments are summed in FP64 by the reduction.  The host sizes
-// segments so that every one is non-empty (jb < je <= N).
+// time lost from the matrix pipe.  The record fields of a step are loaded
+// two steps ahead (the loop is unrolled by two).  Accumulators stay in FP32
+// over the segment; segments are summed in FP64 by the reduction.  The host
+// sizes segments so that every one is non-empty (jb < je <= N).
 //
 // Higher-order (elegant Hermite-Gaussian) beamlets without cross terms keep
 // the factorisation: their Hermite-Gaussian factor is a product of one
@@ -70,6 +70,8 @@ __device__ inline void hg_axis(float df, float gr0, float gi0, float c0r, float 
 struct Fields {
     double arho, brho, p0, p1, p2, p3, p5;
     float m0, m1, m2, m3, m5, arf, brf;
+    float mbias;  // 0, or -inf past the segment end (applied when the factor is formed, so the loads
+                  // are not waited for before then)
     float gxr, gxi, cx0r, cx0i, cx1, cx2;
     float gyr, gyi, cy0r, cy0i, cy1, cy2;
 };
@@ -101,7 +103,8 @@ __device__ inline Fields load_fields(const Rec32 *__restrict__ rec, const RecHG3
     f.p2 = rp->p[2];
     f.p3 = rp->p[3];
     f.p5 = rp->p[5];
-    f.m0 = rp->m[0] + (j < je ? 0.0f : -INFINITY);
+    f.m0 = rp->m[0];
+    f.mbias = j < je ? 0.0f : -INFINITY;
     f.m1 = rp->m[1];
     f.m2 = rp->m[2];
     f.m3 = rp->m[3];
@@ -153,7 +156,7 @@ __global__ void __launch_bounds__(64 * WX * WY) eval_sep_kernel(EvalGeom g, cons
         for (int h = 0; h < 2; h++) {
             float ur, ui, vr, vi;
             const float dxf = axf[h] - f.arf, dyf = byf[h] - f.brf;
-            factor(ax[h] - f.arho, dxf, f.p0, f.p1, f.p3, f.m0 + mx[h], f.m1, f.m3, ur, ui);
+            factor(ax[h] - f.arho, dxf, f.p0, f.p1, f.p3, f.m0 + (f.mbias + mx[h]), f.m1, f.m3, ur, ui);
             factor(by[h] - f.brho, dyf, 0.0, f.p2, f.p5, my[h], f.m2, f.m5, vr, vi);
             if constexpr (HG) {
                 hg_axis(dxf, f.gxr, f.gxi, f.cx0r, f.cx0i, f.cx1, f.cx2, ur, ui);
@@ -173,24 +176,35 @@ __global__ void __launch_bounds__(64 * WX * WY) eval_sep_kernel(EvalGeom g, cons
 
     const int64_t jb = (int64_t)seg * g.seg_len;
     const int64_t je = min(g.n, jb + g.seg_len);
+    // record fields of the steps two and three ahead live in fa / fb in turn
+    // (the loop is unrolled by two), so a load is consumed two steps after
+    // it is issued and no register copies tie the loads to the current step
     publish(load_fields<HG>(rec, hg, jb + lk, jb, je), 0);
-    Fields nxt = load_fields<HG>(rec, hg, jb + 4 + lk, jb, je);
+    Fields fa = load_fields<HG>(rec, hg, jb + 4 + lk, jb, je);
+    Fields fb = load_fields<HG>(rec, hg, jb + 8 + lk, jb, je);
     __syncthreads();
     int buf = 0;
-    for (int64_t j0 = jb; j0 < je; j0 += 4) {
-        const Fields f = nxt;
-        nxt = load_fields<HG>(rec, hg, j0 + 8 + lk, jb, je);
-        if (j0 + 4 < je) publish(f, buf ^ 1);
+    auto step = [&](int64_t j0, Fields &f) {
         float ur[NB], ui[NB], vr[NB], vi[NB], vn[NB];
+        auto read_step = [&]() {
 #pragma unroll
-        for (int b = 0; b < NB; b++) {
-            const float2 u = lu[buf][wx][b][lane], v = lv[buf][wy][b][lane];
-            ur[b] = u.x;
-            ui[b] = u.y;
-            vr[b] = v.x;
-            vi[b] = v.y;
-            vn[b] = -v.y;
-        }
+            for (int b = 0; b < NB; b++) {
+                const float2 u = lu[buf][wx][b][lane], v = lv[buf][wy][b][lane];
+                ur[b] = u.x;
+                ui[b] = u.y;
+                vr[b] = v.x;
+                vi[b] = v.y;
+                vn[b] = -v.y;
+            }
+        };
+        // this step's factors (published before the last barrier) are read
+        // before the next step's factor arithmetic, so that the LDS latency
+        // passes under it; with the higher-order factors the registers this
+        // holds would halve the occupancy, so there they are read after it
+        if constexpr (!HG) read_step();
+        if (j0 + 4 < je) publish(f, buf ^ 1);
+        f = load_fields<HG>(rec, hg, j0 + 12 + lk, jb, je);
+        if constexpr (HG) read_step();
         // Re += Vr Ur - Vi Ui ; Im += Vr Ui + Vi Ur
 #pragma unroll
         for (int p = 0; p < NB; p++)
@@ -208,6 +222,10 @@ __global__ void __launch_bounds__(64 * WX * WY) eval_sep_kernel(EvalGeom g, cons
             }
         __syncthreads();
         buf ^= 1;
+    };
+    for (int64_t j0 = jb; j0 < je; j0 += 8) {
+        step(j0, fa);
+        if (j0 + 4 < je) step(j0 + 4, fb);
     }
 
     // D[row][col] of a 16 x 16 block: lane l holds rows 4 (l / 16) + e, column l % 16
