@@ -59,12 +59,16 @@ typedef struct gbd_plan_s *gbd_plan_t;
 /* Launch shape of the N x M evaluation kernels.  All-zero = library choice
  * (autotuner cache if filled, else built-in defaults). */
 typedef struct {
-    int32_t rows_per_lane;  /* pixels per lane along a detector column: 1, 2, 4, 8 (16: mixed
-                               only; 32: rotor form only, runs 16 where the form resolves
-                               to direct or stepped) */
+    int32_t rows_per_lane;  /* pixels per lane along a detector column: 1, 2, 4, 8, 16, 32
+                               (32: rotor form only, runs 16 where the form resolves to
+                               direct or stepped; the FP64 direct form runs at most 8) */
     int32_t waves;          /* wavefronts per workgroup: 1, 2 or 4 */
     int32_t segments;       /* beamlet segments evaluated by separate workgroups, 0 = auto */
-    int32_t variant;        /* mixed form only.  0 = auto; 1 = direct: FP64 phase and exp2
+    int32_t variant;        /* 0 = auto.  FP64: 1 = direct (exp and sincospi per pixel), 3 =
+                               rotor (the recurrence below in FP64; well-sampled grids and
+                               fundamental beamlets only); auto: rotor where it applies,
+                               else direct; other values resolve as auto.
+                               Mixed: 1 = direct: FP64 phase and exp2
                                per pixel; 2 = stepped: FP64 phase per lane and beamlet
                                with FP32 row steps, amplitude stepped by multiplication;
                                3 = rotor: per lane and beamlet an FP64 anchor phasor at

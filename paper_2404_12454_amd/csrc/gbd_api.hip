@@ -71,6 +71,7 @@ struct gbd_plan_s {
     uint32_t flags;  // FLAG_STEEP / FLAG_CROSS / FLAG_HG of the last setup (which mixed forms apply)
     Rec64 *r64;
     Rec32 *r32;
+    RecSq64 *q64;  // FP64 sigma^(k^2) tables of the FP64 rotor form
     RecHG64 *h64;  // Hermite-Gaussian factors, allocated at the first setup of higher-order beamlets
     RecHG32 *h32;
     RecCut64 *c64;  // truncation factors, allocated at the first setup of truncated beamlets
@@ -191,8 +192,14 @@ struct Shape {
 // FLAG_CROSS); a request that does not apply falls back to the automatic
 // choice among the others.
 int pick_form(int precision, uint32_t flags, const gbd_eval_opts *o, bool allow_sep = true) {
-    if (precision != GBD_MIXED) return 0;
     const bool steep = (flags & FLAG_STEEP) != 0;
+    if (precision != GBD_MIXED) {
+        // FP64: direct or rotor (the rotor form needs a well-sampled grid and
+        // carries no higher-order factor)
+        const int v = o ? o->variant : 0;
+        if (v == 1 || steep || (flags & FLAG_HG)) return 0;
+        return 2;
+    }
     const bool sep = allow_sep && !(flags & FLAG_CROSS);
     const int v = o ? o->variant : 0;
     if (v == 1) return 0;
@@ -203,7 +210,7 @@ int pick_form(int precision, uint32_t flags, const gbd_eval_opts *o, bool allow_
 }
 
 // the variant a resolved form reports (gbd_eval_opts.variant)
-int form_variant(int precision, int form) { return precision == GBD_MIXED ? form + 1 : 0; }
+int form_variant(int precision, int form) { return form + 1; }
 
 int ilog2(int64_t v) {
     int r = 0;
@@ -243,7 +250,7 @@ Shape choose_shape(const gbd_ctx_s *ctx, int precision, int64_t n, const PlaneGe
         return s;
     }
     // rotor form: 32 rows per lane where the grid fills a 4-wave tile
-    s.rows = (precision != GBD_MIXED) ? 4 : (s.form == 2 && pl.ny >= 128) ? 32 : 16;
+    s.rows = (s.form == 2 && pl.ny >= 128) ? 32 : (precision != GBD_MIXED && s.form == 0) ? 4 : 16;
     s.waves = 4;
     s.nseg = 0;
     int seg_pct = 100;
@@ -262,6 +269,7 @@ Shape choose_shape(const gbd_ctx_s *ctx, int precision, int64_t n, const PlaneGe
         if (o->segments) s.nseg = o->segments;
     }
     if (s.rows == 32 && s.form != 2) s.rows = 16;
+    if (precision != GBD_MIXED && s.form == 0 && s.rows > 8) s.rows = 8;  // FP64 direct form: up to 8 rows
     if (s.nseg <= 0) {
         // enough workgroups to keep every SIMD of every CU busy ~6 waves deep,
         // while each segment keeps at least two LDS tiles of beamlets
@@ -278,8 +286,8 @@ Shape choose_shape(const gbd_ctx_s *ctx, int precision, int64_t n, const PlaneGe
 }
 
 bool valid_shape(int rows, int waves, int precision = GBD_MIXED) {
-    const bool r = rows == 1 || rows == 2 || rows == 4 || rows == 8 ||
-                   ((rows == 16 || rows == 32) && precision == GBD_MIXED);
+    const bool r = rows == 1 || rows == 2 || rows == 4 || rows == 8 || rows == 16 || rows == 32;
+    (void)precision;
     return r && (waves == 1 || waves == 2 || waves == 4);
 }
 
@@ -419,7 +427,8 @@ int plan_eval_impl(gbd_ctx_s *ctx, gbd_plan_s *plan, int precision, void *out, i
                                     static_cast<float4 *>(plan->scratch), static_cast<float2 *>(out), ctx->stream),
                     "eval kernel launch");
         else
-            HIP_TRY(launch_eval(precision, s.rows, s.waves, s.form, gl, rec, hrec, plan->scratch, out, ctx->stream),
+            HIP_TRY(launch_eval(precision, s.rows, s.waves, s.form, gl, rec, hrec, plan->q64, plan->scratch, out,
+                                ctx->stream),
                     "eval kernel launch");
     }
     if (nseg_cut > 0) {
@@ -463,7 +472,7 @@ int plan_setup_impl(gbd_ctx_s *ctx, gbd_plan_s *plan, gbd_beamlets_s *b, gbd_pla
         HIP_TRY(hipMemsetAsync(plan->status_dev, 0, sizeof(uint32_t), ctx->stream), "hipMemsetAsync(status)");
         const bool hg = b->dev.order != nullptr;
         const bool cut = b->dev.n_cut > 0;
-        HIP_TRY(launch_setup(b->dev, p->g, gturns, plan->r64, plan->r32, hg ? plan->h64 : nullptr,
+        HIP_TRY(launch_setup(b->dev, p->g, gturns, plan->r64, plan->r32, plan->q64, hg ? plan->h64 : nullptr,
                              hg ? plan->h32 : nullptr, cut ? plan->c64 : nullptr, cut ? plan->c32 : nullptr,
                              plan->status_dev, ctx->stream),
                 "setup kernel launch");
@@ -488,6 +497,7 @@ void plan_destroy(gbd_plan_s *plan) {
     if (!plan) return;
     if (plan->r64) (void)hipFree(plan->r64);
     if (plan->r32) (void)hipFree(plan->r32);
+    if (plan->q64) (void)hipFree(plan->q64);
     if (plan->h64) (void)hipFree(plan->h64);
     if (plan->h32) (void)hipFree(plan->h32);
     if (plan->c64) (void)hipFree(plan->c64);
@@ -506,6 +516,7 @@ int plan_new(gbd_ctx_s *ctx, int64_t capacity, gbd_plan_s **out) {
     const size_t cap = (size_t)std::max<int64_t>(1, capacity);
     hipError_t e = hipMalloc(&p->r64, cap * sizeof(Rec64));
     if (e == hipSuccess) e = hipMalloc(&p->r32, cap * sizeof(Rec32));
+    if (e == hipSuccess) e = hipMalloc(&p->q64, cap * sizeof(RecSq64));
     if (e == hipSuccess) e = hipMalloc(&p->status_dev, sizeof(uint32_t));
     if (e == hipSuccess) e = hipHostMalloc(&p->status_host, sizeof(uint32_t), hipHostMallocDefault);
     if (e != hipSuccess) {
@@ -894,7 +905,8 @@ int gbd_autotune(gbd_ctx_t ctx, gbd_plan_t plan, int precision, int32_t reps, gb
     if (he == hipSuccess) he = hipEventCreate(&e1);
     TuneVal bestv{0, 0, 100, 1e300};
     static const int rows_c[] = {2, 4, 8, 16, 32}, waves_c[] = {1, 2, 4}, pct_c[] = {50, 100, 200, 400};
-    const int n_rows = precision == GBD_MIXED ? ((plan->flags & FLAG_STEEP) ? 4 : 5) : 3;
+    const int n_rows = precision == GBD_MIXED ? ((plan->flags & FLAG_STEEP) ? 4 : 5)
+                                              : ((plan->flags & (FLAG_STEEP | FLAG_HG)) ? 3 : 5);
     for (int ri = 0; ri < n_rows && he == hipSuccess && rc == GBD_OK; ri++)
         for (int wi = 0; wi < 3 && he == hipSuccess && rc == GBD_OK; wi++)
             for (int pi = 0; pi < 4 && he == hipSuccess && rc == GBD_OK; pi++) {

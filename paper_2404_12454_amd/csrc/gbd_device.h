@@ -65,7 +65,7 @@ __device__ inline double il2_dev() { return 1.4426950408889634074; }  // 1 / ln 
 // direct form of their own kernel).
 __device__ inline uint32_t setup_one(const BeamletsDev &b, const PlaneGeom &pl, double gturns, int64_t j,
                                      Rec64 *r64, Rec32 *r32, RecHG64 *h64 = nullptr, RecHG32 *h32 = nullptr,
-                                     RecCut64 *c64 = nullptr, RecCut32 *c32 = nullptr) {
+                                     RecCut64 *c64 = nullptr, RecCut32 *c32 = nullptr, RecSq64 *q64 = nullptr) {
     const double *M = b.abcd + (b.n_abcd == 1 ? 0 : 16 * j);
     double A[2][2], B[2][2], C[2][2], D[2][2];
 #pragma unroll
@@ -103,6 +103,7 @@ __device__ inline uint32_t setup_one(const BeamletsDev &b, const PlaneGeom &pl, 
     const double dl = sqrt(th[0] * th[0] + th[1] * th[1] + 1.0);
     Rec64 o64 = {};
     Rec32 o32 = {};
+    RecSq64 oq = {};
     RecHG64 oh = {};
     RecCut64 oc = {};
     const int64_t cut0 = b.n - b.n_cut;
@@ -356,8 +357,10 @@ __device__ inline uint32_t setup_one(const BeamletsDev &b, const PlaneGeom &pl, 
             double sn, cs;
             sincospi(2.0 * ph, &sn, &cs);
             const double g = exp2(fmin(kk * u2, 64.0));
-            o32.sq[k - 1][0] = (float)(g * cs);
-            o32.sq[k - 1][1] = (float)(g * sn);
+            oq.sq[k - 1][0] = g * cs;
+            oq.sq[k - 1][1] = g * sn;
+            o32.sq[k - 1][0] = (float)oq.sq[k - 1][0];
+            o32.sq[k - 1][1] = (float)oq.sq[k - 1][1];
         }
     }
     if (flag & FLAG_ERRORS) {
@@ -367,6 +370,7 @@ __device__ inline uint32_t setup_one(const BeamletsDev &b, const PlaneGeom &pl, 
     }
     if (r64) r64[j] = o64;
     if (r32) r32[j] = o32;
+    if (q64) q64[j] = oq;
     if (is_cut && c64) c64[j - cut0] = oc;
     if (is_cut && c32) {
         RecCut32 o;

@@ -60,6 +60,13 @@ struct alignas(16) Rec32 {
 static_assert(sizeof(Rec32) == 240, "Rec32 layout");
 constexpr int kRec32Vec4 = sizeof(Rec32) / 16;
 
+// FP64 rotor form: sigma^(k^2), k = 1..16, of each beamlet in FP64 (the Rec32
+// table's source values), kept beside the Rec64 records.
+struct alignas(16) RecSq64 {
+    double sq[16][2];
+};
+static_assert(sizeof(RecSq64) == 256, "RecSq64 layout");
+
 // Elegant Hermite-Gaussian factor of a higher-order beamlet on a plane
 // normal to the axis, as a polynomial in the pixel offset d = (da, db) from
 // the base-ray hit point:
@@ -260,8 +267,8 @@ hipError_t launch_mlp_adamw(float *p, const float *g, float *m, float *v, int64_
                             float eps, float wd, float c1, float c2, hipStream_t s);
 
 hipError_t launch_setup(const BeamletsDev &b, const PlaneGeom &pl, double global_turns, Rec64 *r64,
-                        Rec32 *r32, RecHG64 *h64, RecHG32 *h32, RecCut64 *c64, RecCut32 *c32, uint32_t *status,
-                        hipStream_t s);
+                        Rec32 *r32, RecSq64 *q64, RecHG64 *h64, RecHG32 *h32, RecCut64 *c64, RecCut32 *c32,
+                        uint32_t *status, hipStream_t s);
 
 // Truncated beamlets (direct form with the complex error function): the n
 // beamlets of g (records rec / cut, both starting at the first truncated
@@ -275,9 +282,10 @@ hipError_t launch_eval_cut(int precision, const EvalGeom &g, const void *rec, co
 // by multiplication along each lane's column; 2 rotor: each lane's column
 // factored as anchor x rho^k x sigma^(k^2), no per-pixel transcendental.
 // hg: RecHG64 / RecHG32 records of higher-order beamlets (direct and FP64
-// forms only), or null.
+// forms only), or null.  precision 0 with form 2: the FP64 rotor form, q64
+// its sigma^(k^2) tables.
 hipError_t launch_eval(int precision, int rows, int waves, int form, const EvalGeom &g, const void *rec,
-                       const void *hg, void *partial, void *out, hipStream_t s);
+                       const void *hg, const RecSq64 *q64, void *partial, void *out, hipStream_t s);
 
 hipError_t launch_reduce(int precision, const EvalGeom &g, const void *partial, void *out, hipStream_t s);
 

@@ -24,10 +24,10 @@ __global__ void __launch_bounds__(256) setup_kernel(BeamletsDev b, PlaneGeom pl,
                                                     Rec64 *__restrict__ r64, Rec32 *__restrict__ r32,
                                                     RecHG64 *__restrict__ h64, RecHG32 *__restrict__ h32,
                                                     RecCut64 *__restrict__ c64, RecCut32 *__restrict__ c32,
-                                                    uint32_t *__restrict__ status) {
+                                                    RecSq64 *__restrict__ q64, uint32_t *__restrict__ status) {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= b.n) return;
-    const uint32_t flag = setup_one(b, pl, gturns, j, r64, r32, h64, h32, c64, c32);
+    const uint32_t flag = setup_one(b, pl, gturns, j, r64, r32, h64, h32, c64, c32, q64);
     if (flag) atomicOr(status, flag);
 }
 
@@ -173,6 +173,123 @@ __global__ void __launch_bounds__(64 * WAVES) eval_fp64_kernel(EvalGeom g, const
     }
 }
 
+// FP64 rotor form: the mixed rotor recurrence E(h + k) = E(h) rho^k sigma^(k^2)
+// in FP64 throughout (anchor at the lane's middle row h from the FP64 phase
+// and ln-amplitude quadratics, rho and 1/rho from the row slopes, sigma^(k^2)
+// from the setup kernel's FP64 table), so a further row costs two complex
+// FP64 multiply-adds instead of an exp and a sincospi.  The anchor is flushed
+// below e^-700 and the ln-amplitude slope capped at +-40 per row: with the
+// curvature bound of well-sampled grids (|ln-amplitude curvature| <= 0.07 per
+// row^2) a slope of 40 puts the beamlet's peak over 280 rows away and the
+// anchor below e^-5000, so neither touches a term that is not already zero.
+template <int ROWS, int WAVES>
+__global__ void __launch_bounds__(64 * WAVES) eval_fp64_rotor_kernel(EvalGeom g, const Rec64 *__restrict__ rec,
+                                                                     const RecSq64 *__restrict__ sqt,
+                                                                     double2 *__restrict__ partial,
+                                                                     double2 *__restrict__ out) {
+    constexpr int CH = 64;  // records per LDS tile (8 KiB + 16 KiB of sigma tables)
+    constexpr int H = ROWS / 2;
+    static_assert(H <= 16, "FP64 rotor form: at most 32 rows per lane");
+    __shared__ Rec64 tile[CH];
+    __shared__ RecSq64 stile[CH];
+    const int w = work_item(blockIdx.x, gridDim.x);
+    if (w >= g.work) return;
+    const int tiles = g.tiles_x * g.tiles_y;
+    const int seg = w / tiles;
+    const int t = w - seg * tiles;
+    const int ty = t / g.tiles_x, tx = t - ty * g.tiles_x;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int ix = tx * 64 + lane;
+    const int iy0 = (ty * WAVES + wv) * ROWS;
+    const double a = g.a0 + ix * g.dx;
+    const double dy = g.dy;
+    const double bh = g.b0 + (iy0 + H) * g.dy;
+
+    double acc_re[ROWS], acc_im[ROWS];
+#pragma unroll
+    for (int k = 0; k < ROWS; k++) acc_re[k] = acc_im[k] = 0.0;
+
+    const int64_t jb = (int64_t)seg * g.seg_len;
+    const int64_t je = min(g.n, jb + g.seg_len);
+    for (int64_t j0 = jb; j0 < je; j0 += CH) {
+        const int cnt = (int)min((int64_t)CH, je - j0);
+        __syncthreads();
+        {
+            const double2 *src = reinterpret_cast<const double2 *>(rec + j0);
+            double2 *dst = reinterpret_cast<double2 *>(tile);
+            for (int i = threadIdx.x; i < cnt * 8; i += 64 * WAVES) dst[i] = src[i];
+            const double2 *qs = reinterpret_cast<const double2 *>(sqt + j0);
+            double2 *qd = reinterpret_cast<double2 *>(stile);
+            for (int i = threadIdx.x; i < cnt * 16; i += 64 * WAVES) qd[i] = qs[i];
+        }
+        __syncthreads();
+        for (int jj = 0; jj < cnt; jj++) {
+            const Rec64 &r = tile[jj];
+            const RecSq64 &sq = stile[jj];
+            const double da = a - r.arho, db = bh - r.brho;
+            const double q = r.p[2] + r.p[4] * da;
+            const double T0 = r.p[0] + da * (r.p[1] + r.p[3] * da) + db * (q + r.p[5] * db);
+            const double T1 = dy * (q + 2.0 * r.p[5] * db);
+            const double ql = r.l[2] + r.l[4] * da;
+            const double L0 = r.l[0] + da * (r.l[1] + r.l[3] * da) + db * (ql + r.l[5] * db);
+            const double U1 = fmin(fmax(dy * (ql + 2.0 * r.l[5] * db), -40.0), 40.0);
+            const double m0 = L0 < -700.0 ? 0.0 : exp(L0);
+            double s0, c0;
+            sincospi(2.0 * (T0 - rint(T0)), &s0, &c0);
+            const double zr = m0 * c0, zi = m0 * s0;
+            acc_re[H] += zr;
+            acc_im[H] += zi;
+            const double t1 = T1 - rint(T1);
+            double s1, c1;
+            sincospi(2.0 * t1, &s1, &c1);
+            if (ROWS - 1 - H > 0) {
+                const double mu = exp(U1);
+                const double ur = mu * c1, ui = mu * s1;
+                double pr = zr, pi = zi;
+#pragma unroll
+                for (int k = 1; k < ROWS - H; k++) {
+                    const double nr = fma(pr, ur, -(pi * ui));
+                    const double ni = fma(pr, ui, pi * ur);
+                    pr = nr;
+                    pi = ni;
+                    const double sr = sq.sq[k - 1][0], si = sq.sq[k - 1][1];
+                    acc_re[H + k] = fma(pr, sr, fma(-pi, si, acc_re[H + k]));
+                    acc_im[H + k] = fma(pr, si, fma(pi, sr, acc_im[H + k]));
+                }
+            }
+            if (H > 0) {
+                const double md = exp(-U1);
+                const double vr = md * c1, vi = -(md * s1);
+                double pr = zr, pi = zi;
+#pragma unroll
+                for (int k = 1; k <= H; k++) {
+                    const double nr = fma(pr, vr, -(pi * vi));
+                    const double ni = fma(pr, vi, pi * vr);
+                    pr = nr;
+                    pi = ni;
+                    const double sr = sq.sq[k - 1][0], si = sq.sq[k - 1][1];
+                    acc_re[H - k] = fma(pr, sr, fma(-pi, si, acc_re[H - k]));
+                    acc_im[H - k] = fma(pr, si, fma(pi, sr, acc_im[H - k]));
+                }
+            }
+        }
+    }
+    if (ix >= g.nx) return;
+    const int64_t M = (int64_t)g.nx * g.ny;
+#pragma unroll
+    for (int k = 0; k < ROWS; k++) {
+        const int iy = iy0 + k;
+        if (iy < g.ny) {
+            const int64_t p = (int64_t)iy * g.nx + ix;
+            const double2 v = make_double2(acc_re[k], acc_im[k]);
+            if (g.nseg == 1)
+                out[p] = v;
+            else
+                partial[(int64_t)seg * M + p] = v;
+        }
+    }
+}
+
 __global__ void __launch_bounds__(256) reduce_mixed_kernel(int64_t M, int32_t nseg, const float4 *__restrict__ part,
                                                            float2 *__restrict__ out) {
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < M; p += (int64_t)gridDim.x * blockDim.x) {
@@ -200,9 +317,15 @@ __global__ void __launch_bounds__(256) reduce_fp64_kernel(int64_t M, int32_t nse
 }
 
 template <int ROWS, int WAVES>
-hipError_t launch_eval_t(int precision, int form, const EvalGeom &g, const void *rec, const void *hg, void *partial,
-                         void *out, hipStream_t s) {
+hipError_t launch_eval_t(int precision, int form, const EvalGeom &g, const void *rec, const void *hg,
+                         const RecSq64 *q64, void *partial, void *out, hipStream_t s) {
     const int grid = (g.work + 7) / 8 * 8;
+    if (precision == 0 && form == 2 && !hg) {
+        if (!q64) return hipErrorInvalidValue;
+        eval_fp64_rotor_kernel<ROWS, WAVES><<<grid, 64 * WAVES, 0, s>>>(
+            g, static_cast<const Rec64 *>(rec), q64, static_cast<double2 *>(partial), static_cast<double2 *>(out));
+        return hipGetLastError();
+    }
     if (hg) {
         if (precision == 1 && form == 2)
             eval_mixed_kernel<ROWS, WAVES, 2, true><<<grid, 64 * WAVES, 0, s>>>(
@@ -245,26 +368,40 @@ hipError_t launch_eval_t(int precision, int form, const EvalGeom &g, const void 
 }  // namespace
 
 hipError_t launch_setup(const BeamletsDev &b, const PlaneGeom &pl, double global_turns, Rec64 *r64, Rec32 *r32,
-                        RecHG64 *h64, RecHG32 *h32, RecCut64 *c64, RecCut32 *c32, uint32_t *status, hipStream_t s) {
+                        RecSq64 *q64, RecHG64 *h64, RecHG32 *h32, RecCut64 *c64, RecCut32 *c32, uint32_t *status,
+                        hipStream_t s) {
     if (b.n == 0) return hipSuccess;
     const int64_t blocks = (b.n + 255) / 256;
-    setup_kernel<<<(unsigned)blocks, 256, 0, s>>>(b, pl, global_turns, r64, r32, h64, h32, c64, c32, status);
+    setup_kernel<<<(unsigned)blocks, 256, 0, s>>>(b, pl, global_turns, r64, r32, h64, h32, c64, c32, q64, status);
     return hipGetLastError();
 }
 
 hipError_t launch_eval(int precision, int rows, int waves, int form, const EvalGeom &g, const void *rec, const void *hg,
-                       void *partial, void *out, hipStream_t s) {
+                       const RecSq64 *q64, void *partial, void *out, hipStream_t s) {
 #define GBD_CASE(R, W) \
-    if (rows == R && waves == W) return launch_eval_t<R, W>(precision, form, g, rec, hg, partial, out, s);
+    if (rows == R && waves == W) return launch_eval_t<R, W>(precision, form, g, rec, hg, q64, partial, out, s);
     GBD_CASE(1, 1) GBD_CASE(1, 2) GBD_CASE(1, 4)
     GBD_CASE(2, 1) GBD_CASE(2, 2) GBD_CASE(2, 4)
     GBD_CASE(4, 1) GBD_CASE(4, 2) GBD_CASE(4, 4)
     GBD_CASE(8, 1) GBD_CASE(8, 2) GBD_CASE(8, 4)
 #undef GBD_CASE
     if (precision == 1 && rows == 16) {
-        if (waves == 1) return launch_eval_t<16, 1>(precision, form, g, rec, hg, partial, out, s);
-        if (waves == 2) return launch_eval_t<16, 2>(precision, form, g, rec, hg, partial, out, s);
-        if (waves == 4) return launch_eval_t<16, 4>(precision, form, g, rec, hg, partial, out, s);
+        if (waves == 1) return launch_eval_t<16, 1>(precision, form, g, rec, hg, q64, partial, out, s);
+        if (waves == 2) return launch_eval_t<16, 2>(precision, form, g, rec, hg, q64, partial, out, s);
+        if (waves == 4) return launch_eval_t<16, 4>(precision, form, g, rec, hg, q64, partial, out, s);
+    }
+    if (precision == 0 && form == 2 && !hg && q64 && (rows == 16 || rows == 32)) {
+        const int grid = (g.work + 7) / 8 * 8;
+        double2 *pt = static_cast<double2 *>(partial), *o = static_cast<double2 *>(out);
+        const Rec64 *r = static_cast<const Rec64 *>(rec);
+        if (rows == 16 && waves == 1) eval_fp64_rotor_kernel<16, 1><<<grid, 64, 0, s>>>(g, r, q64, pt, o);
+        else if (rows == 16 && waves == 2) eval_fp64_rotor_kernel<16, 2><<<grid, 128, 0, s>>>(g, r, q64, pt, o);
+        else if (rows == 16 && waves == 4) eval_fp64_rotor_kernel<16, 4><<<grid, 256, 0, s>>>(g, r, q64, pt, o);
+        else if (rows == 32 && waves == 1) eval_fp64_rotor_kernel<32, 1><<<grid, 64, 0, s>>>(g, r, q64, pt, o);
+        else if (rows == 32 && waves == 2) eval_fp64_rotor_kernel<32, 2><<<grid, 128, 0, s>>>(g, r, q64, pt, o);
+        else if (rows == 32 && waves == 4) eval_fp64_rotor_kernel<32, 4><<<grid, 256, 0, s>>>(g, r, q64, pt, o);
+        else return hipErrorInvalidValue;
+        return hipGetLastError();
     }
     if (precision == 1 && rows == 32 && form == 2 && hg) {
         const int grid = (g.work + 7) / 8 * 8;

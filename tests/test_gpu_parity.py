@@ -68,9 +68,9 @@ def test_every_launch_shape_matches_oracle(ctx, precision):
     sc = scenes.zernike_scene(99, n_across=20, npix=70, half_span=40e-6)
     sc.plane.ny = 45
     ref = oracle.eval_field(sc)
-    variants = (1, 2, 3) if precision == gbd.GBD_MIXED else (0,)
-    shapes = SHAPES + ([dict(rows_per_lane=r, waves=w, segments=s) for r in (16, 32) for w in (1, 2, 4) for s in (1, 3)]
-                       if precision == gbd.GBD_MIXED else [])
+    # FP64: the direct and rotor forms; mixed: direct, stepped and rotor
+    variants = (1, 2, 3) if precision == gbd.GBD_MIXED else (1, 3)
+    shapes = SHAPES + [dict(rows_per_lane=r, waves=w, segments=s) for r in (16, 32) for w in (1, 2, 4) for s in (1, 3)]
     for v in variants:
         for o in shapes:
             check(run(ctx, sc, precision, opts=dict(o, variant=v)), ref, precision, f"shape {o} variant {v}")
@@ -146,6 +146,32 @@ def test_steep_grid_falls_back_to_direct(ctx):
     assert plan.shape(gbd.GBD_MIXED, opts=dict(variant=3))["variant"] == 1
     # 32 rows per lane is a rotor-form shape; the direct form runs 16
     assert plan.shape(gbd.GBD_MIXED, opts=dict(rows_per_lane=32, variant=1))["rows_per_lane"] == 16
+    # FP64: the rotor form needs the curvature bound as well; its direct form runs at most 8 rows
+    assert plan.shape(gbd.GBD_FP64)["variant"] == 1
+    assert plan.shape(gbd.GBD_FP64, opts=dict(variant=3))["variant"] == 1
+    assert plan.shape(gbd.GBD_FP64, opts=dict(rows_per_lane=32))["rows_per_lane"] == 8
+
+
+@pytest.mark.parametrize("name", ["airy32_64", "zern128_1024"])
+def test_fp64_rotor_form_is_chosen_and_matches(ctx, name):
+    """On well-sampled grids the automatic FP64 form is the rotor one (the
+    mixed rotor recurrence in FP64, no per-pixel exp or sincospi); it agrees
+    with the FP64 direct form to rounding and with the oracle."""
+    sc = scenes.config(name)
+    b = gbd.beamlets_from_scene(ctx, sc)
+    p = gbd.plane_from_scene(ctx, sc)
+    plan = gbd.Plan(ctx, sc.n).setup(b, p)
+    shape = plan.shape(gbd.GBD_FP64)
+    assert shape["variant"] == 3
+    E3 = plan.eval(gbd.GBD_FP64).cpu().numpy()
+    E1 = plan.eval(gbd.GBD_FP64, opts=dict(variant=1)).cpu().numpy()
+    print(name, shape, "FP64 rotor vs direct", rel_l2(E3, E1), flush=True)
+    assert rel_l2(E3, E1) < 1e-13
+    if sc.plane.npix <= 4096:
+        check(E3, oracle.eval_field(sc), gbd.GBD_FP64, name + " FP64 rotor")
+    else:
+        ix, iy = sample_pixels(sc.plane.nx, sc.plane.ny, 100, 9)
+        check(E3[iy, ix], oracle.eval_field(sc, pixels=(ix, iy)), gbd.GBD_FP64, name + " FP64 rotor sampled")
 
 
 @pytest.mark.parametrize("precision", BOTH)
