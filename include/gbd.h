@@ -231,7 +231,7 @@ int gbd_plan_shape(gbd_ctx_t ctx, gbd_plan_t plan, int precision, const gbd_eval
 
 /* --- autotuner ---------------------------------------------------------------
  * gbd_autotune: times every launch shape of gbd_plan_eval for this plan and
- * precision (rows_per_lane in {2,4,8} (and 16, 32 for the mixed form) x waves in
+ * precision (rows_per_lane in {2,4,8} (and 16, 32 where a rotor form applies) x waves in
  * {1,2,4} x segment counts of
  * 1/2, 1, 2 and 4 times the automatic choice; `reps` timed launches each, HIP
  * events on the context stream), stores the fastest in the context's cache
@@ -283,8 +283,13 @@ int gbd_airy(gbd_ctx_t ctx, gbd_plane_t p, double D, double f, double lambda, fl
  *               origin, then the RMS of each zone; required iff airy != NULL
  *   fields_out  optional device complex64 fields, instance after instance
  *               ([n_inst][ny_i][nx_i]); fields_bytes its size
- * opts: rows_per_lane and waves as for gbd_eval (segments is ignored; default
- * 32 x 4 for the rotor form, else 16 x 4, or the autotuner's choice).
+ * opts: variant as for gbd_eval's mixed form (auto: separable where no
+ * beamlet of any instance has a cross term, each item then a 128 x 128
+ * pixel tile; else rotor, else direct); rows_per_lane and waves as for
+ * gbd_eval for the other forms (segments is ignored; default 32 x 4 for the
+ * rotor form, else 16 x 4, or the autotuner's choice).  Every item sums all
+ * of its instance's beamlets, so a field equals gbd_eval's with the same
+ * form and shape and one segment, bit for bit.
  * Synchronises the context stream (setup status, then metrics). */
 int gbd_eval_batch(gbd_ctx_t ctx, int32_t n_inst, const gbd_beamlets_t *beamlets, const gbd_plane_t *planes,
                    const float *airy, int64_t airy_bytes, const double *zone_edges, int32_t n_zones,

@@ -1129,7 +1129,7 @@ int gbd_eval_batch(gbd_ctx_t ctx, int32_t n_inst, const gbd_beamlets_t *bs, cons
     if (stat & FLAG_PARALLEL) return fail(GBD_EPARALLEL, "instance %d: a base ray is parallel to the plane", bad);
     if (stat & FLAG_BRANCH) return fail(GBD_EBRANCH, "instance %d: an eigenvalue left the principal branch", bad);
     if (stat & FLAG_NONFINITE) return fail(GBD_EINVAL, "instance %d: non-finite beamlet parameters", bad);
-    const int form = pick_form(GBD_MIXED, stat, opts, false);  // no separable batch kernel
+    const int form = pick_form(GBD_MIXED, stat, opts);
     if (rows == 32 && form != 2) rows = 16;  // 32 rows is a rotor-form shape
 
     // evaluation tables; the work list takes instances largest first (LPT),
@@ -1143,8 +1143,13 @@ int gbd_eval_batch(gbd_ctx_t ctx, int32_t n_inst, const gbd_beamlets_t *bs, cons
         e.n = bs[i]->dev.n;
         e.nx = g.nx;
         e.ny = g.ny;
-        e.tiles_x = (g.nx + 63) / 64;
-        e.tiles_y = (g.ny + waves * rows - 1) / (waves * rows);
+        if (form == 3) {  // separable form: 128 x 128 pixel tiles
+            e.tiles_x = (g.nx + kSepTile * kSepWavesX - 1) / (kSepTile * kSepWavesX);
+            e.tiles_y = (g.ny + kSepTile * kSepWavesY - 1) / (kSepTile * kSepWavesY);
+        } else {
+            e.tiles_x = (g.nx + 63) / 64;
+            e.tiles_y = (g.ny + waves * rows - 1) / (waves * rows);
+        }
         e.dx = g.dx;
         e.dy = g.dy;
         e.a0 = -0.5 * (g.nx - 1) * g.dx;

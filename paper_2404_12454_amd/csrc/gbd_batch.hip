@@ -10,9 +10,14 @@
 //                      each item sums all of its instance's beamlets (mixed
 //                      precision) and reduces its metric contribution with
 //                      wavefront shuffles
+//  batch_sep_kernel    the same with the separable (matrix) form where no
+//                      beamlet's phasor has a cross term: items are
+//                      (instance, 128 x 128 tile), each a 2 x 2-wavefront
+//                      MFMA accumulation over all of the instance's beamlets
 //  batch_finalize      per instance, fixed-order sum of its items' partials
 //  airy_kernel         reference irradiance (2 J1(v)/v)^2 in FP64
 #include "gbd_device.h"
+#include "gbd_sep_core.h"
 
 namespace gbd {
 
@@ -167,6 +172,94 @@ __global__ void __launch_bounds__(64 * WAVES) batch_eval_kernel(BatchArgs A) {
     }
 }
 
+// Separable form: the single-instance kernel's accumulation with one beamlet
+// segment (so a field equals gbd_eval's with variant 4 and one segment bit
+// for bit), then the same epilogue from the MFMA accumulators (lane l holds
+// rows 4 (l / 16) + e, column l % 16 of each 16 x 16 block).
+template <int WX, int WY>
+__global__ void __launch_bounds__(64 * WX * WY) batch_sep_kernel(BatchArgs A) {
+    constexpr int NB = sep::kSepBlocks, WAVES = WX * WY, NQ = 2 + 2 * kMaxZones;
+    __shared__ sep::SepLds<NB> L;
+    __shared__ int s_item;
+    __shared__ double red[WAVES][NQ];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int wx = wv % WX, wy = wv / WX;
+    const int li = lane & 15, lk = lane >> 4;
+    const int PS = 2 + 2 * A.n_zones;
+    for (;;) {
+        if (threadIdx.x == 0) s_item = (int)atomicAdd(A.counter, 1u);
+        __syncthreads();
+        const int item = s_item;
+        __syncthreads();
+        if (item >= A.n_items) break;  // uniform across the workgroup
+        const int i = A.items[2 * item], t = A.items[2 * item + 1];
+        const BatchEval I = A.inst[i];
+        const int ty = t / I.tiles_x, tx = t - ty * I.tiles_x;
+        const int x0 = (tx * WX + wx) * 16 * NB, y0 = (ty * WY + wy) * 16 * NB;
+        sep::f4 accR[NB][NB], accI[NB][NB];
+        if (I.n > 0) {
+            const sep::SepGeom sg{I.nx, I.ny, I.a0, I.b0, I.dx, I.dy};
+            sep::sep_accumulate<WX, WY, false>(sg, A.rec + I.rec_off, nullptr, 0, I.n, tx, ty, L, accR, accI);
+        } else {
+#pragma unroll
+            for (int p = 0; p < NB; p++)
+#pragma unroll
+                for (int q = 0; q < NB; q++) accR[p][q] = accI[p][q] = sep::f4{0.0f, 0.0f, 0.0f, 0.0f};
+        }
+        double qm[NQ];
+#pragma unroll
+        for (int z = 0; z < NQ; z++) qm[z] = 0.0;
+        const double2 e0 = A.e0[i];
+        const double n0 = e0.x * e0.x + e0.y * e0.y;
+        const double inv0 = n0 > 0.0 ? 1.0 / n0 : 0.0;  // an empty instance compares a zero field
+#pragma unroll
+        for (int p = 0; p < NB; p++)
+#pragma unroll
+            for (int q = 0; q < NB; q++) {
+                const int ix = x0 + 16 * q + li;
+#pragma unroll
+                for (int e = 0; e < 4; e++) {
+                    const int iy = y0 + 16 * p + 4 * lk + e;
+                    if (ix < I.nx && iy < I.ny) {
+                        const int64_t px = (int64_t)iy * I.nx + ix;
+                        const float er = accR[p][q][e], ei = accI[p][q][e];
+                        if (A.fields) A.fields[I.field_off + px] = make_float2(er, ei);
+                        if (A.airy) {
+                            const double d = ((double)er * er + (double)ei * ei) * inv0 - (double)A.airy[px];
+                            qm[0] += d * d;
+                            qm[1] = fmax(qm[1], fabs(d));
+                            const double a = I.a0 + ix * I.dx, bk = I.b0 + iy * I.dy;
+                            const double r2 = a * a + bk * bk;
+#pragma unroll
+                            for (int z = 0; z < kMaxZones; z++)
+                                if (z < A.n_zones && r2 >= A.zone_r2[z] && r2 < A.zone_r2[z + 1]) {
+                                    qm[2 + 2 * z] += d * d;
+                                    qm[3 + 2 * z] += 1.0;
+                                }
+                        }
+                    }
+                }
+            }
+        if (A.airy) {
+#pragma unroll
+            for (int z = 0; z < NQ; z++) qm[z] = (z == 1) ? wave_max<64>(qm[z]) : wave_sum<64>(qm[z]);
+            if (lane == 0)
+#pragma unroll
+                for (int z = 0; z < NQ; z++) red[wv][z] = qm[z];
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                double *dst = A.part + (int64_t)item * PS;
+                for (int z = 0; z < PS; z++) {
+                    double v = red[0][z];
+                    for (int w = 1; w < WAVES; w++) v = (z == 1) ? fmax(v, red[w][z]) : v + red[w][z];
+                    dst[z] = v;
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
 __global__ void __launch_bounds__(64) batch_finalize_kernel(const BatchEval *__restrict__ inst, int32_t n_inst,
                                                             const double *__restrict__ part, int32_t n_zones,
                                                             double *__restrict__ metrics) {
@@ -235,6 +328,17 @@ hipError_t launch_batch_e0(const BatchEval *inst, int32_t n_inst, const Rec32 *r
 }
 
 hipError_t launch_batch_eval(int rows, int waves, int form, int cus, const BatchArgs &a, hipStream_t s) {
+    if (form == 3) {
+        int per_cu = 0;
+        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &per_cu, batch_sep_kernel<kSepWavesX, kSepWavesY>, 64 * kSepWavesX * kSepWavesY, 0);
+        if (e != hipSuccess) return e;
+        if (per_cu < 1) per_cu = 1;
+        const int grid = (int)min((int64_t)a.n_items, (int64_t)cus * per_cu);
+        if (grid <= 0) return hipSuccess;
+        batch_sep_kernel<kSepWavesX, kSepWavesY><<<grid, 64 * kSepWavesX * kSepWavesY, 0, s>>>(a);
+        return hipGetLastError();
+    }
 #define GBD_CASE(R, W)                                                                         \
     if (rows == R && waves == W)                                                               \
         return form == 2   ? launch_batch_eval_t<R, W, 2>(cus, a, s)                           \

@@ -201,6 +201,7 @@ struct BatchArgs {
 hipError_t launch_batch_setup(const BatchInst *inst, const int64_t *offs, int32_t n_inst, int64_t total,
                               Rec32 *rec, uint32_t *status, int32_t *bad, hipStream_t s);
 hipError_t launch_batch_e0(const BatchEval *inst, int32_t n_inst, const Rec32 *rec, double2 *e0, hipStream_t s);
+// form 3: the separable form (rows and waves do not apply)
 hipError_t launch_batch_eval(int rows, int waves, int form, int cus, const BatchArgs &a, hipStream_t s);
 hipError_t launch_batch_finalize(const BatchEval *inst, int32_t n_inst, const double *part, int32_t n_zones,
                                  double *metrics, hipStream_t s);
