@@ -238,13 +238,22 @@ def main():
     print(json.dumps(rec), flush=True)
 
 
+MFMA_FP64_TFLOPS = 78.6
+
+
 def fp64_record(shape, N, M, ms, mixed_ms):
-    """The FP64 form's figure; for its rotor form (the automatic one on
-    well-sampled grids) also its instruction-mix roofline: per further row
-    two complex FP64 multiply-adds (8 FP64), per lane and beamlet 107 FP64
-    (anchor exp and sincospi, rho, 1/rho) and 70 other VALU instructions,
-    counted in the compiled loop at 32 rows."""
+    """The FP64 form's figure and roofline: the separable form (the automatic
+    one without cross terms) against the FP64 MFMA peak at 8 flops per pair;
+    the rotor form (the automatic one otherwise, on well-sampled grids)
+    against its instruction mix: per further row two complex FP64
+    multiply-adds (8 FP64), per lane and beamlet 107 FP64 (anchor exp and
+    sincospi, rho, 1/rho) and 70 other VALU instructions, counted in the
+    compiled loop at 32 rows."""
     r = {"value": N * M / (ms * 1e-3), "eval_ms": ms, "launch": shape, "speedup_mixed_over_fp64": ms / mixed_ms}
+    if shape["variant"] == 4:
+        achieved = SEP_FLOPS_PER_PAIR * N * M / (ms * 1e-3) / 1e12
+        r.update({"roofline_bound": "mfma", "achieved_tflops": achieved, "roofline_peak_tflops": MFMA_FP64_TFLOPS,
+                  "roofline_frac": achieved / MFMA_FP64_TFLOPS})
     if shape["variant"] == 3:
         R = float(shape["rows_per_lane"])
         mix = {"fp64": (8 * R + 107) / R, "fp32": 70 / R}

@@ -194,11 +194,18 @@ struct Shape {
 int pick_form(int precision, uint32_t flags, const gbd_eval_opts *o, bool allow_sep = true) {
     const bool steep = (flags & FLAG_STEEP) != 0;
     if (precision != GBD_MIXED) {
-        // FP64: direct or rotor (the rotor form needs a well-sampled grid and
-        // carries no higher-order factor)
+        // FP64: direct, rotor (needs a well-sampled grid) or separable (needs
+        // phasors without cross terms); neither of the last two carries a
+        // higher-order factor.  A request that does not apply falls back to
+        // the automatic choice among the others.
+        const bool hg = (flags & FLAG_HG) != 0;
+        const bool sep64 = allow_sep && !(flags & FLAG_CROSS) && !hg;
+        const bool rot64 = !steep && !hg;
         const int v = o ? o->variant : 0;
-        if (v == 1 || steep || (flags & FLAG_HG)) return 0;
-        return 2;
+        if (v == 1) return 0;
+        if (v == 3 && rot64) return 2;
+        if (v == 4 && sep64) return 3;
+        return sep64 ? 3 : rot64 ? 2 : 0;
     }
     const bool sep = allow_sep && !(flags & FLAG_CROSS);
     const int v = o ? o->variant : 0;
@@ -230,9 +237,10 @@ Shape choose_shape(const gbd_ctx_s *ctx, int precision, int64_t n, const PlaneGe
     Shape s;
     s.form = pick_form(precision, flags, o);
     if (s.form == 3) {
-        // separable form: fixed 64 x 64 pixel tile per wavefront; the row and
-        // wavefront options of the other forms do not apply
-        s.rows = kSepTile;
+        // separable form: fixed pixel tile per wavefront, 64 x 64 (mixed) or
+        // 64 x 32 (FP64; s.rows is the tile height); the row and wavefront
+        // options of the other forms do not apply
+        s.rows = precision == GBD_MIXED ? kSepTile : kSepRows64;
         s.waves = kSepWavesX * kSepWavesY;
         s.nseg = (o && o->segments > 0) ? o->segments : 0;
         if (s.nseg <= 0) {
@@ -242,7 +250,7 @@ Shape choose_shape(const gbd_ctx_s *ctx, int precision, int64_t n, const PlaneGe
             // 0.93 ms, 40 1.11 ms, 48 0.95 ms)
             const int64_t tiles = std::max<int64_t>(
                 1, (int64_t)((pl.nx + kSepTile * kSepWavesX - 1) / (kSepTile * kSepWavesX)) *
-                       ((pl.ny + kSepTile * kSepWavesY - 1) / (kSepTile * kSepWavesY)));
+                       ((pl.ny + s.rows * kSepWavesY - 1) / (s.rows * kSepWavesY)));
             int64_t seg = ((int64_t)ctx->cus * 2 + tiles - 1) / tiles;
             seg = std::min<int64_t>(seg, std::max<int64_t>(1, n / 256));
             s.nseg = (int)std::max<int64_t>(1, std::min<int64_t>(seg, 1024));
@@ -301,7 +309,7 @@ EvalGeom make_geom(const PlaneGeom &pl, int64_t n, const Shape &s) {
     g.b0 = -0.5 * (pl.ny - 1) * pl.dy;
     if (s.form == 3) {
         g.tiles_x = (pl.nx + kSepTile * kSepWavesX - 1) / (kSepTile * kSepWavesX);
-        g.tiles_y = (pl.ny + kSepTile * kSepWavesY - 1) / (kSepTile * kSepWavesY);
+        g.tiles_y = (pl.ny + s.rows * kSepWavesY - 1) / (s.rows * kSepWavesY);
     } else {
         g.tiles_x = (pl.nx + 63) / 64;
         g.tiles_y = (pl.ny + s.waves * s.rows - 1) / (s.waves * s.rows);
@@ -422,7 +430,11 @@ int plan_eval_impl(gbd_ctx_s *ctx, gbd_plan_s *plan, int precision, void *out, i
         const void *hrec = !hg ? nullptr : precision == GBD_FP64 ? (const void *)plan->h64 : (const void *)plan->h32;
         EvalGeom gl = g;
         if (reduce) gl.nseg = std::max<int32_t>(total, 2);  // segment partials, never the output
-        if (s.form == 3)
+        if (s.form == 3 && precision == GBD_FP64)
+            HIP_TRY(launch_eval_sep64(gl, plan->r64, static_cast<double2 *>(plan->scratch), static_cast<double2 *>(out),
+                                      ctx->stream),
+                    "eval kernel launch");
+        else if (s.form == 3)
             HIP_TRY(launch_eval_sep(gl, plan->r32, static_cast<const RecHG32 *>(hrec),
                                     static_cast<float4 *>(plan->scratch), static_cast<float2 *>(out), ctx->stream),
                     "eval kernel launch");

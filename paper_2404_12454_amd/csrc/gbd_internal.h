@@ -294,6 +294,11 @@ hipError_t launch_reduce(int precision, const EvalGeom &g, const void *partial, 
 // wavefronts, each wavefront a 64 x 64 pixel tile; partials as float4 (re, im, 0, 0).
 constexpr int kSepWavesX = 2, kSepWavesY = 2;
 constexpr int kSepTile = 64;
+// The FP64 separable form on FP64 MFMA: wavefront tiles of 64 x 32 pixels
+// (kSepRows64 rows), 2 x 2 wavefronts per workgroup; double2 partials.
+constexpr int kSepRows64 = 32;
+hipError_t launch_eval_sep64(const EvalGeom &g, const Rec64 *rec, double2 *partial, double2 *out, hipStream_t s);
+
 // hg: higher-order factors without cross terms (k1 = k0 = 0, G diagonal), or null.
 hipError_t launch_eval_sep(const EvalGeom &g, const Rec32 *rec, const RecHG32 *hg, float4 *partial, float2 *out,
                            hipStream_t s);

@@ -1,0 +1,186 @@
+// Separable (matrix) form in FP64: where no beamlet's phasor has a cross
+// term the coherent sum factors over the plane's two axes,
+//   E(a_i, b_r) = sum_j U_j(a_i) V_j(b_r),
+//   U_j(a) = e^(l0 + l1 da + l3 da^2) e^(2 pi i (p0 + p1 da + p3 da^2)),
+//   V_j(b) = e^(l2 db + l5 db^2)      e^(2 pi i (p2 db + p5 db^2)),
+// a complex matrix product over the beamlet index on FP64 MFMA
+// (v_mfma_f64_16x16x4_f64, FP64 products and sums).  Each factor is the FP64
+// form's phasor (phase reduced to turns, the device library's exp and
+// sincospi), so every beamlet-pixel term is the same product as in the other
+// FP64 forms; only the order of the sum changes.
+//
+// Tiling: a 16 x 16 block of FP64 accumulators takes 8 VGPRs per lane and
+// part (Re, Im), so a wavefront owns 64 x 32 pixels (4 x 2 blocks, 128
+// accumulator VGPRs) and walks its segment four beamlets per step (the
+// MFMA's K = 4), 32 MFMAs per step.  Four wavefronts (2 x 2, a 128 x 64
+// pixel workgroup tile) share the factors through double-buffered LDS, one
+// barrier per step: a lane forms 2 U and 1 V factor per step instead of 6.
+// Operand layout as in the FP32 form: lane l supplies V_{j0 + l/16} at row
+// l % 16 of its block as the A operand and U_{j0 + l/16} at column l % 16 as
+// the B operand; unlike the FP32 instruction it holds rows l / 16 + 4 e,
+// e = 0..3, column l % 16 of each result block (found by a lane-layout probe
+// and fixed by the parity tests).  Segments are summed in FP64 by the
+// reduction; the host sizes them so that every one is non-empty.
+#include "gbd_device.h"
+
+namespace gbd {
+
+namespace {
+
+using namespace dev;
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+constexpr int kBX = 4, kBY = 2;  // 16-pixel blocks per wavefront along x and y
+
+struct Fields64 {
+    double arho, brho, p0, p1, p2, p3, p5, l0, l1, l2, l3, l5;
+    double lbias;  // 0, or -inf past the segment end (factor 0)
+};
+
+__device__ inline Fields64 load_fields64(const Rec64 *__restrict__ rec, int64_t j, int64_t jb, int64_t je) {
+    const Rec64 *rp = rec + (j < je ? j : jb);
+    Fields64 f;
+    f.arho = rp->arho;
+    f.brho = rp->brho;
+    f.p0 = rp->p[0];
+    f.p1 = rp->p[1];
+    f.p2 = rp->p[2];
+    f.p3 = rp->p[3];
+    f.p5 = rp->p[5];
+    f.l0 = rp->l[0];
+    f.l1 = rp->l[1];
+    f.l2 = rp->l[2];
+    f.l3 = rp->l[3];
+    f.l5 = rp->l[5];
+    f.lbias = j < je ? 0.0 : -INFINITY;
+    return f;
+}
+
+// e^(g0 + d (g1 + g2 d)) e^(2 pi i (c0 + d (c1 + c2 d))), FP64
+__device__ inline double2 factor64(double d, double c0, double c1, double c2, double g0, double g1, double g2) {
+    double T = c0 + d * (c1 + c2 * d);
+    T -= rint(T);
+    double s, c;
+    sincospi(2.0 * T, &s, &c);
+    const double m = exp(g0 + d * (g1 + g2 * d));
+    return make_double2(m * c, m * s);
+}
+
+template <int WX, int WY>
+__global__ void __launch_bounds__(64 * WX * WY) eval_sep64_kernel(EvalGeom g, const Rec64 *__restrict__ rec,
+                                                                   double2 *__restrict__ partial,
+                                                                   double2 *__restrict__ out) {
+    static_assert(WX == 2 && WY == 2, "factor sharing assumes 2 x 2 wavefronts");
+    __shared__ double2 lu[2][WX][kBX][64], lv[2][WY][kBY][64];  // [buffer][range][block][lane]
+    const int w = work_item(blockIdx.x, gridDim.x);
+    if (w >= g.work) return;
+    const int tiles = g.tiles_x * g.tiles_y;
+    const int seg = w / tiles;
+    const int t = w - seg * tiles;
+    const int ty = t / g.tiles_x, tx = t - ty * g.tiles_x;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int wx = wv % WX, wy = wv / WX;
+    const int x0 = (tx * WX + wx) * 16 * kBX, y0 = (ty * WY + wy) * 16 * kBY;
+    const int li = lane & 15, lk = lane >> 4;
+
+    // Wavefront (wx, wy) forms U blocks 2 wy, 2 wy + 1 of x range wx (shared
+    // with (wx, 1 - wy)) and V block wx of y range wy (shared with (1 - wx, wy)).
+    double ax[2], lx[2];
+    for (int h = 0; h < 2; h++) {
+        const int ix = x0 + 16 * (2 * wy + h) + li;
+        ax[h] = g.a0 + ix * g.dx;
+        lx[h] = ix < g.nx ? 0.0 : -INFINITY;
+    }
+    const int iyv = y0 + 16 * wx + li;
+    const double by = g.b0 + iyv * g.dy;
+    const double ly = iyv < g.ny ? 0.0 : -INFINITY;
+    auto publish = [&](const Fields64 &f, int buf) {
+#pragma unroll
+        for (int h = 0; h < 2; h++)
+            lu[buf][wx][2 * wy + h][lane] =
+                factor64(ax[h] - f.arho, f.p0, f.p1, f.p3, f.l0 + (f.lbias + lx[h]), f.l1, f.l3);
+        lv[buf][wy][wx][lane] = factor64(by - f.brho, 0.0, f.p2, f.p5, ly, f.l2, f.l5);
+    };
+
+    // accR/accI[p][q]: rows of the product are y (A operand = V), columns x (B = U)
+    d4 accR[kBY][kBX], accI[kBY][kBX];
+#pragma unroll
+    for (int p = 0; p < kBY; p++)
+#pragma unroll
+        for (int q = 0; q < kBX; q++) accR[p][q] = accI[p][q] = d4{0.0, 0.0, 0.0, 0.0};
+
+    const int64_t jb = (int64_t)seg * g.seg_len;
+    const int64_t je = min(g.n, jb + g.seg_len);
+    publish(load_fields64(rec, jb + lk, jb, je), 0);
+    Fields64 nxt = load_fields64(rec, jb + 4 + lk, jb, je);
+    __syncthreads();
+    int buf = 0;
+    for (int64_t j0 = jb; j0 < je; j0 += 4) {
+        // this step's factors first (published before the last barrier)
+        double ur[kBX], ui[kBX], vr[kBY], vi[kBY], vn[kBY];
+#pragma unroll
+        for (int b = 0; b < kBX; b++) {
+            const double2 u = lu[buf][wx][b][lane];
+            ur[b] = u.x;
+            ui[b] = u.y;
+        }
+#pragma unroll
+        for (int b = 0; b < kBY; b++) {
+            const double2 v = lv[buf][wy][b][lane];
+            vr[b] = v.x;
+            vi[b] = v.y;
+            vn[b] = -v.y;
+        }
+        const Fields64 f = nxt;
+        nxt = load_fields64(rec, j0 + 8 + lk, jb, je);
+        if (j0 + 4 < je) publish(f, buf ^ 1);
+        // Re += Vr Ur - Vi Ui ; Im += Vr Ui + Vi Ur
+#pragma unroll
+        for (int p = 0; p < kBY; p++)
+#pragma unroll
+            for (int q = 0; q < kBX; q++) {
+                accR[p][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(vr[p], ur[q], accR[p][q], 0, 0, 0);
+                accI[p][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(vr[p], ui[q], accI[p][q], 0, 0, 0);
+            }
+#pragma unroll
+        for (int p = 0; p < kBY; p++)
+#pragma unroll
+            for (int q = 0; q < kBX; q++) {
+                accR[p][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(vn[p], ui[q], accR[p][q], 0, 0, 0);
+                accI[p][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(vi[p], ur[q], accI[p][q], 0, 0, 0);
+            }
+        __syncthreads();
+        buf ^= 1;
+    }
+
+    const int64_t M = (int64_t)g.nx * g.ny;
+#pragma unroll
+    for (int p = 0; p < kBY; p++)
+#pragma unroll
+        for (int q = 0; q < kBX; q++) {
+            const int ix = x0 + 16 * q + li;
+            if (ix >= g.nx) continue;
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+                const int iy = y0 + 16 * p + lk + 4 * e;
+                if (iy >= g.ny) continue;
+                const int64_t px = (int64_t)iy * g.nx + ix;
+                const double2 v = make_double2(accR[p][q][e], accI[p][q][e]);
+                if (g.nseg == 1)
+                    out[px] = v;
+                else
+                    partial[(int64_t)seg * M + px] = v;
+            }
+        }
+}
+
+}  // namespace
+
+hipError_t launch_eval_sep64(const EvalGeom &g, const Rec64 *rec, double2 *partial, double2 *out, hipStream_t s) {
+    const int grid = (g.work + 7) / 8 * 8;
+    eval_sep64_kernel<kSepWavesX, kSepWavesY><<<grid, 64 * kSepWavesX * kSepWavesY, 0, s>>>(g, rec, partial, out);
+    return hipGetLastError();
+}
+
+}  // namespace gbd

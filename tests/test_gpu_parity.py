@@ -146,32 +146,52 @@ def test_steep_grid_falls_back_to_direct(ctx):
     assert plan.shape(gbd.GBD_MIXED, opts=dict(variant=3))["variant"] == 1
     # 32 rows per lane is a rotor-form shape; the direct form runs 16
     assert plan.shape(gbd.GBD_MIXED, opts=dict(rows_per_lane=32, variant=1))["rows_per_lane"] == 16
-    # FP64: the rotor form needs the curvature bound as well; its direct form runs at most 8 rows
-    assert plan.shape(gbd.GBD_FP64)["variant"] == 1
-    assert plan.shape(gbd.GBD_FP64, opts=dict(variant=3))["variant"] == 1
-    assert plan.shape(gbd.GBD_FP64, opts=dict(rows_per_lane=32))["rows_per_lane"] == 8
+    # FP64: the separable form needs no curvature bound, the rotor form does;
+    # the FP64 direct form runs at most 8 rows
+    assert plan.shape(gbd.GBD_FP64)["variant"] == 4
+    assert plan.shape(gbd.GBD_FP64, opts=dict(variant=3))["variant"] == 4
+    assert plan.shape(gbd.GBD_FP64, opts=dict(rows_per_lane=32, variant=1))["rows_per_lane"] == 8
 
 
 @pytest.mark.parametrize("name", ["airy32_64", "zern128_1024"])
 def test_fp64_rotor_form_is_chosen_and_matches(ctx, name):
-    """On well-sampled grids the automatic FP64 form is the rotor one (the
-    mixed rotor recurrence in FP64, no per-pixel exp or sincospi); it agrees
-    with the FP64 direct form to rounding and with the oracle."""
+    """The automatic FP64 form: separable (FP64 MFMA) without cross terms,
+    else the rotor one (the mixed rotor recurrence in FP64, no per-pixel exp
+    or sincospi); both agree with the FP64 direct form to rounding and with
+    the oracle."""
     sc = scenes.config(name)
     b = gbd.beamlets_from_scene(ctx, sc)
     p = gbd.plane_from_scene(ctx, sc)
     plan = gbd.Plan(ctx, sc.n).setup(b, p)
     shape = plan.shape(gbd.GBD_FP64)
-    assert shape["variant"] == 3
-    E3 = plan.eval(gbd.GBD_FP64).cpu().numpy()
+    assert shape["variant"] == (4 if name.startswith("airy") else 3)
     E1 = plan.eval(gbd.GBD_FP64, opts=dict(variant=1)).cpu().numpy()
-    print(name, shape, "FP64 rotor vs direct", rel_l2(E3, E1), flush=True)
-    assert rel_l2(E3, E1) < 1e-13
-    if sc.plane.npix <= 4096:
-        check(E3, oracle.eval_field(sc), gbd.GBD_FP64, name + " FP64 rotor")
-    else:
-        ix, iy = sample_pixels(sc.plane.nx, sc.plane.ny, 100, 9)
-        check(E3[iy, ix], oracle.eval_field(sc, pixels=(ix, iy)), gbd.GBD_FP64, name + " FP64 rotor sampled")
+    for v in ((4, 3) if name.startswith("airy") else (3,)):
+        E = plan.eval(gbd.GBD_FP64, opts=dict(variant=v)).cpu().numpy()
+        print(name, plan.shape(gbd.GBD_FP64, dict(variant=v)), "FP64 variant", v, "vs direct", rel_l2(E, E1),
+              flush=True)
+        assert rel_l2(E, E1) < 1e-13
+        if sc.plane.npix <= 4096:
+            check(E, oracle.eval_field(sc), gbd.GBD_FP64, f"{name} FP64 variant {v}")
+        else:
+            ix, iy = sample_pixels(sc.plane.nx, sc.plane.ny, 100, 9)
+            check(E[iy, ix], oracle.eval_field(sc, pixels=(ix, iy)), gbd.GBD_FP64, f"{name} FP64 variant {v} sampled")
+
+
+@pytest.mark.parametrize("nx,ny,seg", [(70, 45, 1), (70, 45, 3), (129, 200, 0), (1, 1, 1), (65, 1, 2), (1, 70, 0),
+                                       (300, 97, 5)])
+def test_fp64_separable_form_ragged_defocused_off_axis(ctx, nx, ny, seg):
+    """The FP64 separable form (FP64 MFMA) on grids that leave blocks,
+    wavefront and workgroup tiles partly empty, a beamlet count not a multiple
+    of K = 4, a field angle and a defocused plane."""
+    sc = scenes.airy_scene(21, npix=nx, npix_y=ny, half_span_lamF=6.0, field_angle=(1e-3, -5e-4), z0=30e-6)
+    b = gbd.beamlets_from_scene(ctx, sc)
+    p = gbd.plane_from_scene(ctx, sc)
+    plan = gbd.Plan(ctx, sc.n).setup(b, p)
+    o = dict(segments=seg)
+    assert plan.shape(gbd.GBD_FP64, opts=o)["variant"] == 4
+    check(plan.eval(gbd.GBD_FP64, opts=o).cpu().numpy(), oracle.eval_field(sc), gbd.GBD_FP64,
+          f"FP64 separable {nx}x{ny} seg {seg}")
 
 
 @pytest.mark.parametrize("precision", BOTH)
