@@ -66,8 +66,10 @@ typedef struct {
     int32_t segments;       /* beamlet segments evaluated by separate workgroups, 0 = auto */
     int32_t variant;        /* 0 = auto.  FP64: 1 = direct (exp and sincospi per pixel), 3 =
                                rotor (the recurrence below in FP64; well-sampled grids and
-                               fundamental beamlets only); auto: rotor where it applies,
-                               else direct; other values resolve as auto.
+                               fundamental beamlets only), 4 = separable (below, on FP64
+                               MFMA; no cross terms, fundamental beamlets only); auto:
+                               separable, else rotor, else direct; a request that does not
+                               apply resolves as auto among the others.
                                Mixed: 1 = direct: FP64 phase and exp2
                                per pixel; 2 = stepped: FP64 phase per lane and beamlet
                                with FP32 row steps, amplitude stepped by multiplication;
