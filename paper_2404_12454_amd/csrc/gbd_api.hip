@@ -414,8 +414,11 @@ int plan_eval_impl(gbd_ctx_s *ctx, gbd_plan_s *plan, int precision, void *out, i
     }
     const int32_t total = nseg_main + nseg_cut;
     const bool reduce = total > 1 || nseg_cut > 0;
+    // the mixed separable form's partials are compact (float2) and come first
+    const bool compact = n_main > 0 && s.form == 3 && precision == GBD_MIXED;
+    const int32_t nseg2 = compact ? nseg_main : 0;
     if (reduce) {
-        const size_t need = (size_t)total * (size_t)M * 16;
+        const size_t need = (size_t)total * (size_t)M * 16;  // bounds the compact layout too
         if (need > plan->scratch_bytes) {
             if (plan->scratch) (void)hipFree(plan->scratch);
             plan->scratch = nullptr;
@@ -436,7 +439,7 @@ int plan_eval_impl(gbd_ctx_s *ctx, gbd_plan_s *plan, int precision, void *out, i
                     "eval kernel launch");
         else if (s.form == 3)
             HIP_TRY(launch_eval_sep(gl, plan->r32, static_cast<const RecHG32 *>(hrec),
-                                    static_cast<float4 *>(plan->scratch), static_cast<float2 *>(out), ctx->stream),
+                                    static_cast<float2 *>(plan->scratch), static_cast<float2 *>(out), ctx->stream),
                     "eval kernel launch");
         else
             HIP_TRY(launch_eval(precision, s.rows, s.waves, s.form, gl, rec, hrec, plan->q64, plan->scratch, out,
@@ -446,13 +449,14 @@ int plan_eval_impl(gbd_ctx_s *ctx, gbd_plan_s *plan, int precision, void *out, i
     if (nseg_cut > 0) {
         const void *rec = precision == GBD_FP64 ? (const void *)(plan->r64 + n_main) : (const void *)(plan->r32 + n_main);
         const void *crec = precision == GBD_FP64 ? (const void *)plan->c64 : (const void *)plan->c32;
-        HIP_TRY(launch_eval_cut(precision, gc, rec, crec, faddeeva_coef(), nseg_main, plan->scratch, ctx->stream),
+        void *wide = static_cast<char *>(plan->scratch) + reduce_wide_offset(nseg2, M);
+        HIP_TRY(launch_eval_cut(precision, gc, rec, crec, faddeeva_coef(), nseg_main - nseg2, wide, ctx->stream),
                 "truncated-beamlet kernel launch");
     }
     if (reduce) {
         EvalGeom gr = n_main > 0 ? g : gc;
         gr.nseg = total;
-        HIP_TRY(launch_reduce(precision, gr, plan->scratch, out, ctx->stream), "reduce kernel launch");
+        HIP_TRY(launch_reduce(precision, gr, nseg2, plan->scratch, out, ctx->stream), "reduce kernel launch");
     }
     return GBD_OK;
 }
@@ -484,7 +488,7 @@ int plan_setup_impl(gbd_ctx_s *ctx, gbd_plan_s *plan, gbd_beamlets_s *b, gbd_pla
         HIP_TRY(hipMemsetAsync(plan->status_dev, 0, sizeof(uint32_t), ctx->stream), "hipMemsetAsync(status)");
         const bool hg = b->dev.order != nullptr;
         const bool cut = b->dev.n_cut > 0;
-        HIP_TRY(launch_setup(b->dev, p->g, gturns, plan->r64, plan->r32, plan->q64, hg ? plan->h64 : nullptr,
+        HIP_TRY(launch_setup(b->dev, p->g, gturns, plan->r64, plan->r32, hg ? plan->h64 : nullptr,
                              hg ? plan->h32 : nullptr, cut ? plan->c64 : nullptr, cut ? plan->c32 : nullptr,
                              plan->status_dev, ctx->stream),
                 "setup kernel launch");

@@ -55,6 +55,24 @@ __device__ inline bool on_branch(cd mu) {
 
 __device__ inline double il2_dev() { return 1.4426950408889634074; }  // 1 / ln 2
 
+// sigma^(k^2) of the rotor recurrence in FP64 for a beamlet whose row
+// quadratic coefficients are p5 (turns / m^2) and l5 (ln amplitude / m^2), on
+// rows dy apart: the phase k^2 p5 dy^2 is reduced mod 1 before the
+// trigonometry (k^2 integer), the exponent capped so a refused steep grid
+// still gives finite values.  The setup rounds it to the FP32 table; the FP64
+// rotor form's table is computed from the FP64 records at evaluation.
+__device__ inline double2 rotor_sigma(double p5, double l5, double dy, int k) {
+    const double t2 = p5 * dy * dy;
+    const double u2 = l5 * il2_dev() * dy * dy;
+    const double kk = (double)(k * k);
+    double ph = kk * t2;
+    ph -= rint(ph);
+    double sn, cs;
+    sincospi(2.0 * ph, &sn, &cs);
+    const double g = exp2(fmin(kk * u2, 64.0));
+    return make_double2(g * cs, g * sn);
+}
+
 // One beamlet propagated onto the plane; writes its phasor records (either
 // pointer may be null) and returns FLAG_* bits (0 = fine).
 // Higher-order beamlets: h64 / h32 (either may be null) receive the
@@ -65,7 +83,7 @@ __device__ inline double il2_dev() { return 1.4426950408889634074; }  // 1 / ln 
 // direct form of their own kernel).
 __device__ inline uint32_t setup_one(const BeamletsDev &b, const PlaneGeom &pl, double gturns, int64_t j,
                                      Rec64 *r64, Rec32 *r32, RecHG64 *h64 = nullptr, RecHG32 *h32 = nullptr,
-                                     RecCut64 *c64 = nullptr, RecCut32 *c32 = nullptr, RecSq64 *q64 = nullptr) {
+                                     RecCut64 *c64 = nullptr, RecCut32 *c32 = nullptr) {
     const double *M = b.abcd + (b.n_abcd == 1 ? 0 : 16 * j);
     double A[2][2], B[2][2], C[2][2], D[2][2];
 #pragma unroll
@@ -103,7 +121,6 @@ __device__ inline uint32_t setup_one(const BeamletsDev &b, const PlaneGeom &pl, 
     const double dl = sqrt(th[0] * th[0] + th[1] * th[1] + 1.0);
     Rec64 o64 = {};
     Rec32 o32 = {};
-    RecSq64 oq = {};
     RecHG64 oh = {};
     RecCut64 oc = {};
     const int64_t cut0 = b.n - b.n_cut;
@@ -345,22 +362,12 @@ __device__ inline uint32_t setup_one(const BeamletsDev &b, const PlaneGeom &pl, 
         const float dyf = (float)pl.dy;
         o32.u2 = o32.m[5] * (dyf * dyf);
         o32.s2 = exp2f(fminf(2.0f * o32.u2, 1.0f));
-        // rotor form: sigma^(k^2) in FP64, phase reduced mod 1 before the
-        // trigonometry (k^2 integer), exponent capped so a refused steep grid
-        // still stores finite values
-        const double u2 = l[5] * il2 * pl.dy * pl.dy;
+        // rotor form: sigma^(k^2), rounded from FP64
 #pragma unroll
         for (int k = 1; k <= kRotorRows; k++) {
-            const double kk = (double)(k * k);
-            double ph = kk * t2;
-            ph -= rint(ph);
-            double sn, cs;
-            sincospi(2.0 * ph, &sn, &cs);
-            const double g = exp2(fmin(kk * u2, 64.0));
-            oq.sq[k - 1][0] = g * cs;
-            oq.sq[k - 1][1] = g * sn;
-            o32.sq[k - 1][0] = (float)oq.sq[k - 1][0];
-            o32.sq[k - 1][1] = (float)oq.sq[k - 1][1];
+            const double2 sq = rotor_sigma(p[5], l[5], pl.dy, k);
+            o32.sq[k - 1][0] = (float)sq.x;
+            o32.sq[k - 1][1] = (float)sq.y;
         }
     }
     if (flag & FLAG_ERRORS) {
@@ -370,7 +377,6 @@ __device__ inline uint32_t setup_one(const BeamletsDev &b, const PlaneGeom &pl, 
     }
     if (r64) r64[j] = o64;
     if (r32) r32[j] = o32;
-    if (q64) q64[j] = oq;
     if (is_cut && c64) c64[j - cut0] = oc;
     if (is_cut && c32) {
         RecCut32 o;

@@ -61,7 +61,7 @@ static_assert(sizeof(Rec32) == 240, "Rec32 layout");
 constexpr int kRec32Vec4 = sizeof(Rec32) / 16;
 
 // FP64 rotor form: sigma^(k^2), k = 1..16, of each beamlet in FP64 (the Rec32
-// table's source values), kept beside the Rec64 records.
+// table's source values), computed from the Rec64 records when that form runs.
 struct alignas(16) RecSq64 {
     double sq[16][2];
 };
@@ -268,7 +268,7 @@ hipError_t launch_mlp_adamw(float *p, const float *g, float *m, float *v, int64_
                             float eps, float wd, float c1, float c2, hipStream_t s);
 
 hipError_t launch_setup(const BeamletsDev &b, const PlaneGeom &pl, double global_turns, Rec64 *r64,
-                        Rec32 *r32, RecSq64 *q64, RecHG64 *h64, RecHG32 *h32, RecCut64 *c64, RecCut32 *c32,
+                        Rec32 *r32, RecHG64 *h64, RecHG32 *h32, RecCut64 *c64, RecCut32 *c32,
                         uint32_t *status, hipStream_t s);
 
 // Truncated beamlets (direct form with the complex error function): the n
@@ -284,11 +284,18 @@ hipError_t launch_eval_cut(int precision, const EvalGeom &g, const void *rec, co
 // factored as anchor x rho^k x sigma^(k^2), no per-pixel transcendental.
 // hg: RecHG64 / RecHG32 records of higher-order beamlets (direct and FP64
 // forms only), or null.  precision 0 with form 2: the FP64 rotor form, q64
-// its sigma^(k^2) tables.
+// room for its sigma^(k^2) tables (one per beamlet, filled from the records
+// before the evaluation).
 hipError_t launch_eval(int precision, int rows, int waves, int form, const EvalGeom &g, const void *rec,
                        const void *hg, const RecSq64 *q64, void *partial, void *out, hipStream_t s);
 
-hipError_t launch_reduce(int precision, const EvalGeom &g, const void *partial, void *out, hipStream_t s);
+// Sums the g.nseg segment partials of every pixel in segment order, in FP64.
+// Mixed precision: the first nseg2 segments are compact (float2 sums), the
+// others float4 (sum, compensation) starting at reduce_wide_offset(nseg2, M)
+// bytes into partial; FP64: double2 (nseg2 must be 0).
+hipError_t launch_reduce(int precision, const EvalGeom &g, int32_t nseg2, const void *partial, void *out,
+                         hipStream_t s);
+inline size_t reduce_wide_offset(int32_t nseg2, int64_t M) { return ((size_t)nseg2 * (size_t)M * 8 + 15) & ~(size_t)15; }
 
 // Separable (matrix) form on FP32 MFMA: workgroups of kSepWavesX x kSepWavesY
 // wavefronts, each wavefront a 64 x 64 pixel tile; partials as float4 (re, im, 0, 0).
@@ -300,7 +307,9 @@ constexpr int kSepRows64 = 32;
 hipError_t launch_eval_sep64(const EvalGeom &g, const Rec64 *rec, double2 *partial, double2 *out, hipStream_t s);
 
 // hg: higher-order factors without cross terms (k1 = k0 = 0, G diagonal), or null.
-hipError_t launch_eval_sep(const EvalGeom &g, const Rec32 *rec, const RecHG32 *hg, float4 *partial, float2 *out,
+// Partials as float2 (no compensation term): the compact segments of
+// launch_reduce.
+hipError_t launch_eval_sep(const EvalGeom &g, const Rec32 *rec, const RecHG32 *hg, float2 *partial, float2 *out,
                            hipStream_t s);
 
 }  // namespace gbd

@@ -24,11 +24,30 @@ __global__ void __launch_bounds__(256) setup_kernel(BeamletsDev b, PlaneGeom pl,
                                                     Rec64 *__restrict__ r64, Rec32 *__restrict__ r32,
                                                     RecHG64 *__restrict__ h64, RecHG32 *__restrict__ h32,
                                                     RecCut64 *__restrict__ c64, RecCut32 *__restrict__ c32,
-                                                    RecSq64 *__restrict__ q64, uint32_t *__restrict__ status) {
+                                                    uint32_t *__restrict__ status) {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= b.n) return;
-    const uint32_t flag = setup_one(b, pl, gturns, j, r64, r32, h64, h32, c64, c32, q64);
+    const uint32_t flag = setup_one(b, pl, gturns, j, r64, r32, h64, h32, c64, c32);
     if (flag) atomicOr(status, flag);
+}
+
+// The FP64 rotor form's sigma^(k^2) tables, k = 1..16, from the FP64 records
+// on rows dy apart.  Thread t of a block computes entry t % 16 of beamlet
+// 16 (block) + t / 16, so the 256-byte records are written contiguously.
+__global__ void __launch_bounds__(256) sigma64_kernel(int64_t n, double dy, const Rec64 *__restrict__ rec,
+                                                      RecSq64 *__restrict__ q64) {
+    const int64_t j = (int64_t)blockIdx.x * 16 + (threadIdx.x >> 4);
+    const int k = (threadIdx.x & 15) + 1;
+    if (j >= n) return;
+    const double2 v = rotor_sigma(rec[j].p[5], rec[j].l[5], dy, k);
+    q64[j].sq[k - 1][0] = v.x;
+    q64[j].sq[k - 1][1] = v.y;
+}
+
+hipError_t launch_sigma64(const EvalGeom &g, const Rec64 *rec, RecSq64 *q64, hipStream_t s) {
+    if (g.n == 0) return hipSuccess;
+    sigma64_kernel<<<(unsigned)((g.n + 15) / 16), 256, 0, s>>>(g.n, g.dy, rec, q64);
+    return hipGetLastError();
 }
 
 // Mixed form.  Each lane owns ROWS pixels of one detector column; a
@@ -290,12 +309,18 @@ __global__ void __launch_bounds__(64 * WAVES) eval_fp64_rotor_kernel(EvalGeom g,
     }
 }
 
-__global__ void __launch_bounds__(256) reduce_mixed_kernel(int64_t M, int32_t nseg, const float4 *__restrict__ part,
+__global__ void __launch_bounds__(256) reduce_mixed_kernel(int64_t M, int32_t nseg2, const float2 *__restrict__ part2,
+                                                           int32_t nseg4, const float4 *__restrict__ part4,
                                                            float2 *__restrict__ out) {
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < M; p += (int64_t)gridDim.x * blockDim.x) {
         double re = 0.0, im = 0.0;
-        for (int s = 0; s < nseg; s++) {
-            const float4 v = part[(int64_t)s * M + p];
+        for (int s = 0; s < nseg2; s++) {
+            const float2 v = part2[(int64_t)s * M + p];
+            re += (double)v.x;
+            im += (double)v.y;
+        }
+        for (int s = 0; s < nseg4; s++) {
+            const float4 v = part4[(int64_t)s * M + p];
             re += (double)v.x - (double)v.z;
             im += (double)v.y - (double)v.w;
         }
@@ -322,6 +347,8 @@ hipError_t launch_eval_t(int precision, int form, const EvalGeom &g, const void 
     const int grid = (g.work + 7) / 8 * 8;
     if (precision == 0 && form == 2 && !hg) {
         if (!q64) return hipErrorInvalidValue;
+        const hipError_t e = launch_sigma64(g, static_cast<const Rec64 *>(rec), const_cast<RecSq64 *>(q64), s);
+        if (e != hipSuccess) return e;
         eval_fp64_rotor_kernel<ROWS, WAVES><<<grid, 64 * WAVES, 0, s>>>(
             g, static_cast<const Rec64 *>(rec), q64, static_cast<double2 *>(partial), static_cast<double2 *>(out));
         return hipGetLastError();
@@ -368,11 +395,10 @@ hipError_t launch_eval_t(int precision, int form, const EvalGeom &g, const void 
 }  // namespace
 
 hipError_t launch_setup(const BeamletsDev &b, const PlaneGeom &pl, double global_turns, Rec64 *r64, Rec32 *r32,
-                        RecSq64 *q64, RecHG64 *h64, RecHG32 *h32, RecCut64 *c64, RecCut32 *c32, uint32_t *status,
-                        hipStream_t s) {
+                        RecHG64 *h64, RecHG32 *h32, RecCut64 *c64, RecCut32 *c32, uint32_t *status, hipStream_t s) {
     if (b.n == 0) return hipSuccess;
     const int64_t blocks = (b.n + 255) / 256;
-    setup_kernel<<<(unsigned)blocks, 256, 0, s>>>(b, pl, global_turns, r64, r32, h64, h32, c64, c32, q64, status);
+    setup_kernel<<<(unsigned)blocks, 256, 0, s>>>(b, pl, global_turns, r64, r32, h64, h32, c64, c32, status);
     return hipGetLastError();
 }
 
@@ -394,6 +420,8 @@ hipError_t launch_eval(int precision, int rows, int waves, int form, const EvalG
         const int grid = (g.work + 7) / 8 * 8;
         double2 *pt = static_cast<double2 *>(partial), *o = static_cast<double2 *>(out);
         const Rec64 *r = static_cast<const Rec64 *>(rec);
+        const hipError_t e = launch_sigma64(g, r, const_cast<RecSq64 *>(q64), s);
+        if (e != hipSuccess) return e;
         if (rows == 16 && waves == 1) eval_fp64_rotor_kernel<16, 1><<<grid, 64, 0, s>>>(g, r, q64, pt, o);
         else if (rows == 16 && waves == 2) eval_fp64_rotor_kernel<16, 2><<<grid, 128, 0, s>>>(g, r, q64, pt, o);
         else if (rows == 16 && waves == 4) eval_fp64_rotor_kernel<16, 4><<<grid, 256, 0, s>>>(g, r, q64, pt, o);
@@ -437,13 +465,17 @@ hipError_t launch_eval(int precision, int rows, int waves, int form, const EvalG
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_reduce(int precision, const EvalGeom &g, const void *partial, void *out, hipStream_t s) {
+hipError_t launch_reduce(int precision, const EvalGeom &g, int32_t nseg2, const void *partial, void *out,
+                         hipStream_t s) {
     const int64_t M = (int64_t)g.nx * g.ny;
     if (M == 0) return hipSuccess;
+    if (nseg2 < 0 || nseg2 > g.nseg || (precision != 1 && nseg2 != 0)) return hipErrorInvalidValue;
     const int64_t blocks = min((M + 255) / 256, (int64_t)4096);
     if (precision == 1)
-        reduce_mixed_kernel<<<(unsigned)blocks, 256, 0, s>>>(M, g.nseg, static_cast<const float4 *>(partial),
-                                                             static_cast<float2 *>(out));
+        reduce_mixed_kernel<<<(unsigned)blocks, 256, 0, s>>>(
+            M, nseg2, static_cast<const float2 *>(partial), g.nseg - nseg2,
+            reinterpret_cast<const float4 *>(static_cast<const char *>(partial) + reduce_wide_offset(nseg2, M)),
+            static_cast<float2 *>(out));
     else
         reduce_fp64_kernel<<<(unsigned)blocks, 256, 0, s>>>(M, g.nseg, static_cast<const double2 *>(partial),
                                                             static_cast<double2 *>(out));

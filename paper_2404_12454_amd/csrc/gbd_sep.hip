@@ -40,7 +40,7 @@ using namespace sep;
 template <int WX, int WY, bool HG>
 __global__ void __launch_bounds__(64 * WX * WY) eval_sep_kernel(EvalGeom g, const Rec32 *__restrict__ rec,
                                                                  const RecHG32 *__restrict__ hg,
-                                                                 float4 *__restrict__ partial,
+                                                                 float2 *__restrict__ partial,
                                                                  float2 *__restrict__ out) {
     constexpr int NB = kSepBlocks;
     __shared__ SepLds<NB> L;
@@ -73,17 +73,18 @@ __global__ void __launch_bounds__(64 * WX * WY) eval_sep_kernel(EvalGeom g, cons
                 const int iy = y0 + 16 * p + 4 * lk + e;
                 if (iy >= g.ny) continue;
                 const int64_t px = (int64_t)iy * g.nx + ix;
+                const float2 v = make_float2(accR[p][q][e], accI[p][q][e]);
                 if (g.nseg == 1)
-                    out[px] = make_float2(accR[p][q][e], accI[p][q][e]);
+                    out[px] = v;
                 else
-                    partial[(int64_t)seg * M + px] = make_float4(accR[p][q][e], accI[p][q][e], 0.0f, 0.0f);
+                    partial[(int64_t)seg * M + px] = v;
             }
         }
 }
 
 }  // namespace
 
-hipError_t launch_eval_sep(const EvalGeom &g, const Rec32 *rec, const RecHG32 *hg, float4 *partial, float2 *out,
+hipError_t launch_eval_sep(const EvalGeom &g, const Rec32 *rec, const RecHG32 *hg, float2 *partial, float2 *out,
                            hipStream_t s) {
     const int grid = (g.work + 7) / 8 * 8;
     if (hg)
