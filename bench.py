@@ -53,7 +53,7 @@ RATE = {"fp64": 64, "fp32": 128, "trans": 32}
 # HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE (x2.0)
 # and WRITE_SIZE (x1.0) runs, scale factors from a plain 256 MiB copy; valid
 # only for the kernel and launch they were taken on (else traffic is null).
-TRAFFIC = {("airy256_512", 64, 4, 32, 4): (5315.4 * 2.0 + 65536.0 * 1.0) * 1024}
+TRAFFIC = {("airy256_512", 32, 8, 16, 4): (5300.8 * 2.0 + 32768.0 * 1.0) * 1024}
 
 
 def instruction_mix(rows, variant, hg=False):
@@ -78,24 +78,31 @@ def roofline_peak(rows, variant, hg=False):
     return CUS * CLOCK_HZ / cycles, cycles, mix
 
 
-# Separable (matrix) form: the contraction E = V^T U over beamlets, 4 real
-# FP32 MFMA multiply-adds (8 flops) per beamlet-pixel pair; FP32 MFMA peak.
+# Separable (matrix) form: the contraction E = V^T U over beamlets.  The
+# algorithmic count is a complex multiply-add, 4 real multiply-adds (8 flops),
+# per beamlet-pixel pair, priced against the FP32 MFMA peak; the kernel
+# executes it as 3 real MFMA products (Gauss's form, 6 flops on the matrix
+# cores) plus 2 VALU additions per factor.
 MFMA_FP32_TFLOPS = 157.3
 SEP_FLOPS_PER_PAIR = 8.0
-# per lane and two steps (4 beamlets x 64 x 64 pixels of one wavefront each;
-# the loop is unrolled by two), counted in the compiled loop: 40 FP64, 48 FP32,
-# 24 transcendental and 49 other VALU instructions (the factors shared by 4
-# wavefronts), 128 MFMA 16x16x4
-SEP_VALU_PER_PAIR = {"fp64": 40 / 512, "fp32": 48 / 512, "trans": 24 / 512, "other": 49 / 512,
-                     "mfma_16x16x4": 128 / 32768}
+SEP_MFMA_FLOPS_PER_PAIR = 6.0
+# per lane and pass between barriers (16 beamlets x 64 x 32 pixels of one
+# wavefront), counted in the compiled loop: 40 FP64, 56 FP32, 24
+# transcendental and 62 other VALU instructions (the factors shared by 8
+# wavefronts), 96 MFMA 16x16x4
+SEP_VALU_PER_PAIR = {"fp64": 40 / 512, "fp32": 56 / 512, "trans": 24 / 512, "other": 62 / 512,
+                     "mfma_16x16x4": 96 / 32768}
 
 
 def roofline(shape, N, M, kernel_ms, hg=False):
     if shape["variant"] == 4:
         achieved = SEP_FLOPS_PER_PAIR * N * M / (kernel_ms * 1e-3) / 1e12
+        executed = achieved * SEP_MFMA_FLOPS_PER_PAIR / SEP_FLOPS_PER_PAIR
         return {"bound": "mfma", "achieved": achieved, "peak": MFMA_FP32_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved / MFMA_FP32_TFLOPS, "kernel": "eval_sep_kernel", "kernel_ms": kernel_ms,
-                "flops_per_pair": SEP_FLOPS_PER_PAIR, "instructions_per_pair": SEP_VALU_PER_PAIR}
+                "flops_per_pair": SEP_FLOPS_PER_PAIR, "mfma_flops_per_pair": SEP_MFMA_FLOPS_PER_PAIR,
+                "mfma_executed_tflops": executed, "mfma_busy_frac": executed / MFMA_FP32_TFLOPS,
+                "instructions_per_pair": SEP_VALU_PER_PAIR}
     achieved = N * M / (kernel_ms * 1e-3)
     peak, cycles, mix = roofline_peak(shape["rows_per_lane"], shape["variant"], hg)
     return {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "evals/s", "frac": achieved / peak,

@@ -237,21 +237,26 @@ Shape choose_shape(const gbd_ctx_s *ctx, int precision, int64_t n, const PlaneGe
     Shape s;
     s.form = pick_form(precision, flags, o);
     if (s.form == 3) {
-        // separable form: fixed pixel tile per wavefront, 64 x 64 (mixed) or
-        // 64 x 32 (FP64; s.rows is the tile height); the row and wavefront
-        // options of the other forms do not apply
-        s.rows = precision == GBD_MIXED ? kSepTile : kSepRows64;
-        s.waves = kSepWavesX * kSepWavesY;
+        // separable form: fixed 64 x 32 pixel tile per wavefront (s.rows is
+        // the tile height), 2 x 4 (mixed) or 2 x 2 (FP64) wavefronts per
+        // workgroup (s.waves); the row and wavefront options of the other
+        // forms do not apply
+        const bool mixed = precision == GBD_MIXED;
+        const int wy = mixed ? kSepWavesY : kSep64WavesY;
+        s.rows = mixed ? kSepTileY : kSepRows64;
+        s.waves = kSepWavesX * wy;
         s.nseg = (o && o->segments > 0) ? o->segments : 0;
         if (s.nseg <= 0) {
-            // one round of two 4-wavefront workgroups per CU (the register
+            // one round of workgroups, 8 wavefronts per CU (the register
             // budget allows two wavefronts per SIMD; a partial second round
-            // leaves CUs idle: on 512^2 pixels 24 segments ran 1.21 ms, 32
-            // 0.93 ms, 40 1.11 ms, 48 0.95 ms)
+            // leaves CUs idle: on 512^2 pixels with the four-product form's
+            // 4 x 2 wavefronts of 64 x 64, 16 segments ran 1.78 ms, 32 0.91
+            // ms, 48 1.22 ms, 64 0.93 ms)
             const int64_t tiles = std::max<int64_t>(
-                1, (int64_t)((pl.nx + kSepTile * kSepWavesX - 1) / (kSepTile * kSepWavesX)) *
-                       ((pl.ny + s.rows * kSepWavesY - 1) / (s.rows * kSepWavesY)));
-            int64_t seg = ((int64_t)ctx->cus * 2 + tiles - 1) / tiles;
+                1, (int64_t)((pl.nx + kSepTileX * kSepWavesX - 1) / (kSepTileX * kSepWavesX)) *
+                       ((pl.ny + s.rows * wy - 1) / (s.rows * wy)));
+            const int64_t per_cu = 8 / s.waves;
+            int64_t seg = ((int64_t)ctx->cus * per_cu + tiles - 1) / tiles;
             seg = std::min<int64_t>(seg, std::max<int64_t>(1, n / 256));
             s.nseg = (int)std::max<int64_t>(1, std::min<int64_t>(seg, 1024));
         }
@@ -308,8 +313,9 @@ EvalGeom make_geom(const PlaneGeom &pl, int64_t n, const Shape &s) {
     g.a0 = -0.5 * (pl.nx - 1) * pl.dx;
     g.b0 = -0.5 * (pl.ny - 1) * pl.dy;
     if (s.form == 3) {
-        g.tiles_x = (pl.nx + kSepTile * kSepWavesX - 1) / (kSepTile * kSepWavesX);
-        g.tiles_y = (pl.ny + s.rows * kSepWavesY - 1) / (s.rows * kSepWavesY);
+        const int wy = s.waves / kSepWavesX;  // 2 x 4 (mixed) or 2 x 2 (FP64) wavefronts
+        g.tiles_x = (pl.nx + kSepTileX * kSepWavesX - 1) / (kSepTileX * kSepWavesX);
+        g.tiles_y = (pl.ny + s.rows * wy - 1) / (s.rows * wy);
     } else {
         g.tiles_x = (pl.nx + 63) / 64;
         g.tiles_y = (pl.ny + s.waves * s.rows - 1) / (s.waves * s.rows);
@@ -441,10 +447,15 @@ int plan_eval_impl(gbd_ctx_s *ctx, gbd_plan_s *plan, int precision, void *out, i
             HIP_TRY(launch_eval_sep(gl, plan->r32, static_cast<const RecHG32 *>(hrec),
                                     static_cast<float2 *>(plan->scratch), static_cast<float2 *>(out), ctx->stream),
                     "eval kernel launch");
-        else
+        else {
+            if (s.form == 2)
+                HIP_TRY(launch_sigma(gl, plan->r64, precision == GBD_FP64 ? plan->q64 : nullptr,
+                                     precision == GBD_FP64 ? nullptr : plan->r32, ctx->stream),
+                        "sigma table kernel launch");
             HIP_TRY(launch_eval(precision, s.rows, s.waves, s.form, gl, rec, hrec, plan->q64, plan->scratch, out,
                                 ctx->stream),
                     "eval kernel launch");
+        }
     }
     if (nseg_cut > 0) {
         const void *rec = precision == GBD_FP64 ? (const void *)(plan->r64 + n_main) : (const void *)(plan->r32 + n_main);
@@ -1160,8 +1171,8 @@ int gbd_eval_batch(gbd_ctx_t ctx, int32_t n_inst, const gbd_beamlets_t *bs, cons
         e.nx = g.nx;
         e.ny = g.ny;
         if (form == 3) {  // separable form: 128 x 128 pixel tiles
-            e.tiles_x = (g.nx + kSepTile * kSepWavesX - 1) / (kSepTile * kSepWavesX);
-            e.tiles_y = (g.ny + kSepTile * kSepWavesY - 1) / (kSepTile * kSepWavesY);
+            e.tiles_x = (g.nx + kSepTileX * kSepWavesX - 1) / (kSepTileX * kSepWavesX);
+            e.tiles_y = (g.ny + kSepTileY * kSepWavesY - 1) / (kSepTileY * kSepWavesY);
         } else {
             e.tiles_x = (g.nx + 63) / 64;
             e.tiles_y = (g.ny + waves * rows - 1) / (waves * rows);

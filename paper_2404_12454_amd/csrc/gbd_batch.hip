@@ -176,10 +176,10 @@ __global__ void __launch_bounds__(64 * WAVES) batch_eval_kernel(BatchArgs A) {
 // segment (so a field equals gbd_eval's with variant 4 and one segment bit
 // for bit), then the same epilogue from the MFMA accumulators (lane l holds
 // rows 4 (l / 16) + e, column l % 16 of each 16 x 16 block).
-template <int WX, int WY>
-__global__ void __launch_bounds__(64 * WX * WY) batch_sep_kernel(BatchArgs A) {
-    constexpr int NB = sep::kSepBlocks, WAVES = WX * WY, NQ = 2 + 2 * kMaxZones;
-    __shared__ sep::SepLds<NB> L;
+__global__ void __launch_bounds__(64 * sep::k3WX * sep::k3WY) batch_sep_kernel(BatchArgs A) {
+    constexpr int WX = sep::k3WX, WY = sep::k3WY, BX = sep::k3BX, BY = sep::k3BY;
+    constexpr int WAVES = WX * WY, NQ = 2 + 2 * kMaxZones;
+    __shared__ sep::Sep3Lds<sep::k3Quads> L;
     __shared__ int s_item;
     __shared__ double red[WAVES][NQ];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -195,16 +195,17 @@ __global__ void __launch_bounds__(64 * WX * WY) batch_sep_kernel(BatchArgs A) {
         const int i = A.items[2 * item], t = A.items[2 * item + 1];
         const BatchEval I = A.inst[i];
         const int ty = t / I.tiles_x, tx = t - ty * I.tiles_x;
-        const int x0 = (tx * WX + wx) * 16 * NB, y0 = (ty * WY + wy) * 16 * NB;
-        sep::f4 accR[NB][NB], accI[NB][NB];
+        const int x0 = (tx * WX + wx) * 16 * BX, y0 = (ty * WY + wy) * 16 * BY;
+        sep::f4 accR[BY][BX], accI[BY][BX];
         if (I.n > 0) {
             const sep::SepGeom sg{I.nx, I.ny, I.a0, I.b0, I.dx, I.dy};
-            sep::sep_accumulate<WX, WY, false>(sg, A.rec + I.rec_off, nullptr, 0, I.n, tx, ty, L, accR, accI);
+            sep::sep_accumulate_3m<sep::k3Quads, false>(sg, A.rec + I.rec_off, nullptr, 0, I.n, tx, ty, L, accR,
+                                                        accI);
         } else {
 #pragma unroll
-            for (int p = 0; p < NB; p++)
+            for (int p = 0; p < BY; p++)
 #pragma unroll
-                for (int q = 0; q < NB; q++) accR[p][q] = accI[p][q] = sep::f4{0.0f, 0.0f, 0.0f, 0.0f};
+                for (int q = 0; q < BX; q++) accR[p][q] = accI[p][q] = sep::f4{0.0f, 0.0f, 0.0f, 0.0f};
         }
         double qm[NQ];
 #pragma unroll
@@ -213,9 +214,9 @@ __global__ void __launch_bounds__(64 * WX * WY) batch_sep_kernel(BatchArgs A) {
         const double n0 = e0.x * e0.x + e0.y * e0.y;
         const double inv0 = n0 > 0.0 ? 1.0 / n0 : 0.0;  // an empty instance compares a zero field
 #pragma unroll
-        for (int p = 0; p < NB; p++)
+        for (int p = 0; p < BY; p++)
 #pragma unroll
-            for (int q = 0; q < NB; q++) {
+            for (int q = 0; q < BX; q++) {
                 const int ix = x0 + 16 * q + li;
 #pragma unroll
                 for (int e = 0; e < 4; e++) {
@@ -330,13 +331,13 @@ hipError_t launch_batch_e0(const BatchEval *inst, int32_t n_inst, const Rec32 *r
 hipError_t launch_batch_eval(int rows, int waves, int form, int cus, const BatchArgs &a, hipStream_t s) {
     if (form == 3) {
         int per_cu = 0;
-        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &per_cu, batch_sep_kernel<kSepWavesX, kSepWavesY>, 64 * kSepWavesX * kSepWavesY, 0);
+        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_sep_kernel,
+                                                                    64 * kSepWavesX * kSepWavesY, 0);
         if (e != hipSuccess) return e;
         if (per_cu < 1) per_cu = 1;
         const int grid = (int)min((int64_t)a.n_items, (int64_t)cus * per_cu);
         if (grid <= 0) return hipSuccess;
-        batch_sep_kernel<kSepWavesX, kSepWavesY><<<grid, 64 * kSepWavesX * kSepWavesY, 0, s>>>(a);
+        batch_sep_kernel<<<grid, 64 * kSepWavesX * kSepWavesY, 0, s>>>(a);
         return hipGetLastError();
     }
 #define GBD_CASE(R, W)                                                                         \

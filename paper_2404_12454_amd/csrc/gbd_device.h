@@ -59,8 +59,9 @@ __device__ inline double il2_dev() { return 1.4426950408889634074; }  // 1 / ln 
 // quadratic coefficients are p5 (turns / m^2) and l5 (ln amplitude / m^2), on
 // rows dy apart: the phase k^2 p5 dy^2 is reduced mod 1 before the
 // trigonometry (k^2 integer), the exponent capped so a refused steep grid
-// still gives finite values.  The setup rounds it to the FP32 table; the FP64
-// rotor form's table is computed from the FP64 records at evaluation.
+// still gives finite values.  Rounded, it is the mixed rotor form's FP32
+// table; both tables are computed from the FP64 records when a rotor form
+// runs (the batched setup fills the FP32 one itself).
 __device__ inline double2 rotor_sigma(double p5, double l5, double dy, int k) {
     const double t2 = p5 * dy * dy;
     const double u2 = l5 * il2_dev() * dy * dy;
@@ -83,7 +84,7 @@ __device__ inline double2 rotor_sigma(double p5, double l5, double dy, int k) {
 // direct form of their own kernel).
 __device__ inline uint32_t setup_one(const BeamletsDev &b, const PlaneGeom &pl, double gturns, int64_t j,
                                      Rec64 *r64, Rec32 *r32, RecHG64 *h64 = nullptr, RecHG32 *h32 = nullptr,
-                                     RecCut64 *c64 = nullptr, RecCut32 *c32 = nullptr) {
+                                     RecCut64 *c64 = nullptr, RecCut32 *c32 = nullptr, bool sigma32 = true) {
     const double *M = b.abcd + (b.n_abcd == 1 ? 0 : 16 * j);
     double A[2][2], B[2][2], C[2][2], D[2][2];
 #pragma unroll
@@ -362,12 +363,15 @@ __device__ inline uint32_t setup_one(const BeamletsDev &b, const PlaneGeom &pl, 
         const float dyf = (float)pl.dy;
         o32.u2 = o32.m[5] * (dyf * dyf);
         o32.s2 = exp2f(fminf(2.0f * o32.u2, 1.0f));
-        // rotor form: sigma^(k^2), rounded from FP64
+        // rotor form: sigma^(k^2), rounded from FP64 (else left to
+        // sigma32_kernel, run only before a rotor-form evaluation)
+        if (sigma32) {
 #pragma unroll
-        for (int k = 1; k <= kRotorRows; k++) {
-            const double2 sq = rotor_sigma(p[5], l[5], pl.dy, k);
-            o32.sq[k - 1][0] = (float)sq.x;
-            o32.sq[k - 1][1] = (float)sq.y;
+            for (int k = 1; k <= kRotorRows; k++) {
+                const double2 sq = rotor_sigma(p[5], l[5], pl.dy, k);
+                o32.sq[k - 1][0] = (float)sq.x;
+                o32.sq[k - 1][1] = (float)sq.y;
+            }
         }
     }
     if (flag & FLAG_ERRORS) {

@@ -271,6 +271,12 @@ hipError_t launch_setup(const BeamletsDev &b, const PlaneGeom &pl, double global
                         Rec32 *r32, RecHG64 *h64, RecHG32 *h32, RecCut64 *c64, RecCut32 *c32,
                         uint32_t *status, hipStream_t s);
 
+// The rotor forms' sigma^(k^2) tables (k = 1..16) of the g.n beamlets, from
+// their FP64 records on rows g.dy apart: into q64 (FP64 rotor form) or the
+// Rec32 records r32 (mixed rotor forms), exactly one of the two non-null.
+// launch_setup leaves them unset; run before a rotor-form evaluation.
+hipError_t launch_sigma(const EvalGeom &g, const Rec64 *r64, RecSq64 *q64, Rec32 *r32, hipStream_t s);
+
 // Truncated beamlets (direct form with the complex error function): the n
 // beamlets of g (records rec / cut, both starting at the first truncated
 // beamlet) summed per segment into partial segments seg_base + s; precision
@@ -284,8 +290,7 @@ hipError_t launch_eval_cut(int precision, const EvalGeom &g, const void *rec, co
 // factored as anchor x rho^k x sigma^(k^2), no per-pixel transcendental.
 // hg: RecHG64 / RecHG32 records of higher-order beamlets (direct and FP64
 // forms only), or null.  precision 0 with form 2: the FP64 rotor form, q64
-// room for its sigma^(k^2) tables (one per beamlet, filled from the records
-// before the evaluation).
+// its sigma^(k^2) tables; form 2 reads the tables launch_sigma fills.
 hipError_t launch_eval(int precision, int rows, int waves, int form, const EvalGeom &g, const void *rec,
                        const void *hg, const RecSq64 *q64, void *partial, void *out, hipStream_t s);
 
@@ -297,13 +302,19 @@ hipError_t launch_reduce(int precision, const EvalGeom &g, int32_t nseg2, const 
                          hipStream_t s);
 inline size_t reduce_wide_offset(int32_t nseg2, int64_t M) { return ((size_t)nseg2 * (size_t)M * 8 + 15) & ~(size_t)15; }
 
-// Separable (matrix) form on FP32 MFMA: workgroups of kSepWavesX x kSepWavesY
-// wavefronts, each wavefront a 64 x 64 pixel tile; partials as float4 (re, im, 0, 0).
-constexpr int kSepWavesX = 2, kSepWavesY = 2;
-constexpr int kSepTile = 64;
+// Separable (matrix) form on FP32 MFMA (single evaluations and the batched
+// sweep): wavefront tiles of kSepTileX x kSepTileY pixels, kSepWavesX x
+// kSepWavesY wavefronts per workgroup (128 x 128 pixels, one workgroup per
+// CU at the register and LDS budget).
+constexpr int kSepWavesX = 2, kSepWavesY = 4;
+constexpr int kSepTileX = 64, kSepTileY = 32;
 // The FP64 separable form on FP64 MFMA: wavefront tiles of 64 x 32 pixels
-// (kSepRows64 rows), 2 x 2 wavefronts per workgroup; double2 partials.
+// (kSepRows64 rows), kSep64WavesX x kSep64WavesY wavefronts per workgroup;
+// double2 partials.
 constexpr int kSepRows64 = 32;
+constexpr int kSep64WavesX = 2, kSep64WavesY = 2;
+static_assert(kSep64WavesX == kSepWavesX && kSepRows64 == kSepTileY,
+              "separable tiles: the host derives the y count of wavefronts from the workgroup size");
 hipError_t launch_eval_sep64(const EvalGeom &g, const Rec64 *rec, double2 *partial, double2 *out, hipStream_t s);
 
 // hg: higher-order factors without cross terms (k1 = k0 = 0, G diagonal), or null.

@@ -27,27 +27,27 @@ __global__ void __launch_bounds__(256) setup_kernel(BeamletsDev b, PlaneGeom pl,
                                                     uint32_t *__restrict__ status) {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= b.n) return;
-    const uint32_t flag = setup_one(b, pl, gturns, j, r64, r32, h64, h32, c64, c32);
+    const uint32_t flag = setup_one(b, pl, gturns, j, r64, r32, h64, h32, c64, c32, false);
     if (flag) atomicOr(status, flag);
 }
 
-// The FP64 rotor form's sigma^(k^2) tables, k = 1..16, from the FP64 records
-// on rows dy apart.  Thread t of a block computes entry t % 16 of beamlet
-// 16 (block) + t / 16, so the 256-byte records are written contiguously.
-__global__ void __launch_bounds__(256) sigma64_kernel(int64_t n, double dy, const Rec64 *__restrict__ rec,
-                                                      RecSq64 *__restrict__ q64) {
+// The rotor forms' sigma^(k^2) tables, k = 1..16, from the FP64 records on
+// rows dy apart: FP64 (q64) or rounded into the Rec32 records (r32).  Thread
+// t of a block computes entry t % 16 of beamlet 16 (block) + t / 16, so each
+// beamlet's table is written contiguously.
+__global__ void __launch_bounds__(256) sigma_kernel(int64_t n, double dy, const Rec64 *__restrict__ rec,
+                                                    RecSq64 *__restrict__ q64, Rec32 *__restrict__ r32) {
     const int64_t j = (int64_t)blockIdx.x * 16 + (threadIdx.x >> 4);
     const int k = (threadIdx.x & 15) + 1;
     if (j >= n) return;
     const double2 v = rotor_sigma(rec[j].p[5], rec[j].l[5], dy, k);
-    q64[j].sq[k - 1][0] = v.x;
-    q64[j].sq[k - 1][1] = v.y;
-}
-
-hipError_t launch_sigma64(const EvalGeom &g, const Rec64 *rec, RecSq64 *q64, hipStream_t s) {
-    if (g.n == 0) return hipSuccess;
-    sigma64_kernel<<<(unsigned)((g.n + 15) / 16), 256, 0, s>>>(g.n, g.dy, rec, q64);
-    return hipGetLastError();
+    if (q64) {
+        q64[j].sq[k - 1][0] = v.x;
+        q64[j].sq[k - 1][1] = v.y;
+    } else {
+        r32[j].sq[k - 1][0] = (float)v.x;
+        r32[j].sq[k - 1][1] = (float)v.y;
+    }
 }
 
 // Mixed form.  Each lane owns ROWS pixels of one detector column; a
@@ -347,8 +347,6 @@ hipError_t launch_eval_t(int precision, int form, const EvalGeom &g, const void 
     const int grid = (g.work + 7) / 8 * 8;
     if (precision == 0 && form == 2 && !hg) {
         if (!q64) return hipErrorInvalidValue;
-        const hipError_t e = launch_sigma64(g, static_cast<const Rec64 *>(rec), const_cast<RecSq64 *>(q64), s);
-        if (e != hipSuccess) return e;
         eval_fp64_rotor_kernel<ROWS, WAVES><<<grid, 64 * WAVES, 0, s>>>(
             g, static_cast<const Rec64 *>(rec), q64, static_cast<double2 *>(partial), static_cast<double2 *>(out));
         return hipGetLastError();
@@ -394,6 +392,13 @@ hipError_t launch_eval_t(int precision, int form, const EvalGeom &g, const void 
 
 }  // namespace
 
+hipError_t launch_sigma(const EvalGeom &g, const Rec64 *r64, RecSq64 *q64, Rec32 *r32, hipStream_t s) {
+    if (g.n == 0) return hipSuccess;
+    if ((q64 == nullptr) == (r32 == nullptr)) return hipErrorInvalidValue;
+    sigma_kernel<<<(unsigned)((g.n + 15) / 16), 256, 0, s>>>(g.n, g.dy, r64, q64, r32);
+    return hipGetLastError();
+}
+
 hipError_t launch_setup(const BeamletsDev &b, const PlaneGeom &pl, double global_turns, Rec64 *r64, Rec32 *r32,
                         RecHG64 *h64, RecHG32 *h32, RecCut64 *c64, RecCut32 *c32, uint32_t *status, hipStream_t s) {
     if (b.n == 0) return hipSuccess;
@@ -420,8 +425,6 @@ hipError_t launch_eval(int precision, int rows, int waves, int form, const EvalG
         const int grid = (g.work + 7) / 8 * 8;
         double2 *pt = static_cast<double2 *>(partial), *o = static_cast<double2 *>(out);
         const Rec64 *r = static_cast<const Rec64 *>(rec);
-        const hipError_t e = launch_sigma64(g, r, const_cast<RecSq64 *>(q64), s);
-        if (e != hipSuccess) return e;
         if (rows == 16 && waves == 1) eval_fp64_rotor_kernel<16, 1><<<grid, 64, 0, s>>>(g, r, q64, pt, o);
         else if (rows == 16 && waves == 2) eval_fp64_rotor_kernel<16, 2><<<grid, 128, 0, s>>>(g, r, q64, pt, o);
         else if (rows == 16 && waves == 4) eval_fp64_rotor_kernel<16, 4><<<grid, 256, 0, s>>>(g, r, q64, pt, o);

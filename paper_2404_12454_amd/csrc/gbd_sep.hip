@@ -14,17 +14,18 @@
 // FP32 log2-amplitude from the pixel's own offset, hardware sin/cos/exp2), so
 // every beamlet-pixel term is the same product as in the other forms.
 //
-// Tiling: a wavefront owns a 64 x 64 pixel tile as 4 x 4 blocks of 16 x 16
-// and walks its segment of beamlets four at a time (the MFMA's K = 4): lane l
-// feeds the MFMA U and V of beamlet j0 + l / 16 at the coordinates l % 16 + 16 b
-// of its 4 + 4 blocks, 64 MFMAs per step (16 blocks x {Re, Im} x 2 real
-// products).  Four wavefronts (2 x 2 tiles) share the factors through LDS, so
-// each lane forms 4 phasors per step instead of 8: on gfx950 VALU and MFMA
-// issue from one SIMD do not overlap, so every VALU instruction per MFMA is
-// time lost from the matrix pipe.  The record fields of a step are loaded
-// two steps ahead (the loop is unrolled by two).  Accumulators stay in FP32
-// over the segment; segments are summed in FP64 by the reduction.  The host
-// sizes segments so that every one is non-empty (jb < je <= N).
+// Tiling (the core in gbd_sep_core.h): a wavefront owns a 64 x 32 pixel
+// tile as 4 x 2 blocks of 16 x 16 and walks its segment of beamlets four at a
+// time (the MFMA's K = 4): lane l feeds the MFMA U and V of beamlet j0 + l / 16
+// at the coordinates l % 16 + 16 b of its blocks.  The complex product takes
+// three real MFMA products (Gauss's form), 24 MFMAs per quad of beamlets.
+// Eight wavefronts (2 x 4 tiles, 128 x 128 pixels) share the factors through
+// LDS, so each lane forms 2 phasors per quad instead of 6: on gfx950 VALU and
+// MFMA issue from one SIMD do not overlap, so every VALU instruction per
+// MFMA is time lost from the matrix pipe.  Four quads pass between barriers,
+// and the record fields are loaded two quads ahead.  Accumulators stay in
+// FP32 over the segment; segments are summed in FP64 by the reduction.  The
+// host sizes segments so that every one is non-empty (jb < je <= N).
 //
 // Higher-order (elegant Hermite-Gaussian) beamlets without cross terms keep
 // the factorisation: their Hermite-Gaussian factor is a product of one
@@ -37,13 +38,12 @@ namespace {
 
 using namespace sep;
 
-template <int WX, int WY, bool HG>
-__global__ void __launch_bounds__(64 * WX * WY) eval_sep_kernel(EvalGeom g, const Rec32 *__restrict__ rec,
-                                                                 const RecHG32 *__restrict__ hg,
-                                                                 float2 *__restrict__ partial,
-                                                                 float2 *__restrict__ out) {
-    constexpr int NB = kSepBlocks;
-    __shared__ SepLds<NB> L;
+template <bool HG>
+__global__ void __launch_bounds__(64 * k3WX * k3WY) eval_sep_kernel(EvalGeom g, const Rec32 *__restrict__ rec,
+                                                                     const RecHG32 *__restrict__ hg,
+                                                                     float2 *__restrict__ partial,
+                                                                     float2 *__restrict__ out) {
+    __shared__ Sep3Lds<k3Quads> L;
     const int w = work_item(blockIdx.x, gridDim.x);
     if (w >= g.work) return;
     const int tiles = g.tiles_x * g.tiles_y;
@@ -51,21 +51,21 @@ __global__ void __launch_bounds__(64 * WX * WY) eval_sep_kernel(EvalGeom g, cons
     const int t = w - seg * tiles;
     const int ty = t / g.tiles_x, tx = t - ty * g.tiles_x;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int wx = wv % WX, wy = wv / WX;
-    const int x0 = (tx * WX + wx) * 16 * NB, y0 = (ty * WY + wy) * 16 * NB;
+    const int wx = wv % k3WX, wy = wv / k3WX;
+    const int x0 = (tx * k3WX + wx) * 16 * k3BX, y0 = (ty * k3WY + wy) * 16 * k3BY;
     const int li = lane & 15, lk = lane >> 4;
     const SepGeom sg{g.nx, g.ny, g.a0, g.b0, g.dx, g.dy};
     const int64_t jb = (int64_t)seg * g.seg_len;
     const int64_t je = min(g.n, jb + g.seg_len);
-    f4 accR[NB][NB], accI[NB][NB];
-    sep_accumulate<WX, WY, HG>(sg, rec, hg, jb, je, tx, ty, L, accR, accI);
+    f4 accR[k3BY][k3BX], accI[k3BY][k3BX];
+    sep_accumulate_3m<k3Quads, HG>(sg, rec, hg, jb, je, tx, ty, L, accR, accI);
 
     // D[row][col] of a 16 x 16 block: lane l holds rows 4 (l / 16) + e, column l % 16
     const int64_t M = (int64_t)g.nx * g.ny;
 #pragma unroll
-    for (int p = 0; p < NB; p++)
+    for (int p = 0; p < k3BY; p++)
 #pragma unroll
-        for (int q = 0; q < NB; q++) {
+        for (int q = 0; q < k3BX; q++) {
             const int ix = x0 + 16 * q + li;
             if (ix >= g.nx) continue;
 #pragma unroll
@@ -86,13 +86,13 @@ __global__ void __launch_bounds__(64 * WX * WY) eval_sep_kernel(EvalGeom g, cons
 
 hipError_t launch_eval_sep(const EvalGeom &g, const Rec32 *rec, const RecHG32 *hg, float2 *partial, float2 *out,
                            hipStream_t s) {
+    static_assert(k3WX == kSepWavesX && k3WY == kSepWavesY && 16 * k3BX == kSepTileX && 16 * k3BY == kSepTileY,
+                  "separable form: host and kernel tiles");
     const int grid = (g.work + 7) / 8 * 8;
     if (hg)
-        eval_sep_kernel<kSepWavesX, kSepWavesY, true>
-            <<<grid, 64 * kSepWavesX * kSepWavesY, 0, s>>>(g, rec, hg, partial, out);
+        eval_sep_kernel<true><<<grid, 64 * k3WX * k3WY, 0, s>>>(g, rec, hg, partial, out);
     else
-        eval_sep_kernel<kSepWavesX, kSepWavesY, false>
-            <<<grid, 64 * kSepWavesX * kSepWavesY, 0, s>>>(g, rec, nullptr, partial, out);
+        eval_sep_kernel<false><<<grid, 64 * k3WX * k3WY, 0, s>>>(g, rec, nullptr, partial, out);
     return hipGetLastError();
 }
 

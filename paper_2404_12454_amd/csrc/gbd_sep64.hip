@@ -179,7 +179,8 @@ __global__ void __launch_bounds__(64 * WX * WY) eval_sep64_kernel(EvalGeom g, co
 
 hipError_t launch_eval_sep64(const EvalGeom &g, const Rec64 *rec, double2 *partial, double2 *out, hipStream_t s) {
     const int grid = (g.work + 7) / 8 * 8;
-    eval_sep64_kernel<kSepWavesX, kSepWavesY><<<grid, 64 * kSepWavesX * kSepWavesY, 0, s>>>(g, rec, partial, out);
+    eval_sep64_kernel<kSep64WavesX, kSep64WavesY><<<grid, 64 * kSep64WavesX * kSep64WavesY, 0, s>>>(g, rec, partial,
+                                                                                                 out);
     return hipGetLastError();
 }
 

@@ -1,6 +1,6 @@
 // Core of the separable (matrix) form, shared by the single-instance kernel
-// and the batched sweep: the MFMA accumulation of one 2 x 2-wavefront pixel
-// tile over a range of beamlets (see gbd_sep.hip for the method).
+// and the batched sweep: the MFMA accumulation of one workgroup's 128 x 128
+// pixel tile over a range of beamlets (see gbd_sep.hip for the method).
 #pragma once
 
 #include "gbd_device.h"
@@ -11,8 +11,6 @@ namespace sep {
 using namespace dev;
 
 typedef float f4 __attribute__((ext_vector_type(4)));
-
-constexpr int kSepBlocks = 4;  // 16-pixel blocks per wavefront along each axis
 
 // One factor: 2^(L) e^(2 pi i T), T = c0 + d (c1 + c2 d) in FP64 (turns),
 // L = l0 + df (l1 + l2 df) in FP32 from the pixel's own offset.
@@ -93,122 +91,118 @@ struct SepGeom {
     double a0, b0, dx, dy;
 };
 
-// LDS factor buffers of one workgroup: [buffer][range][block][lane].
-template <int NB>
-struct SepLds {
-    float2 lu[2][2][NB][64], lv[2][2][NB][64];
+// The accumulation in three real products (Gauss's form of the complex
+// product).  With U = ur + i ui and V = vr + i vi, the real products
+// P1 = vr ur, P2 = vi ui and P3 = (vr + vi)(ur + ui) give Re(V U) = P1 - P2
+// and Im(V U) = P3 - P1 - P2: three MFMA products per block and step instead
+// of four, the factor sums formed once by the wavefront that publishes the
+// factor.  The three sums take 12 accumulator VGPRs per 16 x 16 block, so a
+// wavefront owns 64 x 32 pixels (4 x 2 blocks) and a workgroup 2 x 4
+// wavefronts (128 x 128 pixels); U over x range wx is needed by the 4
+// wavefronts (wx, *), V over y range wy by the 2 wavefronts (*, wy), so each
+// lane forms one U and one V factor per quad of beamlets.
+constexpr int k3WX = 2, k3WY = 4;  // wavefronts per workgroup along x and y
+constexpr int k3BX = 4, k3BY = 2;  // 16-pixel blocks per wavefront along x and y
+constexpr int k3Quads = 4;         // quads of beamlets per pass between barriers
+
+template <int Q>
+struct Sep3Lds {
+    // [buffer][quad][range][block][lane]: (re, im, re + im, 0)
+    float4 lu[2][Q][k3WX][k3BX][64], lv[2][Q][k3WY][k3BY][64];
 };
 
-// Accumulates beamlets [jb, je) (je > jb) of rec (and hg) into accR / accI
-// for the wavefront's 64 x 64 pixels of workgroup tile (tx, ty).  All
-// threads of the workgroup call it together; it leaves the LDS buffers free
-// (its last step ends with a barrier).
-template <int WX, int WY, bool HG>
-__device__ inline void sep_accumulate(const SepGeom &g, const Rec32 *__restrict__ rec,
-                                      const RecHG32 *__restrict__ hg, int64_t jb, int64_t je, int tx, int ty,
-                                      SepLds<kSepBlocks> &L, f4 (&accR)[kSepBlocks][kSepBlocks],
-                                      f4 (&accI)[kSepBlocks][kSepBlocks]) {
-    constexpr int NB = kSepBlocks;
+// Accumulates beamlets [jb, je) (je > jb) into accR / accI (rows y, columns
+// x) for the wavefront's 64 x 32 pixels of workgroup tile (tx, ty); all
+// threads of the workgroup call it together; it leaves the LDS buffers free.
+// Each pass between barriers takes Q quads of beamlets (Q MFMA K-steps of
+// 4), so the barrier and the LDS round trip are paid once per 24 Q MFMAs;
+// while a quad's products run, the lane forms its factors of the same quad
+// of the next pass, whose record fields were loaded two quads earlier.  A
+// quad past je publishes zero U factors and adds nothing.
+template <int Q, bool HG>
+__device__ inline void sep_accumulate_3m(const SepGeom &g, const Rec32 *__restrict__ rec,
+                                         const RecHG32 *__restrict__ hg, int64_t jb, int64_t je, int tx, int ty,
+                                         Sep3Lds<Q> &L, f4 (&accR)[k3BY][k3BX], f4 (&accI)[k3BY][k3BX]) {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int wx = wv % WX, wy = wv / WX;
-    const int x0 = (tx * WX + wx) * 16 * NB, y0 = (ty * WY + wy) * 16 * NB;
+    const int wx = wv % k3WX, wy = wv / k3WX;
+    const int x0 = (tx * k3WX + wx) * 16 * k3BX, y0 = (ty * k3WY + wy) * 16 * k3BY;
     const int li = lane & 15, lk = lane >> 4;
     auto &lu = L.lu;
     auto &lv = L.lv;
 
-    // Factor sharing: U over this workgroup's x range wx is needed by the two
-    // wavefronts (wx, 0), (wx, 1), V over y range wy by (0, wy), (1, wy).
-    // Wavefront (wx, wy) forms U blocks 2 wy, 2 wy + 1 of range wx and V blocks
-    // 2 wx, 2 wx + 1 of range wy and publishes them in LDS (double-buffered,
-    // one barrier per step); each lane's value sits where the same lane of the
-    // partner wavefront reads it (same beamlet and in-block position).
-    static_assert(WX == 2 && WY == 2, "factor sharing assumes 2 x 2 wavefronts");
-    double ax[2], by[2];
-    float axf[2], byf[2], mx[2], my[2];
-#pragma unroll
-    for (int h = 0; h < 2; h++) {
-        const int ix = x0 + 16 * (2 * wy + h) + li, iy = y0 + 16 * (2 * wx + h) + li;
-        mx[h] = ix < g.nx ? 0.0f : -INFINITY;
-        my[h] = iy < g.ny ? 0.0f : -INFINITY;
-        ax[h] = g.a0 + ix * g.dx;
-        by[h] = g.b0 + iy * g.dy;
-        axf[h] = (float)ax[h];
-        byf[h] = (float)by[h];
-    }
-    auto publish = [&](const Fields &f, int buf) {
-#pragma unroll
-        for (int h = 0; h < 2; h++) {
-            float ur, ui, vr, vi;
-            const float dxf = axf[h] - f.arf, dyf = byf[h] - f.brf;
-            factor(ax[h] - f.arho, dxf, f.p0, f.p1, f.p3, f.m0 + (f.mbias + mx[h]), f.m1, f.m3, ur, ui);
-            factor(by[h] - f.brho, dyf, 0.0, f.p2, f.p5, my[h], f.m2, f.m5, vr, vi);
-            if constexpr (HG) {
-                hg_axis(dxf, f.gxr, f.gxi, f.cx0r, f.cx0i, f.cx1, f.cx2, ur, ui);
-                hg_axis(dyf, f.gyr, f.gyi, f.cy0r, f.cy0i, f.cy1, f.cy2, vr, vi);
-            }
-            lu[buf][wx][2 * wy + h][lane] = make_float2(ur, ui);
-            lv[buf][wy][2 * wx + h][lane] = make_float2(vr, vi);
+    // this wavefront forms U block wy of x range wx and V block wx of y range wy
+    const int ix = x0 + 16 * wy + li, iy = y0 + 16 * wx + li;
+    const float mx = ix < g.nx ? 0.0f : -INFINITY, my = iy < g.ny ? 0.0f : -INFINITY;
+    const double ax = g.a0 + ix * g.dx, by = g.b0 + iy * g.dy;
+    const float axf = (float)ax, byf = (float)by;
+    auto publish = [&](const Fields &f, int buf, int qd) {
+        float ur, ui, vr, vi;
+        const float dxf = axf - f.arf, dyf = byf - f.brf;
+        factor(ax - f.arho, dxf, f.p0, f.p1, f.p3, f.m0 + (f.mbias + mx), f.m1, f.m3, ur, ui);
+        factor(by - f.brho, dyf, 0.0, f.p2, f.p5, my, f.m2, f.m5, vr, vi);
+        if constexpr (HG) {
+            hg_axis(dxf, f.gxr, f.gxi, f.cx0r, f.cx0i, f.cx1, f.cx2, ur, ui);
+            hg_axis(dyf, f.gyr, f.gyi, f.cy0r, f.cy0i, f.cy1, f.cy2, vr, vi);
         }
+        lu[buf][qd][wx][wy][lane] = make_float4(ur, ui, ur + ui, 0.0f);
+        lv[buf][qd][wy][wx][lane] = make_float4(vr, vi, vr + vi, 0.0f);
     };
 
-    // accR/accI[p][q]: rows of the product are y (A operand = V), columns x (B = U)
+    f4 a1[k3BY][k3BX], a2[k3BY][k3BX], a3[k3BY][k3BX];
 #pragma unroll
-    for (int p = 0; p < NB; p++)
+    for (int p = 0; p < k3BY; p++)
 #pragma unroll
-        for (int q = 0; q < NB; q++) accR[p][q] = accI[p][q] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+        for (int q = 0; q < k3BX; q++) a1[p][q] = a2[p][q] = a3[p][q] = f4{0.0f, 0.0f, 0.0f, 0.0f};
 
-    // record fields of the steps two and three ahead live in fa / fb in turn
-    // (the loop is unrolled by two), so a load is consumed two steps after
-    // it is issued and no register copies tie the loads to the current step
-    publish(load_fields<HG>(rec, hg, jb + lk, jb, je), 0);
-    Fields fa = load_fields<HG>(rec, hg, jb + 4 + lk, jb, je);
-    Fields fb = load_fields<HG>(rec, hg, jb + 8 + lk, jb, je);
+    constexpr int P = 4 * Q;  // beamlets per pass
+#pragma unroll
+    for (int qd = 0; qd < Q; qd++) publish(load_fields<HG>(rec, hg, jb + 4 * qd + lk, jb, je), 0, qd);
+    // the next pass's first two quads (fn[qd % 2] holds its quad qd)
+    Fields fn[2] = {load_fields<HG>(rec, hg, jb + P + lk, jb, je), load_fields<HG>(rec, hg, jb + P + 4 + lk, jb, je)};
     __syncthreads();
     int buf = 0;
-    auto step = [&](int64_t j0, Fields &f) {
-        float ur[NB], ui[NB], vr[NB], vi[NB], vn[NB];
-        auto read_step = [&]() {
+    for (int64_t j0 = jb; j0 < je; j0 += P) {
+        const bool more = j0 + P < je;
 #pragma unroll
-            for (int b = 0; b < NB; b++) {
-                const float2 u = lu[buf][wx][b][lane], v = lv[buf][wy][b][lane];
+        for (int qd = 0; qd < Q; qd++) {
+            float ur[k3BX], ui[k3BX], us[k3BX], vr[k3BY], vi[k3BY], vs[k3BY];
+#pragma unroll
+            for (int b = 0; b < k3BX; b++) {
+                const float4 u = lu[buf][qd][wx][b][lane];
                 ur[b] = u.x;
                 ui[b] = u.y;
+                us[b] = u.z;
+            }
+#pragma unroll
+            for (int b = 0; b < k3BY; b++) {
+                const float4 v = lv[buf][qd][wy][b][lane];
                 vr[b] = v.x;
                 vi[b] = v.y;
-                vn[b] = -v.y;
+                vs[b] = v.z;
             }
-        };
-        // this step's factors (published before the last barrier) are read
-        // before the next step's factor arithmetic, so that the LDS latency
-        // passes under it; with the higher-order factors the registers this
-        // holds would halve the occupancy, so there they are read after it
-        if constexpr (!HG) read_step();
-        if (j0 + 4 < je) publish(f, buf ^ 1);
-        f = load_fields<HG>(rec, hg, j0 + 12 + lk, jb, je);
-        if constexpr (HG) read_step();
-        // Re += Vr Ur - Vi Ui ; Im += Vr Ui + Vi Ur
-#pragma unroll
-        for (int p = 0; p < NB; p++)
-#pragma unroll
-            for (int q = 0; q < NB; q++) {
-                accR[p][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(vr[p], ur[q], accR[p][q], 0, 0, 0);
-                accI[p][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(vr[p], ui[q], accI[p][q], 0, 0, 0);
+            if (more) {
+                publish(fn[qd % 2], buf ^ 1, qd);
+                fn[qd % 2] = load_fields<HG>(rec, hg, j0 + P + 4 * (qd + 2) + lk, jb, je);
             }
 #pragma unroll
-        for (int p = 0; p < NB; p++)
+            for (int p = 0; p < k3BY; p++)
 #pragma unroll
-            for (int q = 0; q < NB; q++) {
-                accR[p][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(vn[p], ui[q], accR[p][q], 0, 0, 0);
-                accI[p][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(vi[p], ur[q], accI[p][q], 0, 0, 0);
-            }
+                for (int q = 0; q < k3BX; q++) {
+                    a1[p][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(vr[p], ur[q], a1[p][q], 0, 0, 0);
+                    a2[p][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(vi[p], ui[q], a2[p][q], 0, 0, 0);
+                    a3[p][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(vs[p], us[q], a3[p][q], 0, 0, 0);
+                }
+        }
         __syncthreads();
         buf ^= 1;
-    };
-    for (int64_t j0 = jb; j0 < je; j0 += 8) {
-        step(j0, fa);
-        if (j0 + 4 < je) step(j0 + 4, fb);
     }
-
+#pragma unroll
+    for (int p = 0; p < k3BY; p++)
+#pragma unroll
+        for (int q = 0; q < k3BX; q++) {
+            accR[p][q] = a1[p][q] - a2[p][q];
+            accI[p][q] = a3[p][q] - a1[p][q] - a2[p][q];
+        }
 }
 
 }  // namespace sep
