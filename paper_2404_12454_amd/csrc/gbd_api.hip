@@ -238,9 +238,8 @@ Shape choose_shape(const gbd_ctx_s *ctx, int precision, int64_t n, const PlaneGe
     s.form = pick_form(precision, flags, o);
     if (s.form == 3) {
         // separable form: fixed 64 x 32 pixel tile per wavefront (s.rows is
-        // the tile height), 2 x 4 (mixed) or 2 x 2 (FP64) wavefronts per
-        // workgroup (s.waves); the row and wavefront options of the other
-        // forms do not apply
+        // the tile height), 2 x 4 wavefronts per workgroup (s.waves); the row
+        // and wavefront options of the other forms do not apply
         const bool mixed = precision == GBD_MIXED;
         const int wy = mixed ? kSepWavesY : kSep64WavesY;
         s.rows = mixed ? kSepTileY : kSepRows64;
@@ -249,9 +248,10 @@ Shape choose_shape(const gbd_ctx_s *ctx, int precision, int64_t n, const PlaneGe
         if (s.nseg <= 0) {
             // one round of workgroups, 8 wavefronts per CU (the register
             // budget allows two wavefronts per SIMD; a partial second round
-            // leaves CUs idle: on 512^2 pixels with the four-product form's
-            // 4 x 2 wavefronts of 64 x 64, 16 segments ran 1.78 ms, 32 0.91
-            // ms, 48 1.22 ms, 64 0.93 ms)
+            // leaves CUs idle: on 512^2 pixels, 16 tiles, 16 segments ran
+            // 0.78 ms, 32 0.79 ms; with the earlier four-product form's
+            // 256 x 128 workgroup tiles 16 segments ran 1.78 ms, 32 0.91 ms,
+            // 48 1.22 ms)
             const int64_t tiles = std::max<int64_t>(
                 1, (int64_t)((pl.nx + kSepTileX * kSepWavesX - 1) / (kSepTileX * kSepWavesX)) *
                        ((pl.ny + s.rows * wy - 1) / (s.rows * wy)));
@@ -313,7 +313,7 @@ EvalGeom make_geom(const PlaneGeom &pl, int64_t n, const Shape &s) {
     g.a0 = -0.5 * (pl.nx - 1) * pl.dx;
     g.b0 = -0.5 * (pl.ny - 1) * pl.dy;
     if (s.form == 3) {
-        const int wy = s.waves / kSepWavesX;  // 2 x 4 (mixed) or 2 x 2 (FP64) wavefronts
+        const int wy = s.waves / kSepWavesX;  // 2 x 4 wavefronts
         g.tiles_x = (pl.nx + kSepTileX * kSepWavesX - 1) / (kSepTileX * kSepWavesX);
         g.tiles_y = (pl.ny + s.rows * wy - 1) / (s.rows * wy);
     } else {

@@ -309,10 +309,10 @@ inline size_t reduce_wide_offset(int32_t nseg2, int64_t M) { return ((size_t)nse
 constexpr int kSepWavesX = 2, kSepWavesY = 4;
 constexpr int kSepTileX = 64, kSepTileY = 32;
 // The FP64 separable form on FP64 MFMA: wavefront tiles of 64 x 32 pixels
-// (kSepRows64 rows), kSep64WavesX x kSep64WavesY wavefronts per workgroup;
-// double2 partials.
+// (kSepRows64 rows), kSep64WavesX x kSep64WavesY wavefronts per workgroup
+// (128 x 128 pixels, one workgroup per CU); double2 partials.
 constexpr int kSepRows64 = 32;
-constexpr int kSep64WavesX = 2, kSep64WavesY = 2;
+constexpr int kSep64WavesX = 2, kSep64WavesY = 4;
 static_assert(kSep64WavesX == kSepWavesX && kSepRows64 == kSepTileY,
               "separable tiles: the host derives the y count of wavefronts from the workgroup size");
 hipError_t launch_eval_sep64(const EvalGeom &g, const Rec64 *rec, double2 *partial, double2 *out, hipStream_t s);

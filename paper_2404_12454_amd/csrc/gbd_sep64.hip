@@ -11,16 +11,19 @@
 //
 // Tiling: a 16 x 16 block of FP64 accumulators takes 8 VGPRs per lane and
 // part (Re, Im), so a wavefront owns 64 x 32 pixels (4 x 2 blocks, 128
-// accumulator VGPRs) and walks its segment four beamlets per step (the
-// MFMA's K = 4), 32 MFMAs per step.  Four wavefronts (2 x 2, a 128 x 64
-// pixel workgroup tile) share the factors through double-buffered LDS, one
-// barrier per step: a lane forms 2 U and 1 V factor per step instead of 6.
-// Operand layout as in the FP32 form: lane l supplies V_{j0 + l/16} at row
-// l % 16 of its block as the A operand and U_{j0 + l/16} at column l % 16 as
-// the B operand; unlike the FP32 instruction it holds rows l / 16 + 4 e,
-// e = 0..3, column l % 16 of each result block (found by a lane-layout probe
-// and fixed by the parity tests).  Segments are summed in FP64 by the
-// reduction; the host sizes them so that every one is non-empty.
+// accumulator VGPRs) and walks its segment four beamlets per quad (the
+// MFMA's K = 4), 32 MFMAs per quad.  Eight wavefronts (2 x 4, a 128 x 128
+// pixel workgroup tile, one workgroup per CU) share the factors through
+// double-buffered LDS: U over an x range is needed by 4 wavefronts, V over a
+// y range by 2, so a lane forms one U and one V factor per quad instead of 6.
+// Q quads pass between barriers; a lane forms its factors of the same quad
+// of the next pass while a quad's products run, from record fields loaded
+// one quad earlier.  Operand layout as in the FP32 form: lane l supplies
+// V_{j0 + l/16} at row l % 16 of its block as the A operand and U_{j0 + l/16}
+// at column l % 16 as the B operand; unlike the FP32 instruction it holds
+// rows l / 16 + 4 e, e = 0..3, column l % 16 of each result block (found by a
+// lane-layout probe and fixed by the parity tests).  Segments are summed in
+// FP64 by the reduction; the host sizes them so that every one is non-empty.
 #include "gbd_device.h"
 
 namespace gbd {
@@ -32,6 +35,8 @@ using namespace dev;
 typedef double d4 __attribute__((ext_vector_type(4)));
 
 constexpr int kBX = 4, kBY = 2;  // 16-pixel blocks per wavefront along x and y
+constexpr int kWX = 2, kWY = 4;  // wavefronts per workgroup along x and y
+constexpr int kQ = 4;            // quads of beamlets per pass between barriers
 
 struct Fields64 {
     double arho, brho, p0, p1, p2, p3, p5, l0, l1, l2, l3, l5;
@@ -67,12 +72,16 @@ __device__ inline double2 factor64(double d, double c0, double c1, double c2, do
     return make_double2(m * c, m * s);
 }
 
-template <int WX, int WY>
-__global__ void __launch_bounds__(64 * WX * WY) eval_sep64_kernel(EvalGeom g, const Rec64 *__restrict__ rec,
-                                                                   double2 *__restrict__ partial,
-                                                                   double2 *__restrict__ out) {
-    static_assert(WX == 2 && WY == 2, "factor sharing assumes 2 x 2 wavefronts");
-    __shared__ double2 lu[2][WX][kBX][64], lv[2][WY][kBY][64];  // [buffer][range][block][lane]
+struct Lds64 {
+    double2 lu[2][kQ][kWX][kBX][64], lv[2][kQ][kWY][kBY][64];  // [buffer][quad][range][block][lane]
+};
+
+__global__ void __launch_bounds__(64 * kWX * kWY) eval_sep64_kernel(EvalGeom g, const Rec64 *__restrict__ rec,
+                                                                     double2 *__restrict__ partial,
+                                                                     double2 *__restrict__ out) {
+    __shared__ Lds64 L;
+    auto &lu = L.lu;
+    auto &lv = L.lv;
     const int w = work_item(blockIdx.x, gridDim.x);
     if (w >= g.work) return;
     const int tiles = g.tiles_x * g.tiles_y;
@@ -80,27 +89,17 @@ __global__ void __launch_bounds__(64 * WX * WY) eval_sep64_kernel(EvalGeom g, co
     const int t = w - seg * tiles;
     const int ty = t / g.tiles_x, tx = t - ty * g.tiles_x;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int wx = wv % WX, wy = wv / WX;
-    const int x0 = (tx * WX + wx) * 16 * kBX, y0 = (ty * WY + wy) * 16 * kBY;
+    const int wx = wv % kWX, wy = wv / kWX;
+    const int x0 = (tx * kWX + wx) * 16 * kBX, y0 = (ty * kWY + wy) * 16 * kBY;
     const int li = lane & 15, lk = lane >> 4;
 
-    // Wavefront (wx, wy) forms U blocks 2 wy, 2 wy + 1 of x range wx (shared
-    // with (wx, 1 - wy)) and V block wx of y range wy (shared with (1 - wx, wy)).
-    double ax[2], lx[2];
-    for (int h = 0; h < 2; h++) {
-        const int ix = x0 + 16 * (2 * wy + h) + li;
-        ax[h] = g.a0 + ix * g.dx;
-        lx[h] = ix < g.nx ? 0.0 : -INFINITY;
-    }
-    const int iyv = y0 + 16 * wx + li;
-    const double by = g.b0 + iyv * g.dy;
-    const double ly = iyv < g.ny ? 0.0 : -INFINITY;
-    auto publish = [&](const Fields64 &f, int buf) {
-#pragma unroll
-        for (int h = 0; h < 2; h++)
-            lu[buf][wx][2 * wy + h][lane] =
-                factor64(ax[h] - f.arho, f.p0, f.p1, f.p3, f.l0 + (f.lbias + lx[h]), f.l1, f.l3);
-        lv[buf][wy][wx][lane] = factor64(by - f.brho, 0.0, f.p2, f.p5, ly, f.l2, f.l5);
+    // this wavefront forms U block wy of x range wx and V block wx of y range wy
+    const int ix = x0 + 16 * wy + li, iyv = y0 + 16 * wx + li;
+    const double ax = g.a0 + ix * g.dx, lx = ix < g.nx ? 0.0 : -INFINITY;
+    const double by = g.b0 + iyv * g.dy, ly = iyv < g.ny ? 0.0 : -INFINITY;
+    auto publish = [&](const Fields64 &f, int buf, int qd) {
+        lu[buf][qd][wx][wy][lane] = factor64(ax - f.arho, f.p0, f.p1, f.p3, f.l0 + (f.lbias + lx), f.l1, f.l3);
+        lv[buf][qd][wy][wx][lane] = factor64(by - f.brho, 0.0, f.p2, f.p5, ly, f.l2, f.l5);
     };
 
     // accR/accI[p][q]: rows of the product are y (A operand = V), columns x (B = U)
@@ -110,46 +109,52 @@ __global__ void __launch_bounds__(64 * WX * WY) eval_sep64_kernel(EvalGeom g, co
 #pragma unroll
         for (int q = 0; q < kBX; q++) accR[p][q] = accI[p][q] = d4{0.0, 0.0, 0.0, 0.0};
 
+    constexpr int P = 4 * kQ;  // beamlets per pass
     const int64_t jb = (int64_t)seg * g.seg_len;
     const int64_t je = min(g.n, jb + g.seg_len);
-    publish(load_fields64(rec, jb + lk, jb, je), 0);
-    Fields64 nxt = load_fields64(rec, jb + 4 + lk, jb, je);
+#pragma unroll
+    for (int qd = 0; qd < kQ; qd++) publish(load_fields64(rec, jb + 4 * qd + lk, jb, je), 0, qd);
+    Fields64 fn = load_fields64(rec, jb + P + lk, jb, je);  // the next pass's first quad
     __syncthreads();
     int buf = 0;
-    for (int64_t j0 = jb; j0 < je; j0 += 4) {
-        // this step's factors first (published before the last barrier)
-        double ur[kBX], ui[kBX], vr[kBY], vi[kBY], vn[kBY];
+    for (int64_t j0 = jb; j0 < je; j0 += P) {
+        const bool more = j0 + P < je;
 #pragma unroll
-        for (int b = 0; b < kBX; b++) {
-            const double2 u = lu[buf][wx][b][lane];
-            ur[b] = u.x;
-            ui[b] = u.y;
-        }
+        for (int qd = 0; qd < kQ; qd++) {
+            double ur[kBX], ui[kBX], vr[kBY], vi[kBY], vn[kBY];
 #pragma unroll
-        for (int b = 0; b < kBY; b++) {
-            const double2 v = lv[buf][wy][b][lane];
-            vr[b] = v.x;
-            vi[b] = v.y;
-            vn[b] = -v.y;
-        }
-        const Fields64 f = nxt;
-        nxt = load_fields64(rec, j0 + 8 + lk, jb, je);
-        if (j0 + 4 < je) publish(f, buf ^ 1);
-        // Re += Vr Ur - Vi Ui ; Im += Vr Ui + Vi Ur
-#pragma unroll
-        for (int p = 0; p < kBY; p++)
-#pragma unroll
-            for (int q = 0; q < kBX; q++) {
-                accR[p][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(vr[p], ur[q], accR[p][q], 0, 0, 0);
-                accI[p][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(vr[p], ui[q], accI[p][q], 0, 0, 0);
+            for (int b = 0; b < kBX; b++) {
+                const double2 u = lu[buf][qd][wx][b][lane];
+                ur[b] = u.x;
+                ui[b] = u.y;
             }
 #pragma unroll
-        for (int p = 0; p < kBY; p++)
-#pragma unroll
-            for (int q = 0; q < kBX; q++) {
-                accR[p][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(vn[p], ui[q], accR[p][q], 0, 0, 0);
-                accI[p][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(vi[p], ur[q], accI[p][q], 0, 0, 0);
+            for (int b = 0; b < kBY; b++) {
+                const double2 v = lv[buf][qd][wy][b][lane];
+                vr[b] = v.x;
+                vi[b] = v.y;
+                vn[b] = -v.y;
             }
+            if (more) {
+                publish(fn, buf ^ 1, qd);
+                fn = load_fields64(rec, j0 + P + 4 * (qd + 1) + lk, jb, je);
+            }
+            // Re += Vr Ur - Vi Ui ; Im += Vr Ui + Vi Ur
+#pragma unroll
+            for (int p = 0; p < kBY; p++)
+#pragma unroll
+                for (int q = 0; q < kBX; q++) {
+                    accR[p][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(vr[p], ur[q], accR[p][q], 0, 0, 0);
+                    accI[p][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(vr[p], ui[q], accI[p][q], 0, 0, 0);
+                }
+#pragma unroll
+            for (int p = 0; p < kBY; p++)
+#pragma unroll
+                for (int q = 0; q < kBX; q++) {
+                    accR[p][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(vn[p], ui[q], accR[p][q], 0, 0, 0);
+                    accI[p][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(vi[p], ur[q], accI[p][q], 0, 0, 0);
+                }
+        }
         __syncthreads();
         buf ^= 1;
     }
@@ -159,13 +164,13 @@ __global__ void __launch_bounds__(64 * WX * WY) eval_sep64_kernel(EvalGeom g, co
     for (int p = 0; p < kBY; p++)
 #pragma unroll
         for (int q = 0; q < kBX; q++) {
-            const int ix = x0 + 16 * q + li;
-            if (ix >= g.nx) continue;
+            const int ixo = x0 + 16 * q + li;
+            if (ixo >= g.nx) continue;
 #pragma unroll
             for (int e = 0; e < 4; e++) {
                 const int iy = y0 + 16 * p + lk + 4 * e;
                 if (iy >= g.ny) continue;
-                const int64_t px = (int64_t)iy * g.nx + ix;
+                const int64_t px = (int64_t)iy * g.nx + ixo;
                 const double2 v = make_double2(accR[p][q][e], accI[p][q][e]);
                 if (g.nseg == 1)
                     out[px] = v;
@@ -178,9 +183,10 @@ __global__ void __launch_bounds__(64 * WX * WY) eval_sep64_kernel(EvalGeom g, co
 }  // namespace
 
 hipError_t launch_eval_sep64(const EvalGeom &g, const Rec64 *rec, double2 *partial, double2 *out, hipStream_t s) {
+    static_assert(kWX == kSep64WavesX && kWY == kSep64WavesY && 16 * kBY == kSepRows64 && 16 * kBX == kSepTileX,
+                  "FP64 separable form: host and kernel tiles");
     const int grid = (g.work + 7) / 8 * 8;
-    eval_sep64_kernel<kSep64WavesX, kSep64WavesY><<<grid, 64 * kSep64WavesX * kSep64WavesY, 0, s>>>(g, rec, partial,
-                                                                                                 out);
+    eval_sep64_kernel<<<grid, 64 * kWX * kWY, 0, s>>>(g, rec, partial, out);
     return hipGetLastError();
 }
 
