@@ -77,7 +77,9 @@ typedef struct {
                                the lane's middle row, the other rows by complex
                                recurrence (anchor x rho^k x sigma^(k^2)); 4 = separable:
                                E = sum_j U_j(x) V_j(y) as a complex matrix product on
-                               FP32 MFMA (rows_per_lane and waves do not apply).
+                               FP32 MFMA in three real products per pair, 128 x 128 pixel
+                               workgroup tiles (rows_per_lane and waves do not apply;
+                               gbd_plan_shape reports 32 and 8).
                                Separable is used (auto) or honoured (4) when no beamlet's
                                phasor has a cross term (rotationally symmetric systems on
                                a plane normal to the axis); stepped and rotor when the
