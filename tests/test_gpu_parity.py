@@ -130,6 +130,26 @@ def test_separable_form_ragged_defocused_off_axis(ctx, nx, ny, seg):
           f"separable {nx}x{ny} seg {seg}")
 
 
+@pytest.mark.parametrize("precision", BOTH)
+@pytest.mark.parametrize("n,seg", [(1, 1), (2, 1), (5, 1), (15, 1), (16, 1), (17, 1), (33, 1), (33, 4), (37, 5),
+                                   (64, 3), (100, 7)])
+def test_separable_form_short_segments(ctx, precision, n, seg):
+    """The separable forms take beamlets in passes of four quads (16) between
+    barriers: segments shorter than a pass, a pass and a quad, and ragged last
+    passes and quads, on a grid smaller than one workgroup tile."""
+    full = scenes.airy_scene(21, npix=70, npix_y=45, half_span_lamF=6.0, field_angle=(1e-3, -5e-4), z0=30e-6)
+    keep = np.zeros(full.n, bool)
+    keep[np.random.default_rng(n).choice(full.n, n, replace=False)] = True
+    sc = oracle._subset(full, keep)
+    b = gbd.beamlets_from_scene(ctx, sc)
+    p = gbd.plane_from_scene(ctx, sc)
+    plan = gbd.Plan(ctx, sc.n).setup(b, p)
+    o = dict(segments=seg, variant=4)
+    assert plan.shape(precision, opts=o)["variant"] == 4
+    check(plan.eval(precision, opts=o).cpu().numpy(), oracle.eval_field(sc), precision,
+          f"separable n {n} seg {seg}")
+
+
 def test_cross_terms_rule_out_the_separable_form(ctx):
     sc = scenes.zernike_scene(7, n_across=12, npix=40, half_span=30e-6)
     plan = gbd.Plan(ctx, sc.n).setup(gbd.beamlets_from_scene(ctx, sc), gbd.plane_from_scene(ctx, sc))
