@@ -77,7 +77,9 @@ struct gbd_plan_s {
     RecCut64 *c64;  // truncation factors, allocated at the first setup of truncated beamlets
     RecCut32 *c32;
     int64_t n_cut;  // truncated beamlets of the last setup (the last n_cut records)
-    uint32_t *status_dev;
+    uint32_t *status_dev;   // two flag words used by alternate setups; each setup clears the other
+    int status_parity;      // the word the next setup uses
+    bool status_zeroed;     // both words cleared (once, before the first setup)
     uint32_t *status_host;  // pinned
     void *scratch;
     size_t scratch_bytes;
@@ -496,15 +498,20 @@ int plan_setup_impl(gbd_ctx_s *ctx, gbd_plan_s *plan, gbd_beamlets_s *b, gbd_pla
         // the axial term l0 / lambda is common to every beamlet: reduce it once
         const double g0 = b->dev.l0 / b->dev.lam;
         const double gturns = g0 - nearbyint(g0);
-        HIP_TRY(hipMemsetAsync(plan->status_dev, 0, sizeof(uint32_t), ctx->stream), "hipMemsetAsync(status)");
+        if (!plan->status_zeroed) {
+            HIP_TRY(hipMemsetAsync(plan->status_dev, 0, 2 * sizeof(uint32_t), ctx->stream), "hipMemsetAsync(status)");
+            plan->status_zeroed = true;
+        }
         const bool hg = b->dev.order != nullptr;
         const bool cut = b->dev.n_cut > 0;
+        uint32_t *status = plan->status_dev + plan->status_parity;
+        uint32_t *status_next = plan->status_dev + (plan->status_parity ^ 1);
         HIP_TRY(launch_setup(b->dev, p->g, gturns, plan->r64, plan->r32, hg ? plan->h64 : nullptr,
                              hg ? plan->h32 : nullptr, cut ? plan->c64 : nullptr, cut ? plan->c32 : nullptr,
-                             plan->status_dev, ctx->stream),
+                             status, status_next, ctx->stream),
                 "setup kernel launch");
-        HIP_TRY(hipMemcpyAsync(plan->status_host, plan->status_dev, sizeof(uint32_t), hipMemcpyDeviceToHost,
-                               ctx->stream),
+        plan->status_parity ^= 1;
+        HIP_TRY(hipMemcpyAsync(plan->status_host, status, sizeof(uint32_t), hipMemcpyDeviceToHost, ctx->stream),
                 "status copy");
         HIP_TRY(hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
         const uint32_t st = *plan->status_host;
@@ -544,7 +551,7 @@ int plan_new(gbd_ctx_s *ctx, int64_t capacity, gbd_plan_s **out) {
     hipError_t e = hipMalloc(&p->r64, cap * sizeof(Rec64));
     if (e == hipSuccess) e = hipMalloc(&p->r32, cap * sizeof(Rec32));
     if (e == hipSuccess) e = hipMalloc(&p->q64, cap * sizeof(RecSq64));
-    if (e == hipSuccess) e = hipMalloc(&p->status_dev, sizeof(uint32_t));
+    if (e == hipSuccess) e = hipMalloc(&p->status_dev, 2 * sizeof(uint32_t));
     if (e == hipSuccess) e = hipHostMalloc(&p->status_host, sizeof(uint32_t), hipHostMallocDefault);
     if (e != hipSuccess) {
         plan_destroy(p);

@@ -267,9 +267,12 @@ hipError_t launch_mlp_colsum(const float *dZ, int B, int W, float *db, hipStream
 hipError_t launch_mlp_adamw(float *p, const float *g, float *m, float *v, int64_t n, float lr, float b1, float b2,
                             float eps, float wd, float c1, float c2, hipStream_t s);
 
+// status: a device word, zero on entry, that receives the OR of the
+// beamlets' FLAG_* bits; status_next: another word, set to zero for the
+// next setup (the host alternates the two, so no separate clear is needed).
 hipError_t launch_setup(const BeamletsDev &b, const PlaneGeom &pl, double global_turns, Rec64 *r64,
                         Rec32 *r32, RecHG64 *h64, RecHG32 *h32, RecCut64 *c64, RecCut32 *c32,
-                        uint32_t *status, hipStream_t s);
+                        uint32_t *status, uint32_t *status_next, hipStream_t s);
 
 // The rotor forms' sigma^(k^2) tables (k = 1..16) of the g.n beamlets, from
 // their FP64 records on rows g.dy apart: into q64 (FP64 rotor form) or the

@@ -24,8 +24,10 @@ __global__ void __launch_bounds__(256) setup_kernel(BeamletsDev b, PlaneGeom pl,
                                                     Rec64 *__restrict__ r64, Rec32 *__restrict__ r32,
                                                     RecHG64 *__restrict__ h64, RecHG32 *__restrict__ h32,
                                                     RecCut64 *__restrict__ c64, RecCut32 *__restrict__ c32,
-                                                    uint32_t *__restrict__ status) {
+                                                    uint32_t *__restrict__ status,
+                                                    uint32_t *__restrict__ status_next) {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j == 0) *status_next = 0u;  // the next setup's flag word (not used by this one)
     if (j >= b.n) return;
     const uint32_t flag = setup_one(b, pl, gturns, j, r64, r32, h64, h32, c64, c32, false);
     if (flag) atomicOr(status, flag);
@@ -400,10 +402,12 @@ hipError_t launch_sigma(const EvalGeom &g, const Rec64 *r64, RecSq64 *q64, Rec32
 }
 
 hipError_t launch_setup(const BeamletsDev &b, const PlaneGeom &pl, double global_turns, Rec64 *r64, Rec32 *r32,
-                        RecHG64 *h64, RecHG32 *h32, RecCut64 *c64, RecCut32 *c32, uint32_t *status, hipStream_t s) {
+                        RecHG64 *h64, RecHG32 *h32, RecCut64 *c64, RecCut32 *c32, uint32_t *status,
+                        uint32_t *status_next, hipStream_t s) {
     if (b.n == 0) return hipSuccess;
     const int64_t blocks = (b.n + 255) / 256;
-    setup_kernel<<<(unsigned)blocks, 256, 0, s>>>(b, pl, global_turns, r64, r32, h64, h32, c64, c32, status);
+    setup_kernel<<<(unsigned)blocks, 256, 0, s>>>(b, pl, global_turns, r64, r32, h64, h32, c64, c32, status,
+                                                  status_next);
     return hipGetLastError();
 }
 
