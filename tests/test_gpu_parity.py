@@ -150,6 +150,34 @@ def test_separable_form_short_segments(ctx, precision, n, seg):
           f"separable n {n} seg {seg}")
 
 
+def test_consecutive_setups_of_one_plan_keep_their_own_flags(ctx):
+    """A plan's setups alternate two device status words, each setup clearing
+    the other: flags (cross terms, a refusal) must not carry over to the next
+    setup, and a refused setup must not leave stale flags behind."""
+    import torch
+    airy = scenes.airy_scene(10, npix=40)
+    zern = scenes.zernike_scene(7, n_across=10, npix=40, half_span=30e-6)
+    n = max(airy.n, zern.n)
+    plan = gbd.Plan(ctx, n)
+    ba, pa = gbd.beamlets_from_scene(ctx, airy), gbd.plane_from_scene(ctx, airy)
+    bz, pz = gbd.beamlets_from_scene(ctx, zern), gbd.plane_from_scene(ctx, zern)
+    binv = gbd.gbd_beamlets(ctx, airy.n, airy.lam, airy.l0, airy.r1, airy.th1, airy.w0, airy.amp, airy.path,
+                            -np.eye(4))
+    ref_a = oracle.eval_field(airy)
+    for step in range(5):
+        for b, p, variant in ((bz, pz, 3), (ba, pa, 4), (ba, pa, 4), (bz, pz, 3)):
+            plan.setup(b, p)
+            assert plan.shape(gbd.GBD_MIXED)["variant"] == variant, (step, variant)
+        with pytest.raises(gbd.GbdError) as e:
+            plan.setup(binv, pa)
+        assert e.value.code == -3
+        plan.setup(ba, pa)
+        assert plan.shape(gbd.GBD_MIXED)["variant"] == 4
+        E = plan.eval(gbd.GBD_MIXED)
+        torch.cuda.synchronize()
+        check(E.cpu().numpy(), ref_a, gbd.GBD_MIXED, f"airy after a refused setup, round {step}")
+
+
 def test_cross_terms_rule_out_the_separable_form(ctx):
     sc = scenes.zernike_scene(7, n_across=12, npix=40, half_span=30e-6)
     plan = gbd.Plan(ctx, sc.n).setup(gbd.beamlets_from_scene(ctx, sc), gbd.plane_from_scene(ctx, sc))
