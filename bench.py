@@ -123,6 +123,8 @@ def main():
     ap.add_argument("--no-telescope", action="store_true", help="skip the ray-traced telescope leg")
     ap.add_argument("--no-hermite", action="store_true", help="skip the higher-order beamlet leg")
     ap.add_argument("--no-truncated", action="store_true", help="skip the truncated-beamlet leg")
+    ap.add_argument("--no-aberrated", action="store_true",
+                    help="skip the aberrated tilted-plane leg (zern128_1024, the general form)")
     ap.add_argument("--fp64-steps", type=int, default=5)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 256 MiB device copy (a known-size kernel for HBM counters)")
@@ -230,6 +232,8 @@ def main():
 
     if shape["variant"] == 4:
         rec["general_form"] = general_form(plan, N, M, out, stream)
+    if not args.no_aberrated and args.workload != "zern128_1024":
+        rec["aberrated"] = aberrated(ctx, stream)
     if not args.no_point:
         rec["point_eval"] = point_eval(ctx, b, p, N * M, eval_ms_mean, eval64_ms)
     if not args.no_sweep:
@@ -289,6 +293,48 @@ def general_form(plan, N, M, out, stream, reps=20):
     r = roofline(shape, N, M, ms)
     return {"launch": shape, "eval_ms": ms, "evals_per_s": N * M / (ms * 1e-3), "roofline_frac": r["frac"],
             "roofline_peak": r["peak"]}
+
+
+def aberrated(ctx, stream, reps=10, reps64=3):
+    """The aberrated, tilted-plane workload (zern128_1024: f/4, 12,892
+    beamlets with seeded Zernike Z4-Z11 terms, a field angle, the plane tilted
+    10 degrees, 1024 x 1024 pixels): cross terms everywhere, so both
+    precisions take their general (rotor) forms."""
+    import numpy as np
+    import torch
+    import paper_2404_12454_amd as gbd
+    from paper_2404_12454_amd import scenes
+    sc = scenes.config("zern128_1024")
+    b = gbd.beamlets_from_scene(ctx, sc)
+    p = gbd.plane_from_scene(ctx, sc)
+    plan = gbd.Plan(ctx, sc.n).setup(b, p)
+    N, M = sc.n, sc.plane.npix
+
+    def timed(prec, out, warm, n):
+        for _ in range(warm):
+            plan.eval(prec, out)
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n)]
+        for a, z in evs:
+            a.record(stream)
+            plan.eval(prec, out)
+            z.record(stream)
+        torch.cuda.synchronize()
+        return float(np.mean([a.elapsed_time(z) for a, z in evs]))
+
+    out = torch.empty((sc.plane.ny, sc.plane.nx), dtype=torch.complex64, device="cuda")
+    out64 = torch.empty((sc.plane.ny, sc.plane.nx), dtype=torch.complex128, device="cuda")
+    ms = timed(gbd.GBD_MIXED, out, reps, reps)
+    ms64 = timed(gbd.GBD_FP64, out64, 1, reps64)
+    E32 = out.cpu().numpy().astype(np.complex128)
+    E64 = out64.cpu().numpy()
+    shape, shape64 = plan.shape(gbd.GBD_MIXED), plan.shape(gbd.GBD_FP64)
+    r = roofline(shape, N, M, ms)
+    r64 = fp64_record(shape64, N, M, ms64, ms)
+    return {"beamlets": N, "npix": [sc.plane.nx, sc.plane.ny], "launch": shape, "eval_ms": ms,
+            "evals_per_s": N * M / (ms * 1e-3), "roofline_frac": r["frac"], "roofline_peak": r["peak"],
+            "fp64": {"launch": shape64, "eval_ms": ms64, "evals_per_s": N * M / (ms64 * 1e-3),
+                     "roofline_frac": r64.get("roofline_frac")},
+            "err_mixed_vs_fp64_full_grid": float(np.linalg.norm(E32 - E64) / np.linalg.norm(E64))}
 
 
 def point_eval(ctx, b, p, pairs, mixed_ms, fp64_ms, reps=2):
