@@ -237,11 +237,13 @@ int gbd_plan_shape(gbd_ctx_t ctx, gbd_plan_t plan, int precision, const gbd_eval
  * gbd_autotune: times every launch shape of gbd_plan_eval for this plan and
  * precision (rows_per_lane in {2,4,8} (and 16, 32 where a rotor form applies) x waves in
  * {1,2,4} x segment counts of
- * 1/2, 1, 2 and 4 times the automatic choice; `reps` timed launches each, HIP
- * events on the context stream), stores the fastest in the context's cache
- * keyed by (precision, log2 N, log2 M) and returns it in *best (resolved
- * segment count) and its time in *best_ms.  Later calls with all-zero opts
- * on the same bucket use it.  Synchronises; overwrites no caller buffer.
+ * 1/2, 1, 2 and 4 times the automatic choice; where the separable form
+ * applies, whose tile is fixed, the segment counts only; `reps` timed
+ * launches each, HIP events on the context stream), stores the fastest in
+ * the context's cache keyed by (form family, precision, log2 N, log2 M) and
+ * returns it in *best (resolved segment count) and its time in *best_ms.
+ * Later calls with all-zero opts (segments 0 for the separable form) on the
+ * same bucket use it.  Synchronises; overwrites no caller buffer.
  * gbd_autotune_batch: the same over rows_per_lane x waves for gbd_eval_batch
  * on these instances (host wall time per call), cached by (log2 pairs,
  * log2 instances).

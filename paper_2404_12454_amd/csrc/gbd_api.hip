@@ -230,6 +230,9 @@ int ilog2(int64_t v) {
     return r;
 }
 
+// cache kinds: single evaluations in a VALU form, batched sweeps, single
+// evaluations in the separable form (only the segment count applies)
+constexpr int kTuneEval = 0, kTuneBatch = 1, kTuneSep = 2;
 TuneKey tune_key(int kind, int precision, int64_t n, int64_t m) { return TuneKey{kind, precision, ilog2(n), ilog2(m)}; }
 
 // Launch shape and mixed form.  32 rows per lane is a rotor-form shape: where
@@ -259,6 +262,8 @@ Shape choose_shape(const gbd_ctx_s *ctx, int precision, int64_t n, const PlaneGe
                        ((pl.ny + s.rows * wy - 1) / (s.rows * wy)));
             const int64_t per_cu = 8 / s.waves;
             int64_t seg = ((int64_t)ctx->cus * per_cu + tiles - 1) / tiles;
+            auto it = ctx->tuned.find(tune_key(kTuneSep, precision, n, (int64_t)pl.nx * pl.ny));
+            if (it != ctx->tuned.end()) seg = std::max<int64_t>(1, seg * it->second.seg_scale_pct / 100);
             seg = std::min<int64_t>(seg, std::max<int64_t>(1, n / 256));
             s.nseg = (int)std::max<int64_t>(1, std::min<int64_t>(seg, 1024));
         }
@@ -271,7 +276,7 @@ Shape choose_shape(const gbd_ctx_s *ctx, int precision, int64_t n, const PlaneGe
     int seg_pct = 100;
     const bool user = o && (o->rows_per_lane || o->waves || o->segments);
     if (!user) {
-        auto it = ctx->tuned.find(tune_key(0, precision, n, (int64_t)pl.nx * pl.ny));
+        auto it = ctx->tuned.find(tune_key(kTuneEval, precision, n, (int64_t)pl.nx * pl.ny));
         if (it != ctx->tuned.end()) {
             s.rows = it->second.rows;
             s.waves = it->second.waves;
@@ -939,16 +944,22 @@ int gbd_autotune(gbd_ctx_t ctx, gbd_plan_t plan, int precision, int32_t reps, gb
     if (he == hipSuccess) he = hipEventCreate(&e1);
     TuneVal bestv{0, 0, 100, 1e300};
     static const int rows_c[] = {2, 4, 8, 16, 32}, waves_c[] = {1, 2, 4}, pct_c[] = {50, 100, 200, 400};
-    const int n_rows = precision == GBD_MIXED ? ((plan->flags & FLAG_STEEP) ? 4 : 5)
-                                              : ((plan->flags & (FLAG_STEEP | FLAG_HG)) ? 3 : 5);
+    const int64_t n_main = plan->n - plan->n_cut;  // the beamlets choose_shape sizes the form for
+    // the separable form has a fixed tile: only its segment count is tuned
+    const bool sep = pick_form(precision, plan->flags, nullptr) == 3;
+    const int kind = sep ? kTuneSep : kTuneEval;
+    const int n_rows = sep ? 1
+                           : precision == GBD_MIXED ? ((plan->flags & FLAG_STEEP) ? 4 : 5)
+                                                    : ((plan->flags & (FLAG_STEEP | FLAG_HG)) ? 3 : 5);
+    const int n_waves = sep ? 1 : 3;
     for (int ri = 0; ri < n_rows && he == hipSuccess && rc == GBD_OK; ri++)
-        for (int wi = 0; wi < 3 && he == hipSuccess && rc == GBD_OK; wi++)
+        for (int wi = 0; wi < n_waves && he == hipSuccess && rc == GBD_OK; wi++)
             for (int pi = 0; pi < 4 && he == hipSuccess && rc == GBD_OK; pi++) {
                 // a candidate is addressed through the cache so that choose_shape
                 // resolves its segment count exactly as a tuned call would
-                const TuneKey key = tune_key(0, precision, plan->n, M);
+                const TuneKey key = tune_key(kind, precision, n_main, M);
                 const auto saved = ctx->tuned.find(key) != ctx->tuned.end() ? ctx->tuned[key] : TuneVal{0, 0, 0, -1};
-                ctx->tuned[key] = TuneVal{rows_c[ri], waves_c[wi], pct_c[pi], 0.0};
+                ctx->tuned[key] = TuneVal{sep ? 0 : rows_c[ri], sep ? 0 : waves_c[wi], pct_c[pi], 0.0};
                 rc = plan_eval_impl(ctx, plan, precision, out, out_bytes, nullptr);  // warm-up / scratch growth
                 double ms = 0.0;
                 if (rc == GBD_OK) {
@@ -966,17 +977,17 @@ int gbd_autotune(gbd_ctx_t ctx, gbd_plan_t plan, int precision, int32_t reps, gb
                 else
                     ctx->tuned[key] = saved;
                 if (rc == GBD_OK && he == hipSuccess && ms < bestv.ms)
-                    bestv = TuneVal{rows_c[ri], waves_c[wi], pct_c[pi], ms};
+                    bestv = TuneVal{sep ? 0 : rows_c[ri], sep ? 0 : waves_c[wi], pct_c[pi], ms};
             }
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
     (void)hipFree(out);
     if (rc) return rc;
     if (he != hipSuccess) return hip_fail(he, "autotune timing");
-    ctx->tuned[tune_key(0, precision, plan->n, M)] = bestv;
+    ctx->tuned[tune_key(kind, precision, n_main, M)] = bestv;
     if (best) {
-        const Shape s = choose_shape(ctx, precision, plan->n - plan->n_cut, plan->pl, plan->flags, nullptr);
-        const EvalGeom g = make_geom(plan->pl, plan->n - plan->n_cut, s);
+        const Shape s = choose_shape(ctx, precision, n_main, plan->pl, plan->flags, nullptr);
+        const EvalGeom g = make_geom(plan->pl, n_main, s);
         *best = gbd_eval_opts{s.rows, s.waves, g.nseg, form_variant(precision, s.form)};
     }
     if (best_ms) *best_ms = bestv.ms;
@@ -1007,7 +1018,9 @@ int gbd_autotune_load(gbd_ctx_t ctx, const char *path) {
         TuneVal v;
         if (sscanf(line, "%d %d %d %d %d %d %d %lf", &k.kind, &k.precision, &k.ln, &k.lm, &v.rows, &v.waves,
                    &v.seg_scale_pct, &v.ms) == 8 &&
-            valid_shape(v.rows, v.waves, k.precision) && v.seg_scale_pct > 0 && v.seg_scale_pct <= 10000) {
+            (k.kind == kTuneSep ? v.rows == 0 && v.waves == 0
+                                : (k.kind == kTuneEval || k.kind == kTuneBatch) && valid_shape(v.rows, v.waves, k.precision)) &&
+            v.seg_scale_pct > 0 && v.seg_scale_pct <= 10000) {
             ctx->tuned[k] = v;
             loaded++;
         }
@@ -1087,7 +1100,7 @@ int gbd_eval_batch(gbd_ctx_t ctx, int32_t n_inst, const gbd_beamlets_t *bs, cons
         pairs += bs[i]->dev.n * ((int64_t)ps[i]->g.nx * ps[i]->g.ny);
     }
     if (!(opts && (opts->rows_per_lane || opts->waves))) {
-        auto it = ctx->tuned.find(tune_key(1, GBD_MIXED, pairs, n_inst));
+        auto it = ctx->tuned.find(tune_key(kTuneBatch, GBD_MIXED, pairs, n_inst));
         if (it != ctx->tuned.end()) {
             rows = it->second.rows;
             waves = it->second.waves;
@@ -1268,7 +1281,7 @@ int gbd_autotune_batch(gbd_ctx_t ctx, int32_t n_inst, const gbd_beamlets_t *bs, 
                 std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count() / reps;
             if (ms < bestv.ms) bestv = TuneVal{rows_c[ri], waves_c[wi], 100, ms};
         }
-    ctx->tuned[tune_key(1, GBD_MIXED, pairs, n_inst)] = bestv;
+    ctx->tuned[tune_key(kTuneBatch, GBD_MIXED, pairs, n_inst)] = bestv;
     if (best) *best = gbd_eval_opts{bestv.rows, bestv.waves, 0, 0};
     if (best_ms) *best_ms = bestv.ms;
     return GBD_OK;

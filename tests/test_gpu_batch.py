@@ -169,3 +169,32 @@ def test_autotuner_picks_a_valid_shape_and_results_hold(ctx, tmp_path):
     assert gbd.gbd_autotune_load(fresh, path) >= 1
     plan2 = gbd.Plan(fresh, sc.n).setup(gbd.beamlets_from_scene(fresh, sc), gbd.plane_from_scene(fresh, sc))
     assert plan2.shape(gbd.GBD_MIXED) == best
+
+
+def test_autotuner_tunes_the_separable_forms_segments(ctx, tmp_path):
+    """Where the separable form applies only its segment count is tuned (the
+    tile is fixed); the cached choice is used with default opts, survives a
+    save and load, and the field still matches the oracle."""
+    import torch
+    sc = scenes.airy_scene(40, npix=300, npix_y=260, half_span_lamF=10.0)
+    b = gbd.beamlets_from_scene(ctx, sc)
+    p = gbd.plane_from_scene(ctx, sc)
+    plan = gbd.Plan(ctx, sc.n).setup(b, p)
+    auto = plan.shape(gbd.GBD_MIXED)
+    assert auto["variant"] == 4
+    best, ms = gbd.gbd_autotune(plan, gbd.GBD_MIXED, reps=2)
+    print("separable autotuned", auto, "->", best, ms, flush=True)
+    assert best["variant"] == 4 and best["segments"] >= 1 and ms > 0
+    assert (best["rows_per_lane"], best["waves"]) == (auto["rows_per_lane"], auto["waves"])
+    assert plan.shape(gbd.GBD_MIXED) == best
+    E = plan.eval(gbd.GBD_MIXED)
+    torch.cuda.synchronize()
+    ref = oracle.eval_field(sc)
+    e = E.cpu().numpy().astype(np.complex128)
+    assert np.linalg.norm(e - ref) / np.linalg.norm(ref) < 1e-5
+    path = str(tmp_path / "tune_sep.txt")
+    gbd.gbd_autotune_save(ctx, path)
+    fresh = gbd.Context(0)
+    assert gbd.gbd_autotune_load(fresh, path) >= 1
+    plan2 = gbd.Plan(fresh, sc.n).setup(gbd.beamlets_from_scene(fresh, sc), gbd.plane_from_scene(fresh, sc))
+    assert plan2.shape(gbd.GBD_MIXED) == best
