@@ -67,7 +67,7 @@ typedef struct {
     int32_t variant;        /* 0 = auto.  FP64: 1 = direct (exp and sincospi per pixel), 3 =
                                rotor (the recurrence below in FP64; well-sampled grids and
                                fundamental beamlets only), 4 = separable (below, on FP64
-                               MFMA; no cross terms, fundamental beamlets only); auto:
+                               MFMA; no cross terms, higher-order factors included); auto:
                                separable, else rotor, else direct; a request that does not
                                apply resolves as auto among the others.
                                Mixed: 1 = direct: FP64 phase and exp2

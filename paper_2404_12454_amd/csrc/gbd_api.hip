@@ -196,12 +196,12 @@ struct Shape {
 int pick_form(int precision, uint32_t flags, const gbd_eval_opts *o, bool allow_sep = true) {
     const bool steep = (flags & FLAG_STEEP) != 0;
     if (precision != GBD_MIXED) {
-        // FP64: direct, rotor (needs a well-sampled grid) or separable (needs
-        // phasors without cross terms); neither of the last two carries a
-        // higher-order factor.  A request that does not apply falls back to
+        // FP64: direct, rotor (needs a well-sampled grid; fundamental
+        // beamlets only) or separable (needs phasors and higher-order factors
+        // without cross terms).  A request that does not apply falls back to
         // the automatic choice among the others.
         const bool hg = (flags & FLAG_HG) != 0;
-        const bool sep64 = allow_sep && !(flags & FLAG_CROSS) && !hg;
+        const bool sep64 = allow_sep && !(flags & FLAG_CROSS);
         const bool rot64 = !steep && !hg;
         const int v = o ? o->variant : 0;
         if (v == 1) return 0;
@@ -447,8 +447,8 @@ int plan_eval_impl(gbd_ctx_s *ctx, gbd_plan_s *plan, int precision, void *out, i
         EvalGeom gl = g;
         if (reduce) gl.nseg = std::max<int32_t>(total, 2);  // segment partials, never the output
         if (s.form == 3 && precision == GBD_FP64)
-            HIP_TRY(launch_eval_sep64(gl, plan->r64, static_cast<double2 *>(plan->scratch), static_cast<double2 *>(out),
-                                      ctx->stream),
+            HIP_TRY(launch_eval_sep64(gl, plan->r64, static_cast<const RecHG64 *>(hrec),
+                                      static_cast<double2 *>(plan->scratch), static_cast<double2 *>(out), ctx->stream),
                     "eval kernel launch");
         else if (s.form == 3)
             HIP_TRY(launch_eval_sep(gl, plan->r32, static_cast<const RecHG32 *>(hrec),

@@ -318,7 +318,9 @@ constexpr int kSepRows64 = 32;
 constexpr int kSep64WavesX = 2, kSep64WavesY = 4;
 static_assert(kSep64WavesX == kSepWavesX && kSepRows64 == kSepTileY,
               "separable tiles: the host derives the y count of wavefronts from the workgroup size");
-hipError_t launch_eval_sep64(const EvalGeom &g, const Rec64 *rec, double2 *partial, double2 *out, hipStream_t s);
+// hg: higher-order factors without cross terms (G diagonal), or null.
+hipError_t launch_eval_sep64(const EvalGeom &g, const Rec64 *rec, const RecHG64 *hg, double2 *partial, double2 *out,
+                             hipStream_t s);
 
 // hg: higher-order factors without cross terms (k1 = k0 = 0, G diagonal), or null.
 // Partials as float2 (no compensation term): the compact segments of

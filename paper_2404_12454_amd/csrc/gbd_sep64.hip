@@ -7,7 +7,9 @@
 // (v_mfma_f64_16x16x4_f64, FP64 products and sums).  Each factor is the FP64
 // form's phasor (phase reduced to turns, the device library's exp and
 // sincospi), so every beamlet-pixel term is the same product as in the other
-// FP64 forms; only the order of the sum changes.
+// FP64 forms; only the order of the sum changes.  Higher-order beamlets
+// without cross terms fold their per-axis Hermite-Gaussian polynomial into U
+// and V.
 //
 // Tiling: a 16 x 16 block of FP64 accumulators takes 8 VGPRs per lane and
 // part (Re, Im), so a wavefront owns 64 x 32 pixels (4 x 2 blocks, 128
@@ -41,11 +43,32 @@ constexpr int kQ = 4;            // quads of beamlets per pass between barriers
 struct Fields64 {
     double arho, brho, p0, p1, p2, p3, p5, l0, l1, l2, l3, l5;
     double lbias;  // 0, or -inf past the segment end (factor 0)
+    // higher-order beamlets: G's diagonal and the per-axis polynomials
+    double gxr, gxi, cx0r, cx0i, cx1, cx2;
+    double gyr, gyi, cy0r, cy0i, cy1, cy2;
 };
 
-__device__ inline Fields64 load_fields64(const Rec64 *__restrict__ rec, int64_t j, int64_t jb, int64_t je) {
-    const Rec64 *rp = rec + (j < je ? j : jb);
+template <bool HG>
+__device__ inline Fields64 load_fields64(const Rec64 *__restrict__ rec, const RecHG64 *__restrict__ hg, int64_t j,
+                                         int64_t jb, int64_t je) {
+    const int64_t jj = j < je ? j : jb;
+    const Rec64 *rp = rec + jj;
     Fields64 f;
+    if constexpr (HG) {
+        const RecHG64 *h = hg + jj;
+        f.gxr = h->g[0][0][0];
+        f.gxi = h->g[0][0][1];
+        f.cx0r = h->cx0[0];
+        f.cx0i = h->cx0[1];
+        f.cx1 = h->cx1;
+        f.cx2 = h->cx2;
+        f.gyr = h->g[1][1][0];
+        f.gyi = h->g[1][1][1];
+        f.cy0r = h->cy0[0];
+        f.cy0i = h->cy0[1];
+        f.cy1 = h->cy1;
+        f.cy2 = h->cy2;
+    }
     f.arho = rp->arho;
     f.brho = rp->brho;
     f.p0 = rp->p[0];
@@ -62,6 +85,16 @@ __device__ inline Fields64 load_fields64(const Rec64 *__restrict__ rec, int64_t 
     return f;
 }
 
+// The factor times a higher-order beamlet's axis polynomial c0 + g (c1 + c2 g),
+// g = G d (no cross terms: G diagonal), FP64.
+__device__ inline double2 hg_axis64(double2 u, double d, double gr0, double gi0, double c0r, double c0i, double c1,
+                                   double c2) {
+    const double gr = gr0 * d, gi = gi0 * d;
+    const double tr = fma(c2, gr, c1), ti = c2 * gi;
+    const double pr = c0r + (gr * tr - gi * ti), pi = c0i + (gr * ti + gi * tr);
+    return make_double2(u.x * pr - u.y * pi, u.x * pi + u.y * pr);
+}
+
 // e^(g0 + d (g1 + g2 d)) e^(2 pi i (c0 + d (c1 + c2 d))), FP64
 __device__ inline double2 factor64(double d, double c0, double c1, double c2, double g0, double g1, double g2) {
     double T = c0 + d * (c1 + c2 * d);
@@ -76,7 +109,9 @@ struct Lds64 {
     double2 lu[2][kQ][kWX][kBX][64], lv[2][kQ][kWY][kBY][64];  // [buffer][quad][range][block][lane]
 };
 
+template <bool HG>
 __global__ void __launch_bounds__(64 * kWX * kWY) eval_sep64_kernel(EvalGeom g, const Rec64 *__restrict__ rec,
+                                                                     const RecHG64 *__restrict__ hg,
                                                                      double2 *__restrict__ partial,
                                                                      double2 *__restrict__ out) {
     __shared__ Lds64 L;
@@ -98,8 +133,15 @@ __global__ void __launch_bounds__(64 * kWX * kWY) eval_sep64_kernel(EvalGeom g, 
     const double ax = g.a0 + ix * g.dx, lx = ix < g.nx ? 0.0 : -INFINITY;
     const double by = g.b0 + iyv * g.dy, ly = iyv < g.ny ? 0.0 : -INFINITY;
     auto publish = [&](const Fields64 &f, int buf, int qd) {
-        lu[buf][qd][wx][wy][lane] = factor64(ax - f.arho, f.p0, f.p1, f.p3, f.l0 + (f.lbias + lx), f.l1, f.l3);
-        lv[buf][qd][wy][wx][lane] = factor64(by - f.brho, 0.0, f.p2, f.p5, ly, f.l2, f.l5);
+        const double da = ax - f.arho, db = by - f.brho;
+        double2 u = factor64(da, f.p0, f.p1, f.p3, f.l0 + (f.lbias + lx), f.l1, f.l3);
+        double2 v = factor64(db, 0.0, f.p2, f.p5, ly, f.l2, f.l5);
+        if constexpr (HG) {
+            u = hg_axis64(u, da, f.gxr, f.gxi, f.cx0r, f.cx0i, f.cx1, f.cx2);
+            v = hg_axis64(v, db, f.gyr, f.gyi, f.cy0r, f.cy0i, f.cy1, f.cy2);
+        }
+        lu[buf][qd][wx][wy][lane] = u;
+        lv[buf][qd][wy][wx][lane] = v;
     };
 
     // accR/accI[p][q]: rows of the product are y (A operand = V), columns x (B = U)
@@ -113,8 +155,8 @@ __global__ void __launch_bounds__(64 * kWX * kWY) eval_sep64_kernel(EvalGeom g, 
     const int64_t jb = (int64_t)seg * g.seg_len;
     const int64_t je = min(g.n, jb + g.seg_len);
 #pragma unroll
-    for (int qd = 0; qd < kQ; qd++) publish(load_fields64(rec, jb + 4 * qd + lk, jb, je), 0, qd);
-    Fields64 fn = load_fields64(rec, jb + P + lk, jb, je);  // the next pass's first quad
+    for (int qd = 0; qd < kQ; qd++) publish(load_fields64<HG>(rec, hg, jb + 4 * qd + lk, jb, je), 0, qd);
+    Fields64 fn = load_fields64<HG>(rec, hg, jb + P + lk, jb, je);  // the next pass's first quad
     __syncthreads();
     int buf = 0;
     for (int64_t j0 = jb; j0 < je; j0 += P) {
@@ -137,7 +179,7 @@ __global__ void __launch_bounds__(64 * kWX * kWY) eval_sep64_kernel(EvalGeom g, 
             }
             if (more) {
                 publish(fn, buf ^ 1, qd);
-                fn = load_fields64(rec, j0 + P + 4 * (qd + 1) + lk, jb, je);
+                fn = load_fields64<HG>(rec, hg, j0 + P + 4 * (qd + 1) + lk, jb, je);
             }
             // Re += Vr Ur - Vi Ui ; Im += Vr Ui + Vi Ur
 #pragma unroll
@@ -182,11 +224,15 @@ __global__ void __launch_bounds__(64 * kWX * kWY) eval_sep64_kernel(EvalGeom g, 
 
 }  // namespace
 
-hipError_t launch_eval_sep64(const EvalGeom &g, const Rec64 *rec, double2 *partial, double2 *out, hipStream_t s) {
+hipError_t launch_eval_sep64(const EvalGeom &g, const Rec64 *rec, const RecHG64 *hg, double2 *partial, double2 *out,
+                             hipStream_t s) {
     static_assert(kWX == kSep64WavesX && kWY == kSep64WavesY && 16 * kBY == kSepRows64 && 16 * kBX == kSepTileX,
                   "FP64 separable form: host and kernel tiles");
     const int grid = (g.work + 7) / 8 * 8;
-    eval_sep64_kernel<<<grid, 64 * kWX * kWY, 0, s>>>(g, rec, partial, out);
+    if (hg)
+        eval_sep64_kernel<true><<<grid, 64 * kWX * kWY, 0, s>>>(g, rec, hg, partial, out);
+    else
+        eval_sep64_kernel<false><<<grid, 64 * kWX * kWY, 0, s>>>(g, rec, nullptr, partial, out);
     return hipGetLastError();
 }
 

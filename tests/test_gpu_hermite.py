@@ -32,11 +32,11 @@ def field(ctx, sc, precision, opts=None):
     return E.cpu().numpy().astype(np.complex128)
 
 
-def resolved_variant(ctx, sc, opts=None):
+def resolved_variant(ctx, sc, opts=None, precision=gbd.GBD_MIXED):
     b = gbd.beamlets_from_scene(ctx, sc)
     p = gbd.plane_from_scene(ctx, sc)
     plan = gbd.Plan(ctx, sc.n).setup(b, p)
-    return plan.shape(gbd.GBD_MIXED, opts)["variant"]
+    return plan.shape(precision, opts)["variant"]
 
 
 SCENES = {
@@ -71,6 +71,12 @@ def test_hermite_forms_resolve(ctx):
     assert resolved_variant(ctx, sym, dict(variant=2)) == 1
     assert resolved_variant(ctx, sym, dict(variant=3)) == 3
     assert resolved_variant(ctx, astig, dict(variant=4)) == 3
+    # FP64: separable without cross terms, else direct (the FP64 rotor form
+    # carries no higher-order factor)
+    assert resolved_variant(ctx, sym, precision=gbd.GBD_FP64) == 4
+    assert resolved_variant(ctx, astig, precision=gbd.GBD_FP64) == 1
+    assert resolved_variant(ctx, sym, dict(variant=3), precision=gbd.GBD_FP64) == 4
+    assert resolved_variant(ctx, sym, dict(variant=1), precision=gbd.GBD_FP64) == 1
     b = gbd.beamlets_from_scene(ctx, astig)
     plan = gbd.Plan(ctx, astig.n).setup(b, gbd.plane_from_scene(ctx, astig))
     assert plan.shape(gbd.GBD_MIXED, dict(rows_per_lane=32, waves=4, variant=3))["rows_per_lane"] == 32
@@ -93,6 +99,21 @@ def test_hermite_fp64_shapes(ctx, rows, waves, segments):
     ref = oracle.eval_field(sc)
     E = field(ctx, sc, gbd.GBD_FP64, dict(rows_per_lane=rows, waves=waves, segments=segments))
     assert rel_l2(E, ref) < 1e-12
+
+
+@pytest.mark.parametrize("nx,ny,seg", [(90, 70, 1), (90, 70, 3), (33, 17, 2), (130, 129, 7), (1, 1, 1)])
+def test_hermite_fp64_separable_form(ctx, nx, ny, seg):
+    """The FP64 separable form with the per-axis Hermite-Gaussian factors on
+    ragged grids and segment counts, defocused, against the oracle and
+    against the FP64 direct form."""
+    sc = scenes.hermite_scene(14, npix=nx, npix_y=ny, seed=13, z0=1e-3, half_span_lamF=12.0)
+    ref = oracle.eval_field(sc)
+    E4 = field(ctx, sc, gbd.GBD_FP64, dict(variant=4, segments=seg))
+    E1 = field(ctx, sc, gbd.GBD_FP64, dict(variant=1))
+    print(f"hermite FP64 separable {nx}x{ny} seg {seg}: vs oracle {rel_l2(E4, ref):.2e}, "
+          f"vs direct {rel_l2(E4, E1):.2e}", flush=True)
+    assert rel_l2(E4, ref) < 1e-12
+    assert rel_l2(E4, E1) < 1e-13
 
 
 @pytest.mark.parametrize("precision", [gbd.GBD_FP64, gbd.GBD_MIXED])
