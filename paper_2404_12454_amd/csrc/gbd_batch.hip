@@ -12,7 +12,7 @@
 //                      wavefront shuffles
 //  batch_sep_kernel    the same with the separable (matrix) form where no
 //                      beamlet's phasor has a cross term: items are
-//                      (instance, 128 x 128 tile), each a 2 x 2-wavefront
+//                      (instance, 128 x 128 tile), each a 2 x 4-wavefront
 //                      MFMA accumulation over all of the instance's beamlets
 //  batch_finalize      per instance, fixed-order sum of its items' partials
 //  airy_kernel         reference irradiance (2 J1(v)/v)^2 in FP64

@@ -48,7 +48,9 @@ static_assert(sizeof(Rec64) == 128, "Rec64 layout");
 // Mixed-precision record: FP64 phase in turns, FP32 log2-amplitude, and the
 // lane-independent row-step terms for this plane's dy:
 //   stepped form: t2 = p5 dy^2 reduced mod 1, u2 = m5 dy^2, s2 = 2^(2 u2);
-//   rotor form:   sq[k-1] = sigma^(k^2), sigma = 2^(u2) e^(2 pi i t2), k = 1..16.
+//   rotor form:   sq[k-1] = sigma^(k^2), sigma = 2^(u2) e^(2 pi i t2), k = 1..16
+//                 (filled by launch_sigma before a rotor-form evaluation; the
+//                 plan's setup leaves it unset, the batched setup fills it).
 struct alignas(16) Rec32 {
     double arho, brho;
     double p[6];
