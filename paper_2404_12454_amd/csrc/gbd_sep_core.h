@@ -154,6 +154,7 @@ __device__ inline void sep_accumulate_3m(const SepGeom &g, const Rec32 *__restri
 #pragma unroll
         for (int q = 0; q < k3BX; q++) a1[p][q] = a2[p][q] = a3[p][q] = f4{0.0f, 0.0f, 0.0f, 0.0f};
 
+    static_assert(Q % 2 == 0, "the two-slot field ring needs an even number of quads per pass");
     constexpr int P = 4 * Q;  // beamlets per pass
 #pragma unroll
     for (int qd = 0; qd < Q; qd++) publish(load_fields<HG>(rec, hg, jb + 4 * qd + lk, jb, je), 0, qd);
