@@ -451,8 +451,8 @@ def hermite(ctx, stream, gauss_ms, n_across=256, npix=512, reps=10):
     beamlet) on the headline grid: through the ideal lens (no cross terms:
     the separable MFMA form with per-axis factors) and through an added
     rotated cylindrical lens (cross terms: the rotor form with the factor's
-    row polynomial), mixed precision; the focal case also in FP64 (separable
-    form on FP64 MFMA)."""
+    row polynomial), mixed precision, and both in FP64 (separable form on
+    FP64 MFMA; FP64 rotor form with the row polynomial)."""
     import numpy as np
     import torch
     import paper_2404_12454_amd as gbd
@@ -479,26 +479,28 @@ def hermite(ctx, stream, gauss_ms, n_across=256, npix=512, reps=10):
         if shape["variant"] == 4:
             r["mfma_frac"] = roofline(shape, sc.n, npix * npix, ms)["frac"]
             r["cost_vs_fundamental"] = ms / gauss_ms
-            # the FP64 separable form (FP64 MFMA) with the same factors
-            out64 = torch.empty((npix, npix), dtype=torch.complex128, device="cuda")
-            plan.eval(gbd.GBD_FP64, out64)
-            e64 = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(3)]
-            for a, z in e64:
-                a.record(stream)
-                plan.eval(gbd.GBD_FP64, out64)
-                z.record(stream)
-            torch.cuda.synchronize()
-            ms64 = float(np.mean([a.elapsed_time(z) for a, z in e64]))
-            E64 = out64.cpu().numpy()
-            r["fp64"] = {"launch": plan.shape(gbd.GBD_FP64), "eval_ms": ms64,
-                         "evals_per_s": sc.n * npix * npix / (ms64 * 1e-3),
-                         "fp64_mfma_frac": SEP_FLOPS_PER_PAIR * sc.n * npix * npix / (ms64 * 1e-3) / 1e12
-                         / MFMA_FP64_TFLOPS,
-                         "err_mixed_vs_fp64": float(np.linalg.norm(out.cpu().numpy() - E64) / np.linalg.norm(E64))}
         elif shape["variant"] == 3:
             rf = roofline(shape, sc.n, npix * npix, ms, hg=True)
             r["roofline_peak"] = rf["peak"]
             r["roofline_frac"] = rf["frac"]
+        # the FP64 form of the same input (separable on FP64 MFMA, or the FP64
+        # rotor form with the factor's row polynomial)
+        out64 = torch.empty((npix, npix), dtype=torch.complex128, device="cuda")
+        plan.eval(gbd.GBD_FP64, out64)
+        e64 = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(3)]
+        for a, z in e64:
+            a.record(stream)
+            plan.eval(gbd.GBD_FP64, out64)
+            z.record(stream)
+        torch.cuda.synchronize()
+        ms64 = float(np.mean([a.elapsed_time(z) for a, z in e64]))
+        E64 = out64.cpu().numpy()
+        shape64 = plan.shape(gbd.GBD_FP64)
+        r64 = {"launch": shape64, "eval_ms": ms64, "evals_per_s": sc.n * npix * npix / (ms64 * 1e-3),
+               "err_mixed_vs_fp64": float(np.linalg.norm(out.cpu().numpy() - E64) / np.linalg.norm(E64))}
+        if shape64["variant"] == 4:
+            r64["fp64_mfma_frac"] = SEP_FLOPS_PER_PAIR * sc.n * npix * npix / (ms64 * 1e-3) / 1e12 / MFMA_FP64_TFLOPS
+        r["fp64"] = r64
         res[name] = r
     return res
 

@@ -65,8 +65,8 @@ typedef struct {
     int32_t waves;          /* wavefronts per workgroup: 1, 2 or 4 */
     int32_t segments;       /* beamlet segments evaluated by separate workgroups, 0 = auto */
     int32_t variant;        /* 0 = auto.  FP64: 1 = direct (exp and sincospi per pixel), 3 =
-                               rotor (the recurrence below in FP64; well-sampled grids and
-                               fundamental beamlets only), 4 = separable (below, on FP64
+                               rotor (the recurrence below in FP64; well-sampled grids; at
+                               most 16 rows with higher-order beamlets), 4 = separable (below, on FP64
                                MFMA; no cross terms, higher-order factors included); auto:
                                separable, else rotor, else direct; a request that does not
                                apply resolves as auto among the others.

@@ -196,13 +196,12 @@ struct Shape {
 int pick_form(int precision, uint32_t flags, const gbd_eval_opts *o, bool allow_sep = true) {
     const bool steep = (flags & FLAG_STEEP) != 0;
     if (precision != GBD_MIXED) {
-        // FP64: direct, rotor (needs a well-sampled grid; fundamental
-        // beamlets only) or separable (needs phasors and higher-order factors
-        // without cross terms).  A request that does not apply falls back to
-        // the automatic choice among the others.
-        const bool hg = (flags & FLAG_HG) != 0;
+        // FP64: direct, rotor (needs a well-sampled grid) or separable (needs
+        // phasors and higher-order factors without cross terms).  A request
+        // that does not apply falls back to the automatic choice among the
+        // others.
         const bool sep64 = allow_sep && !(flags & FLAG_CROSS);
-        const bool rot64 = !steep && !hg;
+        const bool rot64 = !steep;
         const int v = o ? o->variant : 0;
         if (v == 1) return 0;
         if (v == 3 && rot64) return 2;
@@ -290,6 +289,8 @@ Shape choose_shape(const gbd_ctx_s *ctx, int precision, int64_t n, const PlaneGe
     }
     if (s.rows == 32 && s.form != 2) s.rows = 16;
     if (precision != GBD_MIXED && s.form == 0 && s.rows > 8) s.rows = 8;  // FP64 direct form: up to 8 rows
+    // FP64 rotor form with higher-order factors: up to 16 rows (registers)
+    if (precision != GBD_MIXED && s.form == 2 && (flags & FLAG_HG) && s.rows > 16) s.rows = 16;
     if (s.nseg <= 0) {
         // enough workgroups to keep every SIMD of every CU busy ~6 waves deep,
         // while each segment keeps at least two LDS tiles of beamlets
@@ -950,7 +951,9 @@ int gbd_autotune(gbd_ctx_t ctx, gbd_plan_t plan, int precision, int32_t reps, gb
     const int kind = sep ? kTuneSep : kTuneEval;
     const int n_rows = sep ? 1
                            : precision == GBD_MIXED ? ((plan->flags & FLAG_STEEP) ? 4 : 5)
-                                                    : ((plan->flags & (FLAG_STEEP | FLAG_HG)) ? 3 : 5);
+                           : (plan->flags & FLAG_STEEP) ? 3
+                           : (plan->flags & FLAG_HG)    ? 4
+                                                        : 5;
     const int n_waves = sep ? 1 : 3;
     for (int ri = 0; ri < n_rows && he == hipSuccess && rc == GBD_OK; ri++)
         for (int wi = 0; wi < n_waves && he == hipSuccess && rc == GBD_OK; wi++)

@@ -435,36 +435,40 @@ __device__ inline float2 hg_factor32(const RecHG32 &h, float gxa_r, float gxa_i,
     return make_float2(re, im);
 }
 
+// fused multiply-add in the precision of its arguments
+__device__ inline float fm(float a, float b, float c) { return fmaf(a, b, c); }
+__device__ inline double fm(double a, double b, double c) { return fma(a, b, c); }
+
 // The Hermite-Gaussian factor along a lane's column as a polynomial in the
 // row step k from the anchor row (plane offsets da, db there, row pitch dy):
 // gx = ax + k sx, gy = ay + k sy with ax = G[0][0] da + G[0][1] db,
 // sx = G[0][1] dy (likewise y); Px, Py are quadratics and ax, ay linear in
 // k, so P = Px Py + k1 ax ay + k0 has degree <= 4.  q[i] = (re, im) of the
-// coefficient of k^i.
-__device__ inline void hg_row_poly(const RecHG32 &h, float da, float db, float dy, float (&q)[5][2]) {
-    const float axr = fmaf(h.g[0][1][0], db, h.g[0][0][0] * da), axi = fmaf(h.g[0][1][1], db, h.g[0][0][1] * da);
-    const float ayr = fmaf(h.g[1][1][0], db, h.g[1][0][0] * da), ayi = fmaf(h.g[1][1][1], db, h.g[1][0][1] * da);
-    const float sxr = h.g[0][1][0] * dy, sxi = h.g[0][1][1] * dy;
-    const float syr = h.g[1][1][0] * dy, syi = h.g[1][1][1] * dy;
+// coefficient of k^i (T float with RecHG32 records, double with RecHG64).
+template <typename T, typename RecHG>
+__device__ inline void hg_row_poly(const RecHG &h, T da, T db, T dy, T (&q)[5][2]) {
+    const T axr = fm(h.g[0][1][0], db, h.g[0][0][0] * da), axi = fm(h.g[0][1][1], db, h.g[0][0][1] * da);
+    const T ayr = fm(h.g[1][1][0], db, h.g[1][0][0] * da), ayi = fm(h.g[1][1][1], db, h.g[1][0][1] * da);
+    const T sxr = h.g[0][1][0] * dy, sxi = h.g[0][1][1] * dy;
+    const T syr = h.g[1][1][0] * dy, syi = h.g[1][1][1] * dy;
     // Px = cx0 + cx1 g + cx2 g^2 at g = a + s k:
     //   px0 = cx0 + a (cx1 + cx2 a), px1 = s (cx1 + 2 cx2 a), px2 = cx2 s^2
-    auto quad = [](float c0r, float c0i, float c1, float c2, float ar, float ai, float sr, float si,
-                   float (&p)[3][2]) {
-        const float tr = fmaf(c2, ar, c1), ti = c2 * ai;
+    auto quad = [](T c0r, T c0i, T c1, T c2, T ar, T ai, T sr, T si, T (&p)[3][2]) {
+        const T tr = fm(c2, ar, c1), ti = c2 * ai;
         p[0][0] = c0r + (ar * tr - ai * ti);
         p[0][1] = c0i + (ar * ti + ai * tr);
-        const float ur = fmaf(2.0f * c2, ar, c1), ui = 2.0f * c2 * ai;
+        const T ur = fm(T(2) * c2, ar, c1), ui = T(2) * c2 * ai;
         p[1][0] = sr * ur - si * ui;
         p[1][1] = sr * ui + si * ur;
         p[2][0] = c2 * (sr * sr - si * si);
-        p[2][1] = c2 * (2.0f * sr * si);
+        p[2][1] = c2 * (T(2) * sr * si);
     };
-    float px[3][2], py[3][2];
+    T px[3][2], py[3][2];
     quad(h.cx0[0], h.cx0[1], h.cx1, h.cx2, axr, axi, sxr, sxi, px);
     quad(h.cy0[0], h.cy0[1], h.cy1, h.cy2, ayr, ayi, syr, syi, py);
     // Px Py (product of quadratics)
 #pragma unroll
-    for (int i = 0; i < 5; i++) q[i][0] = q[i][1] = 0.0f;
+    for (int i = 0; i < 5; i++) q[i][0] = q[i][1] = T(0);
 #pragma unroll
     for (int i = 0; i < 3; i++)
 #pragma unroll
@@ -473,13 +477,13 @@ __device__ inline void hg_row_poly(const RecHG32 &h, float da, float db, float d
             q[i + j][1] += px[i][0] * py[j][1] + px[i][1] * py[j][0];
         }
     // k1 ax ay + k0, ax = (ex0 + ex1 a) + ex1 s k
-    const float x0r = fmaf(h.ex1, axr, h.ex0), x0i = h.ex1 * axi, x1r = h.ex1 * sxr, x1i = h.ex1 * sxi;
-    const float y0r = fmaf(h.ey1, ayr, h.ey0), y0i = h.ey1 * ayi, y1r = h.ey1 * syr, y1i = h.ey1 * syi;
-    const float m0r = x0r * y0r - x0i * y0i, m0i = x0r * y0i + x0i * y0r;
-    const float m1r = (x0r * y1r - x0i * y1i) + (x1r * y0r - x1i * y0i);
-    const float m1i = (x0r * y1i + x0i * y1r) + (x1r * y0i + x1i * y0r);
-    const float m2r = x1r * y1r - x1i * y1i, m2i = x1r * y1i + x1i * y1r;
-    const float kr = h.k1[0], ki = h.k1[1];
+    const T x0r = fm(h.ex1, axr, h.ex0), x0i = h.ex1 * axi, x1r = h.ex1 * sxr, x1i = h.ex1 * sxi;
+    const T y0r = fm(h.ey1, ayr, h.ey0), y0i = h.ey1 * ayi, y1r = h.ey1 * syr, y1i = h.ey1 * syi;
+    const T m0r = x0r * y0r - x0i * y0i, m0i = x0r * y0i + x0i * y0r;
+    const T m1r = (x0r * y1r - x0i * y1i) + (x1r * y0r - x1i * y0i);
+    const T m1i = (x0r * y1i + x0i * y1r) + (x1r * y0i + x1i * y0r);
+    const T m2r = x1r * y1r - x1i * y1i, m2i = x1r * y1i + x1i * y1r;
+    const T kr = h.k1[0], ki = h.k1[1];
     q[0][0] += (kr * m0r - ki * m0i) + h.k0[0];
     q[0][1] += (kr * m0i + ki * m0r) + h.k0[1];
     q[1][0] += kr * m1r - ki * m1i;
@@ -488,14 +492,16 @@ __device__ inline void hg_row_poly(const RecHG32 &h, float da, float db, float d
     q[2][1] += kr * m2i + ki * m2r;
 }
 
-// q0 + k (q1 + k (q2 + k (q3 + k q4))) for real k.
-__device__ inline float2 horner4(const float (&q)[5][2], float k) {
-    float re = fmaf(q[4][0], k, q[3][0]), im = fmaf(q[4][1], k, q[3][1]);
-    re = fmaf(re, k, q[2][0]);
-    im = fmaf(im, k, q[2][1]);
-    re = fmaf(re, k, q[1][0]);
-    im = fmaf(im, k, q[1][1]);
-    return make_float2(fmaf(re, k, q[0][0]), fmaf(im, k, q[0][1]));
+// q0 + k (q1 + k (q2 + k (q3 + k q4))) for real k, as (re, im).
+template <typename T>
+__device__ inline void horner4(const T (&q)[5][2], T k, T &re_out, T &im_out) {
+    T re = fm(q[4][0], k, q[3][0]), im = fm(q[4][1], k, q[3][1]);
+    re = fm(re, k, q[2][0]);
+    im = fm(im, k, q[2][1]);
+    re = fm(re, k, q[1][0]);
+    im = fm(im, k, q[1][1]);
+    re_out = fm(re, k, q[0][0]);
+    im_out = fm(im, k, q[0][1]);
 }
 
 __device__ inline void kahan(float &s, float &c, float x) {
@@ -737,10 +743,11 @@ __device__ inline void mixed_accumulate_rotor(Rec32 *tile, const Rec32 *__restri
                     pi = ni;
                     const float sr = r.sq[k - 1][0], si = r.sq[k - 1][1];
                     if constexpr (HG) {
-                        const float2 P = horner4(hq, (float)k);
+                        float Px, Py;
+                        horner4(hq, (float)k, Px, Py);
                         const float tr = fmaf(pr, sr, -(pi * si)), ti = fmaf(pr, si, pi * sr);
-                        acc_re[H + k] = fmaf(tr, P.x, fmaf(-ti, P.y, acc_re[H + k]));
-                        acc_im[H + k] = fmaf(tr, P.y, fmaf(ti, P.x, acc_im[H + k]));
+                        acc_re[H + k] = fmaf(tr, Px, fmaf(-ti, Py, acc_re[H + k]));
+                        acc_im[H + k] = fmaf(tr, Py, fmaf(ti, Px, acc_im[H + k]));
                     } else {
                         acc_re[H + k] = fmaf(pr, sr, fmaf(-pi, si, acc_re[H + k]));
                         acc_im[H + k] = fmaf(pr, si, fmaf(pi, sr, acc_im[H + k]));
@@ -759,10 +766,11 @@ __device__ inline void mixed_accumulate_rotor(Rec32 *tile, const Rec32 *__restri
                     pi = ni;
                     const float sr = r.sq[k - 1][0], si = r.sq[k - 1][1];
                     if constexpr (HG) {
-                        const float2 P = horner4(hq, -(float)k);
+                        float Px, Py;
+                        horner4(hq, -(float)k, Px, Py);
                         const float tr = fmaf(pr, sr, -(pi * si)), ti = fmaf(pr, si, pi * sr);
-                        acc_re[H - k] = fmaf(tr, P.x, fmaf(-ti, P.y, acc_re[H - k]));
-                        acc_im[H - k] = fmaf(tr, P.y, fmaf(ti, P.x, acc_im[H - k]));
+                        acc_re[H - k] = fmaf(tr, Px, fmaf(-ti, Py, acc_re[H - k]));
+                        acc_im[H - k] = fmaf(tr, Py, fmaf(ti, Px, acc_im[H - k]));
                     } else {
                         acc_re[H - k] = fmaf(pr, sr, fmaf(-pi, si, acc_re[H - k]));
                         acc_im[H - k] = fmaf(pr, si, fmaf(pi, sr, acc_im[H - k]));

@@ -197,22 +197,27 @@ __global__ void __launch_bounds__(64 * WAVES) eval_fp64_kernel(EvalGeom g, const
 // FP64 rotor form: the mixed rotor recurrence E(h + k) = E(h) rho^k sigma^(k^2)
 // in FP64 throughout (anchor at the lane's middle row h from the FP64 phase
 // and ln-amplitude quadratics, rho and 1/rho from the row slopes, sigma^(k^2)
-// from the setup kernel's FP64 table), so a further row costs two complex
-// FP64 multiply-adds instead of an exp and a sincospi.  The anchor is flushed
+// from the FP64 table sigma_kernel fills), so a further row costs two complex
+// FP64 multiply-adds instead of an exp and a sincospi.  HG: higher-order
+// beamlets, each term times the Hermite-Gaussian factor's degree-4 row
+// polynomial (as in the mixed rotor form), records hg.  The anchor is flushed
 // below e^-700 and the ln-amplitude slope capped at +-40 per row: with the
 // curvature bound of well-sampled grids (|ln-amplitude curvature| <= 0.07 per
 // row^2) a slope of 40 puts the beamlet's peak over 280 rows away and the
 // anchor below e^-5000, so neither touches a term that is not already zero.
-template <int ROWS, int WAVES>
+template <int ROWS, int WAVES, bool HG = false>
 __global__ void __launch_bounds__(64 * WAVES) eval_fp64_rotor_kernel(EvalGeom g, const Rec64 *__restrict__ rec,
                                                                      const RecSq64 *__restrict__ sqt,
                                                                      double2 *__restrict__ partial,
-                                                                     double2 *__restrict__ out) {
-    constexpr int CH = 64;  // records per LDS tile (8 KiB + 16 KiB of sigma tables)
+                                                                     double2 *__restrict__ out,
+                                                                     const RecHG64 *__restrict__ hg = nullptr) {
+    constexpr int CH = 64;  // records per LDS tile (8 KiB + 16 KiB of sigma tables + 12 KiB HG)
     constexpr int H = ROWS / 2;
     static_assert(H <= 16, "FP64 rotor form: at most 32 rows per lane");
+    static_assert(!HG || ROWS <= 16, "FP64 rotor form with higher-order factors: at most 16 rows per lane");
     __shared__ Rec64 tile[CH];
     __shared__ RecSq64 stile[CH];
+    __shared__ RecHG64 htile[HG ? CH : 1];
     const int w = work_item(blockIdx.x, gridDim.x);
     if (w >= g.work) return;
     const int tiles = g.tiles_x * g.tiles_y;
@@ -242,6 +247,11 @@ __global__ void __launch_bounds__(64 * WAVES) eval_fp64_rotor_kernel(EvalGeom g,
             const double2 *qs = reinterpret_cast<const double2 *>(sqt + j0);
             double2 *qd = reinterpret_cast<double2 *>(stile);
             for (int i = threadIdx.x; i < cnt * 16; i += 64 * WAVES) qd[i] = qs[i];
+            if constexpr (HG) {
+                const double2 *hs = reinterpret_cast<const double2 *>(hg + j0);
+                double2 *hd = reinterpret_cast<double2 *>(htile);
+                for (int i = threadIdx.x; i < cnt * 12; i += 64 * WAVES) hd[i] = hs[i];
+            }
         }
         __syncthreads();
         for (int jj = 0; jj < cnt; jj++) {
@@ -258,8 +268,15 @@ __global__ void __launch_bounds__(64 * WAVES) eval_fp64_rotor_kernel(EvalGeom g,
             double s0, c0;
             sincospi(2.0 * (T0 - rint(T0)), &s0, &c0);
             const double zr = m0 * c0, zi = m0 * s0;
-            acc_re[H] += zr;
-            acc_im[H] += zi;
+            [[maybe_unused]] double hq[5][2];
+            if constexpr (HG) {
+                hg_row_poly(htile[jj], da, db, dy, hq);
+                acc_re[H] += zr * hq[0][0] - zi * hq[0][1];
+                acc_im[H] += zr * hq[0][1] + zi * hq[0][0];
+            } else {
+                acc_re[H] += zr;
+                acc_im[H] += zi;
+            }
             const double t1 = T1 - rint(T1);
             double s1, c1;
             sincospi(2.0 * t1, &s1, &c1);
@@ -274,8 +291,16 @@ __global__ void __launch_bounds__(64 * WAVES) eval_fp64_rotor_kernel(EvalGeom g,
                     pr = nr;
                     pi = ni;
                     const double sr = sq.sq[k - 1][0], si = sq.sq[k - 1][1];
-                    acc_re[H + k] = fma(pr, sr, fma(-pi, si, acc_re[H + k]));
-                    acc_im[H + k] = fma(pr, si, fma(pi, sr, acc_im[H + k]));
+                    if constexpr (HG) {
+                        double Px, Py;
+                        horner4(hq, (double)k, Px, Py);
+                        const double tr = fma(pr, sr, -(pi * si)), ti = fma(pr, si, pi * sr);
+                        acc_re[H + k] = fma(tr, Px, fma(-ti, Py, acc_re[H + k]));
+                        acc_im[H + k] = fma(tr, Py, fma(ti, Px, acc_im[H + k]));
+                    } else {
+                        acc_re[H + k] = fma(pr, sr, fma(-pi, si, acc_re[H + k]));
+                        acc_im[H + k] = fma(pr, si, fma(pi, sr, acc_im[H + k]));
+                    }
                 }
             }
             if (H > 0) {
@@ -289,8 +314,16 @@ __global__ void __launch_bounds__(64 * WAVES) eval_fp64_rotor_kernel(EvalGeom g,
                     pr = nr;
                     pi = ni;
                     const double sr = sq.sq[k - 1][0], si = sq.sq[k - 1][1];
-                    acc_re[H - k] = fma(pr, sr, fma(-pi, si, acc_re[H - k]));
-                    acc_im[H - k] = fma(pr, si, fma(pi, sr, acc_im[H - k]));
+                    if constexpr (HG) {
+                        double Px, Py;
+                        horner4(hq, -(double)k, Px, Py);
+                        const double tr = fma(pr, sr, -(pi * si)), ti = fma(pr, si, pi * sr);
+                        acc_re[H - k] = fma(tr, Px, fma(-ti, Py, acc_re[H - k]));
+                        acc_im[H - k] = fma(tr, Py, fma(ti, Px, acc_im[H - k]));
+                    } else {
+                        acc_re[H - k] = fma(pr, sr, fma(-pi, si, acc_re[H - k]));
+                        acc_im[H - k] = fma(pr, si, fma(pi, sr, acc_im[H - k]));
+                    }
                 }
             }
         }
@@ -347,10 +380,15 @@ template <int ROWS, int WAVES>
 hipError_t launch_eval_t(int precision, int form, const EvalGeom &g, const void *rec, const void *hg,
                          const RecSq64 *q64, void *partial, void *out, hipStream_t s) {
     const int grid = (g.work + 7) / 8 * 8;
-    if (precision == 0 && form == 2 && !hg) {
+    if (precision == 0 && form == 2) {
         if (!q64) return hipErrorInvalidValue;
-        eval_fp64_rotor_kernel<ROWS, WAVES><<<grid, 64 * WAVES, 0, s>>>(
-            g, static_cast<const Rec64 *>(rec), q64, static_cast<double2 *>(partial), static_cast<double2 *>(out));
+        if (hg)
+            eval_fp64_rotor_kernel<ROWS, WAVES, true><<<grid, 64 * WAVES, 0, s>>>(
+                g, static_cast<const Rec64 *>(rec), q64, static_cast<double2 *>(partial), static_cast<double2 *>(out),
+                static_cast<const RecHG64 *>(hg));
+        else
+            eval_fp64_rotor_kernel<ROWS, WAVES><<<grid, 64 * WAVES, 0, s>>>(
+                g, static_cast<const Rec64 *>(rec), q64, static_cast<double2 *>(partial), static_cast<double2 *>(out));
         return hipGetLastError();
     }
     if (hg) {
@@ -435,6 +473,17 @@ hipError_t launch_eval(int precision, int rows, int waves, int form, const EvalG
         else if (rows == 32 && waves == 1) eval_fp64_rotor_kernel<32, 1><<<grid, 64, 0, s>>>(g, r, q64, pt, o);
         else if (rows == 32 && waves == 2) eval_fp64_rotor_kernel<32, 2><<<grid, 128, 0, s>>>(g, r, q64, pt, o);
         else if (rows == 32 && waves == 4) eval_fp64_rotor_kernel<32, 4><<<grid, 256, 0, s>>>(g, r, q64, pt, o);
+        else return hipErrorInvalidValue;
+        return hipGetLastError();
+    }
+    if (precision == 0 && form == 2 && hg && q64 && rows == 16) {
+        const int grid = (g.work + 7) / 8 * 8;
+        double2 *pt = static_cast<double2 *>(partial), *o = static_cast<double2 *>(out);
+        const Rec64 *r = static_cast<const Rec64 *>(rec);
+        const RecHG64 *h = static_cast<const RecHG64 *>(hg);
+        if (waves == 1) eval_fp64_rotor_kernel<16, 1, true><<<grid, 64, 0, s>>>(g, r, q64, pt, o, h);
+        else if (waves == 2) eval_fp64_rotor_kernel<16, 2, true><<<grid, 128, 0, s>>>(g, r, q64, pt, o, h);
+        else if (waves == 4) eval_fp64_rotor_kernel<16, 4, true><<<grid, 256, 0, s>>>(g, r, q64, pt, o, h);
         else return hipErrorInvalidValue;
         return hipGetLastError();
     }

@@ -71,11 +71,15 @@ def test_hermite_forms_resolve(ctx):
     assert resolved_variant(ctx, sym, dict(variant=2)) == 1
     assert resolved_variant(ctx, sym, dict(variant=3)) == 3
     assert resolved_variant(ctx, astig, dict(variant=4)) == 3
-    # FP64: separable without cross terms, else direct (the FP64 rotor form
-    # carries no higher-order factor)
+    # FP64: separable without cross terms, else the rotor form (16 rows at
+    # most with the higher-order factor)
     assert resolved_variant(ctx, sym, precision=gbd.GBD_FP64) == 4
-    assert resolved_variant(ctx, astig, precision=gbd.GBD_FP64) == 1
-    assert resolved_variant(ctx, sym, dict(variant=3), precision=gbd.GBD_FP64) == 4
+    assert resolved_variant(ctx, astig, precision=gbd.GBD_FP64) == 3
+    assert resolved_variant(ctx, astig, dict(variant=1), precision=gbd.GBD_FP64) == 1
+    b = gbd.beamlets_from_scene(ctx, astig)
+    plan64 = gbd.Plan(ctx, astig.n).setup(b, gbd.plane_from_scene(ctx, astig))
+    assert plan64.shape(gbd.GBD_FP64, dict(rows_per_lane=32, waves=4, variant=3))["rows_per_lane"] == 16
+    assert resolved_variant(ctx, sym, dict(variant=3), precision=gbd.GBD_FP64) == 3
     assert resolved_variant(ctx, sym, dict(variant=1), precision=gbd.GBD_FP64) == 1
     b = gbd.beamlets_from_scene(ctx, astig)
     plan = gbd.Plan(ctx, astig.n).setup(b, gbd.plane_from_scene(ctx, astig))
@@ -91,6 +95,22 @@ def test_hermite_mixed_shapes(ctx, variant, rows, waves, segments):
     ref = oracle.eval_field(sc)
     E = field(ctx, sc, gbd.GBD_MIXED, dict(rows_per_lane=rows, waves=waves, segments=segments, variant=variant))
     assert rel_l2(E, ref) < 1e-5
+
+
+@pytest.mark.parametrize("rows,waves,segments", [(1, 1, 1), (2, 4, 3), (4, 2, 1), (8, 4, 4), (16, 4, 2), (16, 1, 5),
+                                                 (32, 2, 1)])
+def test_hermite_fp64_rotor_form(ctx, rows, waves, segments):
+    """The FP64 rotor form with the higher-order factor's row polynomial
+    (astigmatic, cross terms) in every launch shape, against the oracle and
+    against the FP64 direct form."""
+    sc = scenes.hermite_scene(14, npix=90, npix_y=70, seed=12, cyl_f=4.0, half_span_lamF=12.0)
+    ref = oracle.eval_field(sc)
+    E3 = field(ctx, sc, gbd.GBD_FP64, dict(rows_per_lane=rows, waves=waves, segments=segments, variant=3))
+    E1 = field(ctx, sc, gbd.GBD_FP64, dict(variant=1))
+    print(f"hermite FP64 rotor {rows}x{waves} seg {segments}: vs oracle {rel_l2(E3, ref):.2e}, "
+          f"vs direct {rel_l2(E3, E1):.2e}", flush=True)
+    assert rel_l2(E3, ref) < 1e-12
+    assert rel_l2(E3, E1) < 1e-13
 
 
 @pytest.mark.parametrize("rows,waves,segments", [(1, 1, 1), (2, 4, 3), (4, 2, 1), (8, 4, 4)])
