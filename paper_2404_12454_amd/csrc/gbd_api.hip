@@ -398,7 +398,11 @@ int plan_eval_impl(gbd_ctx_s *ctx, gbd_plan_s *plan, int precision, void *out, i
     if (out_bytes < M * elem)
         return fail(GBD_ERANGE, "field_out holds %lld bytes, %lld needed", (long long)out_bytes, (long long)(M * elem));
     if (opts && (opts->variant < 0 || opts->variant > 4)) return fail(GBD_EINVAL, "variant must be 0 ... 4");
-    if (opts && opts->rows_per_lane && !valid_shape(opts->rows_per_lane, opts->waves ? opts->waves : 4, precision))
+    // rows_per_lane and waves do not apply to the separable form (its tile is
+    // fixed; gbd_plan_shape reports it, and handing that shape back is fine)
+    const bool sep_form = pick_form(precision, plan->flags, opts) == 3;
+    if (opts && opts->rows_per_lane && !sep_form &&
+        !valid_shape(opts->rows_per_lane, opts->waves ? opts->waves : 4, precision))
         return fail(GBD_EINVAL, "unsupported rows_per_lane %d / waves %d", opts->rows_per_lane, opts->waves);
     Shape s = choose_shape(ctx, precision, plan->n - plan->n_cut, plan->pl, plan->flags, opts);
     if (s.form != 3 && !valid_shape(s.rows, s.waves, precision))

@@ -178,6 +178,25 @@ def test_consecutive_setups_of_one_plan_keep_their_own_flags(ctx):
         check(E.cpu().numpy(), ref_a, gbd.GBD_MIXED, f"airy after a refused setup, round {step}")
 
 
+@pytest.mark.parametrize("precision", BOTH)
+def test_reported_shape_is_accepted_back(ctx, precision):
+    """The shape gbd_plan_shape reports (for the separable form a fixed tile,
+    reported as 32 rows x 8 wavefronts) is accepted as options and gives the
+    default evaluation bit for bit; in a VALU form rows and waves are still
+    checked."""
+    import torch
+    for sc in (scenes.airy_scene(12, npix=48), scenes.zernike_scene(5, n_across=12, npix=48)):
+        plan = gbd.Plan(ctx, sc.n).setup(gbd.beamlets_from_scene(ctx, sc), gbd.plane_from_scene(ctx, sc))
+        shape = plan.shape(precision)
+        a = plan.eval(precision).clone()
+        b = plan.eval(precision, opts=shape)
+        torch.cuda.synchronize()
+        assert torch.equal(a.cpu(), b.cpu()), shape
+    with pytest.raises(gbd.GbdError) as e:
+        plan.eval(precision, opts=dict(rows_per_lane=32, waves=8, variant=3))
+    assert e.value.code == -1
+
+
 def test_cross_terms_rule_out_the_separable_form(ctx):
     sc = scenes.zernike_scene(7, n_across=12, npix=40, half_span=30e-6)
     plan = gbd.Plan(ctx, sc.n).setup(gbd.beamlets_from_scene(ctx, sc), gbd.plane_from_scene(ctx, sc))
