@@ -179,7 +179,7 @@ __global__ void __launch_bounds__(64 * WAVES) batch_eval_kernel(BatchArgs A) {
 __global__ void __launch_bounds__(64 * sep::k3WX * sep::k3WY) batch_sep_kernel(BatchArgs A) {
     constexpr int WX = sep::k3WX, WY = sep::k3WY, BX = sep::k3BX, BY = sep::k3BY;
     constexpr int WAVES = WX * WY, NQ = 2 + 2 * kMaxZones;
-    __shared__ sep::Sep3Lds<sep::k3Quads> L;
+    __shared__ sep::Sep3Lds<false> L;
     __shared__ int s_item;
     __shared__ double red[WAVES][NQ];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -199,7 +199,7 @@ __global__ void __launch_bounds__(64 * sep::k3WX * sep::k3WY) batch_sep_kernel(B
         sep::f4 accR[BY][BX], accI[BY][BX];
         if (I.n > 0) {
             const sep::SepGeom sg{I.nx, I.ny, I.a0, I.b0, I.dx, I.dy};
-            sep::sep_accumulate_3m<sep::k3Quads, false>(sg, A.rec + I.rec_off, nullptr, 0, I.n, tx, ty, L, accR,
+            sep::sep_accumulate_3m<false>(sg, A.rec + I.rec_off, nullptr, 0, I.n, tx, ty, L, accR,
                                                         accI);
         } else {
 #pragma unroll

@@ -22,8 +22,9 @@
 // Eight wavefronts (2 x 4 tiles, 128 x 128 pixels) share the factors through
 // LDS, so each lane forms 2 phasors per quad instead of 6: on gfx950 VALU and
 // MFMA issue from one SIMD do not overlap, so every VALU instruction per
-// MFMA is time lost from the matrix pipe.  Four quads pass between barriers,
-// and the record fields are loaded two quads ahead.  Accumulators stay in
+// MFMA is time lost from the matrix pipe.  Four quads (eight with
+// higher-order factors) pass between barriers, and the record fields are
+// loaded two quads ahead.  Accumulators stay in
 // FP32 over the segment; segments are summed in FP64 by the reduction.  The
 // host sizes segments so that every one is non-empty (jb < je <= N).
 //
@@ -43,7 +44,7 @@ __global__ void __launch_bounds__(64 * k3WX * k3WY) eval_sep_kernel(EvalGeom g, 
                                                                      const RecHG32 *__restrict__ hg,
                                                                      float2 *__restrict__ partial,
                                                                      float2 *__restrict__ out) {
-    __shared__ Sep3Lds<k3Quads> L;
+    __shared__ Sep3Lds<HG> L;
     const int w = work_item(blockIdx.x, gridDim.x);
     if (w >= g.work) return;
     const int tiles = g.tiles_x * g.tiles_y;
@@ -58,7 +59,7 @@ __global__ void __launch_bounds__(64 * k3WX * k3WY) eval_sep_kernel(EvalGeom g, 
     const int64_t jb = (int64_t)seg * g.seg_len;
     const int64_t je = min(g.n, jb + g.seg_len);
     f4 accR[k3BY][k3BX], accI[k3BY][k3BX];
-    sep_accumulate_3m<k3Quads, HG>(sg, rec, hg, jb, je, tx, ty, L, accR, accI);
+    sep_accumulate_3m<HG>(sg, rec, hg, jb, je, tx, ty, L, accR, accI);
 
     // D[row][col] of a 16 x 16 block: lane l holds rows 4 (l / 16) + e, column l % 16
     const int64_t M = (int64_t)g.nx * g.ny;

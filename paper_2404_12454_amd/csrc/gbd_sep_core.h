@@ -3,6 +3,8 @@
 // pixel tile over a range of beamlets (see gbd_sep.hip for the method).
 #pragma once
 
+#include <type_traits>
+
 #include "gbd_device.h"
 
 namespace gbd {
@@ -103,26 +105,39 @@ struct SepGeom {
 // lane forms one U and one V factor per quad of beamlets.
 constexpr int k3WX = 2, k3WY = 4;  // wavefronts per workgroup along x and y
 constexpr int k3BX = 4, k3BY = 2;  // 16-pixel blocks per wavefront along x and y
-constexpr int k3Quads = 4;         // quads of beamlets per pass between barriers
+// Quads of beamlets per pass between barriers, and the LDS slot of a factor:
+// fundamental beamlets keep (re, im, re + im, 0) in a float4, four quads per
+// pass; higher-order beamlets, whose factors cost more VALU, pay more for
+// each barrier and take eight quads per pass in the same 128 KiB, the factor
+// as (re, im) with re + im formed by the reader (the same FP32 sum either
+// way).  Measured on 51,468 x 512^2: fundamental 0.780 ms (four quads) against
+// 0.799 ms (eight), higher-order 1.029 ms against 0.966 ms.
+template <bool HG>
+struct Sep3Cfg {
+    static constexpr int quads = HG ? 8 : 4;
+    using slot = typename std::conditional<HG, float2, float4>::type;
+};
 
-template <int Q>
+template <bool HG>
 struct Sep3Lds {
-    // [buffer][quad][range][block][lane]: (re, im, re + im, 0)
-    float4 lu[2][Q][k3WX][k3BX][64], lv[2][Q][k3WY][k3BY][64];
+    // [buffer][quad][range][block][lane]
+    typename Sep3Cfg<HG>::slot lu[2][Sep3Cfg<HG>::quads][k3WX][k3BX][64], lv[2][Sep3Cfg<HG>::quads][k3WY][k3BY][64];
 };
 
 // Accumulates beamlets [jb, je) (je > jb) into accR / accI (rows y, columns
 // x) for the wavefront's 64 x 32 pixels of workgroup tile (tx, ty); all
 // threads of the workgroup call it together; it leaves the LDS buffers free.
 // Each pass between barriers takes Q quads of beamlets (Q MFMA K-steps of
-// 4), so the barrier and the LDS round trip are paid once per 24 Q MFMAs;
+// 4, Sep3Cfg), so the barrier and the LDS round trip are paid once per 24 Q
+// MFMAs;
 // while a quad's products run, the lane forms its factors of the same quad
 // of the next pass, whose record fields were loaded two quads earlier.  A
 // quad past je publishes zero U factors and adds nothing.
-template <int Q, bool HG>
+template <bool HG>
 __device__ inline void sep_accumulate_3m(const SepGeom &g, const Rec32 *__restrict__ rec,
                                          const RecHG32 *__restrict__ hg, int64_t jb, int64_t je, int tx, int ty,
-                                         Sep3Lds<Q> &L, f4 (&accR)[k3BY][k3BX], f4 (&accI)[k3BY][k3BX]) {
+                                         Sep3Lds<HG> &L, f4 (&accR)[k3BY][k3BX], f4 (&accI)[k3BY][k3BX]) {
+    constexpr int Q = Sep3Cfg<HG>::quads;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int wx = wv % k3WX, wy = wv / k3WX;
     const int x0 = (tx * k3WX + wx) * 16 * k3BX, y0 = (ty * k3WY + wy) * 16 * k3BY;
@@ -144,8 +159,13 @@ __device__ inline void sep_accumulate_3m(const SepGeom &g, const Rec32 *__restri
             hg_axis(dxf, f.gxr, f.gxi, f.cx0r, f.cx0i, f.cx1, f.cx2, ur, ui);
             hg_axis(dyf, f.gyr, f.gyi, f.cy0r, f.cy0i, f.cy1, f.cy2, vr, vi);
         }
-        lu[buf][qd][wx][wy][lane] = make_float4(ur, ui, ur + ui, 0.0f);
-        lv[buf][qd][wy][wx][lane] = make_float4(vr, vi, vr + vi, 0.0f);
+        if constexpr (HG) {
+            lu[buf][qd][wx][wy][lane] = make_float2(ur, ui);
+            lv[buf][qd][wy][wx][lane] = make_float2(vr, vi);
+        } else {
+            lu[buf][qd][wx][wy][lane] = make_float4(ur, ui, ur + ui, 0.0f);
+            lv[buf][qd][wy][wx][lane] = make_float4(vr, vi, vr + vi, 0.0f);
+        }
     };
 
     f4 a1[k3BY][k3BX], a2[k3BY][k3BX], a3[k3BY][k3BX];
@@ -169,17 +189,23 @@ __device__ inline void sep_accumulate_3m(const SepGeom &g, const Rec32 *__restri
             float ur[k3BX], ui[k3BX], us[k3BX], vr[k3BY], vi[k3BY], vs[k3BY];
 #pragma unroll
             for (int b = 0; b < k3BX; b++) {
-                const float4 u = lu[buf][qd][wx][b][lane];
+                const auto u = lu[buf][qd][wx][b][lane];
                 ur[b] = u.x;
                 ui[b] = u.y;
-                us[b] = u.z;
+                if constexpr (HG)
+                    us[b] = u.x + u.y;
+                else
+                    us[b] = u.z;
             }
 #pragma unroll
             for (int b = 0; b < k3BY; b++) {
-                const float4 v = lv[buf][qd][wy][b][lane];
+                const auto v = lv[buf][qd][wy][b][lane];
                 vr[b] = v.x;
                 vi[b] = v.y;
-                vs[b] = v.z;
+                if constexpr (HG)
+                    vs[b] = v.x + v.y;
+                else
+                    vs[b] = v.z;
             }
             if (more) {
                 publish(fn[qd % 2], buf ^ 1, qd);
