@@ -505,11 +505,11 @@ def hermite(ctx, stream, gauss_ms, n_across=256, npix=512, reps=10):
     return res
 
 
-# Truncated-beamlet kernel (eval_cut_mixed_kernel, 8 rows x 4 wavefronts,
+# Truncated-beamlet kernel (eval_cut_mixed_kernel, 2 rows x 4 wavefronts,
 # Faddeeva function with N = 16): per lane and beamlet, counted in the
-# compiled loop: 839 FP32, 43 FP64, 56 transcendental (exp2, sin, cos twice
-# and one reciprocal per pixel) and 40 other VALU instructions for 8 pixels.
-CUT_MIX = {"fp64": 43 / 8, "fp32": (839 + 40) / 8, "trans": 56 / 8}
+# compiled loop: 215 FP32, 19 FP64, 14 transcendental (exp2, sin, cos twice
+# and one reciprocal per pixel) and 10 other VALU instructions for 2 pixels.
+CUT_MIX = {"fp64": 19 / 2, "fp32": (215 + 10) / 2, "trans": 14 / 2}
 
 
 def truncated(ctx, stream, gauss_ms, n_across=256, npix=512, reps=10):

@@ -120,7 +120,7 @@ static_assert(sizeof(RecCut32) == 32, "RecCut32 layout");
 // N = 40 for FP64 (relative error 2e-14 over the upper half plane), 16 for
 // the mixed form (4e-7 in exact arithmetic, 5e-7 with FP32 rounding).
 constexpr int kFaddeevaN64 = 40, kFaddeevaN32 = 16;
-constexpr int kCutRows32 = 8, kCutRows64 = 4;  // rows per lane of the truncated-beamlet kernels (4 wavefronts)
+constexpr int kCutRows32 = 2, kCutRows64 = 4;  // rows per lane of the truncated-beamlet kernels (4 wavefronts)
 struct FaddeevaCoef {
     double L64, a64[kFaddeevaN64];
     float L32, a32[kFaddeevaN32];
