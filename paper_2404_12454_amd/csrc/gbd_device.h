@@ -435,6 +435,75 @@ __device__ inline float2 hg_factor32(const RecHG32 &h, float gxa_r, float gxa_i,
     return make_float2(re, im);
 }
 
+// FP64 exponentials without the special-case paths a general library exp and
+// sincospi carry (their arguments here are bounded), each within a few units
+// in the last place:
+// exp_cw64(g) = e^g by Cody and Waite's reduction g = n ln 2 + r, ln 2 split
+// into a head of 32 significant bits (n ln2_hi exact for |n| < 2^21) and a
+// tail, |r| <= ln 2 / 2, e^r by its Taylor series to r^12 (truncation below
+// 2e-16 relative), scaled by 2^n; g is clamped at -1100, where the result is
+// zero anyway, so that g = -inf (a masked term) gives 0, not NaN.
+__device__ inline double exp_cw64(double g) {
+    g = fmax(g, -1100.0);
+    const double n = rint(g * 1.4426950408889634);                  // 1 / ln 2
+    double r = fma(-n, 0.6931471806019545, g);                      // ln 2, head
+    r = fma(-n, -4.2009150726810846e-11, r);                         // ln 2, tail
+    double e = 1.0 / 479001600.0;                                    // 1 / 12!
+    e = fma(e, r, 1.0 / 39916800.0);
+    e = fma(e, r, 1.0 / 3628800.0);
+    e = fma(e, r, 1.0 / 362880.0);
+    e = fma(e, r, 1.0 / 40320.0);
+    e = fma(e, r, 1.0 / 5040.0);
+    e = fma(e, r, 1.0 / 720.0);
+    e = fma(e, r, 1.0 / 120.0);
+    e = fma(e, r, 1.0 / 24.0);
+    e = fma(e, r, 1.0 / 6.0);
+    e = fma(e, r, 0.5);
+    e = fma(e, r, 1.0);
+    e = fma(e, r, 1.0);
+    return ldexp(e, (int)n);
+}
+
+// (cos 2 pi T, sin 2 pi T) for T in [-1/2, 1/2] turns: q = round(4 T) quarter
+// turns, r = T - q / 4 in [-1/8, 1/8], theta = 2 pi r in [-pi/4, pi/4], sin and
+// cos of theta by their Taylor series to theta^15 and theta^16 (truncation
+// below 1e-16 relative), then turned by q quarter turns.
+__device__ inline double2 cis_turns64(double T) {
+    const double q = rint(4.0 * T);
+    const double th = (T - 0.25 * q) * 6.283185307179586;           // 2 pi
+    const double z = th * th;
+    double sp = -1.0 / 1307674368000.0;                              // -1 / 15!
+    sp = fma(sp, z, 1.0 / 6227020800.0);
+    sp = fma(sp, z, -1.0 / 39916800.0);
+    sp = fma(sp, z, 1.0 / 362880.0);
+    sp = fma(sp, z, -1.0 / 5040.0);
+    sp = fma(sp, z, 1.0 / 120.0);
+    sp = fma(sp, z, -1.0 / 6.0);
+    const double sn = fma(th * z, sp, th);
+    double cp = 1.0 / 20922789888000.0;                              // 1 / 16!
+    cp = fma(cp, z, -1.0 / 87178291200.0);
+    cp = fma(cp, z, 1.0 / 479001600.0);
+    cp = fma(cp, z, -1.0 / 3628800.0);
+    cp = fma(cp, z, 1.0 / 40320.0);
+    cp = fma(cp, z, -1.0 / 720.0);
+    cp = fma(cp, z, 1.0 / 24.0);
+    cp = fma(cp, z, -0.5);
+    const double cs = fma(z, cp, 1.0);
+    // turn (cs, sn) by q quarter turns: i^q
+    const int qi = (int)q & 3;
+    double c = (qi & 1) ? sn : cs, s = (qi & 1) ? cs : sn;
+    c = (qi == 1 || qi == 2) ? -c : c;
+    s = (qi & 2) ? -s : s;
+    return make_double2(c, s);
+}
+
+// e^g (cos 2 pi T, sin 2 pi T), T in [-1/2, 1/2]
+__device__ inline double2 cexp_turns64(double g, double T) {
+    const double m = exp_cw64(g);
+    const double2 cs = cis_turns64(T);
+    return make_double2(m * cs.x, m * cs.y);
+}
+
 // fused multiply-add in the precision of its arguments
 __device__ inline float fm(float a, float b, float c) { return fmaf(a, b, c); }
 __device__ inline double fm(double a, double b, double c) { return fma(a, b, c); }

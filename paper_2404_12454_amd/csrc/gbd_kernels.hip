@@ -198,7 +198,9 @@ __global__ void __launch_bounds__(64 * WAVES) eval_fp64_kernel(EvalGeom g, const
 // in FP64 throughout (anchor at the lane's middle row h from the FP64 phase
 // and ln-amplitude quadratics, rho and 1/rho from the row slopes, sigma^(k^2)
 // from the FP64 table sigma_kernel fills), so a further row costs two complex
-// FP64 multiply-adds instead of an exp and a sincospi.  HG: higher-order
+// FP64 multiply-adds instead of an exp and a sincospi (the anchor's by
+// exp_cw64 and cis_turns64; the FP64 direct form keeps the device library's,
+// an independent check of them).  HG: higher-order
 // beamlets, each term times the Hermite-Gaussian factor's degree-4 row
 // polynomial (as in the mixed rotor form), records hg.  The anchor is flushed
 // below e^-700 and the ln-amplitude slope capped at +-40 per row: with the
@@ -264,10 +266,9 @@ __global__ void __launch_bounds__(64 * WAVES) eval_fp64_rotor_kernel(EvalGeom g,
             const double ql = r.l[2] + r.l[4] * da;
             const double L0 = r.l[0] + da * (r.l[1] + r.l[3] * da) + db * (ql + r.l[5] * db);
             const double U1 = fmin(fmax(dy * (ql + 2.0 * r.l[5] * db), -40.0), 40.0);
-            const double m0 = L0 < -700.0 ? 0.0 : exp(L0);
-            double s0, c0;
-            sincospi(2.0 * (T0 - rint(T0)), &s0, &c0);
-            const double zr = m0 * c0, zi = m0 * s0;
+            const double m0 = L0 < -700.0 ? 0.0 : exp_cw64(L0);
+            const double2 cs0 = cis_turns64(T0 - rint(T0));
+            const double zr = m0 * cs0.x, zi = m0 * cs0.y;
             [[maybe_unused]] double hq[5][2];
             if constexpr (HG) {
                 hg_row_poly(htile[jj], da, db, dy, hq);
@@ -277,11 +278,10 @@ __global__ void __launch_bounds__(64 * WAVES) eval_fp64_rotor_kernel(EvalGeom g,
                 acc_re[H] += zr;
                 acc_im[H] += zi;
             }
-            const double t1 = T1 - rint(T1);
-            double s1, c1;
-            sincospi(2.0 * t1, &s1, &c1);
+            const double2 cs1 = cis_turns64(T1 - rint(T1));
+            const double c1 = cs1.x, s1 = cs1.y;
             if (ROWS - 1 - H > 0) {
-                const double mu = exp(U1);
+                const double mu = exp_cw64(U1);
                 const double ur = mu * c1, ui = mu * s1;
                 double pr = zr, pi = zi;
 #pragma unroll
@@ -304,7 +304,7 @@ __global__ void __launch_bounds__(64 * WAVES) eval_fp64_rotor_kernel(EvalGeom g,
                 }
             }
             if (H > 0) {
-                const double md = exp(-U1);
+                const double md = exp_cw64(-U1);
                 const double vr = md * c1, vi = -(md * s1);
                 double pr = zr, pi = zi;
 #pragma unroll

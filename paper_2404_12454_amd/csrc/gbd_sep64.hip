@@ -5,9 +5,10 @@
 //   V_j(b) = e^(l2 db + l5 db^2)      e^(2 pi i (p2 db + p5 db^2)),
 // a complex matrix product over the beamlet index on FP64 MFMA
 // (v_mfma_f64_16x16x4_f64, FP64 products and sums).  Each factor is the FP64
-// form's phasor (phase reduced to turns, the device library's exp and
-// sincospi), so every beamlet-pixel term is the same product as in the other
-// FP64 forms; only the order of the sum changes.  Higher-order beamlets
+// form's phasor (phase reduced to turns; exp and the turn-phase sine and
+// cosine by cexp_turns64, within a few units in the last place of the device
+// library's exp and sincospi), so every beamlet-pixel term is the same
+// product as in the other FP64 forms up to rounding.  Higher-order beamlets
 // without cross terms fold their per-axis Hermite-Gaussian polynomial into U
 // and V.
 //
@@ -99,10 +100,7 @@ __device__ inline double2 hg_axis64(double2 u, double d, double gr0, double gi0,
 __device__ inline double2 factor64(double d, double c0, double c1, double c2, double g0, double g1, double g2) {
     double T = c0 + d * (c1 + c2 * d);
     T -= rint(T);
-    double s, c;
-    sincospi(2.0 * T, &s, &c);
-    const double m = exp(g0 + d * (g1 + g2 * d));
-    return make_double2(m * c, m * s);
+    return cexp_turns64(g0 + d * (g1 + g2 * d), T);
 }
 
 struct Lds64 {
