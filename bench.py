@@ -258,7 +258,7 @@ def fp64_record(shape, N, M, ms, mixed_ms):
     the rotor form (the automatic one otherwise, on well-sampled grids)
     against its instruction mix: per further row two complex FP64
     multiply-adds (8 FP64), per lane and beamlet 107 FP64 (anchor exp and
-    sincospi, rho, 1/rho) and 70 other VALU instructions, counted in the
+    sine/cosine, rho, 1/rho) and 36 other VALU instructions, counted in the
     compiled loop at 32 rows."""
     r = {"value": N * M / (ms * 1e-3), "eval_ms": ms, "launch": shape, "speedup_mixed_over_fp64": ms / mixed_ms}
     if shape["variant"] == 4:
@@ -267,7 +267,7 @@ def fp64_record(shape, N, M, ms, mixed_ms):
                   "roofline_frac": achieved / MFMA_FP64_TFLOPS})
     if shape["variant"] == 3:
         R = float(shape["rows_per_lane"])
-        mix = {"fp64": (8 * R + 107) / R, "fp32": 70 / R}
+        mix = {"fp64": (8 * R + 107) / R, "fp32": 36 / R}
         peak = CUS * CLOCK_HZ / sum(n / RATE[k] for k, n in mix.items())
         r.update({"roofline_peak": peak, "roofline_frac": r["value"] / peak, "instructions_per_pair": mix})
     return r
