@@ -221,8 +221,10 @@ int gbd_eval(gbd_ctx_t ctx, gbd_beamlets_t b, gbd_plane_t p, int precision, void
  * gbd_plan_create allocates device records for up to `capacity` beamlets;
  * gbd_plan_setup runs the FP64 per-beamlet kernel (Q-law, eigenvalue-branch
  * amplitude, base ray, hit point on the plane, phasor coefficients) and
- * synchronises on its status; gbd_plan_eval runs only the N x M kernels and
- * does not synchronise. */
+ * synchronises on its status; gbd_plan_eval runs the N x M kernels (before a
+ * rotor form also a small kernel that fills the form's sigma^(k^2) tables in
+ * the plan's records) and does not synchronise.  A plan's calls are ordered
+ * on the context stream; calls on one plan must not overlap from two streams. */
 int gbd_plan_create(gbd_ctx_t ctx, gbd_plan_t *out, int64_t capacity);
 int gbd_plan_setup(gbd_ctx_t ctx, gbd_plan_t plan, gbd_beamlets_t b, gbd_plane_t p);
 int gbd_plan_eval(gbd_ctx_t ctx, gbd_plan_t plan, int precision, void *field_out, int64_t out_bytes,
