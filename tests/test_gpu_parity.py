@@ -197,6 +197,24 @@ def test_reported_shape_is_accepted_back(ctx, precision):
     assert e.value.code == -1
 
 
+@pytest.mark.parametrize("precision", BOTH)
+def test_rotor_tables_follow_the_plane(ctx, precision):
+    """The rotor forms' sigma^(k^2) tables depend on the plane's row pitch and
+    are filled at evaluation: one plan set up in turn on planes of different
+    pitch (and the same plane again) gives the oracle's field each time."""
+    import torch
+    plan = None
+    for span in (30e-6, 45e-6, 20e-6, 30e-6):
+        sc = scenes.zernike_scene(9, n_across=12, npix=72, half_span=span)
+        b, p = gbd.beamlets_from_scene(ctx, sc), gbd.plane_from_scene(ctx, sc)
+        plan = plan or gbd.Plan(ctx, sc.n)
+        plan.setup(b, p)
+        assert plan.shape(precision, dict(variant=3))["variant"] == 3
+        E = plan.eval(precision, opts=dict(variant=3))
+        torch.cuda.synchronize()
+        check(E.cpu().numpy(), oracle.eval_field(sc), precision, f"rotor after re-setup, half span {span}")
+
+
 def test_cross_terms_rule_out_the_separable_form(ctx):
     sc = scenes.zernike_scene(7, n_across=12, npix=40, half_span=30e-6)
     plan = gbd.Plan(ctx, sc.n).setup(gbd.beamlets_from_scene(ctx, sc), gbd.plane_from_scene(ctx, sc))
