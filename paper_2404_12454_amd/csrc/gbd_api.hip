@@ -264,6 +264,11 @@ Shape choose_shape(const gbd_ctx_s *ctx, int precision, int64_t n, const PlaneGe
             auto it = ctx->tuned.find(tune_key(kTuneSep, precision, n, (int64_t)pl.nx * pl.ny));
             if (it != ctx->tuned.end()) seg = std::max<int64_t>(1, seg * it->second.seg_scale_pct / 100);
             seg = std::min<int64_t>(seg, std::max<int64_t>(1, n / 256));
+            // the MFMA accumulators sum a segment in plain FP32: its error grows
+            // with the segment's length (823,592 beamlets on 64^2 pixels: 1.6e-7
+            // at 3,217 per segment, 6.1e-7 at 12,868, 3.4e-6 at 51,474, 1.4e-5
+            // at 205,898), so mixed-precision segments hold at most 16,384
+            if (mixed) seg = std::max<int64_t>(seg, (n + kSepMaxSegLen - 1) / kSepMaxSegLen);
             s.nseg = (int)std::max<int64_t>(1, std::min<int64_t>(seg, 1024));
         }
         return s;

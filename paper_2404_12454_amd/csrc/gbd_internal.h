@@ -313,6 +313,7 @@ inline size_t reduce_wide_offset(int32_t nseg2, int64_t M) { return ((size_t)nse
 // CU at the register and LDS budget).
 constexpr int kSepWavesX = 2, kSepWavesY = 4;
 constexpr int kSepTileX = 64, kSepTileY = 32;
+constexpr int64_t kSepMaxSegLen = 16384;  // beamlets per FP32 segment at most (automatic segment count)
 // The FP64 separable form on FP64 MFMA: wavefront tiles of 64 x 32 pixels
 // (kSepRows64 rows), kSep64WavesX x kSep64WavesY wavefronts per workgroup
 // (128 x 128 pixels, one workgroup per CU); double2 partials.

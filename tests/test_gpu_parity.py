@@ -215,6 +215,26 @@ def test_rotor_tables_follow_the_plane(ctx, precision):
         check(E.cpu().numpy(), oracle.eval_field(sc), precision, f"rotor after re-setup, half span {span}")
 
 
+def test_separable_form_long_segments_are_split(ctx):
+    """823,592 beamlets (1024 across) on 512 x 512 pixels: occupancy alone
+    would give 16 segments of 51,474 beamlets summed in FP32; the automatic
+    count keeps segments at most 16,384 long, and the field stays within the
+    mixed tolerance at sampled pixels."""
+    sc = scenes.airy_scene(1024, npix=512, half_span_lamF=20.0)
+    b, p = gbd.beamlets_from_scene(ctx, sc), gbd.plane_from_scene(ctx, sc)
+    plan = gbd.Plan(ctx, sc.n).setup(b, p)
+    shape = plan.shape(gbd.GBD_MIXED)
+    assert shape["variant"] == 4 and shape["segments"] >= -(-sc.n // 16384)
+    E = plan.eval(gbd.GBD_MIXED).cpu().numpy().astype(np.complex128)
+    rng = np.random.default_rng(8)
+    ix = rng.integers(0, 512, 60).astype(np.int32)
+    iy = rng.integers(0, 512, 60).astype(np.int32)
+    ref = oracle.eval_field(sc, pixels=(ix, iy))
+    err = rel_l2(E[iy, ix], ref)
+    print(f"1024 across ({sc.n} beamlets), {shape['segments']} segments: rel_l2 {err:.2e}", flush=True)
+    assert err < 1e-5
+
+
 def test_cross_terms_rule_out_the_separable_form(ctx):
     sc = scenes.zernike_scene(7, n_across=12, npix=40, half_span=30e-6)
     plan = gbd.Plan(ctx, sc.n).setup(gbd.beamlets_from_scene(ctx, sc), gbd.plane_from_scene(ctx, sc))
