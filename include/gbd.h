@@ -297,7 +297,9 @@ int gbd_airy(gbd_ctx_t ctx, gbd_plane_t p, double D, double f, double lambda, fl
  * gbd_eval for the other forms (segments is ignored; default 32 x 4 for the
  * rotor form, else 16 x 4, or the autotuner's choice).  Every item sums all
  * of its instance's beamlets, so a field equals gbd_eval's with the same
- * form and shape and one segment, bit for bit.
+ * form and shape and one segment, bit for bit; in the separable form that is
+ * one plain FP32 sum per pixel, whose error grows with the instance's beamlet
+ * count (about 6e-7 at 13k beamlets, 1e-5 at 200k; gbd_eval splits long sums).
  * Synchronises the context stream (setup status, then metrics). */
 int gbd_eval_batch(gbd_ctx_t ctx, int32_t n_inst, const gbd_beamlets_t *beamlets, const gbd_plane_t *planes,
                    const float *airy, int64_t airy_bytes, const double *zone_edges, int32_t n_zones,
