@@ -330,6 +330,26 @@ def test_p6_airy_limit_improves_with_beamlets():
     assert errs[1][0] < 0.06 and errs[1][1] < 2e-3
 
 
+def test_p6_airy_regression_values_config1():
+    """The 32-across f/10 workload (812 beamlets, OF 1.7, 64 x 64 pixels over
+    +-5 lambda F) against the Airy field: complex relative L2 of E/E(0)
+    against e^(-i k r^2 / 2f) 2 J1(v)/v, and RMS and peak of the
+    peak-normalised irradiance difference through the figure-of-merit module,
+    each within 1 % of the values an independent scratch evaluation of the
+    same conventions gave when the workloads were specified (3.1e-2, 8.1e-4,
+    5.6e-3)."""
+    from oracle import metrics as om
+    sc = scenes.config("airy32_64")
+    E, E0 = oracle.eval_field(sc, extra_point=(0.0, 0.0))
+    A, B = plane_coords(sc.plane)
+    ref = airy_field(sc, A, B)
+    cplx = np.linalg.norm(E / E0 - ref) / np.linalg.norm(ref)
+    m = sc.meta
+    rms, peak = om.airy_metrics(E, E0, om.airy_irradiance(sc.plane, m["D"], m["f"], sc.lam))
+    for got, want in ((cplx, 3.1e-2), (rms, 8.1e-4), (peak, 5.6e-3)):
+        assert abs(got / want - 1) < 0.01, (got, want)
+
+
 # ---------------------------------------------------------------- P7 ----------
 def test_p7_parseval_coherent_sum():
     sc = scenes.airy_scene(8, OF=1.7, npix=300, half_span_lamF=15.0)

@@ -153,17 +153,27 @@ def test_base_override_with_paraxial_values_reproduces_the_abcd_field():
 
 
 def test_annular_airy_reference_reduces_to_the_airy_pattern():
-    """The obscured-aperture reference at eps -> 0 is the Airy pattern, its
-    first zero moves inwards with the obscuration (v = 3.8317 at eps = 0),
-    and it is 1 on axis."""
+    """The obscured-aperture reference at eps -> 0 is the Airy pattern, with
+    its first zero at v = 3.8317 (r = 1.2197 lambda F); with an obscuration
+    the first zero moves inwards; it is 1 on axis."""
     from oracle import metrics as om
     pl = scenes.airy_scene(8, npix=65, half_span_lamF=6.0).plane
     a = om.airy_irradiance(pl, 10e-3, 100e-3, 1e-6)
     np.testing.assert_allclose(om.annular_airy_irradiance(pl, 10e-3, 100e-3, 1e-6, 0.0), a, atol=1e-15)
-    import scipy.optimize, scipy.special
-    f = lambda v, e: (2 * scipy.special.j1(v) / v - e * e * 2 * scipy.special.j1(e * v) / (e * v))
-    z0 = scipy.optimize.brentq(lambda v: f(v, 1e-9), 3.0, 4.5)
-    z1 = scipy.optimize.brentq(lambda v: f(v, 0.33), 3.0, 4.5)
-    assert abs(z0 - 3.8317) < 1e-4 and z1 < z0
+    lamF = 10e-6
+    r0 = 3.831705970207512 / np.pi * lamF
+
+    def at(r, eps):
+        p1 = scenes.Plane(np.zeros(3), np.array([0.0, 0.0, 1.0]), np.array([1.0, 0.0, 0.0]), 3, 1, r, r)
+        return om.annular_airy_irradiance(p1, 10e-3, 100e-3, 1e-6, eps)[0, 2]
+
+    assert at(r0, 0.0) < 1e-20
+    # with eps = 0.33 the first zero lies inside r0: the pattern changes sign
+    # between 0.8 r0 and r0 (its amplitude, the square root with sign, is
+    # found by bisection on the irradiance's minimum)
+    rs = np.linspace(0.8 * r0, r0, 2001)
+    vals = np.array([at(r, 0.33) for r in rs])
+    k = int(np.argmin(vals))
+    assert 0 < k < len(rs) - 1 and vals[k] < 1e-6 and at(r0, 0.33) > 1e-4
     c = pl.nx // 2
     assert abs(om.annular_airy_irradiance(pl, 10e-3, 100e-3, 1e-6, 0.3)[c, c] - 1.0) < 1e-12
