@@ -63,7 +63,10 @@ typedef struct {
                                (32: rotor form only, runs 16 where the form resolves to
                                direct or stepped; the FP64 direct form runs at most 8) */
     int32_t waves;          /* wavefronts per workgroup: 1, 2 or 4 */
-    int32_t segments;       /* beamlet segments evaluated by separate workgroups, 0 = auto */
+    int32_t segments;       /* beamlet segments evaluated by separate workgroups, 0 = auto.
+                               The mixed separable form sums a segment in plain FP32, so
+                               it raises any count (automatic, tuned or explicit) to at
+                               least ceil(N / 16384): at most 16,384 beamlets per FP32 sum */
     int32_t variant;        /* 0 = auto.  FP64: 1 = direct (exp and sincospi per pixel), 3 =
                                rotor (the recurrence below in FP64; well-sampled grids; at
                                most 16 rows with higher-order beamlets), 4 = separable (below, on FP64
@@ -100,7 +103,7 @@ void gbd_ctx_destroy(gbd_ctx_t ctx);
 /* Thread-local description of the last failure in this thread. */
 const char *gbd_last_error(void);
 
-/* --- a1: pupil decomposition (Sec. 2.2 beamlet decomposition, Sec. 6 OF) --
+/* --- pupil decomposition (Sec. 2.2 beamlet decomposition, Sec. 6 OF) ------
  * n beamlets; lambda > 0 (m); l0 = axial length of the ABCD system (m),
  * the axial propagation distance of the Collins integral (Sec. 2.1).
  *   r1   [n][2]        beamlet centres in the input plane (required)
@@ -205,13 +208,18 @@ int gbd_plane(gbd_ctx_t ctx, gbd_plane_t *out, const double origin[3], const dou
               const double xhint[3], int32_t nx, int32_t ny, double dx, double dy);
 void gbd_plane_free(gbd_plane_t p);
 
-/* --- a4/a5: field evaluation ----------------------------------------------
+/* --- field evaluation (Sec. 3 plane evaluation, Sec. 1 coherent sum) -----
  * field_out: device pointer to [ny][nx] interleaved complex: complex128 for
  * GBD_FP64 (all-FP64 arithmetic), complex64 for GBD_MIXED (FP64 phase and
- * coordinates, FP32 exp2/sin/cos, FP32 compensated accumulation).
+ * coordinates, FP32 exp2/sin/cos; FP32 sums per beamlet segment, added in
+ * FP64 across segments: Kahan-compensated in the direct and stepped forms
+ * and in the rotor form up to 16 rows per lane, 128-beamlet tile sums added
+ * plainly in the rotor form at 32 rows, a plain FP32 MFMA sum of at most
+ * 16,384 beamlets in the separable form).
  * out_bytes: size of field_out in bytes (GBD_ERANGE if too small).
- * Runs the per-beamlet setup (a2/a3) and the N x M evaluation on the
- * context stream.  Plane-dependent checks (GBD_EPARALLEL, GBD_EBRANCH) are
+ * Runs the per-beamlet setup (propagation, plane transfer) and the N x M
+ * evaluation on the context stream.  Plane-dependent checks (GBD_EPARALLEL,
+ * GBD_EBRANCH) are
  * made by the setup kernel; this call synchronises on them before launching
  * the evaluation, so a failing call leaves field_out untouched. */
 int gbd_eval(gbd_ctx_t ctx, gbd_beamlets_t b, gbd_plane_t p, int precision, void *field_out,
@@ -269,7 +277,7 @@ int gbd_autotune_load(gbd_ctx_t ctx, const char *path);
  * principal branch. */
 int gbd_eval_point(gbd_ctx_t ctx, gbd_beamlets_t b, gbd_plane_t p, void *field_out, int64_t out_bytes);
 
-/* --- a6: analytic reference irradiance ------------------------------------
+/* --- analytic reference irradiance ----------------------------------------
  * out[iy][ix] = (2 J1(v)/v)^2 with v = pi D r / (lambda f), r the distance of
  * the pixel from the plane origin: the Airy pattern of an unobscured circular
  * pupil of diameter D focused at focal length f, normalised to 1 on axis (the
@@ -277,7 +285,7 @@ int gbd_eval_point(gbd_ctx_t ctx, gbd_beamlets_t b, gbd_plane_t p, void *field_o
  * evaluation, FP32 device output; out_bytes >= 4 nx ny. */
 int gbd_airy(gbd_ctx_t ctx, gbd_plane_t p, double D, double f, double lambda, float *out, int64_t out_bytes);
 
-/* --- a7: batched parameter sweep (Sec. 6) ----------------------------------
+/* --- batched parameter sweep (Sec. 6) --------------------------------------
  * Evaluates n_inst independent instances (beamlets[i] on planes[i], mixed
  * precision) in one persistent launch whose workgroups pull (instance, pixel
  * tile) items, largest instances first, from an atomic queue.
@@ -297,15 +305,17 @@ int gbd_airy(gbd_ctx_t ctx, gbd_plane_t p, double D, double f, double lambda, fl
  * gbd_eval for the other forms (segments is ignored; default 32 x 4 for the
  * rotor form, else 16 x 4, or the autotuner's choice).  Every item sums all
  * of its instance's beamlets, so a field equals gbd_eval's with the same
- * form and shape and one segment, bit for bit; in the separable form that is
- * one plain FP32 sum per pixel, whose error grows with the instance's beamlet
- * count (about 6e-7 at 13k beamlets, 1e-5 at 200k; gbd_eval splits long sums).
+ * form and shape and one segment, bit for bit.  In the separable form that
+ * is one plain FP32 sum per pixel, whose error grows with the instance's
+ * beamlet count, so the separable form applies (auto or requested) only when
+ * no instance has more than 16,384 beamlets, the longest FP32 sum gbd_eval
+ * allows; otherwise the batch resolves as auto among the other forms.
  * Synchronises the context stream (setup status, then metrics). */
 int gbd_eval_batch(gbd_ctx_t ctx, int32_t n_inst, const gbd_beamlets_t *beamlets, const gbd_plane_t *planes,
                    const float *airy, int64_t airy_bytes, const double *zone_edges, int32_t n_zones,
                    double *metrics_out, void *fields_out, int64_t fields_bytes, const gbd_eval_opts *opts);
 
-/* --- a8: surrogate network --------------------------------------------------
+/* --- surrogate network ------------------------------------------------------
  * A multilayer perceptron n_in -> width (SiLU) x depth -> 1 trained with AdamW
  * on the mean squared error (the figure of merit of Sec. 6 as a function of
  * the decomposition's free parameters).  Parameters are one flat FP32 vector:

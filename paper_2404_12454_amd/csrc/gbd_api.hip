@@ -249,6 +249,12 @@ Shape choose_shape(const gbd_ctx_s *ctx, int precision, int64_t n, const PlaneGe
         s.rows = mixed ? kSepTileY : kSepRows64;
         s.waves = kSepWavesX * wy;
         s.nseg = (o && o->segments > 0) ? o->segments : 0;
+        // the MFMA accumulators sum a segment in plain FP32: its error grows
+        // with the segment's length (823,592 beamlets on 64^2 pixels: 1.6e-7
+        // at 3,217 per segment, 6.1e-7 at 12,868, 3.4e-6 at 51,474, 1.4e-5
+        // at 205,898), so mixed-precision segments hold at most 16,384
+        // beamlets, whatever the count's source (automatic, tuned or explicit)
+        const int64_t min_seg = mixed ? (n + kSepMaxSegLen - 1) / kSepMaxSegLen : 1;
         if (s.nseg <= 0) {
             // one round of workgroups, 8 wavefronts per CU (the register
             // budget allows two wavefronts per SIMD; a partial second round
@@ -264,13 +270,10 @@ Shape choose_shape(const gbd_ctx_s *ctx, int precision, int64_t n, const PlaneGe
             auto it = ctx->tuned.find(tune_key(kTuneSep, precision, n, (int64_t)pl.nx * pl.ny));
             if (it != ctx->tuned.end()) seg = std::max<int64_t>(1, seg * it->second.seg_scale_pct / 100);
             seg = std::min<int64_t>(seg, std::max<int64_t>(1, n / 256));
-            // the MFMA accumulators sum a segment in plain FP32: its error grows
-            // with the segment's length (823,592 beamlets on 64^2 pixels: 1.6e-7
-            // at 3,217 per segment, 6.1e-7 at 12,868, 3.4e-6 at 51,474, 1.4e-5
-            // at 205,898), so mixed-precision segments hold at most 16,384
-            if (mixed) seg = std::max<int64_t>(seg, (n + kSepMaxSegLen - 1) / kSepMaxSegLen);
             s.nseg = (int)std::max<int64_t>(1, std::min<int64_t>(seg, 1024));
         }
+        // the cap wins over the 1024-segment limit (above 16.7 M beamlets)
+        if (s.nseg < min_seg) s.nseg = (int)std::min<int64_t>(min_seg, 0x7fffffff);
         return s;
     }
     // rotor form: 32 rows per lane where the grid fills a 4-wave tile
@@ -1104,12 +1107,13 @@ int gbd_eval_batch(gbd_ctx_t ctx, int32_t n_inst, const gbd_beamlets_t *bs, cons
     if (airy && !metrics_out) return fail(GBD_EINVAL, "metrics_out is NULL");
     if (opts && (opts->variant < 0 || opts->variant > 4)) return fail(GBD_EINVAL, "variant must be 0 ... 4");
     int rows = 32, waves = 4;  // 32 rows: rotor form; 16 where the form resolves otherwise
-    int64_t pairs = 0;
+    int64_t pairs = 0, n_max = 0;
     for (int32_t i = 0; i < n_inst; i++) {
         if (!bs[i] || !ps[i]) return fail(GBD_EINVAL, "instance %d has a NULL handle", i);
         if (bs[i]->higher_order || bs[i]->dev.n_cut > 0)
             return fail(GBD_EINVAL, "instance %d: the batched sweep takes whole fundamental Gaussian beamlets only", i);
         pairs += bs[i]->dev.n * ((int64_t)ps[i]->g.nx * ps[i]->g.ny);
+        n_max = std::max<int64_t>(n_max, bs[i]->dev.n);
     }
     if (!(opts && (opts->rows_per_lane || opts->waves))) {
         auto it = ctx->tuned.find(tune_key(kTuneBatch, GBD_MIXED, pairs, n_inst));
@@ -1188,7 +1192,11 @@ int gbd_eval_batch(gbd_ctx_t ctx, int32_t n_inst, const gbd_beamlets_t *bs, cons
     if (stat & FLAG_PARALLEL) return fail(GBD_EPARALLEL, "instance %d: a base ray is parallel to the plane", bad);
     if (stat & FLAG_BRANCH) return fail(GBD_EBRANCH, "instance %d: an eigenvalue left the principal branch", bad);
     if (stat & FLAG_NONFINITE) return fail(GBD_EINVAL, "instance %d: non-finite beamlet parameters", bad);
-    const int form = pick_form(GBD_MIXED, stat, opts);
+    // an item sums all of its instance's beamlets; the separable form does so
+    // in one plain FP32 sum per pixel, so it applies only while every
+    // instance fits one segment of the single evaluation (kSepMaxSegLen);
+    // the rotor form folds 128-beamlet tile sums and stays accurate at any N
+    const int form = pick_form(GBD_MIXED, stat, opts, n_max <= kSepMaxSegLen);
     if (rows == 32 && form != 2) rows = 16;  // 32 rows is a rotor-form shape
 
     // evaluation tables; the work list takes instances largest first (LPT),

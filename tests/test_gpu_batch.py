@@ -64,6 +64,31 @@ def test_batch_fields_bitwise_equal_single_instance(ctx):
             assert torch.equal(F.cpu().view(torch.float32), E.cpu().view(torch.float32)), o
 
 
+def test_batch_long_instance_leaves_the_separable_form(ctx):
+    """An instance above 16,384 beamlets (160 across: one FP32 MFMA sum would
+    exceed the longest the single evaluation allows) sends the batch to the
+    rotor form, whose fields equal gbd_eval's rotor form with one segment bit
+    for bit and meet the mixed tolerance against the oracle; a request for the
+    separable form resolves the same way."""
+    import torch
+    big = sweep_scene(160, 1.7, 1.0, npix=64, npix_y=48, span=6.0)
+    small = sweep_scene(24, 1.5, 1.0, npix=64, npix_y=48, span=6.0)
+    assert big.n > 16384
+    bs = [gbd.beamlets_from_scene(ctx, s) for s in (big, small)]
+    ps = [gbd.plane_from_scene(ctx, s) for s in (big, small)]
+    for req in (None, dict(variant=4)):
+        _, fields = gbd.gbd_eval_batch(ctx, bs, ps, fields=True, opts=req)
+        for s, b, p, F in zip((big, small), bs, ps, fields):
+            E = gbd.gbd_eval(ctx, b, p, gbd.GBD_MIXED, opts=dict(rows_per_lane=32, waves=4, segments=1, variant=3))
+            torch.cuda.synchronize()
+            assert torch.equal(F.cpu().view(torch.float32), E.cpu().view(torch.float32)), (s.n, req)
+        got = fields[0].cpu().numpy().astype(np.complex128)
+        ref = oracle.eval_field(big)
+        err = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+        print(f"batch instance of {big.n} beamlets, request {req}: rel_l2 {err:.2e}", flush=True)
+        assert err <= 1e-5
+
+
 def test_batch_metrics_match_oracle(ctx):
     import torch
     insts = small_instances()
@@ -81,6 +106,37 @@ def test_batch_metrics_match_oracle(ctx):
         want = om.airy_metrics(E, E0, ref_airy, radius, edges)
         print(s.meta["n_across"], s.meta["OF"], s.meta["q"], got, want, flush=True)
         np.testing.assert_allclose(got, want, rtol=2e-4, atol=1e-9)
+
+
+def test_sweep_instances_full_size_match_oracle(ctx):
+    """One instance of the 441-instance sweep per beamlet count (208 ...
+    12,892 beamlets), each at its full 256 x 256 grid over +-8 lambda F,
+    batched as in the sweep (separable form, one FP32 sum per pixel): every
+    field pixel within the mixed tolerance of the oracle, and the metrics
+    (peak-normalised irradiance, RMS and peak against the Airy pattern)
+    within 1e-5 absolute of the oracle's."""
+    import torch
+    picks = [(1.5, 1.0, 16), (1.75, 0.75, 24), (2.0, 1.25, 32), (1.25, 1.5, 48), (2.5, 0.5, 64), (2.25, 0.75, 96),
+             (1.75, 1.0, 128)]
+    grid = {tuple(g) for g in scenes.sweep_grid()}
+    assert all(p in grid for p in picks)
+    insts = [sweep_scene(na, of, q) for of, q, na in picks]
+    assert [s.n for s in insts] == [208, 448, 812, 1804, 3228, 7232, 12892]
+    bs = [gbd.beamlets_from_scene(ctx, s) for s in insts]
+    ps = [gbd.plane_from_scene(ctx, s) for s in insts]
+    m0 = insts[0].meta
+    airy = gbd.gbd_airy(ctx, ps[0], m0["D"], m0["f"], insts[0].lam)
+    metrics, fields = gbd.gbd_eval_batch(ctx, bs, ps, airy=airy, fields=True)
+    torch.cuda.synchronize()
+    ref_airy = om.airy_irradiance(insts[0].plane, m0["D"], m0["f"], insts[0].lam)
+    for s, got, F in zip(insts, metrics, fields):
+        E, E0 = oracle.eval_field(s, extra_point=(0.0, 0.0))
+        e = F.cpu().numpy().astype(np.complex128)
+        err = float(np.linalg.norm(e - E) / np.linalg.norm(E))
+        want = om.airy_metrics(E, E0, ref_airy)
+        print(f"sweep instance {s.n} beamlets: field rel_l2 {err:.2e}, metrics {got} oracle {want}", flush=True)
+        assert err <= 1e-5
+        assert np.abs(got - want).max() <= 1e-5
 
 
 def test_full_sweep_matches_single_instances(ctx):

@@ -235,6 +235,24 @@ def test_separable_form_long_segments_are_split(ctx):
     assert err < 1e-5
 
 
+@pytest.mark.parametrize("segments", [1, 5])
+def test_separable_explicit_segments_respect_the_fp32_cap(ctx, segments):
+    """An explicit segment count that would put more than 16,384 beamlets in
+    one FP32 MFMA sum is raised to ceil(N / 16384): 512 across (205,898
+    beamlets, 1.4e-5 in one plain FP32 sum) on a 48 x 40 grid, full grid
+    against the oracle."""
+    sc = scenes.airy_scene(512, npix=48, npix_y=40, half_span_lamF=6.0)
+    b, p = gbd.beamlets_from_scene(ctx, sc), gbd.plane_from_scene(ctx, sc)
+    plan = gbd.Plan(ctx, sc.n).setup(b, p)
+    o = dict(segments=segments)
+    shape = plan.shape(gbd.GBD_MIXED, opts=o)
+    floor = -(-sc.n // 16384)
+    assert shape["variant"] == 4 and shape["segments"] >= floor, shape
+    assert -(-sc.n // shape["segments"]) <= 16384
+    E = plan.eval(gbd.GBD_MIXED, opts=o).cpu().numpy()
+    check(E, oracle.eval_field(sc), gbd.GBD_MIXED, f"512 across, segments {segments} -> {shape['segments']}")
+
+
 def test_cross_terms_rule_out_the_separable_form(ctx):
     sc = scenes.zernike_scene(7, n_across=12, npix=40, half_span=30e-6)
     plan = gbd.Plan(ctx, sc.n).setup(gbd.beamlets_from_scene(ctx, sc), gbd.plane_from_scene(ctx, sc))
@@ -328,14 +346,32 @@ def test_airy256_512_full_size_sampled(ctx, precision):
     assert np.abs(E - E[::-1, :]).max() <= 4 * TOL[precision] * scale
 
 
+_ZERN_REF = {}
+
+
+def zern_dense_reference(sc):
+    """The oracle on every 8th pixel row of the 1024 x 1024 tilted plane
+    (131,072 pixels x 12,892 beamlets), computed once for both precisions."""
+    if "ref" not in _ZERN_REF:
+        rows = np.arange(0, sc.plane.ny, 8)
+        iy, ix = np.meshgrid(rows, np.arange(sc.plane.nx), indexing="ij")
+        ix, iy = ix.ravel().astype(np.int32), iy.ravel().astype(np.int32)
+        _ZERN_REF["ref"] = (ix, iy, oracle.eval_field(sc, pixels=(ix, iy)))
+    return _ZERN_REF["ref"]
+
+
 @pytest.mark.parametrize("precision", BOTH)
 def test_zern128_1024_full_size_sampled(ctx, precision):
-    """12,892 aberrated beamlets on a 1024 x 1024 tilted plane."""
+    """12,892 aberrated beamlets on a 1024 x 1024 tilted plane in the
+    benchmark's launch shape: random pixels and every 8th row against the
+    oracle."""
     sc = scenes.config("zern128_1024")
     E = run(ctx, sc, precision)
     ix, iy = sample_pixels(1024, 1024, 200, 2)
     ref = oracle.eval_field(sc, pixels=(ix, iy))
     check(E[iy, ix], ref, precision, "zern128_1024 sampled")
+    ix, iy, ref = zern_dense_reference(sc)
+    check(E[iy, ix], ref, precision, "zern128_1024 every 8th row")
     assert np.isfinite(E).all()
 
 
