@@ -239,6 +239,31 @@ int gbd_plan_eval(gbd_ctx_t ctx, gbd_plan_t plan, int precision, void *field_out
                   const gbd_eval_opts *opts);
 void gbd_plan_free(gbd_plan_t plan);
 
+/* --- allocation-free evaluation ---------------------------------------------
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.
+ * gbd_plan_eval_noalloc is gbd_plan_eval (same arguments, same kernels)
+ * with its segment partial sums in a static device buffer of
+ * GBD_NOALLOC_SCRATCH_BYTES (64 MiB) instead of a buffer the plan grows; it
+ * calls no hipMalloc, hipFree or other allocating routine (an empty plan's
+ * output is cleared by a kernel, not a memset).  Every GPU the library runs
+ * on holds its own buffer from the first gbd_ctx_create on that device until
+ * the process ends.  Launch shape: gbd_plan_eval's, except that an automatic
+ * segment count (built-in or tuned) is lowered to the largest whose partial
+ * sums fit the buffer (truncated beamlets' segments within half of it; the
+ * mixed separable form's floor of ceil(N / 16384) kept); with the same
+ * resolved shape the field equals gbd_plan_eval's bit for bit.  GBD_ERANGE,
+ * before any launch: an explicit opts->segments whose partials do not fit,
+ * or a workload whose fewest allowed segments do not (partials take
+ * 8 bytes per pixel and segment in the mixed separable form, 16 otherwise;
+ * one segment without truncated beamlets takes none).  All calls on one GPU
+ * share its buffer, which keeps the last call's contents (every partial is
+ * written before it is read): calls that overlap in time on one GPU, from two
+ * streams, threads or contexts, race; calls ordered on one stream do not. */
+#define GBD_NOALLOC_SCRATCH_BYTES (64ll << 20)
+int gbd_plan_eval_noalloc(gbd_ctx_t ctx, gbd_plan_t plan, int precision, void *field_out, int64_t out_bytes,
+                          const gbd_eval_opts *opts);
+
 /* Number of beamlet segments (and launch shape) gbd_plan_eval would use. */
 int gbd_plan_shape(gbd_ctx_t ctx, gbd_plan_t plan, int precision, const gbd_eval_opts *opts,
                    gbd_eval_opts *resolved);

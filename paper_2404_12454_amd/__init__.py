@@ -22,7 +22,7 @@ import numpy as np
 __all__ = [
     "GBD_FP64", "GBD_MIXED", "GbdError", "gbd_eval_opts", "library_path", "load_library",
     "gbd_ctx_create", "gbd_beamlets", "gbd_plane", "gbd_eval", "gbd_plan_create", "gbd_plan_setup",
-    "gbd_plan_eval", "gbd_plan_shape", "gbd_airy", "gbd_eval_batch", "gbd_eval_point", "gbd_autotune", "gbd_autotune_batch",
+    "gbd_plan_eval", "gbd_plan_eval_noalloc", "gbd_plan_shape", "gbd_airy", "gbd_eval_batch", "gbd_eval_point", "gbd_autotune", "gbd_autotune_batch",
     "gbd_autotune_save", "gbd_autotune_load", "GBD_MLP_FP32", "GBD_MLP_BF16", "Mlp", "gbd_mlp_create", "beamlets_from_scene", "plane_from_scene",
     "gbd_trace", "gbd_beamlets_traced", "gbd_beamlets_hg", "gbd_beamlets_truncated",
     "Context", "Beamlets", "Plane", "Plan",
@@ -82,6 +82,7 @@ def load_library():
         "gbd_plan_create": (ctypes.c_int, [P, PP, I64]),
         "gbd_plan_setup": (ctypes.c_int, [P, P, P, P]),
         "gbd_plan_eval": (ctypes.c_int, [P, P, ctypes.c_int, P, I64, P]),
+        "gbd_plan_eval_noalloc": (ctypes.c_int, [P, P, ctypes.c_int, P, I64, P]),
         "gbd_plan_free": (None, [P]),
         "gbd_plan_shape": (ctypes.c_int, [P, P, ctypes.c_int, P, P]),
         "gbd_airy": (ctypes.c_int, [P, P, D, D, D, P, I64]),
@@ -340,6 +341,16 @@ class Plan:
                                             None if o is None else ctypes.byref(o)))
         return out
 
+    def eval_noalloc(self, precision: int = GBD_MIXED, out=None, opts=None):
+        """gbd_plan_eval_noalloc: partial sums in the library's static device
+        buffer; ``out`` should be pre-allocated by callers that cannot allocate."""
+        out = _out_tensor(self.ctx, self.nx, self.ny, precision, out)
+        o = _opts(opts)
+        _check(load_library().gbd_plan_eval_noalloc(self.ctx.handle, self.handle, int(precision),
+                                                    ctypes.c_void_p(out.data_ptr()), out.numel() * out.element_size(),
+                                                    None if o is None else ctypes.byref(o)))
+        return out
+
     def shape(self, precision: int = GBD_MIXED, opts=None) -> dict:
         o = _opts(opts)
         r = gbd_eval_opts()
@@ -365,6 +376,10 @@ def gbd_plan_setup(plan: Plan, beamlets: Beamlets, plane: Plane) -> Plan:
 
 def gbd_plan_eval(plan: Plan, precision: int = GBD_MIXED, out=None, opts=None):
     return plan.eval(precision, out, opts)
+
+
+def gbd_plan_eval_noalloc(plan: Plan, precision: int = GBD_MIXED, out=None, opts=None):
+    return plan.eval_noalloc(precision, out, opts)
 
 
 def gbd_plan_shape(plan: Plan, precision: int = GBD_MIXED, opts=None) -> dict:

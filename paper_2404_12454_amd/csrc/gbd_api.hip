@@ -10,11 +10,26 @@
 #include <algorithm>
 #include <chrono>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
 
 using namespace gbd;
+
+// Segment partials of gbd_plan_eval_noalloc: a static device array, so that
+// entry point allocates nothing.  Each GPU the library runs on holds its own
+// copy until the process ends.  Host code never passes `scratch` itself to a
+// kernel (on the host it names a stand-in, not device memory): gbd_ctx_create
+// takes each device's address with hipGetSymbolAddress once, with that
+// device current, and every use goes through that address.
+static __device__ __align__(256) unsigned char scratch[GBD_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_dev[kMaxDevices];  // per device: the address of its `scratch`
+}  // namespace
 
 // grow-only device buffer
 struct DevBuf {
@@ -234,6 +249,12 @@ int ilog2(int64_t v) {
 constexpr int kTuneEval = 0, kTuneBatch = 1, kTuneSep = 2;
 TuneKey tune_key(int kind, int precision, int64_t n, int64_t m) { return TuneKey{kind, precision, ilog2(n), ilog2(m)}; }
 
+// Fewest segments a form allows: the mixed separable form sums a segment in
+// plain FP32 on the matrix cores, at most kSepMaxSegLen beamlets per sum.
+int64_t min_segments(int precision, int form, int64_t n) {
+    return (form == 3 && precision == GBD_MIXED) ? (n + kSepMaxSegLen - 1) / kSepMaxSegLen : 1;
+}
+
 // Launch shape and mixed form.  32 rows per lane is a rotor-form shape: where
 // the form resolves to direct or stepped it runs 16.
 Shape choose_shape(const gbd_ctx_s *ctx, int precision, int64_t n, const PlaneGeom &pl, uint32_t flags,
@@ -254,7 +275,7 @@ Shape choose_shape(const gbd_ctx_s *ctx, int precision, int64_t n, const PlaneGe
         // at 3,217 per segment, 6.1e-7 at 12,868, 3.4e-6 at 51,474, 1.4e-5
         // at 205,898), so mixed-precision segments hold at most 16,384
         // beamlets, whatever the count's source (automatic, tuned or explicit)
-        const int64_t min_seg = mixed ? (n + kSepMaxSegLen - 1) / kSepMaxSegLen : 1;
+        const int64_t min_seg = min_segments(precision, s.form, n);
         if (s.nseg <= 0) {
             // one round of workgroups, 8 wavefronts per CU (the register
             // budget allows two wavefronts per SIMD; a partial second round
@@ -381,7 +402,7 @@ const FaddeevaCoef &faddeeva_coef() {
 // Launch geometry of the truncated-beamlet kernel: 64-column tiles of
 // 4 wavefronts x kCutRows rows, segments for ~6 wavefronts per SIMD, each
 // segment at least 32 beamlets.
-EvalGeom cut_geom(const gbd_ctx_s *ctx, int precision, const PlaneGeom &pl, int64_t n_cut) {
+EvalGeom cut_geom(const gbd_ctx_s *ctx, int precision, const PlaneGeom &pl, int64_t n_cut, int64_t max_seg = 1024) {
     Shape s;
     s.form = 0;
     s.waves = 4;
@@ -391,12 +412,15 @@ EvalGeom cut_geom(const gbd_ctx_s *ctx, int precision, const PlaneGeom &pl, int6
     const int64_t tiles = std::max<int64_t>(1, tx * ty);
     int64_t seg = ((int64_t)ctx->cus * 6 + tiles - 1) / tiles;
     seg = std::min<int64_t>(seg, std::max<int64_t>(1, n_cut / 32));
-    s.nseg = (int)std::max<int64_t>(1, std::min<int64_t>(seg, 1024));
+    s.nseg = (int)std::max<int64_t>(1, std::min<int64_t>(seg, max_seg));
     return make_geom(pl, n_cut, s);
 }
 
+// fixed: a caller-provided partial-sum buffer of fixed_bytes (the static
+// buffer of gbd_plan_eval_noalloc), used instead of the plan's grow-only one;
+// then nothing is allocated and an automatic segment count is lowered to fit.
 int plan_eval_impl(gbd_ctx_s *ctx, gbd_plan_s *plan, int precision, void *out, int64_t out_bytes,
-                   const gbd_eval_opts *opts) {
+                   const gbd_eval_opts *opts, void *fixed = nullptr, size_t fixed_bytes = 0) {
     if (!plan->ready) return fail(GBD_EINVAL, "gbd_plan_eval: plan has no valid setup");
     if (precision != GBD_FP64 && precision != GBD_MIXED) return fail(GBD_EINVAL, "precision must be GBD_FP64 or GBD_MIXED");
     const int64_t M = (int64_t)plan->pl.nx * plan->pl.ny;
@@ -418,32 +442,79 @@ int plan_eval_impl(gbd_ctx_s *ctx, gbd_plan_s *plan, int precision, void *out, i
     int rc = ensure_device(ctx);
     if (rc) return rc;
     if (plan->n == 0) {
-        HIP_TRY(hipMemsetAsync(out, 0, (size_t)(M * elem), ctx->stream), "hipMemsetAsync");
+        if (fixed)
+            HIP_TRY(launch_fill_zero(out, (size_t)(M * elem), ctx->stream), "zero fill launch");
+        else
+            HIP_TRY(hipMemsetAsync(out, 0, (size_t)(M * elem), ctx->stream), "hipMemsetAsync");
         return GBD_OK;
     }
     // the whole beamlets [0, n_main) in the chosen form; truncated ones
     // [n_main, n) by their own kernel into the following segments
     const int64_t n_main = plan->n - plan->n_cut;
+    // the mixed separable form's partials are compact (float2) and come first
+    const bool compact = n_main > 0 && s.form == 3 && precision == GBD_MIXED;
     EvalGeom g{}, gc{};
     int32_t nseg_main = 0, nseg_cut = 0;
     if (n_main > 0) {
         g = make_geom(plan->pl, n_main, s);
-        if ((int64_t)g.tiles_x * g.tiles_y * g.nseg > (int64_t)0x7fffffff - 8)
-            return fail(GBD_ERANGE, "grid too large");
         nseg_main = g.nseg;
     }
     if (plan->n_cut > 0) {
         gc = cut_geom(ctx, precision, plan->pl, plan->n_cut);
-        if ((int64_t)gc.tiles_x * gc.tiles_y * gc.nseg > (int64_t)0x7fffffff - 8)
-            return fail(GBD_ERANGE, "grid too large");
         nseg_cut = gc.nseg;
     }
+    if (fixed) {
+        // partial bytes of nm main and nc truncated segments (none when one
+        // segment writes the output directly)
+        const size_t per_main = (size_t)M * (compact ? 8 : 16), per_cut = (size_t)M * 16;
+        auto need_of = [&](int64_t nm, int64_t nc) -> size_t {
+            if (nm + nc <= 1 && nc == 0) return 0;
+            return compact ? reduce_wide_offset((int32_t)nm, M) + (size_t)nc * per_cut : (size_t)(nm + nc) * per_cut;
+        };
+        if (need_of(nseg_main, nseg_cut) > fixed_bytes) {
+            if (opts && opts->segments > 0)
+                return fail(GBD_ERANGE, "%d segments of %lld pixels need %zu bytes of partial sums; the static buffer "
+                            "holds %zu", (int)(nseg_main + nseg_cut), (long long)M, need_of(nseg_main, nseg_cut),
+                            fixed_bytes);
+            if (nseg_cut > 0) {  // truncated beamlets: at most half the buffer
+                const int64_t max_cut = (int64_t)((fixed_bytes / 2) / per_cut);
+                if (max_cut < 1)
+                    return fail(GBD_ERANGE, "%lld pixels: one segment of partial sums (%zu bytes) exceeds half the "
+                                "static buffer (%zu bytes)", (long long)M, per_cut, fixed_bytes);
+                if (nseg_cut > max_cut) {
+                    gc = cut_geom(ctx, precision, plan->pl, plan->n_cut, max_cut);
+                    nseg_cut = gc.nseg;
+                }
+            }
+            if (n_main > 0) {
+                const size_t used = (size_t)nseg_cut * per_cut + (compact ? 16 : 0);
+                int64_t max_main = used < fixed_bytes ? (int64_t)((fixed_bytes - used) / per_main) : 0;
+                if (nseg_cut == 0 && max_main < 2) max_main = 1;  // one segment: no partials
+                const int64_t floor_seg = min_segments(precision, s.form, n_main);
+                if (max_main < std::max<int64_t>(floor_seg, 1))
+                    return fail(GBD_ERANGE, "%lld beamlets on %lld pixels need at least %lld segments of partial sums; "
+                                "the static buffer (%zu bytes) holds %lld", (long long)n_main, (long long)M,
+                                (long long)std::max<int64_t>(floor_seg, 1), fixed_bytes, (long long)max_main);
+                if (nseg_main > max_main) {
+                    s.nseg = (int)max_main;
+                    g = make_geom(plan->pl, n_main, s);
+                    nseg_main = g.nseg;
+                }
+            }
+            if (need_of(nseg_main, nseg_cut) > fixed_bytes)
+                return fail(GBD_ERANGE, "partial sums need %zu bytes; the static buffer holds %zu",
+                            need_of(nseg_main, nseg_cut), fixed_bytes);
+        }
+    }
+    if (n_main > 0 && (int64_t)g.tiles_x * g.tiles_y * g.nseg > (int64_t)0x7fffffff - 8)
+        return fail(GBD_ERANGE, "grid too large");
+    if (nseg_cut > 0 && (int64_t)gc.tiles_x * gc.tiles_y * gc.nseg > (int64_t)0x7fffffff - 8)
+        return fail(GBD_ERANGE, "grid too large");
     const int32_t total = nseg_main + nseg_cut;
     const bool reduce = total > 1 || nseg_cut > 0;
-    // the mixed separable form's partials are compact (float2) and come first
-    const bool compact = n_main > 0 && s.form == 3 && precision == GBD_MIXED;
     const int32_t nseg2 = compact ? nseg_main : 0;
-    if (reduce) {
+    void *partial = fixed ? fixed : plan->scratch;
+    if (reduce && !fixed) {
         const size_t need = (size_t)total * (size_t)M * 16;  // bounds the compact layout too
         if (need > plan->scratch_bytes) {
             if (plan->scratch) (void)hipFree(plan->scratch);
@@ -452,6 +523,7 @@ int plan_eval_impl(gbd_ctx_s *ctx, gbd_plan_s *plan, int precision, void *out, i
             HIP_TRY(hipMalloc(&plan->scratch, need), "hipMalloc(segment partials)");
             plan->scratch_bytes = need;
         }
+        partial = plan->scratch;
     }
     if (n_main > 0) {
         const void *rec = precision == GBD_FP64 ? (const void *)plan->r64 : (const void *)plan->r32;
@@ -461,18 +533,18 @@ int plan_eval_impl(gbd_ctx_s *ctx, gbd_plan_s *plan, int precision, void *out, i
         if (reduce) gl.nseg = std::max<int32_t>(total, 2);  // segment partials, never the output
         if (s.form == 3 && precision == GBD_FP64)
             HIP_TRY(launch_eval_sep64(gl, plan->r64, static_cast<const RecHG64 *>(hrec),
-                                      static_cast<double2 *>(plan->scratch), static_cast<double2 *>(out), ctx->stream),
+                                      static_cast<double2 *>(partial), static_cast<double2 *>(out), ctx->stream),
                     "eval kernel launch");
         else if (s.form == 3)
             HIP_TRY(launch_eval_sep(gl, plan->r32, static_cast<const RecHG32 *>(hrec),
-                                    static_cast<float2 *>(plan->scratch), static_cast<float2 *>(out), ctx->stream),
+                                    static_cast<float2 *>(partial), static_cast<float2 *>(out), ctx->stream),
                     "eval kernel launch");
         else {
             if (s.form == 2)
                 HIP_TRY(launch_sigma(gl, plan->r64, precision == GBD_FP64 ? plan->q64 : nullptr,
                                      precision == GBD_FP64 ? nullptr : plan->r32, ctx->stream),
                         "sigma table kernel launch");
-            HIP_TRY(launch_eval(precision, s.rows, s.waves, s.form, gl, rec, hrec, plan->q64, plan->scratch, out,
+            HIP_TRY(launch_eval(precision, s.rows, s.waves, s.form, gl, rec, hrec, plan->q64, partial, out,
                                 ctx->stream),
                     "eval kernel launch");
         }
@@ -480,14 +552,14 @@ int plan_eval_impl(gbd_ctx_s *ctx, gbd_plan_s *plan, int precision, void *out, i
     if (nseg_cut > 0) {
         const void *rec = precision == GBD_FP64 ? (const void *)(plan->r64 + n_main) : (const void *)(plan->r32 + n_main);
         const void *crec = precision == GBD_FP64 ? (const void *)plan->c64 : (const void *)plan->c32;
-        void *wide = static_cast<char *>(plan->scratch) + reduce_wide_offset(nseg2, M);
+        void *wide = static_cast<char *>(partial) + reduce_wide_offset(nseg2, M);
         HIP_TRY(launch_eval_cut(precision, gc, rec, crec, faddeeva_coef(), nseg_main - nseg2, wide, ctx->stream),
                 "truncated-beamlet kernel launch");
     }
     if (reduce) {
         EvalGeom gr = n_main > 0 ? g : gc;
         gr.nseg = total;
-        HIP_TRY(launch_reduce(precision, gr, nseg2, plan->scratch, out, ctx->stream), "reduce kernel launch");
+        HIP_TRY(launch_reduce(precision, gr, nseg2, partial, out, ctx->stream), "reduce kernel launch");
     }
     return GBD_OK;
 }
@@ -611,6 +683,16 @@ int gbd_ctx_create(gbd_ctx_t *out, int device, void *hip_stream) {
     HIP_TRY(hipGetDeviceCount(&count), "hipGetDeviceCount");
     if (device < 0 || device >= count) return fail(GBD_EINVAL, "device %d out of range (%d devices)", device, count);
     HIP_TRY(hipSetDevice(device), "hipSetDevice");
+    if (device >= kMaxDevices) return fail(GBD_EINVAL, "device %d: at most %d devices", device, kMaxDevices);
+    {
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        if (!g_scratch_dev[device]) {
+            void *ptr = nullptr;
+            HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(static partial buffer)");
+            if (!ptr) return fail(GBD_EHIP, "hipGetSymbolAddress(static partial buffer) returned NULL");
+            g_scratch_dev[device] = ptr;
+        }
+    }
     int cus = 0;
     HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device), "hipDeviceGetAttribute");
     gbd_ctx_s *c = new (std::nothrow) gbd_ctx_s();
@@ -903,6 +985,18 @@ int gbd_plan_eval(gbd_ctx_t ctx, gbd_plan_t plan, int precision, void *field_out
                   const gbd_eval_opts *opts) {
     if (!ctx || !plan) return fail(GBD_EINVAL, "NULL argument");
     return plan_eval_impl(ctx, plan, precision, field_out, out_bytes, opts);
+}
+
+int gbd_plan_eval_noalloc(gbd_ctx_t ctx, gbd_plan_t plan, int precision, void *field_out, int64_t out_bytes,
+                          const gbd_eval_opts *opts) {
+    if (!ctx || !plan) return fail(GBD_EINVAL, "NULL argument");
+    void *buf = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        buf = g_scratch_dev[ctx->device];
+    }
+    if (!buf) return fail(GBD_EHIP, "device %d has no static partial buffer address", ctx->device);
+    return plan_eval_impl(ctx, plan, precision, field_out, out_bytes, opts, buf, (size_t)GBD_NOALLOC_SCRATCH_BYTES);
 }
 
 void gbd_plan_free(gbd_plan_t plan) { plan_destroy(plan); }

@@ -307,6 +307,10 @@ hipError_t launch_reduce(int precision, const EvalGeom &g, int32_t nseg2, const 
                          hipStream_t s);
 inline size_t reduce_wide_offset(int32_t nseg2, int64_t M) { return ((size_t)nseg2 * (size_t)M * 8 + 15) & ~(size_t)15; }
 
+// Zeroes `bytes` bytes at p (16-byte aligned) with a kernel, not a memset
+// node (for callers that capture the stream into a graph).
+hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t s);
+
 // Separable (matrix) form on FP32 MFMA (single evaluations and the batched
 // sweep): wavefront tiles of kSepTileX x kSepTileY pixels, kSepWavesX x
 // kSepWavesY wavefronts per workgroup (128 x 128 pixels, one workgroup per

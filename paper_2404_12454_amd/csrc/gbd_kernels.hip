@@ -521,6 +521,26 @@ hipError_t launch_eval(int precision, int rows, int waves, int form, const EvalG
     return hipErrorInvalidValue;
 }
 
+__global__ void __launch_bounds__(256) fill_zero_kernel(uint4 *__restrict__ p, int64_t n16,
+                                                        unsigned char *__restrict__ tail, int32_t n_tail) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (int64_t i = t; i < n16; i += (int64_t)gridDim.x * blockDim.x) p[i] = make_uint4(0u, 0u, 0u, 0u);
+    if (t < n_tail) tail[t] = 0;
+}
+
+hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t s) {
+    if (bytes == 0) return hipSuccess;
+    if (!p || (reinterpret_cast<uintptr_t>(p) & 15) != 0) return hipErrorInvalidValue;
+    const int64_t n16 = (int64_t)(bytes / 16);
+    const int32_t n_tail = (int32_t)(bytes % 16);
+    int64_t blocks = (n16 + 255) / 256;
+    if (blocks < 1) blocks = 1;
+    if (blocks > 4096) blocks = 4096;
+    fill_zero_kernel<<<(unsigned)blocks, 256, 0, s>>>(static_cast<uint4 *>(p), n16,
+                                                      static_cast<unsigned char *>(p) + n16 * 16, n_tail);
+    return hipGetLastError();
+}
+
 hipError_t launch_reduce(int precision, const EvalGeom &g, int32_t nseg2, const void *partial, void *out,
                          hipStream_t s) {
     const int64_t M = (int64_t)g.nx * g.ny;
