@@ -344,15 +344,20 @@ def sweep_grid():
     return [(of, q, na) for na in SWEEP_NACROSS for of in SWEEP_OF for q in SWEEP_Q]
 
 
-def surrogate_draws(n: int = 20000, seed: int = 12454):
+def surrogate_draws(n: int = 20000, seed: int = 12454, counts=None):
     """Seeded uniform draws of the surrogate's inputs:
-    OF ~ U[1,3], q ~ U[0.5,2], ln n_across ~ U[ln 16, ln 128] (rounded),
-    F# ~ U[4,20], ln lam ~ U[ln 0.4 um, ln 2.0 um].  Returns [n,5] float64
-    columns (OF, q, n_across, fnum, lam)."""
+    OF ~ U[1,3], q ~ U[0.5,2], beamlets across uniform over ``counts`` (a
+    list of integers, e.g. the candidate pool's), or, with counts None,
+    ln n_across ~ U[ln 16, ln 128] rounded; F# ~ U[4,20],
+    ln lam ~ U[ln 0.4 um, ln 2.0 um].  Returns [n,5] float64 columns
+    (OF, q, n_across, fnum, lam)."""
     rng = np.random.Generator(np.random.PCG64(seed))
     of = rng.uniform(1.0, 3.0, n)
     q = rng.uniform(0.5, 2.0, n)
-    na = np.rint(np.exp(rng.uniform(math.log(16), math.log(128), n)))
+    if counts is None:
+        na = np.rint(np.exp(rng.uniform(math.log(16), math.log(128), n)))
+    else:
+        na = np.asarray(counts, np.float64)[rng.integers(0, len(counts), n)]
     fn = rng.uniform(4.0, 20.0, n)
     lam = np.exp(rng.uniform(math.log(0.4e-6), math.log(2.0e-6), n))
     return np.stack([of, q, na, fn, lam], axis=1)

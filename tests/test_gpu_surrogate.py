@@ -1,7 +1,7 @@
 """GPU test of the surrogate-pruned search (reduced sizes): labels from the
 batched GBD sweep, training on the device, top-32 proposals re-scored by
-plain GBD, compared with the exhaustive sweep of the same candidate pool and
-with randomly chosen candidates."""
+plain GBD, compared with the exhaustive sweep of the same candidate pool, with
+random orders and draws of candidates, and with a model-free heuristic."""
 import numpy as np
 import pytest
 
@@ -12,15 +12,26 @@ pytestmark = pytest.mark.gpu
 
 
 def test_surrogate_prunes_the_search():
+    """231 candidates (OF 11 x q 7 x 48, 96, 128 across) at 128 x 128 over
+    +-8 lambda F; 11 of them lie within 1 % of the exhaustive optimum (at 96
+    across: the figure of merit is not monotone in the count).  Taken in the
+    network's order, GBD meets one of them within 3 re-scores, before the
+    median of 101 random orders and before the heuristic (most beamlets,
+    OF q nearest 1.7); the top 32 land within 0.5 % of the optimum and do no
+    worse than the median of 5 random draws of 32."""
     ensure_library()
-    pool = surrogate.candidate_pool(n_of=11, n_q=9, nacross=(24, 48, 96))
+    pool = surrogate.candidate_pool(n_of=11, n_q=7, nacross=(48, 96, 128))
     rec = surrogate.run(n_train=3000, epochs=60, pool=pool, top=32, label_npix=128, rescore_npix=128, span=8.0,
-                        random_baselines=5)
+                        random_baselines=5, random_orders=101, within=1.01)
     print({k: v for k, v in rec.items() if k != "loss_history"}, flush=True)
-    assert rec["val_r2"] > 0.9
-    # the proposals, re-scored by GBD, come within 15% of the exhaustive optimum
-    assert rec["rms_ratio_to_optimum"] <= 1.15
-    # and the online phase (inference + 32 re-scores) is cheaper than the exhaustive sweep
+    assert rec["val_r2"] > 0.99
+    assert rec["rescores_to_reach_surrogate"] <= 3
+    assert rec["rescores_to_reach_surrogate"] < rec["rescores_to_reach_random_median"]
+    assert rec["rescores_to_reach_surrogate"] < rec["rescores_to_reach_heuristic"]
+    assert rec["rms_ratio_to_optimum"] <= 1.005
+    assert rec["rms_ratio_to_optimum"] <= float(np.median(rec["random32_ratio_to_optimum"]))
+    assert rec["rms_ratio_to_optimum"] < rec["heuristic32_ratio_to_optimum"]
+    # the online phase (inference + 32 re-scores) is cheaper than the exhaustive sweep
     assert rec["online_s"] < rec["exhaustive_s"]
 
 
