@@ -10,10 +10,12 @@ inputs already resident in HBM.  Workload: 51,468 beamlets (256 across a
 
 The mixed evaluation takes the library's automatic form: on this workload
 (a rotationally symmetric system on a plane normal to the axis, so no
-beamlet's phasor has a cross term) the separable matrix form on FP32 MFMA,
-whose roofline is the MFMA peak; the rotor form, which any plane with cross
-terms gets, is timed on the same workload beside it (general_form) with its
-instruction-mix roofline.
+beamlet's phasor has a cross term) the separable matrix form on FP16 MFMA
+with every factor split into FP16 hi and lo halves, whose roofline is the
+FP16 MFMA peak; the same form on FP32 MFMA (separable_fp32) and the rotor
+form, which any plane with cross terms gets (general_form, with its
+instruction-mix roofline at nominal and at measured issue rates), are timed
+on the same workload beside it.
 
 Also reported: the FP64 form on the same workload (and the mixed/FP64
 speed-up), the dominant kernel's live HIP-event duration, point evaluation,
@@ -35,8 +37,12 @@ METRIC = "beamlet·pixel evals/s (FP32+FP64-phase vs FP64) at ≤1e-5 rel field 
 
 # Instruction-mix roofline of the mixed evaluation kernel.  Issue rates in
 # lanes per CU per clock from the chip's unit counts: FP64 64 (78.6 TFLOP/s
-# FP64 FMA), FP32 128 (157.3 TFLOP/s FP32), transcendental 32 (half the FP64
-# rate, measured on gfx950).  Instructions per beamlet-pixel pair for R rows
+# FP64 FMA), FP32 128 (157.3 TFLOP/s FP32: reached without packed
+# instructions by the two-operand v_fmac_f32 / v_mul_f32, which the
+# issue-rate probe measures at 102-107 lanes per CU per nominal clock against
+# 58 for the three-operand v_fma_f32), transcendental 32 (half the FP64 rate;
+# probe: 28-29).  The benchmark prices each VALU form at these rates and at
+# the probe's measured ones.  Instructions per beamlet-pixel pair for R rows
 # per lane (per-lane-beamlet work amortised over the R pixels it serves):
 #   stepped form: per pixel 2 transcendental (sin, cos in revolutions) and
 #     6 FP32 (2 phase-step FMA, 2 amplitude-step multiply, 2 accumulate FMA);
@@ -53,7 +59,7 @@ RATE = {"fp64": 64, "fp32": 128, "trans": 32}
 # HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE (x2.0)
 # and WRITE_SIZE (x1.0) runs, scale factors from a plain 256 MiB copy; valid
 # only for the kernel and launch they were taken on (else traffic is null).
-TRAFFIC = {("airy256_512", 32, 8, 16, 4): (5300.8 * 2.0 + 32768.0 * 1.0) * 1024}
+TRAFFIC = {}
 
 
 def instruction_mix(rows, variant, hg=False):
@@ -72,9 +78,12 @@ def instruction_mix(rows, variant, hg=False):
     return {"fp64": (4 * R + 10) / R, "fp32": (5 * R + 5) / R, "trans": 3.0}
 
 
-def roofline_peak(rows, variant, hg=False):
+def roofline_peak(rows, variant, hg=False, rate=None):
+    """Instruction-mix roofline at the nominal issue rates (RATE) or at the
+    given measured ones."""
+    rate = rate or RATE
     mix = instruction_mix(rows, variant, hg)
-    cycles = sum(n / RATE[k] for k, n in mix.items())
+    cycles = sum(n / rate[k] for k, n in mix.items())
     return CUS * CLOCK_HZ / cycles, cycles, mix
 
 
@@ -90,6 +99,12 @@ SEP_FLOPS_PER_PAIR = 6.0
 SEP_COMPLEX_MADD_FLOPS = 8.0
 # the FP64 separable form multiplies in four real FP64 MFMA products
 SEP64_FLOPS_PER_PAIR = 8.0
+# FP16 halves form (variant 4 for fundamental beamlets): each factor as FP16
+# hi + lo, all four hi/lo products of the four real products of the complex
+# multiply: 16 FP16 multiply-adds (32 flops) per pair on the matrix cores,
+# against the FP16 MFMA peak
+MFMA_FP16_TFLOPS = 2500.0
+SEPH_FLOPS_PER_PAIR = 32.0
 # per lane and pass between barriers (16 beamlets x 64 x 32 pixels of one
 # wavefront), counted in the compiled loop: 40 FP64, 56 FP32, 24
 # transcendental and 62 other VALU instructions (the factors shared by 8
@@ -98,8 +113,53 @@ SEP_VALU_PER_PAIR = {"fp64": 40 / 512, "fp32": 56 / 512, "trans": 24 / 512, "oth
                      "mfma_16x16x4": 96 / 32768}
 
 
+PROBE_CLASSES = [("fp32_fma", 0, 128), ("fp64_fma", 1, 128), ("sin_f32", 2, 32), ("exp_f32", 3, 32),
+                 ("mfma_f32_16x16x4", 4, 4096), ("mfma_f16_16x16x32", 5, 4096), ("mfma_f64_16x16x4", 6, 2048),
+                 ("fp32_fmac", 7, 128), ("fp32_mul", 8, 128)]
+MFMA_FLOPS_PER_INSTR = {"mfma_f32_16x16x4": 2048, "mfma_f16_16x16x32": 16384, "mfma_f64_16x16x4": 2048}
+
+
+def issue_rates(ctx):
+    """Measured issue rates (gbd_issue_probe): VALU classes in lane-
+    instructions per CU per clock, MFMA classes in TFLOP/s and instructions
+    per CU per clock, at the nominal 2.4 GHz clock on 256 CUs."""
+    import paper_2404_12454_amd as gbd
+    out = {}
+    for name, cls, iters in PROBE_CLASSES:
+        ms, n = gbd.gbd_issue_probe(ctx, cls, iters)
+        if ms < 4.0:  # lengthen to ~5 ms so launch overhead and ramp do not count
+            iters = int(iters * min(5.0 / max(ms, 1e-3), 4096.0))
+            ms, n = gbd.gbd_issue_probe(ctx, cls, iters)
+        per_cu_clk = n / (ms * 1e-3) / (CUS * CLOCK_HZ)
+        if name.startswith("mfma"):
+            out[name] = {"tflops": n * MFMA_FLOPS_PER_INSTR[name] / (ms * 1e-3) / 1e12,
+                         "instr_per_cu_clk": per_cu_clk, "ms": ms, "iters": iters}
+        else:
+            out[name] = {"lanes_per_cu_clk": 64.0 * per_cu_clk, "ms": ms, "iters": iters}
+    return out
+
+
+def measured_rate(rates):
+    """Issue rates per CU per clock in the roofline's classes from the probe:
+    FP32 at the slower of the two-operand multiply and multiply-add (the
+    forms the VALU kernels' inner loops use; the three-operand v_fma_f32
+    issues at about half their rate), the transcendental class at the
+    slower of sin and exp."""
+    if not rates:
+        return None
+    return {"fp64": rates["fp64_fma"]["lanes_per_cu_clk"],
+            "fp32": min(rates["fp32_fmac"]["lanes_per_cu_clk"], rates["fp32_mul"]["lanes_per_cu_clk"]),
+            "trans": min(rates["sin_f32"]["lanes_per_cu_clk"], rates["exp_f32"]["lanes_per_cu_clk"])}
+
+
 def roofline(shape, N, M, kernel_ms, hg=False):
     if shape["variant"] == 4:
+        achieved = SEPH_FLOPS_PER_PAIR * N * M / (kernel_ms * 1e-3) / 1e12
+        return {"bound": "mfma", "achieved": achieved, "peak": MFMA_FP16_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / MFMA_FP16_TFLOPS, "kernel": "eval_seph_kernel", "kernel_ms": kernel_ms,
+                "flops_per_pair": SEPH_FLOPS_PER_PAIR,
+                "complex_madd_equiv_tflops": SEP_COMPLEX_MADD_FLOPS * N * M / (kernel_ms * 1e-3) / 1e12}
+    if shape["variant"] == 5:
         achieved = SEP_FLOPS_PER_PAIR * N * M / (kernel_ms * 1e-3) / 1e12
         return {"bound": "mfma", "achieved": achieved, "peak": MFMA_FP32_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved / MFMA_FP32_TFLOPS, "kernel": "eval_sep_kernel", "kernel_ms": kernel_ms,
@@ -108,9 +168,16 @@ def roofline(shape, N, M, kernel_ms, hg=False):
                 "instructions_per_pair": SEP_VALU_PER_PAIR}
     achieved = N * M / (kernel_ms * 1e-3)
     peak, cycles, mix = roofline_peak(shape["rows_per_lane"], shape["variant"], hg)
-    return {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "evals/s", "frac": achieved / peak,
-            "kernel": "eval_mixed_kernel", "kernel_ms": kernel_ms, "cu_cycles_per_pair": cycles,
-            "instructions_per_pair": mix}
+    r = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "evals/s", "frac": achieved / peak,
+         "kernel": "eval_mixed_kernel", "kernel_ms": kernel_ms, "cu_cycles_per_pair": cycles,
+         "instructions_per_pair": mix}
+    if MEASURED_RATE:
+        peak_m = roofline_peak(shape["rows_per_lane"], shape["variant"], hg, MEASURED_RATE)[0]
+        r.update({"peak_at_measured_rates": peak_m, "frac_at_measured_rates": achieved / peak_m})
+    return r
+
+
+MEASURED_RATE = None  # filled by main() from the issue-rate probe
 
 
 def main():
@@ -129,6 +196,8 @@ def main():
     ap.add_argument("--no-aberrated", action="store_true",
                     help="skip the aberrated tilted-plane leg (zern128_1024, the general form)")
     ap.add_argument("--fp64-steps", type=int, default=5)
+    ap.add_argument("--issue-rates-only", action="store_true",
+                    help="run only the issue-rate probe and print its rates (for profiling the probe)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 256 MiB device copy (a known-size kernel for HBM counters)")
     args = ap.parse_args()
@@ -147,6 +216,9 @@ def main():
         from paper_2404_12454_amd import build
         build.build()
 
+    if args.issue_rates_only:
+        print(json.dumps({"issue_rates": issue_rates(gbd.Context(0))}), flush=True)
+        return
     sc = scenes.config(args.workload)
     N, M = sc.n, sc.plane.npix
     ctx = gbd.Context(0)
@@ -172,6 +244,9 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    global MEASURED_RATE
+    rates = issue_rates(ctx)
+    MEASURED_RATE = measured_rate(rates)
     for _ in range(args.warmup):
         step(gbd.GBD_MIXED, out)
     torch.cuda.synchronize()
@@ -231,10 +306,13 @@ def main():
         "fp64": fp64_record(shape64, N, M, eval64_ms, eval_ms_mean),
         "err_mixed_vs_fp64_full_grid": mixed_vs_fp64,
         "wall_s_timed": wall,
+        "issue_rates": rates,
     }
 
-    if shape["variant"] == 4:
+    if shape["variant"] in (4, 5):
         rec["general_form"] = general_form(plan, N, M, out, stream)
+    if shape["variant"] == 4:
+        rec["separable_fp32"] = general_form(plan, N, M, out, stream, variant=5)
     if not args.no_aberrated and args.workload != "zern128_1024":
         rec["aberrated"] = aberrated(ctx, stream)
     if not args.no_point:
@@ -277,13 +355,14 @@ def fp64_record(shape, N, M, ms, mixed_ms):
     return r
 
 
-def general_form(plan, N, M, out, stream, reps=20):
-    """The same workload through the form that needs no separability (rotor,
-    variant 3): what any plane with cross terms (tilted, astigmatic) gets."""
+def general_form(plan, N, M, out, stream, reps=20, variant=3):
+    """The same workload through another form: by default the one that needs
+    no separability (rotor, variant 3), what any plane with cross terms
+    (tilted, astigmatic) gets; variant 5, the separable form on FP32 MFMA."""
     import numpy as np
     import torch
     import paper_2404_12454_amd as gbd
-    o = dict(variant=3)
+    o = dict(variant=variant)
     for _ in range(reps):
         plan.eval(gbd.GBD_MIXED, out, opts=o)
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
@@ -295,8 +374,12 @@ def general_form(plan, N, M, out, stream, reps=20):
     ms = float(np.mean([a.elapsed_time(z) for a, z in evs]))
     shape = plan.shape(gbd.GBD_MIXED, opts=o)
     r = roofline(shape, N, M, ms)
-    return {"launch": shape, "eval_ms": ms, "evals_per_s": N * M / (ms * 1e-3), "roofline_frac": r["frac"],
-            "roofline_peak": r["peak"]}
+    g = {"launch": shape, "eval_ms": ms, "evals_per_s": N * M / (ms * 1e-3), "roofline_frac": r["frac"],
+         "roofline_peak": r["peak"], "roofline_bound": r["bound"], "roofline_unit": r["unit"]}
+    if "peak_at_measured_rates" in r:
+        g.update({"roofline_peak_at_measured_rates": r["peak_at_measured_rates"],
+                  "roofline_frac_at_measured_rates": r["frac_at_measured_rates"]})
+    return g
 
 
 def aberrated(ctx, stream, reps=10, reps64=3, oracle_stride=8):
@@ -341,6 +424,9 @@ def aberrated(ctx, stream, reps=10, reps64=3, oracle_stride=8):
            "fp64": {"launch": shape64, "eval_ms": ms64, "evals_per_s": N * M / (ms64 * 1e-3),
                     "roofline_frac": r64.get("roofline_frac")},
            "err_mixed_vs_fp64_full_grid": float(np.linalg.norm(E32 - E64) / np.linalg.norm(E64))}
+    if "peak_at_measured_rates" in r:
+        rec.update({"roofline_peak_at_measured_rates": r["peak_at_measured_rates"],
+                    "roofline_frac_at_measured_rates": r["frac_at_measured_rates"]})
     if oracle_stride:
         import oracle
         rows = np.arange(0, sc.plane.ny, oracle_stride)
@@ -494,7 +580,7 @@ def hermite(ctx, stream, gauss_ms, n_across=256, npix=512, reps=10):
         shape = plan.shape(gbd.GBD_MIXED)
         r = {"beamlets": sc.n, "npix": npix, "launch": shape, "eval_ms": ms,
              "evals_per_s": sc.n * npix * npix / (ms * 1e-3)}
-        if shape["variant"] == 4:
+        if shape["variant"] in (4, 5):
             r["mfma_frac"] = roofline(shape, sc.n, npix * npix, ms)["frac"]
             r["cost_vs_fundamental"] = ms / gauss_ms
         elif shape["variant"] == 3:

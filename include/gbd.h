@@ -79,11 +79,19 @@ typedef struct {
                                3 = rotor: per lane and beamlet an FP64 anchor phasor at
                                the lane's middle row, the other rows by complex
                                recurrence (anchor x rho^k x sigma^(k^2)); 4 = separable:
-                               E = sum_j U_j(x) V_j(y) as a complex matrix product on
-                               FP32 MFMA in three real products per pair, 128 x 128 pixel
-                               workgroup tiles (rows_per_lane and waves do not apply;
-                               gbd_plan_shape reports 32 and 8).
-                               Separable is used (auto) or honoured (4) when no beamlet's
+                               E = sum_j U_j(x) V_j(y) as a complex matrix product, for
+                               fundamental beamlets on FP16 MFMA with every factor split
+                               into FP16 hi and lo halves (all four hi/lo products, FP32
+                               accumulation; each beamlet's factors scaled by powers of
+                               two into FP16's range from the setup's bounds over the
+                               grid, so a term's error stays below 2^-21 of itself or
+                               2^-38 of the largest term over the grid, whichever is
+                               larger), for higher-order beamlets as 5; 5 = separable
+                               on FP32 MFMA in three real products per pair (Gauss's
+                               form).  Both: 128 x 128 pixel workgroup tiles
+                               (rows_per_lane and waves do not apply; gbd_plan_shape
+                               reports 32 and 8).
+                               Separable is used (auto) or honoured (4, 5) when no beamlet's
                                phasor has a cross term (rotationally symmetric systems on
                                a plane normal to the axis); stepped and rotor when the
                                setup finds every beamlet's log2-amplitude curvature below
@@ -289,6 +297,20 @@ int gbd_autotune_batch(gbd_ctx_t ctx, int32_t n_inst, const gbd_beamlets_t *beam
                        const float *airy, int64_t airy_bytes, int32_t reps, gbd_eval_opts *best, double *best_ms);
 int gbd_autotune_save(gbd_ctx_t ctx, const char *path);
 int gbd_autotune_load(gbd_ctx_t ctx, const char *path);
+
+/* --- measurement: issue rates of the instruction classes the evaluation
+ * kernels use (for pricing their rooflines) ---------------------------------
+ * gbd_issue_probe runs a kernel of 8 workgroups x 256 threads per CU whose
+ * threads issue `iters` (>= 1) rounds of independent chains of one class:
+ * 0 v_fma_f32, 1 v_fma_f64, 2 v_sin_f32, 3 v_exp_f32, 7 v_fmac_f32,
+ * 8 v_mul_f32 (16 chains per thread), 4 v_mfma_f32_16x16x4_f32,
+ * 5 v_mfma_f32_16x16x32_f16, 6 v_mfma_f64_16x16x4_f64 (4 chains per
+ * wavefront); after one untimed
+ * launch it times one launch with HIP events on the context stream
+ * (synchronises) and returns the time in *ms_out and the wavefront-
+ * instructions of that class the launch issued in *wave_instructions_out.
+ * Owns its scratch (allocated and freed in the call). */
+int gbd_issue_probe(gbd_ctx_t ctx, int32_t cls, int32_t iters, double *ms_out, double *wave_instructions_out);
 
 /* --- point evaluation (paraxial, FP64) --------------------------------------
  * The per-point algorithm that plane evaluation replaces (Sec. 2.2, in its

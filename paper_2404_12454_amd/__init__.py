@@ -22,7 +22,7 @@ import numpy as np
 __all__ = [
     "GBD_FP64", "GBD_MIXED", "GbdError", "gbd_eval_opts", "library_path", "load_library",
     "gbd_ctx_create", "gbd_beamlets", "gbd_plane", "gbd_eval", "gbd_plan_create", "gbd_plan_setup",
-    "gbd_plan_eval", "gbd_plan_eval_noalloc", "gbd_plan_shape", "gbd_airy", "gbd_eval_batch", "gbd_eval_point", "gbd_autotune", "gbd_autotune_batch",
+    "gbd_plan_eval", "gbd_plan_eval_noalloc", "gbd_plan_shape", "gbd_issue_probe", "gbd_airy", "gbd_eval_batch", "gbd_eval_point", "gbd_autotune", "gbd_autotune_batch",
     "gbd_autotune_save", "gbd_autotune_load", "GBD_MLP_FP32", "GBD_MLP_BF16", "Mlp", "gbd_mlp_create", "beamlets_from_scene", "plane_from_scene",
     "gbd_trace", "gbd_beamlets_traced", "gbd_beamlets_hg", "gbd_beamlets_truncated",
     "Context", "Beamlets", "Plane", "Plan",
@@ -102,6 +102,7 @@ def load_library():
         "gbd_autotune_save": (ctypes.c_int, [P, ctypes.c_char_p]),
         "gbd_autotune_load": (ctypes.c_int, [P, ctypes.c_char_p]),
         "gbd_eval_batch": (ctypes.c_int, [P, I32, P, P, P, I64, P, I32, P, P, I64, P]),
+        "gbd_issue_probe": (ctypes.c_int, [P, I32, I32, P, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -376,6 +377,14 @@ def gbd_plan_setup(plan: Plan, beamlets: Beamlets, plane: Plane) -> Plan:
 
 def gbd_plan_eval(plan: Plan, precision: int = GBD_MIXED, out=None, opts=None):
     return plan.eval(precision, out, opts)
+
+
+def gbd_issue_probe(ctx: Context, cls: int, iters: int):
+    """(milliseconds, wavefront-instructions) of one timed launch of the
+    issue-rate probe for instruction class ``cls`` (see include/gbd.h)."""
+    ms, n = ctypes.c_double(), ctypes.c_double()
+    _check(load_library().gbd_issue_probe(ctx.handle, int(cls), int(iters), ctypes.byref(ms), ctypes.byref(n)))
+    return ms.value, n.value
 
 
 def gbd_plan_eval_noalloc(plan: Plan, precision: int = GBD_MIXED, out=None, opts=None):

@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgbd.so")
 SOURCES = ["gbd_api.hip", "gbd_kernels.hip", "gbd_sep.hip", "gbd_batch.hip", "gbd_mlp.hip", "gbd_point.hip",
-           "gbd_trace.hip", "gbd_cut.hip", "gbd_sep64.hip"]
+           "gbd_trace.hip", "gbd_cut.hip", "gbd_sep64.hip", "gbd_probe.hip"]
 ARCH = os.environ.get("GBD_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [

@@ -92,10 +92,11 @@ struct gbd_plan_s {
     RecCut64 *c64;  // truncation factors, allocated at the first setup of truncated beamlets
     RecCut32 *c32;
     int64_t n_cut;  // truncated beamlets of the last setup (the last n_cut records)
-    uint32_t *status_dev;   // two flag words used by alternate setups; each setup clears the other
-    int status_parity;      // the word the next setup uses
+    uint32_t *status_dev;   // two (flags, peak) word pairs used by alternate setups; each setup clears the other
+    int status_parity;      // the pair the next setup uses
     bool status_zeroed;     // both words cleared (once, before the first setup)
-    uint32_t *status_host;  // pinned
+    uint32_t *status_host;  // pinned, two words
+    int sep_scale;          // FP16 separable form: accumulators hold the field times 2^sep_scale
     void *scratch;
     size_t scratch_bytes;
 };
@@ -201,6 +202,7 @@ int ensure_device(gbd_ctx_s *ctx) {
 
 struct Shape {
     int rows, waves, nseg, form;
+    bool half;  // mixed separable form in FP16 hi/lo halves (else FP32 MFMA)
 };
 
 // mixed kernel form (0 direct, 1 stepped, 2 rotor, 3 separable): requested
@@ -217,14 +219,14 @@ int pick_form(int precision, uint32_t flags, const gbd_eval_opts *o, bool allow_
         // others.
         const bool sep64 = allow_sep && !(flags & FLAG_CROSS);
         const bool rot64 = !steep;
-        const int v = o ? o->variant : 0;
+        const int v = o ? (o->variant == 5 ? 4 : o->variant) : 0;
         if (v == 1) return 0;
         if (v == 3 && rot64) return 2;
         if (v == 4 && sep64) return 3;
         return sep64 ? 3 : rot64 ? 2 : 0;
     }
     const bool sep = allow_sep && !(flags & FLAG_CROSS);
-    const int v = o ? o->variant : 0;
+    const int v = o ? (o->variant == 5 ? 4 : o->variant) : 0;  // 5: the separable form on FP32 MFMA
     if (v == 1) return 0;
     // higher-order beamlets: the stepped form does not carry their factor
     if (v == 2) return (steep || (flags & FLAG_HG)) ? 0 : 1;
@@ -233,7 +235,9 @@ int pick_form(int precision, uint32_t flags, const gbd_eval_opts *o, bool allow_
 }
 
 // the variant a resolved form reports (gbd_eval_opts.variant)
-int form_variant(int precision, int form) { return form + 1; }
+int form_variant(int precision, int form, bool half = false) {
+    return (precision == GBD_MIXED && form == 3 && !half) ? 5 : form + 1;
+}
 
 int ilog2(int64_t v) {
     int r = 0;
@@ -261,6 +265,10 @@ Shape choose_shape(const gbd_ctx_s *ctx, int precision, int64_t n, const PlaneGe
                    const gbd_eval_opts *o) {
     Shape s;
     s.form = pick_form(precision, flags, o);
+    // the mixed separable form of fundamental beamlets runs on FP16 MFMA in
+    // hi/lo halves unless the FP32 one is requested (variant 5); higher-order
+    // factors keep FP32 (their polynomial moduli are not bounded by the setup)
+    s.half = s.form == 3 && precision == GBD_MIXED && !(flags & FLAG_HG) && !(o && o->variant == 5);
     if (s.form == 3) {
         // separable form: fixed 64 x 32 pixel tile per wavefront (s.rows is
         // the tile height), 2 x 4 wavefronts per workgroup (s.waves); the row
@@ -405,6 +413,7 @@ const FaddeevaCoef &faddeeva_coef() {
 EvalGeom cut_geom(const gbd_ctx_s *ctx, int precision, const PlaneGeom &pl, int64_t n_cut, int64_t max_seg = 1024) {
     Shape s;
     s.form = 0;
+    s.half = false;
     s.waves = 4;
     s.rows = precision == GBD_MIXED ? kCutRows32 : kCutRows64;
     const int64_t tx = (pl.nx + 63) / 64;
@@ -429,7 +438,7 @@ int plan_eval_impl(gbd_ctx_s *ctx, gbd_plan_s *plan, int precision, void *out, i
     if (!out) return fail(GBD_EINVAL, "field_out is NULL");
     if (out_bytes < M * elem)
         return fail(GBD_ERANGE, "field_out holds %lld bytes, %lld needed", (long long)out_bytes, (long long)(M * elem));
-    if (opts && (opts->variant < 0 || opts->variant > 4)) return fail(GBD_EINVAL, "variant must be 0 ... 4");
+    if (opts && (opts->variant < 0 || opts->variant > 5)) return fail(GBD_EINVAL, "variant must be 0 ... 5");
     // rows_per_lane and waves do not apply to the separable form (its tile is
     // fixed; gbd_plan_shape reports it, and handing that shape back is fine)
     const bool sep_form = pick_form(precision, plan->flags, opts) == 3;
@@ -535,6 +544,10 @@ int plan_eval_impl(gbd_ctx_s *ctx, gbd_plan_s *plan, int precision, void *out, i
             HIP_TRY(launch_eval_sep64(gl, plan->r64, static_cast<const RecHG64 *>(hrec),
                                       static_cast<double2 *>(partial), static_cast<double2 *>(out), ctx->stream),
                     "eval kernel launch");
+        else if (s.form == 3 && s.half)
+            HIP_TRY(launch_eval_seph(gl, plan->r32, plan->sep_scale, static_cast<float2 *>(partial),
+                                     static_cast<float2 *>(out), ctx->stream),
+                    "eval kernel launch");
         else if (s.form == 3)
             HIP_TRY(launch_eval_sep(gl, plan->r32, static_cast<const RecHG32 *>(hrec),
                                     static_cast<float2 *>(partial), static_cast<float2 *>(out), ctx->stream),
@@ -589,22 +602,25 @@ int plan_setup_impl(gbd_ctx_s *ctx, gbd_plan_s *plan, gbd_beamlets_s *b, gbd_pla
         const double g0 = b->dev.l0 / b->dev.lam;
         const double gturns = g0 - nearbyint(g0);
         if (!plan->status_zeroed) {
-            HIP_TRY(hipMemsetAsync(plan->status_dev, 0, 2 * sizeof(uint32_t), ctx->stream), "hipMemsetAsync(status)");
+            HIP_TRY(hipMemsetAsync(plan->status_dev, 0, 4 * sizeof(uint32_t), ctx->stream), "hipMemsetAsync(status)");
             plan->status_zeroed = true;
         }
         const bool hg = b->dev.order != nullptr;
         const bool cut = b->dev.n_cut > 0;
-        uint32_t *status = plan->status_dev + plan->status_parity;
-        uint32_t *status_next = plan->status_dev + (plan->status_parity ^ 1);
+        uint32_t *status = plan->status_dev + 2 * plan->status_parity;
+        uint32_t *status_next = plan->status_dev + 2 * (plan->status_parity ^ 1);
         HIP_TRY(launch_setup(b->dev, p->g, gturns, plan->r64, plan->r32, hg ? plan->h64 : nullptr,
                              hg ? plan->h32 : nullptr, cut ? plan->c64 : nullptr, cut ? plan->c32 : nullptr,
                              status, status_next, ctx->stream),
                 "setup kernel launch");
         plan->status_parity ^= 1;
-        HIP_TRY(hipMemcpyAsync(plan->status_host, status, sizeof(uint32_t), hipMemcpyDeviceToHost, ctx->stream),
+        HIP_TRY(hipMemcpyAsync(plan->status_host, status, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, ctx->stream),
                 "status copy");
         HIP_TRY(hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
-        const uint32_t st = *plan->status_host;
+        const uint32_t st = plan->status_host[0];
+        // FP16 separable form: largest term 2^P over the grid -> scale 2^(2 kSepHalfExp - P)
+        const uint32_t key = plan->status_host[1];
+        plan->sep_scale = key ? 2 * kSepHalfExp - ((int)key - 2048) : 0;
         if (st & FLAG_PARALLEL) return fail(GBD_EPARALLEL, "a base ray is parallel to the detector plane");
         if (st & FLAG_BRANCH)
             return fail(GBD_EBRANCH, "an eigenvalue of A + B Q1^-1 lies off the principal branch (inverting system)");
@@ -641,8 +657,8 @@ int plan_new(gbd_ctx_s *ctx, int64_t capacity, gbd_plan_s **out) {
     hipError_t e = hipMalloc(&p->r64, cap * sizeof(Rec64));
     if (e == hipSuccess) e = hipMalloc(&p->r32, cap * sizeof(Rec32));
     if (e == hipSuccess) e = hipMalloc(&p->q64, cap * sizeof(RecSq64));
-    if (e == hipSuccess) e = hipMalloc(&p->status_dev, 2 * sizeof(uint32_t));
-    if (e == hipSuccess) e = hipHostMalloc(&p->status_host, sizeof(uint32_t), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipMalloc(&p->status_dev, 4 * sizeof(uint32_t));
+    if (e == hipSuccess) e = hipHostMalloc(&p->status_host, 2 * sizeof(uint32_t), hipHostMallocDefault);
     if (e != hipSuccess) {
         plan_destroy(p);
         return hip_fail(e, "plan allocation");
@@ -1001,6 +1017,35 @@ int gbd_plan_eval_noalloc(gbd_ctx_t ctx, gbd_plan_t plan, int precision, void *f
 
 void gbd_plan_free(gbd_plan_t plan) { plan_destroy(plan); }
 
+int gbd_issue_probe(gbd_ctx_t ctx, int32_t cls, int32_t iters, double *ms_out, double *wave_instructions_out) {
+    if (!ctx || !ms_out || !wave_instructions_out) return fail(GBD_EINVAL, "NULL argument");
+    if (cls < 0 || cls > 8) return fail(GBD_EINVAL, "class must be 0 ... 8");
+    if (iters < 1) return fail(GBD_EINVAL, "iters must be >= 1");
+    int rc = ensure_device(ctx);
+    if (rc) return rc;
+    const int blocks = ctx->cus * 8;
+    float *sink = nullptr;
+    HIP_TRY(hipMalloc(&sink, (size_t)blocks * 256 * sizeof(float)), "hipMalloc(probe)");
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e == hipSuccess) e = launch_issue_probe(cls, blocks, iters, sink, ctx->stream);
+    if (e == hipSuccess) e = hipEventRecord(e0, ctx->stream);
+    if (e == hipSuccess) e = launch_issue_probe(cls, blocks, iters, sink, ctx->stream);
+    if (e == hipSuccess) e = hipEventRecord(e1, ctx->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(sink);
+    if (e != hipSuccess) return hip_fail(e, "issue probe");
+    const double waves = (double)blocks * 4.0;
+    *ms_out = ms;
+    *wave_instructions_out = waves * (double)iters * ((cls <= 3 || cls >= 7) ? 16.0 : 4.0);
+    return GBD_OK;
+}
+
 int gbd_plan_shape(gbd_ctx_t ctx, gbd_plan_t plan, int precision, const gbd_eval_opts *opts, gbd_eval_opts *resolved) {
     if (!ctx || !plan || !resolved) return fail(GBD_EINVAL, "NULL argument");
     Shape s = choose_shape(ctx, precision, plan->n - plan->n_cut, plan->pl, plan->flags, opts);
@@ -1008,7 +1053,7 @@ int gbd_plan_shape(gbd_ctx_t ctx, gbd_plan_t plan, int precision, const gbd_eval
     resolved->rows_per_lane = s.rows;
     resolved->waves = s.waves;
     resolved->segments = g.nseg;
-    resolved->variant = form_variant(precision, s.form);
+    resolved->variant = form_variant(precision, s.form, s.half);
     return GBD_OK;
 }
 
@@ -1097,7 +1142,7 @@ int gbd_autotune(gbd_ctx_t ctx, gbd_plan_t plan, int precision, int32_t reps, gb
     if (best) {
         const Shape s = choose_shape(ctx, precision, n_main, plan->pl, plan->flags, nullptr);
         const EvalGeom g = make_geom(plan->pl, n_main, s);
-        *best = gbd_eval_opts{s.rows, s.waves, g.nseg, form_variant(precision, s.form)};
+        *best = gbd_eval_opts{s.rows, s.waves, g.nseg, form_variant(precision, s.form, s.half)};
     }
     if (best_ms) *best_ms = bestv.ms;
     return GBD_OK;
@@ -1199,7 +1244,7 @@ int gbd_eval_batch(gbd_ctx_t ctx, int32_t n_inst, const gbd_beamlets_t *bs, cons
     }
     if (metrics_out && !airy) return fail(GBD_EINVAL, "metrics need the reference irradiance");
     if (airy && !metrics_out) return fail(GBD_EINVAL, "metrics_out is NULL");
-    if (opts && (opts->variant < 0 || opts->variant > 4)) return fail(GBD_EINVAL, "variant must be 0 ... 4");
+    if (opts && (opts->variant < 0 || opts->variant > 5)) return fail(GBD_EINVAL, "variant must be 0 ... 5");
     int rows = 32, waves = 4;  // 32 rows: rotor form; 16 where the form resolves otherwise
     int64_t pairs = 0, n_max = 0;
     for (int32_t i = 0; i < n_inst; i++) {

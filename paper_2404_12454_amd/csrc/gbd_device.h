@@ -82,9 +82,32 @@ __device__ inline double2 rotor_sigma(double p5, double l5, double dy, int k) {
 // receive the truncation factor's coefficients at j - (n - n_cut); their
 // FLAG_STEEP / FLAG_CROSS are not reported (they are evaluated by the
 // direct form of their own kernel).
+// log2 of the largest modulus of a separable factor's envelope 2^(c1 d + c2 d^2)
+// over the pixel offsets d_k = d0 + k step, k = 0 .. n-1, of one grid axis:
+// the lattice points at both ends and, for a decaying envelope, the two next
+// to its vertex (a grid that misses the spot must not be bounded by the spot)
+__device__ inline double log2_envelope_max(double c1, double c2, double d0, double step, int n) {
+    if (n <= 0) return 0.0;
+    auto f = [&](int k) {
+        const double d = d0 + k * step;
+        return c1 * d + c2 * d * d;
+    };
+    double m = fmax(f(0), f(n - 1));
+    if (c2 < 0.0 && n > 2) {
+        const double kv = fmin(fmax((-c1 / (2.0 * c2) - d0) / step, 0.0), (double)(n - 1));
+        const int k = (int)floor(kv);
+        m = fmax(m, fmax(f(k), f(k + 1 < n ? k + 1 : k)));
+    }
+    return m;
+}
+
+// sep_peak (optional): log2 of the largest modulus of the beamlet's term over
+// the grid, U's part of it stored in the Rec32 record (pad) for the FP16
+// separable form's range balancing; -inf for a beamlet that contributes nothing.
 __device__ inline uint32_t setup_one(const BeamletsDev &b, const PlaneGeom &pl, double gturns, int64_t j,
                                      Rec64 *r64, Rec32 *r32, RecHG64 *h64 = nullptr, RecHG32 *h32 = nullptr,
-                                     RecCut64 *c64 = nullptr, RecCut32 *c32 = nullptr, bool sigma32 = true) {
+                                     RecCut64 *c64 = nullptr, RecCut32 *c32 = nullptr, bool sigma32 = true,
+                                     float *sep_peak = nullptr) {
     const double *M = b.abcd + (b.n_abcd == 1 ? 0 : 16 * j);
     double A[2][2], B[2][2], C[2][2], D[2][2];
 #pragma unroll
@@ -363,6 +386,15 @@ __device__ inline uint32_t setup_one(const BeamletsDev &b, const PlaneGeom &pl, 
         const float dyf = (float)pl.dy;
         o32.u2 = o32.m[5] * (dyf * dyf);
         o32.s2 = exp2f(fminf(2.0f * o32.u2, 1.0f));
+        {
+            // separable factors' moduli over the grid: |U| <= 2^umax, |V| <= 2^vmax
+            const double a0 = -0.5 * (pl.nx - 1) * pl.dx, b0 = -0.5 * (pl.ny - 1) * pl.dy;
+            const double umax = (double)o32.m[0] + log2_envelope_max(o32.m[1], o32.m[3], a0 - arho, pl.dx, pl.nx);
+            const double vmax = log2_envelope_max(o32.m[2], o32.m[5], b0 - brho, pl.dy, pl.ny);
+            const bool ok = isfinite(umax) && isfinite(vmax);
+            o32.pad = ok ? (float)umax : 0.0f;
+            if (sep_peak) *sep_peak = ok ? (float)(umax + vmax) : -INFINITY;
+        }
         // rotor form: sigma^(k^2), rounded from FP64 (else left to
         // sigma32_kernel, run only before a rotor-form evaluation)
         if (sigma32) {

@@ -269,9 +269,11 @@ hipError_t launch_mlp_colsum(const float *dZ, int B, int W, float *db, hipStream
 hipError_t launch_mlp_adamw(float *p, const float *g, float *m, float *v, int64_t n, float lr, float b1, float b2,
                             float eps, float wd, float c1, float c2, hipStream_t s);
 
-// status: a device word, zero on entry, that receives the OR of the
-// beamlets' FLAG_* bits; status_next: another word, set to zero for the
-// next setup (the host alternates the two, so no separate clear is needed).
+// status: two device words, zero on entry: [0] receives the OR of the
+// beamlets' FLAG_* bits, [1] the largest beamlet term modulus over the grid
+// as ceil(log2) + 2048 (0: none; the FP16 separable form's range); and
+// status_next: the next setup's two words, set to zero (the host alternates
+// the pairs, so no separate clear is needed).
 hipError_t launch_setup(const BeamletsDev &b, const PlaneGeom &pl, double global_turns, Rec64 *r64,
                         Rec32 *r32, RecHG64 *h64, RecHG32 *h32, RecCut64 *c64, RecCut32 *c32,
                         uint32_t *status, uint32_t *status_next, hipStream_t s);
@@ -307,6 +309,11 @@ hipError_t launch_reduce(int precision, const EvalGeom &g, int32_t nseg2, const 
                          hipStream_t s);
 inline size_t reduce_wide_offset(int32_t nseg2, int64_t M) { return ((size_t)nseg2 * (size_t)M * 8 + 15) & ~(size_t)15; }
 
+// Issue-rate probe (gbd_probe.hip): `blocks` workgroups of 256 threads,
+// `iters` rounds of one instruction class (gbd_issue_probe's classes);
+// sink is never written (its store is guarded by a condition false at run time).
+hipError_t launch_issue_probe(int cls, int blocks, int iters, float *sink, hipStream_t s);
+
 // Zeroes `bytes` bytes at p (16-byte aligned) with a kernel, not a memset
 // node (for callers that capture the stream into a graph).
 hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t s);
@@ -334,5 +341,16 @@ hipError_t launch_eval_sep64(const EvalGeom &g, const Rec64 *rec, const RecHG64 
 // launch_reduce.
 hipError_t launch_eval_sep(const EvalGeom &g, const Rec32 *rec, const RecHG32 *hg, float2 *partial, float2 *out,
                            hipStream_t s);
+
+// The same form for fundamental beamlets on FP16 MFMA (v_mfma_f32_16x16x32_f16)
+// with every factor split into FP16 hi and lo halves: beamlet j's U factor is
+// scaled by 2^(kSepHalfExp - u_j) (u_j = log2 of its largest modulus over the
+// grid, Rec32::pad) and its V factor by 2^(scale - kSepHalfExp + u_j), so both
+// stay below 2^kSepHalfExp and the accumulators hold the field times
+// 2^scale (scale = 2 kSepHalfExp - P, 2^P the largest term over the grid,
+// from the setup); partials and output are written descaled.
+constexpr int kSepHalfExp = 14;
+hipError_t launch_eval_seph(const EvalGeom &g, const Rec32 *rec, int scale, float2 *partial, float2 *out,
+                            hipStream_t s);
 
 }  // namespace gbd

@@ -27,10 +27,20 @@ __global__ void __launch_bounds__(256) setup_kernel(BeamletsDev b, PlaneGeom pl,
                                                     uint32_t *__restrict__ status,
                                                     uint32_t *__restrict__ status_next) {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j == 0) *status_next = 0u;  // the next setup's flag word (not used by this one)
-    if (j >= b.n) return;
-    const uint32_t flag = setup_one(b, pl, gturns, j, r64, r32, h64, h32, c64, c32, false);
+    if (j == 0) {  // the next setup's flag and peak words (not used by this one)
+        status_next[0] = 0u;
+        status_next[1] = 0u;
+    }
+    float peak = -INFINITY;
+    uint32_t flag = 0;
+    if (j < b.n) flag = setup_one(b, pl, gturns, j, r64, r32, h64, h32, c64, c32, false, &peak);
     if (flag) atomicOr(status, flag);
+    // status[1]: the largest term modulus of any beamlet over the grid, as
+    // ceil(log2) + 2048 clamped to [1, 4095] (0: none), one atomic per wavefront
+    uint32_t key = isfinite(peak) ? (uint32_t)fminf(fmaxf(ceilf(peak) + 2048.0f, 1.0f), 4095.0f) : 0u;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) key = max(key, (uint32_t)__shfl_xor((int)key, o));
+    if ((threadIdx.x & 63) == 0 && key) atomicMax(status + 1, key);
 }
 
 // The rotor forms' sigma^(k^2) tables, k = 1..16, from the FP64 records on

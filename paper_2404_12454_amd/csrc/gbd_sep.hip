@@ -83,7 +83,57 @@ __global__ void __launch_bounds__(64 * k3WX * k3WY) eval_sep_kernel(EvalGeom g, 
         }
 }
 
+// FP16 halves form (fundamental beamlets): the same tiles and stores, the
+// accumulators descaled by 2^-scale (exact: a power of two).
+__global__ void __launch_bounds__(64 * k3WX * k3WY) eval_seph_kernel(EvalGeom g, const Rec32 *__restrict__ rec,
+                                                                      int scale, float2 *__restrict__ partial,
+                                                                      float2 *__restrict__ out) {
+    __shared__ SepHLds L;
+    const int w = work_item(blockIdx.x, gridDim.x);
+    if (w >= g.work) return;
+    const int tiles = g.tiles_x * g.tiles_y;
+    const int seg = w / tiles;
+    const int t = w - seg * tiles;
+    const int ty = t / g.tiles_x, tx = t - ty * g.tiles_x;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int wx = wv % k3WX, wy = wv / k3WX;
+    const int x0 = (tx * k3WX + wx) * 16 * k3BX, y0 = (ty * k3WY + wy) * 16 * k3BY;
+    const int li = lane & 15, lk = lane >> 4;
+    const SepGeom sg{g.nx, g.ny, g.a0, g.b0, g.dx, g.dy};
+    const int64_t jb = (int64_t)seg * g.seg_len;
+    const int64_t je = min(g.n, jb + g.seg_len);
+    f4 accR[k3BY][k3BX], accI[k3BY][k3BX];
+    sep_accumulate_h(sg, rec, jb, je, tx, ty, scale, L, accR, accI);
+
+    const int64_t M = (int64_t)g.nx * g.ny;
+#pragma unroll
+    for (int p = 0; p < k3BY; p++)
+#pragma unroll
+        for (int q = 0; q < k3BX; q++) {
+            const int ix = x0 + 16 * q + li;
+            if (ix >= g.nx) continue;
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+                const int iy = y0 + 16 * p + 4 * lk + e;
+                if (iy >= g.ny) continue;
+                const int64_t px = (int64_t)iy * g.nx + ix;
+                const float2 v = make_float2(ldexpf(accR[p][q][e], -scale), ldexpf(accI[p][q][e], -scale));
+                if (g.nseg == 1)
+                    out[px] = v;
+                else
+                    partial[(int64_t)seg * M + px] = v;
+            }
+        }
+}
+
 }  // namespace
+
+hipError_t launch_eval_seph(const EvalGeom &g, const Rec32 *rec, int scale, float2 *partial, float2 *out,
+                            hipStream_t s) {
+    const int grid = (g.work + 7) / 8 * 8;
+    eval_seph_kernel<<<grid, 64 * k3WX * k3WY, 0, s>>>(g, rec, scale, partial, out);
+    return hipGetLastError();
+}
 
 hipError_t launch_eval_sep(const EvalGeom &g, const Rec32 *rec, const RecHG32 *hg, float2 *partial, float2 *out,
                            hipStream_t s) {

@@ -232,5 +232,178 @@ __device__ inline void sep_accumulate_3m(const SepGeom &g, const Rec32 *__restri
         }
 }
 
+// ---------------------------------------------------------------------------
+// The same contraction on FP16 MFMA (v_mfma_f32_16x16x32_f16: 16 x 16 x 32
+// per instruction in a quarter of the issue time of FP32's 16 x 16 x 4).
+// Every factor x (FP32) is split into FP16 halves x = hi + lo + r,
+// hi = fp16(x), lo = fp16(x - hi), |r| <= 2^-22 |x| for |x| >= 2^-3 (lo
+// normal) and |r| <= 2^-25 below; products of halves are exact in FP32, so
+// with all four hi/lo products
+//   V U = Vh Uh + Vh Ul + Vl Uh + Vl Ul
+// a term carries only the two splits' errors.
+//
+// K layout: the 32 K slots of one instruction are 16 beamlets x (re, im):
+// lane group l / 16 supplies beamlets 4 (l / 16) ... + 3 of a pass of 16,
+// two slots each, so every operand register holds one beamlet's packed
+// (re, im) pair and no value appears twice in an operand:
+//   B_h = (Ur_h, Ui_h), B_l = (Ur_l, Ui_l)                     (U, columns)
+//   A_h = (Vr_h, -Vi_h), A_l = (Vr_l, -Vi_l)  ->  Re: A B = Vr Ur - Vi Ui
+//   W_h = (Vi_h, Vr_h),  W_l = (Vi_l, Vr_l)   ->  Im: W B = Vi Ur + Vr Ui
+// and a pass of 16 beamlets takes 4 instructions (h/l x h/l) per sum and
+// block, 8 accumulator VGPRs per block.  The factors are formed, split and
+// packed once, by the lane that publishes them to LDS; the readers load
+// each operand with one 16-byte read.
+//
+// FP16's range (largest 65504, spacing 2^-24 below 2^-14) is met by scaling:
+// beamlet j's U by 2^(E - u_j), its V by 2^(scale - E + u_j) (E =
+// kSepHalfExp, u_j its U modulus bound over the grid, 2^scale the common
+// factor), so every factor is below 2^E and a term's error stays below
+// 2^-21 of itself or 2^-38 of the largest term, whichever is larger.
+typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+typedef _Float16 h8 __attribute__((ext_vector_type(8)));
+
+// (re, im) as two packed FP16 pairs: hi = (fp16(re), fp16(im)), lo the
+// rounded remainders (round to nearest even throughout)
+__device__ inline void split_halves(float re, float im, uint32_t &hi, uint32_t &lo) {
+    // re and im as the FP32 values they are (not re-formed from the product
+    // that made them, which could round hi differently in its two uses)
+    asm("" : "+v"(re), "+v"(im));
+    hi = __builtin_bit_cast(uint32_t, h2{(_Float16)re, (_Float16)im});
+    // lo = fp16(x - hi) in one mixed-precision fused multiply-add per half
+    // (FP32 x, FP16 hi from the packed pair, one rounding to FP16): the low
+    // half of lo from re and hi's low half, its high half from im and hi's
+    // high half (op_sel picks the half, op_sel_hi marks the FP16 source)
+    asm("v_fma_mixlo_f16 %0, %1, 1.0, -%2 op_sel_hi:[0,0,1]\n\t"
+        "v_fma_mixhi_f16 %0, %3, 1.0, -%2 op_sel:[0,0,1] op_sel_hi:[0,0,1]"
+        : "=&v"(lo)
+        : "v"(re), "v"(hi), "v"(im));
+}
+
+// (a, b) -> (b, a) of a packed FP16 pair
+__device__ inline uint32_t swap_halves(uint32_t v) { return (v >> 16) | (v << 16); }
+
+// Passes of 16 beamlets between barriers; LDS per buffer and pass: U
+// (hi, lo) 20 KiB, V (A_h, A_l, W_h, W_l) 40 KiB, so one pass per barrier
+// (120 KiB double-buffered).  A pixel's 16 beamlets sit in a row of
+// kHRow = 20 words: the 16 lanes of a lane group then read 16-byte operands
+// from 16 distinct groups of 4 banks (20 l mod 64 is distinct for
+// l = 0 ... 15), and a wavefront's 64 single-word writes hit 64 distinct
+// banks (rows 64 bytes apart put 16 lanes on 4 bank groups).
+constexpr int kHPasses = 1, kHRow = 20;
+struct SepHLds {
+    // [buffer][pass][range][block][part][pixel in block][beamlet in pass]
+    uint32_t lu[2][kHPasses][k3WX][k3BX][2][16][kHRow];
+    uint32_t lv[2][kHPasses][k3WY][k3BY][4][16][kHRow];
+};
+
+__device__ inline h8 operand(const uint32_t *p) { return __builtin_bit_cast(h8, *reinterpret_cast<const uint4 *>(p)); }
+
+// As sep_accumulate_3m (same tiles, segment walk and record prefetch two
+// quads ahead) for fundamental beamlets in FP16 halves; accR / accI hold the
+// field times 2^scale.
+__device__ inline void sep_accumulate_h(const SepGeom &g, const Rec32 *__restrict__ rec, int64_t jb, int64_t je,
+                                        int tx, int ty, int scale, SepHLds &L, f4 (&accR)[k3BY][k3BX],
+                                        f4 (&accI)[k3BY][k3BX]) {
+    constexpr int Q = 4 * kHPasses;  // quads of beamlets per barrier
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int wx = wv % k3WX, wy = wv / k3WX;
+    const int x0 = (tx * k3WX + wx) * 16 * k3BX, y0 = (ty * k3WY + wy) * 16 * k3BY;
+    const int li = lane & 15, lk = lane >> 4;
+    auto &lu = L.lu;
+    auto &lv = L.lv;
+
+    const int ix = x0 + 16 * wy + li, iy = y0 + 16 * wx + li;
+    const float mx = ix < g.nx ? 0.0f : -INFINITY, my = iy < g.ny ? 0.0f : -INFINITY;
+    const double ax = g.a0 + ix * g.dx, by = g.b0 + iy * g.dy;
+    const float axf = (float)ax, byf = (float)by;
+    const float E = (float)kSepHalfExp, sc = (float)scale;
+    struct FieldsH {
+        Fields f;
+        float u;  // log2 bound of |U| over the grid (Rec32::pad)
+    };
+    auto load = [&](int64_t j) {
+        FieldsH h;
+        h.f = load_fields<false>(rec, nullptr, j, jb, je);
+        h.u = rec[j < je ? j : jb].pad;
+        return h;
+    };
+    // quad qd of a barrier interval: beamlet 4 qd + lk, i.e. beamlet
+    // 4 (qd % 4) + lk of pass qd / 4
+    auto publish = [&](const FieldsH &h, int buf, int qd) {
+        const Fields &f = h.f;
+        float ur, ui, vr, vi;
+        const float dxf = axf - f.arf, dyf = byf - f.brf;
+        factor(ax - f.arho, dxf, f.p0, f.p1, f.p3, (f.m0 + (E - h.u)) + (f.mbias + mx), f.m1, f.m3, ur, ui);
+        factor(by - f.brho, dyf, 0.0, f.p2, f.p5, (sc - E + h.u) + my, f.m2, f.m5, vr, vi);
+        uint32_t uh, ul, vh, vl;
+        split_halves(ur, ui, uh, ul);
+        split_halves(vr, vi, vh, vl);
+        const int ps = qd >> 2, b = 4 * (qd & 3) + lk;
+        lu[buf][ps][wx][wy][0][li][b] = uh;
+        lu[buf][ps][wx][wy][1][li][b] = ul;
+        lv[buf][ps][wy][wx][0][li][b] = vh ^ 0x80000000u;
+        lv[buf][ps][wy][wx][1][li][b] = vl ^ 0x80000000u;
+        lv[buf][ps][wy][wx][2][li][b] = swap_halves(vh);
+        lv[buf][ps][wy][wx][3][li][b] = swap_halves(vl);
+    };
+
+#pragma unroll
+    for (int p = 0; p < k3BY; p++)
+#pragma unroll
+        for (int q = 0; q < k3BX; q++) accR[p][q] = accI[p][q] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+
+    static_assert(Q % 2 == 0, "the two-slot field ring needs an even number of quads per barrier");
+    constexpr int P = 4 * Q;  // beamlets per barrier
+#pragma unroll
+    for (int qd = 0; qd < Q; qd++) publish(load(jb + 4 * qd + lk), 0, qd);
+    FieldsH fn[2] = {load(jb + P + lk), load(jb + P + 4 + lk)};
+    __syncthreads();
+    int buf = 0;
+    for (int64_t j0 = jb; j0 < je; j0 += P) {
+        const bool more = j0 + P < je;
+#pragma unroll
+        for (int ps = 0; ps < kHPasses; ps++) {
+            h8 bh[k3BX], bl[k3BX], ah[k3BY], al[k3BY], wh[k3BY], wl[k3BY];
+#pragma unroll
+            for (int q = 0; q < k3BX; q++) {
+                bh[q] = operand(&lu[buf][ps][wx][q][0][li][4 * lk]);
+                bl[q] = operand(&lu[buf][ps][wx][q][1][li][4 * lk]);
+            }
+#pragma unroll
+            for (int p = 0; p < k3BY; p++) {
+                ah[p] = operand(&lv[buf][ps][wy][p][0][li][4 * lk]);
+                al[p] = operand(&lv[buf][ps][wy][p][1][li][4 * lk]);
+                wh[p] = operand(&lv[buf][ps][wy][p][2][li][4 * lk]);
+                wl[p] = operand(&lv[buf][ps][wy][p][3][li][4 * lk]);
+            }
+            // the next interval's quads of this pass, formed between the products
+#pragma unroll
+            for (int k = 0; k < 4; k++) {
+                const int qd = 4 * ps + k;
+                if (more) {
+                    publish(fn[qd % 2], buf ^ 1, qd);
+                    fn[qd % 2] = load(j0 + P + 4 * (qd + 2) + lk);
+                }
+                // products of block row p = k / 2, columns 2 (k % 2) ... + 1
+                const int p = k >> 1;
+#pragma unroll
+                for (int qq = 0; qq < 2; qq++) {
+                    const int q = 2 * (k & 1) + qq;
+                    accR[p][q] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[p], bh[q], accR[p][q], 0, 0, 0);
+                    accI[p][q] = __builtin_amdgcn_mfma_f32_16x16x32_f16(wh[p], bh[q], accI[p][q], 0, 0, 0);
+                    accR[p][q] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[p], bl[q], accR[p][q], 0, 0, 0);
+                    accI[p][q] = __builtin_amdgcn_mfma_f32_16x16x32_f16(wh[p], bl[q], accI[p][q], 0, 0, 0);
+                    accR[p][q] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al[p], bh[q], accR[p][q], 0, 0, 0);
+                    accI[p][q] = __builtin_amdgcn_mfma_f32_16x16x32_f16(wl[p], bh[q], accI[p][q], 0, 0, 0);
+                    accR[p][q] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al[p], bl[q], accR[p][q], 0, 0, 0);
+                    accI[p][q] = __builtin_amdgcn_mfma_f32_16x16x32_f16(wl[p], bl[q], accI[p][q], 0, 0, 0);
+                }
+            }
+        }
+        __syncthreads();
+        buf ^= 1;
+    }
+}
+
 }  // namespace sep
 }  // namespace gbd

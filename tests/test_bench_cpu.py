@@ -29,7 +29,7 @@ def test_more_than_one_gpu_is_refused():
 def test_separable_roofline_arithmetic():
     b = load_bench()
     N, M, ms = 51468, 512 * 512, 0.8
-    r = b.roofline({"variant": 4, "rows_per_lane": 32, "waves": 8, "segments": 16}, N, M, ms)
+    r = b.roofline({"variant": 5, "rows_per_lane": 32, "waves": 8, "segments": 16}, N, M, ms)
     # Gauss's form: three real multiply-adds (6 flops) per pair on the
     # matrix cores; the textbook complex multiply-add (8 flops) only as a rate
     achieved = 6.0 * N * M / (ms * 1e-3) / 1e12
@@ -38,6 +38,12 @@ def test_separable_roofline_arithmetic():
     assert r["frac"] == pytest.approx(achieved / 157.3, rel=1e-12)
     assert r["frac"] <= 1.0
     assert r["complex_madd_equiv_tflops"] == pytest.approx(achieved * 8.0 / 6.0, rel=1e-12)
+    # FP16 halves: all four hi/lo products of the four real products, 32
+    # flops per pair against the FP16 MFMA peak
+    h = b.roofline({"variant": 4, "rows_per_lane": 32, "waves": 8, "segments": 16}, N, M, ms)
+    assert h["bound"] == "mfma" and h["peak"] == 2500.0
+    assert h["achieved"] == pytest.approx(32.0 * N * M / (ms * 1e-3) / 1e12, rel=1e-12)
+    assert h["frac"] == pytest.approx(h["achieved"] / 2500.0, rel=1e-12) and h["frac"] <= 1.0
 
 
 def test_rotor_instruction_mix_roofline():

@@ -114,26 +114,49 @@ def test_separable_form_is_chosen_and_matches_oracle(ctx):
     check(E4, oracle.eval_field(sc), gbd.GBD_MIXED, "airy32_64 separable")
 
 
+@pytest.mark.parametrize("variant", [0, 5])
 @pytest.mark.parametrize("nx,ny,seg", [(70, 45, 1), (70, 45, 3), (129, 200, 0), (1, 1, 1), (65, 1, 2), (1, 70, 0)])
-def test_separable_form_ragged_defocused_off_axis(ctx, nx, ny, seg):
+def test_separable_form_ragged_defocused_off_axis(ctx, nx, ny, seg, variant):
     """Grids that leave every 16 x 16 block, wavefront and workgroup tile
-    partly empty, beamlet counts not a multiple of the MFMA's K = 4, a field
-    angle and a defocused plane (strong per-beamlet phase slopes)."""
+    partly empty, beamlet counts not a multiple of the quad of beamlets an
+    MFMA step takes, a field angle and a defocused plane (strong per-beamlet
+    phase slopes); the automatic form (FP16 halves) and the FP32 one (5)."""
     sc = scenes.airy_scene(21, npix=nx, npix_y=ny, half_span_lamF=6.0, field_angle=(1e-3, -5e-4), z0=30e-6)
     assert sc.n % 4 != 0
     b = gbd.beamlets_from_scene(ctx, sc)
     p = gbd.plane_from_scene(ctx, sc)
     plan = gbd.Plan(ctx, sc.n).setup(b, p)
-    o = dict(segments=seg)
-    assert plan.shape(gbd.GBD_MIXED, opts=o)["variant"] == 4
+    o = dict(segments=seg, variant=variant)
+    assert plan.shape(gbd.GBD_MIXED, opts=o)["variant"] == (variant or 4)
     check(plan.eval(gbd.GBD_MIXED, opts=o).cpu().numpy(), oracle.eval_field(sc), gbd.GBD_MIXED,
-          f"separable {nx}x{ny} seg {seg}")
+          f"separable {nx}x{ny} seg {seg} variant {variant or 4}")
 
 
-@pytest.mark.parametrize("precision", BOTH)
+@pytest.mark.parametrize("scale,spread", [(1e12, 1.0), (1e-12, 1.0), (1.0, 1e-9), (1e6, 1e-14)])
+def test_separable_halves_across_amplitude_ranges(ctx, scale, spread):
+    """The FP16 halves form scales each beamlet's factors into FP16's range
+    from the setup's bounds: uniform amplitudes far from 1, and half of the
+    beamlets weaker by `spread`, on a defocused grid whose envelopes fall
+    off across it; against the oracle and the FP32 separable form."""
+    sc = scenes.airy_scene(24, npix=96, npix_y=80, half_span_lamF=8.0, z0=200e-6)
+    amp = np.asarray(sc.amp, np.float64).reshape(-1, 2) * scale
+    amp[::2] *= spread
+    sc.amp = amp
+    b = gbd.beamlets_from_scene(ctx, sc)
+    p = gbd.plane_from_scene(ctx, sc)
+    plan = gbd.Plan(ctx, sc.n).setup(b, p)
+    assert plan.shape(gbd.GBD_MIXED)["variant"] == 4
+    E4 = plan.eval(gbd.GBD_MIXED).cpu().numpy()
+    E5 = plan.eval(gbd.GBD_MIXED, opts=dict(variant=5)).cpu().numpy()
+    ref = oracle.eval_field(sc)
+    check(E4, ref, gbd.GBD_MIXED, f"halves amplitude x{scale:g}, spread {spread:g}")
+    check(E5, ref, gbd.GBD_MIXED, f"FP32 separable amplitude x{scale:g}, spread {spread:g}")
+
+
+@pytest.mark.parametrize("precision,variant", [(gbd.GBD_FP64, 4), (gbd.GBD_MIXED, 4), (gbd.GBD_MIXED, 5)])
 @pytest.mark.parametrize("n,seg", [(1, 1), (2, 1), (5, 1), (15, 1), (16, 1), (17, 1), (33, 1), (33, 4), (37, 5),
                                    (64, 3), (100, 7)])
-def test_separable_form_short_segments(ctx, precision, n, seg):
+def test_separable_form_short_segments(ctx, precision, variant, n, seg):
     """The separable forms take beamlets in passes of four quads (16) between
     barriers: segments shorter than a pass, a pass and a quad, and ragged last
     passes and quads, on a grid smaller than one workgroup tile."""
@@ -144,10 +167,10 @@ def test_separable_form_short_segments(ctx, precision, n, seg):
     b = gbd.beamlets_from_scene(ctx, sc)
     p = gbd.plane_from_scene(ctx, sc)
     plan = gbd.Plan(ctx, sc.n).setup(b, p)
-    o = dict(segments=seg, variant=4)
-    assert plan.shape(precision, opts=o)["variant"] == 4
+    o = dict(segments=seg, variant=variant)
+    assert plan.shape(precision, opts=o)["variant"] == (variant if precision == gbd.GBD_MIXED else 4)
     check(plan.eval(precision, opts=o).cpu().numpy(), oracle.eval_field(sc), precision,
-          f"separable n {n} seg {seg}")
+          f"separable n {n} seg {seg} variant {variant}")
 
 
 def test_consecutive_setups_of_one_plan_keep_their_own_flags(ctx):
@@ -468,7 +491,7 @@ def test_errors_are_reported_before_any_write(ctx):
     # output buffer too small; unknown mixed form
     good = gbd.beamlets_from_scene(ctx, sc)
     with pytest.raises(gbd.GbdError) as e:
-        gbd.gbd_eval(ctx, good, p, gbd.GBD_MIXED, out=sentinel, opts=dict(variant=5))
+        gbd.gbd_eval(ctx, good, p, gbd.GBD_MIXED, out=sentinel, opts=dict(variant=6))
     assert e.value.code == -1
     small = torch.empty((3, 4), dtype=torch.complex128, device="cuda")
     with pytest.raises(gbd.GbdError) as e:
