@@ -100,11 +100,11 @@ SEP_COMPLEX_MADD_FLOPS = 8.0
 # the FP64 separable form multiplies in four real FP64 MFMA products
 SEP64_FLOPS_PER_PAIR = 8.0
 # FP16 halves form (variant 4 for fundamental beamlets): each factor as FP16
-# hi + lo, all four hi/lo products of the four real products of the complex
-# multiply: 16 FP16 multiply-adds (32 flops) per pair on the matrix cores,
-# against the FP16 MFMA peak
+# hi + lo, the hi hi, hi lo and lo hi products of the four real products of
+# the complex multiply: 12 FP16 multiply-adds (24 flops) per pair on the
+# matrix cores, against the FP16 MFMA peak
 MFMA_FP16_TFLOPS = 2500.0
-SEPH_FLOPS_PER_PAIR = 32.0
+SEPH_FLOPS_PER_PAIR = 24.0
 # per lane and pass between barriers (16 beamlets x 64 x 32 pixels of one
 # wavefront), counted in the compiled loop: 40 FP64, 56 FP32, 24
 # transcendental and 62 other VALU instructions (the factors shared by 8

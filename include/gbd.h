@@ -81,12 +81,13 @@ typedef struct {
                                recurrence (anchor x rho^k x sigma^(k^2)); 4 = separable:
                                E = sum_j U_j(x) V_j(y) as a complex matrix product, for
                                fundamental beamlets on FP16 MFMA with every factor split
-                               into FP16 hi and lo halves (all four hi/lo products, FP32
-                               accumulation; each beamlet's factors scaled by powers of
-                               two into FP16's range from the setup's bounds over the
-                               grid, so a term's error stays below 2^-21 of itself or
-                               2^-38 of the largest term over the grid, whichever is
-                               larger), for higher-order beamlets as 5; 5 = separable
+                               into FP16 hi and lo halves (the hi x hi, hi x lo and
+                               lo x hi products, FP32 accumulation; each beamlet's
+                               factors scaled by powers of two into FP16's range from
+                               the setup's bounds over the grid, so a term's error
+                               stays below 2^-20 of itself or 2^-38 of the largest
+                               term over the grid, whichever is larger), for
+                               higher-order beamlets as 5; 5 = separable
                                on FP32 MFMA in three real products per pair (Gauss's
                                form).  Both: 128 x 128 pixel workgroup tiles
                                (rows_per_lane and waves do not apply; gbd_plan_shape

@@ -343,7 +343,8 @@ hipError_t launch_eval_sep(const EvalGeom &g, const Rec32 *rec, const RecHG32 *h
                            hipStream_t s);
 
 // The same form for fundamental beamlets on FP16 MFMA (v_mfma_f32_16x16x32_f16)
-// with every factor split into FP16 hi and lo halves: beamlet j's U factor is
+// with every factor split into FP16 hi and lo halves (products hi hi, hi lo,
+// lo hi): beamlet j's U factor is
 // scaled by 2^(kSepHalfExp - u_j) (u_j = log2 of its largest modulus over the
 // grid, Rec32::pad) and its V factor by 2^(scale - kSepHalfExp + u_j), so both
 // stay below 2^kSepHalfExp and the accumulators hold the field times

@@ -237,10 +237,10 @@ __device__ inline void sep_accumulate_3m(const SepGeom &g, const Rec32 *__restri
 // per instruction in a quarter of the issue time of FP32's 16 x 16 x 4).
 // Every factor x (FP32) is split into FP16 halves x = hi + lo + r,
 // hi = fp16(x), lo = fp16(x - hi), |r| <= 2^-22 |x| for |x| >= 2^-3 (lo
-// normal) and |r| <= 2^-25 below; products of halves are exact in FP32, so
-// with all four hi/lo products
-//   V U = Vh Uh + Vh Ul + Vl Uh + Vl Ul
-// a term carries only the two splits' errors.
+// normal) and |r| <= 2^-25 below; products of halves are exact in FP32, and
+//   V U = Vh Uh + Vh Ul + Vl Uh  (+ Vl Ul, at most 2^-22 |V U|, left out)
+// so a term carries the two splits' errors and the dropped product:
+// within 2^-20.4 of itself.
 //
 // K layout: the 32 K slots of one instruction are 16 beamlets x (re, im):
 // lane group l / 16 supplies beamlets 4 (l / 16) ... + 3 of a pass of 16,
@@ -249,7 +249,7 @@ __device__ inline void sep_accumulate_3m(const SepGeom &g, const Rec32 *__restri
 //   B_h = (Ur_h, Ui_h), B_l = (Ur_l, Ui_l)                     (U, columns)
 //   A_h = (Vr_h, -Vi_h), A_l = (Vr_l, -Vi_l)  ->  Re: A B = Vr Ur - Vi Ui
 //   W_h = (Vi_h, Vr_h),  W_l = (Vi_l, Vr_l)   ->  Im: W B = Vi Ur + Vr Ui
-// and a pass of 16 beamlets takes 4 instructions (h/l x h/l) per sum and
+// and a pass of 16 beamlets takes 3 instructions (hh, hl, lh) per sum and
 // block, 8 accumulator VGPRs per block.  The factors are formed, split and
 // packed once, by the lane that publishes them to LDS; the readers load
 // each operand with one 16-byte read.
@@ -258,7 +258,7 @@ __device__ inline void sep_accumulate_3m(const SepGeom &g, const Rec32 *__restri
 // beamlet j's U by 2^(E - u_j), its V by 2^(scale - E + u_j) (E =
 // kSepHalfExp, u_j its U modulus bound over the grid, 2^scale the common
 // factor), so every factor is below 2^E and a term's error stays below
-// 2^-21 of itself or 2^-38 of the largest term, whichever is larger.
+// 2^-20 of itself or 2^-38 of the largest term, whichever is larger.
 typedef _Float16 h2 __attribute__((ext_vector_type(2)));
 typedef _Float16 h8 __attribute__((ext_vector_type(8)));
 
@@ -290,6 +290,7 @@ __device__ inline uint32_t swap_halves(uint32_t v) { return (v >> 16) | (v << 16
 // l = 0 ... 15), and a wavefront's 64 single-word writes hit 64 distinct
 // banks (rows 64 bytes apart put 16 lanes on 4 bank groups).
 constexpr int kHPasses = 1, kHRow = 20;
+constexpr bool kHLoLo = false;  // the lo x lo product (2^-22 relative) is left out
 struct SepHLds {
     // [buffer][pass][range][block][part][pixel in block][beamlet in pass]
     uint32_t lu[2][kHPasses][k3WX][k3BX][2][16][kHRow];
@@ -395,8 +396,10 @@ __device__ inline void sep_accumulate_h(const SepGeom &g, const Rec32 *__restric
                     accI[p][q] = __builtin_amdgcn_mfma_f32_16x16x32_f16(wh[p], bl[q], accI[p][q], 0, 0, 0);
                     accR[p][q] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al[p], bh[q], accR[p][q], 0, 0, 0);
                     accI[p][q] = __builtin_amdgcn_mfma_f32_16x16x32_f16(wl[p], bh[q], accI[p][q], 0, 0, 0);
-                    accR[p][q] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al[p], bl[q], accR[p][q], 0, 0, 0);
-                    accI[p][q] = __builtin_amdgcn_mfma_f32_16x16x32_f16(wl[p], bl[q], accI[p][q], 0, 0, 0);
+                    if constexpr (kHLoLo) {
+                        accR[p][q] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al[p], bl[q], accR[p][q], 0, 0, 0);
+                        accI[p][q] = __builtin_amdgcn_mfma_f32_16x16x32_f16(wl[p], bl[q], accI[p][q], 0, 0, 0);
+                    }
                 }
             }
         }
