@@ -198,7 +198,7 @@ int gbd_beamlets_hg(gbd_ctx_t ctx, gbd_beamlets_t *out, int64_t n, double lambda
  * the cut beamlets after the whole ones: the whole ones are evaluated in the
  * chosen form (FP64, direct, stepped, rotor or separable), the cut ones by a
  * direct-form kernel with the complex error function (Weideman's rational
- * approximation of the Faddeeva function, N = 40 in FP64 and 20 in the mixed
+ * approximation of the Faddeeva function, N = 40 in FP64 and 16 in the mixed
  * form), both into the same ordered segment sums.  Planes normal to the axis
  * only (else GBD_EINVAL from the setup); a plane through an exact image of
  * the input plane (B' = 0, an infinitely sharp edge) gives GBD_EINVAL
