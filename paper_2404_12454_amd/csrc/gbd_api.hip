@@ -38,7 +38,7 @@ struct DevBuf {
 };
 
 struct BatchWork {
-    DevBuf rec, inst, offs, eval, items, e0, part, metrics, flags, point;
+    DevBuf rec, inst, offs, eval, items, e0, part, metrics, flags, point, peaks;
     uint32_t *host_flags = nullptr;  // pinned: status, bad instance
 };
 
@@ -680,7 +680,8 @@ int grow(DevBuf &b, size_t bytes, const char *what) {
 }
 
 void batch_free(BatchWork &w) {
-    DevBuf *all[] = {&w.rec, &w.inst, &w.offs, &w.eval, &w.items, &w.e0, &w.part, &w.metrics, &w.flags, &w.point};
+    DevBuf *all[] = {&w.rec, &w.inst, &w.offs, &w.eval, &w.items, &w.e0, &w.part, &w.metrics, &w.flags, &w.point,
+                     &w.peaks};
     for (DevBuf *b : all)
         if (b->p) (void)hipFree(b->p);
     if (w.host_flags) (void)hipHostFree(w.host_flags);
@@ -1312,7 +1313,8 @@ int gbd_eval_batch(gbd_ctx_t ctx, int32_t n_inst, const gbd_beamlets_t *bs, cons
         (rc = grow(w.e0, n_inst * sizeof(double2), "batch normalisation")) ||
         (rc = grow(w.part, (size_t)std::max<int64_t>(n_items, 1) * PS * sizeof(double), "batch partials")) ||
         (rc = grow(w.metrics, (size_t)n_inst * (2 + n_zones) * sizeof(double), "batch metrics")) ||
-        (rc = grow(w.flags, 4 * sizeof(uint32_t), "batch flags")))
+        (rc = grow(w.flags, 4 * sizeof(uint32_t), "batch flags")) ||
+        (rc = grow(w.peaks, n_inst * sizeof(uint32_t), "batch peaks")))
         return rc;
     if (!w.host_flags) HIP_TRY(hipHostMalloc(&w.host_flags, 4 * sizeof(uint32_t), hipHostMallocDefault), "hipHostMalloc");
     hipStream_t st = ctx->stream;
@@ -1321,10 +1323,15 @@ int gbd_eval_batch(gbd_ctx_t ctx, int32_t n_inst, const gbd_beamlets_t *bs, cons
     uint32_t *flags = static_cast<uint32_t *>(w.flags.p);  // [0] status, [1] first bad instance, [2] queue head
     HIP_TRY(hipMemsetAsync(flags, 0, sizeof(uint32_t), st), "hipMemsetAsync");
     HIP_TRY(hipMemsetAsync(flags + 1, 0x7f, sizeof(uint32_t), st), "hipMemsetAsync");
+    HIP_TRY(hipMemsetAsync(w.peaks.p, 0, n_inst * sizeof(uint32_t), st), "hipMemsetAsync");
     HIP_TRY(launch_batch_setup(static_cast<BatchInst *>(w.inst.p), static_cast<int64_t *>(w.offs.p), n_inst, total,
-                               static_cast<Rec32 *>(w.rec.p), flags, reinterpret_cast<int32_t *>(flags + 1), st),
+                               static_cast<Rec32 *>(w.rec.p), flags, reinterpret_cast<int32_t *>(flags + 1),
+                               static_cast<uint32_t *>(w.peaks.p), st),
             "batch setup launch");
+    std::vector<uint32_t> peaks(n_inst);
     HIP_TRY(hipMemcpyAsync(w.host_flags, flags, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, st), "status copy");
+    HIP_TRY(hipMemcpyAsync(peaks.data(), w.peaks.p, n_inst * sizeof(uint32_t), hipMemcpyDeviceToHost, st),
+            "peak copy");
     HIP_TRY(hipStreamSynchronize(st), "hipStreamSynchronize");
     const uint32_t stat = w.host_flags[0];
     const int32_t bad = (int32_t)w.host_flags[1];
@@ -1336,6 +1343,8 @@ int gbd_eval_batch(gbd_ctx_t ctx, int32_t n_inst, const gbd_beamlets_t *bs, cons
     // instance fits one segment of the single evaluation (kSepMaxSegLen);
     // the rotor form folds 128-beamlet tile sums and stays accurate at any N
     const int form = pick_form(GBD_MIXED, stat, opts, n_max <= kSepMaxSegLen);
+    // the separable form in FP16 halves unless FP32 MFMA is requested (variant 5)
+    const bool half = form == 3 && !(opts && opts->variant == 5);
     if (rows == 32 && form != 2) rows = 16;  // 32 rows is a rotor-form shape
 
     // evaluation tables; the work list takes instances largest first (LPT),
@@ -1362,6 +1371,7 @@ int gbd_eval_batch(gbd_ctx_t ctx, int32_t n_inst, const gbd_beamlets_t *bs, cons
         e.b0 = -0.5 * (g.ny - 1) * g.dy;
         e.field_off = foff;
         foff += (int64_t)g.nx * g.ny;
+        e.scale = peaks[i] ? 2 * kSepHalfExp - ((int)peaks[i] - 2048) : 0;  // as a single evaluation's setup
     }
     std::vector<int32_t> order(n_inst);
     for (int32_t i = 0; i < n_inst; i++) order[i] = i;
@@ -1402,7 +1412,7 @@ int gbd_eval_batch(gbd_ctx_t ctx, int32_t n_inst, const gbd_beamlets_t *bs, cons
     if (airy)
         HIP_TRY(launch_batch_e0(a.inst, n_inst, a.rec, static_cast<double2 *>(w.e0.p), st), "normalisation launch");
     HIP_TRY(hipMemsetAsync(flags + 2, 0, sizeof(uint32_t), st), "hipMemsetAsync");
-    HIP_TRY(launch_batch_eval(rows, waves, form, ctx->cus, a, st), "batch eval launch");
+    HIP_TRY(launch_batch_eval(rows, waves, form, half, ctx->cus, a, st), "batch eval launch");
     if (airy) {
         HIP_TRY(launch_batch_finalize(a.inst, n_inst, a.part, n_zones, static_cast<double *>(w.metrics.p), st),
                 "finalize launch");

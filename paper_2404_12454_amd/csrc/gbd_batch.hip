@@ -14,6 +14,7 @@
 //                      beamlet's phasor has a cross term: items are
 //                      (instance, 128 x 128 tile), each a 2 x 4-wavefront
 //                      MFMA accumulation over all of the instance's beamlets
+//                      (FP16 halves, or FP32 MFMA when requested)
 //  batch_finalize      per instance, fixed-order sum of its items' partials
 //  airy_kernel         reference irradiance (2 J1(v)/v)^2 in FP64
 #include "gbd_device.h"
@@ -28,9 +29,11 @@ using namespace dev;
 __global__ void __launch_bounds__(256) batch_setup_kernel(const BatchInst *__restrict__ inst,
                                                           const int64_t *__restrict__ offs, int32_t n_inst,
                                                           int64_t total, Rec32 *__restrict__ rec,
-                                                          uint32_t *__restrict__ status, int32_t *__restrict__ bad) {
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= total) return;
+                                                          uint32_t *__restrict__ status, int32_t *__restrict__ bad,
+                                                          uint32_t *__restrict__ peak) {
+    const int64_t j0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool live = j0 < total;
+    const int64_t j = live ? j0 : total - 1;  // a lane past the end repeats the last beamlet, writing nothing
     // instance holding beamlet j: the last i with offs[i] <= j (empty instances skipped)
     int lo = 0, hi = n_inst - 1;
     while (lo < hi) {
@@ -41,9 +44,25 @@ __global__ void __launch_bounds__(256) batch_setup_kernel(const BatchInst *__res
             hi = mid - 1;
     }
     const BatchInst &I = inst[lo];
-    const uint32_t flag = setup_one(I.b, I.pl, I.gturns, j - offs[lo], nullptr, rec + I.rec_off);
+    float pk = -INFINITY;
+    uint32_t flag = 0;
+    if (live)
+        flag = setup_one(I.b, I.pl, I.gturns, j - offs[lo], nullptr, rec + I.rec_off, nullptr, nullptr, nullptr,
+                         nullptr, true, &pk);
     if (flag) atomicOr(status, flag);
     if (flag & FLAG_ERRORS) atomicMin(bad, lo);
+    // the instance's largest term over its grid (the FP16 halves form's
+    // range): one atomic per wavefront when all its lanes hold one instance
+    // (instances are hundreds of beamlets long), else one per lane
+    uint32_t key = (live && isfinite(pk)) ? (uint32_t)fminf(fmaxf(ceilf(pk) + 2048.0f, 1.0f), 4095.0f) : 0u;
+    const int lo0 = __shfl(lo, 0);
+    if (__all(lo == lo0)) {
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) key = max(key, (uint32_t)__shfl_xor((int)key, o));
+        if ((threadIdx.x & 63) == 0 && key) atomicMax(peak + lo0, key);
+    } else if (key) {
+        atomicMax(peak + lo, key);
+    }
 }
 
 // E(0): the same mixed-precision phasor at plane coordinates (0, 0), summed
@@ -173,13 +192,15 @@ __global__ void __launch_bounds__(64 * WAVES) batch_eval_kernel(BatchArgs A) {
 }
 
 // Separable form: the single-instance kernel's accumulation with one beamlet
-// segment (so a field equals gbd_eval's with variant 4 and one segment bit
-// for bit), then the same epilogue from the MFMA accumulators (lane l holds
-// rows 4 (l / 16) + e, column l % 16 of each 16 x 16 block).
+// segment (so a field equals gbd_eval's with the same variant, 4 in FP16
+// halves (HALF) or 5 on FP32 MFMA, and one segment bit for bit), then the
+// same epilogue from the MFMA accumulators (lane l holds rows 4 (l / 16) + e,
+// column l % 16 of each 16 x 16 block).
+template <bool HALF>
 __global__ void __launch_bounds__(64 * sep::k3WX * sep::k3WY) batch_sep_kernel(BatchArgs A) {
     constexpr int WX = sep::k3WX, WY = sep::k3WY, BX = sep::k3BX, BY = sep::k3BY;
     constexpr int WAVES = WX * WY, NQ = 2 + 2 * kMaxZones;
-    __shared__ sep::Sep3Lds<false> L;
+    __shared__ typename std::conditional<HALF, sep::SepHLds, sep::Sep3Lds<false>>::type L;
     __shared__ int s_item;
     __shared__ double red[WAVES][NQ];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -199,8 +220,20 @@ __global__ void __launch_bounds__(64 * sep::k3WX * sep::k3WY) batch_sep_kernel(B
         sep::f4 accR[BY][BX], accI[BY][BX];
         if (I.n > 0) {
             const sep::SepGeom sg{I.nx, I.ny, I.a0, I.b0, I.dx, I.dy};
-            sep::sep_accumulate_3m<false>(sg, A.rec + I.rec_off, nullptr, 0, I.n, tx, ty, L, accR,
-                                                        accI);
+            if constexpr (HALF) {
+                sep::sep_accumulate_h(sg, A.rec + I.rec_off, 0, I.n, tx, ty, I.scale, L, accR, accI);
+#pragma unroll
+                for (int p = 0; p < BY; p++)
+#pragma unroll
+                    for (int q = 0; q < BX; q++)
+#pragma unroll
+                        for (int e = 0; e < 4; e++) {
+                            accR[p][q][e] = ldexpf(accR[p][q][e], -I.scale);
+                            accI[p][q][e] = ldexpf(accI[p][q][e], -I.scale);
+                        }
+            } else {
+                sep::sep_accumulate_3m<false>(sg, A.rec + I.rec_off, nullptr, 0, I.n, tx, ty, L, accR, accI);
+            }
         } else {
 #pragma unroll
             for (int p = 0; p < BY; p++)
@@ -316,9 +349,10 @@ hipError_t launch_batch_eval_t(int cus, const BatchArgs &a, hipStream_t s) {
 }  // namespace
 
 hipError_t launch_batch_setup(const BatchInst *inst, const int64_t *offs, int32_t n_inst, int64_t total, Rec32 *rec,
-                              uint32_t *status, int32_t *bad, hipStream_t s) {
+                              uint32_t *status, int32_t *bad, uint32_t *peak, hipStream_t s) {
     if (total == 0) return hipSuccess;
-    batch_setup_kernel<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(inst, offs, n_inst, total, rec, status, bad);
+    batch_setup_kernel<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(inst, offs, n_inst, total, rec, status, bad,
+                                                                       peak);
     return hipGetLastError();
 }
 
@@ -328,16 +362,21 @@ hipError_t launch_batch_e0(const BatchEval *inst, int32_t n_inst, const Rec32 *r
     return hipGetLastError();
 }
 
-hipError_t launch_batch_eval(int rows, int waves, int form, int cus, const BatchArgs &a, hipStream_t s) {
+hipError_t launch_batch_eval(int rows, int waves, int form, bool half, int cus, const BatchArgs &a, hipStream_t s) {
     if (form == 3) {
         int per_cu = 0;
-        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_sep_kernel,
-                                                                    64 * kSepWavesX * kSepWavesY, 0);
+        hipError_t e = half ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_sep_kernel<true>,
+                                                                           64 * kSepWavesX * kSepWavesY, 0)
+                            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_sep_kernel<false>,
+                                                                           64 * kSepWavesX * kSepWavesY, 0);
         if (e != hipSuccess) return e;
         if (per_cu < 1) per_cu = 1;
         const int grid = (int)min((int64_t)a.n_items, (int64_t)cus * per_cu);
         if (grid <= 0) return hipSuccess;
-        batch_sep_kernel<<<grid, 64 * kSepWavesX * kSepWavesY, 0, s>>>(a);
+        if (half)
+            batch_sep_kernel<true><<<grid, 64 * kSepWavesX * kSepWavesY, 0, s>>>(a);
+        else
+            batch_sep_kernel<false><<<grid, 64 * kSepWavesX * kSepWavesY, 0, s>>>(a);
         return hipGetLastError();
     }
 #define GBD_CASE(R, W)                                                                         \

@@ -183,6 +183,7 @@ struct BatchEval {
     double dx, dy, a0, b0;
     int64_t item_off;   // first work item; an instance's items are contiguous, in tile order
     int64_t field_off;  // element offset of this instance in the optional field output
+    int32_t scale;      // FP16 halves form: its accumulators hold the field times 2^scale
 };
 
 struct BatchArgs {
@@ -200,11 +201,14 @@ struct BatchArgs {
     double zone_r2[kMaxZones + 1];  // squared radii bounding the annular zones
 };
 
+// peak: per instance, the largest beamlet term modulus over the grid as
+// ceil(log2) + 2048 (0: none), the setup kernel's atomic maximum; zero on entry.
 hipError_t launch_batch_setup(const BatchInst *inst, const int64_t *offs, int32_t n_inst, int64_t total,
-                              Rec32 *rec, uint32_t *status, int32_t *bad, hipStream_t s);
+                              Rec32 *rec, uint32_t *status, int32_t *bad, uint32_t *peak, hipStream_t s);
 hipError_t launch_batch_e0(const BatchEval *inst, int32_t n_inst, const Rec32 *rec, double2 *e0, hipStream_t s);
-// form 3: the separable form (rows and waves do not apply)
-hipError_t launch_batch_eval(int rows, int waves, int form, int cus, const BatchArgs &a, hipStream_t s);
+// form 3: the separable form (rows and waves do not apply), in FP16 halves
+// when half (scales from BatchEval::scale), else on FP32 MFMA
+hipError_t launch_batch_eval(int rows, int waves, int form, bool half, int cus, const BatchArgs &a, hipStream_t s);
 hipError_t launch_batch_finalize(const BatchEval *inst, int32_t n_inst, const double *part, int32_t n_zones,
                                  double *metrics, hipStream_t s);
 hipError_t launch_airy(int32_t nx, int32_t ny, double dx, double dy, double vscale, float *out, hipStream_t s);

@@ -55,12 +55,13 @@ def test_batch_fields_bitwise_equal_single_instance(ctx):
     insts = small_instances()
     bs = [gbd.beamlets_from_scene(ctx, s) for s in insts]
     ps = [gbd.plane_from_scene(ctx, s) for s in insts]
-    # the batch's separable form runs on FP32 MFMA: variant 5 of gbd_eval
+    # variant 4: the separable form in FP16 halves (per-instance scale from the
+    # batched setup, as a single evaluation's); 5: on FP32 MFMA
     for rows, waves, variant in ((4, 2, 1), (4, 2, 2), (4, 2, 3), (32, 4, 3), (32, 1, 3), (4, 2, 4), (4, 2, 5)):
         o = dict(rows_per_lane=rows, waves=waves, variant=variant)
         _, fields = gbd.gbd_eval_batch(ctx, bs, ps, fields=True, opts=o)
         for s, b, p, F in zip(insts, bs, ps, fields):
-            E = gbd.gbd_eval(ctx, b, p, gbd.GBD_MIXED, opts=dict(o, segments=1, variant=5 if variant == 4 else variant))
+            E = gbd.gbd_eval(ctx, b, p, gbd.GBD_MIXED, opts=dict(o, segments=1))
             torch.cuda.synchronize()
             assert torch.equal(F.cpu().view(torch.float32), E.cpu().view(torch.float32)), o
 
@@ -161,9 +162,9 @@ def test_full_sweep_matches_single_instances(ctx):
     origin = [None]
     for k in range(0, len(insts), 7):
         s, b = insts[k], bs[k]
-        # the batch kernel's form (separable: the sweep's Airy scenes have no
-        # cross terms) with one segment: the same field arithmetic
-        E = gbd.gbd_eval(ctx, b, ps[k], gbd.GBD_MIXED, opts=dict(segments=1, variant=5))
+        # the batch kernel's form (separable in FP16 halves: the sweep's Airy
+        # scenes have no cross terms) with one segment: the same field arithmetic
+        E = gbd.gbd_eval(ctx, b, ps[k], gbd.GBD_MIXED, opts=dict(segments=1, variant=4))
         pl = s.plane
         if origin[0] is None:
             origin[0] = gbd.gbd_plane(ctx, pl.origin, pl.normal, pl.xhint, 1, 1, pl.dx, pl.dy)
