@@ -89,9 +89,10 @@ typedef struct {
                                term over the grid, whichever is larger), for
                                higher-order beamlets as 5; 5 = separable
                                on FP32 MFMA in three real products per pair (Gauss's
-                               form).  Both: 128 x 128 pixel workgroup tiles
-                               (rows_per_lane and waves do not apply; gbd_plan_shape
-                               reports 32 and 8).
+                               form).  Workgroup tiles: 4 x 2 wavefronts of 64 x 64
+                               pixels in FP16 halves (gbd_plan_shape reports 64 rows, 8
+                               waves), 2 x 4 of 64 x 32 on FP32 (32 and 8); rows_per_lane
+                               and waves do not apply.
                                Separable is used (auto) or honoured (4, 5) when no beamlet's
                                phasor has a cross term (rotationally symmetric systems on
                                a plane normal to the axis); stepped and rotor when the

@@ -259,6 +259,17 @@ int64_t min_segments(int precision, int form, int64_t n) {
     return (form == 3 && precision == GBD_MIXED) ? (n + kSepMaxSegLen - 1) / kSepMaxSegLen : 1;
 }
 
+// Workgroup tile of a separable shape in pixels.
+void sep_wg_tile(const Shape &s, int &px, int &py) {
+    if (s.half) {
+        px = kSepHWavesX * kSepHTile;
+        py = kSepHWavesY * kSepHTile;
+    } else {
+        px = kSepTileX * kSepWavesX;
+        py = s.rows * (s.waves / kSepWavesX);
+    }
+}
+
 // Launch shape and mixed form.  32 rows per lane is a rotor-form shape: where
 // the form resolves to direct or stepped it runs 16.
 Shape choose_shape(const gbd_ctx_s *ctx, int precision, int64_t n, const PlaneGeom &pl, uint32_t flags,
@@ -271,12 +282,14 @@ Shape choose_shape(const gbd_ctx_s *ctx, int precision, int64_t n, const PlaneGe
     s.half = s.form == 3 && precision == GBD_MIXED && !(flags & FLAG_HG) && !(o && o->variant == 5);
     if (s.form == 3) {
         // separable form: fixed 64 x 32 pixel tile per wavefront (s.rows is
-        // the tile height), 2 x 4 wavefronts per workgroup (s.waves); the row
-        // and wavefront options of the other forms do not apply
+        // the tile height), 2 x 4 wavefronts per workgroup (s.waves), or in
+        // FP16 halves 64 x 64 per wavefront, 4 x 2 wavefronts; the row and
+        // wavefront options of the other forms do not apply
         const bool mixed = precision == GBD_MIXED;
-        const int wy = mixed ? kSepWavesY : kSep64WavesY;
-        s.rows = mixed ? kSepTileY : kSepRows64;
-        s.waves = kSepWavesX * wy;
+        s.rows = s.half ? kSepHTile : mixed ? kSepTileY : kSepRows64;
+        s.waves = s.half ? kSepHWavesX * kSepHWavesY : kSepWavesX * (mixed ? kSepWavesY : kSep64WavesY);
+        int wgx, wgy;
+        sep_wg_tile(s, wgx, wgy);
         s.nseg = (o && o->segments > 0) ? o->segments : 0;
         // the MFMA accumulators sum a segment in plain FP32: its error grows
         // with the segment's length (823,592 beamlets on 64^2 pixels: 1.6e-7
@@ -291,9 +304,8 @@ Shape choose_shape(const gbd_ctx_s *ctx, int precision, int64_t n, const PlaneGe
             // 0.78 ms, 32 0.79 ms; with the earlier four-product form's
             // 256 x 128 workgroup tiles 16 segments ran 1.78 ms, 32 0.91 ms,
             // 48 1.22 ms)
-            const int64_t tiles = std::max<int64_t>(
-                1, (int64_t)((pl.nx + kSepTileX * kSepWavesX - 1) / (kSepTileX * kSepWavesX)) *
-                       ((pl.ny + s.rows * wy - 1) / (s.rows * wy)));
+            const int64_t tiles =
+                std::max<int64_t>(1, (int64_t)((pl.nx + wgx - 1) / wgx) * ((pl.ny + wgy - 1) / wgy));
             const int64_t per_cu = 8 / s.waves;
             int64_t seg = ((int64_t)ctx->cus * per_cu + tiles - 1) / tiles;
             auto it = ctx->tuned.find(tune_key(kTuneSep, precision, n, (int64_t)pl.nx * pl.ny));
@@ -358,9 +370,10 @@ EvalGeom make_geom(const PlaneGeom &pl, int64_t n, const Shape &s) {
     g.a0 = -0.5 * (pl.nx - 1) * pl.dx;
     g.b0 = -0.5 * (pl.ny - 1) * pl.dy;
     if (s.form == 3) {
-        const int wy = s.waves / kSepWavesX;  // 2 x 4 wavefronts
-        g.tiles_x = (pl.nx + kSepTileX * kSepWavesX - 1) / (kSepTileX * kSepWavesX);
-        g.tiles_y = (pl.ny + s.rows * wy - 1) / (s.rows * wy);
+        int wgx, wgy;
+        sep_wg_tile(s, wgx, wgy);
+        g.tiles_x = (pl.nx + wgx - 1) / wgx;
+        g.tiles_y = (pl.ny + wgy - 1) / wgy;
     } else {
         g.tiles_x = (pl.nx + 63) / 64;
         g.tiles_y = (pl.ny + s.waves * s.rows - 1) / (s.waves * s.rows);

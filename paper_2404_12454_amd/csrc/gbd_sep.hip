@@ -83,12 +83,14 @@ __global__ void __launch_bounds__(64 * k3WX * k3WY) eval_sep_kernel(EvalGeom g, 
         }
 }
 
-// FP16 halves form (fundamental beamlets): the same tiles and stores, the
-// accumulators descaled by 2^-scale (exact: a power of two).
-__global__ void __launch_bounds__(64 * k3WX * k3WY) eval_seph_kernel(EvalGeom g, const Rec32 *__restrict__ rec,
-                                                                      int scale, float2 *__restrict__ partial,
-                                                                      float2 *__restrict__ out) {
-    __shared__ SepHLds L;
+// FP16 halves form (fundamental beamlets): the same stores from tiles of
+// T (HTileLarge: 4 x 2 wavefronts of 64 x 64 pixels), the accumulators
+// descaled by 2^-scale (exact: a power of two).
+template <class T>
+__global__ void __launch_bounds__(64 * T::WX * T::WY) eval_seph_kernel(EvalGeom g, const Rec32 *__restrict__ rec,
+                                                                        int scale, float2 *__restrict__ partial,
+                                                                        float2 *__restrict__ out) {
+    __shared__ SepHLdsT<T> L;
     const int w = work_item(blockIdx.x, gridDim.x);
     if (w >= g.work) return;
     const int tiles = g.tiles_x * g.tiles_y;
@@ -96,20 +98,20 @@ __global__ void __launch_bounds__(64 * k3WX * k3WY) eval_seph_kernel(EvalGeom g,
     const int t = w - seg * tiles;
     const int ty = t / g.tiles_x, tx = t - ty * g.tiles_x;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int wx = wv % k3WX, wy = wv / k3WX;
-    const int x0 = (tx * k3WX + wx) * 16 * k3BX, y0 = (ty * k3WY + wy) * 16 * k3BY;
+    const int wx = wv % T::WX, wy = wv / T::WX;
+    const int x0 = (tx * T::WX + wx) * 16 * T::BX, y0 = (ty * T::WY + wy) * 16 * T::BY;
     const int li = lane & 15, lk = lane >> 4;
     const SepGeom sg{g.nx, g.ny, g.a0, g.b0, g.dx, g.dy};
     const int64_t jb = (int64_t)seg * g.seg_len;
     const int64_t je = min(g.n, jb + g.seg_len);
-    f4 accR[k3BY][k3BX], accI[k3BY][k3BX];
-    sep_accumulate_h(sg, rec, jb, je, tx, ty, scale, L, accR, accI);
+    f4 accR[T::BY][T::BX], accI[T::BY][T::BX];
+    sep_accumulate_h<T>(sg, rec, jb, je, tx, ty, scale, L, accR, accI);
 
     const int64_t M = (int64_t)g.nx * g.ny;
 #pragma unroll
-    for (int p = 0; p < k3BY; p++)
+    for (int p = 0; p < T::BY; p++)
 #pragma unroll
-        for (int q = 0; q < k3BX; q++) {
+        for (int q = 0; q < T::BX; q++) {
             const int ix = x0 + 16 * q + li;
             if (ix >= g.nx) continue;
 #pragma unroll
@@ -130,8 +132,11 @@ __global__ void __launch_bounds__(64 * k3WX * k3WY) eval_seph_kernel(EvalGeom g,
 
 hipError_t launch_eval_seph(const EvalGeom &g, const Rec32 *rec, int scale, float2 *partial, float2 *out,
                             hipStream_t s) {
+    using T = HTileLarge;
+    static_assert(T::WX == kSepHWavesX && T::WY == kSepHWavesY && 16 * T::BX == kSepHTile && 16 * T::BY == kSepHTile,
+                  "FP16 halves tiles: host and kernel disagree");
     const int grid = (g.work + 7) / 8 * 8;
-    eval_seph_kernel<<<grid, 64 * k3WX * k3WY, 0, s>>>(g, rec, scale, partial, out);
+    eval_seph_kernel<T><<<grid, 64 * T::WX * T::WY, 0, s>>>(g, rec, scale, partial, out);
     return hipGetLastError();
 }
 

@@ -282,41 +282,81 @@ __device__ inline void split_halves(float re, float im, uint32_t &hi, uint32_t &
 // (a, b) -> (b, a) of a packed FP16 pair
 __device__ inline uint32_t swap_halves(uint32_t v) { return (v >> 16) | (v << 16); }
 
-// Passes of 16 beamlets between barriers; LDS per buffer and pass: U
-// (hi, lo) 20 KiB, V (A_h, A_l, W_h, W_l) 40 KiB, so one pass per barrier
-// (120 KiB double-buffered).  A pixel's 16 beamlets sit in a row of
-// kHRow = 20 words: the 16 lanes of a lane group then read 16-byte operands
-// from 16 distinct groups of 4 banks (20 l mod 64 is distinct for
-// l = 0 ... 15), and a wavefront's 64 single-word writes hit 64 distinct
-// banks (rows 64 bytes apart put 16 lanes on 4 bank groups).
-constexpr int kHPasses = 1, kHRow = 20;
-constexpr bool kHLoLo = false;  // the lo x lo product (2^-22 relative) is left out
-struct SepHLds {
-    // [buffer][pass][range][block][part][pixel in block][beamlet in pass]
-    uint32_t lu[2][kHPasses][k3WX][k3BX][2][16][kHRow];
-    uint32_t lv[2][kHPasses][k3WY][k3BY][4][16][kHRow];
+// Tiles of the FP16 halves form: WX x WY wavefronts of BX x BY 16 x 16
+// blocks.  Per quad of beamlets a lane forms UB = BX / WY factors U (its
+// wavefront shares its x range with WY - 1 others) and VB = BY / WX factors V.
+//   HTileSmall: 2 x 4 wavefronts of 64 x 32 pixels (128 x 128 per
+//     workgroup, LDS 120 KiB: the batched sweep's items, beside its own
+//     shared words); per lane and quad 1 U + 1 V factor beside the
+//     products of 2 blocks;
+//   HTileLarge: 4 x 2 wavefronts of 64 x 64 pixels (256 x 128 per
+//     workgroup, LDS 160 KiB, all of it); per lane and quad 2 U + 1 V
+//     beside the products of 4 blocks: a quarter less factor arithmetic
+//     per pair.
+template <int WX_, int WY_, int BX_, int BY_>
+struct HTile {
+    static constexpr int WX = WX_, WY = WY_, BX = BX_, BY = BY_;
+    static constexpr int UB = BX / WY, VB = BY / WX;
+    static_assert(BX % WY == 0 && BY % WX == 0 && BX * BY % 4 == 0, "FP16 halves tile");
 };
+using HTileSmall = HTile<k3WX, k3WY, k3BX, k3BY>;
+using HTileLarge = HTile<4, 2, 4, 4>;
+
+// LDS per buffer: U (hi, lo) and V (A_h, A_l, W_h, W_l) words of one pass of
+// 16 beamlets, double-buffered so the next pass's factors are written while
+// this pass's products run.  A pixel's 16 beamlets sit in a row of kHRow =
+// 20 words: the 16 lanes of a lane group then read 16-byte operands from 16
+// distinct groups of 4 banks (20 l mod 64 is distinct for l = 0 ... 15), and
+// a wavefront's 64 single-word writes hit 64 distinct banks (rows 64 bytes
+// apart put 16 lanes on 4 bank groups).
+constexpr int kHRow = 20;
+template <class T>
+struct SepHLdsT {
+    // [buffer][range][block][part][pixel in block][beamlet in pass]
+    uint32_t lu[2][T::WX][T::BX][2][16][kHRow];
+    uint32_t lv[2][T::WY][T::BY][4][16][kHRow];
+};
+using SepHLds = SepHLdsT<HTileSmall>;
+static_assert(sizeof(SepHLdsT<HTileLarge>) <= 163840, "the large tile's LDS exceeds a workgroup's 160 KiB");
 
 __device__ inline h8 operand(const uint32_t *p) { return __builtin_bit_cast(h8, *reinterpret_cast<const uint4 *>(p)); }
 
-// As sep_accumulate_3m (same tiles, segment walk and record prefetch two
-// quads ahead) for fundamental beamlets in FP16 halves; accR / accI hold the
-// field times 2^scale.
+// As sep_accumulate_3m (segment walk, record prefetch two quads ahead) for
+// fundamental beamlets in FP16 halves, tile T; accR / accI hold the field
+// times 2^scale.  The hi x hi, hi x lo and lo x hi products of every block
+// in that order each pass (lo x lo, at most 2^-22 of a term, is left out).
+template <class T = HTileSmall>
 __device__ inline void sep_accumulate_h(const SepGeom &g, const Rec32 *__restrict__ rec, int64_t jb, int64_t je,
-                                        int tx, int ty, int scale, SepHLds &L, f4 (&accR)[k3BY][k3BX],
-                                        f4 (&accI)[k3BY][k3BX]) {
-    constexpr int Q = 4 * kHPasses;  // quads of beamlets per barrier
+                                        int tx, int ty, int scale, SepHLdsT<T> &L, f4 (&accR)[T::BY][T::BX],
+                                        f4 (&accI)[T::BY][T::BX]) {
+    constexpr int WX = T::WX, WY = T::WY, BX = T::BX, BY = T::BY, UB = T::UB, VB = T::VB;
+    constexpr int Q = 4;                 // quads of beamlets per pass (one pass of 16 between barriers)
+    constexpr int PERQ = BX * BY / Q;    // blocks whose products run beside one quad's factors
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int wx = wv % k3WX, wy = wv / k3WX;
-    const int x0 = (tx * k3WX + wx) * 16 * k3BX, y0 = (ty * k3WY + wy) * 16 * k3BY;
+    const int wx = wv % WX, wy = wv / WX;
+    const int x0 = (tx * WX + wx) * 16 * BX, y0 = (ty * WY + wy) * 16 * BY;
     const int li = lane & 15, lk = lane >> 4;
     auto &lu = L.lu;
     auto &lv = L.lv;
 
-    const int ix = x0 + 16 * wy + li, iy = y0 + 16 * wx + li;
-    const float mx = ix < g.nx ? 0.0f : -INFINITY, my = iy < g.ny ? 0.0f : -INFINITY;
-    const double ax = g.a0 + ix * g.dx, by = g.b0 + iy * g.dy;
-    const float axf = (float)ax, byf = (float)by;
+    // this wavefront forms U blocks wy UB ... + UB - 1 of x range wx and V
+    // blocks wx VB ... + VB - 1 of y range wy
+    double ax[UB], by[VB];
+    float axf[UB], byf[VB], mx[UB], my[VB];
+#pragma unroll
+    for (int u = 0; u < UB; u++) {
+        const int ix = x0 + 16 * (wy * UB + u) + li;
+        mx[u] = ix < g.nx ? 0.0f : -INFINITY;
+        ax[u] = g.a0 + ix * g.dx;
+        axf[u] = (float)ax[u];
+    }
+#pragma unroll
+    for (int v = 0; v < VB; v++) {
+        const int iy = y0 + 16 * (wx * VB + v) + li;
+        my[v] = iy < g.ny ? 0.0f : -INFINITY;
+        by[v] = g.b0 + iy * g.dy;
+        byf[v] = (float)by[v];
+    }
     const float E = (float)kSepHalfExp, sc = (float)scale;
     struct FieldsH {
         Fields f;
@@ -328,33 +368,40 @@ __device__ inline void sep_accumulate_h(const SepGeom &g, const Rec32 *__restric
         h.u = rec[j < je ? j : jb].pad;
         return h;
     };
-    // quad qd of a barrier interval: beamlet 4 qd + lk, i.e. beamlet
-    // 4 (qd % 4) + lk of pass qd / 4
+    // quad qd of a pass: beamlet 4 qd + lk of the pass
     auto publish = [&](const FieldsH &h, int buf, int qd) {
         const Fields &f = h.f;
-        float ur, ui, vr, vi;
-        const float dxf = axf - f.arf, dyf = byf - f.brf;
-        factor(ax - f.arho, dxf, f.p0, f.p1, f.p3, (f.m0 + (E - h.u)) + (f.mbias + mx), f.m1, f.m3, ur, ui);
-        factor(by - f.brho, dyf, 0.0, f.p2, f.p5, (sc - E + h.u) + my, f.m2, f.m5, vr, vi);
-        uint32_t uh, ul, vh, vl;
-        split_halves(ur, ui, uh, ul);
-        split_halves(vr, vi, vh, vl);
-        const int ps = qd >> 2, b = 4 * (qd & 3) + lk;
-        lu[buf][ps][wx][wy][0][li][b] = uh;
-        lu[buf][ps][wx][wy][1][li][b] = ul;
-        lv[buf][ps][wy][wx][0][li][b] = vh ^ 0x80000000u;
-        lv[buf][ps][wy][wx][1][li][b] = vl ^ 0x80000000u;
-        lv[buf][ps][wy][wx][2][li][b] = swap_halves(vh);
-        lv[buf][ps][wy][wx][3][li][b] = swap_halves(vl);
+        const int b = 4 * qd + lk;
+#pragma unroll
+        for (int u = 0; u < UB; u++) {
+            float ur, ui;
+            factor(ax[u] - f.arho, axf[u] - f.arf, f.p0, f.p1, f.p3, (f.m0 + (E - h.u)) + (f.mbias + mx[u]), f.m1,
+                   f.m3, ur, ui);
+            uint32_t uh, ul;
+            split_halves(ur, ui, uh, ul);
+            lu[buf][wx][wy * UB + u][0][li][b] = uh;
+            lu[buf][wx][wy * UB + u][1][li][b] = ul;
+        }
+#pragma unroll
+        for (int v = 0; v < VB; v++) {
+            float vr, vi;
+            factor(by[v] - f.brho, byf[v] - f.brf, 0.0, f.p2, f.p5, (sc - E + h.u) + my[v], f.m2, f.m5, vr, vi);
+            uint32_t vh, vl;
+            split_halves(vr, vi, vh, vl);
+            const int blk = wx * VB + v;
+            lv[buf][wy][blk][0][li][b] = vh ^ 0x80000000u;
+            lv[buf][wy][blk][1][li][b] = vl ^ 0x80000000u;
+            lv[buf][wy][blk][2][li][b] = swap_halves(vh);
+            lv[buf][wy][blk][3][li][b] = swap_halves(vl);
+        }
     };
 
 #pragma unroll
-    for (int p = 0; p < k3BY; p++)
+    for (int p = 0; p < BY; p++)
 #pragma unroll
-        for (int q = 0; q < k3BX; q++) accR[p][q] = accI[p][q] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+        for (int q = 0; q < BX; q++) accR[p][q] = accI[p][q] = f4{0.0f, 0.0f, 0.0f, 0.0f};
 
-    static_assert(Q % 2 == 0, "the two-slot field ring needs an even number of quads per barrier");
-    constexpr int P = 4 * Q;  // beamlets per barrier
+    constexpr int P = 4 * Q;  // beamlets per pass
 #pragma unroll
     for (int qd = 0; qd < Q; qd++) publish(load(jb + 4 * qd + lk), 0, qd);
     FieldsH fn[2] = {load(jb + P + lk), load(jb + P + 4 + lk)};
@@ -362,45 +409,37 @@ __device__ inline void sep_accumulate_h(const SepGeom &g, const Rec32 *__restric
     int buf = 0;
     for (int64_t j0 = jb; j0 < je; j0 += P) {
         const bool more = j0 + P < je;
+        h8 bh[BX], bl[BX];
 #pragma unroll
-        for (int ps = 0; ps < kHPasses; ps++) {
-            h8 bh[k3BX], bl[k3BX], ah[k3BY], al[k3BY], wh[k3BY], wl[k3BY];
+        for (int q = 0; q < BX; q++) {
+            bh[q] = operand(&lu[buf][wx][q][0][li][4 * lk]);
+            bl[q] = operand(&lu[buf][wx][q][1][li][4 * lk]);
+        }
+        h8 ah, al, wh, wl;
+        // the next pass's quads, formed between this pass's products
 #pragma unroll
-            for (int q = 0; q < k3BX; q++) {
-                bh[q] = operand(&lu[buf][ps][wx][q][0][li][4 * lk]);
-                bl[q] = operand(&lu[buf][ps][wx][q][1][li][4 * lk]);
+        for (int k = 0; k < Q; k++) {
+            if (more) {
+                publish(fn[k % 2], buf ^ 1, k);
+                fn[k % 2] = load(j0 + P + 4 * (k + 2) + lk);
             }
+            // blocks PERQ k ... + PERQ - 1 in row-major order; a block row's
+            // V operands are read at its first block
 #pragma unroll
-            for (int p = 0; p < k3BY; p++) {
-                ah[p] = operand(&lv[buf][ps][wy][p][0][li][4 * lk]);
-                al[p] = operand(&lv[buf][ps][wy][p][1][li][4 * lk]);
-                wh[p] = operand(&lv[buf][ps][wy][p][2][li][4 * lk]);
-                wl[p] = operand(&lv[buf][ps][wy][p][3][li][4 * lk]);
-            }
-            // the next interval's quads of this pass, formed between the products
-#pragma unroll
-            for (int k = 0; k < 4; k++) {
-                const int qd = 4 * ps + k;
-                if (more) {
-                    publish(fn[qd % 2], buf ^ 1, qd);
-                    fn[qd % 2] = load(j0 + P + 4 * (qd + 2) + lk);
+            for (int i = 0; i < PERQ; i++) {
+                const int m = PERQ * k + i, p = m / BX, q = m % BX;
+                if (q == 0 || i == 0) {
+                    ah = operand(&lv[buf][wy][p][0][li][4 * lk]);
+                    al = operand(&lv[buf][wy][p][1][li][4 * lk]);
+                    wh = operand(&lv[buf][wy][p][2][li][4 * lk]);
+                    wl = operand(&lv[buf][wy][p][3][li][4 * lk]);
                 }
-                // products of block row p = k / 2, columns 2 (k % 2) ... + 1
-                const int p = k >> 1;
-#pragma unroll
-                for (int qq = 0; qq < 2; qq++) {
-                    const int q = 2 * (k & 1) + qq;
-                    accR[p][q] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[p], bh[q], accR[p][q], 0, 0, 0);
-                    accI[p][q] = __builtin_amdgcn_mfma_f32_16x16x32_f16(wh[p], bh[q], accI[p][q], 0, 0, 0);
-                    accR[p][q] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[p], bl[q], accR[p][q], 0, 0, 0);
-                    accI[p][q] = __builtin_amdgcn_mfma_f32_16x16x32_f16(wh[p], bl[q], accI[p][q], 0, 0, 0);
-                    accR[p][q] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al[p], bh[q], accR[p][q], 0, 0, 0);
-                    accI[p][q] = __builtin_amdgcn_mfma_f32_16x16x32_f16(wl[p], bh[q], accI[p][q], 0, 0, 0);
-                    if constexpr (kHLoLo) {
-                        accR[p][q] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al[p], bl[q], accR[p][q], 0, 0, 0);
-                        accI[p][q] = __builtin_amdgcn_mfma_f32_16x16x32_f16(wl[p], bl[q], accI[p][q], 0, 0, 0);
-                    }
-                }
+                accR[p][q] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bh[q], accR[p][q], 0, 0, 0);
+                accI[p][q] = __builtin_amdgcn_mfma_f32_16x16x32_f16(wh, bh[q], accI[p][q], 0, 0, 0);
+                accR[p][q] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bl[q], accR[p][q], 0, 0, 0);
+                accI[p][q] = __builtin_amdgcn_mfma_f32_16x16x32_f16(wh, bl[q], accI[p][q], 0, 0, 0);
+                accR[p][q] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al, bh[q], accR[p][q], 0, 0, 0);
+                accI[p][q] = __builtin_amdgcn_mfma_f32_16x16x32_f16(wl, bh[q], accI[p][q], 0, 0, 0);
             }
         }
         __syncthreads();
