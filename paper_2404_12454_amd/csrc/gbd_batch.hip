@@ -120,7 +120,7 @@ __global__ void __launch_bounds__(64 * WAVES) batch_eval_kernel(BatchArgs A) {
     for (;;) {
         if (threadIdx.x == 0) s_item = (int)atomicAdd(A.counter, 1u);
         __syncthreads();
-        const int item = s_item;
+        const int item = __builtin_amdgcn_readfirstlane(s_item);  // uniform: the instance fields load as scalars
         __syncthreads();
         if (item >= A.n_items) break;  // uniform across the workgroup
         const int i = A.items[2 * item], t = A.items[2 * item + 1];
@@ -210,7 +210,7 @@ __global__ void __launch_bounds__(64 * sep::k3WX * sep::k3WY) batch_sep_kernel(B
     for (;;) {
         if (threadIdx.x == 0) s_item = (int)atomicAdd(A.counter, 1u);
         __syncthreads();
-        const int item = s_item;
+        const int item = __builtin_amdgcn_readfirstlane(s_item);  // uniform: the instance fields load as scalars
         __syncthreads();
         if (item >= A.n_items) break;  // uniform across the workgroup
         const int i = A.items[2 * item], t = A.items[2 * item + 1];

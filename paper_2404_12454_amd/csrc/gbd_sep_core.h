@@ -279,8 +279,25 @@ __device__ inline void split_halves(float re, float im, uint32_t &hi, uint32_t &
         : "v"(re), "v"(hi), "v"(im));
 }
 
-// (a, b) -> (b, a) of a packed FP16 pair
-__device__ inline uint32_t swap_halves(uint32_t v) { return (v >> 16) | (v << 16); }
+// split_halves of (re, -im): the conjugate's halves, the negation folded
+// into the conversions' source modifiers
+__device__ inline void split_halves_conj(float re, float im, uint32_t &hi, uint32_t &lo) {
+    asm("" : "+v"(re), "+v"(im));
+    hi = __builtin_bit_cast(uint32_t, h2{(_Float16)re, (_Float16)(-im)});
+    asm("v_fma_mixlo_f16 %0, %1, 1.0, -%2 op_sel_hi:[0,0,1]\n\t"
+        "v_fma_mixhi_f16 %0, -%3, 1.0, -%2 op_sel:[0,0,1] op_sel_hi:[0,0,1]"
+        : "=&v"(lo)
+        : "v"(re), "v"(hi), "v"(im));
+}
+
+// (a, b) -> (-b, a) of a packed FP16 pair, exactly (a product by 1.0 whose
+// low result takes the negated high half and high result the low half;
+// FP16 denormals are kept)
+__device__ inline uint32_t rot_halves(uint32_t v) {
+    uint32_t w;
+    asm("v_pk_mul_f16 %0, %1, 1.0 op_sel:[1,0] op_sel_hi:[0,0] neg_lo:[1,0]" : "=v"(w) : "v"(v));
+    return w;
+}
 
 // Tiles of the FP16 halves form: WX x WY wavefronts of BX x BY 16 x 16
 // blocks.  Per quad of beamlets a lane forms UB = BX / WY factors U (its
@@ -304,27 +321,53 @@ using HTileLarge = HTile<4, 2, 4, 4>;
 
 // LDS per buffer: U (hi, lo) and V (A_h, A_l, W_h, W_l) words of one pass of
 // 16 beamlets, double-buffered so the next pass's factors are written while
-// this pass's products run.  A pixel's 16 beamlets sit in a row of kHRow =
-// 20 words: the 16 lanes of a lane group then read 16-byte operands from 16
-// distinct groups of 4 banks (20 l mod 64 is distinct for l = 0 ... 15), and
-// a wavefront's 64 single-word writes hit 64 distinct banks (rows 64 bytes
-// apart put 16 lanes on 4 bank groups).
-constexpr int kHRow = 20;
+// this pass's products run.  A pixel's 16 beamlets fill a row of 16 words
+// as 4 groups of 4 (one 16-byte operand each), the groups of row r stored
+// in the order g ^ swz(r), swz(r) = ((r >> 1) & 3) ^ ((r >> 3) & 1).  Then
+// the 16 lanes of a lane group (rows 0 ... 15, one group each) read from 16
+// distinct 4-bank groups of a 64-bank LDS, and any 8 consecutive lanes from
+// 8 distinct ones of a 32-bank one; a wavefront's 64 single-word writes
+// (row l % 16, word l / 16 of one group) hit 64 distinct banks of 64.
+__device__ inline int swz(int r) { return ((r >> 1) & 3) ^ ((r >> 3) & 1); }
+
+// Records staged in LDS a pass ahead: the 22 words of a Rec32 that the
+// factors need, 24 to a record (6 16-byte reads), 16 records a pass.
+constexpr int kStageWords = 24, kStageUsed = 22;
+// staged word w holds Rec32 word kStageSrc[w]:
+//   0-7  arho, p0, p1, p3 (FP64, U)    8-13  brho, p2, p5 (FP64, V)
+//   14-16 m0, m1, m3 (U)   17-18 m2, m5 (V)   19-20 arho_f, brho_f   21 pad (the U bound)
+__device__ constexpr int kStageSrc[kStageUsed] = {0, 1, 4, 5, 6, 7, 10, 11, 2, 3, 8, 9, 14, 15,
+                                                  16, 17, 19, 18, 21, 22, 23, 27};
+static_assert(sizeof(Rec32) == 60 * 4 && kStageWords % 4 == 0, "staged record layout");
+
 template <class T>
 struct SepHLdsT {
-    // [buffer][range][block][part][pixel in block][beamlet in pass]
-    uint32_t lu[2][T::WX][T::BX][2][16][kHRow];
-    uint32_t lv[2][T::WY][T::BY][4][16][kHRow];
+    // [buffer][range][block][part][pixel in block][beamlet in pass, swizzled]
+    uint32_t lu[2][T::WX][T::BX][2][16][16];
+    uint32_t lv[2][T::WY][T::BY][4][16][16];
+    // [buffer][beamlet in pass][staged word]; rows 16 ... take the idle
+    // threads' words (every thread stores: a guarded store would let the
+    // compiler sink the load into the guard, next to the store)
+    static constexpr int kRows = (64 * T::WX * T::WY + kStageUsed - 1) / kStageUsed;
+    uint32_t rs[2][kRows][kStageWords];
 };
 using SepHLds = SepHLdsT<HTileSmall>;
 static_assert(sizeof(SepHLdsT<HTileLarge>) <= 163840, "the large tile's LDS exceeds a workgroup's 160 KiB");
+static_assert(64 * HTileSmall::WX * HTileSmall::WY >= 16 * kStageUsed &&
+                  64 * HTileLarge::WX * HTileLarge::WY >= 16 * kStageUsed,
+              "a workgroup stages a pass's records one word per thread");
 
 __device__ inline h8 operand(const uint32_t *p) { return __builtin_bit_cast(h8, *reinterpret_cast<const uint4 *>(p)); }
 
-// As sep_accumulate_3m (segment walk, record prefetch two quads ahead) for
-// fundamental beamlets in FP16 halves, tile T; accR / accI hold the field
-// times 2^scale.  The hi x hi, hi x lo and lo x hi products of every block
-// in that order each pass (lo x lo, at most 2^-22 of a term, is left out).
+// As sep_accumulate_3m (segment walk) for fundamental beamlets in FP16
+// halves, tile T; accR / accI hold the field times 2^scale.  The hi x hi,
+// hi x lo and lo x hi products of every block in that order each pass (lo
+// x lo, at most 2^-22 of a term, is left out).  The record words reach LDS
+// two passes before their factors are used: during pass p each thread loads
+// one word of pass p + 2's records and writes it before the pass's barrier,
+// and the factors of pass p + 1, formed during pass p, read pass p + 1's.
+// Every pass forms the next one's factors, the last one too (past the end:
+// zero factors nobody reads), so the loop body has no branch.
 template <class T = HTileSmall>
 __device__ inline void sep_accumulate_h(const SepGeom &g, const Rec32 *__restrict__ rec, int64_t jb, int64_t je,
                                         int tx, int ty, int scale, SepHLdsT<T> &L, f4 (&accR)[T::BY][T::BX],
@@ -332,67 +375,95 @@ __device__ inline void sep_accumulate_h(const SepGeom &g, const Rec32 *__restric
     constexpr int WX = T::WX, WY = T::WY, BX = T::BX, BY = T::BY, UB = T::UB, VB = T::VB;
     constexpr int Q = 4;                 // quads of beamlets per pass (one pass of 16 between barriers)
     constexpr int PERQ = BX * BY / Q;    // blocks whose products run beside one quad's factors
+    constexpr int P = 4 * Q;             // beamlets per pass
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int wx = wv % WX, wy = wv / WX;
     const int x0 = (tx * WX + wx) * 16 * BX, y0 = (ty * WY + wy) * 16 * BY;
     const int li = lane & 15, lk = lane >> 4;
+    const int sw = swz(li);
     auto &lu = L.lu;
     auto &lv = L.lv;
+    auto &rs = L.rs;
 
     // this wavefront forms U blocks wy UB ... + UB - 1 of x range wx and V
-    // blocks wx VB ... + VB - 1 of y range wy
+    // blocks wx VB ... + VB - 1 of y range wy (unmasked past the grid's edge,
+    // as in sep_accumulate_3m; there the factors may even leave FP16's range,
+    // which reaches only outputs that are not stored)
     double ax[UB], by[VB];
-    float axf[UB], byf[VB], mx[UB], my[VB];
+    float axf[UB], byf[VB];
 #pragma unroll
     for (int u = 0; u < UB; u++) {
         const int ix = x0 + 16 * (wy * UB + u) + li;
-        mx[u] = ix < g.nx ? 0.0f : -INFINITY;
         ax[u] = g.a0 + ix * g.dx;
         axf[u] = (float)ax[u];
     }
 #pragma unroll
     for (int v = 0; v < VB; v++) {
         const int iy = y0 + 16 * (wx * VB + v) + li;
-        my[v] = iy < g.ny ? 0.0f : -INFINITY;
         by[v] = g.b0 + iy * g.dy;
         byf[v] = (float)by[v];
     }
     const float E = (float)kSepHalfExp, sc = (float)scale;
-    struct FieldsH {
-        Fields f;
-        float u;  // log2 bound of |U| over the grid (Rec32::pad)
+    const Rec32 *__restrict__ srec = rec + jb;
+    const int n = (int)(je - jb);
+
+    // staging: thread t moves word kStageSrc[t % 22] of record t / 22 (the
+    // threads past 16 x 22 load words of later records, clamped, and store
+    // them into rows nobody reads)
+    const int st = threadIdx.x, sr = st / kStageUsed, sc_w = st - sr * kStageUsed, sw_src = kStageSrc[sc_w];
+    auto stage_load = [&](int i0) {  // a word of the pass starting at beamlet i0
+        const int i = i0 + sr;
+        return reinterpret_cast<const uint32_t *>(srec + (i < n ? i : 0))[sw_src];
     };
-    auto load = [&](int64_t j) {
-        FieldsH h;
-        h.f = load_fields<false>(rec, nullptr, j, jb, je);
-        h.u = rec[j < je ? j : jb].pad;
-        return h;
+    auto stage_store = [&](int sbuf, uint32_t w) {
+        rs[sbuf][sr][sc_w] = w;
     };
-    // quad qd of a pass: beamlet 4 qd + lk of the pass
-    auto publish = [&](const FieldsH &h, int buf, int qd) {
-        const Fields &f = h.f;
+
+    // quad qd of a pass: beamlet b = 4 qd + lk, the pass's records in rs[sbuf]
+    auto publish = [&](int sbuf, int i0, int buf, int qd) {
         const int b = 4 * qd + lk;
+        const uint32_t *r = rs[sbuf][b];
+        uint4 w[6];
 #pragma unroll
-        for (int u = 0; u < UB; u++) {
+        for (int k = 0; k < 6; k++) w[k] = reinterpret_cast<const uint4 *>(r)[k];
+        auto f64 = [&](int k) {
+            const uint4 &q = w[k >> 2];
+            const uint32_t lo = (k & 3) == 0 ? q.x : q.z, hi = (k & 3) == 0 ? q.y : q.w;
+            return __builtin_bit_cast(double, (uint64_t)lo | ((uint64_t)hi << 32));
+        };
+        auto f32 = [&](int k) {
+            const uint4 &q = w[k >> 2];
+            const uint32_t v = (k & 3) == 0 ? q.x : (k & 3) == 1 ? q.y : (k & 3) == 2 ? q.z : q.w;
+            return __builtin_bit_cast(float, v);
+        };
+        const double arho = f64(0), p0 = f64(2), p1 = f64(4), p3 = f64(6);
+        const double brho = f64(8), p2 = f64(10), p5 = f64(12);
+        const float m0 = f32(14), m1 = f32(15), m3 = f32(16), m2 = f32(17), m5 = f32(18);
+        const float arf = f32(19), brf = f32(20), u = f32(21);
+        const float mbias = i0 + b < n ? 0.0f : -INFINITY;
+        const float lu0 = (m0 + (E - u)) + mbias, lv0 = (sc - E) + u;
+        const int col = 4 * (qd ^ sw) + lk;
+#pragma unroll
+        for (int k = 0; k < UB; k++) {
             float ur, ui;
-            factor(ax[u] - f.arho, axf[u] - f.arf, f.p0, f.p1, f.p3, (f.m0 + (E - h.u)) + (f.mbias + mx[u]), f.m1,
-                   f.m3, ur, ui);
+            factor(ax[k] - arho, axf[k] - arf, p0, p1, p3, lu0, m1, m3, ur, ui);
             uint32_t uh, ul;
             split_halves(ur, ui, uh, ul);
-            lu[buf][wx][wy * UB + u][0][li][b] = uh;
-            lu[buf][wx][wy * UB + u][1][li][b] = ul;
+            lu[buf][wx][wy * UB + k][0][li][col] = uh;
+            lu[buf][wx][wy * UB + k][1][li][col] = ul;
         }
 #pragma unroll
-        for (int v = 0; v < VB; v++) {
+        for (int k = 0; k < VB; k++) {
             float vr, vi;
-            factor(by[v] - f.brho, byf[v] - f.brf, 0.0, f.p2, f.p5, (sc - E + h.u) + my[v], f.m2, f.m5, vr, vi);
-            uint32_t vh, vl;
-            split_halves(vr, vi, vh, vl);
-            const int blk = wx * VB + v;
-            lv[buf][wy][blk][0][li][b] = vh ^ 0x80000000u;
-            lv[buf][wy][blk][1][li][b] = vl ^ 0x80000000u;
-            lv[buf][wy][blk][2][li][b] = swap_halves(vh);
-            lv[buf][wy][blk][3][li][b] = swap_halves(vl);
+            factor(by[k] - brho, byf[k] - brf, 0.0, p2, p5, lv0, m2, m5, vr, vi);
+            // A = (Vr, -Vi) halves; W = (Vi, Vr) = rot_halves(A)
+            uint32_t ah, al;
+            split_halves_conj(vr, vi, ah, al);
+            const int blk = wx * VB + k;
+            lv[buf][wy][blk][0][li][col] = ah;
+            lv[buf][wy][blk][1][li][col] = al;
+            lv[buf][wy][blk][2][li][col] = rot_halves(ah);
+            lv[buf][wy][blk][3][li][col] = rot_halves(al);
         }
     };
 
@@ -401,38 +472,45 @@ __device__ inline void sep_accumulate_h(const SepGeom &g, const Rec32 *__restric
 #pragma unroll
         for (int q = 0; q < BX; q++) accR[p][q] = accI[p][q] = f4{0.0f, 0.0f, 0.0f, 0.0f};
 
-    constexpr int P = 4 * Q;  // beamlets per pass
-#pragma unroll
-    for (int qd = 0; qd < Q; qd++) publish(load(jb + 4 * qd + lk), 0, qd);
-    FieldsH fn[2] = {load(jb + P + lk), load(jb + P + 4 + lk)};
+    // passes 0 and 1's records, then pass 0's factors
+    {
+        const uint32_t w0 = stage_load(0), w1 = stage_load(P);
+        stage_store(0, w0);
+        stage_store(1, w1);
+    }
     __syncthreads();
+#pragma unroll
+    for (int qd = 0; qd < Q; qd++) publish(0, 0, 0, qd);
+    __syncthreads();
+    const int rd = 4 * (lk ^ sw);  // this lane's operand group in a row
     int buf = 0;
-    for (int64_t j0 = jb; j0 < je; j0 += P) {
-        const bool more = j0 + P < je;
+    for (int i0 = 0; i0 < n; i0 += P) {
+        // pass p = i0 / P: factors in buf, records of pass p + 1 in rs[buf ^ 1]
+        const uint32_t wnext = stage_load(i0 + 2 * P);
+        // keep the load here, a pass before its use (the scheduler would
+        // otherwise sink it to the store and wait on it there)
+        __builtin_amdgcn_sched_barrier(0);
         h8 bh[BX], bl[BX];
 #pragma unroll
         for (int q = 0; q < BX; q++) {
-            bh[q] = operand(&lu[buf][wx][q][0][li][4 * lk]);
-            bl[q] = operand(&lu[buf][wx][q][1][li][4 * lk]);
+            bh[q] = operand(&lu[buf][wx][q][0][li][rd]);
+            bl[q] = operand(&lu[buf][wx][q][1][li][rd]);
         }
         h8 ah, al, wh, wl;
         // the next pass's quads, formed between this pass's products
 #pragma unroll
         for (int k = 0; k < Q; k++) {
-            if (more) {
-                publish(fn[k % 2], buf ^ 1, k);
-                fn[k % 2] = load(j0 + P + 4 * (k + 2) + lk);
-            }
+            publish(buf ^ 1, i0 + P, buf ^ 1, k);
             // blocks PERQ k ... + PERQ - 1 in row-major order; a block row's
             // V operands are read at its first block
 #pragma unroll
             for (int i = 0; i < PERQ; i++) {
                 const int m = PERQ * k + i, p = m / BX, q = m % BX;
                 if (q == 0 || i == 0) {
-                    ah = operand(&lv[buf][wy][p][0][li][4 * lk]);
-                    al = operand(&lv[buf][wy][p][1][li][4 * lk]);
-                    wh = operand(&lv[buf][wy][p][2][li][4 * lk]);
-                    wl = operand(&lv[buf][wy][p][3][li][4 * lk]);
+                    ah = operand(&lv[buf][wy][p][0][li][rd]);
+                    al = operand(&lv[buf][wy][p][1][li][rd]);
+                    wh = operand(&lv[buf][wy][p][2][li][rd]);
+                    wl = operand(&lv[buf][wy][p][3][li][rd]);
                 }
                 accR[p][q] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bh[q], accR[p][q], 0, 0, 0);
                 accI[p][q] = __builtin_amdgcn_mfma_f32_16x16x32_f16(wh, bh[q], accI[p][q], 0, 0, 0);
@@ -442,6 +520,8 @@ __device__ inline void sep_accumulate_h(const SepGeom &g, const Rec32 *__restric
                 accI[p][q] = __builtin_amdgcn_mfma_f32_16x16x32_f16(wl, bh[q], accI[p][q], 0, 0, 0);
             }
         }
+        // pass p + 2's records into the buffer pass p - 1 read
+        stage_store(buf, wnext);
         __syncthreads();
         buf ^= 1;
     }
