@@ -349,9 +349,9 @@ int gbd_airy(gbd_ctx_t ctx, gbd_plane_t p, double D, double f, double lambda, fl
  *   fields_out  optional device complex64 fields, instance after instance
  *               ([n_inst][ny_i][nx_i]); fields_bytes its size
  * opts: variant as for gbd_eval's mixed form (auto: separable where no
- * beamlet of any instance has a cross term, each item then a 128 x 128
- * pixel tile, in FP16 halves with each instance's own scale (4) or on FP32
- * MFMA (5); else rotor, else direct); rows_per_lane and waves as for
+ * beamlet of any instance has a cross term, each item then a 256 x 128
+ * pixel tile in FP16 halves with each instance's own scale (4) or a 128 x 128
+ * one on FP32 MFMA (5); else rotor, else direct); rows_per_lane and waves as for
  * gbd_eval for the other forms (segments is ignored; default 32 x 4 for the
  * rotor form, else 16 x 4, or the autotuner's choice).  Every item sums all
  * of its instance's beamlets, so a field equals gbd_eval's with the same

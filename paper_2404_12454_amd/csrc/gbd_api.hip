@@ -1371,9 +1371,16 @@ int gbd_eval_batch(gbd_ctx_t ctx, int32_t n_inst, const gbd_beamlets_t *bs, cons
         e.n = bs[i]->dev.n;
         e.nx = g.nx;
         e.ny = g.ny;
-        if (form == 3) {  // separable form: 128 x 128 pixel tiles
-            e.tiles_x = (g.nx + kSepTileX * kSepWavesX - 1) / (kSepTileX * kSepWavesX);
-            e.tiles_y = (g.ny + kSepTileY * kSepWavesY - 1) / (kSepTileY * kSepWavesY);
+        if (form == 3) {  // separable form: the single evaluation's workgroup tiles
+            Shape sh;
+            sh.form = 3;
+            sh.half = half;
+            sh.rows = kSepTileY;
+            sh.waves = kSepWavesX * kSepWavesY;
+            int wgx, wgy;
+            sep_wg_tile(sh, wgx, wgy);
+            e.tiles_x = (g.nx + wgx - 1) / wgx;
+            e.tiles_y = (g.ny + wgy - 1) / wgy;
         } else {
             e.tiles_x = (g.nx + 63) / 64;
             e.tiles_y = (g.ny + waves * rows - 1) / (waves * rows);

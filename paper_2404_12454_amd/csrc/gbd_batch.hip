@@ -12,9 +12,10 @@
 //                      wavefront shuffles
 //  batch_sep_kernel    the same with the separable (matrix) form where no
 //                      beamlet's phasor has a cross term: items are
-//                      (instance, 128 x 128 tile), each a 2 x 4-wavefront
-//                      MFMA accumulation over all of the instance's beamlets
-//                      (FP16 halves, or FP32 MFMA when requested)
+//                      (instance, workgroup tile: 256 x 128 pixels in FP16
+//                      halves, 128 x 128 on FP32 MFMA when requested), each
+//                      an MFMA accumulation over all of the instance's
+//                      beamlets
 //  batch_finalize      per instance, fixed-order sum of its items' partials
 //  airy_kernel         reference irradiance (2 J1(v)/v)^2 in FP64
 #include "gbd_device.h"
@@ -196,11 +197,17 @@ __global__ void __launch_bounds__(64 * WAVES) batch_eval_kernel(BatchArgs A) {
 // halves (HALF) or 5 on FP32 MFMA, and one segment bit for bit), then the
 // same epilogue from the MFMA accumulators (lane l holds rows 4 (l / 16) + e,
 // column l % 16 of each 16 x 16 block).
+// The FP16 halves form takes the single evaluation's 256 x 128 workgroup
+// tiles (HTileLarge), the FP32 one its 128 x 128 (the k3 layout).
 template <bool HALF>
-__global__ void __launch_bounds__(64 * sep::k3WX * sep::k3WY) batch_sep_kernel(BatchArgs A) {
-    constexpr int WX = sep::k3WX, WY = sep::k3WY, BX = sep::k3BX, BY = sep::k3BY;
+using BatchTile = typename std::conditional<HALF, sep::HTileLarge, sep::HTileSmall>::type;
+
+template <bool HALF>
+__global__ void __launch_bounds__(64 * BatchTile<HALF>::WX * BatchTile<HALF>::WY) batch_sep_kernel(BatchArgs A) {
+    using T = BatchTile<HALF>;
+    constexpr int WX = T::WX, WY = T::WY, BX = T::BX, BY = T::BY;
     constexpr int WAVES = WX * WY, NQ = 2 + 2 * kMaxZones;
-    __shared__ typename std::conditional<HALF, sep::SepHLds, sep::Sep3Lds<false>>::type L;
+    __shared__ typename std::conditional<HALF, sep::SepHLdsT<T>, sep::Sep3Lds<false>>::type L;
     __shared__ int s_item;
     __shared__ double red[WAVES][NQ];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -221,7 +228,7 @@ __global__ void __launch_bounds__(64 * sep::k3WX * sep::k3WY) batch_sep_kernel(B
         if (I.n > 0) {
             const sep::SepGeom sg{I.nx, I.ny, I.a0, I.b0, I.dx, I.dy};
             if constexpr (HALF) {
-                sep::sep_accumulate_h(sg, A.rec + I.rec_off, 0, I.n, tx, ty, I.scale, L, accR, accI);
+                sep::sep_accumulate_h<T>(sg, A.rec + I.rec_off, 0, I.n, tx, ty, I.scale, L, accR, accI);
 #pragma unroll
                 for (int p = 0; p < BY; p++)
 #pragma unroll
@@ -365,18 +372,21 @@ hipError_t launch_batch_e0(const BatchEval *inst, int32_t n_inst, const Rec32 *r
 hipError_t launch_batch_eval(int rows, int waves, int form, bool half, int cus, const BatchArgs &a, hipStream_t s) {
     if (form == 3) {
         int per_cu = 0;
-        hipError_t e = half ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_sep_kernel<true>,
-                                                                           64 * kSepWavesX * kSepWavesY, 0)
-                            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_sep_kernel<false>,
-                                                                           64 * kSepWavesX * kSepWavesY, 0);
+        const int th = half ? 64 * BatchTile<true>::WX * BatchTile<true>::WY
+                            : 64 * BatchTile<false>::WX * BatchTile<false>::WY;
+        static_assert(BatchTile<false>::WX == kSepWavesX && BatchTile<false>::WY == kSepWavesY &&
+                          BatchTile<true>::WX == kSepHWavesX && BatchTile<true>::WY == kSepHWavesY,
+                      "batched separable tiles: host and kernel disagree");
+        hipError_t e = half ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_sep_kernel<true>, th, 0)
+                            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_sep_kernel<false>, th, 0);
         if (e != hipSuccess) return e;
         if (per_cu < 1) per_cu = 1;
         const int grid = (int)min((int64_t)a.n_items, (int64_t)cus * per_cu);
         if (grid <= 0) return hipSuccess;
         if (half)
-            batch_sep_kernel<true><<<grid, 64 * kSepWavesX * kSepWavesY, 0, s>>>(a);
+            batch_sep_kernel<true><<<grid, th, 0, s>>>(a);
         else
-            batch_sep_kernel<false><<<grid, 64 * kSepWavesX * kSepWavesY, 0, s>>>(a);
+            batch_sep_kernel<false><<<grid, th, 0, s>>>(a);
         return hipGetLastError();
     }
 #define GBD_CASE(R, W)                                                                         \

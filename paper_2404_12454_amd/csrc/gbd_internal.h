@@ -328,10 +328,9 @@ hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t s);
 // CU at the register and LDS budget).
 constexpr int kSepWavesX = 2, kSepWavesY = 4;
 constexpr int kSepTileX = 64, kSepTileY = 32;
-// The FP16 halves form of single evaluations: wavefront tiles of kSepHTile x
-// kSepHTile pixels, kSepHWavesX x kSepHWavesY wavefronts per workgroup
-// (256 x 128 pixels, all of a CU's LDS).  The batched sweep keeps the
-// 128 x 128 workgroup tiles above for both of its separable forms.
+// The FP16 halves form (single evaluations and the batched sweep): wavefront
+// tiles of kSepHTile x kSepHTile pixels, kSepHWavesX x kSepHWavesY wavefronts
+// per workgroup (256 x 128 pixels, one workgroup per CU).
 constexpr int kSepHWavesX = 4, kSepHWavesY = 2, kSepHTile = 64;
 constexpr int64_t kSepMaxSegLen = 16384;  // beamlets per FP32 segment at most (automatic segment count)
 // The FP64 separable form on FP64 MFMA: wavefront tiles of 64 x 32 pixels
