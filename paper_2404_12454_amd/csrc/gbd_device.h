@@ -412,7 +412,19 @@ __device__ inline uint32_t setup_one(const BeamletsDev &b, const PlaneGeom &pl, 
         o32.m[0] = -INFINITY;
     }
     if (r64) r64[j] = o64;
-    if (r32) r32[j] = o32;
+    if (r32) {
+        if (sigma32) {
+            r32[j] = o32;
+        } else {
+            // the rotor tables are left to launch_sigma, run before every
+            // rotor-form evaluation: the record's first 112 bytes only
+            static_assert(offsetof(Rec32, sq) == 112, "Rec32 layout");
+            const uint4 *src = reinterpret_cast<const uint4 *>(&o32);
+            uint4 *dst = reinterpret_cast<uint4 *>(r32 + j);
+#pragma unroll
+            for (int k = 0; k < 7; k++) dst[k] = src[k];
+        }
+    }
     if (is_cut && c64) c64[j - cut0] = oc;
     if (is_cut && c32) {
         RecCut32 o;

@@ -34,13 +34,32 @@ __global__ void __launch_bounds__(256) setup_kernel(BeamletsDev b, PlaneGeom pl,
     float peak = -INFINITY;
     uint32_t flag = 0;
     if (j < b.n) flag = setup_one(b, pl, gturns, j, r64, r32, h64, h32, c64, c32, false, &peak);
-    if (flag) atomicOr(status, flag);
-    // status[1]: the largest term modulus of any beamlet over the grid, as
-    // ceil(log2) + 2048 clamped to [1, 4095] (0: none), one atomic per wavefront
+    // status[0]: the flags OR-ed; status[1]: the largest term modulus of any
+    // beamlet over the grid, as ceil(log2) + 2048 clamped to [1, 4095] (0:
+    // none).  One atomic of each per workgroup: the words are shared by the
+    // whole grid, so per-lane atomics serialise (an informational flag such as
+    // FLAG_STEEP is set by most beamlets)
     uint32_t key = isfinite(peak) ? (uint32_t)fminf(fmaxf(ceilf(peak) + 2048.0f, 1.0f), 4095.0f) : 0u;
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) key = max(key, (uint32_t)__shfl_xor((int)key, o));
-    if ((threadIdx.x & 63) == 0 && key) atomicMax(status + 1, key);
+    for (int o = 32; o > 0; o >>= 1) {
+        key = max(key, (uint32_t)__shfl_xor((int)key, o));
+        flag |= (uint32_t)__shfl_xor((int)flag, o);
+    }
+    __shared__ uint32_t wflag[4], wkey[4];
+    if ((threadIdx.x & 63) == 0) {
+        wflag[threadIdx.x >> 6] = flag;
+        wkey[threadIdx.x >> 6] = key;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t f = 0, k = 0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); w++) {
+            f |= wflag[w];
+            k = max(k, wkey[w]);
+        }
+        if (f) atomicOr(status, f);
+        if (k) atomicMax(status + 1, k);
+    }
 }
 
 // The rotor forms' sigma^(k^2) tables, k = 1..16, from the FP64 records on
@@ -359,11 +378,15 @@ __global__ void __launch_bounds__(256) reduce_mixed_kernel(int64_t M, int32_t ns
                                                            float2 *__restrict__ out) {
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < M; p += (int64_t)gridDim.x * blockDim.x) {
         double re = 0.0, im = 0.0;
+        // unrolled so that several segments' loads are in flight at once;
+        // the sums still run in segment order
+#pragma unroll 8
         for (int s = 0; s < nseg2; s++) {
             const float2 v = part2[(int64_t)s * M + p];
             re += (double)v.x;
             im += (double)v.y;
         }
+#pragma unroll 8
         for (int s = 0; s < nseg4; s++) {
             const float4 v = part4[(int64_t)s * M + p];
             re += (double)v.x - (double)v.z;
@@ -377,6 +400,7 @@ __global__ void __launch_bounds__(256) reduce_fp64_kernel(int64_t M, int32_t nse
                                                           double2 *__restrict__ out) {
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < M; p += (int64_t)gridDim.x * blockDim.x) {
         double re = 0.0, im = 0.0;
+#pragma unroll 8
         for (int s = 0; s < nseg; s++) {
             const double2 v = part[(int64_t)s * M + p];
             re += v.x;
