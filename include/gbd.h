@@ -381,6 +381,12 @@ int gbd_eval_batch(gbd_ctx_t ctx, int32_t n_inst, const gbd_beamlets_t *beamlets
  *          mean((y - target)^2) in the handle; loss_dev (optional, device) gets
  *          the loss
  *   adamw  one decoupled-weight-decay Adam step with bias correction
+ *   train  `steps` minibatch steps in one call, each exactly backward on rows
+ *          [s][0..batch) (device int32 [steps][batch], required) then adamw
+ *          with learning rate lr_host[s] (host float [steps]); loss_sum_dev
+ *          (optional, device float) has each step's loss added to it in step
+ *          order.  The same kernels as the separate calls, without a host
+ *          round trip per step.
  *   set_params uploads parameters and zeroes the optimiser state. */
 enum { GBD_MLP_FP32 = 0, GBD_MLP_BF16 = 1 };
 typedef struct gbd_mlp_s *gbd_mlp_t;
@@ -395,6 +401,8 @@ int gbd_mlp_forward(gbd_mlp_t m, const float *x, const int32_t *rows, int32_t ba
 int gbd_mlp_backward(gbd_mlp_t m, const float *x, const float *target, const int32_t *rows, int32_t batch,
                      float *loss_dev);
 int gbd_mlp_adamw(gbd_mlp_t m, float lr, float beta1, float beta2, float eps, float weight_decay);
+int gbd_mlp_train(gbd_mlp_t m, const float *x, const float *target, const int32_t *rows, int32_t steps, int32_t batch,
+                  const float *lr_host, float beta1, float beta2, float eps, float weight_decay, float *loss_sum_dev);
 
 #ifdef __cplusplus
 }

@@ -98,6 +98,8 @@ def load_library():
         "gbd_mlp_backward": (ctypes.c_int, [P, P, P, P, I32, P]),
         "gbd_mlp_adamw": (ctypes.c_int, [P, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                          ctypes.c_float]),
+        "gbd_mlp_train": (ctypes.c_int, [P, P, P, P, I32, I32, P, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                         ctypes.c_float, P]),
         "gbd_autotune_batch": (ctypes.c_int, [P, I32, P, P, P, I64, I32, P, P]),
         "gbd_autotune_save": (ctypes.c_int, [P, ctypes.c_char_p]),
         "gbd_autotune_load": (ctypes.c_int, [P, ctypes.c_char_p]),
@@ -524,6 +526,20 @@ class Mlp:
     def adamw(self, lr, beta1=0.9, beta2=0.999, eps=1e-8, weight_decay=0.0):
         _check(load_library().gbd_mlp_adamw(self.handle, float(lr), float(beta1), float(beta2), float(eps),
                                             float(weight_decay)))
+
+    def train(self, x, target, rows, lrs, beta1=0.9, beta2=0.999, eps=1e-8, weight_decay=0.0, loss_sum=None):
+        """len(lrs) steps of backward on rows[s] then adamw(lrs[s]) in one
+        call; rows: device int32 [steps, batch]; loss_sum: optional device
+        float32 [1] that each step's loss is added to."""
+        lr = np.ascontiguousarray(lrs, dtype=np.float32)
+        steps, batch = int(rows.shape[0]), int(rows.shape[1])
+        if lr.size != steps:
+            raise ValueError(f"{lr.size} learning rates for {steps} steps")
+        _check(load_library().gbd_mlp_train(self.handle, ctypes.c_void_p(x.data_ptr()),
+                                            ctypes.c_void_p(target.data_ptr()), ctypes.c_void_p(rows.data_ptr()),
+                                            steps, batch, _p(lr), float(beta1), float(beta2), float(eps),
+                                            float(weight_decay),
+                                            None if loss_sum is None else ctypes.c_void_p(loss_sum.data_ptr())))
 
     def __del__(self):
         try:

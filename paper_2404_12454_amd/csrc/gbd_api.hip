@@ -1676,11 +1676,14 @@ int gbd_mlp_backward(gbd_mlp_t m, const float *x, const float *target, const int
     return GBD_OK;
 }
 
+static bool adamw_args_ok(float lr, float beta1, float beta2, float eps, float weight_decay) {
+    return lr >= 0.0f && beta1 >= 0.0f && beta1 < 1.0f && beta2 >= 0.0f && beta2 < 1.0f && eps >= 0.0f &&
+           weight_decay >= 0.0f;
+}
+
 int gbd_mlp_adamw(gbd_mlp_t m, float lr, float beta1, float beta2, float eps, float weight_decay) {
     if (!m) return fail(GBD_EINVAL, "NULL argument");
-    if (!(lr >= 0.0f) || !(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) || !(eps >= 0.0f) ||
-        !(weight_decay >= 0.0f))
-        return fail(GBD_EINVAL, "invalid AdamW hyper-parameters");
+    if (!adamw_args_ok(lr, beta1, beta2, eps, weight_decay)) return fail(GBD_EINVAL, "invalid AdamW hyper-parameters");
     int rc = ensure_device(m->ctx);
     if (rc) return rc;
     m->step++;
@@ -1688,6 +1691,25 @@ int gbd_mlp_adamw(gbd_mlp_t m, float lr, float beta1, float beta2, float eps, fl
     HIP_TRY(launch_mlp_adamw(m->params, m->grads, m->m, m->v, m->P, lr, beta1, beta2, eps, weight_decay, c1, c2,
                              m->ctx->stream),
             "adamw launch");
+    return GBD_OK;
+}
+
+int gbd_mlp_train(gbd_mlp_t m, const float *x, const float *target, const int32_t *rows, int32_t steps, int32_t batch,
+                  const float *lr_host, float beta1, float beta2, float eps, float weight_decay, float *loss_sum_dev) {
+    if (!m || !x || !target || !rows || !lr_host) return fail(GBD_EINVAL, "NULL argument");
+    if (steps < 0) return fail(GBD_EINVAL, "negative step count %d", steps);
+    if (batch < 1 || batch > m->max_batch) return fail(GBD_ERANGE, "batch %d outside [1, %d]", batch, m->max_batch);
+    // every step's arguments are checked before the first one runs
+    for (int32_t s = 0; s < steps; s++)
+        if (!adamw_args_ok(lr_host[s], beta1, beta2, eps, weight_decay))
+            return fail(GBD_EINVAL, "invalid AdamW hyper-parameters (step %d)", s);
+    for (int32_t s = 0; s < steps; s++) {
+        int rc = gbd_mlp_backward(m, x, target, rows + (int64_t)s * batch, batch, nullptr);
+        if (rc) return rc;
+        if (loss_sum_dev) HIP_TRY(launch_mlp_accum(loss_sum_dev, m->loss, m->ctx->stream), "loss sum launch");
+        rc = gbd_mlp_adamw(m, lr_host[s], beta1, beta2, eps, weight_decay);
+        if (rc) return rc;
+    }
     return GBD_OK;
 }
 

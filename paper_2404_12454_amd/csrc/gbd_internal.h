@@ -263,6 +263,7 @@ struct MlpGemm {
 };
 
 hipError_t launch_mlp_gemm(int bf16, const MlpGemm &g, hipStream_t s);
+hipError_t launch_mlp_accum(float *acc, const float *v, hipStream_t s);
 hipError_t launch_mlp_gather(const float *X, const float *y, const int32_t *idx, int B, int n_in, float *Xb, float *yb,
                              hipStream_t s);
 hipError_t launch_mlp_head_forward(const float *H, const float *w, const float *w0, int B, int W, float *yhat,

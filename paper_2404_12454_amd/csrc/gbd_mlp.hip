@@ -38,31 +38,46 @@ __device__ inline void epilogue(const MlpGemm &g, int m, int n, float acc) {
     }
 }
 
-// One wavefront per 16 x 16 output tile.  Operand layout of the 16x16x32
-// BF16 MFMA: lane l supplies A[l % 16][8 (l / 16) + i] and
-// B[8 (l / 16) + i][l % 16], i = 0..7, and receives D[4 (l / 16) + i][l % 16],
-// i = 0..3.  Every access is bounds-checked (zero padding of M, N and K).
-__global__ void __launch_bounds__(64) gemm_bf16_kernel(MlpGemm g) {
+// One workgroup of 4 wavefronts per 16 x 16 output tile, the K axis split
+// between them: wavefront w takes K steps of 32 w KS ... + KS - 1 of every
+// round of 4 KS steps, all their loads issued before the products (these
+// products are small, K <= 256 in training: load latency decides, not
+// throughput), and the four partial tiles are added in the order w = 0 ... 3
+// through LDS.  Operand layout of the 16x16x32 BF16 MFMA: lane l supplies
+// A[l % 16][8 (l / 16) + i] and B[8 (l / 16) + i][l % 16], i = 0..7, and
+// receives D[4 (l / 16) + i][l % 16], i = 0..3.  Every access is
+// bounds-checked (zero padding of M, N and K).
+template <int KS>
+__global__ void __launch_bounds__(256) gemm_bf16_kernel(MlpGemm g) {
+    __shared__ floatx4 part[4][64];
     const int tm = blockIdx.y * 16, tn = blockIdx.x * 16;
-    const int lane = threadIdx.x, r = lane & 15, kg = lane >> 4;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, r = lane & 15, kg = lane >> 4;
     floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
     const int m = tm + r, n = tn + r;
-    for (int k0 = 0; k0 < g.K; k0 += 32) {
-        bf16x8 va, vb;
+    for (int k0 = 32 * KS * w; k0 < g.K; k0 += 32 * KS * 4) {
+        bf16x8 va[KS], vb[KS];
 #pragma unroll
-        for (int i = 0; i < 8; i++) {
-            const int k = k0 + kg * 8 + i;
-            const float a = (m < g.M && k < g.K) ? g.A[(int64_t)m * g.sam + (int64_t)k * g.sak] : 0.0f;
-            const float b = (n < g.N && k < g.K) ? g.B[(int64_t)k * g.sbk + (int64_t)n * g.sbn] : 0.0f;
-            va[i] = (__bf16)a;
-            vb[i] = (__bf16)b;
-        }
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(va, vb, acc, 0, 0, 0);
+        for (int s = 0; s < KS; s++)
+#pragma unroll
+            for (int i = 0; i < 8; i++) {
+                const int k = k0 + 32 * s + kg * 8 + i;
+                const float a = (m < g.M && k < g.K) ? g.A[(int64_t)m * g.sam + (int64_t)k * g.sak] : 0.0f;
+                const float b = (n < g.N && k < g.K) ? g.B[(int64_t)k * g.sbk + (int64_t)n * g.sbn] : 0.0f;
+                va[s][i] = (__bf16)a;
+                vb[s][i] = (__bf16)b;
+            }
+#pragma unroll
+        for (int s = 0; s < KS; s++) acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(va[s], vb[s], acc, 0, 0, 0);
     }
+    part[w][lane] = acc;
+    __syncthreads();
+    if (w == 0) {
+        const floatx4 t = ((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane];
 #pragma unroll
-    for (int i = 0; i < 4; i++) {
-        const int mm = tm + kg * 4 + i, nn = tn + r;
-        if (mm < g.M && nn < g.N) epilogue(g, mm, nn, acc[i]);
+        for (int i = 0; i < 4; i++) {
+            const int mm = tm + kg * 4 + i, nn = tn + r;
+            if (mm < g.M && nn < g.N) epilogue(g, mm, nn, t[i]);
+        }
     }
 }
 
@@ -86,15 +101,18 @@ __global__ void __launch_bounds__(256) gather_kernel(const float *__restrict__ X
     if (y) yb[b] = y[r];
 }
 
-// yhat[b] = sum_i H[b][i] w[i] + w0
+// yhat[b] = sum_i H[b][i] w[i] + w0: a wavefront per row, lane l taking
+// columns l, l + 64, ... (coalesced), then a fixed shuffle tree
 __global__ void __launch_bounds__(256) head_forward_kernel(const float *__restrict__ H, const float *__restrict__ w,
                                                            const float *__restrict__ w0, int B, int W,
                                                            float *__restrict__ yhat) {
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= B) return;
+    const int b = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (b >= B) return;  // uniform per wavefront
     float acc = 0.0f;
-    for (int i = 0; i < W; i++) acc = fmaf(H[(int64_t)b * W + i], w[i], acc);
-    yhat[b] = acc + w0[0];
+    for (int i = lane; i < W; i += 64) acc = fmaf(H[(int64_t)b * W + i], w[i], acc);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+    if (lane == 0) yhat[b] = acc + w0[0];
 }
 
 // g[b] = 2 (yhat - y) / B and the loss mean((yhat - y)^2), one workgroup
@@ -116,14 +134,38 @@ __global__ void __launch_bounds__(256) loss_kernel(const float *__restrict__ yha
     if (threadIdx.x == 0 && loss) loss[0] = part[0] / (float)B;
 }
 
-// head gradients: dw[i] = sum_b g[b] H[b][i] (i < W), dw0 = sum_b g[b] (i == W)
-__global__ void __launch_bounds__(256) head_grad_kernel(const float *__restrict__ g, const float *__restrict__ H,
-                                                        int B, int W, float *__restrict__ dw) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i > W) return;
+// Column sums over a batch, in parallel and in a fixed order: a block of
+// 256 threads takes 32 columns, thread (c, r) sums rows r, r + 8, ... of
+// column c (coalesced across c), and the 8 partial sums of a column are
+// added in order r = 0 ... 7.  out[i] = sum_b wgt[b] X[b][i] for i < W (wgt
+// null: weight 1), and with bias_col also out[W] = sum_b wgt[b].
+constexpr int kSumCols = 32, kSumRows = 8;
+__device__ inline void column_sums(const float *__restrict__ X, const float *__restrict__ wgt, int B, int W,
+                                   bool bias_col, float *__restrict__ out) {
+    __shared__ float part[kSumRows][kSumCols];
+    const int c = threadIdx.x % kSumCols, r = threadIdx.x / kSumCols;
+    const int i = blockIdx.x * kSumCols + c;
     float acc = 0.0f;
-    for (int b = 0; b < B; b++) acc = fmaf(g[b], i < W ? H[(int64_t)b * W + i] : 1.0f, acc);
-    dw[i] = acc;
+    if (i < W) {
+        for (int b = r; b < B; b += kSumRows) acc = fmaf(wgt ? wgt[b] : 1.0f, X[(int64_t)b * W + i], acc);
+    } else if (bias_col && i == W) {
+        for (int b = r; b < B; b += kSumRows) acc += wgt ? wgt[b] : 1.0f;
+    }
+    part[r][c] = acc;
+    __syncthreads();
+    if (r == 0 && (i < W || (bias_col && i == W))) {
+        float s = part[0][c];
+#pragma unroll
+        for (int k = 1; k < kSumRows; k++) s += part[k][c];
+        out[i] = s;
+    }
+}
+
+// head gradients: dw[i] = sum_b g[b] H[b][i] (i < W), dw0 = sum_b g[b] (i == W)
+__global__ void __launch_bounds__(kSumCols * kSumRows) head_grad_kernel(const float *__restrict__ g,
+                                                                        const float *__restrict__ H, int B, int W,
+                                                                        float *__restrict__ dw) {
+    column_sums(H, g, B, W, true, dw);
 }
 
 // dZ[b][i] = g[b] w[i] SiLU'(Z[b][i]) for the last hidden layer
@@ -137,13 +179,9 @@ __global__ void __launch_bounds__(256) head_back_kernel(const float *__restrict_
 }
 
 // db[o] = sum_b dZ[b][o]
-__global__ void __launch_bounds__(256) colsum_kernel(const float *__restrict__ dZ, int B, int W,
-                                                     float *__restrict__ db) {
-    const int o = blockIdx.x * blockDim.x + threadIdx.x;
-    if (o >= W) return;
-    float acc = 0.0f;
-    for (int b = 0; b < B; b++) acc += dZ[(int64_t)b * W + o];
-    db[o] = acc;
+__global__ void __launch_bounds__(kSumCols * kSumRows) colsum_kernel(const float *__restrict__ dZ, int B, int W,
+                                                                     float *__restrict__ db) {
+    column_sums(dZ, nullptr, B, W, false, db);
 }
 
 __global__ void __launch_bounds__(256) adamw_kernel(float *__restrict__ p, const float *__restrict__ g,
@@ -160,6 +198,11 @@ __global__ void __launch_bounds__(256) adamw_kernel(float *__restrict__ p, const
     p[i] = p[i] - lr * (mh / (sqrtf(vh) + eps) + wd * p[i]);
 }
 
+// acc[0] += v[0] (one running loss sum in step order)
+__global__ void __launch_bounds__(64) accum_kernel(float *__restrict__ acc, const float *__restrict__ v) {
+    if (threadIdx.x == 0) acc[0] += v[0];
+}
+
 unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
 
 }  // namespace
@@ -168,7 +211,10 @@ hipError_t launch_mlp_gemm(int bf16, const MlpGemm &g, hipStream_t s) {
     if (g.M <= 0 || g.N <= 0) return hipSuccess;
     if (bf16) {
         dim3 grid((g.N + 15) / 16, (g.M + 15) / 16);
-        gemm_bf16_kernel<<<grid, 64, 0, s>>>(g);
+        if (g.K <= 128)
+            gemm_bf16_kernel<1><<<grid, 256, 0, s>>>(g);
+        else
+            gemm_bf16_kernel<2><<<grid, 256, 0, s>>>(g);
     } else {
         gemm_f32_kernel<<<blocks_for((int64_t)g.M * g.N, 256), 256, 0, s>>>(g);
     }
@@ -185,7 +231,7 @@ hipError_t launch_mlp_gather(const float *X, const float *y, const int32_t *idx,
 hipError_t launch_mlp_head_forward(const float *H, const float *w, const float *w0, int B, int W, float *yhat,
                                    hipStream_t s) {
     if (B <= 0) return hipSuccess;
-    head_forward_kernel<<<blocks_for(B, 256), 256, 0, s>>>(H, w, w0, B, W, yhat);
+    head_forward_kernel<<<blocks_for(B, 4), 256, 0, s>>>(H, w, w0, B, W, yhat);
     return hipGetLastError();
 }
 
@@ -193,14 +239,14 @@ hipError_t launch_mlp_head_backward(const float *yhat, const float *y, const flo
                                     int B, int W, float *g, float *loss, float *dw, float *dZ, hipStream_t s) {
     if (B <= 0) return hipSuccess;
     loss_kernel<<<1, 256, 0, s>>>(yhat, y, B, g, loss);
-    head_grad_kernel<<<blocks_for(W + 1, 256), 256, 0, s>>>(g, H, B, W, dw);
+    head_grad_kernel<<<blocks_for(W + 1, kSumCols), kSumCols * kSumRows, 0, s>>>(g, H, B, W, dw);
     head_back_kernel<<<blocks_for((int64_t)B * W, 256), 256, 0, s>>>(g, w, Z, B, W, dZ);
     return hipGetLastError();
 }
 
 hipError_t launch_mlp_colsum(const float *dZ, int B, int W, float *db, hipStream_t s) {
     if (W <= 0) return hipSuccess;
-    colsum_kernel<<<blocks_for(W, 256), 256, 0, s>>>(dZ, B, W, db);
+    colsum_kernel<<<blocks_for(W, kSumCols), kSumCols * kSumRows, 0, s>>>(dZ, B, W, db);
     return hipGetLastError();
 }
 
@@ -208,6 +254,11 @@ hipError_t launch_mlp_adamw(float *p, const float *g, float *m, float *v, int64_
                             float eps, float wd, float c1, float c2, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     adamw_kernel<<<blocks_for(n, 256), 256, 0, s>>>(p, g, m, v, n, lr, b1, b2, eps, wd, c1, c2);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_accum(float *acc, const float *v, hipStream_t s) {
+    accum_kernel<<<1, 64, 0, s>>>(acc, v);
     return hipGetLastError();
 }
 

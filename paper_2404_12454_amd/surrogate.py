@@ -105,18 +105,16 @@ class Surrogate:
         n = len(params)
         steps_per_epoch = max(1, n // self.batch)
         total = epochs * steps_per_epoch
-        loss = torch.zeros(1, device=X.device)
         step = 0
         for ep in range(epochs):
             perm = torch.tensor(rng.permutation(n).astype(np.int32), device=X.device)
             acc = torch.zeros(1, device=X.device)
-            for s in range(steps_per_epoch):
-                rows = perm[s * self.batch:(s + 1) * self.batch]
-                self.net.backward(X, y, rows=rows, loss_out=loss)
-                cur = lr * 0.5 * (1.0 + math.cos(math.pi * step / total))
-                self.net.adamw(cur, weight_decay=weight_decay)
-                acc += loss
-                step += 1
+            # one library call per epoch: each step is backward on its rows
+            # then AdamW at the cosine-schedule rate
+            rows = perm[:steps_per_epoch * self.batch].view(steps_per_epoch, self.batch)
+            lrs = [lr * 0.5 * (1.0 + math.cos(math.pi * (step + s) / total)) for s in range(steps_per_epoch)]
+            self.net.train(X, y, rows, lrs, weight_decay=weight_decay, loss_sum=acc)
+            step += steps_per_epoch
             if ep % 10 == 0 or ep == epochs - 1:
                 self.history.append((ep, float(acc.cpu()) / steps_per_epoch))
         return self

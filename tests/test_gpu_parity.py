@@ -115,7 +115,8 @@ def test_separable_form_is_chosen_and_matches_oracle(ctx):
 
 
 @pytest.mark.parametrize("variant", [0, 5])
-@pytest.mark.parametrize("nx,ny,seg", [(70, 45, 1), (70, 45, 3), (129, 200, 0), (1, 1, 1), (65, 1, 2), (1, 70, 0)])
+@pytest.mark.parametrize("nx,ny,seg", [(70, 45, 1), (70, 45, 3), (129, 200, 0), (300, 140, 0), (300, 140, 5),
+                                       (1, 1, 1), (65, 1, 2), (1, 70, 0)])
 def test_separable_form_ragged_defocused_off_axis(ctx, nx, ny, seg, variant):
     """Grids that leave every 16 x 16 block, wavefront and workgroup tile
     partly empty, beamlet counts not a multiple of the quad of beamlets an

@@ -31,8 +31,12 @@ def test_surrogate_prunes_the_search():
     assert rec["rms_ratio_to_optimum"] <= 1.005
     assert rec["rms_ratio_to_optimum"] <= float(np.median(rec["random32_ratio_to_optimum"]))
     assert rec["rms_ratio_to_optimum"] < rec["heuristic32_ratio_to_optimum"]
-    # the online phase (inference + 32 re-scores) is cheaper than the exhaustive sweep
-    assert rec["online_s"] < rec["exhaustive_s"]
+    # No timing assertion at this size: the exhaustive sweep over 231 small
+    # instances is one call of ~50 ms and the online phase (inference, then one
+    # 32-instance call) ~2 calls, so their ratio is set by per-call costs that
+    # vary between runs (below 1 in one run, above 1 in others).  The full-size
+    # test below asserts the speed-up where the sweep is what costs (8,897
+    # candidates at 512 x 512).
 
 
 def test_surrogate_full_size_finds_the_optimum_first():
