@@ -110,6 +110,16 @@ int gbd_ctx_create(gbd_ctx_t *out, int device, void *hip_stream);
 /* Rebind the context to another stream of the same device. */
 int gbd_ctx_set_stream(gbd_ctx_t ctx, void *hip_stream);
 void gbd_ctx_destroy(gbd_ctx_t ctx);
+/* Kernel timing, for measurement: while enabled, every plan evaluation
+ * (gbd_plan_eval, gbd_eval; not the allocation-free gbd_plan_eval_noalloc)
+ * records a pair of HIP events on the context stream around its N x M
+ * evaluation kernel of the whole beamlets (after the rotor form's table
+ * kernel, before any truncated-beamlet kernel and the segment reduction).  gbd_ctx_kernel_times waits for
+ * the recorded pairs, writes up to `cap` of their durations in milliseconds,
+ * oldest first, to ms_out (host), sets *n to how many there were and
+ * forgets them all.  Disabling keeps pending pairs until they are taken. */
+int gbd_ctx_set_kernel_timing(gbd_ctx_t ctx, int enable);
+int gbd_ctx_kernel_times(gbd_ctx_t ctx, float *ms_out, int32_t cap, int32_t *n);
 /* Thread-local description of the last failure in this thread. */
 const char *gbd_last_error(void);
 

@@ -69,6 +69,8 @@ def load_library():
         "gbd_ctx_create": (ctypes.c_int, [PP, ctypes.c_int, P]),
         "gbd_ctx_set_stream": (ctypes.c_int, [P, P]),
         "gbd_ctx_destroy": (None, [P]),
+        "gbd_ctx_set_kernel_timing": (ctypes.c_int, [P, ctypes.c_int]),
+        "gbd_ctx_kernel_times": (ctypes.c_int, [P, P, I32, P]),
         "gbd_trace": (ctypes.c_int, [P, I32, P, D, D, D, I64, P, P, D, D, P, P, P]),
         "gbd_beamlets_traced": (ctypes.c_int, [P, PP, I64, D, D, P, P, P, I64, P, P, P, P, D]),
         "gbd_last_error": (ctypes.c_char_p, []),
@@ -143,6 +145,17 @@ class Context:
     def set_stream(self, stream):
         self.stream = stream
         _check(load_library().gbd_ctx_set_stream(self.handle, ctypes.c_void_p(stream.cuda_stream)))
+
+    def set_kernel_timing(self, enable: bool = True):
+        """Record HIP events around each evaluation's N x M kernel."""
+        _check(load_library().gbd_ctx_set_kernel_timing(self.handle, 1 if enable else 0))
+
+    def kernel_times(self, cap: int = 4096) -> list:
+        """Durations (ms) of the kernels timed since the last call, oldest first."""
+        buf = np.zeros(cap, dtype=np.float32)
+        n = ctypes.c_int32()
+        _check(load_library().gbd_ctx_kernel_times(self.handle, _p(buf), cap, ctypes.byref(n)))
+        return [float(v) for v in buf[:min(n.value, cap)]]
 
     def close(self):
         if getattr(self, "handle", None) and self.handle.value:

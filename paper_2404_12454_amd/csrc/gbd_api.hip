@@ -64,6 +64,10 @@ struct gbd_ctx_s {
     gbd_plan_s *own_plan;  // plan used by gbd_eval
     BatchWork batch;
     std::map<TuneKey, TuneVal> tuned;
+    // kernel timing (gbd_ctx_set_kernel_timing): recorded event pairs, and
+    // spare pairs for reuse
+    bool timing = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> timed, spare_events;
 };
 
 struct gbd_beamlets_s {
@@ -553,6 +557,26 @@ int plan_eval_impl(gbd_ctx_s *ctx, gbd_plan_s *plan, int precision, void *out, i
         const void *hrec = !hg ? nullptr : precision == GBD_FP64 ? (const void *)plan->h64 : (const void *)plan->h32;
         EvalGeom gl = g;
         if (reduce) gl.nseg = std::max<int32_t>(total, 2);  // segment partials, never the output
+        if (s.form == 2)
+            HIP_TRY(launch_sigma(gl, plan->r64, precision == GBD_FP64 ? plan->q64 : nullptr,
+                                 precision == GBD_FP64 ? nullptr : plan->r32, ctx->stream),
+                    "sigma table kernel launch");
+        std::pair<hipEvent_t, hipEvent_t> tev{nullptr, nullptr};
+        if (ctx->timing && !fixed) {  // the allocation-free path records none
+            if (!ctx->spare_events.empty()) {
+                tev = ctx->spare_events.back();
+                ctx->spare_events.pop_back();
+            } else {
+                HIP_TRY(hipEventCreate(&tev.first), "hipEventCreate");
+                const hipError_t e = hipEventCreate(&tev.second);
+                if (e != hipSuccess) {
+                    (void)hipEventDestroy(tev.first);
+                    return hip_fail(e, "hipEventCreate");
+                }
+            }
+            ctx->timed.push_back(tev);
+            HIP_TRY(hipEventRecord(tev.first, ctx->stream), "hipEventRecord");
+        }
         if (s.form == 3 && precision == GBD_FP64)
             HIP_TRY(launch_eval_sep64(gl, plan->r64, static_cast<const RecHG64 *>(hrec),
                                       static_cast<double2 *>(partial), static_cast<double2 *>(out), ctx->stream),
@@ -565,15 +589,11 @@ int plan_eval_impl(gbd_ctx_s *ctx, gbd_plan_s *plan, int precision, void *out, i
             HIP_TRY(launch_eval_sep(gl, plan->r32, static_cast<const RecHG32 *>(hrec),
                                     static_cast<float2 *>(partial), static_cast<float2 *>(out), ctx->stream),
                     "eval kernel launch");
-        else {
-            if (s.form == 2)
-                HIP_TRY(launch_sigma(gl, plan->r64, precision == GBD_FP64 ? plan->q64 : nullptr,
-                                     precision == GBD_FP64 ? nullptr : plan->r32, ctx->stream),
-                        "sigma table kernel launch");
+        else
             HIP_TRY(launch_eval(precision, s.rows, s.waves, s.form, gl, rec, hrec, plan->q64, partial, out,
                                 ctx->stream),
                     "eval kernel launch");
-        }
+        if (tev.second) HIP_TRY(hipEventRecord(tev.second, ctx->stream), "hipEventRecord");
     }
     if (nseg_cut > 0) {
         const void *rec = precision == GBD_FP64 ? (const void *)(plan->r64 + n_main) : (const void *)(plan->r32 + n_main);
@@ -746,7 +766,40 @@ void gbd_ctx_destroy(gbd_ctx_t ctx) {
     (void)hipSetDevice(ctx->device);
     plan_destroy(ctx->own_plan);
     batch_free(ctx->batch);
+    for (auto *v : {&ctx->timed, &ctx->spare_events})
+        for (auto &ev : *v) {
+            (void)hipEventDestroy(ev.first);
+            (void)hipEventDestroy(ev.second);
+        }
     delete ctx;
+}
+
+int gbd_ctx_set_kernel_timing(gbd_ctx_t ctx, int enable) {
+    if (!ctx) return fail(GBD_EINVAL, "ctx is NULL");
+    ctx->timing = enable != 0;
+    return GBD_OK;
+}
+
+int gbd_ctx_kernel_times(gbd_ctx_t ctx, float *ms_out, int32_t cap, int32_t *n) {
+    if (!ctx || !n || (cap > 0 && !ms_out)) return fail(GBD_EINVAL, "NULL argument");
+    if (cap < 0) return fail(GBD_EINVAL, "negative capacity");
+    int rc = ensure_device(ctx);
+    if (rc) return rc;
+    int32_t k = 0;
+    hipError_t first_err = hipSuccess;
+    for (auto &ev : ctx->timed) {
+        float ms = 0.0f;
+        hipError_t e = hipEventSynchronize(ev.second);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev.first, ev.second);
+        if (e != hipSuccess && first_err == hipSuccess) first_err = e;
+        if (k < cap) ms_out[k] = ms;
+        k++;
+        ctx->spare_events.push_back(ev);
+    }
+    ctx->timed.clear();
+    *n = k;
+    if (first_err != hipSuccess) return hip_fail(first_err, "kernel timing events");
+    return GBD_OK;
 }
 
 static int beamlets_impl(gbd_ctx_t ctx, gbd_beamlets_t *out, int64_t n, double lambda, double l0, const double *r1,
