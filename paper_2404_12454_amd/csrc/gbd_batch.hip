@@ -200,7 +200,7 @@ __global__ void __launch_bounds__(64 * WAVES) batch_eval_kernel(BatchArgs A) {
 // The FP16 halves form takes the single evaluation's 256 x 128 workgroup
 // tiles (HTileLarge), the FP32 one its 128 x 128 (the k3 layout).
 template <bool HALF>
-using BatchTile = typename std::conditional<HALF, sep::HTileLarge, sep::HTileSmall>::type;
+using BatchTile = typename std::conditional<HALF, sep::HTileLarge, sep::Sep3Tile>::type;
 
 template <bool HALF>
 __global__ void __launch_bounds__(64 * BatchTile<HALF>::WX * BatchTile<HALF>::WY) batch_sep_kernel(BatchArgs A) {

@@ -300,25 +300,25 @@ __device__ inline uint32_t rot_halves(uint32_t v) {
     return w;
 }
 
-// Tiles of the FP16 halves form: WX x WY wavefronts of BX x BY 16 x 16
-// blocks.  Per quad of beamlets a lane forms UB = BX / WY factors U (its
-// wavefront shares its x range with WY - 1 others) and VB = BY / WX factors V.
-//   HTileSmall: 2 x 4 wavefronts of 64 x 32 pixels (128 x 128 per
-//     workgroup, 99 KiB of LDS); per lane and quad 1 U + 1 V factor beside
-//     the products of 2 blocks;
-//   HTileLarge: 4 x 2 wavefronts of 64 x 64 pixels (256 x 128 per
-//     workgroup, 133 KiB of LDS); per lane and quad 2 U + 1 V beside the
-//     products of 4 blocks: a quarter less factor arithmetic per pair
-//     (0.442 -> 0.339 ms on 51,468 beamlets x 512^2 pixels).  Both single
-//     evaluations and the batched sweep use it.
+// Workgroup tiles: WX x WY wavefronts of BX x BY 16 x 16 blocks.  In the
+// FP16 halves form a lane forms, per quad of beamlets, UB = BX / WY factors
+// U (its wavefront shares its x range with WY - 1 others) and VB = BY / WX
+// factors V.
+//   HTileLarge (the FP16 halves form, single evaluations and the batched
+//     sweep): 4 x 2 wavefronts of 64 x 64 pixels (256 x 128 per workgroup,
+//     133 KiB of LDS); per lane and quad 2 U + 1 V beside the products of 4
+//     blocks.  The k3 layout (2 x 4 of 64 x 32, 1 U + 1 V beside 2 blocks)
+//     took a third more factor arithmetic per pair in this form (0.442
+//     against 0.339 ms on 51,468 beamlets x 512^2 pixels); the FP32 form
+//     keeps it (Sep3Tile).
 template <int WX_, int WY_, int BX_, int BY_>
 struct HTile {
     static constexpr int WX = WX_, WY = WY_, BX = BX_, BY = BY_;
     static constexpr int UB = BX / WY, VB = BY / WX;
     static_assert(BX % WY == 0 && BY % WX == 0 && BX * BY % 4 == 0, "FP16 halves tile");
 };
-using HTileSmall = HTile<k3WX, k3WY, k3BX, k3BY>;
 using HTileLarge = HTile<4, 2, 4, 4>;
+using Sep3Tile = HTile<k3WX, k3WY, k3BX, k3BY>;  // the FP32 form's workgroup (dimensions only)
 
 // LDS per buffer: U (hi, lo) and V (A_h, A_l, W_h, W_l) words of one pass of
 // 16 beamlets, double-buffered so the next pass's factors are written while
@@ -352,10 +352,8 @@ struct SepHLdsT {
     static constexpr int kRows = (64 * T::WX * T::WY + kStageUsed - 1) / kStageUsed;
     uint32_t rs[2][kRows][kStageWords];
 };
-using SepHLds = SepHLdsT<HTileSmall>;
 static_assert(sizeof(SepHLdsT<HTileLarge>) <= 163840, "the large tile's LDS exceeds a workgroup's 160 KiB");
-static_assert(64 * HTileSmall::WX * HTileSmall::WY >= 16 * kStageUsed &&
-                  64 * HTileLarge::WX * HTileLarge::WY >= 16 * kStageUsed,
+static_assert(64 * HTileLarge::WX * HTileLarge::WY >= 16 * kStageUsed,
               "a workgroup stages a pass's records one word per thread");
 
 __device__ inline h8 operand(const uint32_t *p) { return __builtin_bit_cast(h8, *reinterpret_cast<const uint4 *>(p)); }
@@ -369,7 +367,7 @@ __device__ inline h8 operand(const uint32_t *p) { return __builtin_bit_cast(h8, 
 // and the factors of pass p + 1, formed during pass p, read pass p + 1's.
 // Every pass forms the next one's factors, the last one too (past the end:
 // zero factors nobody reads), so the loop body has no branch.
-template <class T = HTileSmall>
+template <class T>
 __device__ inline void sep_accumulate_h(const SepGeom &g, const Rec32 *__restrict__ rec, int64_t jb, int64_t je,
                                         int tx, int ty, int scale, SepHLdsT<T> &L, f4 (&accR)[T::BY][T::BX],
                                         f4 (&accI)[T::BY][T::BX]) {
