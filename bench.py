@@ -591,6 +591,19 @@ def hermite(ctx, stream, gauss_ms, n_across=256, npix=512, reps=10):
         if shape["variant"] in (4, 5):
             r["mfma_frac"] = roofline(shape, sc.n, npix * npix, ms)["frac"]
             r["cost_vs_fundamental"] = ms / gauss_ms
+        if shape["variant"] == 4:  # the same on FP32 MFMA (variant 5) for comparison
+            o5 = gbd.gbd_eval_opts(variant=5)
+            plan.eval(gbd.GBD_MIXED, out, opts=o5)
+            e5 = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+            for a, z in e5:
+                a.record(stream)
+                plan.eval(gbd.GBD_MIXED, out, opts=o5)
+                z.record(stream)
+            torch.cuda.synchronize()
+            ms5 = float(np.mean([a.elapsed_time(z) for a, z in e5]))
+            r["separable_fp32"] = {"eval_ms": ms5, "launch": plan.shape(gbd.GBD_MIXED, o5),
+                                   "mfma_frac": roofline(plan.shape(gbd.GBD_MIXED, o5), sc.n, npix * npix, ms5)["frac"]}
+            plan.eval(gbd.GBD_MIXED, out)  # the automatic form's field, for the FP64 comparison below
         elif shape["variant"] == 3:
             rf = roofline(shape, sc.n, npix * npix, ms, hg=True)
             r["roofline_peak"] = rf["peak"]

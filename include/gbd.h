@@ -79,15 +79,18 @@ typedef struct {
                                3 = rotor: per lane and beamlet an FP64 anchor phasor at
                                the lane's middle row, the other rows by complex
                                recurrence (anchor x rho^k x sigma^(k^2)); 4 = separable:
-                               E = sum_j U_j(x) V_j(y) as a complex matrix product, for
-                               fundamental beamlets on FP16 MFMA with every factor split
-                               into FP16 hi and lo halves (the hi x hi, hi x lo and
-                               lo x hi products, FP32 accumulation; each beamlet's
-                               factors scaled by powers of two into FP16's range from
-                               the setup's bounds over the grid, so a term's error
-                               stays below 2^-20 of itself or 2^-38 of the largest
-                               term over the grid, whichever is larger), for
-                               higher-order beamlets as 5; 5 = separable
+                               E = sum_j U_j(x) V_j(y) as a complex matrix product on
+                               FP16 MFMA with every factor (of a higher-order beamlet:
+                               times its axis polynomial) split into FP16 hi and lo
+                               halves (the hi x hi, hi x lo and lo x hi products, FP32
+                               accumulation; each beamlet's factors scaled by powers of
+                               two into FP16's range from the setup's bounds over the
+                               grid, so a term's error stays below 2^-20 of itself or
+                               2^-38 of the largest term over the grid, whichever is
+                               larger; a higher-order factor's bound takes its
+                               polynomial's largest modulus near the spot, which can
+                               exceed the term's, loosening the second figure by that
+                               ratio); 5 = separable
                                on FP32 MFMA in three real products per pair (Gauss's
                                form).  Workgroup tiles: 4 x 2 wavefronts of 64 x 64
                                pixels in FP16 halves (gbd_plan_shape reports 64 rows, 8

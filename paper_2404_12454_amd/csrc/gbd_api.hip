@@ -280,10 +280,10 @@ Shape choose_shape(const gbd_ctx_s *ctx, int precision, int64_t n, const PlaneGe
                    const gbd_eval_opts *o) {
     Shape s;
     s.form = pick_form(precision, flags, o);
-    // the mixed separable form of fundamental beamlets runs on FP16 MFMA in
-    // hi/lo halves unless the FP32 one is requested (variant 5); higher-order
-    // factors keep FP32 (their polynomial moduli are not bounded by the setup)
-    s.half = s.form == 3 && precision == GBD_MIXED && !(flags & FLAG_HG) && !(o && o->variant == 5);
+    // the mixed separable form runs on FP16 MFMA in hi/lo halves unless the
+    // FP32 one is requested (variant 5); the setup bounds higher-order
+    // factors with their axis polynomials for the FP16 scaling
+    s.half = s.form == 3 && precision == GBD_MIXED && !(o && o->variant == 5);
     if (s.form == 3) {
         // separable form: fixed 64 x 32 pixel tile per wavefront (s.rows is
         // the tile height), 2 x 4 wavefronts per workgroup (s.waves), or in
@@ -582,7 +582,8 @@ int plan_eval_impl(gbd_ctx_s *ctx, gbd_plan_s *plan, int precision, void *out, i
                                       static_cast<double2 *>(partial), static_cast<double2 *>(out), ctx->stream),
                     "eval kernel launch");
         else if (s.form == 3 && s.half)
-            HIP_TRY(launch_eval_seph(gl, plan->r32, plan->sep_scale, static_cast<float2 *>(partial),
+            HIP_TRY(launch_eval_seph(gl, plan->r32, static_cast<const RecHG32 *>(hrec), plan->sep_scale,
+                                     static_cast<float2 *>(partial),
                                      static_cast<float2 *>(out), ctx->stream),
                     "eval kernel launch");
         else if (s.form == 3)

@@ -228,7 +228,7 @@ __global__ void __launch_bounds__(64 * BatchTile<HALF>::WX * BatchTile<HALF>::WY
         if (I.n > 0) {
             const sep::SepGeom sg{I.nx, I.ny, I.a0, I.b0, I.dx, I.dy};
             if constexpr (HALF) {
-                sep::sep_accumulate_h<T>(sg, A.rec + I.rec_off, 0, I.n, tx, ty, I.scale, L, accR, accI);
+                sep::sep_accumulate_h<T>(sg, A.rec + I.rec_off, nullptr, 0, I.n, tx, ty, I.scale, L, accR, accI);
 #pragma unroll
                 for (int p = 0; p < BY; p++)
 #pragma unroll

@@ -101,6 +101,24 @@ __device__ inline double log2_envelope_max(double c1, double c2, double d0, doub
     return m;
 }
 
+// The same bound for an envelope times a higher-order axis polynomial
+// |c0 + c1 g + c2 g^2|, g = G d (|G| = ga, |c0| = a0c, |c1| = a1, |c2| = a2):
+// |P| <= Pm(|d|) = a0c + a1 ga |d| + a2 ga^2 d^2, increasing in |d|.  Where
+// the envelope decays, beyond 8 / sqrt(-c2) of its vertex it lies 64 bits
+// below its largest value on the lattice (env), so the bound is the larger of
+// env + log2 Pm(|vertex| + 8 / sqrt(-c2)) and env - 64 + log2 Pm(T), T the
+// largest |d| on the lattice; otherwise env + log2 Pm(T).
+__device__ inline double log2_hg_envelope_max(double c1, double c2, double d0, double step, int n, double a0c,
+                                              double a1, double a2, double ga) {
+    const double env = log2_envelope_max(c1, c2, d0, step, n);
+    if (n <= 0) return env;
+    auto pm = [&](double r) { return log2(a0c + a1 * ga * r + a2 * ga * ga * r * r); };
+    const double T = fmax(fabs(d0), fabs(d0 + (n - 1) * step));
+    if (!(c2 < 0.0)) return env + pm(T);
+    const double R = fmin(T, fabs(-c1 / (2.0 * c2)) + 8.0 / sqrt(-c2));
+    return fmax(env + pm(R), env - 64.0 + pm(T));
+}
+
 // sep_peak (optional): log2 of the largest modulus of the beamlet's term over
 // the grid, U's part of it stored in the Rec32 record (pad) for the FP16
 // separable form's range balancing; -inf for a beamlet that contributes nothing.
@@ -243,6 +261,9 @@ __device__ inline uint32_t setup_one(const BeamletsDev &b, const PlaneGeom &pl, 
         l[4] = 2.0 * (kh * G[0][1].im + 0.25 * trQ2.re * ez[0] * ez[1]);
         l[5] = kh * G[1][1].im + 0.25 * trQ2.re * ez[1] * ez[1];
         bool fin = isfinite(arho) && isfinite(brho) && isfinite(ag.re) && isfinite(ag.im);
+        // higher-order factors' coefficient moduli (x: |cx0|, |cx1|, |cx2|, |g_xx|; y likewise)
+        double hgb[8] = {1.0, 0.0, 0.0, 0.0, 1.0, 0.0, 0.0, 0.0};
+        bool has_hgb = false;
 #pragma unroll
         for (int i = 0; i < 6; i++) fin = fin && isfinite(p[i]) && (i == 0 || isfinite(l[i]));
         if (h64 || h32) {
@@ -296,6 +317,15 @@ __device__ inline uint32_t setup_one(const BeamletsDev &b, const PlaneGeom &pl, 
             oh.ex1 = hm == 2 ? 1.0 : 0.0;
             oh.ey0 = hn == 2 ? 0.0 : 1.0;
             oh.ey1 = hn == 2 ? 1.0 : 0.0;
+            hgb[0] = hypot(oh.cx0[0], oh.cx0[1]);
+            hgb[1] = fabs(oh.cx1);
+            hgb[2] = fabs(oh.cx2);
+            hgb[3] = hypot(Gh[0][0].re, Gh[0][0].im);
+            hgb[4] = hypot(oh.cy0[0], oh.cy0[1]);
+            hgb[5] = fabs(oh.cy1);
+            hgb[6] = fabs(oh.cy2);
+            hgb[7] = hypot(Gh[1][1].re, Gh[1][1].im);
+            has_hgb = true;
             const cd k1 = scl(hxy, (double)(hm * hn));
             const cd k0 = (hm == 2 && hn == 2) ? scl(mul(hxy, hxy), 2.0) : mk(0.0, 0.0);
             oh.k1[0] = k1.re;
@@ -389,8 +419,15 @@ __device__ inline uint32_t setup_one(const BeamletsDev &b, const PlaneGeom &pl, 
         {
             // separable factors' moduli over the grid: |U| <= 2^umax, |V| <= 2^vmax
             const double a0 = -0.5 * (pl.nx - 1) * pl.dx, b0 = -0.5 * (pl.ny - 1) * pl.dy;
-            const double umax = (double)o32.m[0] + log2_envelope_max(o32.m[1], o32.m[3], a0 - arho, pl.dx, pl.nx);
-            const double vmax = log2_envelope_max(o32.m[2], o32.m[5], b0 - brho, pl.dy, pl.ny);
+            // (with a higher-order factor, times its axis polynomial's bound)
+            const double umax =
+                (double)o32.m[0] +
+                (has_hgb ? log2_hg_envelope_max(o32.m[1], o32.m[3], a0 - arho, pl.dx, pl.nx, hgb[0], hgb[1], hgb[2],
+                                                hgb[3])
+                         : log2_envelope_max(o32.m[1], o32.m[3], a0 - arho, pl.dx, pl.nx));
+            const double vmax = has_hgb ? log2_hg_envelope_max(o32.m[2], o32.m[5], b0 - brho, pl.dy, pl.ny, hgb[4],
+                                                               hgb[5], hgb[6], hgb[7])
+                                        : log2_envelope_max(o32.m[2], o32.m[5], b0 - brho, pl.dy, pl.ny);
             const bool ok = isfinite(umax) && isfinite(vmax);
             o32.pad = ok ? (float)umax : 0.0f;
             if (sep_peak) *sep_peak = ok ? (float)(umax + vmax) : -INFINITY;

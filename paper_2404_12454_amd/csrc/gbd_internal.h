@@ -360,7 +360,7 @@ hipError_t launch_eval_sep(const EvalGeom &g, const Rec32 *rec, const RecHG32 *h
 // 2^scale (scale = 2 kSepHalfExp - P, 2^P the largest term over the grid,
 // from the setup); partials and output are written descaled.
 constexpr int kSepHalfExp = 14;
-hipError_t launch_eval_seph(const EvalGeom &g, const Rec32 *rec, int scale, float2 *partial, float2 *out,
-                            hipStream_t s);
+hipError_t launch_eval_seph(const EvalGeom &g, const Rec32 *rec, const RecHG32 *hg, int scale, float2 *partial,
+                            float2 *out, hipStream_t s);
 
 }  // namespace gbd

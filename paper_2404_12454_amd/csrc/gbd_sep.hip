@@ -86,9 +86,10 @@ __global__ void __launch_bounds__(64 * k3WX * k3WY) eval_sep_kernel(EvalGeom g, 
 // FP16 halves form (fundamental beamlets): the same stores from tiles of
 // T (HTileLarge: 4 x 2 wavefronts of 64 x 64 pixels), the accumulators
 // descaled by 2^-scale (exact: a power of two).
-template <class T>
+template <class T, bool HG>
 __global__ void __launch_bounds__(64 * T::WX * T::WY) eval_seph_kernel(EvalGeom g, const Rec32 *__restrict__ rec,
-                                                                        int scale, float2 *__restrict__ partial,
+                                                                        const RecHG32 *__restrict__ hg, int scale,
+                                                                        float2 *__restrict__ partial,
                                                                         float2 *__restrict__ out) {
     __shared__ SepHLdsT<T> L;
     const int w = work_item(blockIdx.x, gridDim.x);
@@ -105,7 +106,7 @@ __global__ void __launch_bounds__(64 * T::WX * T::WY) eval_seph_kernel(EvalGeom 
     const int64_t jb = (int64_t)seg * g.seg_len;
     const int64_t je = min(g.n, jb + g.seg_len);
     f4 accR[T::BY][T::BX], accI[T::BY][T::BX];
-    sep_accumulate_h<T>(sg, rec, jb, je, tx, ty, scale, L, accR, accI);
+    sep_accumulate_h<T, HG>(sg, rec, hg, jb, je, tx, ty, scale, L, accR, accI);
 
     const int64_t M = (int64_t)g.nx * g.ny;
 #pragma unroll
@@ -130,13 +131,16 @@ __global__ void __launch_bounds__(64 * T::WX * T::WY) eval_seph_kernel(EvalGeom 
 
 }  // namespace
 
-hipError_t launch_eval_seph(const EvalGeom &g, const Rec32 *rec, int scale, float2 *partial, float2 *out,
-                            hipStream_t s) {
+hipError_t launch_eval_seph(const EvalGeom &g, const Rec32 *rec, const RecHG32 *hg, int scale, float2 *partial,
+                            float2 *out, hipStream_t s) {
     using T = HTileLarge;
     static_assert(T::WX == kSepHWavesX && T::WY == kSepHWavesY && 16 * T::BX == kSepHTile && 16 * T::BY == kSepHTile,
                   "FP16 halves tiles: host and kernel disagree");
     const int grid = (g.work + 7) / 8 * 8;
-    eval_seph_kernel<T><<<grid, 64 * T::WX * T::WY, 0, s>>>(g, rec, scale, partial, out);
+    if (hg)
+        eval_seph_kernel<T, true><<<grid, 64 * T::WX * T::WY, 0, s>>>(g, rec, hg, scale, partial, out);
+    else
+        eval_seph_kernel<T, false><<<grid, 64 * T::WX * T::WY, 0, s>>>(g, rec, nullptr, scale, partial, out);
     return hipGetLastError();
 }
 

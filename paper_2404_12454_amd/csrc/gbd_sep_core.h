@@ -340,6 +340,13 @@ constexpr int kStageWords = 24, kStageUsed = 22;
 __device__ constexpr int kStageSrc[kStageUsed] = {0, 1, 4, 5, 6, 7, 10, 11, 2, 3, 8, 9, 14, 15,
                                                   16, 17, 19, 18, 21, 22, 23, 27};
 static_assert(sizeof(Rec32) == 60 * 4 && kStageWords % 4 == 0, "staged record layout");
+// Higher-order beamlets: 12 words of each RecHG32 (the diagonal of G and the
+// per-axis polynomial coefficients), staged beside the record words by the
+// first 16 x 12 threads: staged word w holds RecHG32 word kStageSrcHG[w]:
+//   0-5 g_xx (re, im), cx0 (re, im), cx1, cx2     6-11 g_yy, cy0, cy1, cy2
+constexpr int kStageHG = 12;
+__device__ constexpr int kStageSrcHG[kStageHG] = {0, 1, 8, 9, 12, 13, 6, 7, 10, 11, 14, 15};
+static_assert(sizeof(RecHG32) == 24 * 4, "staged higher-order record layout");
 
 template <class T>
 struct SepHLdsT {
@@ -351,6 +358,9 @@ struct SepHLdsT {
     // compiler sink the load into the guard, next to the store)
     static constexpr int kRows = (64 * T::WX * T::WY + kStageUsed - 1) / kStageUsed;
     uint32_t rs[2][kRows][kStageWords];
+    // higher-order words, [buffer][beamlet in pass][staged word] likewise
+    static constexpr int kRowsHG = (64 * T::WX * T::WY + kStageHG - 1) / kStageHG;
+    uint32_t rh[2][kRowsHG][kStageHG];
 };
 static_assert(sizeof(SepHLdsT<HTileLarge>) <= 163840, "the large tile's LDS exceeds a workgroup's 160 KiB");
 static_assert(64 * HTileLarge::WX * HTileLarge::WY >= 16 * kStageUsed,
@@ -358,8 +368,10 @@ static_assert(64 * HTileLarge::WX * HTileLarge::WY >= 16 * kStageUsed,
 
 __device__ inline h8 operand(const uint32_t *p) { return __builtin_bit_cast(h8, *reinterpret_cast<const uint4 *>(p)); }
 
-// As sep_accumulate_3m (segment walk) for fundamental beamlets in FP16
-// halves, tile T; accR / accI hold the field times 2^scale.  The hi x hi,
+// As sep_accumulate_3m (segment walk) in FP16 halves, tile T; accR / accI
+// hold the field times 2^scale.  HG: higher-order beamlets without cross
+// terms, each factor times its axis polynomial (hg_axis, as in the FP32
+// form) before the split.  The hi x hi,
 // hi x lo and lo x hi products of every block in that order each pass (lo
 // x lo, at most 2^-22 of a term, is left out).  The record words reach LDS
 // two passes before their factors are used: during pass p each thread loads
@@ -367,9 +379,10 @@ __device__ inline h8 operand(const uint32_t *p) { return __builtin_bit_cast(h8, 
 // and the factors of pass p + 1, formed during pass p, read pass p + 1's.
 // Every pass forms the next one's factors, the last one too (past the end:
 // zero factors nobody reads), so the loop body has no branch.
-template <class T>
-__device__ inline void sep_accumulate_h(const SepGeom &g, const Rec32 *__restrict__ rec, int64_t jb, int64_t je,
-                                        int tx, int ty, int scale, SepHLdsT<T> &L, f4 (&accR)[T::BY][T::BX],
+template <class T, bool HG = false>
+__device__ inline void sep_accumulate_h(const SepGeom &g, const Rec32 *__restrict__ rec,
+                                        const RecHG32 *__restrict__ hg, int64_t jb, int64_t je, int tx, int ty,
+                                        int scale, SepHLdsT<T> &L, f4 (&accR)[T::BY][T::BX],
                                         f4 (&accI)[T::BY][T::BX]) {
     constexpr int WX = T::WX, WY = T::WY, BX = T::BX, BY = T::BY, UB = T::UB, VB = T::VB;
     constexpr int Q = 4;                 // quads of beamlets per pass (one pass of 16 between barriers)
@@ -383,6 +396,7 @@ __device__ inline void sep_accumulate_h(const SepGeom &g, const Rec32 *__restric
     auto &lu = L.lu;
     auto &lv = L.lv;
     auto &rs = L.rs;
+    auto &rh = L.rh;
 
     // this wavefront forms U blocks wy UB ... + UB - 1 of x range wx and V
     // blocks wx VB ... + VB - 1 of y range wy (unmasked past the grid's edge,
@@ -404,18 +418,32 @@ __device__ inline void sep_accumulate_h(const SepGeom &g, const Rec32 *__restric
     }
     const float E = (float)kSepHalfExp, sc = (float)scale;
     const Rec32 *__restrict__ srec = rec + jb;
+    const RecHG32 *__restrict__ shg = HG ? hg + jb : nullptr;
     const int n = (int)(je - jb);
 
     // staging: thread t moves word kStageSrc[t % 22] of record t / 22 (the
     // threads past 16 x 22 load words of later records, clamped, and store
     // them into rows nobody reads)
     const int st = threadIdx.x, sr = st / kStageUsed, sc_w = st - sr * kStageUsed, sw_src = kStageSrc[sc_w];
-    auto stage_load = [&](int i0) {  // a word of the pass starting at beamlet i0
-        const int i = i0 + sr;
-        return reinterpret_cast<const uint32_t *>(srec + (i < n ? i : 0))[sw_src];
+    // and, for higher-order beamlets, word kStageSrcHG[t % 12] of record t / 12
+    const int hr = st / kStageHG, hc = st - hr * kStageHG, hw_src = HG ? kStageSrcHG[hc] : 0;
+    struct Staged {
+        uint32_t w, h;
     };
-    auto stage_store = [&](int sbuf, uint32_t w) {
-        rs[sbuf][sr][sc_w] = w;
+    auto stage_load = [&](int i0) {  // words of the pass starting at beamlet i0
+        const int i = i0 + sr;
+        Staged v;
+        v.w = reinterpret_cast<const uint32_t *>(srec + (i < n ? i : 0))[sw_src];
+        v.h = 0u;
+        if constexpr (HG) {
+            const int ih = i0 + hr;
+            v.h = reinterpret_cast<const uint32_t *>(shg + (ih < n ? ih : 0))[hw_src];
+        }
+        return v;
+    };
+    auto stage_store = [&](int sbuf, const Staged &v) {
+        rs[sbuf][sr][sc_w] = v.w;
+        if constexpr (HG) rh[sbuf][hr][hc] = v.h;
     };
 
     // quad qd of a pass: beamlet b = 4 qd + lk, the pass's records in rs[sbuf]
@@ -442,10 +470,22 @@ __device__ inline void sep_accumulate_h(const SepGeom &g, const Rec32 *__restric
         const float mbias = i0 + b < n ? 0.0f : -INFINITY;
         const float lu0 = (m0 + (E - u)) + mbias, lv0 = (sc - E) + u;
         const int col = 4 * (qd ^ sw) + lk;
+        float hx[6], hy[6];
+        if constexpr (HG) {
+            const uint4 *hq = reinterpret_cast<const uint4 *>(rh[sbuf][b]);
+            const uint4 q0 = hq[0], q1 = hq[1], q2 = hq[2];
+            const uint32_t hw[12] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w, q2.x, q2.y, q2.z, q2.w};
+#pragma unroll
+            for (int k = 0; k < 6; k++) {
+                hx[k] = __builtin_bit_cast(float, hw[k]);
+                hy[k] = __builtin_bit_cast(float, hw[6 + k]);
+            }
+        }
 #pragma unroll
         for (int k = 0; k < UB; k++) {
             float ur, ui;
             factor(ax[k] - arho, axf[k] - arf, p0, p1, p3, lu0, m1, m3, ur, ui);
+            if constexpr (HG) hg_axis(axf[k] - arf, hx[0], hx[1], hx[2], hx[3], hx[4], hx[5], ur, ui);
             uint32_t uh, ul;
             split_halves(ur, ui, uh, ul);
             lu[buf][wx][wy * UB + k][0][li][col] = uh;
@@ -455,6 +495,7 @@ __device__ inline void sep_accumulate_h(const SepGeom &g, const Rec32 *__restric
         for (int k = 0; k < VB; k++) {
             float vr, vi;
             factor(by[k] - brho, byf[k] - brf, 0.0, p2, p5, lv0, m2, m5, vr, vi);
+            if constexpr (HG) hg_axis(byf[k] - brf, hy[0], hy[1], hy[2], hy[3], hy[4], hy[5], vr, vi);
             // A = (Vr, -Vi) halves; W = (Vi, Vr) = rot_halves(A)
             uint32_t ah, al;
             split_halves_conj(vr, vi, ah, al);
@@ -473,7 +514,7 @@ __device__ inline void sep_accumulate_h(const SepGeom &g, const Rec32 *__restric
 
     // passes 0 and 1's records, then pass 0's factors
     {
-        const uint32_t w0 = stage_load(0), w1 = stage_load(P);
+        const Staged w0 = stage_load(0), w1 = stage_load(P);
         stage_store(0, w0);
         stage_store(1, w1);
     }
@@ -485,7 +526,7 @@ __device__ inline void sep_accumulate_h(const SepGeom &g, const Rec32 *__restric
     int buf = 0;
     for (int i0 = 0; i0 < n; i0 += P) {
         // pass p = i0 / P: factors in buf, records of pass p + 1 in rs[buf ^ 1]
-        const uint32_t wnext = stage_load(i0 + 2 * P);
+        const Staged wnext = stage_load(i0 + 2 * P);
         // keep the load here, a pass before its use (the scheduler would
         // otherwise sink it to the store and wait on it there)
         __builtin_amdgcn_sched_barrier(0);

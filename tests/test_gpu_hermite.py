@@ -65,9 +65,11 @@ def test_hermite_beamlets_match_oracle(ctx, name, precision):
 def test_hermite_forms_resolve(ctx):
     sym = scenes.hermite_scene(12, npix=64)
     astig = scenes.hermite_scene(12, npix=64, cyl_f=3.0)
-    # mixed: the separable form of higher-order beamlets stays on FP32 MFMA (5)
-    assert resolved_variant(ctx, sym) == 5
-    assert resolved_variant(ctx, sym, dict(variant=4)) == 5
+    # mixed: the separable form of higher-order beamlets in FP16 halves (4),
+    # or on FP32 MFMA on request (5)
+    assert resolved_variant(ctx, sym) == 4
+    assert resolved_variant(ctx, sym, dict(variant=4)) == 4
+    assert resolved_variant(ctx, sym, dict(variant=5)) == 5
     assert resolved_variant(ctx, astig) == 3
     # the stepped form does not carry the Hermite-Gaussian factor
     assert resolved_variant(ctx, sym, dict(variant=2)) == 1
@@ -89,7 +91,7 @@ def test_hermite_forms_resolve(ctx):
     assert plan.shape(gbd.GBD_MIXED, dict(rows_per_lane=32, waves=4, variant=1))["rows_per_lane"] == 16
 
 
-@pytest.mark.parametrize("variant", [1, 3, 4])
+@pytest.mark.parametrize("variant", [1, 3, 4, 5])
 @pytest.mark.parametrize("rows,waves,segments", [(1, 1, 1), (2, 2, 3), (4, 4, 2), (8, 1, 5), (16, 4, 1), (16, 2, 7),
                                                  (32, 4, 3), (32, 1, 1)])
 def test_hermite_mixed_shapes(ctx, variant, rows, waves, segments):
@@ -211,3 +213,22 @@ def test_hermite_refusals(ctx):
     import torch
     torch.cuda.synchronize()
     assert not E.cpu().numpy().any()
+
+
+@pytest.mark.parametrize("variant", [4, 5])
+def test_hermite_separable_halves_wide_spots_and_orders(ctx, variant):
+    """The separable form in FP16 halves (4) against the FP32 one (5) and the
+    oracle where the axis polynomials reach far: order 2 on both axes, a
+    defocused plane (broad spots, large g at the grid's edge), a multi-tile
+    ragged grid; the setup's bound of each factor with its polynomial keeps
+    every factor inside FP16's range."""
+    sc = scenes.hermite_scene(16, npix=300, npix_y=140, z0=3e-3, half_span_lamF=24.0, seed=3)
+    sc.order = np.array([(2, 2)] * sc.n, np.int32)
+    ref = oracle.eval_field(sc)
+    assert resolved_variant(ctx, sc, dict(variant=variant)) == variant
+    E = field(ctx, sc, gbd.GBD_MIXED, dict(variant=variant))
+    err = rel_l2(E, ref)
+    print(f"hermite (2, 2) defocused variant {variant}: rel_l2 {err:.2e}", flush=True)
+    assert np.isfinite(E).all()
+    assert err < 1e-5
+
