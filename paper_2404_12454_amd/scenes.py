@@ -25,6 +25,7 @@ Conventions (metres, paraxial slopes, ray vector order (x, y, theta_x, theta_y))
 """
 from __future__ import annotations
 
+import functools
 import math
 from dataclasses import dataclass, field
 from typing import Optional
@@ -98,23 +99,32 @@ class Scene:
         return self.abcd.shape[0] == 1
 
 
-def pupil_grid(n_across: int, D: float) -> tuple[np.ndarray, float]:
-    """Cell-centred square grid clipped to the circular aperture of diameter D.
-    Returns (r1 [n,2] in row-major order of (iy, ix), spacing s)."""
+@functools.lru_cache(maxsize=64)
+def _pupil_grid(n_across: int, D: float) -> tuple[np.ndarray, float]:
     s = D / n_across
     c = (np.arange(n_across) - (n_across - 1) / 2.0) * s
     yy, xx = np.meshgrid(c, c, indexing="ij")
     keep = xx * xx + yy * yy <= (D / 2.0) ** 2
     r1 = np.stack([xx[keep], yy[keep]], axis=1).astype(np.float64)
-    return np.ascontiguousarray(r1), s
+    r1.flags.writeable = False
+    return r1, s
+
+
+def pupil_grid(n_across: int, D: float) -> tuple[np.ndarray, float]:
+    """Cell-centred square grid clipped to the circular aperture of diameter D.
+    Returns (r1 [n,2] in row-major order of (iy, ix), spacing s): a fresh copy
+    of a cached grid (the parameter sweeps draw the same few grids many times)."""
+    r1, s = _pupil_grid(int(n_across), float(D))
+    return np.array(r1, dtype=np.float64, order="C"), s
 
 
 def lens_then_distance(f: float, d: float) -> np.ndarray:
     """4x4 row-major ray-transfer matrix: thin lens f, then free space d."""
     I = np.eye(2)
-    Z = np.zeros((2, 2))
-    lens = np.block([[I, Z], [-I / f, I]])
-    dist = np.block([[I, d * I], [Z, I]])
+    lens = np.eye(4)
+    lens[2:, :2] = -I / f
+    dist = np.eye(4)
+    dist[:2, 2:] = d * I
     return dist @ lens
 
 
