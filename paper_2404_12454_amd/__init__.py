@@ -129,6 +129,11 @@ def _p(a: Optional[np.ndarray]):
     return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
 
 
+def _handles(objs) -> np.ndarray:
+    """The objects' C handles as one array of pointers."""
+    return np.fromiter((o.hv for o in objs), dtype=np.uintp, count=len(objs))
+
+
 class Context:
     """A library context bound to one device and one HIP stream (default:
     torch's current stream on that device)."""
@@ -176,6 +181,7 @@ def gbd_ctx_create(device: int = 0, stream=None) -> Context:
 class Beamlets:
     def __init__(self, handle, n):
         self.handle, self.n = handle, n
+        self.hv = handle.value or 0  # the handle as an int, for handle arrays
 
     def __del__(self):
         try:
@@ -188,6 +194,7 @@ class Beamlets:
 class Plane:
     def __init__(self, handle, nx, ny):
         self.handle, self.nx, self.ny = handle, nx, ny
+        self.hv = handle.value or 0
 
     def __del__(self):
         try:
@@ -433,8 +440,7 @@ def gbd_eval_batch(ctx: Context, beamlets, planes, airy=None, zone_edges=None, f
     n = len(beamlets)
     if len(planes) != n:
         raise ValueError("beamlets and planes differ in length")
-    hb = (ctypes.c_void_p * max(n, 1))(*[b.handle.value for b in beamlets])
-    hp = (ctypes.c_void_p * max(n, 1))(*[p.handle.value for p in planes])
+    hb, hp = _handles(beamlets), _handles(planes)
     ze = None if zone_edges is None else _f64(zone_edges)
     nz = 0 if ze is None else ze.size - 1
     metrics = np.zeros((n, 2 + nz)) if airy is not None else None
@@ -444,7 +450,7 @@ def gbd_eval_batch(ctx: Context, beamlets, planes, airy=None, zone_edges=None, f
         fbuf = torch.empty(max(total, 1), dtype=torch.complex64, device=f"cuda:{ctx.device}")
     o = _opts(opts)
     _check(load_library().gbd_eval_batch(
-        ctx.handle, n, hb, hp, None if airy is None else ctypes.c_void_p(airy.data_ptr()),
+        ctx.handle, n, _p(hb), _p(hp), None if airy is None else ctypes.c_void_p(airy.data_ptr()),
         0 if airy is None else airy.numel() * 4, _p(ze), nz, _p(metrics),
         None if fbuf is None else ctypes.c_void_p(fbuf.data_ptr()), 0 if fbuf is None else fbuf.numel() * 8,
         None if o is None else ctypes.byref(o)))
@@ -471,11 +477,10 @@ def gbd_autotune(plan: Plan, precision: int = GBD_MIXED, reps: int = 3):
 
 def gbd_autotune_batch(ctx: Context, beamlets, planes, airy, reps: int = 2):
     n = len(beamlets)
-    hb = (ctypes.c_void_p * n)(*[b.handle.value for b in beamlets])
-    hp = (ctypes.c_void_p * n)(*[p.handle.value for p in planes])
+    hb, hp = _handles(beamlets), _handles(planes)
     best = gbd_eval_opts()
     ms = ctypes.c_double()
-    _check(load_library().gbd_autotune_batch(ctx.handle, n, hb, hp, ctypes.c_void_p(airy.data_ptr()), airy.numel() * 4,
+    _check(load_library().gbd_autotune_batch(ctx.handle, n, _p(hb), _p(hp), ctypes.c_void_p(airy.data_ptr()), airy.numel() * 4,
                                              int(reps), ctypes.byref(best), ctypes.byref(ms)))
     return dict(rows_per_lane=best.rows_per_lane, waves=best.waves), ms.value
 

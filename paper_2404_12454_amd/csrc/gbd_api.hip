@@ -38,8 +38,12 @@ struct DevBuf {
 };
 
 struct BatchWork {
-    DevBuf rec, inst, offs, eval, items, e0, part, metrics, flags, point, peaks;
-    uint32_t *host_flags = nullptr;  // pinned: status, bad instance
+    DevBuf rec, l5, e0t, tab1, tab2, e0, e0part, part, metrics, flags, point;
+    uint32_t *host_flags = nullptr;  // pinned: the point evaluation's status
+    void *stage = nullptr;           // pinned staging of the batch tables
+    size_t stage_bytes = 0;
+    hipEvent_t stage_ev = nullptr;   // after the last copy from stage
+    bool stage_pending = false;      // stage_ev recorded and not yet waited for
 };
 
 // autotuner cache key: (kind, precision, log2 N bucket, log2 M bucket)
@@ -714,11 +718,16 @@ int grow(DevBuf &b, size_t bytes, const char *what) {
 }
 
 void batch_free(BatchWork &w) {
-    DevBuf *all[] = {&w.rec, &w.inst, &w.offs, &w.eval, &w.items, &w.e0, &w.part, &w.metrics, &w.flags, &w.point,
-                     &w.peaks};
+    DevBuf *all[] = {&w.rec,    &w.l5,   &w.e0t,     &w.tab1,  &w.tab2, &w.e0,
+                     &w.e0part, &w.part, &w.metrics, &w.flags, &w.point};
+    if (w.stage_ev) {
+        (void)hipEventSynchronize(w.stage_ev);
+        (void)hipEventDestroy(w.stage_ev);
+    }
     for (DevBuf *b : all)
         if (b->p) (void)hipFree(b->p);
     if (w.host_flags) (void)hipHostFree(w.host_flags);
+    if (w.stage) (void)hipHostFree(w.stage);
     w = BatchWork();
 }
 
@@ -1355,12 +1364,55 @@ int gbd_eval_batch(gbd_ctx_t ctx, int32_t n_inst, const gbd_beamlets_t *bs, cons
         return fail(GBD_ERANGE, "fields_out holds %lld bytes, %lld needed", (long long)fields_bytes,
                     (long long)(field_elems * 8));
     if (n_items > 0x3fffffff) return fail(GBD_ERANGE, "too many work items");
+    if (total / kE0Chunk + n_inst > 0x3fffffff) return fail(GBD_ERANGE, "too many beamlets in the batch");
     int rc = ensure_device(ctx);
     if (rc) return rc;
 
-    // per-beamlet setup of every instance; the status decides the mixed form
-    std::vector<BatchInst> inst(n_inst);
-    std::vector<int64_t> offs(n_inst + 1, 0);
+    // per-beamlet setup of every instance; the status decides the mixed form.
+    // The host tables pass through one pinned staging buffer:
+    //   [BatchInst x n | offs x (n + 1)]   uploaded before the setup (tab1)
+    //   [status x 4 | peaks x n]           read back after it
+    //   [BatchEval x n | items | e0map]    uploaded before the evaluation (tab2)
+    // each table part in one copy to a device buffer of the same layout.  The
+    // host rewrites the buffer only once the stream has passed the previous
+    // call's copies from it (stage_ev).
+    const int PS = 2 + 2 * n_zones;
+    BatchWork &w = ctx->batch;
+    const int64_t max_chunks = total / kE0Chunk + n_inst;  // normalisation chunks, at most
+    auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    const size_t t1_offs = al(n_inst * sizeof(BatchInst));
+    const size_t t1_bytes = t1_offs + al((n_inst + 1) * sizeof(int64_t));
+    const size_t rb_bytes = al((4 + (size_t)n_inst) * sizeof(uint32_t));
+    const size_t t2_items = al(n_inst * sizeof(BatchEval));
+    const size_t t2_e0map = t2_items + al((size_t)std::max<int64_t>(2 * n_items, 2) * sizeof(int32_t));
+    const size_t t2_bytes = t2_e0map + al((size_t)max_chunks * sizeof(int32_t));
+    if ((rc = grow(w.rec, (size_t)std::max<int64_t>(total, 1) * sizeof(Rec32), "batch records")) ||
+        (rc = grow(w.l5, (size_t)std::max<int64_t>(total, 1) * sizeof(double), "batch records")) ||
+        (airy && (rc = grow(w.e0t, (size_t)std::max<int64_t>(total, 1) * sizeof(double2), "batch normalisation"))) ||
+        (airy && (rc = grow(w.e0part, (size_t)max_chunks * sizeof(double2), "batch normalisation"))) ||
+        (rc = grow(w.tab1, t1_bytes, "batch table")) || (rc = grow(w.tab2, t2_bytes, "batch table")) ||
+        (rc = grow(w.e0, n_inst * sizeof(double2), "batch normalisation")) ||
+        (rc = grow(w.part, (size_t)std::max<int64_t>(n_items, 1) * PS * sizeof(double), "batch partials")) ||
+        (rc = grow(w.metrics, (size_t)n_inst * (2 + n_zones) * sizeof(double), "batch metrics")) ||
+        (rc = grow(w.flags, rb_bytes, "batch flags")))
+        return rc;
+    hipStream_t st = ctx->stream;
+    if (!w.stage_ev) HIP_TRY(hipEventCreateWithFlags(&w.stage_ev, hipEventDisableTiming), "hipEventCreate");
+    if (w.stage_pending) HIP_TRY(hipEventSynchronize(w.stage_ev), "hipEventSynchronize");
+    w.stage_pending = false;
+    const size_t stage_bytes = t1_bytes + rb_bytes + t2_bytes;
+    if (stage_bytes > w.stage_bytes) {
+        if (w.stage) (void)hipHostFree(w.stage);
+        w.stage = nullptr;
+        w.stage_bytes = 0;
+        HIP_TRY(hipHostMalloc(&w.stage, stage_bytes, hipHostMallocDefault), "hipHostMalloc(batch staging)");
+        w.stage_bytes = stage_bytes;
+    }
+    char *h1 = static_cast<char *>(w.stage), *hrb = h1 + t1_bytes, *h2 = hrb + rb_bytes;
+    char *d1 = static_cast<char *>(w.tab1.p), *d2 = static_cast<char *>(w.tab2.p);
+    BatchInst *inst = reinterpret_cast<BatchInst *>(h1);
+    int64_t *offs = reinterpret_cast<int64_t *>(h1 + t1_offs);
+    offs[0] = 0;
     for (int32_t i = 0; i < n_inst; i++) {
         const BeamletsDev &b = bs[i]->dev;
         offs[i + 1] = offs[i] + b.n;
@@ -1370,38 +1422,25 @@ int gbd_eval_batch(gbd_ctx_t ctx, int32_t n_inst, const gbd_beamlets_t *bs, cons
         inst[i].rec_off = offs[i];
         inst[i].gturns = g0 - nearbyint(g0);
     }
-    const int PS = 2 + 2 * n_zones;
-    BatchWork &w = ctx->batch;
-    if ((rc = grow(w.rec, (size_t)std::max<int64_t>(total, 1) * sizeof(Rec32), "batch records")) ||
-        (rc = grow(w.inst, n_inst * sizeof(BatchInst), "batch table")) ||
-        (rc = grow(w.offs, (n_inst + 1) * sizeof(int64_t), "batch offsets")) ||
-        (rc = grow(w.eval, n_inst * sizeof(BatchEval), "batch table")) ||
-        (rc = grow(w.items, (size_t)std::max<int64_t>(2 * n_items, 2) * sizeof(int32_t), "batch work list")) ||
-        (rc = grow(w.e0, n_inst * sizeof(double2), "batch normalisation")) ||
-        (rc = grow(w.part, (size_t)std::max<int64_t>(n_items, 1) * PS * sizeof(double), "batch partials")) ||
-        (rc = grow(w.metrics, (size_t)n_inst * (2 + n_zones) * sizeof(double), "batch metrics")) ||
-        (rc = grow(w.flags, 4 * sizeof(uint32_t), "batch flags")) ||
-        (rc = grow(w.peaks, n_inst * sizeof(uint32_t), "batch peaks")))
-        return rc;
-    if (!w.host_flags) HIP_TRY(hipHostMalloc(&w.host_flags, 4 * sizeof(uint32_t), hipHostMallocDefault), "hipHostMalloc");
-    hipStream_t st = ctx->stream;
-    HIP_TRY(hipMemcpyAsync(w.inst.p, inst.data(), n_inst * sizeof(BatchInst), hipMemcpyHostToDevice, st), "table upload");
-    HIP_TRY(hipMemcpyAsync(w.offs.p, offs.data(), (n_inst + 1) * sizeof(int64_t), hipMemcpyHostToDevice, st), "table upload");
-    uint32_t *flags = static_cast<uint32_t *>(w.flags.p);  // [0] status, [1] first bad instance, [2] queue head
-    HIP_TRY(hipMemsetAsync(flags, 0, sizeof(uint32_t), st), "hipMemsetAsync");
-    HIP_TRY(hipMemsetAsync(flags + 1, 0x7f, sizeof(uint32_t), st), "hipMemsetAsync");
-    HIP_TRY(hipMemsetAsync(w.peaks.p, 0, n_inst * sizeof(uint32_t), st), "hipMemsetAsync");
-    HIP_TRY(launch_batch_setup(static_cast<BatchInst *>(w.inst.p), static_cast<int64_t *>(w.offs.p), n_inst, total,
-                               static_cast<Rec32 *>(w.rec.p), flags, reinterpret_cast<int32_t *>(flags + 1),
-                               static_cast<uint32_t *>(w.peaks.p), st),
+    const BatchInst *dinst = reinterpret_cast<const BatchInst *>(d1);
+    const int64_t *doffs = reinterpret_cast<const int64_t *>(d1 + t1_offs);
+    HIP_TRY(hipMemcpyAsync(d1, h1, t1_bytes, hipMemcpyHostToDevice, st), "table upload");
+    HIP_TRY(hipEventRecord(w.stage_ev, st), "hipEventRecord");
+    w.stage_pending = true;
+    // [0] status, [1] first bad instance, [2] queue head, [4 ...] per-instance peaks
+    uint32_t *flags = static_cast<uint32_t *>(w.flags.p);
+    HIP_TRY(launch_batch_clear(flags, n_inst, st), "batch clear launch");
+    HIP_TRY(launch_batch_setup(dinst, doffs, n_inst, total, static_cast<Rec32 *>(w.rec.p),
+                               static_cast<double *>(w.l5.p), airy ? static_cast<double2 *>(w.e0t.p) : nullptr,
+                               flags, reinterpret_cast<int32_t *>(flags + 1), flags + 4, st),
             "batch setup launch");
-    std::vector<uint32_t> peaks(n_inst);
-    HIP_TRY(hipMemcpyAsync(w.host_flags, flags, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, st), "status copy");
-    HIP_TRY(hipMemcpyAsync(peaks.data(), w.peaks.p, n_inst * sizeof(uint32_t), hipMemcpyDeviceToHost, st),
-            "peak copy");
+    HIP_TRY(hipMemcpyAsync(hrb, flags, (4 + (size_t)n_inst) * sizeof(uint32_t), hipMemcpyDeviceToHost, st),
+            "status copy");
     HIP_TRY(hipStreamSynchronize(st), "hipStreamSynchronize");
-    const uint32_t stat = w.host_flags[0];
-    const int32_t bad = (int32_t)w.host_flags[1];
+    w.stage_pending = false;
+    const uint32_t *hflags = reinterpret_cast<const uint32_t *>(hrb), *peaks = hflags + 4;
+    const uint32_t stat = hflags[0];
+    const int32_t bad = (int32_t)hflags[1];
     if (stat & FLAG_PARALLEL) return fail(GBD_EPARALLEL, "instance %d: a base ray is parallel to the plane", bad);
     if (stat & FLAG_BRANCH) return fail(GBD_EBRANCH, "instance %d: an eigenvalue left the principal branch", bad);
     if (stat & FLAG_NONFINITE) return fail(GBD_EINVAL, "instance %d: non-finite beamlet parameters", bad);
@@ -1413,14 +1452,22 @@ int gbd_eval_batch(gbd_ctx_t ctx, int32_t n_inst, const gbd_beamlets_t *bs, cons
     // the separable form in FP16 halves unless FP32 MFMA is requested (variant 5)
     const bool half = form == 3 && !(opts && opts->variant == 5);
     if (rows == 32 && form != 2) rows = 16;  // 32 rows is a rotor-form shape
+    if (form == 2)
+        HIP_TRY(launch_batch_sigma(dinst, doffs, n_inst, total, static_cast<const double *>(w.l5.p),
+                                   static_cast<Rec32 *>(w.rec.p), st),
+                "rotor table launch");
 
     // evaluation tables; the work list takes instances largest first (LPT),
     // each instance's tiles contiguous and in order
-    std::vector<BatchEval> ev(n_inst);
+    BatchEval *ev = reinterpret_cast<BatchEval *>(h2);
+    int32_t *items = reinterpret_cast<int32_t *>(h2 + t2_items);
+    int32_t *e0map = reinterpret_cast<int32_t *>(h2 + t2_e0map);  // normalisation chunk -> instance
     int64_t foff = 0;
+    int32_t n_chunks = 0;
     for (int32_t i = 0; i < n_inst; i++) {
         const PlaneGeom &g = ps[i]->g;
         BatchEval &e = ev[i];
+        e = BatchEval();
         e.rec_off = offs[i];
         e.n = bs[i]->dev.n;
         e.nx = g.nx;
@@ -1446,33 +1493,36 @@ int gbd_eval_batch(gbd_ctx_t ctx, int32_t n_inst, const gbd_beamlets_t *bs, cons
         e.field_off = foff;
         foff += (int64_t)g.nx * g.ny;
         e.scale = peaks[i] ? 2 * kSepHalfExp - ((int)peaks[i] - 2048) : 0;  // as a single evaluation's setup
+        e.e0_off = n_chunks;
+        e.e0_chunks = (int32_t)((e.n + kE0Chunk - 1) / kE0Chunk);
+        for (int32_t c = 0; c < e.e0_chunks; c++) e0map[n_chunks++] = i;
     }
     std::vector<int32_t> order(n_inst);
     for (int32_t i = 0; i < n_inst; i++) order[i] = i;
     std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
         return ev[x].n * ((int64_t)ev[x].nx * ev[x].ny) > ev[y].n * ((int64_t)ev[y].nx * ev[y].ny);
     });
-    std::vector<int32_t> items;
-    items.reserve(2 * n_items);
+    int64_t n_it = 0;
     for (int32_t k = 0; k < n_inst; k++) {
         const int32_t i = order[k];
-        ev[i].item_off = (int64_t)items.size() / 2;
+        ev[i].item_off = n_it;
         const int32_t tiles = ev[i].tiles_x * ev[i].tiles_y;
         for (int32_t t = 0; t < tiles; t++) {
-            items.push_back(i);
-            items.push_back(t);
+            items[2 * n_it] = i;
+            items[2 * n_it + 1] = t;
+            n_it++;
         }
     }
-    n_items = (int64_t)items.size() / 2;
-    HIP_TRY(hipMemcpyAsync(w.eval.p, ev.data(), n_inst * sizeof(BatchEval), hipMemcpyHostToDevice, st), "table upload");
-    if (!items.empty())
-        HIP_TRY(hipMemcpyAsync(w.items.p, items.data(), items.size() * sizeof(int32_t), hipMemcpyHostToDevice, st),
-                "work list upload");
+    n_items = n_it;
+    HIP_TRY(hipMemcpyAsync(d2, h2, t2_e0map + (size_t)n_chunks * sizeof(int32_t), hipMemcpyHostToDevice, st),
+            "table upload");
+    HIP_TRY(hipEventRecord(w.stage_ev, st), "hipEventRecord");
+    w.stage_pending = true;
 
     BatchArgs a;
-    a.inst = static_cast<const BatchEval *>(w.eval.p);
+    a.inst = reinterpret_cast<const BatchEval *>(d2);
     a.n_inst = n_inst;
-    a.items = static_cast<const int32_t *>(w.items.p);
+    a.items = reinterpret_cast<const int32_t *>(d2 + t2_items);
     a.n_items = (int32_t)n_items;
     a.rec = static_cast<const Rec32 *>(w.rec.p);
     a.e0 = static_cast<const double2 *>(w.e0.p);
@@ -1484,8 +1534,10 @@ int gbd_eval_batch(gbd_ctx_t ctx, int32_t n_inst, const gbd_beamlets_t *bs, cons
     for (int z = 0; z <= kMaxZones; z++)
         a.zone_r2[z] = (z <= n_zones && n_zones > 0) ? zone_edges[z] * zone_edges[z] : 0.0;
     if (airy)
-        HIP_TRY(launch_batch_e0(a.inst, n_inst, a.rec, static_cast<double2 *>(w.e0.p), st), "normalisation launch");
-    HIP_TRY(hipMemsetAsync(flags + 2, 0, sizeof(uint32_t), st), "hipMemsetAsync");
+        HIP_TRY(launch_batch_e0(a.inst, n_inst, reinterpret_cast<const int32_t *>(d2 + t2_e0map), n_chunks,
+                                static_cast<const double2 *>(w.e0t.p), static_cast<double2 *>(w.e0part.p),
+                                static_cast<double2 *>(w.e0.p), st),
+                "normalisation launch");
     HIP_TRY(launch_batch_eval(rows, waves, form, half, ctx->cus, a, st), "batch eval launch");
     if (airy) {
         HIP_TRY(launch_batch_finalize(a.inst, n_inst, a.part, n_zones, static_cast<double *>(w.metrics.p), st),
@@ -1494,6 +1546,7 @@ int gbd_eval_batch(gbd_ctx_t ctx, int32_t n_inst, const gbd_beamlets_t *bs, cons
                                hipMemcpyDeviceToHost, st),
                 "metrics copy");
         HIP_TRY(hipStreamSynchronize(st), "hipStreamSynchronize");
+        w.stage_pending = false;
     }
     return GBD_OK;
 }

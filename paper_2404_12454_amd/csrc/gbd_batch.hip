@@ -3,7 +3,9 @@
 // Sec. 6: RMS difference of the peak-normalised irradiance to the analytic
 // Airy pattern, plus annular zones) reduced in the same kernel.
 //
-//  batch_setup_kernel  per-beamlet FP64 setup over the concatenated beamlets
+//  batch_setup_kernel  per-beamlet FP64 setup over the concatenated beamlets,
+//                      with each beamlet's term at its plane's origin
+//  batch_sigma_kernel  the rotor tables, before a rotor-form evaluation only
 //  batch_e0_kernel     field at each plane's origin (the normalisation point)
 //  batch_eval_kernel   persistent workgroups pull (instance, pixel tile) items,
 //                      largest instances first, from an atomic queue head;
@@ -27,15 +29,17 @@ namespace {
 
 using namespace dev;
 
-__global__ void __launch_bounds__(256) batch_setup_kernel(const BatchInst *__restrict__ inst,
-                                                          const int64_t *__restrict__ offs, int32_t n_inst,
-                                                          int64_t total, Rec32 *__restrict__ rec,
-                                                          uint32_t *__restrict__ status, int32_t *__restrict__ bad,
-                                                          uint32_t *__restrict__ peak) {
-    const int64_t j0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const bool live = j0 < total;
-    const int64_t j = live ? j0 : total - 1;  // a lane past the end repeats the last beamlet, writing nothing
-    // instance holding beamlet j: the last i with offs[i] <= j (empty instances skipped)
+// The batch's flag words before its setup: [0] status 0, [1] first bad
+// instance 0x7f7f7f7f, [2] queue head 0, [3] 0, [4 ...] the n_inst peaks 0.
+__global__ void __launch_bounds__(256) batch_clear_kernel(uint32_t *__restrict__ flags, int32_t n_inst) {
+    const int64_t n = 4 + (int64_t)n_inst;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        flags[i] = i == 1 ? 0x7f7f7f7fu : 0u;
+}
+
+// the instance holding beamlet j: the last i with offs[i] <= j (empty
+// instances skipped)
+__device__ inline int instance_of(const int64_t *__restrict__ offs, int32_t n_inst, int64_t j) {
     int lo = 0, hi = n_inst - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
@@ -44,12 +48,45 @@ __global__ void __launch_bounds__(256) batch_setup_kernel(const BatchInst *__res
         else
             hi = mid - 1;
     }
+    return lo;
+}
+
+// E(0) term of one beamlet: the mixed-precision phasor of its record at plane
+// coordinates (0, 0), each part widened to FP64 for the sum
+__device__ inline double2 e0_term(const Rec32 &r) {
+    const double da = -r.arho, db = -r.brho;
+    const double th = r.p[0] + da * (r.p[1] + r.p[3] * da) + db * (r.p[2] + r.p[4] * da + r.p[5] * db);
+    const float ph = (float)__builtin_amdgcn_fract(th);
+    const float daf = -r.arho_f, dbf = -r.brho_f;
+    const float L = r.m[0] + daf * (r.m[1] + r.m[3] * daf) + dbf * (r.m[2] + r.m[4] * daf + r.m[5] * dbf);
+    const float m = __builtin_amdgcn_exp2f(L);
+    return make_double2((double)(m * __builtin_amdgcn_cosf(ph)), (double)(m * __builtin_amdgcn_sinf(ph)));
+}
+
+// The records' first 112 bytes (the rotor tables are left to
+// batch_sigma_kernel, run only before a rotor-form evaluation), with each
+// beamlet's FP64 l5 for that pass and, when e0t is given, its E(0) term.
+__global__ void __launch_bounds__(256) batch_setup_kernel(const BatchInst *__restrict__ inst,
+                                                          const int64_t *__restrict__ offs, int32_t n_inst,
+                                                          int64_t total, Rec32 *__restrict__ rec,
+                                                          double *__restrict__ l5, double2 *__restrict__ e0t,
+                                                          uint32_t *__restrict__ status, int32_t *__restrict__ bad,
+                                                          uint32_t *__restrict__ peak) {
+    const int64_t j0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool live = j0 < total;
+    const int64_t j = live ? j0 : total - 1;  // a lane past the end repeats the last beamlet, writing nothing
+    const int lo = instance_of(offs, n_inst, j);
     const BatchInst &I = inst[lo];
     float pk = -INFINITY;
     uint32_t flag = 0;
-    if (live)
+    if (live) {
+        double l5v;
+        Rec32 o;
         flag = setup_one(I.b, I.pl, I.gturns, j - offs[lo], nullptr, rec + I.rec_off, nullptr, nullptr, nullptr,
-                         nullptr, true, &pk);
+                         nullptr, false, &pk, &l5v, &o);
+        l5[j] = l5v;
+        if (e0t) e0t[j] = e0_term(o);
+    }
     if (flag) atomicOr(status, flag);
     if (flag & FLAG_ERRORS) atomicMin(bad, lo);
     // the instance's largest term over its grid (the FP16 halves form's
@@ -66,23 +103,38 @@ __global__ void __launch_bounds__(256) batch_setup_kernel(const BatchInst *__res
     }
 }
 
-// E(0): the same mixed-precision phasor at plane coordinates (0, 0), summed
-// in FP64 with a fixed-order tree in LDS.
+// Rotor tables sigma^(k^2), k = 1..16, rows dy apart (each instance's dy),
+// rounded into the records: thread t of a block computes entry t % 16 of
+// beamlet 16 (block) + t / 16, from the record's p5 and the setup's l5 (the
+// values the single evaluation's tables come from).
+__global__ void __launch_bounds__(256) batch_sigma_kernel(const BatchInst *__restrict__ inst,
+                                                          const int64_t *__restrict__ offs, int32_t n_inst,
+                                                          int64_t total, const double *__restrict__ l5,
+                                                          Rec32 *__restrict__ rec) {
+    const int64_t j = (int64_t)blockIdx.x * 16 + (threadIdx.x >> 4);
+    const int k = (threadIdx.x & 15) + 1;
+    if (j >= total) return;
+    const double dy = inst[instance_of(offs, n_inst, j)].pl.dy;
+    const double2 v = rotor_sigma(rec[j].p[5], l5[j], dy, k);
+    rec[j].sq[k - 1][0] = (float)v.x;
+    rec[j].sq[k - 1][1] = (float)v.y;
+}
+
+// E(0): the instance's E(0) terms summed in FP64, each workgroup one chunk
+// of kE0Chunk beamlets of one instance (a fixed-order tree in LDS), then
+// batch_e0_sum_kernel adds an instance's chunk sums in chunk order.
 __global__ void __launch_bounds__(256) batch_e0_kernel(const BatchEval *__restrict__ inst,
-                                                       const Rec32 *__restrict__ rec, double2 *__restrict__ e0) {
+                                                       const int32_t *__restrict__ e0map,
+                                                       const double2 *__restrict__ e0t, double2 *__restrict__ part) {
     __shared__ double sre[256], sim[256];
-    const BatchEval I = inst[blockIdx.x];
+    const int32_t c = blockIdx.x;
+    const BatchEval &I = inst[e0map[c]];
+    const int64_t j0 = (int64_t)(c - I.e0_off) * kE0Chunk, j1 = min(I.n, j0 + kE0Chunk);
     double re = 0.0, im = 0.0;
-    for (int64_t j = threadIdx.x; j < I.n; j += 256) {
-        const Rec32 r = rec[I.rec_off + j];
-        const double da = -r.arho, db = -r.brho;
-        const double th = r.p[0] + da * (r.p[1] + r.p[3] * da) + db * (r.p[2] + r.p[4] * da + r.p[5] * db);
-        const float ph = (float)__builtin_amdgcn_fract(th);
-        const float daf = -r.arho_f, dbf = -r.brho_f;
-        const float L = r.m[0] + daf * (r.m[1] + r.m[3] * daf) + dbf * (r.m[2] + r.m[4] * daf + r.m[5] * dbf);
-        const float m = __builtin_amdgcn_exp2f(L);
-        re += (double)(m * __builtin_amdgcn_cosf(ph));
-        im += (double)(m * __builtin_amdgcn_sinf(ph));
+    for (int64_t j = j0 + threadIdx.x; j < j1; j += 256) {
+        const double2 t = e0t[I.rec_off + j];
+        re += t.x;
+        im += t.y;
     }
     sre[threadIdx.x] = re;
     sim[threadIdx.x] = im;
@@ -94,7 +146,22 @@ __global__ void __launch_bounds__(256) batch_e0_kernel(const BatchEval *__restri
         }
         __syncthreads();
     }
-    if (threadIdx.x == 0) e0[blockIdx.x] = make_double2(sre[0], sim[0]);
+    if (threadIdx.x == 0) part[c] = make_double2(sre[0], sim[0]);
+}
+
+__global__ void __launch_bounds__(64) batch_e0_sum_kernel(const BatchEval *__restrict__ inst, int32_t n_inst,
+                                                          const double2 *__restrict__ part,
+                                                          double2 *__restrict__ e0) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_inst) return;
+    const BatchEval &I = inst[i];
+    double re = 0.0, im = 0.0;
+    for (int k = 0; k < I.e0_chunks; k++) {
+        const double2 q = part[I.e0_off + k];
+        re += q.x;
+        im += q.y;
+    }
+    e0[i] = make_double2(re, im);
 }
 
 template <int WIDTH>
@@ -355,17 +422,33 @@ hipError_t launch_batch_eval_t(int cus, const BatchArgs &a, hipStream_t s) {
 
 }  // namespace
 
-hipError_t launch_batch_setup(const BatchInst *inst, const int64_t *offs, int32_t n_inst, int64_t total, Rec32 *rec,
-                              uint32_t *status, int32_t *bad, uint32_t *peak, hipStream_t s) {
-    if (total == 0) return hipSuccess;
-    batch_setup_kernel<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(inst, offs, n_inst, total, rec, status, bad,
-                                                                       peak);
+hipError_t launch_batch_clear(uint32_t *flags, int32_t n_inst, hipStream_t s) {
+    const int64_t blocks = min((4 + (int64_t)n_inst + 255) / 256, (int64_t)1024);
+    batch_clear_kernel<<<(unsigned)blocks, 256, 0, s>>>(flags, n_inst);
     return hipGetLastError();
 }
 
-hipError_t launch_batch_e0(const BatchEval *inst, int32_t n_inst, const Rec32 *rec, double2 *e0, hipStream_t s) {
+hipError_t launch_batch_setup(const BatchInst *inst, const int64_t *offs, int32_t n_inst, int64_t total, Rec32 *rec,
+                              double *l5, double2 *e0t, uint32_t *status, int32_t *bad, uint32_t *peak,
+                              hipStream_t s) {
+    if (total == 0) return hipSuccess;
+    batch_setup_kernel<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(inst, offs, n_inst, total, rec, l5, e0t,
+                                                                       status, bad, peak);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_sigma(const BatchInst *inst, const int64_t *offs, int32_t n_inst, int64_t total,
+                              const double *l5, Rec32 *rec, hipStream_t s) {
+    if (total == 0) return hipSuccess;
+    batch_sigma_kernel<<<(unsigned)((total + 15) / 16), 256, 0, s>>>(inst, offs, n_inst, total, l5, rec);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_e0(const BatchEval *inst, int32_t n_inst, const int32_t *e0map, int32_t n_chunks,
+                           const double2 *e0t, double2 *part, double2 *e0, hipStream_t s) {
     if (n_inst == 0) return hipSuccess;
-    batch_e0_kernel<<<n_inst, 256, 0, s>>>(inst, rec, e0);
+    if (n_chunks > 0) batch_e0_kernel<<<n_chunks, 256, 0, s>>>(inst, e0map, e0t, part);
+    batch_e0_sum_kernel<<<(n_inst + 63) / 64, 64, 0, s>>>(inst, n_inst, part, e0);
     return hipGetLastError();
 }
 

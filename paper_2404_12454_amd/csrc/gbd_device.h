@@ -122,10 +122,14 @@ __device__ inline double log2_hg_envelope_max(double c1, double c2, double d0, d
 // sep_peak (optional): log2 of the largest modulus of the beamlet's term over
 // the grid, U's part of it stored in the Rec32 record (pad) for the FP16
 // separable form's range balancing; -inf for a beamlet that contributes nothing.
+// l5_out and r32_copy (optional): the FP64 ln-amplitude curvature l5 (with
+// p5 of the record, the source of the rotor tables when a later pass fills
+// them) and a copy of the finished Rec32 record.
 __device__ inline uint32_t setup_one(const BeamletsDev &b, const PlaneGeom &pl, double gturns, int64_t j,
                                      Rec64 *r64, Rec32 *r32, RecHG64 *h64 = nullptr, RecHG32 *h32 = nullptr,
                                      RecCut64 *c64 = nullptr, RecCut32 *c32 = nullptr, bool sigma32 = true,
-                                     float *sep_peak = nullptr) {
+                                     float *sep_peak = nullptr, double *l5_out = nullptr,
+                                     Rec32 *r32_copy = nullptr) {
     const double *M = b.abcd + (b.n_abcd == 1 ? 0 : 16 * j);
     double A[2][2], B[2][2], C[2][2], D[2][2];
 #pragma unroll
@@ -448,6 +452,8 @@ __device__ inline uint32_t setup_one(const BeamletsDev &b, const PlaneGeom &pl, 
         o64.l[0] = -INFINITY;
         o32.m[0] = -INFINITY;
     }
+    if (l5_out) *l5_out = o64.l[5];
+    if (r32_copy) *r32_copy = o32;
     if (r64) r64[j] = o64;
     if (r32) {
         if (sigma32) {

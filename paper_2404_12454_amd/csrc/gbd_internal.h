@@ -50,7 +50,7 @@ static_assert(sizeof(Rec64) == 128, "Rec64 layout");
 //   stepped form: t2 = p5 dy^2 reduced mod 1, u2 = m5 dy^2, s2 = 2^(2 u2);
 //   rotor form:   sq[k-1] = sigma^(k^2), sigma = 2^(u2) e^(2 pi i t2), k = 1..16
 //                 (filled by launch_sigma before a rotor-form evaluation; the
-//                 plan's setup leaves it unset, the batched setup fills it).
+//                 setups leave it unset; the batch fills it with launch_batch_sigma).
 struct alignas(16) Rec32 {
     double arho, brho;
     double p[6];
@@ -184,7 +184,11 @@ struct BatchEval {
     int64_t item_off;   // first work item; an instance's items are contiguous, in tile order
     int64_t field_off;  // element offset of this instance in the optional field output
     int32_t scale;      // FP16 halves form: its accumulators hold the field times 2^scale
+    int32_t e0_off, e0_chunks;  // its normalisation chunks (kE0Chunk beamlets each), contiguous
 };
+
+// beamlets per workgroup of the normalisation sum
+constexpr int kE0Chunk = 2048;
 
 struct BatchArgs {
     const BatchEval *inst;
@@ -203,9 +207,22 @@ struct BatchArgs {
 
 // peak: per instance, the largest beamlet term modulus over the grid as
 // ceil(log2) + 2048 (0: none), the setup kernel's atomic maximum; zero on entry.
+// flags[0 .. 3] and the n_inst peaks after them set for a batch setup (the
+// first bad instance to 0x7f7f7f7f, the rest to 0)
+hipError_t launch_batch_clear(uint32_t *flags, int32_t n_inst, hipStream_t s);
+// The records' first 112 bytes; l5[j] receives beamlet j's FP64 l5 (the rotor
+// tables' source) and, unless e0t is null, e0t[j] its term at the plane origin.
 hipError_t launch_batch_setup(const BatchInst *inst, const int64_t *offs, int32_t n_inst, int64_t total,
-                              Rec32 *rec, uint32_t *status, int32_t *bad, uint32_t *peak, hipStream_t s);
-hipError_t launch_batch_e0(const BatchEval *inst, int32_t n_inst, const Rec32 *rec, double2 *e0, hipStream_t s);
+                              Rec32 *rec, double *l5, double2 *e0t, uint32_t *status, int32_t *bad, uint32_t *peak,
+                              hipStream_t s);
+// the rotor tables of every record (before a rotor-form evaluation)
+hipError_t launch_batch_sigma(const BatchInst *inst, const int64_t *offs, int32_t n_inst, int64_t total,
+                              const double *l5, Rec32 *rec, hipStream_t s);
+// E(0) per instance from the setup's terms: e0map[c] is the instance of chunk
+// c (n_chunks of them, each instance's in order from BatchEval::e0_off); part
+// holds n_chunks sums
+hipError_t launch_batch_e0(const BatchEval *inst, int32_t n_inst, const int32_t *e0map, int32_t n_chunks,
+                           const double2 *e0t, double2 *part, double2 *e0, hipStream_t s);
 // form 3: the separable form (rows and waves do not apply), in FP16 halves
 // when half (scales from BatchEval::scale), else on FP32 MFMA
 hipError_t launch_batch_eval(int rows, int waves, int form, bool half, int cus, const BatchArgs &a, hipStream_t s);
