@@ -110,7 +110,8 @@ typedef struct {
 /* Create a context bound to HIP device `device` and stream `hip_stream`
  * (a hipStream_t; NULL = the null stream). */
 int gbd_ctx_create(gbd_ctx_t *out, int device, void *hip_stream);
-/* Rebind the context to another stream of the same device. */
+/* Rebind the context to another stream of the same device (waits for the
+ * work already enqueued on the old one). */
 int gbd_ctx_set_stream(gbd_ctx_t ctx, void *hip_stream);
 void gbd_ctx_destroy(gbd_ctx_t ctx);
 /* Kernel timing, for measurement: while enabled, every plan evaluation
@@ -138,7 +139,13 @@ const char *gbd_last_error(void);
  *                      each must satisfy the symplectic relations (Sec. 2.1)
  *                      to 1e-10 relative, else GBD_ENOTSYMPLECTIC.
  * n == 0 is allowed (the field is then zero).  The inputs are validated,
- * copied and uploaded to device memory owned by the handle. */
+ * copied and uploaded to device memory held by the handle: a block of the
+ * context's pool, which gbd_beamlets_free returns there for the context's
+ * next handle (at most 4 GiB wait; the pool's blocks go back to the driver
+ * once the context and all its handles are destroyed).  A handle is used
+ * with the context that created it: the calls that take one refuse a handle
+ * of another context (GBD_EINVAL), whose upload may still be in flight on
+ * that context's stream. */
 int gbd_beamlets(gbd_ctx_t ctx, gbd_beamlets_t *out, int64_t n, double lambda, double l0,
                  const double *r1, const double *th1, const double *w0, int64_t n_w0,
                  const double *amp, const double *path, const double *abcd, int64_t n_abcd);

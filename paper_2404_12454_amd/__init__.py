@@ -126,7 +126,7 @@ def _f64(a) -> Optional[np.ndarray]:
 
 
 def _p(a: Optional[np.ndarray]):
-    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+    return None if a is None else a.ctypes.data  # the caller keeps the array alive over the call
 
 
 def _handles(objs) -> np.ndarray:

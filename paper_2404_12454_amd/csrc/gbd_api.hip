@@ -10,6 +10,7 @@
 #include <algorithm>
 #include <chrono>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <new>
 #include <string>
@@ -61,8 +62,65 @@ struct TuneVal {
     double ms;
 };
 
+// Device blocks of beamlet handles, by power-of-two size class (4 KiB and
+// up): a freed handle's block waits in its class for the next handle of the
+// same context instead of going back to the driver (hipMalloc and hipFree
+// take tens of microseconds each, and a parameter sweep creates and frees
+// thousands of handles).  A reused block is written by an upload on the
+// context stream, after every kernel that read its previous contents there
+// (gbd_ctx_set_stream waits for the old stream first).  At most
+// kPoolCacheBytes wait; the pool frees them once the context and every handle
+// drawn from it are gone.
+constexpr size_t kPoolCacheBytes = (size_t)4 << 30;
+struct DevPool {
+    std::mutex mu;
+    std::map<size_t, std::vector<void *>> cached;
+    size_t cached_bytes = 0;
+    ~DevPool() {
+        for (auto &kv : cached)
+            for (void *p : kv.second) (void)hipFree(p);
+    }
+    static size_t size_class(size_t bytes) {
+        size_t c = 4096;
+        while (c < bytes) c <<= 1;
+        return c;
+    }
+    // a block of size class cls on the current device
+    hipError_t get(size_t cls, void **p) {
+        {
+            std::lock_guard<std::mutex> lock(mu);
+            auto it = cached.find(cls);
+            if (it != cached.end() && !it->second.empty()) {
+                *p = it->second.back();
+                it->second.pop_back();
+                cached_bytes -= cls;
+                return hipSuccess;
+            }
+        }
+        return hipMalloc(p, cls);
+    }
+    void put(void *p, size_t cls) {
+        {
+            std::lock_guard<std::mutex> lock(mu);
+            if (cached_bytes + cls <= kPoolCacheBytes) {
+                cached[cls].push_back(p);
+                cached_bytes += cls;
+                return;
+            }
+        }
+        (void)hipFree(p);
+    }
+};
+
 struct gbd_ctx_s {
     int device;
+    std::shared_ptr<DevPool> pool;  // beamlet handles' device blocks
+    // pinned staging of beamlet uploads: rewritten once the previous upload's
+    // copy has run (up_ev), so a handle's creation does not wait for its own
+    void *up_stage = nullptr;
+    size_t up_bytes = 0;
+    hipEvent_t up_ev = nullptr;
+    bool up_pending = false;
     hipStream_t stream;
     int cus;
     gbd_plan_s *own_plan;  // plan used by gbd_eval
@@ -78,6 +136,8 @@ struct gbd_beamlets_s {
     gbd_ctx_s *ctx;
     BeamletsDev dev;
     void *mem;
+    size_t mem_class;               // mem's size class in pool
+    std::shared_ptr<DevPool> pool;  // where mem returns (kept alive past the context)
     bool higher_order;  // some beamlet has a nonzero Hermite-Gaussian order
 };
 
@@ -757,6 +817,7 @@ int gbd_ctx_create(gbd_ctx_t *out, int device, void *hip_stream) {
     HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device), "hipDeviceGetAttribute");
     gbd_ctx_s *c = new (std::nothrow) gbd_ctx_s();
     if (!c) return fail(GBD_ENOMEM, "host allocation failed");
+    c->pool = std::make_shared<DevPool>();
     c->device = device;
     c->stream = static_cast<hipStream_t>(hip_stream);
     c->cus = cus > 0 ? cus : 256;
@@ -767,13 +828,24 @@ int gbd_ctx_create(gbd_ctx_t *out, int device, void *hip_stream) {
 
 int gbd_ctx_set_stream(gbd_ctx_t ctx, void *hip_stream) {
     if (!ctx) return fail(GBD_EINVAL, "ctx is NULL");
-    ctx->stream = static_cast<hipStream_t>(hip_stream);
+    hipStream_t next = static_cast<hipStream_t>(hip_stream);
+    if (next != ctx->stream) {
+        // pooled blocks are reused in stream order: drain the old stream first
+        HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
+        HIP_TRY(hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
+    }
+    ctx->stream = next;
     return GBD_OK;
 }
 
 void gbd_ctx_destroy(gbd_ctx_t ctx) {
     if (!ctx) return;
     (void)hipSetDevice(ctx->device);
+    if (ctx->up_ev) {
+        (void)hipEventSynchronize(ctx->up_ev);
+        (void)hipEventDestroy(ctx->up_ev);
+    }
+    if (ctx->up_stage) (void)hipHostFree(ctx->up_stage);
     plan_destroy(ctx->own_plan);
     batch_free(ctx->batch);
     for (auto *v : {&ctx->timed, &ctx->spare_events})
@@ -879,7 +951,20 @@ static int beamlets_impl(gbd_ctx_t ctx, gbd_beamlets_t *out, int64_t n, double l
                  off_path = off_w0 + (size_t)n_w0, off_abcd = off_path + nn, off_base = off_abcd + 16 * (size_t)n_abcd,
                  off_edge = off_base + (base ? 5 * nn : 0), off_order = off_edge + (edge ? 3 * nn : 0),
                  total = off_order + (order ? nn : 0);
-    std::vector<double> host(total, 0.0);
+    const size_t bytes = total * sizeof(double);
+    if (!ctx->up_ev) HIP_TRY(hipEventCreateWithFlags(&ctx->up_ev, hipEventDisableTiming), "hipEventCreate");
+    if (ctx->up_pending) HIP_TRY(hipEventSynchronize(ctx->up_ev), "hipEventSynchronize");
+    ctx->up_pending = false;
+    if (bytes > ctx->up_bytes) {
+        if (ctx->up_stage) (void)hipHostFree(ctx->up_stage);
+        ctx->up_stage = nullptr;
+        ctx->up_bytes = 0;
+        const size_t want = std::max<size_t>(bytes, (size_t)1 << 20);
+        HIP_TRY(hipHostMalloc(&ctx->up_stage, want, hipHostMallocDefault), "hipHostMalloc(beamlet staging)");
+        ctx->up_bytes = want;
+    }
+    double *host = static_cast<double *>(ctx->up_stage);
+    memset(host, 0, bytes);
     if (n > 0) {
         int32_t *ord = reinterpret_cast<int32_t *>(&host[off_order]);
         if (n_w0 == 1) host[off_w0] = w0[0];
@@ -909,21 +994,26 @@ static int beamlets_impl(gbd_ctx_t ctx, gbd_beamlets_t *out, int64_t n, double l
         for (int i = 0; i < 4; i++) host[off_abcd + 5 * i] = 1.0;
     }
     void *mem = nullptr;
-    HIP_TRY(hipMalloc(&mem, total * sizeof(double)), "hipMalloc(beamlets)");
-    hipError_t e = hipMemcpyAsync(mem, host.data(), total * sizeof(double), hipMemcpyHostToDevice, ctx->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    const size_t cls = DevPool::size_class(total * sizeof(double));
+    HIP_TRY(ctx->pool->get(cls, &mem), "hipMalloc(beamlets)");
+    hipError_t e = hipMemcpyAsync(mem, host, bytes, hipMemcpyHostToDevice, ctx->stream);
+    if (e == hipSuccess) e = hipEventRecord(ctx->up_ev, ctx->stream);
     if (e != hipSuccess) {
-        (void)hipFree(mem);
+        (void)hipStreamSynchronize(ctx->stream);
+        ctx->pool->put(mem, cls);
         return hip_fail(e, "beamlet upload");
     }
+    ctx->up_pending = true;
     gbd_beamlets_s *b = new (std::nothrow) gbd_beamlets_s();
     if (!b) {
-        (void)hipFree(mem);
+        ctx->pool->put(mem, cls);
         return fail(GBD_ENOMEM, "host allocation failed");
     }
     double *d = static_cast<double *>(mem);
     b->ctx = ctx;
     b->mem = mem;
+    b->mem_class = cls;
+    b->pool = ctx->pool;
     b->dev.n = n;
     b->dev.n_w0 = n_w0;
     b->dev.n_abcd = n_abcd;
@@ -1020,7 +1110,7 @@ int gbd_trace(gbd_ctx_t ctx, int32_t n_mirrors, const double *mirrors, double z_
 
 void gbd_beamlets_free(gbd_beamlets_t b) {
     if (!b) return;
-    if (b->mem) (void)hipFree(b->mem);
+    if (b->mem) b->pool->put(b->mem, b->mem_class);
     delete b;
 }
 
@@ -1071,6 +1161,7 @@ int gbd_plan_create(gbd_ctx_t ctx, gbd_plan_t *out, int64_t capacity) {
 
 int gbd_plan_setup(gbd_ctx_t ctx, gbd_plan_t plan, gbd_beamlets_t b, gbd_plane_t p) {
     if (!ctx || !plan || !b || !p) return fail(GBD_EINVAL, "NULL argument");
+    if (b->ctx != ctx) return fail(GBD_EINVAL, "the beamlets belong to another context");
     return plan_setup_impl(ctx, plan, b, p);
 }
 
@@ -1137,6 +1228,7 @@ int gbd_plan_shape(gbd_ctx_t ctx, gbd_plan_t plan, int precision, const gbd_eval
 int gbd_eval(gbd_ctx_t ctx, gbd_beamlets_t b, gbd_plane_t p, int precision, void *field_out, int64_t out_bytes,
              const gbd_eval_opts *opts) {
     if (!ctx || !b || !p) return fail(GBD_EINVAL, "NULL argument");
+    if (b->ctx != ctx) return fail(GBD_EINVAL, "the beamlets belong to another context");
     if (precision != GBD_FP64 && precision != GBD_MIXED) return fail(GBD_EINVAL, "precision must be GBD_FP64 or GBD_MIXED");
     const int64_t M = (int64_t)p->g.nx * p->g.ny;
     const int64_t elem = precision == GBD_FP64 ? 16 : 8;
@@ -1262,6 +1354,7 @@ int gbd_autotune_load(gbd_ctx_t ctx, const char *path) {
 
 int gbd_eval_point(gbd_ctx_t ctx, gbd_beamlets_t b, gbd_plane_t p, void *field_out, int64_t out_bytes) {
     if (!ctx || !b || !p) return fail(GBD_EINVAL, "NULL argument");
+    if (b->ctx != ctx) return fail(GBD_EINVAL, "the beamlets belong to another context");
     if (b->higher_order || b->dev.n_cut > 0)
         return fail(GBD_EINVAL, "point evaluation takes whole fundamental Gaussian beamlets only");
     const int64_t M = (int64_t)p->g.nx * p->g.ny;
@@ -1326,6 +1419,7 @@ int gbd_eval_batch(gbd_ctx_t ctx, int32_t n_inst, const gbd_beamlets_t *bs, cons
     int64_t pairs = 0, n_max = 0;
     for (int32_t i = 0; i < n_inst; i++) {
         if (!bs[i] || !ps[i]) return fail(GBD_EINVAL, "instance %d has a NULL handle", i);
+        if (bs[i]->ctx != ctx) return fail(GBD_EINVAL, "instance %d: the beamlets belong to another context", i);
         if (bs[i]->higher_order || bs[i]->dev.n_cut > 0)
             return fail(GBD_EINVAL, "instance %d: the batched sweep takes whole fundamental Gaussian beamlets only", i);
         pairs += bs[i]->dev.n * ((int64_t)ps[i]->g.nx * ps[i]->g.ny);

@@ -527,3 +527,41 @@ def test_point_evaluation_matches_oracle_exact_model(ctx):
     torch.cuda.synchronize()
     print("tilted-plane model error vs point evaluation", rel_l2(Epl_t.cpu().numpy(), E), flush=True)
     assert rel_l2(Epl_t.cpu().numpy(), E) < 2e-3
+
+
+def test_pooled_beamlet_blocks_and_foreign_handles(ctx):
+    """A freed beamlet handle's device block serves the context's next handle
+    of the same size class (the upload lands after every kernel that read
+    the old contents): fields after such reuse equal those of a fresh
+    context bit for bit and match the oracle; a handle used with another
+    context is refused before anything runs."""
+    import torch
+    a = scenes.airy_scene(40, npix=96, npix_y=80, half_span_lamF=6.0)
+    b = scenes.airy_scene(40, OF=1.3, q=0.8, npix=96, npix_y=80, half_span_lamF=6.0)
+    assert a.n == b.n
+    p = gbd.plane_from_scene(ctx, b)
+    fields = []
+    for _ in range(3):
+        ba = gbd.beamlets_from_scene(ctx, a)
+        gbd.gbd_eval(ctx, ba, gbd.plane_from_scene(ctx, a), gbd.GBD_MIXED)
+        del ba  # its block returns to the pool while the evaluation may still run
+        bb = gbd.beamlets_from_scene(ctx, b)
+        fields.append(gbd.gbd_eval(ctx, bb, p, gbd.GBD_MIXED))
+        del bb
+    fresh = gbd.Context(0)
+    ref_gpu = gbd.gbd_eval(fresh, gbd.beamlets_from_scene(fresh, b), gbd.plane_from_scene(fresh, b), gbd.GBD_MIXED)
+    torch.cuda.synchronize()
+    for F in fields:
+        assert torch.equal(F.cpu().view(torch.float32), ref_gpu.cpu().view(torch.float32))
+    ref = oracle.eval_field(b)
+    assert rel_l2(fields[-1].cpu().numpy().astype(np.complex128), ref) < 1e-5
+    foreign = gbd.beamlets_from_scene(fresh, b)
+    sentinel = torch.full((80, 96), 7.0 + 7.0j, dtype=torch.complex64, device="cuda")
+    with pytest.raises(gbd.GbdError) as e:
+        gbd.gbd_eval(ctx, foreign, p, gbd.GBD_MIXED, out=sentinel)
+    assert e.value.code == -1
+    with pytest.raises(gbd.GbdError) as e:
+        gbd.Plan(ctx, b.n).setup(foreign, p)
+    assert e.value.code == -1
+    torch.cuda.synchronize()
+    assert bool((sentinel == (7.0 + 7.0j)).all())
