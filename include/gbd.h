@@ -249,9 +249,16 @@ void gbd_plane_free(gbd_plane_t p);
  * out_bytes: size of field_out in bytes (GBD_ERANGE if too small).
  * Runs the per-beamlet setup (propagation, plane transfer) and the N x M
  * evaluation on the context stream.  Plane-dependent checks (GBD_EPARALLEL,
- * GBD_EBRANCH) are
- * made by the setup kernel; this call synchronises on them before launching
- * the evaluation, so a failing call leaves field_out untouched. */
+ * GBD_EBRANCH) are made by the setup kernel; this call waits for them
+ * before it returns, and a failing call leaves field_out untouched.  After a
+ * successful call the next one launches its evaluation right behind its
+ * setup, with the previous call's form and FP16 scale, before it reads the
+ * new status (no host round trip between the kernels): the final reduction
+ * writes field_out only if that status has no error and selects the same
+ * form and scale; otherwise nothing is written, and on a change of form or
+ * scale the evaluation runs again.  Evaluations that write field_out
+ * without a reduction (a single segment, no beamlets) are launched after
+ * the status is read. */
 int gbd_eval(gbd_ctx_t ctx, gbd_beamlets_t b, gbd_plane_t p, int precision, void *field_out,
              int64_t out_bytes, const gbd_eval_opts *opts);
 

@@ -323,12 +323,24 @@ hipError_t launch_eval_cut(int precision, const EvalGeom &g, const void *rec, co
 hipError_t launch_eval(int precision, int rows, int waves, int form, const EvalGeom &g, const void *rec,
                        const void *hg, const RecSq64 *q64, void *partial, void *out, hipStream_t s);
 
+// A condition on the setup status words (flags, key) that the output write
+// waits for: an evaluation launched before the host has read the setup's
+// status writes its output only if no error flag is set, the flags under
+// `mask` equal `flags` and, when check_key, the key equals `key` (the form
+// and the FP16 scale it was launched with).  status null: no condition.
+struct EvalGuard {
+    const uint32_t *status = nullptr;
+    uint32_t mask = 0, flags = 0, key = 0;
+    int32_t check_key = 0;
+};
+
 // Sums the g.nseg segment partials of every pixel in segment order, in FP64.
 // Mixed precision: the first nseg2 segments are compact (float2 sums), the
 // others float4 (sum, compensation) starting at reduce_wide_offset(nseg2, M)
-// bytes into partial; FP64: double2 (nseg2 must be 0).
+// bytes into partial; FP64: double2 (nseg2 must be 0).  Writes nothing unless
+// the guard's condition holds.
 hipError_t launch_reduce(int precision, const EvalGeom &g, int32_t nseg2, const void *partial, void *out,
-                         hipStream_t s);
+                         hipStream_t s, const EvalGuard &guard = EvalGuard());
 inline size_t reduce_wide_offset(int32_t nseg2, int64_t M) { return ((size_t)nseg2 * (size_t)M * 8 + 15) & ~(size_t)15; }
 
 // Issue-rate probe (gbd_probe.hip): `blocks` workgroups of 256 threads,

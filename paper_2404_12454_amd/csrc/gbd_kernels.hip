@@ -373,9 +373,17 @@ __global__ void __launch_bounds__(64 * WAVES) eval_fp64_rotor_kernel(EvalGeom g,
     }
 }
 
+// the guard's condition (EvalGuard), the same for every thread
+__device__ inline bool guard_holds(const EvalGuard &gd) {
+    if (!gd.status) return true;
+    const uint32_t st = gd.status[0], key = gd.status[1];
+    return !(st & FLAG_ERRORS) && (st & gd.mask) == gd.flags && (!gd.check_key || key == gd.key);
+}
+
 __global__ void __launch_bounds__(256) reduce_mixed_kernel(int64_t M, int32_t nseg2, const float2 *__restrict__ part2,
                                                            int32_t nseg4, const float4 *__restrict__ part4,
-                                                           float2 *__restrict__ out) {
+                                                           float2 *__restrict__ out, EvalGuard gd) {
+    if (!guard_holds(gd)) return;
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < M; p += (int64_t)gridDim.x * blockDim.x) {
         double re = 0.0, im = 0.0;
         // unrolled so that several segments' loads are in flight at once;
@@ -397,7 +405,8 @@ __global__ void __launch_bounds__(256) reduce_mixed_kernel(int64_t M, int32_t ns
 }
 
 __global__ void __launch_bounds__(256) reduce_fp64_kernel(int64_t M, int32_t nseg, const double2 *__restrict__ part,
-                                                          double2 *__restrict__ out) {
+                                                          double2 *__restrict__ out, EvalGuard gd) {
+    if (!guard_holds(gd)) return;
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < M; p += (int64_t)gridDim.x * blockDim.x) {
         double re = 0.0, im = 0.0;
 #pragma unroll 8
@@ -576,7 +585,7 @@ hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t s) {
 }
 
 hipError_t launch_reduce(int precision, const EvalGeom &g, int32_t nseg2, const void *partial, void *out,
-                         hipStream_t s) {
+                         hipStream_t s, const EvalGuard &guard) {
     const int64_t M = (int64_t)g.nx * g.ny;
     if (M == 0) return hipSuccess;
     if (nseg2 < 0 || nseg2 > g.nseg || (precision != 1 && nseg2 != 0)) return hipErrorInvalidValue;
@@ -585,10 +594,10 @@ hipError_t launch_reduce(int precision, const EvalGeom &g, int32_t nseg2, const 
         reduce_mixed_kernel<<<(unsigned)blocks, 256, 0, s>>>(
             M, nseg2, static_cast<const float2 *>(partial), g.nseg - nseg2,
             reinterpret_cast<const float4 *>(static_cast<const char *>(partial) + reduce_wide_offset(nseg2, M)),
-            static_cast<float2 *>(out));
+            static_cast<float2 *>(out), guard);
     else
         reduce_fp64_kernel<<<(unsigned)blocks, 256, 0, s>>>(M, g.nseg, static_cast<const double2 *>(partial),
-                                                            static_cast<double2 *>(out));
+                                                            static_cast<double2 *>(out), guard);
     return hipGetLastError();
 }
 

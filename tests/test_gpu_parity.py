@@ -565,3 +565,47 @@ def test_pooled_beamlet_blocks_and_foreign_handles(ctx):
     assert e.value.code == -1
     torch.cuda.synchronize()
     assert bool((sentinel == (7.0 + 7.0j)).all())
+
+
+def test_eval_launched_ahead_of_the_setup_status():
+    """After a successful call gbd_eval launches the next evaluation behind
+    its setup with the previous form and FP16 scale, before reading the new
+    status.  Across calls that keep them, change the scale, change the form
+    (cross terms, higher orders, FP64) or fail, every field equals a first
+    call's on a fresh context bit for bit, a failing call (several segments,
+    so the launch ahead reaches the guarded reduction) leaves its output
+    untouched, and kernel timing keeps one pair per evaluation."""
+    import torch
+    seg = dict(segments=4)
+    airy = scenes.airy_scene(40, npix=96, npix_y=80, half_span_lamF=6.0)
+    small = scenes.airy_scene(24, npix=64, half_span_lamF=6.0)
+    cases = [(airy, gbd.GBD_MIXED, None),
+             (airy, gbd.GBD_MIXED, None),                      # same form and scale: launched ahead
+             (scenes.airy_scene(40, OF=1.3, q=0.8, npix=96, npix_y=80, half_span_lamF=6.0), gbd.GBD_MIXED, None),
+             (scenes.zernike_scene(5, n_across=12, npix=48), gbd.GBD_MIXED, seg),   # cross terms
+             (scenes.hermite_scene(12, npix=64, half_span_lamF=8.0), gbd.GBD_MIXED, None),
+             (small, gbd.GBD_FP64, seg),
+             (small, gbd.GBD_MIXED, seg)]
+    ctx_a = gbd.Context(0)
+    ctx_a.set_kernel_timing(True)
+    done = 0
+    for i, (sc, prec, o) in enumerate(cases):
+        b = gbd.beamlets_from_scene(ctx_a, sc)
+        p = gbd.plane_from_scene(ctx_a, sc)
+        E = gbd.gbd_eval(ctx_a, b, p, prec, opts=o)
+        done += 1
+        fresh = gbd.Context(0)
+        R = gbd.gbd_eval(fresh, gbd.beamlets_from_scene(fresh, sc), gbd.plane_from_scene(fresh, sc), prec, opts=o)
+        torch.cuda.synchronize()
+        real = torch.float64 if prec == gbd.GBD_FP64 else torch.float32
+        assert torch.equal(E.cpu().view(real), R.cpu().view(real)), i
+        if i == 2:
+            # an inverting relay (eigenvalue on the branch cut) between successful calls
+            bad = gbd.gbd_beamlets(ctx_a, sc.n, sc.lam, sc.l0, sc.r1, sc.th1, sc.w0, sc.amp, sc.path, -np.eye(4))
+            sentinel = torch.full((sc.plane.ny, sc.plane.nx), 7.0 + 7.0j, dtype=torch.complex64, device="cuda")
+            with pytest.raises(gbd.GbdError) as e:
+                gbd.gbd_eval(ctx_a, bad, p, gbd.GBD_MIXED, out=sentinel, opts=seg)
+            assert e.value.code == -3
+            torch.cuda.synchronize()
+            assert bool((sentinel == (7.0 + 7.0j)).all())
+    assert len(ctx_a.kernel_times()) == done
