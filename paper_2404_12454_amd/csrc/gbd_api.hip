@@ -14,6 +14,7 @@
 #include <mutex>
 #include <new>
 #include <string>
+#include <thread>
 #include <vector>
 
 using namespace gbd;
@@ -163,15 +164,13 @@ struct gbd_plan_s {
     uint32_t *status_dev;   // two (flags, peak) word pairs used by alternate setups; each setup clears the other
     int status_parity;      // the pair the next setup uses
     bool status_zeroed;     // both words cleared (once, before the first setup)
-    uint32_t *status_host;  // pinned, two words
+    uint64_t *status_post;  // coherent host memory: the last setup's status words and sequence number
+    uint32_t status_seq;    // the last launched setup's sequence number
     int sep_scale;          // FP16 separable form: accumulators hold the field times 2^sep_scale
     uint32_t sep_key;       // the status key sep_scale came from
     void *scratch;
     size_t scratch_bytes;
-    // the last launched setup: its status pair, and an event after the copy
-    // of that pair to status_host
-    uint32_t *status_cur;
-    hipEvent_t status_ev;
+    uint32_t *status_cur;  // the last launched setup's status pair (null: none launched)
     bool spec_ok;  // the last setup succeeded: gbd_eval may launch the next evaluation before reading the status
 };
 
@@ -701,8 +700,8 @@ int plan_eval_impl(gbd_ctx_s *ctx, gbd_plan_s *plan, int precision, void *out, i
 }
 
 // The setup in two halves: plan_setup_launch enqueues the setup kernel and
-// the copy of its status pair to status_host (then status_ev), and
-// plan_setup_finish waits for that copy and takes the status.
+// the post of its status pair (status_post_kernel), and plan_setup_finish
+// waits for the post and takes the status.
 int plan_setup_launch(gbd_ctx_s *ctx, gbd_plan_s *plan, gbd_beamlets_s *b, gbd_plane_s *p) {
     if (b->dev.n > plan->capacity)
         return fail(GBD_ERANGE, "plan capacity %lld < %lld beamlets", (long long)plan->capacity, (long long)b->dev.n);
@@ -741,9 +740,8 @@ int plan_setup_launch(gbd_ctx_s *ctx, gbd_plan_s *plan, gbd_beamlets_s *b, gbd_p
                              status, status_next, ctx->stream),
                 "setup kernel launch");
         plan->status_parity ^= 1;
-        HIP_TRY(hipMemcpyAsync(plan->status_host, status, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, ctx->stream),
-                "status copy");
-        HIP_TRY(hipEventRecord(plan->status_ev, ctx->stream), "hipEventRecord");
+        plan->status_seq++;
+        HIP_TRY(launch_status_post(status, plan->status_post, plan->status_seq, ctx->stream), "status post launch");
         plan->status_cur = status;
     }
     return GBD_OK;
@@ -752,11 +750,27 @@ int plan_setup_launch(gbd_ctx_s *ctx, gbd_plan_s *plan, gbd_beamlets_s *b, gbd_p
 int plan_setup_finish(gbd_ctx_s *ctx, gbd_plan_s *plan) {
     plan->flags = 0;
     if (plan->status_cur) {
-        (void)ctx;
-        HIP_TRY(hipEventSynchronize(plan->status_ev), "hipEventSynchronize");
-        const uint32_t st = plan->status_host[0];
+        // poll the posted word for this setup's sequence number: busy at
+        // first, then yielding; after a second (a stream with long work queued
+        // ahead) wait for the stream, after which the post is visible
+        const uint32_t seq = plan->status_seq;
+        const volatile uint64_t *post = plan->status_post;
+        uint64_t w = *post;
+        const auto t0 = std::chrono::steady_clock::now();
+        for (uint32_t spins = 0; (uint32_t)(w >> 32) != seq; w = *post) {
+            if (++spins < 4096) continue;
+            const auto dt = std::chrono::steady_clock::now() - t0;
+            if (dt > std::chrono::seconds(1)) {
+                HIP_TRY(hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
+                w = *post;
+                if ((uint32_t)(w >> 32) != seq) return fail(GBD_EHIP, "the setup status was not posted");
+                break;
+            }
+            if (dt > std::chrono::microseconds(200)) std::this_thread::yield();
+        }
+        const uint32_t st = (uint32_t)w & 0xffu;
         // FP16 separable form: largest term 2^P over the grid -> scale 2^(2 kSepHalfExp - P)
-        const uint32_t key = plan->status_host[1];
+        const uint32_t key = ((uint32_t)w >> 8) & 0xfffu;
         plan->sep_key = key;
         plan->sep_scale = key ? 2 * kSepHalfExp - ((int)key - 2048) : 0;
         if (st & FLAG_PARALLEL) return fail(GBD_EPARALLEL, "a base ray is parallel to the detector plane");
@@ -787,11 +801,11 @@ void plan_destroy(gbd_plan_s *plan) {
     if (plan->c64) (void)hipFree(plan->c64);
     if (plan->c32) (void)hipFree(plan->c32);
     if (plan->status_dev) (void)hipFree(plan->status_dev);
-    if (plan->status_host) (void)hipHostFree(plan->status_host);
     if (plan->scratch) (void)hipFree(plan->scratch);
-    if (plan->status_ev) {
-        (void)hipEventSynchronize(plan->status_ev);
-        (void)hipEventDestroy(plan->status_ev);
+    if (plan->status_post) {
+        // a post still in flight writes this memory: let the device finish first
+        (void)hipDeviceSynchronize();
+        (void)hipHostFree(plan->status_post);
     }
     delete plan;
 }
@@ -806,8 +820,8 @@ int plan_new(gbd_ctx_s *ctx, int64_t capacity, gbd_plan_s **out) {
     if (e == hipSuccess) e = hipMalloc(&p->r32, cap * sizeof(Rec32));
     if (e == hipSuccess) e = hipMalloc(&p->q64, cap * sizeof(RecSq64));
     if (e == hipSuccess) e = hipMalloc(&p->status_dev, 4 * sizeof(uint32_t));
-    if (e == hipSuccess) e = hipHostMalloc(&p->status_host, 2 * sizeof(uint32_t), hipHostMallocDefault);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&p->status_ev, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipHostMalloc(&p->status_post, sizeof(uint64_t), hipHostMallocCoherent);
+    if (e == hipSuccess) *p->status_post = 0;
     if (e != hipSuccess) {
         plan_destroy(p);
         return hip_fail(e, "plan allocation");

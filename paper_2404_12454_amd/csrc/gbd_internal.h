@@ -296,6 +296,9 @@ hipError_t launch_mlp_adamw(float *p, const float *g, float *m, float *v, int64_
 // as ceil(log2) + 2048 (0: none; the FP16 separable form's range); and
 // status_next: the next setup's two words, set to zero (the host alternates
 // the pairs, so no separate clear is needed).
+// status[0] (flags, < 256) and status[1] (key, < 4096) of a finished setup
+// into *post (coherent host memory) as (seq << 32) | flags | key << 8
+hipError_t launch_status_post(const uint32_t *status, uint64_t *post, uint32_t seq, hipStream_t s);
 hipError_t launch_setup(const BeamletsDev &b, const PlaneGeom &pl, double global_turns, Rec64 *r64,
                         Rec32 *r32, RecHG64 *h64, RecHG32 *h32, RecCut64 *c64, RecCut32 *c32,
                         uint32_t *status, uint32_t *status_next, hipStream_t s);
