@@ -334,7 +334,8 @@ int gbd_autotune_load(gbd_ctx_t ctx, const char *path);
  * 0 v_fma_f32, 1 v_fma_f64, 2 v_sin_f32, 3 v_exp_f32, 7 v_fmac_f32,
  * 8 v_mul_f32 (16 chains per thread), 4 v_mfma_f32_16x16x4_f32,
  * 5 v_mfma_f32_16x16x32_f16, 6 v_mfma_f64_16x16x4_f64 (4 chains per
- * wavefront); after one untimed
+ * wavefront), 9 classes 5 and 0 together (per round 4 MFMA and 16 v_fma_f32
+ * chains, all independent; counted as its MFMA instructions); after one untimed
  * launch it times one launch with HIP events on the context stream
  * (synchronises) and returns the time in *ms_out and the wavefront-
  * instructions of that class the launch issued in *wave_instructions_out.

@@ -1252,7 +1252,7 @@ void gbd_plan_free(gbd_plan_t plan) { plan_destroy(plan); }
 
 int gbd_issue_probe(gbd_ctx_t ctx, int32_t cls, int32_t iters, double *ms_out, double *wave_instructions_out) {
     if (!ctx || !ms_out || !wave_instructions_out) return fail(GBD_EINVAL, "NULL argument");
-    if (cls < 0 || cls > 8) return fail(GBD_EINVAL, "class must be 0 ... 8");
+    if (cls < 0 || cls > 9) return fail(GBD_EINVAL, "class must be 0 ... 9");
     if (iters < 1) return fail(GBD_EINVAL, "iters must be >= 1");
     int rc = ensure_device(ctx);
     if (rc) return rc;
@@ -1275,7 +1275,8 @@ int gbd_issue_probe(gbd_ctx_t ctx, int32_t cls, int32_t iters, double *ms_out, d
     if (e != hipSuccess) return hip_fail(e, "issue probe");
     const double waves = (double)blocks * 4.0;
     *ms_out = ms;
-    *wave_instructions_out = waves * (double)iters * ((cls <= 3 || cls >= 7) ? 16.0 : 4.0);
+    // class 9 counts its MFMA instructions
+    *wave_instructions_out = waves * (double)iters * ((cls <= 3 || cls == 7 || cls == 8) ? 16.0 : 4.0);
     return GBD_OK;
 }
 

@@ -14,6 +14,10 @@
 //   class 6  v_mfma_f64_16x16x4_f64   (4 chains per wavefront)
 //   class 7  v_fmac_f32         (FP32 multiply-add, two-operand encoding)
 //   class 8  v_mul_f32          (FP32 multiply)
+//   class 9  classes 5 and 0 together: per round 4 v_mfma_f32_16x16x32_f16
+//            (4 chains) and 16 v_fma_f32 (16 chains), all independent, so
+//            its time against the two classes' shows how far the matrix and
+//            vector instructions of one SIMD overlap
 #include "../../include/gbd.h"
 #include "gbd_internal.h"
 
@@ -94,6 +98,29 @@ __global__ void __launch_bounds__(256) issue_probe_kernel(int iters, float x, fl
         }
 #pragma unroll
         for (int k = 0; k < 4; k++) acc += c[k][0] + c[k][1] + c[k][2] + c[k][3];
+    } else if constexpr (CLS == 9) {
+        pf4 c[4];
+#pragma unroll
+        for (int k = 0; k < 4; k++) c[k] = pf4{0.0f, 0.0f, 0.0f, 0.0f};
+        ph8 a, b;
+#pragma unroll
+        for (int t = 0; t < 8; t++) {
+            a[t] = (_Float16)(x + 0.001f * t);
+            b[t] = (_Float16)y;
+        }
+        float v[16];
+#pragma unroll
+        for (int k = 0; k < 16; k++) v[k] = x + 0.001f * (k + threadIdx.x);
+        for (int it = 0; it < iters; it++) {
+#pragma unroll
+            for (int k = 0; k < 4; k++) c[k] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c[k], 0, 0, 0);
+#pragma unroll
+            for (int k = 0; k < 16; k++) v[k] = fmaf(v[k], x, y);
+        }
+#pragma unroll
+        for (int k = 0; k < 4; k++) acc += c[k][0] + c[k][1] + c[k][2] + c[k][3];
+#pragma unroll
+        for (int k = 0; k < 16; k++) acc += v[k];
     } else {
         pd4 c[4];
 #pragma unroll
@@ -123,6 +150,7 @@ hipError_t launch_issue_probe(int cls, int blocks, int iters, float *sink, hipSt
         case 6: issue_probe_kernel<6><<<blocks, 256, 0, s>>>(iters, 0.999f, 0.0f, sink); break;
         case 7: issue_probe_kernel<7><<<blocks, 256, 0, s>>>(iters, 0.999f, 0.0f, sink); break;
         case 8: issue_probe_kernel<8><<<blocks, 256, 0, s>>>(iters, 0.999f, 0.0f, sink); break;
+        case 9: issue_probe_kernel<9><<<blocks, 256, 0, s>>>(iters, 0.999f, 0.0f, sink); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

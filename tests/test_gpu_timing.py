@@ -33,3 +33,16 @@ def test_kernel_timing_counts_and_leaves_fields_unchanged():
     for v in (3, 4, 5):
         assert np.array_equal(ref[v], got[v]), v
     assert E64.dtype == torch.complex128
+
+
+def test_issue_probe_overlap_class():
+    """The issue probe's class 9 (class 5's MFMA chains and class 0's FMA
+    chains in one loop) counts its MFMA instructions like class 5; classes
+    outside 0 ... 9 are refused."""
+    ctx = gbd.Context(0)
+    ms5, n5 = gbd.gbd_issue_probe(ctx, 5, 64)
+    ms9, n9 = gbd.gbd_issue_probe(ctx, 9, 64)
+    ms0, _ = gbd.gbd_issue_probe(ctx, 0, 64)
+    assert n9 == n5 and ms9 > 0 and ms5 > 0 and ms0 > 0
+    with pytest.raises(gbd.GbdError):
+        gbd.gbd_issue_probe(ctx, 10, 64)
