@@ -39,8 +39,8 @@ METRIC = "beamlet·pixel evals/s (FP32+FP64-phase vs FP64) at ≤1e-5 rel field 
 # lanes per CU per clock from the chip's unit counts: FP64 64 (78.6 TFLOP/s
 # FP64 FMA), FP32 128 (157.3 TFLOP/s FP32: reached without packed
 # instructions by the two-operand v_fmac_f32 / v_mul_f32, which the
-# issue-rate probe measures at 102-107 lanes per CU per nominal clock against
-# 58 for the three-operand v_fma_f32), transcendental 32 (half the FP64 rate;
+# issue-rate probe measures at 102-107 lanes per CU per nominal clock; its
+# three-operand v_fma_f32 loop reaches 58), transcendental 32 (half the FP64 rate;
 # probe: 28-29).  The benchmark prices each VALU form at these rates and at
 # the probe's measured ones.  Instructions per beamlet-pixel pair for R rows
 # per lane (per-lane-beamlet work amortised over the R pixels it serves):
@@ -150,9 +150,9 @@ def issue_rates(ctx):
 def measured_rate(rates):
     """Issue rates per CU per clock in the roofline's classes from the probe:
     FP32 at the slower of the two-operand multiply and multiply-add (the
-    forms the VALU kernels' inner loops use; the three-operand v_fma_f32
-    issues at about half their rate), the transcendental class at the
-    slower of sin and exp."""
+    forms the VALU kernels' inner loops use mostly; the probe's
+    three-operand v_fma_f32 loop issues at about half their rate), the
+    transcendental class at the slower of sin and exp."""
     if not rates:
         return None
     return {"fp64": rates["fp64_fma"]["lanes_per_cu_clk"],
