@@ -256,3 +256,31 @@ def test_autotuner_tunes_the_separable_forms_segments(ctx, tmp_path):
     assert gbd.gbd_autotune_load(fresh, path) >= 1
     plan2 = gbd.Plan(fresh, sc.n).setup(gbd.beamlets_from_scene(fresh, sc), gbd.plane_from_scene(fresh, sc))
     assert plan2.shape(gbd.GBD_MIXED) == best
+
+
+def test_batch_with_an_empty_instance(ctx):
+    """An instance without beamlets in the middle of a batch: its field is
+    zero, its metrics compare a zero field (RMS of the Airy pattern itself,
+    peak its maximum), and the other instances' metrics and fields equal those
+    of the batch without it bit for bit (each instance's E(0) chunks and
+    item partials are its own)."""
+    import torch
+    a = sweep_scene(24, 1.5, 1.0, npix=96, npix_y=80, span=6.0)
+    b = sweep_scene(40, 1.7, 0.8, npix=96, npix_y=80, span=6.0)
+    empty = scenes.Scene(a.lam, a.l0, np.zeros((0, 2)), np.zeros((0, 2)), np.zeros(0) + 1e-3,
+                         np.zeros((0, 2)), np.zeros(0), a.abcd, a.plane)
+    m = a.meta
+    pa = gbd.plane_from_scene(ctx, a)
+    airy = gbd.gbd_airy(ctx, pa, m["D"], m["f"], a.lam)
+    bs3 = [gbd.beamlets_from_scene(ctx, s) for s in (a, empty, b)]
+    ps3 = [gbd.plane_from_scene(ctx, s) for s in (a, empty, b)]
+    m3, f3 = gbd.gbd_eval_batch(ctx, bs3, ps3, airy=airy, fields=True)
+    m2, f2 = gbd.gbd_eval_batch(ctx, [bs3[0], bs3[2]], [ps3[0], ps3[2]], airy=airy, fields=True)
+    torch.cuda.synchronize()
+    assert np.array_equal(m3[[0, 2]], m2)
+    for F3, F2 in ((f3[0], f2[0]), (f3[2], f2[1])):
+        assert torch.equal(F3.cpu().view(torch.float32), F2.cpu().view(torch.float32))
+    assert not torch.any(f3[1].cpu().view(torch.float32) != 0)
+    A = airy.cpu().numpy().astype(np.float64)
+    np.testing.assert_allclose(m3[1, 0], np.sqrt(np.mean(A * A)), rtol=1e-6)
+    np.testing.assert_allclose(m3[1, 1], A.max(), rtol=1e-6)
