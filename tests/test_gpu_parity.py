@@ -609,3 +609,31 @@ def test_eval_launched_ahead_of_the_setup_status():
             torch.cuda.synchronize()
             assert bool((sentinel == (7.0 + 7.0j)).all())
     assert len(ctx_a.kernel_times()) == done
+
+
+def test_context_on_streams_of_its_own():
+    """A context bound to a stream of its own, then rebound to another: the
+    evaluations on either stream (the launch ahead of the status included)
+    and a beamlet handle created after the switch in a block freed before it
+    give the fields of a default context bit for bit."""
+    import torch
+    a = scenes.airy_scene(40, npix=96, npix_y=80, half_span_lamF=6.0)
+    b = scenes.airy_scene(40, OF=1.3, q=0.8, npix=96, npix_y=80, half_span_lamF=6.0)
+    ref = gbd.Context(0)
+    want = {}
+    for name, sc in (("a", a), ("b", b)):
+        want[name] = gbd.gbd_eval(ref, gbd.beamlets_from_scene(ref, sc), gbd.plane_from_scene(ref, sc), gbd.GBD_MIXED)
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    ctx = gbd.Context(0, stream=s1)
+    ba = gbd.beamlets_from_scene(ctx, a)
+    pa = gbd.plane_from_scene(ctx, a)
+    got = [gbd.gbd_eval(ctx, ba, pa, gbd.GBD_MIXED) for _ in range(2)]
+    del ba  # its block waits in the pool; the switch below drains s1 first
+    ctx.set_stream(s2)
+    bb = gbd.beamlets_from_scene(ctx, b)
+    got_b = [gbd.gbd_eval(ctx, bb, gbd.plane_from_scene(ctx, b), gbd.GBD_MIXED) for _ in range(2)]
+    torch.cuda.synchronize()
+    for E in got:
+        assert torch.equal(E.cpu().view(torch.float32), want["a"].cpu().view(torch.float32))
+    for E in got_b:
+        assert torch.equal(E.cpu().view(torch.float32), want["b"].cpu().view(torch.float32))
