@@ -116,9 +116,11 @@ int gbd_ctx_set_stream(gbd_ctx_t ctx, void *hip_stream);
 void gbd_ctx_destroy(gbd_ctx_t ctx);
 /* Kernel timing, for measurement: while enabled, every plan evaluation
  * (gbd_plan_eval, gbd_eval; not the allocation-free gbd_plan_eval_noalloc)
- * records a pair of HIP events on the context stream around its N x M
- * evaluation kernel of the whole beamlets (after the rotor form's table
- * kernel, before any truncated-beamlet kernel and the segment reduction).  gbd_ctx_kernel_times waits for
+ * times its N x M evaluation kernel of the whole beamlets (after the rotor
+ * form's table kernel, before any truncated-beamlet kernel and the segment
+ * reduction) with a pair of HIP events on the context stream: stamped with
+ * the kernel's own start and end for the separable forms, recorded around
+ * the launch for the others.  gbd_ctx_kernel_times waits for
  * the recorded pairs, writes up to `cap` of their durations in milliseconds,
  * oldest first, to ms_out (host), sets *n to how many there were and
  * forgets them all.  Disabling keeps pending pairs until they are taken. */

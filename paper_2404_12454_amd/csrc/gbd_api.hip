@@ -658,26 +658,30 @@ int plan_eval_impl(gbd_ctx_s *ctx, gbd_plan_s *plan, int precision, void *out, i
                 }
             }
             ctx->timed.push_back(tev);
-            HIP_TRY(hipEventRecord(tev.first, ctx->stream), "hipEventRecord");
+            // the separable forms' launches take the kernel's own times; the
+            // others are bracketed by event records
+            if (s.form != 3) HIP_TRY(hipEventRecord(tev.first, ctx->stream), "hipEventRecord");
         }
         if (s.form == 3 && precision == GBD_FP64)
             HIP_TRY(launch_eval_sep64(gl, plan->r64, static_cast<const RecHG64 *>(hrec),
-                                      static_cast<double2 *>(partial), static_cast<double2 *>(out), ctx->stream),
+                                      static_cast<double2 *>(partial), static_cast<double2 *>(out), ctx->stream,
+                                      tev.first, tev.second),
                     "eval kernel launch");
         else if (s.form == 3 && s.half)
             HIP_TRY(launch_eval_seph(gl, plan->r32, static_cast<const RecHG32 *>(hrec), plan->sep_scale,
-                                     static_cast<float2 *>(partial),
-                                     static_cast<float2 *>(out), ctx->stream),
+                                     static_cast<float2 *>(partial), static_cast<float2 *>(out), ctx->stream,
+                                     tev.first, tev.second),
                     "eval kernel launch");
         else if (s.form == 3)
             HIP_TRY(launch_eval_sep(gl, plan->r32, static_cast<const RecHG32 *>(hrec),
-                                    static_cast<float2 *>(partial), static_cast<float2 *>(out), ctx->stream),
+                                    static_cast<float2 *>(partial), static_cast<float2 *>(out), ctx->stream,
+                                    tev.first, tev.second),
                     "eval kernel launch");
         else
             HIP_TRY(launch_eval(precision, s.rows, s.waves, s.form, gl, rec, hrec, plan->q64, partial, out,
                                 ctx->stream),
                     "eval kernel launch");
-        if (tev.second) HIP_TRY(hipEventRecord(tev.second, ctx->stream), "hipEventRecord");
+        if (tev.second && s.form != 3) HIP_TRY(hipEventRecord(tev.second, ctx->stream), "hipEventRecord");
     }
     if (nseg_cut > 0) {
         const void *rec = precision == GBD_FP64 ? (const void *)(plan->r64 + n_main) : (const void *)(plan->r32 + n_main);

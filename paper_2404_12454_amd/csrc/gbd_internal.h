@@ -1,8 +1,12 @@
 // Internal types shared by the host API and the gfx950 kernels.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include <tuple>
+#include <utility>
 
 namespace gbd {
 
@@ -373,15 +377,37 @@ constexpr int kSepRows64 = 32;
 constexpr int kSep64WavesX = 2, kSep64WavesY = 4;
 static_assert(kSep64WavesX == kSepWavesX && kSepRows64 == kSepTileY,
               "separable tiles: the host derives the y count of wavefronts from the workgroup size");
+// A kernel launch whose start and stop events (either may be null) take the
+// kernel's own start and end times from its dispatch (hipExtLaunchKernel),
+// with no marker packets of their own on the stream between the kernels.
+template <typename... P, size_t... I>
+hipError_t launch_timed_args(void (*k)(P...), dim3 grid, dim3 block, hipStream_t s, hipEvent_t t0, hipEvent_t t1,
+                             std::tuple<std::decay_t<P>...> &a, std::index_sequence<I...>) {
+    void *p[sizeof...(P) > 0 ? sizeof...(P) : 1] = {static_cast<void *>(&std::get<I>(a))...};
+    return hipExtLaunchKernel(reinterpret_cast<const void *>(k), grid, block, p, 0, s, t0, t1, 0);
+}
+template <typename... P, typename... A>
+hipError_t launch_timed(void (*k)(P...), dim3 grid, dim3 block, hipStream_t s, hipEvent_t t0, hipEvent_t t1,
+                        A... a) {
+    static_assert(sizeof...(P) == sizeof...(A), "kernel arguments");
+    if (!t0 && !t1) {
+        k<<<grid, block, 0, s>>>(a...);
+        return hipGetLastError();
+    }
+    std::tuple<std::decay_t<P>...> args{a...};  // each converted to its parameter's type
+    return launch_timed_args(k, grid, block, s, t0, t1, args, std::index_sequence_for<P...>());
+}
+
 // hg: higher-order factors without cross terms (G diagonal), or null.
+// t0, t1 (optional): events that take the kernel's start and end times.
 hipError_t launch_eval_sep64(const EvalGeom &g, const Rec64 *rec, const RecHG64 *hg, double2 *partial, double2 *out,
-                             hipStream_t s);
+                             hipStream_t s, hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
 
 // hg: higher-order factors without cross terms (k1 = k0 = 0, G diagonal), or null.
 // Partials as float2 (no compensation term): the compact segments of
 // launch_reduce.
 hipError_t launch_eval_sep(const EvalGeom &g, const Rec32 *rec, const RecHG32 *hg, float2 *partial, float2 *out,
-                           hipStream_t s);
+                           hipStream_t s, hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
 
 // The same form for fundamental beamlets on FP16 MFMA (v_mfma_f32_16x16x32_f16)
 // with every factor split into FP16 hi and lo halves (products hi hi, hi lo,
@@ -393,6 +419,6 @@ hipError_t launch_eval_sep(const EvalGeom &g, const Rec32 *rec, const RecHG32 *h
 // from the setup); partials and output are written descaled.
 constexpr int kSepHalfExp = 14;
 hipError_t launch_eval_seph(const EvalGeom &g, const Rec32 *rec, const RecHG32 *hg, int scale, float2 *partial,
-                            float2 *out, hipStream_t s);
+                            float2 *out, hipStream_t s, hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
 
 }  // namespace gbd

@@ -398,18 +398,43 @@ __global__ void __launch_bounds__(256) reduce_mixed_kernel(int64_t M, int32_t ns
                                                            int32_t nseg4, const float4 *__restrict__ part4,
                                                            float2 *__restrict__ out, EvalGuard gd) {
     if (!guard_holds(gd)) return;
+    // A batch of segments' loads is issued before any of them is added, so a
+    // pixel costs one memory round trip per batch (32 float2 or 16 float4
+    // partials) instead of one per few segments; the sums still run in
+    // segment order.
+    constexpr int B2 = 32, B4 = 16;
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < M; p += (int64_t)gridDim.x * blockDim.x) {
         double re = 0.0, im = 0.0;
-        // unrolled so that several segments' loads are in flight at once;
-        // the sums still run in segment order
+        int s = 0;
+        for (; s + B2 <= nseg2; s += B2) {
+            float2 v[B2];
+#pragma unroll
+            for (int u = 0; u < B2; u++) v[u] = part2[(int64_t)(s + u) * M + p];
+#pragma unroll
+            for (int u = 0; u < B2; u++) {
+                re += (double)v[u].x;
+                im += (double)v[u].y;
+            }
+        }
 #pragma unroll 8
-        for (int s = 0; s < nseg2; s++) {
+        for (; s < nseg2; s++) {
             const float2 v = part2[(int64_t)s * M + p];
             re += (double)v.x;
             im += (double)v.y;
         }
+        s = 0;
+        for (; s + B4 <= nseg4; s += B4) {
+            float4 v[B4];
+#pragma unroll
+            for (int u = 0; u < B4; u++) v[u] = part4[(int64_t)(s + u) * M + p];
+#pragma unroll
+            for (int u = 0; u < B4; u++) {
+                re += (double)v[u].x - (double)v[u].z;
+                im += (double)v[u].y - (double)v[u].w;
+            }
+        }
 #pragma unroll 8
-        for (int s = 0; s < nseg4; s++) {
+        for (; s < nseg4; s++) {
             const float4 v = part4[(int64_t)s * M + p];
             re += (double)v.x - (double)v.z;
             im += (double)v.y - (double)v.w;

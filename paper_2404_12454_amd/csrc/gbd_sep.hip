@@ -132,28 +132,22 @@ __global__ void __launch_bounds__(64 * T::WX * T::WY) eval_seph_kernel(EvalGeom 
 }  // namespace
 
 hipError_t launch_eval_seph(const EvalGeom &g, const Rec32 *rec, const RecHG32 *hg, int scale, float2 *partial,
-                            float2 *out, hipStream_t s) {
+                            float2 *out, hipStream_t s, hipEvent_t t0, hipEvent_t t1) {
     using T = HTileLarge;
     static_assert(T::WX == kSepHWavesX && T::WY == kSepHWavesY && 16 * T::BX == kSepHTile && 16 * T::BY == kSepHTile,
                   "FP16 halves tiles: host and kernel disagree");
-    const int grid = (g.work + 7) / 8 * 8;
-    if (hg)
-        eval_seph_kernel<T, true><<<grid, 64 * T::WX * T::WY, 0, s>>>(g, rec, hg, scale, partial, out);
-    else
-        eval_seph_kernel<T, false><<<grid, 64 * T::WX * T::WY, 0, s>>>(g, rec, nullptr, scale, partial, out);
-    return hipGetLastError();
+    const dim3 grid((g.work + 7) / 8 * 8), block(64 * T::WX * T::WY);
+    if (hg) return launch_timed(eval_seph_kernel<T, true>, grid, block, s, t0, t1, g, rec, hg, scale, partial, out);
+    return launch_timed(eval_seph_kernel<T, false>, grid, block, s, t0, t1, g, rec, hg, scale, partial, out);
 }
 
 hipError_t launch_eval_sep(const EvalGeom &g, const Rec32 *rec, const RecHG32 *hg, float2 *partial, float2 *out,
-                           hipStream_t s) {
+                           hipStream_t s, hipEvent_t t0, hipEvent_t t1) {
     static_assert(k3WX == kSepWavesX && k3WY == kSepWavesY && 16 * k3BX == kSepTileX && 16 * k3BY == kSepTileY,
                   "separable form: host and kernel tiles");
-    const int grid = (g.work + 7) / 8 * 8;
-    if (hg)
-        eval_sep_kernel<true><<<grid, 64 * k3WX * k3WY, 0, s>>>(g, rec, hg, partial, out);
-    else
-        eval_sep_kernel<false><<<grid, 64 * k3WX * k3WY, 0, s>>>(g, rec, nullptr, partial, out);
-    return hipGetLastError();
+    const dim3 grid((g.work + 7) / 8 * 8), block(64 * k3WX * k3WY);
+    if (hg) return launch_timed(eval_sep_kernel<true>, grid, block, s, t0, t1, g, rec, hg, partial, out);
+    return launch_timed(eval_sep_kernel<false>, grid, block, s, t0, t1, g, rec, hg, partial, out);
 }
 
 }  // namespace gbd

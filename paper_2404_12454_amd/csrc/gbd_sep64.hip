@@ -223,15 +223,12 @@ __global__ void __launch_bounds__(64 * kWX * kWY) eval_sep64_kernel(EvalGeom g, 
 }  // namespace
 
 hipError_t launch_eval_sep64(const EvalGeom &g, const Rec64 *rec, const RecHG64 *hg, double2 *partial, double2 *out,
-                             hipStream_t s) {
+                             hipStream_t s, hipEvent_t t0, hipEvent_t t1) {
     static_assert(kWX == kSep64WavesX && kWY == kSep64WavesY && 16 * kBY == kSepRows64 && 16 * kBX == kSepTileX,
                   "FP64 separable form: host and kernel tiles");
-    const int grid = (g.work + 7) / 8 * 8;
-    if (hg)
-        eval_sep64_kernel<true><<<grid, 64 * kWX * kWY, 0, s>>>(g, rec, hg, partial, out);
-    else
-        eval_sep64_kernel<false><<<grid, 64 * kWX * kWY, 0, s>>>(g, rec, nullptr, partial, out);
-    return hipGetLastError();
+    const dim3 grid((g.work + 7) / 8 * 8), block(64 * kWX * kWY);
+    if (hg) return launch_timed(eval_sep64_kernel<true>, grid, block, s, t0, t1, g, rec, hg, partial, out);
+    return launch_timed(eval_sep64_kernel<false>, grid, block, s, t0, t1, g, rec, hg, partial, out);
 }
 
 }  // namespace gbd
