@@ -522,9 +522,13 @@ EvalGeom cut_geom(const gbd_ctx_s *ctx, int precision, const PlaneGeom &pl, int6
 // written only by the guarded reduction, or nothing is launched and the call
 // returns kNoSpeculation; guard->check_key is set when the form's FP16 scale
 // depends on the key.
+// post_req (with post set): a setup status still to be posted, by the
+// separable form's evaluation kernel at its start, else by status_post_kernel
+// ahead of this evaluation's first kernel; post is cleared once a launch has
+// taken it (a call that launches nothing leaves it set).
 int plan_eval_impl(gbd_ctx_s *ctx, gbd_plan_s *plan, int precision, void *out, int64_t out_bytes,
                    const gbd_eval_opts *opts, void *fixed = nullptr, size_t fixed_bytes = 0,
-                   EvalGuard *guard = nullptr) {
+                   EvalGuard *guard = nullptr, StatusPost *post_req = nullptr) {
     if (!plan->ready && !guard) return fail(GBD_EINVAL, "gbd_plan_eval: plan has no valid setup");
     if (precision != GBD_FP64 && precision != GBD_MIXED) return fail(GBD_EINVAL, "precision must be GBD_FP64 or GBD_MIXED");
     const int64_t M = (int64_t)plan->pl.nx * plan->pl.ny;
@@ -618,6 +622,15 @@ int plan_eval_impl(gbd_ctx_s *ctx, gbd_plan_s *plan, int precision, void *out, i
     const int32_t total = nseg_main + nseg_cut;
     const bool reduce = total > 1 || nseg_cut > 0;
     if (guard && !reduce) return kNoSpeculation;
+    StatusPost sp;  // the post handed to the separable form's kernel
+    if (post_req && post_req->post) {
+        if (n_main > 0 && s.form == 3) {
+            sp = *post_req;
+        } else {
+            HIP_TRY(launch_status_post(*post_req, ctx->stream), "status post launch");
+            post_req->post = nullptr;
+        }
+    }
     const int32_t nseg2 = compact ? nseg_main : 0;
     void *partial = fixed ? fixed : plan->scratch;
     if (reduce && !fixed) {
@@ -665,23 +678,24 @@ int plan_eval_impl(gbd_ctx_s *ctx, gbd_plan_s *plan, int precision, void *out, i
         if (s.form == 3 && precision == GBD_FP64)
             HIP_TRY(launch_eval_sep64(gl, plan->r64, static_cast<const RecHG64 *>(hrec),
                                       static_cast<double2 *>(partial), static_cast<double2 *>(out), ctx->stream,
-                                      tev.first, tev.second),
+                                      tev.first, tev.second, sp),
                     "eval kernel launch");
         else if (s.form == 3 && s.half)
             HIP_TRY(launch_eval_seph(gl, plan->r32, static_cast<const RecHG32 *>(hrec), plan->sep_scale,
                                      static_cast<float2 *>(partial), static_cast<float2 *>(out), ctx->stream,
-                                     tev.first, tev.second),
+                                     tev.first, tev.second, sp),
                     "eval kernel launch");
         else if (s.form == 3)
             HIP_TRY(launch_eval_sep(gl, plan->r32, static_cast<const RecHG32 *>(hrec),
                                     static_cast<float2 *>(partial), static_cast<float2 *>(out), ctx->stream,
-                                    tev.first, tev.second),
+                                    tev.first, tev.second, sp),
                     "eval kernel launch");
         else
             HIP_TRY(launch_eval(precision, s.rows, s.waves, s.form, gl, rec, hrec, plan->q64, partial, out,
                                 ctx->stream),
                     "eval kernel launch");
         if (tev.second && s.form != 3) HIP_TRY(hipEventRecord(tev.second, ctx->stream), "hipEventRecord");
+        if (post_req) post_req->post = nullptr;  // posted by the kernel just launched (form 3), or above
     }
     if (nseg_cut > 0) {
         const void *rec = precision == GBD_FP64 ? (const void *)(plan->r64 + n_main) : (const void *)(plan->r32 + n_main);
@@ -703,10 +717,20 @@ int plan_eval_impl(gbd_ctx_s *ctx, gbd_plan_s *plan, int precision, void *out, i
     return GBD_OK;
 }
 
+// The post of the last launched setup's status.
+StatusPost pending_post(const gbd_plan_s *plan) {
+    StatusPost sp;
+    sp.status = plan->status_cur;
+    sp.post = plan->status_post;
+    sp.seq = plan->status_seq;
+    return sp;
+}
+
 // The setup in two halves: plan_setup_launch enqueues the setup kernel and
-// the post of its status pair (status_post_kernel), and plan_setup_finish
-// waits for the post and takes the status.
-int plan_setup_launch(gbd_ctx_s *ctx, gbd_plan_s *plan, gbd_beamlets_s *b, gbd_plane_s *p) {
+// the post of its status pair (status_post_kernel; with post false the
+// caller has the post made, as gbd_eval does by its evaluation kernel), and
+// plan_setup_finish waits for the post and takes the status.
+int plan_setup_launch(gbd_ctx_s *ctx, gbd_plan_s *plan, gbd_beamlets_s *b, gbd_plane_s *p, bool post = true) {
     if (b->dev.n > plan->capacity)
         return fail(GBD_ERANGE, "plan capacity %lld < %lld beamlets", (long long)plan->capacity, (long long)b->dev.n);
     int rc = ensure_device(ctx);
@@ -745,8 +769,8 @@ int plan_setup_launch(gbd_ctx_s *ctx, gbd_plan_s *plan, gbd_beamlets_s *b, gbd_p
                 "setup kernel launch");
         plan->status_parity ^= 1;
         plan->status_seq++;
-        HIP_TRY(launch_status_post(status, plan->status_post, plan->status_seq, ctx->stream), "status post launch");
         plan->status_cur = status;
+        if (post) HIP_TRY(launch_status_post(pending_post(plan), ctx->stream), "status post launch");
     }
     return GBD_OK;
 }
@@ -1329,7 +1353,7 @@ int gbd_eval(gbd_ctx_t ctx, gbd_beamlets_t b, gbd_plane_t p, int precision, void
     const uint32_t pflags = plan->flags;
     const uint32_t pkey = plan->sep_key;
     const int pscale = plan->sep_scale;
-    int rc = plan_setup_launch(ctx, plan, b, p);
+    int rc = plan_setup_launch(ctx, plan, b, p, false);
     if (rc) return rc;
     if (!plan->status_cur)  // no beamlets: nothing was launched
         return (rc = plan_setup_finish(ctx, plan)) ? rc : plan_eval_impl(ctx, plan, precision, field_out, out_bytes, opts);
@@ -1342,7 +1366,11 @@ int gbd_eval(gbd_ctx_t ctx, gbd_beamlets_t b, gbd_plane_t p, int precision, void
     guard.flags = pflags & kFormFlags;
     guard.key = pkey;
     const size_t timed_before = ctx->timed.size();
-    const int ahead = plan_eval_impl(ctx, plan, precision, field_out, out_bytes, opts, nullptr, 0, &guard);
+    // the setup status is posted by the separable form's kernel at its start
+    // (one kernel launch fewer), else by its own kernel
+    StatusPost post_req = pending_post(plan);
+    const int ahead = plan_eval_impl(ctx, plan, precision, field_out, out_bytes, opts, nullptr, 0, &guard, &post_req);
+    if (post_req.post) HIP_TRY(launch_status_post(post_req, ctx->stream), "status post launch");
     rc = plan_setup_finish(ctx, plan);
     if (!rc && ahead == GBD_OK && (plan->flags & kFormFlags) == guard.flags &&
         (!guard.check_key || plan->sep_key == pkey))

@@ -300,9 +300,25 @@ hipError_t launch_mlp_adamw(float *p, const float *g, float *m, float *v, int64_
 // as ceil(log2) + 2048 (0: none; the FP16 separable form's range); and
 // status_next: the next setup's two words, set to zero (the host alternates
 // the pairs, so no separate clear is needed).
-// status[0] (flags, < 256) and status[1] (key, < 4096) of a finished setup
-// into *post (coherent host memory) as (seq << 32) | flags | key << 8
-hipError_t launch_status_post(const uint32_t *status, uint64_t *post, uint32_t seq, hipStream_t s);
+// A finished setup's status[0] (flags, < 256) and status[1] (key, < 4096)
+// posted to the host: (seq << 32) | flags | key << 8 in one system-scope
+// store into *post (coherent host memory), which the host polls for seq (an
+// event after a copy would end with a system-scope release that stalls the
+// stream for the cache writeback).  Any kernel that runs after the setup in
+// stream order can make it: status_post_kernel, or the first thread of
+// workgroup 0 of a separable-form evaluation kernel handed a StatusPost whose
+// post is set (post null: nothing to post).
+struct StatusPost {
+    const uint32_t *status = nullptr;
+    uint64_t *post = nullptr;
+    uint32_t seq = 0;
+};
+__device__ inline void post_status(const StatusPost &sp) {
+    const uint32_t f = sp.status[0], k = sp.status[1];
+    const uint64_t w = ((uint64_t)sp.seq << 32) | (uint64_t)(f & 0xffu) | ((uint64_t)(k & 0xfffu) << 8);
+    __hip_atomic_store(sp.post, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+hipError_t launch_status_post(const StatusPost &sp, hipStream_t s);
 hipError_t launch_setup(const BeamletsDev &b, const PlaneGeom &pl, double global_turns, Rec64 *r64,
                         Rec32 *r32, RecHG64 *h64, RecHG32 *h32, RecCut64 *c64, RecCut32 *c32,
                         uint32_t *status, uint32_t *status_next, hipStream_t s);
@@ -399,15 +415,18 @@ hipError_t launch_timed(void (*k)(P...), dim3 grid, dim3 block, hipStream_t s, h
 }
 
 // hg: higher-order factors without cross terms (G diagonal), or null.
-// t0, t1 (optional): events that take the kernel's start and end times.
+// t0, t1 (optional): events that take the kernel's start and end times;
+// sp (optional): a setup status the kernel posts at its start.
 hipError_t launch_eval_sep64(const EvalGeom &g, const Rec64 *rec, const RecHG64 *hg, double2 *partial, double2 *out,
-                             hipStream_t s, hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
+                             hipStream_t s, hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr,
+                             const StatusPost &sp = StatusPost());
 
 // hg: higher-order factors without cross terms (k1 = k0 = 0, G diagonal), or null.
 // Partials as float2 (no compensation term): the compact segments of
 // launch_reduce.
 hipError_t launch_eval_sep(const EvalGeom &g, const Rec32 *rec, const RecHG32 *hg, float2 *partial, float2 *out,
-                           hipStream_t s, hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
+                           hipStream_t s, hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr,
+                           const StatusPost &sp = StatusPost());
 
 // The same form for fundamental beamlets on FP16 MFMA (v_mfma_f32_16x16x32_f16)
 // with every factor split into FP16 hi and lo halves (products hi hi, hi lo,
@@ -419,6 +438,7 @@ hipError_t launch_eval_sep(const EvalGeom &g, const Rec32 *rec, const RecHG32 *h
 // from the setup); partials and output are written descaled.
 constexpr int kSepHalfExp = 14;
 hipError_t launch_eval_seph(const EvalGeom &g, const Rec32 *rec, const RecHG32 *hg, int scale, float2 *partial,
-                            float2 *out, hipStream_t s, hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
+                            float2 *out, hipStream_t s, hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr,
+                            const StatusPost &sp = StatusPost());
 
 }  // namespace gbd

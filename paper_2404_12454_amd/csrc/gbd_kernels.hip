@@ -62,18 +62,10 @@ __global__ void __launch_bounds__(256) setup_kernel(BeamletsDev b, PlaneGeom pl,
     }
 }
 
-// The setup's status words and a sequence number in one 64-bit word of
-// coherent host memory, (seq << 32) | flags | key << 8, by one system-scope
-// store that the host polls for its sequence number (an event after a copy
-// would end with a system-scope release that stalls the stream for the
-// cache writeback).
-__global__ void __launch_bounds__(64) status_post_kernel(const uint32_t *__restrict__ status, uint64_t *post,
-                                                         uint32_t seq) {
-    if (threadIdx.x == 0) {
-        const uint32_t f = status[0], k = status[1];
-        const uint64_t w = ((uint64_t)seq << 32) | (uint64_t)(f & 0xffu) | ((uint64_t)(k & 0xfffu) << 8);
-        __hip_atomic_store(post, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-    }
+// The setup's status words and a sequence number posted to the host by a
+// kernel of their own (post_status).
+__global__ void __launch_bounds__(64) status_post_kernel(StatusPost sp) {
+    if (threadIdx.x == 0) post_status(sp);
 }
 
 // The rotor forms' sigma^(k^2) tables, k = 1..16, from the FP64 records on
@@ -521,8 +513,9 @@ hipError_t launch_sigma(const EvalGeom &g, const Rec64 *r64, RecSq64 *q64, Rec32
     return hipGetLastError();
 }
 
-hipError_t launch_status_post(const uint32_t *status, uint64_t *post, uint32_t seq, hipStream_t s) {
-    status_post_kernel<<<1, 64, 0, s>>>(status, post, seq);
+hipError_t launch_status_post(const StatusPost &sp, hipStream_t s) {
+    if (!sp.status || !sp.post) return hipErrorInvalidValue;
+    status_post_kernel<<<1, 64, 0, s>>>(sp);
     return hipGetLastError();
 }
 

@@ -43,8 +43,9 @@ template <bool HG>
 __global__ void __launch_bounds__(64 * k3WX * k3WY) eval_sep_kernel(EvalGeom g, const Rec32 *__restrict__ rec,
                                                                      const RecHG32 *__restrict__ hg,
                                                                      float2 *__restrict__ partial,
-                                                                     float2 *__restrict__ out) {
+                                                                     float2 *__restrict__ out, StatusPost sp) {
     __shared__ Sep3Lds<HG> L;
+    if (sp.post && blockIdx.x == 0 && threadIdx.x == 0) post_status(sp);
     const int w = work_item(blockIdx.x, gridDim.x);
     if (w >= g.work) return;
     const int tiles = g.tiles_x * g.tiles_y;
@@ -90,8 +91,9 @@ template <class T, bool HG>
 __global__ void __launch_bounds__(64 * T::WX * T::WY) eval_seph_kernel(EvalGeom g, const Rec32 *__restrict__ rec,
                                                                         const RecHG32 *__restrict__ hg, int scale,
                                                                         float2 *__restrict__ partial,
-                                                                        float2 *__restrict__ out) {
+                                                                        float2 *__restrict__ out, StatusPost sp) {
     __shared__ SepHLdsT<T> L;
+    if (sp.post && blockIdx.x == 0 && threadIdx.x == 0) post_status(sp);
     const int w = work_item(blockIdx.x, gridDim.x);
     if (w >= g.work) return;
     const int tiles = g.tiles_x * g.tiles_y;
@@ -132,22 +134,23 @@ __global__ void __launch_bounds__(64 * T::WX * T::WY) eval_seph_kernel(EvalGeom 
 }  // namespace
 
 hipError_t launch_eval_seph(const EvalGeom &g, const Rec32 *rec, const RecHG32 *hg, int scale, float2 *partial,
-                            float2 *out, hipStream_t s, hipEvent_t t0, hipEvent_t t1) {
+                            float2 *out, hipStream_t s, hipEvent_t t0, hipEvent_t t1, const StatusPost &sp) {
     using T = HTileLarge;
     static_assert(T::WX == kSepHWavesX && T::WY == kSepHWavesY && 16 * T::BX == kSepHTile && 16 * T::BY == kSepHTile,
                   "FP16 halves tiles: host and kernel disagree");
     const dim3 grid((g.work + 7) / 8 * 8), block(64 * T::WX * T::WY);
-    if (hg) return launch_timed(eval_seph_kernel<T, true>, grid, block, s, t0, t1, g, rec, hg, scale, partial, out);
-    return launch_timed(eval_seph_kernel<T, false>, grid, block, s, t0, t1, g, rec, hg, scale, partial, out);
+    if (hg)
+        return launch_timed(eval_seph_kernel<T, true>, grid, block, s, t0, t1, g, rec, hg, scale, partial, out, sp);
+    return launch_timed(eval_seph_kernel<T, false>, grid, block, s, t0, t1, g, rec, hg, scale, partial, out, sp);
 }
 
 hipError_t launch_eval_sep(const EvalGeom &g, const Rec32 *rec, const RecHG32 *hg, float2 *partial, float2 *out,
-                           hipStream_t s, hipEvent_t t0, hipEvent_t t1) {
+                           hipStream_t s, hipEvent_t t0, hipEvent_t t1, const StatusPost &sp) {
     static_assert(k3WX == kSepWavesX && k3WY == kSepWavesY && 16 * k3BX == kSepTileX && 16 * k3BY == kSepTileY,
                   "separable form: host and kernel tiles");
     const dim3 grid((g.work + 7) / 8 * 8), block(64 * k3WX * k3WY);
-    if (hg) return launch_timed(eval_sep_kernel<true>, grid, block, s, t0, t1, g, rec, hg, partial, out);
-    return launch_timed(eval_sep_kernel<false>, grid, block, s, t0, t1, g, rec, hg, partial, out);
+    if (hg) return launch_timed(eval_sep_kernel<true>, grid, block, s, t0, t1, g, rec, hg, partial, out, sp);
+    return launch_timed(eval_sep_kernel<false>, grid, block, s, t0, t1, g, rec, hg, partial, out, sp);
 }
 
 }  // namespace gbd

@@ -111,8 +111,9 @@ template <bool HG>
 __global__ void __launch_bounds__(64 * kWX * kWY) eval_sep64_kernel(EvalGeom g, const Rec64 *__restrict__ rec,
                                                                      const RecHG64 *__restrict__ hg,
                                                                      double2 *__restrict__ partial,
-                                                                     double2 *__restrict__ out) {
+                                                                     double2 *__restrict__ out, StatusPost sp) {
     __shared__ Lds64 L;
+    if (sp.post && blockIdx.x == 0 && threadIdx.x == 0) post_status(sp);
     auto &lu = L.lu;
     auto &lv = L.lv;
     const int w = work_item(blockIdx.x, gridDim.x);
@@ -223,12 +224,12 @@ __global__ void __launch_bounds__(64 * kWX * kWY) eval_sep64_kernel(EvalGeom g, 
 }  // namespace
 
 hipError_t launch_eval_sep64(const EvalGeom &g, const Rec64 *rec, const RecHG64 *hg, double2 *partial, double2 *out,
-                             hipStream_t s, hipEvent_t t0, hipEvent_t t1) {
+                             hipStream_t s, hipEvent_t t0, hipEvent_t t1, const StatusPost &sp) {
     static_assert(kWX == kSep64WavesX && kWY == kSep64WavesY && 16 * kBY == kSepRows64 && 16 * kBX == kSepTileX,
                   "FP64 separable form: host and kernel tiles");
     const dim3 grid((g.work + 7) / 8 * 8), block(64 * kWX * kWY);
-    if (hg) return launch_timed(eval_sep64_kernel<true>, grid, block, s, t0, t1, g, rec, hg, partial, out);
-    return launch_timed(eval_sep64_kernel<false>, grid, block, s, t0, t1, g, rec, hg, partial, out);
+    if (hg) return launch_timed(eval_sep64_kernel<true>, grid, block, s, t0, t1, g, rec, hg, partial, out, sp);
+    return launch_timed(eval_sep64_kernel<false>, grid, block, s, t0, t1, g, rec, hg, partial, out, sp);
 }
 
 }  // namespace gbd
