@@ -611,6 +611,48 @@ def test_eval_launched_ahead_of_the_setup_status():
     assert len(ctx_a.kernel_times()) == done
 
 
+def test_eval_sequence_moves_the_status_post_between_kernels():
+    """One context through a seeded random sequence of gbd_eval calls whose
+    forms change from call to call: the separable form in FP16 halves at two
+    FP16 scales (its evaluation kernel posts the setup status when launched
+    ahead), a plane with cross terms and higher-order beamlets (the post by a
+    kernel of its own, ahead of a mispredicted or other form), the FP64
+    separable form, and single-segment launches (no launch ahead).  Every
+    field equals a fresh context's bit for bit, and kernel timing keeps one
+    duration per call."""
+    import torch
+    seg = dict(segments=4)
+    airy = scenes.airy_scene(40, npix=96, npix_y=80, half_span_lamF=6.0)
+    airy_b = scenes.airy_scene(40, OF=1.3, q=0.8, npix=96, npix_y=80, half_span_lamF=6.0)
+    small = scenes.airy_scene(24, npix=64, half_span_lamF=6.0)
+    cases = [(airy, gbd.GBD_MIXED, seg),
+             (airy, gbd.GBD_MIXED, dict(segments=1)),
+             (airy_b, gbd.GBD_MIXED, seg),
+             (scenes.zernike_scene(5, n_across=12, npix=48), gbd.GBD_MIXED, seg),
+             (scenes.hermite_scene(12, npix=64, half_span_lamF=8.0), gbd.GBD_MIXED, seg),
+             (small, gbd.GBD_FP64, seg)]
+    want = []
+    for sc, prec, o in cases:
+        fresh = gbd.Context(0)
+        want.append(gbd.gbd_eval(fresh, gbd.beamlets_from_scene(fresh, sc), gbd.plane_from_scene(fresh, sc), prec,
+                                 opts=o))
+    rng = np.random.default_rng(2404)
+    order = [int(i) for i in rng.integers(0, len(cases), 30)] + [0, 0, 2, 2, 0, 5, 5, 3, 3, 0, 4, 4, 0]
+    ctx_a = gbd.Context(0)
+    handles = [(gbd.beamlets_from_scene(ctx_a, sc), gbd.plane_from_scene(ctx_a, sc)) for sc, _, _ in cases]
+    ctx_a.set_kernel_timing(True)
+    got = []
+    for i in order:
+        b, p = handles[i]
+        _, prec, o = cases[i]
+        got.append(gbd.gbd_eval(ctx_a, b, p, prec, opts=o))
+    torch.cuda.synchronize()
+    for k, (i, E) in enumerate(zip(order, got)):
+        real = torch.float64 if cases[i][1] == gbd.GBD_FP64 else torch.float32
+        assert torch.equal(E.cpu().view(real), want[i].cpu().view(real)), (k, i)
+    assert len(ctx_a.kernel_times()) == len(order)
+
+
 def test_context_on_streams_of_its_own():
     """A context bound to a stream of its own, then rebound to another: the
     evaluations on either stream (the launch ahead of the status included)
