@@ -340,6 +340,14 @@ constexpr int kStageWords = 24, kStageUsed = 22;
 __device__ constexpr int kStageSrc[kStageUsed] = {0, 1, 4, 5, 6, 7, 10, 11, 2, 3, 8, 9, 14, 15,
                                                   16, 17, 19, 18, 21, 22, 23, 27};
 static_assert(sizeof(Rec32) == 60 * 4 && kStageWords % 4 == 0, "staged record layout");
+// A record past the segment's end is staged as m0 = -inf (staged word
+// kStagedM0), its U bound u = -1e30 (kStagedU) and zeros in its other words:
+// its U factors 2^(m0 + 14 - u) and V factors 2^(scale - 14 + u) are both
+// exactly zero (a finite V there could leave FP16's range, and 0 x inf is NaN).
+constexpr int kStagedM0 = 14, kStagedU = 21;
+constexpr uint32_t kPadU = 0xf149f2cau;  // -1e30f
+static_assert(kStageSrc[kStagedM0] == offsetof(Rec32, m) / 4, "staged m0 word");
+static_assert(kStageSrc[kStagedU] == offsetof(Rec32, pad) / 4, "staged U bound word");
 // Higher-order beamlets: 12 words of each RecHG32 (the diagonal of G and the
 // per-axis polynomial coefficients), staged beside the record words by the
 // first 16 x 12 threads: staged word w holds RecHG32 word kStageSrcHG[w]:
@@ -423,8 +431,11 @@ __device__ inline void sep_accumulate_h(const SepGeom &g, const Rec32 *__restric
 
     // staging: thread t moves word kStageSrc[t % 22] of record t / 22 (the
     // threads past 16 x 22 load words of later records, clamped, and store
-    // them into rows nobody reads)
+    // them into rows nobody reads); past the segment's end it stores the pad
+    // word instead (m0 = -inf, u = -1e30, else 0), which zeroes that
+    // beamlet's U and V factors
     const int st = threadIdx.x, sr = st / kStageUsed, sc_w = st - sr * kStageUsed, sw_src = kStageSrc[sc_w];
+    const uint32_t pad_w = sc_w == kStagedM0 ? 0xff800000u : sc_w == kStagedU ? kPadU : 0u;
     // and, for higher-order beamlets, word kStageSrcHG[t % 12] of record t / 12
     const int hr = st / kStageHG, hc = st - hr * kStageHG, hw_src = HG ? kStageSrcHG[hc] : 0;
     struct Staged {
@@ -433,7 +444,11 @@ __device__ inline void sep_accumulate_h(const SepGeom &g, const Rec32 *__restric
     auto stage_load = [&](int i0) {  // words of the pass starting at beamlet i0
         const int i = i0 + sr;
         Staged v;
-        v.w = reinterpret_cast<const uint32_t *>(srec + (i < n ? i : 0))[sw_src];
+        const uint32_t w = reinterpret_cast<const uint32_t *>(srec + (i < n ? i : 0))[sw_src];
+        // the word masked and the pad merged by bit operations, so the load
+        // stays unconditional (a select on it becomes a branch in the loop)
+        const uint32_t keep = 0u - (uint32_t)(i < n);
+        v.w = (w & keep) | (pad_w & ~keep);
         v.h = 0u;
         if constexpr (HG) {
             const int ih = i0 + hr;
@@ -467,8 +482,8 @@ __device__ inline void sep_accumulate_h(const SepGeom &g, const Rec32 *__restric
         const double brho = f64(8), p2 = f64(10), p5 = f64(12);
         const float m0 = f32(14), m1 = f32(15), m3 = f32(16), m2 = f32(17), m5 = f32(18);
         const float arf = f32(19), brf = f32(20), u = f32(21);
-        const float mbias = i0 + b < n ? 0.0f : -INFINITY;
-        const float lu0 = (m0 + (E - u)) + mbias, lv0 = (sc - E) + u;
+        // (a beamlet past the segment's end was staged with m0 = -inf)
+        const float lu0 = m0 + (E - u), lv0 = (sc - E) + u;
         const int col = 4 * (qd ^ sw) + lk;
         float hx[6], hy[6];
         if constexpr (HG) {
