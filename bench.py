@@ -59,7 +59,7 @@ RATE = {"fp64": 64, "fp32": 128, "trans": 32}
 # HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE (x2.0)
 # and WRITE_SIZE (x1.0) runs, scale factors from a plain 256 MiB copy; valid
 # only for the kernel and launch they were taken on (else traffic is null).
-TRAFFIC = {("airy256_512", 64, 8, 32, 4): (5742.5 * 2.0 + 65536.0 * 1.0) * 1024}
+TRAFFIC = {("airy256_512", 64, 8, 32, 4): (5742.0 * 2.0 + 65536.0 * 1.0) * 1024}
 
 
 def instruction_mix(rows, variant, hg=False):
